@@ -1,0 +1,84 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in the oracle (on the CPU, through monkeypatch) and
+checks that at least one of the pins in test_oracle_pins fails with it.
+"""
+import numpy as np
+import pytest
+
+import oracle.glam_oracle as O
+from tests import test_oracle_pins as P
+
+
+def _fails(fns):
+    for fn in fns:
+        try:
+            fn()
+        except Exception:
+            return True
+    return False
+
+
+def _gauss_pins():
+    return [lambda: P.test_gaussian_closed_form_orthogonal_design(),
+            lambda: P.test_gaussian_matches_coordinate_descent("gauss")]
+
+
+def _poisson_pins():
+    return [lambda: P.test_poisson_matches_prox_newton(0.3), lambda: P.test_poisson_lambda_zero_is_mle()]
+
+
+MUTANTS = {
+    # wrong sign of the score (eq. four)
+    "score_sign": ("score", lambda orig: (lambda fam, eta, y, a=None: -orig(fam, eta, y, a)),
+                   lambda: _gauss_pins() + [lambda: P.test_score_is_derivative_of_loglik("poisson")]),
+    # prior weights dropped from the score
+    "score_drops_a": ("score", lambda orig: (lambda fam, eta, y, a=None: orig(fam, eta, y, None)),
+                      lambda: [lambda: P.test_score_is_derivative_of_loglik("gaussian"),
+                               lambda: P.test_gaussian_with_observation_weights_matches_cd()]),
+    # working response without the + eta term (eq. tennew)
+    "z_drops_eta": ("working_response",
+                    lambda orig: (lambda fam, eta, y, a=None: orig(fam, eta, y, a) - eta),
+                    lambda: [lambda: P.test_working_response_forms_agree("poisson")] + _poisson_pins()),
+    # soft threshold at half the level
+    "prox_half": ("soft_threshold", lambda orig: (lambda z, t: orig(z, 0.5 * t)),
+                  lambda: [P.test_soft_threshold_is_the_l1_prox] + _gauss_pins()),
+    # KKT residual with the wrong subgradient sign
+    "kkt_sign": ("kkt_residual",
+                 lambda orig: (lambda th, g, lam, lm, pen_w=None: orig(th, -np.asarray(g), lam, lm, pen_w)),
+                 lambda: [P.test_kkt_residual_definition] + _gauss_pins()),
+    # H applies the factors in reverse order (wrong mode index)
+    "H_reversed": ("H", lambda orig: (lambda Xs, Th: orig(list(Xs)[::-1], Th)),
+                   lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),
+    # G forgets the transpose on the factors (transposed operand)
+    "G_no_transpose": ("G", lambda orig: (lambda Xs, U: orig([np.asarray(X).T for X in Xs], U)),
+                       lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),
+    # rho appends the new mode first instead of last
+    "rho_mode_first": ("rho", lambda orig: (lambda X, A: np.moveaxis(orig(X, A), -1, 0)),
+                       lambda: [lambda: P.test_rho_matches_defining_sum((2, 3, 4), 3),
+                                P.test_rho_identity_factor_is_cyclic_rotation]),
+    # lambda_max without the 1/n scale
+    "lmax_no_n": ("lambda_max",
+                  lambda orig: (lambda fam, Xs, Y, a=None, pen_w=None: orig(fam, Xs, Y, a, pen_w) * Y.size),
+                  lambda: [lambda: P.test_lambda_max_gives_zero_solution("gaussian")]),
+    # Lipschitz bound with a sum of spectral radii instead of the product
+    "lhat_sum": ("lipschitz_bound",
+                 lambda orig: (lambda Xs, w, n: float(np.max(w)) * float(np.sum(O.spectral_radii(Xs))) / n),
+                 lambda: [P.test_lipschitz_bound_prop1]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, monkeypatch):
+    attr, make, pins = MUTANTS[name]
+    orig = getattr(O, attr)
+    monkeypatch.setattr(O, attr, make(orig))
+    assert _fails(pins()), f"no pin caught mutant {name}"
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_pass_without_mutation(name):
+    """Control: the same pin lists pass on the unmodified oracle."""
+    _, _, pins = MUTANTS[name]
+    for fn in pins():
+        fn()
