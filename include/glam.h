@@ -1,0 +1,168 @@
+/*
+ * glam.h -- C ABI of the MI355X (gfx950) l1-penalised GLAM solver.
+ *
+ * Model (Lund, Vincent & Hansen, arXiv:1510.03298):
+ *   design X = X_3 (x) X_2 (x) X_1 (Sec. 2, eq. fivenew), X_j is n_j x p_j;
+ *   linear predictor eta = H(<X_j>, Theta) = rho(X_3, rho(X_2, rho(X_1, Theta)))
+ *   (Sec. 6.1, eq. eighteen; rho of App. A); gradient maps use
+ *   G(<X_j>, U) = rho(X_3^T, rho(X_2^T, rho(X_1^T, U))) (eq. nineteen);
+ *   PMLE theta* = argmin -l(eta(theta))/n + lambda sum_m w_m |theta_m| (eq. five,
+ *   with the 1/n scale of eqs. eleven and twentyfour carried to the objective).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are column-major, i.e. the paper's vec (App. A, eq. index): the
+ *     first index runs fastest.  X_j is n_j x p_j with leading dimension n_j;
+ *     Theta is p_1 x p_2 x p_3; Eta, U, Y and observation weights are
+ *     n_1 x n_2 x n_3.
+ *   - Only d = 3 is supported (a d = 2 model is a d = 3 model with n_3 = p_3 = 1
+ *     and X_3 = [1]).  Sizes are int64_t; every n_j and p_j must be >= 1.
+ *   - Array pointers are DEVICE pointers owned by the caller unless stated
+ *     otherwise.  The library never frees or retains them after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Return value: a glam_status code.  GLAM_EINVAL is returned before any
+ *     work is enqueued; glam_last_error() then gives a message for the calling
+ *     thread.
+ *   - The rho entry points are asynchronous on `stream`; glam_fit_path is
+ *     synchronous (it needs host control flow) and returns when its results are
+ *     in place.
+ */
+#ifndef GLAM_H
+#define GLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GLAM_OK = 0,
+  GLAM_EINVAL = 1,      /* invalid argument (sizes, pointers, values, limits)      */
+  GLAM_ENOMEM = 2,      /* device allocation failed                                */
+  GLAM_EDEVICE = 3,     /* a HIP runtime call failed                               */
+  GLAM_ENOCONV = 4,     /* a fit hit its iteration limit (path truncated)          */
+  GLAM_ENONFINITE = 5   /* a non-finite gradient or objective was produced         */
+} glam_status;
+
+typedef enum { GLAM_GAUSSIAN = 0, GLAM_POISSON = 1 } glam_family;
+
+/* Element type of the rho products.  F64: all FP64.  F32: FP32 inputs and
+ * outputs, FP32 accumulation.  BF16: bfloat16 inputs (stored as uint16_t),
+ * FP32 accumulation and FP32 outputs. */
+typedef enum { GLAM_F64 = 0, GLAM_F32 = 1, GLAM_BF16 = 2 } glam_dtype;
+
+/* Text of a status code (static storage). */
+const char* glam_status_string(int status);
+/* Detail message of the last failing call on this thread ("" if none). */
+const char* glam_last_error(void);
+/* Library version string, e.g. "glam-mi355x 0.1.0 (gfx950)". */
+const char* glam_version(void);
+
+/* Limits of the fused slab kernels: modes 1 and 2 must satisfy
+ * p_j <= GLAM_MAX_INNER_P and n_j <= GLAM_MAX_INNER_N (mode 3 is unrestricted). */
+#define GLAM_MAX_INNER_P 32
+#define GLAM_MAX_INNER_N 256
+
+/* ---------------------------------------------------------------------------
+ * rho transforms (App. A; Sec. 6.1 eqs. eighteen and nineteen, c = 1)
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace the rho entry points need for these sizes/dtype. */
+size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype);
+
+/* Eta = H(<X_j>, Theta) = rho(X_3, rho(X_2, rho(X_1, Theta)))  (eq. eighteen).
+ *   n, p     : host arrays of length d (d == 3).
+ *   X        : host array of d device pointers; X[j] -> n_j x p_j of `dtype`.
+ *   Theta    : device, p_1 x p_2 x p_3 of `dtype`.
+ *   Eta      : device, n_1 x n_2 x n_3; FP64 for GLAM_F64, FP32 otherwise.
+ *   workspace: device, >= glam_rho_workspace_size(...) bytes, 256-byte aligned.
+ * Errors: GLAM_EINVAL for d != 3, sizes < 1 or beyond the inner-mode limits,
+ * NULL pointers, a bad dtype or a too-small workspace. */
+int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X,
+                     const void* Theta, void* Eta, int dtype, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* Out = G(<X_j>, U) = rho(X_3^T, rho(X_2^T, rho(X_1^T, U)))  (eq. nineteen),
+ * i.e. vec(Out) = X^T vec(U).
+ *   U   : device, n_1 x n_2 x n_3 of `dtype`.
+ *   Out : device, p_1 x p_2 x p_3; FP64 for GLAM_F64, FP32 otherwise.
+ * Other arguments and errors as glam_rho_forward. */
+int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X,
+                     const void* U, void* Out, int dtype, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * lambda path of the GD-PG algorithm (Sec. 3, Algorithm 1; Sec. 6.4)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int d;                  /* must be 3                                              */
+  int64_t n[3], p[3];     /* mode sizes                                             */
+  const double* X[3];     /* device, FP64, X[j] is n_j x p_j column-major           */
+  const double* Y;        /* device, FP64 response array n_1 x n_2 x n_3            */
+  const double* obs_w;    /* device, FP64 prior weights a_i >= 0 (App. B), or NULL  */
+  int family;             /* glam_family                                            */
+  const double* pen_w;    /* device, FP64 penalty weights w_m > 0 (length p), or NULL = 1 */
+} glam_problem;
+
+typedef struct {
+  const double* lambda;   /* HOST array of nlambda strictly decreasing values, or NULL:
+                             log grid lambda_max * ratio^(l/(nlambda-1))           */
+  int nlambda;            /* number of models (>= 1)                                */
+  double lambda_min_ratio;/* ratio of the log grid (0 < ratio <= 1)                 */
+  int dtype;              /* glam_dtype of the inner rho chain (FP64 anchors always) */
+  double kkt_tol;         /* target FP64 KKT residual (relative to lambda_max), e.g. 1e-6 */
+  double nu;              /* step control (Sec. 6.4): 1 = delta = 1/Lhat, no backtracking;
+                             0 < nu < 1: delta = 1/(nu Lhat) with backtracking      */
+  int max_outer;          /* outer (Alg. 1) iterations per lambda, e.g. 100         */
+  int max_inner;          /* inner PG iterations per outer iteration, e.g. 100000   */
+  int check_every;        /* inner iterations between host convergence checks (>= 1) */
+  const double* theta0;   /* device, FP64 p-array warm start for the first lambda, or NULL */
+  void* stream;           /* hipStream_t (NULL = default stream)                    */
+} glam_options;
+
+typedef struct {
+  double* theta;          /* device, FP64, nlambda x p (model l at offset l*p), caller-allocated */
+  double* lambda_out;     /* host, nlambda: the lambda values used                   */
+  double* kkt;            /* host, nlambda: FP64 KKT residual / lambda_max at return */
+  double* objective;      /* host, nlambda: F = -l/n + lambda J                      */
+  int* iters_outer;       /* host, nlambda                                           */
+  int* iters_inner;       /* host, nlambda: total inner iterations                   */
+  int* status;            /* host, nlambda: glam_status per model                    */
+  int n_done;             /* out: number of models fitted (< nlambda on early exit) */
+  double lambda_max;      /* out: lambda_max (Sec. 6.4)                              */
+  double seconds;         /* out: wall time of the call                              */
+} glam_result;
+
+/* Fit the whole lambda path with warm starts.  Models are fitted in order;
+ * on a fit that does not converge (GLAM_ENOCONV) or produces non-finite values
+ * (GLAM_ENONFINITE) the path stops and only the preceding models are valid
+ * (n_done), as the reference package does (Sec. 6.5).
+ * Errors: GLAM_EINVAL for bad sizes/pointers/options, non-finite Y, negative Y
+ * for the Poisson family, negative obs_w, non-positive pen_w, or a lambda
+ * sequence that is not strictly decreasing and positive. */
+int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res);
+
+/* ---------------------------------------------------------------------------
+ * Poisson negative log-likelihood in beta (eqs. two, three and four with
+ * a = 1, log y! dropped): L(beta) = (1/n) sum_i (exp(eta_i) - y_i eta_i),
+ * eta = H(<X_j>, beta); grad L = G(<X_j>, exp(eta) - y) / n.
+ * ------------------------------------------------------------------------- */
+size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype);
+
+/* loss (device, one FP64) = L(beta).  X and beta of `dtype`; Y FP64 counts. */
+int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* const* X,
+                             const void* beta, const double* Y, double* loss, int dtype,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* grad (device, FP32 for F32/BF16, FP64 for F64, p-array) = gscale * grad L(beta),
+ * where gscale is the device FP64 scalar *gscale (the upstream gradient). */
+int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* const* X,
+                              const void* beta, const double* Y, const double* gscale,
+                              void* grad, int dtype, void* workspace, size_t ws_bytes,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLAM_H */

@@ -1,0 +1,197 @@
+// api.cpp -- C ABI entry points (include/glam.h): validation, workspace layout
+// and the host control flow of the lambda path (Sec. 3, Algorithm 1; Sec. 6.4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "glam.h"
+#include "launch.h"
+
+namespace glam {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+Geom make_geom(const int64_t* n, const int64_t* p) {
+  Geom G;
+  G.n1 = (int)n[0]; G.n2 = (int)n[1]; G.n3 = (int)n[2];
+  G.p1 = (int)p[0]; G.p2 = (int)p[1]; G.p3 = (int)p[2];
+  G.P12 = G.p1 * G.p2;
+  G.N1T = (G.n1 + 15) / 16;
+  G.NJB = (G.n2 + 15) / 16;
+  G.PT = (std::max(G.p1, G.p2) + 15) / 16;
+  G.nint = (long long)G.n3 * G.NJB * G.N1T * 256;
+  G.n = (long long)G.n1 * G.n2 * G.n3;
+  G.p = (long long)G.p1 * G.p2 * G.p3;
+  return G;
+}
+
+static const size_t kMaxLds = 159 * 1024;   // 160 KB per CU minus static LDS
+
+// Common size validation of the rho-based entry points.
+static int check_sizes(int d, const int64_t* n, const int64_t* p, int dtype, Geom* Gout) {
+  if (d != 3) return fail(GLAM_EINVAL, "only d = 3 is supported");
+  if (!n || !p) return fail(GLAM_EINVAL, "NULL size array");
+  for (int j = 0; j < 3; ++j) {
+    if (n[j] < 1 || p[j] < 1) return fail(GLAM_EINVAL, "mode sizes must be >= 1");
+    if (n[j] > (1 << 30) || p[j] > (1 << 30)) return fail(GLAM_EINVAL, "mode size too large");
+  }
+  if (dtype < 0 || dtype > 2) return fail(GLAM_EINVAL, "bad dtype");
+  if (p[0] > GLAM_MAX_INNER_P || p[1] > GLAM_MAX_INNER_P)
+    return fail(GLAM_EINVAL, "p_1 and p_2 must be <= GLAM_MAX_INNER_P");
+  if (n[0] > GLAM_MAX_INNER_N || n[1] > GLAM_MAX_INNER_N)
+    return fail(GLAM_EINVAL, "n_1 and n_2 must be <= GLAM_MAX_INNER_N");
+  Geom G = make_geom(n, p);
+  if ((long long)G.n3 * G.P12 > (1LL << 40)) return fail(GLAM_EINVAL, "problem too large");
+  if (slab_chain_lds_bytes(dtype, G) > kMaxLds)
+    return fail(GLAM_EINVAL, "modes 1-2 too large for the slab kernel's LDS budget (n_1, n_2 too big for this dtype)");
+  *Gout = G;
+  return GLAM_OK;
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define HIPCHK(expr)                                                           \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      return fail(GLAM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                          \
+  } while (0)
+
+}  // namespace glam
+
+using namespace glam;
+
+extern "C" {
+
+const char* glam_status_string(int status) {
+  switch (status) {
+    case GLAM_OK: return "ok";
+    case GLAM_EINVAL: return "invalid argument";
+    case GLAM_ENOMEM: return "device allocation failed";
+    case GLAM_EDEVICE: return "HIP runtime error";
+    case GLAM_ENOCONV: return "iteration limit reached (path truncated)";
+    case GLAM_ENONFINITE: return "non-finite value produced";
+    default: return "unknown status";
+  }
+}
+
+const char* glam_last_error(void) { return g_err.c_str(); }
+
+const char* glam_version(void) { return "glam-mi355x 0.1.0 (gfx950)"; }
+
+size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype) {
+  Geom G;
+  if (check_sizes(d, n, p, dtype, &G) != GLAM_OK) return 0;
+  return align256((size_t)G.n3 * G.P12 * dt_size(dtype));
+}
+
+int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* Theta, void* Eta,
+                     int dtype, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Geom G;
+  int st = check_sizes(d, n, p, dtype, &G);
+  if (st) return st;
+  if (!X || !X[0] || !X[1] || !X[2] || !Theta || !Eta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  FwdParams F{};
+  F.G = G; F.theta = Theta; F.X3 = X[2]; F.T1 = workspace; F.iter = nullptr;
+  HIPCHK(launch_slab_fwd(dtype, F, s));
+  SlabParams S{};
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = workspace; S.eta_out = Eta;
+  HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, s));
+  return GLAM_OK;
+}
+
+int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* U, void* Out,
+                     int dtype, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Geom G;
+  int st = check_sizes(d, n, p, dtype, &G);
+  if (st) return st;
+  if (!X || !X[0] || !X[1] || !X[2] || !U || !Out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  SlabParams S{};
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.S2 = workspace; S.u_in = U;
+  HIPCHK(launch_slab_chain(dtype, SM_ADJ_STD, S, s));
+  AdjParams A{};
+  A.G = G; A.S2 = workspace; A.X3 = X[2]; A.out = Out; A.scale = 1.0;
+  HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  return GLAM_OK;
+}
+
+size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype) {
+  Geom G;
+  if (check_sizes(3, n, p, dtype, &G) != GLAM_OK) return 0;
+  return 2 * align256((size_t)G.n3 * G.P12 * dt_size(dtype)) + align256((size_t)G.n3 * 2 * sizeof(double));
+}
+
+int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* const* X, const void* beta,
+                             const double* Y, double* loss, int dtype, void* workspace, size_t ws_bytes,
+                             void* stream) {
+  g_err.clear();
+  Geom G;
+  int st = check_sizes(3, n, p, dtype, &G);
+  if (st) return st;
+  if (!X || !X[0] || !X[1] || !X[2] || !beta || !Y || !loss || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const size_t tsz = align256((size_t)G.n3 * G.P12 * dt_size(dtype));
+  void* T1 = ws;
+  double* part = (double*)(ws + 2 * tsz);
+  FwdParams F{};
+  F.G = G; F.theta = beta; F.X3 = X[2]; F.T1 = T1;
+  HIPCHK(launch_slab_fwd(dtype, F, s));
+  SlabParams S{};
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = T1; S.y_std = Y; S.partials = part;
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_FWD, S, s));
+  const int ops[1] = {0};
+  HIPCHK(launch_reduce_strided(part, G.n3, 2, 1, ops, 1.0 / (double)G.n, loss, s));
+  return GLAM_OK;
+}
+
+int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* const* X, const void* beta,
+                              const double* Y, const double* gscale, void* grad, int dtype, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Geom G;
+  int st = check_sizes(3, n, p, dtype, &G);
+  if (st) return st;
+  if (!X || !X[0] || !X[1] || !X[2] || !beta || !Y || !grad || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const size_t tsz = align256((size_t)G.n3 * G.P12 * dt_size(dtype));
+  void* T1 = ws;
+  void* S2 = ws + tsz;
+  double* part = (double*)(ws + 2 * tsz);
+  FwdParams F{};
+  F.G = G; F.theta = beta; F.X3 = X[2]; F.T1 = T1;
+  HIPCHK(launch_slab_fwd(dtype, F, s));
+  SlabParams S{};
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = T1; S.S2 = S2; S.y_std = Y; S.partials = part;
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, s));
+  AdjParams A{};
+  A.G = G; A.S2 = S2; A.X3 = X[2]; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
+  HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  return GLAM_OK;
+}
+
+}  // extern "C"

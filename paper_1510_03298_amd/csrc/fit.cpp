@@ -1,0 +1,444 @@
+// fit.cpp -- glam_fit_path: the GD-PG lambda path (Sec. 3, Algorithm 1; Sec. 6.4)
+// on one gfx950 GPU.
+//
+// Per lambda, the outer loop of Algorithm 1 runs with FP64 anchors:
+//   step 2 : FP64 chain at theta^k -> eta^k, weights V (eq. nine), score u
+//            (eq. four), -l/n, and the FP64 gradient g^k = -G(U)/n, whose KKT
+//            residual is the convergence criterion;
+//   step 3 : delta = 1 / (nu Lhat), Lhat of Proposition 1;
+//   step 4 : inner PG loop (Sec. 3.2) in the chosen dtype on the increment:
+//            grad h(x) = g^k + G(V .* H(x - theta^k)) / n  (exact because h is
+//            quadratic and grad h(theta^k) = g^k), with FISTA extrapolation;
+//   step 5 : Armijo rule on FP64 reductions (F differences along t d).
+// The low-precision chain only ever sees the increment x - theta^k, and every
+// outer iteration re-anchors at an FP64 gradient: this is the residual
+// correction that lets FP32/BF16 rho products reach an FP64-certified KKT.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "glam.h"
+#include "launch.h"
+
+namespace glam {
+
+// Largest eigenvalue of X^T X (X host, n x p column-major) by cyclic Jacobi
+// rotations on the p x p Gram matrix (Proposition 1 needs rho(X_j^T X_j)).
+static double gram_spectral_radius(const std::vector<double>& X, int n, int p) {
+  std::vector<double> A((size_t)p * p, 0.0);
+  for (int a = 0; a < p; ++a)
+    for (int b = a; b < p; ++b) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += X[(size_t)a * n + i] * X[(size_t)b * n + i];
+      A[(size_t)a * p + b] = s;
+      A[(size_t)b * p + a] = s;
+    }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int a = 0; a < p; ++a) {
+      diag += A[(size_t)a * p + a] * A[(size_t)a * p + a];
+      for (int b = a + 1; b < p; ++b) off += A[(size_t)a * p + b] * A[(size_t)a * p + b];
+    }
+    if (off <= 1e-30 * diag) break;
+    for (int a = 0; a < p; ++a)
+      for (int b = a + 1; b < p; ++b) {
+        const double apq = A[(size_t)a * p + b];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[(size_t)a * p + a], aqq = A[(size_t)b * p + b];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < p; ++k) {
+          const double akp = A[(size_t)k * p + a], akq = A[(size_t)k * p + b];
+          A[(size_t)k * p + a] = c * akp - s * akq;
+          A[(size_t)k * p + b] = s * akp + c * akq;
+        }
+        for (int k = 0; k < p; ++k) {
+          const double apk = A[(size_t)a * p + k], aqk = A[(size_t)b * p + k];
+          A[(size_t)a * p + k] = c * apk - s * aqk;
+          A[(size_t)b * p + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  double m = 0.0;
+  for (int a = 0; a < p; ++a) m = std::max(m, A[(size_t)a * p + a]);
+  return m;
+}
+
+
+static const double kEps[3] = {1.1102230246251565e-16, 5.960464477539063e-08, 3.90625e-03};
+
+struct Fit {
+  Geom G;
+  int dt;
+  hipStream_t s;
+  int family;
+  const glam_problem* prob;
+  // device buffers (owned; freed by the destructor)
+  std::vector<void*> bufs;
+  const void* Xc[3];       // chain-dtype factors
+  double *y_int, *a_int, *eta_int, *xd_int;
+  void* v_int;             // tiled weights (acc type of the chain) or NULL (Gaussian)
+  void *T1c, *S2c;         // chain dtype intermediates
+  double *T1d, *S2d;       // FP64 intermediates
+  double *theta, *gref, *x, *xp, *gp, *dvec;
+  void* inc;
+  int* iter;
+  double* part;            // partial sums
+  double* red;             // reduced values (device)
+  double* hred;            // reduced values (pinned host)
+  double sprod;            // prod_j rho(X_j^T X_j)
+  std::string err;
+
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return p;
+  }
+  Fit() = default;
+  Fit(const Fit&) = delete;
+  Fit& operator=(const Fit&) = delete;
+  ~Fit() {
+    if (!bufs.empty()) (void)hipStreamSynchronize(s);
+    for (void* p : bufs) (void)hipFree(p);
+  }
+};
+
+struct StepStats {
+  double nll;       // -l/n at theta^k
+  double vmax;      // max weight
+  double kkt_raw;   // max KKT residual (absolute)
+  double lmax_raw;  // max |g|/w
+  double pen;       // sum w |theta|
+};
+
+#define FCHK(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      F.err = std::string(#expr) + ": " + hipGetErrorString(e_);                           \
+      return GLAM_EDEVICE;                                                                 \
+    }                                                                                      \
+  } while (0)
+
+// Step 2 of Algorithm 1 at theta (FP64): eta, V, -l/n, g = -G(U)/n, KKT.
+static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats* st) {
+  const Geom& G = F.G;
+  FwdParams fw{};
+  fw.G = G; fw.theta = theta_dev; fw.X3 = F.prob->X[2]; fw.T1 = F.T1d;
+  FCHK(launch_slab_fwd(DT_F64, fw, F.s));
+  SlabParams sp{};
+  sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.S2 = F.S2d;
+  sp.y_int = F.y_int; sp.a_int = F.a_int; sp.eta_int = F.eta_int;
+  sp.v_out = F.v_int; sp.v_out_f32 = F.dt != DT_F64; sp.family = F.family; sp.partials = F.part;
+  FCHK(launch_slab_chain(DT_F64, SM_FAMILY, sp, F.s));
+  const int ops2[2] = {0, 1};
+  FCHK(launch_reduce(F.part, G.n3, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
+  AdjParams ap{};
+  ap.G = G; ap.S2 = F.S2d; ap.X3 = F.prob->X[2]; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
+  ap.theta = theta_dev; ap.pen_w = F.prob->pen_w; ap.lambda = lambda;
+  double* part2 = F.part + (size_t)2 * G.n3;
+  ap.partials = part2;
+  int nb = 0;
+  FCHK(launch_slab_adj(DT_F64, EPI_GRAD, ap, &nb, F.s));
+  const int ops4[4] = {1, 1, 0, 0};
+  FCHK(launch_reduce(part2, nb, 4, ops4, 1.0, F.red + 2, F.s));
+  FCHK(hipMemcpyAsync(F.hred, F.red, 6 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+  FCHK(hipStreamSynchronize(F.s));
+  st->nll = F.hred[0];
+  st->vmax = F.hred[1];
+  st->kkt_raw = F.hred[2];
+  st->lmax_raw = F.hred[3];
+  st->pen = F.hred[4];
+  return GLAM_OK;
+}
+
+// One inner PG iteration (Sec. 3.2) in the chain dtype.
+static int inner_iteration(Fit& F, double lambda, double delta, int* nblk) {
+  const Geom& G = F.G;
+  FwdParams fw{};
+  fw.G = G; fw.theta = F.inc; fw.X3 = F.Xc[2]; fw.T1 = F.T1c; fw.iter = F.iter;
+  FCHK(launch_slab_fwd(F.dt, fw, F.s));
+  SlabParams sp{};
+  sp.G = G; sp.X1 = F.Xc[0]; sp.X2 = F.Xc[1]; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
+  FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, F.s));
+  AdjParams ap{};
+  ap.G = G; ap.S2 = F.S2c; ap.X3 = F.Xc[2]; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+  ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
+  ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta;
+  FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
+  return GLAM_OK;
+}
+
+// Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
+static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* delta_out) {
+  const Geom& G = F.G;
+  // xd = H(d) in FP64 (tiled)
+  FwdParams fw{};
+  fw.G = G; fw.theta = F.dvec; fw.X3 = F.prob->X[2]; fw.T1 = F.T1d;
+  FCHK(launch_slab_fwd(DT_F64, fw, F.s));
+  SlabParams sp{};
+  sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
+  FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, F.s));
+  constexpr int NV = ARMIJO_TRIALS + 1;
+  const int ops[NV] = {0};
+  double Delta = 0.0;
+  for (int j0 = 0; j0 < 64; j0 += ARMIJO_TRIALS) {
+    int nb1 = 0, nb2 = 0;
+    FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
+    FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
+    double* part2 = F.part + (size_t)nb1 * NV;
+    FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, j0, part2, &nb2, F.s));
+    FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
+    FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
+    FCHK(hipStreamSynchronize(F.s));
+    const double* sm = F.hred;         // [0] = sum u xd / n ; [1+j] = smooth change / n
+    const double* pj = F.hred + NV;    // [0] = J(theta~) - J(theta) ; [1+j] = J change at t_j
+    if (j0 == 0) Delta = -sm[0] + lambda * pj[0];
+    for (int j = 0; j < ARMIJO_TRIALS; ++j) {
+      const double t = std::ldexp(1.0, -(j0 + j));
+      const double dF = sm[1 + j] + lambda * pj[1 + j];
+      if (std::isfinite(dF) && dF <= t * v * Delta) {
+        *alpha_out = t;
+        *delta_out = Delta;
+        return GLAM_OK;
+      }
+    }
+  }
+  *alpha_out = 0.0;
+  *delta_out = Delta;
+  return GLAM_OK;
+}
+
+}  // namespace glam
+
+using namespace glam;
+
+static int fit_fail(int code, const std::string& msg);
+
+extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!prob || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
+  if (prob->d != 3) return fit_fail(GLAM_EINVAL, "only d = 3 is supported");
+  for (int j = 0; j < 3; ++j) {
+    if (prob->n[j] < 1 || prob->p[j] < 1) return fit_fail(GLAM_EINVAL, "mode sizes must be >= 1");
+    if (!prob->X[j]) return fit_fail(GLAM_EINVAL, "NULL factor");
+  }
+  if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
+  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) return fit_fail(GLAM_EINVAL, "bad family");
+  if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
+  if (opt->nlambda < 1) return fit_fail(GLAM_EINVAL, "nlambda must be >= 1");
+  if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
+    return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
+  if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
+  if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
+  if (opt->nu != 1.0) return fit_fail(GLAM_EINVAL, "nu < 1 (inner backtracking) is not implemented in this version");
+  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
+    return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
+  if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
+      !res->status)
+    return fit_fail(GLAM_EINVAL, "NULL result array");
+  if (opt->lambda) {
+    for (int l = 0; l < opt->nlambda; ++l) {
+      if (!(opt->lambda[l] >= 0.0) || !std::isfinite(opt->lambda[l]))
+        return fit_fail(GLAM_EINVAL, "lambda values must be finite and >= 0");
+      if (l > 0 && !(opt->lambda[l] < opt->lambda[l - 1]))
+        return fit_fail(GLAM_EINVAL, "lambda sequence must be strictly decreasing");
+    }
+  }
+  size_t ws_probe = glam_rho_workspace_size(3, prob->n, prob->p, opt->dtype);
+  if (ws_probe == 0) return fit_fail(GLAM_EINVAL, glam_last_error());
+  if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024)
+    return fit_fail(GLAM_EINVAL, "modes 1-2 too large for the FP64 slab kernel");
+
+  Fit F;
+  F.G = make_geom(prob->n, prob->p);
+  F.dt = opt->dtype;
+  F.s = (hipStream_t)opt->stream;
+  F.family = prob->family;
+  F.prob = prob;
+  const Geom& G = F.G;
+  const size_t es = dt_size(F.dt);
+  const size_t accs = F.dt == DT_F64 ? 8 : 4;
+  const size_t slab = (size_t)G.n3 * G.P12;
+  const size_t nadj = (size_t)slab_adj_blocks(G);
+  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * 4, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1), nadj * 4});
+
+  bool ok = true;
+  auto A = [&](size_t b) { void* p = F.alloc(b); if (!p) ok = false; return p; };
+  F.y_int = (double*)A(G.nint * 8);
+  F.a_int = (double*)A(G.nint * 8);
+  F.eta_int = (double*)A(G.nint * 8);
+  F.xd_int = (double*)A(G.nint * 8);
+  F.v_int = F.family == GLAM_POISSON ? A(G.nint * accs) : nullptr;
+  F.T1d = (double*)A(slab * 8);
+  F.S2d = (double*)A(slab * 8);
+  if (F.dt == DT_F64) {
+    F.T1c = F.T1d; F.S2c = F.S2d;
+    for (int j = 0; j < 3; ++j) F.Xc[j] = prob->X[j];
+  } else {
+    F.T1c = A(slab * es);
+    F.S2c = A(slab * es);
+    for (int j = 0; j < 3; ++j) F.Xc[j] = A((size_t)prob->n[j] * prob->p[j] * es);
+  }
+  F.theta = (double*)A(G.p * 8);
+  F.gref = (double*)A(G.p * 8);
+  F.x = (double*)A(G.p * 8);
+  F.xp = (double*)A(G.p * 8);
+  F.gp = (double*)A(G.p * 8);
+  F.dvec = (double*)A(G.p * 8);
+  F.inc = A(G.p * es);
+  F.iter = (int*)A(sizeof(int));
+  F.part = (double*)A(npart * 8);
+  F.red = (double*)A(64 * 8);
+  if (!ok) return fit_fail(GLAM_ENOMEM, "device allocation failed");
+  if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess)
+    return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
+  struct HostFree { double* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{F.hred};
+
+#define PCHK(expr)                                                                               \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fit_fail(GLAM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define RCHK(expr)                                \
+  do {                                            \
+    int r_ = (expr);                              \
+    if (r_ != GLAM_OK) return fit_fail(r_, F.err); \
+  } while (0)
+
+  // ---- input checks (device) ----
+  {
+    int nb = 0;
+    PCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family == GLAM_POISSON, F.part, &nb, F.s));
+    const int ops[4] = {1, 1, 1, 1};
+    PCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
+    PCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+    PCHK(hipStreamSynchronize(F.s));
+    if (F.hred[0] != 0.0) return fit_fail(GLAM_EINVAL, "Y has non-finite entries");
+    if (F.hred[1] != 0.0) return fit_fail(GLAM_EINVAL, "Poisson Y must be >= 0");
+    if (F.hred[2] != 0.0) return fit_fail(GLAM_EINVAL, "obs_w must be finite and >= 0");
+    if (F.hred[3] != 0.0) return fit_fail(GLAM_EINVAL, "pen_w must be finite and > 0");
+  }
+  // ---- setup: tiled data, chain copies of the factors, spectral radii ----
+  PCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
+  PCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
+  if (F.dt != DT_F64)
+    for (int j = 0; j < 3; ++j)
+      PCHK(launch_convert(F.dt, prob->X[j], (void*)F.Xc[j], (long long)prob->n[j] * prob->p[j], F.s));
+  F.sprod = 1.0;
+  for (int j = 0; j < 3; ++j) {
+    std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
+    PCHK(hipMemcpyAsync(hx.data(), prob->X[j], hx.size() * 8, hipMemcpyDeviceToHost, F.s));
+    PCHK(hipStreamSynchronize(F.s));
+    F.sprod *= gram_spectral_radius(hx, (int)prob->n[j], (int)prob->p[j]);
+  }
+  // ---- lambda_max: the zero solution's gradient (Sec. 6.4) ----
+  PCHK(launch_fill(F.theta, G.p, 0.0, F.s));
+  StepStats st0;
+  RCHK(family_step(F, F.theta, 0.0, &st0));
+  const double lam_max = st0.lmax_raw;
+  res->lambda_max = lam_max;
+  if (!std::isfinite(lam_max)) return fit_fail(GLAM_ENONFINITE, "non-finite lambda_max");
+  const double lam_scale = lam_max > 0.0 ? lam_max : 1.0;
+  std::vector<double> lams(opt->nlambda);
+  for (int l = 0; l < opt->nlambda; ++l) {
+    if (opt->lambda) lams[l] = opt->lambda[l];
+    else lams[l] = opt->nlambda == 1 ? lam_max
+                                     : lam_max * std::pow(opt->lambda_min_ratio, (double)l / (opt->nlambda - 1));
+  }
+  if (opt->theta0) PCHK(hipMemcpyAsync(F.theta, opt->theta0, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+
+  const bool exact_model = F.family == GLAM_GAUSSIAN && prob->obs_w == nullptr;
+  const double tol = opt->kkt_tol;
+  const int check_every = opt->check_every;
+  const bool verbose = getenv("GLAM_LOG") && atoi(getenv("GLAM_LOG")) > 0;
+  int path_status = GLAM_OK;
+  res->n_done = 0;
+
+  for (int l = 0; l < opt->nlambda; ++l) {
+    const double lam = lams[l];
+    res->lambda_out[l] = lam;
+    int status = GLAM_ENOCONV;
+    int outer = 0;
+    long long inner_total = 0;
+    StepStats st{};
+    double kkt = INFINITY, Fobj = NAN;
+    for (int k = 0; k <= opt->max_outer; ++k) {
+      RCHK(family_step(F, F.theta, lam, &st));
+      kkt = st.kkt_raw / lam_scale;
+      Fobj = st.nll + lam * st.pen;
+      outer = k;
+      if (!std::isfinite(kkt) || !std::isfinite(Fobj)) { status = GLAM_ENONFINITE; break; }
+      if (kkt <= tol) { status = GLAM_OK; break; }
+      if (k == opt->max_outer) break;
+      const double wmax = F.family == GLAM_POISSON ? st.vmax : 1.0;
+      const double Lhat = wmax * F.sprod / (double)G.n;
+      if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
+      const double delta = 1.0 / (opt->nu * Lhat);
+      const double tol_in = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
+      // ---- inner PG loop ----
+      PCHK(launch_inner_init(G.p, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      int it = 0;
+      double kin = INFINITY, noise = 0.0;
+      while (it < opt->max_inner) {
+        int nb = 0;
+        const int m = std::min(check_every, opt->max_inner - it);
+        for (int q = 0; q < m; ++q) RCHK(inner_iteration(F, lam, delta, &nb));
+        it += m;
+        const int ops[4] = {1, 1, 0, 0};
+        PCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
+        PCHK(hipMemcpyAsync(F.hred, F.red, 2 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+        PCHK(hipStreamSynchronize(F.s));
+        kin = F.hred[0] / lam_scale;
+        noise = 8.0 * kEps[F.dt] * F.hred[1] / lam_scale;
+        if (!std::isfinite(kin)) break;
+        if (kin <= std::max(tol_in, noise)) break;
+      }
+      inner_total += it;
+      if (!std::isfinite(kin)) { status = GLAM_ENONFINITE; break; }
+      // theta~ = x^l of the last checked iteration (held in xp)
+      PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
+      double alpha = 0.0, Delta = 0.0;
+      RCHK(armijo(F, lam, 0.1, &alpha, &Delta));
+      if (verbose)
+        fprintf(stderr, "[glam] lambda %d k %d kkt %.3e F %.12e inner %d kin %.2e noise %.2e alpha %g Delta %.3e\n", l,
+                k, kkt, Fobj, it, kin, noise, alpha, Delta);
+      if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
+    }
+    PCHK(hipMemcpyAsync(res->theta + (size_t)l * G.p, F.theta, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+    res->kkt[l] = kkt;
+    res->objective[l] = Fobj;
+    res->iters_outer[l] = outer;
+    res->iters_inner[l] = (int)std::min<long long>(inner_total, 2000000000LL);
+    res->status[l] = status;
+    if (verbose)
+      fprintf(stderr, "[glam] lambda %d = %.6e status %d kkt %.3e outer %d inner %lld\n", l, lam, status, kkt, outer,
+              inner_total);
+    if (status != GLAM_OK) {
+      path_status = status;
+      break;
+    }
+    res->n_done = l + 1;
+  }
+  PCHK(hipStreamSynchronize(F.s));
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (path_status != GLAM_OK) return fit_fail(path_status, "path stopped early (see status array)");
+  return GLAM_OK;
+}
+
+namespace glam {
+void set_last_error(const std::string& msg);   // api.cpp
+}
+static int fit_fail(int code, const std::string& msg) {
+  glam::set_last_error(msg);
+  return code;
+}

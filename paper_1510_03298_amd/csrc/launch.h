@@ -1,0 +1,140 @@
+// launch.h -- host-side launchers of the gfx950 kernels (internal to the library).
+//
+// Geometry used by every kernel.  The rho chain of Sec. 6.1 is evaluated with
+// mode 3 as the "slab" mode: the mode-3 products are plain GEMMs (one launch
+// each, kernels "slab_fwd" and "slab_adj"), and the mode-1 and mode-2 products
+// of one i_3 slab run inside one workgroup with all intermediates in registers
+// (kernel "slab_chain").  Modes 1 and 2 are padded to 16-row tiles.
+//
+// Internal n-array layout ("tiled"): for slab i3, mode-2 tile jb, mode-1 tile
+// ut, a 16 x 16 tile stored column-major (i1 fastest):
+//   index = ((i3 * NJB + jb) * N1T + ut) * 256 + (i2 % 16) * 16 + (i1 % 16),
+// with zeros in the padding.  Slab-GEMM intermediates T1 and S2 are stored as
+// [i3][m], m = i1 + p1 * i2 (one contiguous p1 x p2 slab per i3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace glam {
+
+struct Geom {
+  int n1, n2, n3, p1, p2, p3;
+  int P12;          // p1 * p2
+  int N1T, NJB;     // ceil(n1 / 16), ceil(n2 / 16)
+  int PT;           // ceil(max(p1, p2) / 16), 1 or 2
+  long long nint;   // length of a tiled n-array
+  long long n;      // n1 * n2 * n3
+  long long p;      // p1 * p2 * p3
+};
+
+Geom make_geom(const int64_t* n, const int64_t* p);
+
+enum Dt { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+inline size_t dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+
+enum SlabMode {
+  SM_FWD_STD = 0,   // eta (standard layout, FP64 for F64 else FP32)
+  SM_FWD_INT = 1,   // eta (tiled layout, accumulation type)
+  SM_ADJ_STD = 2,   // R read from a standard-layout n-array of the chain type
+  SM_FUSED = 3,     // R = eta (.* V tiled) -> S2  (inner-loop gradient)
+  SM_FAMILY = 4,    // FP64: eta -> (eta, V, u, -l partial sums) -> R = u -> S2
+  SM_NLL_FWD = 5,   // eta -> partial sums of exp(eta) - y eta
+  SM_NLL_BWD = 6    // eta -> R = exp(eta) - y -> S2
+};
+
+struct SlabParams {
+  Geom G;
+  const void* X1;     // chain type, n1 x p1 column-major
+  const void* X2;     // chain type, n2 x p2 column-major
+  const void* T1;     // chain type [n3][P12]
+  void* S2;           // chain type [n3][P12]
+  void* eta_out;      // FWD_STD / FWD_INT output
+  const void* u_in;   // ADJ_STD input (chain type, standard layout)
+  const void* v_int;  // FUSED weights (tiled, accumulation type) or NULL = 1
+  // FAMILY (FP64 chain)
+  const double* y_int;
+  const double* a_int;
+  double* eta_int;
+  void* v_out;        // tiled weights written for the inner loop (FP32 or FP64), may be NULL
+  int v_out_f32;      // 1: v_out is float, 0: double
+  int family;         // 0 Gaussian, 1 Poisson
+  // NLL (standard-layout FP64 counts)
+  const double* y_std;
+  double* partials;   // per-workgroup partial sums [n3][nsum]
+};
+
+enum AdjEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_PROX = 2 };
+
+struct AdjParams {
+  Geom G;
+  const void* S2;     // chain type [n3][P12]
+  const void* X3;     // chain type n3 x p3 column-major
+  void* out;          // EPI_STORE: p-array (FP64 for F64 chains, FP32 otherwise)
+  double scale;       // EPI_STORE: out = scale * acc ; EPI_GRAD: g = scale * acc
+  const double* gscale_dev;  // EPI_STORE: optional device scalar multiplier
+  // EPI_GRAD: g = scale * acc written to gout; KKT / lambda_max partial maxima
+  double* gout;
+  const double* theta;   // FP64 p-array (KKT at theta) or NULL
+  const double* pen_w;   // FP64 p-array or NULL
+  double lambda;
+  double* partials;      // per-workgroup [nblk][4]: max KKT residual, max |g|/w, sum w|theta|, unused
+  // EPI_PROX (inner PG iteration, FP64 state)
+  const double* gref;    // gradient at the anchor
+  const double* theta_ref;
+  double* x;             // x^l   (updated to x^{l+1})
+  double* xp;            // x^{l-1} (updated to x^l)
+  double* gp;            // grad h(x^{l-1}) (updated to grad h(x^l))
+  void* inc;             // chain type: x^{l+1} - theta_ref
+  const int* iter;       // device iteration counter l
+  double delta;          // step size
+};
+
+struct FwdParams {
+  Geom G;
+  const void* theta;  // chain type p-array (standard layout)
+  const void* X3;     // chain type n3 x p3
+  void* T1;           // chain type [n3][P12]
+  int* iter;          // optional: incremented once by the first thread
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
+hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, hipStream_t s);
+hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, hipStream_t s);
+size_t slab_chain_lds_bytes(int dt, const Geom& G);
+int slab_adj_blocks(const Geom& G);
+
+// small kernels
+// out[v] = scale * sum_b partials[b][v]  (ops[v] == 0)  or  max_b partials[b][v]  (ops[v] == 1);
+// summation order is fixed, so results are reproducible run to run.
+hipError_t launch_reduce(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
+                         hipStream_t s);
+// same with partials[b * stride + v], v < nval <= stride
+hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
+                                 double* out, hipStream_t s);
+hipError_t launch_convert(int dt, const double* src, void* dst, long long count, hipStream_t s);
+hipError_t launch_to_tiled(const Geom& G, const double* src_std, double fill_valid, double* dst_tiled,
+                           hipStream_t s);
+hipError_t launch_inner_init(long long p, const double* theta, const double* gref, double* x, double* xp,
+                             double* gp, int dt, void* inc, int* iter, hipStream_t s);
+hipError_t launch_sub(long long p, const double* a, const double* b, double* out, hipStream_t s);
+hipError_t launch_axpy(long long p, double alpha, const double* d, double* theta, hipStream_t s);
+hipError_t launch_armijo(const Geom& G, int family, const double* eta_int, const double* xd_int,
+                         const double* y_int, const double* a_int, int j0, double* partials, int* nblk_out,
+                         hipStream_t s);
+hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);
+// sum_m w_m (|theta_m + t_j d_m| - |theta_m|) for t = 1 (slot 0) and the Armijo trial steps (slots 1..)
+hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, int j0,
+                             double* partials, int* nblk_out, hipStream_t s);
+// data checks, per-block maxima of 4 indicators: non-finite y, negative y (Poisson),
+// negative or non-finite a, non-positive or non-finite pen_w
+hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int poisson,
+                        double* partials, int* nblk_out, hipStream_t s);
+
+constexpr int ARMIJO_TRIALS = 16;   // step sizes 2^-j0 .. 2^-(j0+15) evaluated in one pass
+constexpr int FAMILY_NSUM = 2;      // -l partial sum, max weight
+constexpr int GRAD_NSUM = 4;
+
+}  // namespace glam

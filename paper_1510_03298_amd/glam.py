@@ -1,0 +1,320 @@
+"""ctypes binding of libglam.so (the C ABI of include/glam.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  torch tensors supply device memory and the HIP stream.  Importing this
+module raises if the built library is missing (build it with
+``python -m paper_1510_03298_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libglam.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1510_03298_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+GLAM_OK, GLAM_EINVAL, GLAM_ENOMEM, GLAM_EDEVICE, GLAM_ENOCONV, GLAM_ENONFINITE = range(6)
+GAUSSIAN, POISSON = 0, 1
+F64, F32, BF16 = 0, 1, 2
+MAX_INNER_P = 32
+MAX_INNER_N = 256
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+FAMILIES = {"gaussian": GAUSSIAN, "poisson": POISSON}
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+class GlamProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("p", ctypes.c_int64 * 3),
+                ("X", _vp * 3), ("Y", _vp), ("obs_w", _vp), ("family", ctypes.c_int), ("pen_w", _vp)]
+
+
+class GlamOptions(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("nlambda", ctypes.c_int),
+                ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
+                ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp)]
+
+
+class GlamResult(ctypes.Structure):
+    _fields_ = [("theta", _vp), ("lambda_out", ctypes.POINTER(ctypes.c_double)),
+                ("kkt", ctypes.POINTER(ctypes.c_double)), ("objective", ctypes.POINTER(ctypes.c_double)),
+                ("iters_outer", ctypes.POINTER(ctypes.c_int)), ("iters_inner", ctypes.POINTER(ctypes.c_int)),
+                ("status", ctypes.POINTER(ctypes.c_int)), ("n_done", ctypes.c_int), ("lambda_max", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+glam_status_string = _sig("glam_status_string", ctypes.c_char_p, [ctypes.c_int])
+glam_last_error = _sig("glam_last_error", ctypes.c_char_p, [])
+glam_version = _sig("glam_version", ctypes.c_char_p, [])
+glam_rho_workspace_size = _sig("glam_rho_workspace_size", ctypes.c_size_t, [ctypes.c_int, _i64p, _i64p, ctypes.c_int])
+glam_rho_forward = _sig("glam_rho_forward", ctypes.c_int,
+                        [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_int, _vp,
+                         ctypes.c_size_t, _vp])
+glam_rho_adjoint = _sig("glam_rho_adjoint", ctypes.c_int,
+                        [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_int, _vp,
+                         ctypes.c_size_t, _vp])
+glam_fit_path = _sig("glam_fit_path", ctypes.c_int,
+                     [ctypes.POINTER(GlamProblem), ctypes.POINTER(GlamOptions), ctypes.POINTER(GlamResult)])
+glam_nll_workspace_size = _sig("glam_nll_workspace_size", ctypes.c_size_t, [_i64p, _i64p, ctypes.c_int])
+glam_poisson_nll_forward = _sig("glam_poisson_nll_forward", ctypes.c_int,
+                                [_i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int, _vp,
+                                 ctypes.c_size_t, _vp])
+glam_poisson_nll_backward = _sig("glam_poisson_nll_backward", ctypes.c_int,
+                                 [_i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp, ctypes.c_int, _vp,
+                                  ctypes.c_size_t, _vp])
+
+EXPORTED = ["glam_status_string", "glam_last_error", "glam_version", "glam_rho_workspace_size",
+            "glam_rho_forward", "glam_rho_adjoint", "glam_fit_path", "glam_nll_workspace_size",
+            "glam_poisson_nll_forward", "glam_poisson_nll_backward"]
+
+
+class GlamError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        msg = glam_status_string(code).decode()
+        detail = glam_last_error().decode()
+        super().__init__(f"{where}: {msg} ({detail})" if where else f"{msg} ({detail})")
+
+
+def _check(code, where):
+    if code != GLAM_OK:
+        raise GlamError(code, where)
+
+
+# ----------------------------------------------------------------------------- torch helpers
+def _torch():
+    import torch
+    return torch
+
+
+def torch_dtype(dt):
+    torch = _torch()
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[dt]
+
+
+def out_dtype(dt):
+    torch = _torch()
+    return torch.float64 if dt == F64 else torch.float32
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _sizes(n, p):
+    return (ctypes.c_int64 * 3)(*[int(v) for v in n]), (ctypes.c_int64 * 3)(*[int(v) for v in p])
+
+
+def _fortran_flat(t):
+    """Column-major (vec) flattening of a 3-D torch tensor."""
+    return t.permute(*reversed(range(t.dim()))).contiguous().reshape(-1)
+
+
+def to_device_colmajor(a, dtype, device="cuda"):
+    """numpy array (any order) -> 1-D device tensor holding its column-major vec."""
+    torch = _torch()
+    flat = np.asarray(a, dtype=np.float64).reshape(-1, order="F")
+    tdt = torch_dtype(dtype) if isinstance(dtype, int) else dtype
+    return torch.from_numpy(np.ascontiguousarray(flat)).to(tdt).to(device=device)
+
+
+def from_colmajor(t, dims):
+    return t.detach().to("cpu", dtype=_torch().float64).numpy().reshape(tuple(dims), order="F")
+
+
+# ----------------------------------------------------------------------------- rho transforms
+def rho_workspace_size(n, p, dtype):
+    nn, pp = _sizes(n, p)
+    return int(glam_rho_workspace_size(3, nn, pp, int(dtype)))
+
+
+def rho_forward(Xs, theta, n, p, dtype, eta=None, workspace=None, stream=None):
+    """eta = H(<X_j>, theta) on the device (all tensors 1-D column-major device tensors)."""
+    torch = _torch()
+    nn, pp = _sizes(n, p)
+    ws_bytes = rho_workspace_size(n, p, dtype)
+    if ws_bytes == 0:
+        raise GlamError(GLAM_EINVAL, "rho_forward")
+    if workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=theta.device)
+    if eta is None:
+        eta = torch.empty(int(np.prod(n)), dtype=out_dtype(dtype), device=theta.device)
+    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
+    _check(glam_rho_forward(3, nn, pp, xp, theta.data_ptr(), eta.data_ptr(), int(dtype), workspace.data_ptr(),
+                            ws_bytes, _stream_ptr(stream)), "glam_rho_forward")
+    return eta
+
+
+def rho_adjoint(Xs, U, n, p, dtype, out=None, workspace=None, stream=None):
+    """out = G(<X_j>, U) on the device."""
+    torch = _torch()
+    nn, pp = _sizes(n, p)
+    ws_bytes = rho_workspace_size(n, p, dtype)
+    if ws_bytes == 0:
+        raise GlamError(GLAM_EINVAL, "rho_adjoint")
+    if workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=U.device)
+    if out is None:
+        out = torch.empty(int(np.prod(p)), dtype=out_dtype(dtype), device=U.device)
+    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
+    _check(glam_rho_adjoint(3, nn, pp, xp, U.data_ptr(), out.data_ptr(), int(dtype), workspace.data_ptr(),
+                            ws_bytes, _stream_ptr(stream)), "glam_rho_adjoint")
+    return out
+
+
+# ----------------------------------------------------------------------------- Poisson NLL
+def nll_workspace_size(n, p, dtype):
+    nn, pp = _sizes(n, p)
+    return int(glam_nll_workspace_size(nn, pp, int(dtype)))
+
+
+def poisson_nll_forward(Xs, beta, Y, n, p, dtype, workspace=None, stream=None):
+    torch = _torch()
+    nn, pp = _sizes(n, p)
+    wsb = nll_workspace_size(n, p, dtype)
+    if workspace is None:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=beta.device)
+    loss = torch.empty(1, dtype=torch.float64, device=beta.device)
+    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
+    _check(glam_poisson_nll_forward(nn, pp, xp, beta.data_ptr(), Y.data_ptr(), loss.data_ptr(), int(dtype),
+                                    workspace.data_ptr(), wsb, _stream_ptr(stream)), "glam_poisson_nll_forward")
+    return loss
+
+
+def poisson_nll_backward(Xs, beta, Y, gscale, n, p, dtype, workspace=None, stream=None):
+    torch = _torch()
+    nn, pp = _sizes(n, p)
+    wsb = nll_workspace_size(n, p, dtype)
+    if workspace is None:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=beta.device)
+    grad = torch.empty(int(np.prod(p)), dtype=out_dtype(dtype), device=beta.device)
+    gs = gscale.to(torch.float64).reshape(1).contiguous()
+    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
+    _check(glam_poisson_nll_backward(nn, pp, xp, beta.data_ptr(), Y.data_ptr(), gs.data_ptr(), grad.data_ptr(),
+                                     int(dtype), workspace.data_ptr(), wsb, _stream_ptr(stream)),
+           "glam_poisson_nll_backward")
+    return grad
+
+
+class PoissonNLL:
+    """torch.autograd.Function for L(beta) = (1/n) sum(exp(eta) - y eta), eta = H(beta).
+
+    Usage: ``loss = PoissonNLL.apply(beta, Xs, Y, n, p, dtype)``; beta is a 1-D
+    column-major device tensor of the chain dtype (its gradient is returned as
+    FP32 for F32/BF16 and FP64 for F64, cast to beta's dtype)."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, beta, Xs, Y, n, p, dtype):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, b, Xs_, Y_, n_, p_, dt_):
+                    ctx.save_for_backward(b)
+                    ctx.extra = (Xs_, Y_, n_, p_, dt_)
+                    return poisson_nll_forward(Xs_, b.detach().contiguous(), Y_, n_, p_, dt_).reshape(())
+
+                @staticmethod
+                def backward(ctx, gout):
+                    (b,) = ctx.saved_tensors
+                    Xs_, Y_, n_, p_, dt_ = ctx.extra
+                    g = poisson_nll_backward(Xs_, b.detach().contiguous(), Y_, gout.reshape(1), n_, p_, dt_)
+                    return g.to(b.dtype), None, None, None, None, None
+
+            cls._fn = _F
+        return cls._fn.apply(beta, Xs, Y, n, p, dtype)
+
+
+# ----------------------------------------------------------------------------- lambda path
+@dataclass
+class PathResult:
+    lambdas: np.ndarray
+    theta: "object"          # device tensor (nlambda, p) FP64, column-major p-arrays
+    kkt: np.ndarray
+    objective: np.ndarray
+    iters_outer: np.ndarray
+    iters_inner: np.ndarray
+    status: np.ndarray
+    n_done: int
+    lambda_max: float
+    seconds: float
+    code: int
+
+
+def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
+             lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
+             check_every=10, theta0=None, stream=None, raise_on_error=True) -> PathResult:
+    """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
+    1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays."""
+    torch = _torch()
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    prob = GlamProblem()
+    prob.d = 3
+    for j in range(3):
+        prob.n[j] = int(n[j])
+        prob.p[j] = int(p[j])
+        prob.X[j] = Xs[j].data_ptr()
+    prob.Y = Y.data_ptr()
+    prob.obs_w = obs_w.data_ptr() if obs_w is not None else None
+    prob.family = fam
+    prob.pen_w = pen_w.data_ptr() if pen_w is not None else None
+    L = int(nlambda if lambdas is None else len(lambdas))
+    lam_arr = None
+    opt = GlamOptions()
+    if lambdas is not None:
+        lam_arr = (ctypes.c_double * L)(*[float(v) for v in lambdas])
+        opt.lambda_ = lam_arr
+    opt.nlambda = L
+    opt.lambda_min_ratio = float(lambda_min_ratio)
+    opt.dtype = int(dtype)
+    opt.kkt_tol = float(kkt_tol)
+    opt.nu = float(nu)
+    opt.max_outer = int(max_outer)
+    opt.max_inner = int(max_inner)
+    opt.check_every = int(check_every)
+    opt.theta0 = theta0.data_ptr() if theta0 is not None else None
+    opt.stream = _stream_ptr(stream)
+    P = int(np.prod(p))
+    theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
+    lam_out = (ctypes.c_double * L)()
+    kkt = (ctypes.c_double * L)()
+    obj = (ctypes.c_double * L)()
+    io = (ctypes.c_int * L)()
+    ii = (ctypes.c_int * L)()
+    stt = (ctypes.c_int * L)(*([-1] * L))
+    res = GlamResult()
+    res.theta = theta.data_ptr()
+    res.lambda_out, res.kkt, res.objective = lam_out, kkt, obj
+    res.iters_outer, res.iters_inner, res.status = io, ii, stt
+    code = glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    if code == GLAM_EINVAL or code == GLAM_ENOMEM or code == GLAM_EDEVICE:
+        raise GlamError(code, "glam_fit_path")
+    out = PathResult(np.array(lam_out[:]), theta, np.array(kkt[:]), np.array(obj[:]), np.array(io[:]),
+                     np.array(ii[:]), np.array(stt[:]), int(res.n_done), float(res.lambda_max),
+                     float(res.seconds), int(code))
+    if raise_on_error and code != GLAM_OK:
+        raise GlamError(code, "glam_fit_path")
+    return out

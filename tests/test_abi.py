@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glam.h")
+LIB = os.path.join(ROOT, "paper_1510_03298_amd", "libglam.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(glam_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libglam.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["glam_fit_path", "glam_rho_forward", "glam_rho_adjoint", "glam_rho_workspace_size",
+                     "glam_poisson_nll_forward", "glam_poisson_nll_backward", "glam_status_string",
+                     "glam_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib()
+    for name in declared_functions():
+        assert hasattr(L, name), f"{name} declared in glam.h but not exported"
+
+
+def test_binding_exports_match_header():
+    from paper_1510_03298_amd import glam
+    assert sorted(glam.EXPORTED) == declared_functions()
+
+
+def test_status_strings_and_version():
+    from paper_1510_03298_amd import glam
+    assert glam.glam_status_string(0) == b"ok"
+    assert b"invalid" in glam.glam_status_string(1)
+    assert b"gfx950" in glam.glam_version()
+
+
+def _sizes(n, p):
+    return (ctypes.c_int64 * 3)(*n), (ctypes.c_int64 * 3)(*p)
+
+
+def test_workspace_size_and_limits():
+    from paper_1510_03298_amd import glam
+    n, p = _sizes((100, 100, 1000), (30, 30, 200))
+    al = lambda b: (b + 255) // 256 * 256
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == al(1000 * 900 * 4)
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) == al(1000 * 900 * 8)
+    assert glam.glam_rho_workspace_size(2, n, p, glam.F64) == 0          # d must be 3
+    n, p = _sizes((100, 100, 1000), (33, 30, 200))
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # p_1 beyond the inner-mode limit
+    n, p = _sizes((0, 100, 1000), (3, 3, 3))
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # empty mode
+    n, p = _sizes((256, 256, 10), (32, 32, 3))
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) > 0
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) == 0          # FP64 copies exceed the LDS budget
+    assert b"LDS" in glam.glam_last_error()
+
+
+def test_invalid_arguments_rejected_without_device_work():
+    from paper_1510_03298_amd import glam
+    n, p = _sizes((10, 10, 10), (4, 4, 4))
+    X = (ctypes.c_void_p * 3)(None, None, None)
+    rc = glam.glam_rho_forward(3, n, p, X, None, None, glam.F64, None, 0, None)
+    assert rc == glam.GLAM_EINVAL and b"NULL" in glam.glam_last_error()
+    rc = glam.glam_rho_adjoint(4, n, p, X, None, None, glam.F64, None, 0, None)
+    assert rc == glam.GLAM_EINVAL
+    rc = glam.glam_rho_forward(3, n, p, X, None, None, 7, None, 0, None)
+    assert rc == glam.GLAM_EINVAL
+    assert glam.glam_fit_path(None, None, None) == glam.GLAM_EINVAL
+    prob = glam.GlamProblem()
+    prob.d = 3
+    for j in range(3):
+        prob.n[j], prob.p[j] = 10, 4
+    opt = glam.GlamOptions()
+    res = glam.GlamResult()
+    rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    assert rc == glam.GLAM_EINVAL       # NULL factors
+    # a non-decreasing lambda sequence is rejected before any device work
+    dummy = ctypes.c_double(0.0)
+    for j in range(3):
+        prob.X[j] = ctypes.addressof(dummy)
+    prob.Y = ctypes.addressof(dummy)
+    lam = (ctypes.c_double * 3)(1.0, 2.0, 0.5)
+    opt.lambda_ = lam
+    opt.nlambda = 3
+    opt.kkt_tol, opt.nu, opt.max_outer, opt.max_inner, opt.check_every = 1e-6, 1.0, 10, 10, 1
+    out = (ctypes.c_double * 3)()
+    io = (ctypes.c_int * 3)()
+    res.theta = ctypes.addressof(dummy)
+    res.lambda_out = res.kkt = res.objective = out
+    res.iters_outer = res.iters_inner = res.status = io
+    rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    assert rc == glam.GLAM_EINVAL and b"decreasing" in glam.glam_last_error()
+    opt.nu = 0.0
+    lam2 = (ctypes.c_double * 3)(3.0, 2.0, 1.0)
+    opt.lambda_ = lam2
+    assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL

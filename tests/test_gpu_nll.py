@@ -1,0 +1,84 @@
+"""Poisson NLL forward/backward (torch.autograd.Function over the fused adjoint
+kernel) against the oracle and central finite differences."""
+import numpy as np
+import pytest
+
+import oracle.glam_oracle as O
+from paper_1510_03298_amd import inputs
+from tests.gpu_util import need_gpu, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5, 2: 3e-2}
+
+
+def _check(glam, d, beta, loss, grad, dt):
+    """Value: relative to sum |exp(eta) - y eta| / n.  Gradient: entrywise, relative
+    to G(|X|, |exp(eta) - y|) / n, the sum of magnitudes of the terms (the
+    gradient itself cancels, so the rounding bound scales with these sums)."""
+    eta = O.H(d.X, beta)
+    Lref = O.poisson_nll(d.X, beta, d.Y)
+    Lscale = float(np.sum(np.abs(np.exp(eta) - d.Y * eta))) / d.Y.size
+    assert abs(loss - Lref) <= TOL[dt] * Lscale, (loss, Lref)
+    gref = O.poisson_nll_grad(d.X, beta, d.Y)
+    gabs = O.G([np.abs(X) for X in d.X], np.abs(np.exp(eta) - d.Y)) / d.Y.size
+    g = glam.from_colmajor(grad.float() if dt else grad, d.p)
+    err = float(np.max(np.abs(g - gref) / gabs))
+    assert err <= TOL[dt], err
+
+
+@pytest.mark.parametrize("dt", [0, 1, 2])
+@pytest.mark.parametrize("n,p", [((21, 18, 30), (7, 6, 9)), ((40, 33, 17), (20, 17, 5))])
+def test_nll_value_and_gradient(n, p, dt):
+    torch, glam = need_gpu()
+    print(f"nll n={n} p={p} dt={dt}", flush=True)
+    d = inputs.random_problem(n, p, family="poisson", seed=31, scale=0.3)
+    beta = np.random.default_rng(5).normal(0.0, 0.2, p)
+    Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    b = glam.to_device_colmajor(beta, dt).requires_grad_(True)
+    loss = glam.PoissonNLL.apply(b, Xd, Yd, n, p, dt)
+    loss.backward()
+    torch.cuda.synchronize()
+    Lref = O.poisson_nll(d.X, beta, d.Y)
+    _check(glam, d, beta, float(loss.detach()), b.grad, dt)
+
+
+def test_nll_gradient_central_differences_f64():
+    """Gradient of the device loss vs central differences of the device loss (h = 1e-6)."""
+    torch, glam = need_gpu()
+    n, p = (16, 12, 10), (5, 4, 3)
+    d = inputs.random_problem(n, p, family="poisson", seed=32, scale=0.3, basis="gauss")
+    beta = np.random.default_rng(6).normal(0.0, 0.2, p)
+    Xd = [glam.to_device_colmajor(X, 0) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    b = glam.to_device_colmajor(beta, 0).requires_grad_(True)
+    glam.PoissonNLL.apply(b, Xd, Yd, n, p, 0).backward()
+    g = b.grad.cpu().numpy()
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for _ in range(16):
+        v = rng.standard_normal(b.numel())
+        v /= np.linalg.norm(v)
+        vd = torch.from_numpy(v).cuda()
+        with torch.no_grad():
+            lp = float(glam.poisson_nll_forward(Xd, b + h * vd, Yd, n, p, 0))
+            lm = float(glam.poisson_nll_forward(Xd, b - h * vd, Yd, n, p, 0))
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - float(g @ v)) <= 1e-7 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+def test_nll_full_size_workload(dt):
+    """n=(128,128,256), p=(32,32,64): value and gradient vs the FP64 oracle."""
+    torch, glam = need_gpu()
+    d = inputs.config_c5()
+    n, p = d.n, d.p
+    beta = d.extra["beta"]
+    Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    b = glam.to_device_colmajor(beta, dt).requires_grad_(True)
+    loss = glam.PoissonNLL.apply(b, Xd, Yd, n, p, dt)
+    loss.backward()
+    torch.cuda.synchronize()
+    _check(glam, d, beta, float(loss.detach()), b.grad, dt)
