@@ -1,0 +1,189 @@
+"""Benchmark: lambda-path fit time of the GD-PG solver on one MI355X.
+
+Workload: Gaussian 3-D GLAM, n = (100, 100, 1000), p = (30, 30, 200) clamped
+cubic B-spline factors, smooth spatio-temporal signal + N(0,1) noise, a
+100-value log-spaced lambda path down to 1e-4 lambda_max, every model fitted to
+an FP64 KKT residual <= 1e-6.  One "step" is one whole path fit (all rows of the
+hot path: rho chains, family update, prox, Armijo, KKT, warm starts).
+
+Prints one JSON line.  The timed form is the inner-chain dtype --dtype (default
+bf16); the other forms (f32, f64) are run once each, untimed, for the
+speed-up at equal accuracy.  The dominant kernel (the fused slab kernel of the
+inner iteration) is timed live with HIP events on the fit's stream.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
+}
+METRIC = "lambda-path fit time & rho-transform TFLOP/s at KKT<=1e-6, BF16/FP32 vs FP64"
+
+
+def flop_model(n, p):
+    """Algorithmic flops of one inner iteration in the executed mode order
+    (mode 3 first forward, last adjoint): slab_fwd, fused slab chain, slab_adj."""
+    n1, n2, n3 = n
+    p1, p2, p3 = p
+    fwd3 = 2 * p1 * p2 * p3 * n3
+    chain = 4 * p1 * n2 * (p2 + n1) * n3       # T2, eta, S1, S2 for every slab
+    adj3 = 2 * p1 * p2 * n3 * p3
+    return fwd3, chain, adj3
+
+
+def chain_bytes(n, p, dt_bytes, poisson=False):
+    """Algorithmic HBM bytes of one fused slab-chain launch: read T1, write S2
+    (p1 p2 n3 each, chain dtype), read the factors once (and V for Poisson)."""
+    n1, n2, n3 = n
+    p1, p2, p3 = p
+    b = 2 * p1 * p2 * n3 * dt_bytes + (n1 * p1 + n2 * p2) * dt_bytes
+    if poisson:
+        b += n1 * n2 * n3 * 4
+    return b
+
+
+def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
+    """The oracle (plain NumPy FP64, never tuned) on the host cores: seconds per
+    inner PG iteration at this workload's size, measured on a bounded sample,
+    extrapolated to the full path with the FP64 GPU form's iteration counts."""
+    import oracle.glam_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    n = d.Y.size
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    lam = lm * (1e-4) ** (1.0 / 99.0)
+    V = np.ones_like(d.Y)
+    cz = O.G(d.X, d.Y) / n
+    theta0 = np.zeros(d.p)
+    s_prod = float(np.prod(O.spectral_radii(d.X)))
+    delta = n / s_prod
+    t0 = time.perf_counter()
+    iters = 0
+    while time.perf_counter() - t0 < budget_s and iters < 200:
+        O.inner_pg(d.X, V, cz, theta0, lam, delta, None, -1.0, lm, 1)
+        iters += 1
+    per_iter = (time.perf_counter() - t0) / iters
+    # one oracle inner iteration evaluates grad h twice (at y and at x^{l+1}); the
+    # GPU evaluates it once, so the per-gradient cost is the fair unit
+    per_grad = per_iter / 2.0
+    est = per_grad * (total_inner_f64 + 3 * outer_f64)
+    return {
+        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"{iters} oracle inner PG iterations at lambda_1 of the same workload "
+                   f"({per_grad*1e3:.1f} ms per gradient evaluation), extrapolated to the full path with "
+                   f"the FP64 GPU form's {total_inner_f64} inner iterations and {outer_f64} outer steps"),
+        "extrapolated": True,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="bf16", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--nlambda", type=int, default=100)
+    ap.add_argument("--no-compare", action="store_true", help="skip the untimed runs of the other forms")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--profile-every", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the lambda path is sequential and the multi-GPU split is a design note, not a run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1510_03298_amd import glam, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    d = inputs.config_c2(nlambda=args.nlambda)
+    n, p = d.n, d.p
+    Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    dts = {"f64": glam.F64, "f32": glam.F32, "bf16": glam.BF16}
+
+    def fit(dt, profile_every=0):
+        return glam.fit_path(Xd, Yd, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=1e-4,
+                             dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
+                             profile_every=profile_every, raise_on_error=False)
+
+    for _ in range(args.warmup):
+        fit(args.dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(fit(args.dtype, args.profile_every))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ok = all(r.code == 0 and r.n_done == args.nlambda and float(np.max(r.kkt)) <= 1e-6 for r in results)
+    sec = elapsed / args.steps
+
+    fwd3, chain, adj3 = flop_model(n, p)
+    dtb = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
+    chain_ms = sum(r.chain_ms for r in results)
+    samples = sum(r.chain_samples for r in results)
+    iter_ms = sum(r.iter_ms for r in results)
+    avg_chain = chain_ms / max(samples, 1) * 1e-3
+    avg_iter = iter_ms / max(samples, 1) * 1e-3
+    achieved = chain / avg_chain if samples else None
+    roofline = {
+        "kernel": "slab_chain (fused modes 1-2 forward + adjoint of one inner PG iteration)",
+        "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
+        "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
+        "frac": (achieved / PEAKS[args.dtype]) if achieved else None,
+        "traffic": None,
+        "flops_per_launch": chain, "launches_sampled": samples,
+        "avg_launch_us": avg_chain * 1e6,
+        "algorithmic_bytes_per_launch": chain_bytes(n, p, dtb),
+        "inner_iteration_us": avg_iter * 1e6,
+        "inner_iteration_tflops": (fwd3 + chain + adj3) / avg_iter / 1e12 if samples else None,
+    }
+    forms = {args.dtype: {"seconds": sec, "inner": int(np.mean([r.inner_total for r in results])),
+                          "outer": int(np.mean([r.iters_outer.sum() for r in results])),
+                          "max_kkt": float(max(np.max(r.kkt) for r in results)), "ok": ok}}
+    if not args.no_compare:
+        for dt in ["f64", "f32", "bf16"]:
+            if dt in forms:
+                continue
+            r = fit(dt)
+            forms[dt] = {"seconds": r.seconds, "inner": int(r.inner_total), "outer": int(r.iters_outer.sum()),
+                         "max_kkt": float(np.max(r.kkt)), "ok": r.code == 0 and r.n_done == args.nlambda}
+        for dt in forms:
+            forms[dt]["speedup_vs_f64"] = forms["f64"]["seconds"] / forms[dt]["seconds"]
+    cpu = None
+    if not args.no_cpu and "f64" in forms:
+        cpu = cpu_baseline(d, forms["f64"]["inner"], forms["f64"]["outer"])
+    out = {
+        "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "gaussian_path_n100x100x1000_p30x30x200_100lambda_kkt1e-6",
+                   "n": list(n), "p": list(p), "nlambda": args.nlambda, "lambda_min_ratio": 1e-4,
+                   "kkt_tol": 1e-6, "family": "gaussian"},
+        "all_models_converged": ok,
+        "forms": forms,
+        "flops_per_inner_iteration": fwd3 + chain + adj3,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -119,6 +119,8 @@ typedef struct {
   int check_every;        /* inner iterations between host convergence checks (>= 1) */
   const double* theta0;   /* device, FP64 p-array warm start for the first lambda, or NULL */
   void* stream;           /* hipStream_t (NULL = default stream)                    */
+  int profile_every;      /* > 0: time every profile_every-th inner iteration's fused
+                             slab kernel with HIP events on `stream` (0 = off)      */
 } glam_options;
 
 typedef struct {
@@ -132,6 +134,10 @@ typedef struct {
   int n_done;             /* out: number of models fitted (< nlambda on early exit) */
   double lambda_max;      /* out: lambda_max (Sec. 6.4)                              */
   double seconds;         /* out: wall time of the call                              */
+  double chain_ms;        /* out: summed duration of the sampled fused slab kernels  */
+  int chain_samples;      /* out: number of sampled launches (profile_every > 0)     */
+  double iter_ms;         /* out: summed duration of the sampled whole inner iterations */
+  long long inner_total;  /* out: inner iterations over the whole path               */
 } glam_result;
 
 /* Fit the whole lambda path with warm starts.  Models are fitted in order;

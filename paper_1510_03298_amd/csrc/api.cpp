@@ -33,9 +33,16 @@ Geom make_geom(const int64_t* n, const int64_t* p) {
   G.N1T = (G.n1 + 15) / 16;
   G.NJB = (G.n2 + 15) / 16;
   G.PT = (std::max(G.p1, G.p2) + 15) / 16;
+  G.KB3 = (G.p3 + 15) / 16;
+  G.KBN3 = (G.n3 + 15) / 16;
   G.nint = (long long)G.n3 * G.NJB * G.N1T * 256;
   G.n = (long long)G.n1 * G.n2 * G.n3;
   G.p = (long long)G.p1 * G.p2 * G.p3;
+  G.t1_len = (long long)G.n3 * G.PT * G.PT * 256;
+  G.s2_len = (long long)G.KBN3 * 16 * G.P12;
+  G.inc_len = (long long)G.KB3 * 16 * G.P12;
+  G.x3f_len = (long long)G.KB3 * 16 * G.n3;
+  G.x3a_len = (long long)G.KBN3 * 16 * G.p3;
   return G;
 }
 
@@ -63,6 +70,25 @@ static int check_sizes(int d, const int64_t* n, const int64_t* p, int dtype, Geo
 }
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the rho / NLL entry points: k-blocked Theta, both packed copies of
+// X_3, fragment-ordered T1, k-blocked S2 and per-workgroup partial sums.
+struct WsLayout {
+  size_t inc, x3f, t1, x3a, s2, part, total;
+};
+static WsLayout ws_layout(const Geom& G, int dt) {
+  const size_t es = dt_size(dt);
+  WsLayout W;
+  size_t o = 0;
+  W.inc = o; o += align256(G.inc_len * es);
+  W.x3f = o; o += align256(G.x3f_len * es);
+  W.t1 = o;  o += align256(G.t1_len * es);
+  W.x3a = o; o += align256(G.x3a_len * es);
+  W.s2 = o;  o += align256(G.s2_len * es);
+  W.part = o; o += align256((size_t)G.n3 * 2 * sizeof(double));
+  W.total = o;
+  return W;
+}
 
 #define HIPCHK(expr)                                                           \
   do {                                                                         \
@@ -97,7 +123,7 @@ const char* glam_version(void) { return "glam-mi355x 0.1.0 (gfx950)"; }
 size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype) {
   Geom G;
   if (check_sizes(d, n, p, dtype, &G) != GLAM_OK) return 0;
-  return align256((size_t)G.n3 * G.P12 * dt_size(dtype));
+  return ws_layout(G, dtype).total;
 }
 
 int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* Theta, void* Eta,
@@ -109,12 +135,18 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
   if (!X || !X[0] || !X[1] || !X[2] || !Theta || !Eta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
+  const WsLayout W = ws_layout(G, dtype);
+  char* ws = (char*)workspace;
+  const size_t es = dt_size(dtype);
+  HIPCHK(launch_pack(dtype, dtype, Theta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
+  HIPCHK(launch_zero(ws + W.t1, G.t1_len * es, s));
   FwdParams F{};
-  F.G = G; F.theta = Theta; F.X3 = X[2]; F.T1 = workspace; F.iter = nullptr;
+  F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1; F.iter = nullptr;
   HIPCHK(launch_slab_fwd(dtype, F, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = workspace; S.eta_out = Eta;
-  HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, s));
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.eta_out = Eta;
+  HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, nullptr, s));
   return GLAM_OK;
 }
 
@@ -127,11 +159,16 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
   if (!X || !X[0] || !X[1] || !X[2] || !U || !Out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
+  const WsLayout W = ws_layout(G, dtype);
+  char* ws = (char*)workspace;
+  const size_t es = dt_size(dtype);
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
+  HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.S2 = workspace; S.u_in = U;
-  HIPCHK(launch_slab_chain(dtype, SM_ADJ_STD, S, s));
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.S2 = ws + W.s2; S.u_in = U;
+  HIPCHK(launch_slab_chain(dtype, SM_ADJ_STD, S, nullptr, s));
   AdjParams A{};
-  A.G = G; A.S2 = workspace; A.X3 = X[2]; A.out = Out; A.scale = 1.0;
+  A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = Out; A.scale = 1.0;
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
   return GLAM_OK;
 }
@@ -139,7 +176,20 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
 size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype) {
   Geom G;
   if (check_sizes(3, n, p, dtype, &G) != GLAM_OK) return 0;
-  return 2 * align256((size_t)G.n3 * G.P12 * dt_size(dtype)) + align256((size_t)G.n3 * 2 * sizeof(double));
+  return ws_layout(G, dtype).total;
+}
+
+// Shared forward part of the NLL entry points: eta = H(beta) inside slab_chain.
+static int nll_prepare(const Geom& G, const void* const* X, const void* beta, int dtype, char* ws, const WsLayout& W,
+                       hipStream_t s) {
+  const size_t es = dt_size(dtype);
+  HIPCHK(launch_pack(dtype, dtype, beta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
+  HIPCHK(launch_zero(ws + W.t1, G.t1_len * es, s));
+  FwdParams F{};
+  F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1;
+  HIPCHK(launch_slab_fwd(dtype, F, s));
+  return GLAM_OK;
 }
 
 int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* const* X, const void* beta,
@@ -153,17 +203,16 @@ int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* con
   if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  const size_t tsz = align256((size_t)G.n3 * G.P12 * dt_size(dtype));
-  void* T1 = ws;
-  double* part = (double*)(ws + 2 * tsz);
-  FwdParams F{};
-  F.G = G; F.theta = beta; F.X3 = X[2]; F.T1 = T1;
-  HIPCHK(launch_slab_fwd(dtype, F, s));
+  const WsLayout W = ws_layout(G, dtype);
+  st = nll_prepare(G, X, beta, dtype, ws, W, s);
+  if (st) return st;
+  double* part = (double*)(ws + W.part);
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = T1; S.y_std = Y; S.partials = part;
-  HIPCHK(launch_slab_chain(dtype, SM_NLL_FWD, S, s));
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.y_std = Y; S.partials = part;
+  int nb = 0;
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_FWD, S, &nb, s));
   const int ops[1] = {0};
-  HIPCHK(launch_reduce_strided(part, G.n3, 2, 1, ops, 1.0 / (double)G.n, loss, s));
+  HIPCHK(launch_reduce_strided(part, nb, 2, 1, ops, 1.0 / (double)G.n, loss, s));
   return GLAM_OK;
 }
 
@@ -178,18 +227,18 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
   if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  const size_t tsz = align256((size_t)G.n3 * G.P12 * dt_size(dtype));
-  void* T1 = ws;
-  void* S2 = ws + tsz;
-  double* part = (double*)(ws + 2 * tsz);
-  FwdParams F{};
-  F.G = G; F.theta = beta; F.X3 = X[2]; F.T1 = T1;
-  HIPCHK(launch_slab_fwd(dtype, F, s));
+  const WsLayout W = ws_layout(G, dtype);
+  const size_t es = dt_size(dtype);
+  st = nll_prepare(G, X, beta, dtype, ws, W, s);
+  if (st) return st;
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
+  HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = T1; S.S2 = S2; S.y_std = Y; S.partials = part;
-  HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, s));
+  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.S2 = ws + W.s2; S.y_std = Y;
+  S.partials = (double*)(ws + W.part);
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, nullptr, s));
   AdjParams A{};
-  A.G = G; A.S2 = S2; A.X3 = X[2]; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
+  A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
   return GLAM_OK;
 }

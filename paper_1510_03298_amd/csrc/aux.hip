@@ -1,0 +1,345 @@
+// aux.hip -- small gfx950 kernels around the rho chain: reductions, layout
+// conversion, the elementwise parts of the GD-PG iteration (Sec. 3) and the
+// FP64 Armijo trial sums (Sec. 5).
+#include "launch.h"
+#include "mfma.h"
+
+namespace glam {
+
+constexpr int WG = 256;
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+
+__device__ inline double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NV>
+__device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], double* sred) {
+#pragma unroll
+  for (int s = 0; s < NV; ++s) v[s] = ops[s] ? warp_max(v[s]) : warp_sum(v[s]);
+  __syncthreads();
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) sred[wave_id() * NV + s] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      double a = sred[s];
+      for (int w = 1; w < WG / 64; ++w) a = ops[s] ? fmax(a, sred[w * NV + s]) : a + sred[w * NV + s];
+      v[s] = a;
+    }
+  }
+}
+
+// ============================================================================
+// small kernels
+// ============================================================================
+__global__ void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval, int ops_bits, double scale,
+                         double* __restrict__ out) {
+  __shared__ double sm[WG];
+  for (int v = 0; v < nval; ++v) {
+    const int op = (ops_bits >> v) & 1;
+    double a = op ? -INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nblk; b += WG) {
+      const double x = part[(long long)b * stride + v];
+      a = op ? fmax(a, x) : a + x;
+    }
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sm[threadIdx.x] = op ? fmax(sm[threadIdx.x], sm[threadIdx.x + s]) : sm[threadIdx.x] + sm[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = op ? sm[0] : scale * sm[0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = Tr<T>::from_acc((typename Tr<T>::acc_t)src[i]);
+}
+
+__global__ void k_to_tiled(Geom G, const double* __restrict__ src, double fill, double* __restrict__ dst) {
+  // one thread per tiled element; src == NULL means the constant `fill` on valid cells
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < G.nint; t += (long long)gridDim.x * blockDim.x) {
+    const int i1l = (int)(t & 15), i2l = (int)((t >> 4) & 15);
+    long long q = t >> 8;
+    const int ut = (int)(q % G.N1T);
+    q /= G.N1T;
+    const int jb = (int)(q % G.NJB);
+    const long long i3 = q / G.NJB;
+    const int i1 = ut * 16 + i1l, i2 = jb * 16 + i2l;
+    double v = 0.0;
+    if (i1 < G.n1 && i2 < G.n2) v = src ? src[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)] : fill;
+    dst[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_inner_init(long long p, long long inc_len, const double* __restrict__ theta,
+                             const double* __restrict__ gref, double* x, double* xp, double* gp, T* inc, int* iter) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p; i += (long long)gridDim.x * blockDim.x) {
+    x[i] = theta[i];
+    xp[i] = theta[i];
+    gp[i] = gref[i];
+  }
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < inc_len; i += (long long)gridDim.x * blockDim.x)
+    inc[i] = zero_val<T>();
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iter = 0;
+}
+
+__global__ void k_sub(long long p, const double* a, const double* b, double* out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p; i += (long long)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+__global__ void k_axpy(long long p, double alpha, const double* d, double* th) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p; i += (long long)gridDim.x * blockDim.x)
+    th[i] = th[i] + alpha * d[i];
+}
+__global__ void k_fill(double* p, long long count, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Armijo trials (Sec. 5): change of the smooth part of F along t * xd for the
+// step sizes t_j = 2^-(j0 + j), j < ARMIJO_TRIALS, plus sum u . xd (for Delta_k).
+// Padding cells carry a = 0 and contribute nothing.
+__global__ __launch_bounds__(WG) void k_armijo(Geom G, int family, const double* __restrict__ eta,
+                                                const double* __restrict__ xd, const double* __restrict__ y,
+                                                const double* __restrict__ a, int j0, double* __restrict__ part) {
+  constexpr int NV = ARMIJO_TRIALS + 1;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (long long t = blockIdx.x * (long long)WG + threadIdx.x; t < G.nint; t += (long long)gridDim.x * WG) {
+    const double av = a[t];
+    if (av == 0.0) continue;
+    const double e = eta[t], s0 = xd[t], yv = y[t];
+    const double mu = family == 1 ? exp(e) : e;
+    acc[0] += av * (yv - mu) * s0;
+#pragma unroll
+    for (int j = 0; j < ARMIJO_TRIALS; ++j) {
+      const double s = ldexp(s0, -(j0 + j));
+      const double db = family == 1 ? mu * expm1(s) : s * (e + 0.5 * s);
+      acc[1 + j] += av * (db - yv * s);
+    }
+  }
+  __shared__ double sm[WG / 64][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = warp_sum(acc[v]);
+  if (lane_id() == 0)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sm[wave_id()][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int ww = 0; ww < WG / 64; ++ww) s += sm[ww][threadIdx.x];
+    part[(long long)blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+// J(theta + t d) - J(theta) entrywise for t = 1 and the Armijo trial steps.
+__global__ __launch_bounds__(WG) void k_pen_trials(long long p, const double* __restrict__ th,
+                                                    const double* __restrict__ d, const double* __restrict__ w,
+                                                    int j0, double* __restrict__ part) {
+  constexpr int NV = ARMIJO_TRIALS + 1;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < p; i += (long long)gridDim.x * WG) {
+    const double t0 = th[i], dv = d[i], wm = w ? w[i] : 1.0, a0 = fabs(t0);
+    acc[0] += wm * (fabs(t0 + dv) - a0);
+#pragma unroll
+    for (int j = 0; j < ARMIJO_TRIALS; ++j) acc[1 + j] += wm * (fabs(t0 + ldexp(dv, -(j0 + j))) - a0);
+  }
+  __shared__ double sm[WG / 64][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = warp_sum(acc[v]);
+  if (lane_id() == 0)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sm[wave_id()][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int ww = 0; ww < WG / 64; ++ww) s += sm[ww][threadIdx.x];
+    part[(long long)blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+// Input checks: per-block maxima of 4 indicator values (non-finite y, negative y
+// for Poisson, bad prior weight, bad penalty weight); reduced with launch_reduce.
+__global__ __launch_bounds__(WG) void k_check(long long n, const double* __restrict__ y, const double* __restrict__ a,
+                                               long long p, const double* __restrict__ w, int poisson,
+                                               double* __restrict__ part) {
+  double f[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n; i += (long long)gridDim.x * WG) {
+    const double yv = y[i];
+    if (!isfinite(yv)) f[0] = 1.0;
+    if (poisson && yv < 0.0) f[1] = 1.0;
+    if (a) {
+      const double av = a[i];
+      if (!isfinite(av) || av < 0.0) f[2] = 1.0;
+    }
+  }
+  if (w)
+    for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < p; i += (long long)gridDim.x * WG) {
+      const double wv = w[i];
+      if (!(wv > 0.0) || !isfinite(wv)) f[3] = 1.0;
+    }
+  __shared__ double sred[4 * 4];
+  const int ops[4] = {1, 1, 1, 1};
+  block_reduce<4>(f, ops, sred);
+  if (threadIdx.x == 0)
+    for (int s = 0; s < 4; ++s) part[(long long)blockIdx.x * 4 + s] = f[s];
+}
+
+// k-blocked packing: dst elem(k, c) = src[k * sk + c * sc] (converted), zero for k >= K.
+template <typename S, typename T>
+__global__ void k_pack(const S* __restrict__ src, long long K, long long C, long long sk, long long sc,
+                       T* __restrict__ dst, long long total) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total; idx += (long long)gridDim.x * blockDim.x) {
+    const int pos = (int)(idx & 15);
+    const long long c = (idx >> 4) % C;
+    const long long kb = (idx >> 4) / C;
+    const long long k = kb * 16 + kpos<T>(pos);    // kpos is an involution on 0..15
+    T v = zero_val<T>();
+    if (k < K) v = Tr<T>::from_acc((typename Tr<T>::acc_t)src[k * sk + c * sc]);
+    dst[idx] = v;
+  }
+}
+template <typename T>
+__global__ void k_pack_same(const T* __restrict__ src, long long K, long long C, long long sk, long long sc,
+                            T* __restrict__ dst, long long total) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total; idx += (long long)gridDim.x * blockDim.x) {
+    const int pos = (int)(idx & 15);
+    const long long c = (idx >> 4) % C;
+    const long long kb = (idx >> 4) / C;
+    const long long k = kb * 16 + kpos<T>(pos);
+    dst[idx] = k < K ? src[k * sk + c * sc] : zero_val<T>();
+  }
+}
+__global__ void k_zero(uint32_t* p, long long nwords) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nwords; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+static inline int grid1d(long long n) {
+  long long b = (n + WG - 1) / WG;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+hipError_t launch_pack(int dt, int src_dt, const void* src, long long K, long long C, long long sk, long long sc,
+                       void* dst, hipStream_t s) {
+  const long long total = ((K + 15) / 16) * 16 * C;
+  const int gr = grid1d(total);
+  if (src_dt == DT_F64) {
+    if (dt == DT_F64) hipLaunchKernelGGL((k_pack<double, double>), dim3(gr), dim3(WG), 0, s, (const double*)src, K, C, sk, sc, (double*)dst, total);
+    else if (dt == DT_F32) hipLaunchKernelGGL((k_pack<double, float>), dim3(gr), dim3(WG), 0, s, (const double*)src, K, C, sk, sc, (float*)dst, total);
+    else hipLaunchKernelGGL((k_pack<double, bf16>), dim3(gr), dim3(WG), 0, s, (const double*)src, K, C, sk, sc, (bf16*)dst, total);
+  } else {
+    if (src_dt != dt) return hipErrorInvalidValue;
+    if (dt == DT_F32) hipLaunchKernelGGL(k_pack_same<float>, dim3(gr), dim3(WG), 0, s, (const float*)src, K, C, sk, sc, (float*)dst, total);
+    else hipLaunchKernelGGL(k_pack_same<bf16>, dim3(gr), dim3(WG), 0, s, (const bf16*)src, K, C, sk, sc, (bf16*)dst, total);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long nw = (long long)((bytes + 3) / 4);
+  hipLaunchKernelGGL(k_zero, dim3(grid1d(nw)), dim3(WG), 0, s, (uint32_t*)p, nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
+                                 double* out, hipStream_t s) {
+  int bits = 0;
+  for (int v = 0; v < nval; ++v) bits |= (ops[v] & 1) << v;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, stride, nval, bits, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
+                         hipStream_t s) {
+  return launch_reduce_strided(partials, nblk, nval, nval, ops, scale, out, s);
+}
+
+hipError_t launch_convert(int dt, const double* src, void* dst, long long count, hipStream_t s) {
+  const int gr = grid1d(count);
+  if (dt == DT_F64) hipLaunchKernelGGL(k_convert<double>, dim3(gr), dim3(WG), 0, s, src, (double*)dst, count);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_convert<float>, dim3(gr), dim3(WG), 0, s, src, (float*)dst, count);
+  else hipLaunchKernelGGL(k_convert<bf16>, dim3(gr), dim3(WG), 0, s, src, (bf16*)dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_tiled(const Geom& G, const double* src_std, double fill_valid, double* dst_tiled, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_tiled, dim3(grid1d(G.nint)), dim3(WG), 0, s, G, src_std, fill_valid, dst_tiled);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_init(const Geom& G, const double* theta, const double* gref, double* x, double* xp, double* gp,
+                             int dt, void* inc, int* iter, hipStream_t s) {
+  const long long p = G.p, il = G.inc_len;
+  const int gr = grid1d(p > il ? p : il);
+  if (dt == DT_F64) hipLaunchKernelGGL(k_inner_init<double>, dim3(gr), dim3(WG), 0, s, p, il, theta, gref, x, xp, gp, (double*)inc, iter);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_inner_init<float>, dim3(gr), dim3(WG), 0, s, p, il, theta, gref, x, xp, gp, (float*)inc, iter);
+  else hipLaunchKernelGGL(k_inner_init<bf16>, dim3(gr), dim3(WG), 0, s, p, il, theta, gref, x, xp, gp, (bf16*)inc, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(long long p, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(grid1d(p)), dim3(WG), 0, s, p, a, b, out);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(long long p, double alpha, const double* d, double* theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid1d(p)), dim3(WG), 0, s, p, alpha, d, theta);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(count)), dim3(WG), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, int j0,
+                             double* partials, int* nblk_out, hipStream_t s) {
+  int nb = grid1d(p);
+  if (nb > 256) nb = 256;
+  *nblk_out = nb;
+  hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, j0, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int poisson,
+                        double* partials, int* nblk_out, hipStream_t s) {
+  int nb = grid1d(n > p ? n : p);
+  if (nb > 1024) nb = 1024;
+  *nblk_out = nb;
+  hipLaunchKernelGGL(k_check, dim3(nb), dim3(WG), 0, s, n, y, a, p, pen_w, poisson, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_armijo(const Geom& G, int family, const double* eta_int, const double* xd_int, const double* y_int,
+                         const double* a_int, int j0, double* partials, int* nblk_out, hipStream_t s) {
+  int nb = grid1d(G.nint);
+  if (nb > 1024) nb = 1024;
+  *nblk_out = nb;
+  hipLaunchKernelGGL(k_armijo, dim3(nb), dim3(WG), 0, s, G, family, eta_int, xd_int, y_int, a_int, j0, partials);
+  return hipGetLastError();
+}
+
+}  // namespace glam

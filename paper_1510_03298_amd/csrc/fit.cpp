@@ -83,7 +83,10 @@ struct Fit {
   const glam_problem* prob;
   // device buffers (owned; freed by the destructor)
   std::vector<void*> bufs;
-  const void* Xc[3];       // chain-dtype factors
+  const void* Xc[2];       // chain-dtype mode-1 and mode-2 factors
+  void *X3fc, *X3ac;       // chain-dtype packed mode-3 factor (slab_fwd / slab_adj operands)
+  double *X3fd, *X3ad;     // FP64 packed mode-3 factor
+  double* thpk;            // FP64 k-blocked copy of theta (or of a direction)
   double *y_int, *a_int, *eta_int, *xd_int;
   void* v_int;             // tiled weights (acc type of the chain) or NULL (Gaussian)
   void *T1c, *S2c;         // chain dtype intermediates
@@ -96,6 +99,10 @@ struct Fit {
   double* hred;            // reduced values (pinned host)
   double sprod;            // prod_j rho(X_j^T X_j)
   std::string err;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
+  bool pending = false;
+  double chain_ms = 0.0, iter_ms = 0.0;
+  int samples = 0;
 
   void* alloc(size_t bytes) {
     void* p = nullptr;
@@ -109,6 +116,8 @@ struct Fit {
   ~Fit() {
     if (!bufs.empty()) (void)hipStreamSynchronize(s);
     for (void* p : bufs) (void)hipFree(p);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -132,24 +141,26 @@ struct StepStats {
 // Step 2 of Algorithm 1 at theta (FP64): eta, V, -l/n, g = -G(U)/n, KKT.
 static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats* st) {
   const Geom& G = F.G;
+  FCHK(launch_pack(DT_F64, DT_F64, theta_dev, G.p3, G.P12, G.P12, 1, F.thpk, F.s));
   FwdParams fw{};
-  fw.G = G; fw.theta = theta_dev; fw.X3 = F.prob->X[2]; fw.T1 = F.T1d;
+  fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
   FCHK(launch_slab_fwd(DT_F64, fw, F.s));
   SlabParams sp{};
   sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.S2 = F.S2d;
   sp.y_int = F.y_int; sp.a_int = F.a_int; sp.eta_int = F.eta_int;
   sp.v_out = F.v_int; sp.v_out_f32 = F.dt != DT_F64; sp.family = F.family; sp.partials = F.part;
-  FCHK(launch_slab_chain(DT_F64, SM_FAMILY, sp, F.s));
+  int nbc = 0;
+  FCHK(launch_slab_chain(DT_F64, SM_FAMILY, sp, &nbc, F.s));
   const int ops2[2] = {0, 1};
-  FCHK(launch_reduce(F.part, G.n3, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
+  FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
   AdjParams ap{};
-  ap.G = G; ap.S2 = F.S2d; ap.X3 = F.prob->X[2]; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
+  ap.G = G; ap.S2 = F.S2d; ap.X3a = F.X3ad; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
   ap.theta = theta_dev; ap.pen_w = F.prob->pen_w; ap.lambda = lambda;
-  double* part2 = F.part + (size_t)2 * G.n3;
+  double* part2 = F.part + (size_t)2 * nbc;
   ap.partials = part2;
   int nb = 0;
   FCHK(launch_slab_adj(DT_F64, EPI_GRAD, ap, &nb, F.s));
-  const int ops4[4] = {1, 1, 0, 0};
+  const int ops4[4] = {1, 1, 0, 1};
   FCHK(launch_reduce(part2, nb, 4, ops4, 1.0, F.red + 2, F.s));
   FCHK(hipMemcpyAsync(F.hred, F.red, 6 * sizeof(double), hipMemcpyDeviceToHost, F.s));
   FCHK(hipStreamSynchronize(F.s));
@@ -162,19 +173,40 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
 }
 
 // One inner PG iteration (Sec. 3.2) in the chain dtype.
-static int inner_iteration(Fit& F, double lambda, double delta, int* nblk) {
+static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool sample) {
   const Geom& G = F.G;
+  if (sample) FCHK(hipEventRecord(F.ev[0], F.s));
   FwdParams fw{};
-  fw.G = G; fw.theta = F.inc; fw.X3 = F.Xc[2]; fw.T1 = F.T1c; fw.iter = F.iter;
+  fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c; fw.iter = F.iter;
   FCHK(launch_slab_fwd(F.dt, fw, F.s));
   SlabParams sp{};
   sp.G = G; sp.X1 = F.Xc[0]; sp.X2 = F.Xc[1]; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
-  FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, F.s));
+  if (sample) FCHK(hipEventRecord(F.ev[1], F.s));
+  FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
+  if (sample) FCHK(hipEventRecord(F.ev[2], F.s));
   AdjParams ap{};
-  ap.G = G; ap.S2 = F.S2c; ap.X3 = F.Xc[2]; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+  ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
   ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
   ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta;
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
+  if (sample) {
+    FCHK(hipEventRecord(F.ev[3], F.s));
+    F.pending = true;
+  }
+  return GLAM_OK;
+}
+
+// Accumulate the durations of the last sampled inner iteration (events are complete
+// after the stream synchronisation of the convergence check).
+static int collect_sample(Fit& F) {
+  if (!F.pending) return GLAM_OK;
+  float a = 0.f, b = 0.f;
+  FCHK(hipEventElapsedTime(&a, F.ev[1], F.ev[2]));
+  FCHK(hipEventElapsedTime(&b, F.ev[0], F.ev[3]));
+  F.chain_ms += a;
+  F.iter_ms += b;
+  F.samples += 1;
+  F.pending = false;
   return GLAM_OK;
 }
 
@@ -182,12 +214,13 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk) {
 static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* delta_out) {
   const Geom& G = F.G;
   // xd = H(d) in FP64 (tiled)
+  FCHK(launch_pack(DT_F64, DT_F64, F.dvec, G.p3, G.P12, G.P12, 1, F.thpk, F.s));
   FwdParams fw{};
-  fw.G = G; fw.theta = F.dvec; fw.X3 = F.prob->X[2]; fw.T1 = F.T1d;
+  fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
   FCHK(launch_slab_fwd(DT_F64, fw, F.s));
   SlabParams sp{};
   sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
-  FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, F.s));
+  FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, nullptr, F.s));
   constexpr int NV = ARMIJO_TRIALS + 1;
   const int ops[NV] = {0};
   double Delta = 0.0;
@@ -268,9 +301,8 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   const Geom& G = F.G;
   const size_t es = dt_size(F.dt);
   const size_t accs = F.dt == DT_F64 ? 8 : 4;
-  const size_t slab = (size_t)G.n3 * G.P12;
   const size_t nadj = (size_t)slab_adj_blocks(G);
-  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * 4, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1), nadj * 4});
+  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * 4, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1)});
 
   bool ok = true;
   auto A = [&](size_t b) { void* p = F.alloc(b); if (!p) ok = false; return p; };
@@ -279,15 +311,20 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   F.eta_int = (double*)A(G.nint * 8);
   F.xd_int = (double*)A(G.nint * 8);
   F.v_int = F.family == GLAM_POISSON ? A(G.nint * accs) : nullptr;
-  F.T1d = (double*)A(slab * 8);
-  F.S2d = (double*)A(slab * 8);
+  F.T1d = (double*)A(G.t1_len * 8);
+  F.S2d = (double*)A(G.s2_len * 8);
+  F.X3fd = (double*)A(G.x3f_len * 8);
+  F.X3ad = (double*)A(G.x3a_len * 8);
+  F.thpk = (double*)A(G.inc_len * 8);
   if (F.dt == DT_F64) {
-    F.T1c = F.T1d; F.S2c = F.S2d;
-    for (int j = 0; j < 3; ++j) F.Xc[j] = prob->X[j];
+    F.T1c = F.T1d; F.S2c = F.S2d; F.X3fc = F.X3fd; F.X3ac = F.X3ad;
+    for (int j = 0; j < 2; ++j) F.Xc[j] = prob->X[j];
   } else {
-    F.T1c = A(slab * es);
-    F.S2c = A(slab * es);
-    for (int j = 0; j < 3; ++j) F.Xc[j] = A((size_t)prob->n[j] * prob->p[j] * es);
+    F.T1c = A(G.t1_len * es);
+    F.S2c = A(G.s2_len * es);
+    F.X3fc = A(G.x3f_len * es);
+    F.X3ac = A(G.x3a_len * es);
+    for (int j = 0; j < 2; ++j) F.Xc[j] = A((size_t)prob->n[j] * prob->p[j] * es);
   }
   F.theta = (double*)A(G.p * 8);
   F.gref = (double*)A(G.p * 8);
@@ -295,11 +332,14 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   F.xp = (double*)A(G.p * 8);
   F.gp = (double*)A(G.p * 8);
   F.dvec = (double*)A(G.p * 8);
-  F.inc = A(G.p * es);
+  F.inc = A(G.inc_len * es);
   F.iter = (int*)A(sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
   if (!ok) return fit_fail(GLAM_ENOMEM, "device allocation failed");
+  if (opt->profile_every > 0)
+    for (auto& e : F.ev)
+      if (hipEventCreate(&e) != hipSuccess) return fit_fail(GLAM_EDEVICE, "hipEventCreate failed");
   if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess)
     return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
   struct HostFree { double* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{F.hred};
@@ -332,8 +372,19 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   PCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
   PCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
   if (F.dt != DT_F64)
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 2; ++j)
       PCHK(launch_convert(F.dt, prob->X[j], (void*)F.Xc[j], (long long)prob->n[j] * prob->p[j], F.s));
+  // packed mode-3 factor (FP64 and chain dtype); zero the padded intermediates once
+  PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fd, F.s));
+  PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ad, F.s));
+  PCHK(launch_zero(F.T1d, G.t1_len * 8, F.s));
+  PCHK(launch_zero(F.S2d, G.s2_len * 8, F.s));
+  if (F.dt != DT_F64) {
+    PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fc, F.s));
+    PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ac, F.s));
+    PCHK(launch_zero(F.T1c, G.t1_len * es, F.s));
+    PCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
+  }
   F.sprod = 1.0;
   for (int j = 0; j < 3; ++j) {
     std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
@@ -360,9 +411,15 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   const bool exact_model = F.family == GLAM_GAUSSIAN && prob->obs_w == nullptr;
   const double tol = opt->kkt_tol;
   const int check_every = opt->check_every;
-  const bool verbose = getenv("GLAM_LOG") && atoi(getenv("GLAM_LOG")) > 0;
+  const int log_level = getenv("GLAM_LOG") ? atoi(getenv("GLAM_LOG")) : 0;
+  const bool verbose = log_level > 0;
   int path_status = GLAM_OK;
+  long long path_inner = 0;
   res->n_done = 0;
+  res->chain_ms = 0.0;
+  res->iter_ms = 0.0;
+  res->chain_samples = 0;
+  res->inner_total = 0;
 
   for (int l = 0; l < opt->nlambda; ++l) {
     const double lam = lams[l];
@@ -384,22 +441,43 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
       const double delta = 1.0 / (opt->nu * Lhat);
-      const double tol_in = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
+      double tol_in = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
+      // A BF16 chain perturbs grad h by roughly eps_bf16 * kappa relative to the
+      // increment, so one outer pass cannot gain more than that factor: ask each
+      // pass for a 10x reduction and re-anchor in FP64 (iterative refinement).
+      if (F.dt == DT_BF16) tol_in = std::max(tol_in, 0.1 * kkt);
       // ---- inner PG loop ----
-      PCHK(launch_inner_init(G.p, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
       int it = 0;
       double kin = INFINITY, noise = 0.0;
+      double best = INFINITY, window_best = INFINITY;
+      int window_start = 0;
       while (it < opt->max_inner) {
         int nb = 0;
         const int m = std::min(check_every, opt->max_inner - it);
-        for (int q = 0; q < m; ++q) RCHK(inner_iteration(F, lam, delta, &nb));
+        for (int q = 0; q < m; ++q) {
+          const long long gi = inner_total + it + q;
+          const bool sample = opt->profile_every > 0 && (gi % opt->profile_every) == 0 && !F.pending;
+          RCHK(inner_iteration(F, lam, delta, &nb, sample));
+        }
         it += m;
-        const int ops[4] = {1, 1, 0, 0};
+        const int ops[4] = {1, 1, 0, 1};
         PCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
-        PCHK(hipMemcpyAsync(F.hred, F.red, 2 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+        PCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
         PCHK(hipStreamSynchronize(F.s));
+        RCHK(collect_sample(F));
         kin = F.hred[0] / lam_scale;
-        noise = 8.0 * kEps[F.dt] * F.hred[1] / lam_scale;
+        // rounding floor of the low-precision chain output (a lower bound of its error)
+        noise = 4.0 * kEps[F.dt] * F.hred[1] / lam_scale;
+        best = std::min(best, kin);
+        if (it - window_start >= 20 * check_every) {
+          // stalled: no 2x progress over the window -> leave for an FP64 re-anchor
+          if (!(best < 0.5 * window_best) && F.dt != DT_F64) break;
+          window_best = best;
+          window_start = it;
+        }
+        if (log_level >= 2)
+          fprintf(stderr, "[glam]   lambda %d k %d it %d kin %.3e noise %.3e\n", l, k, it, kin, noise);
         if (!std::isfinite(kin)) break;
         if (kin <= std::max(tol_in, noise)) break;
       }
@@ -420,6 +498,7 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
     res->iters_outer[l] = outer;
     res->iters_inner[l] = (int)std::min<long long>(inner_total, 2000000000LL);
     res->status[l] = status;
+    path_inner += inner_total;
     if (verbose)
       fprintf(stderr, "[glam] lambda %d = %.6e status %d kkt %.3e outer %d inner %lld\n", l, lam, status, kkt, outer,
               inner_total);
@@ -430,7 +509,12 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
     res->n_done = l + 1;
   }
   PCHK(hipStreamSynchronize(F.s));
+  RCHK(collect_sample(F));
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  res->chain_ms = F.chain_ms;
+  res->iter_ms = F.iter_ms;
+  res->chain_samples = F.samples;
+  res->inner_total = path_inner;
   if (path_status != GLAM_OK) return fit_fail(path_status, "path stopped early (see status array)");
   return GLAM_OK;
 }

@@ -1,16 +1,22 @@
 // launch.h -- host-side launchers of the gfx950 kernels (internal to the library).
 //
-// Geometry used by every kernel.  The rho chain of Sec. 6.1 is evaluated with
-// mode 3 as the "slab" mode: the mode-3 products are plain GEMMs (one launch
-// each, kernels "slab_fwd" and "slab_adj"), and the mode-1 and mode-2 products
-// of one i_3 slab run inside one workgroup with all intermediates in registers
-// (kernel "slab_chain").  Modes 1 and 2 are padded to 16-row tiles.
+// The rho chain of Sec. 6.1 is evaluated with mode 3 as the "slab" mode: the
+// mode-3 products are GEMMs (kernels slab_fwd and slab_adj), and the mode-1 and
+// mode-2 products of one i3 slab run inside one workgroup with all
+// intermediates in registers (kernel slab_chain).  Modes 1 and 2 are padded to
+// 16-row tiles.
 //
-// Internal n-array layout ("tiled"): for slab i3, mode-2 tile jb, mode-1 tile
-// ut, a 16 x 16 tile stored column-major (i1 fastest):
-//   index = ((i3 * NJB + jb) * N1T + ut) * 256 + (i2 % 16) * 16 + (i1 % 16),
-// with zeros in the padding.  Slab-GEMM intermediates T1 and S2 are stored as
-// [i3][m], m = i1 + p1 * i2 (one contiguous p1 x p2 slab per i3).
+// Internal layouts (all zero padded):
+//  * k-blocked operand of a GEMM with contraction length K and free length C:
+//      elem(k, c) at ((k / 16) * C + c) * 16 + kpos<T>(k % 16)
+//    so that one lane's MFMA fragment is 4 contiguous elements;
+//    S2 (K = n3, C = P12), the increment / Theta (K = p3, C = P12), and the two
+//    copies of X_3 (K = p3, C = n3 for slab_fwd; K = n3, C = p3 for slab_adj).
+//  * T1 in fragment order: slab i3, p1-tile mt, p2-block kb, lane, slot t:
+//      ((((i3 * PT + mt) * PT + kb) * 64 + lane) * 4 + t)
+//  * tiled n-arrays (eta, V, Y, a): slab i3, mode-2 tile jb, mode-1 tile ut,
+//    a 16 x 16 column-major tile (i1 fastest):
+//      ((i3 * NJB + jb) * N1T + ut) * 256 + (i2 % 16) * 16 + (i1 % 16)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -23,9 +29,15 @@ struct Geom {
   int P12;          // p1 * p2
   int N1T, NJB;     // ceil(n1 / 16), ceil(n2 / 16)
   int PT;           // ceil(max(p1, p2) / 16), 1 or 2
+  int KB3, KBN3;    // ceil(p3 / 16), ceil(n3 / 16)
   long long nint;   // length of a tiled n-array
   long long n;      // n1 * n2 * n3
   long long p;      // p1 * p2 * p3
+  long long t1_len; // n3 * PT * PT * 256
+  long long s2_len; // KBN3 * 16 * P12
+  long long inc_len;// KB3 * 16 * P12
+  long long x3f_len;// KB3 * 16 * n3
+  long long x3a_len;// KBN3 * 16 * p3
 };
 
 Geom make_geom(const int64_t* n, const int64_t* p);
@@ -48,8 +60,8 @@ struct SlabParams {
   Geom G;
   const void* X1;     // chain type, n1 x p1 column-major
   const void* X2;     // chain type, n2 x p2 column-major
-  const void* T1;     // chain type [n3][P12]
-  void* S2;           // chain type [n3][P12]
+  const void* T1;     // chain type, fragment-ordered slabs
+  void* S2;           // chain type, k-blocked (K = n3, C = P12)
   void* eta_out;      // FWD_STD / FWD_INT output
   const void* u_in;   // ADJ_STD input (chain type, standard layout)
   const void* v_int;  // FUSED weights (tiled, accumulation type) or NULL = 1
@@ -62,15 +74,15 @@ struct SlabParams {
   int family;         // 0 Gaussian, 1 Poisson
   // NLL (standard-layout FP64 counts)
   const double* y_std;
-  double* partials;   // per-workgroup partial sums [n3][nsum]
+  double* partials;   // per-workgroup partial sums [grid][2]
 };
 
 enum AdjEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_PROX = 2 };
 
 struct AdjParams {
   Geom G;
-  const void* S2;     // chain type [n3][P12]
-  const void* X3;     // chain type n3 x p3 column-major
+  const void* S2;     // chain type, k-blocked (K = n3, C = P12)
+  const void* X3a;    // chain type, k-blocked (K = n3, C = p3)
   void* out;          // EPI_STORE: p-array (FP64 for F64 chains, FP32 otherwise)
   double scale;       // EPI_STORE: out = scale * acc ; EPI_GRAD: g = scale * acc
   const double* gscale_dev;  // EPI_STORE: optional device scalar multiplier
@@ -79,32 +91,39 @@ struct AdjParams {
   const double* theta;   // FP64 p-array (KKT at theta) or NULL
   const double* pen_w;   // FP64 p-array or NULL
   double lambda;
-  double* partials;      // per-workgroup [nblk][4]: max KKT residual, max |g|/w, sum w|theta|, unused
+  double* partials;      // per-workgroup [nblk][4]
   // EPI_PROX (inner PG iteration, FP64 state)
   const double* gref;    // gradient at the anchor
   const double* theta_ref;
   double* x;             // x^l   (updated to x^{l+1})
   double* xp;            // x^{l-1} (updated to x^l)
   double* gp;            // grad h(x^{l-1}) (updated to grad h(x^l))
-  void* inc;             // chain type: x^{l+1} - theta_ref
+  void* inc;             // chain type, k-blocked (K = p3, C = P12): x^{l+1} - theta_ref
   const int* iter;       // device iteration counter l
   double delta;          // step size
 };
 
 struct FwdParams {
   Geom G;
-  const void* theta;  // chain type p-array (standard layout)
-  const void* X3;     // chain type n3 x p3
-  void* T1;           // chain type [n3][P12]
+  const void* theta;  // chain type, k-blocked (K = p3, C = P12)
+  const void* X3f;    // chain type, k-blocked (K = p3, C = n3)
+  void* T1;           // chain type, fragment-ordered
   int* iter;          // optional: incremented once by the first thread
 };
 
-// launchers (return hipError_t of the launch)
+// rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
-hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, hipStream_t s);
+hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s);
 hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, hipStream_t s);
 size_t slab_chain_lds_bytes(int dt, const Geom& G);
 int slab_adj_blocks(const Geom& G);
+int slab_chain_blocks(int dt, const Geom& G);
+
+// layout conversion: dst (k-blocked, dtype dt) elem(k, c) = src[k * sk + c * sc] for k < K, 0 beyond;
+// src is FP64 (src_dt = DT_F64) or of dtype dt.
+hipError_t launch_pack(int dt, int src_dt, const void* src, long long K, long long C, long long sk, long long sc,
+                       void* dst, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // small kernels
 // out[v] = scale * sum_b partials[b][v]  (ops[v] == 0)  or  max_b partials[b][v]  (ops[v] == 1);
@@ -117,7 +136,7 @@ hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, i
 hipError_t launch_convert(int dt, const double* src, void* dst, long long count, hipStream_t s);
 hipError_t launch_to_tiled(const Geom& G, const double* src_std, double fill_valid, double* dst_tiled,
                            hipStream_t s);
-hipError_t launch_inner_init(long long p, const double* theta, const double* gref, double* x, double* xp,
+hipError_t launch_inner_init(const Geom& G, const double* theta, const double* gref, double* x, double* xp,
                              double* gp, int dt, void* inc, int* iter, hipStream_t s);
 hipError_t launch_sub(long long p, const double* a, const double* b, double* out, hipStream_t s);
 hipError_t launch_axpy(long long p, double alpha, const double* d, double* theta, hipStream_t s);
@@ -134,7 +153,5 @@ hipError_t launch_check(long long n, const double* y, const double* a, long long
                         double* partials, int* nblk_out, hipStream_t s);
 
 constexpr int ARMIJO_TRIALS = 16;   // step sizes 2^-j0 .. 2^-(j0+15) evaluated in one pass
-constexpr int FAMILY_NSUM = 2;      // -l partial sum, max weight
-constexpr int GRAD_NSUM = 4;
 
 }  // namespace glam

@@ -116,6 +116,35 @@ template <typename T> __device__ inline typename Tr<T>::frag_t acc_frag(const ty
   return make_frag<T>(c[0], c[1], c[2], c[3]);
 }
 
+// ---- k-blocked storage ---------------------------------------------------------
+// Operands staged in LDS or stored in the library's k-blocked global layouts keep
+// the 16 contraction indices of a block in the order kidx(g, t) = position
+// 4 g + t, so that a lane's fragment is 4 contiguous elements.
+template <typename T> __host__ __device__ inline int kpos(int k);   // position of k within its block
+template <> __host__ __device__ inline int kpos<double>(int k) { return (k & ~15) | (((k & 3) << 2) | ((k & 15) >> 2)); }
+template <> __host__ __device__ inline int kpos<float>(int k) { return k; }
+template <> __host__ __device__ inline int kpos<bf16>(int k) { return k; }
+
+// Fragment = 4 contiguous elements (16-byte aligned for FP32/FP64, 8-byte for BF16).
+__device__ inline Tr<double>::frag_t load_frag(const double* p) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v a = *(const d2v*)p, b = *(const d2v*)(p + 2);
+  Tr<double>::frag_t f; f.v[0] = a[0]; f.v[1] = a[1]; f.v[2] = b[0]; f.v[3] = b[1];
+  return f;
+}
+__device__ inline Tr<float>::frag_t load_frag(const float* p) {
+  const f4v a = *(const f4v*)p;
+  Tr<float>::frag_t f; f.v[0] = a[0]; f.v[1] = a[1]; f.v[2] = a[2]; f.v[3] = a[3];
+  return f;
+}
+__device__ inline Tr<bf16>::frag_t load_frag(const bf16* p) {
+  Tr<bf16>::frag_t f; f.s = *(const s4v*)p;
+  return f;
+}
+template <typename T> __device__ inline typename Tr<T>::frag_t zero_frag() {
+  return raw_frag<T>(zero_val<T>(), zero_val<T>(), zero_val<T>(), zero_val<T>());
+}
+
 // ---- one 16 x 16 x 16 block: acc += A_frag * B_frag -------------------------
 __device__ inline void mma(d4v& c, const Tr<double>::frag_t& a, const Tr<double>::frag_t& b) {
 #pragma unroll

@@ -1,0 +1,591 @@
+// slab.hip -- gfx950 kernels of the rho chain (App. A; Sec. 6.1, eqs. eighteen,
+// nineteen, twentysixnew) for d = 3 GLAMs.
+//
+// One H / G pass is three launches:
+//   slab_fwd   : T1[i3] = sum_k3 Theta[., ., k3] X_3[i3, k3]            (mode-3 GEMM)
+//   slab_chain : per slab i3, in registers:
+//                T2 = T1_s X_2^T, eta = X_1 T2, R = f(eta), S1^T = R^T X_1,
+//                S2^T = sum_jb X_2blk^T S1blk^T                           (modes 1, 2)
+//   slab_adj   : out[., ., k3] = sum_i3 S2[i3] X_3[i3, k3] (+ epilogue)  (mode-3 GEMM)
+// The mode products commute (the mixed-product property behind the rho /
+// Kronecker identity of App. A), so H and G are taken mode 3 first / mode 3
+// last: the same linear maps as the cyclic rho order, with the least work when
+// mode 3 is the largest mode.
+#include "launch.h"
+#include "mfma.h"
+
+namespace glam {
+
+constexpr int WG = 256;   // 4 waves
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+
+template <typename T> struct OutOf { typedef float type; };
+template <> struct OutOf<double> { typedef double type; };
+
+__device__ inline double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroup reduction of NV doubles (sum or max per value), result valid in thread 0.
+template <int NV>
+__device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], double* sred /* 4*NV */) {
+#pragma unroll
+  for (int s = 0; s < NV; ++s) v[s] = ops[s] ? warp_max(v[s]) : warp_sum(v[s]);
+  __syncthreads();
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) sred[wave_id() * NV + s] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      double a = sred[s];
+      for (int w = 1; w < WG / 64; ++w) a = ops[s] ? fmax(a, sred[w * NV + s]) : a + sred[w * NV + s];
+      v[s] = a;
+    }
+  }
+}
+
+// ============================================================================
+// slab_fwd: T1 (P12 x n3) = Theta_kb^T (P12 x p3) X3f (p3 x n3), both k-blocked.
+// One wave per 16 x 16 output tile, 2 x 2 tiles per workgroup.
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
+  typedef Tr<T> R;
+  typedef typename R::frag_t F;
+  const Geom& G = P.G;
+  const T* __restrict__ A = (const T*)P.theta;
+  const T* __restrict__ B = (const T*)P.X3f;
+  T* __restrict__ T1 = (T*)P.T1;
+  if (P.iter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *P.iter += 1;
+  const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
+  const int mt = blockIdx.x * 2 + (w & 1);
+  const int nt = blockIdx.y * 2 + (w >> 1);
+  const int m = mt * 16 + r;     // A column (P12 index)
+  const int i3 = nt * 16 + r;    // B column (n3 index)
+  const bool am = m < G.P12, bn = i3 < G.n3;
+  typename R::accv_t acc = R::zero();
+  const T* pa = A + (long long)m * 16 + 4 * g;
+  const T* pb = B + (long long)i3 * 16 + 4 * g;
+  const long long sa = (long long)G.P12 * 16, sb = (long long)G.n3 * 16;
+  F fa = am ? load_frag(pa) : zero_frag<T>();
+  F fb = bn ? load_frag(pb) : zero_frag<T>();
+  for (int kb = 1; kb < G.KB3; ++kb) {
+    const F na = am ? load_frag(pa + kb * sa) : zero_frag<T>();
+    const F nb = bn ? load_frag(pb + kb * sb) : zero_frag<T>();
+    mma(acc, fa, fb);
+    fa = na;
+    fb = nb;
+  }
+  mma(acc, fa, fb);
+  if (!bn) return;
+  // scatter into the fragment order of slab_chain's first product
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = mt * 16 + R::kidx(g, i);
+    if (row >= G.P12) continue;
+    const int i1 = row % G.p1, i2 = row / G.p1;
+    const int pp = kpos<T>(i2 & 15);
+    const int lane2 = (pp >> 2) * 16 + (i1 & 15);
+    const long long o = ((((long long)i3 * G.PT + (i1 >> 4)) * G.PT + (i2 >> 4)) * 64 + lane2) * 4 + (pp & 3);
+    T1[o] = R::from_acc(acc[i]);
+  }
+}
+
+// ============================================================================
+// slab_chain
+// ============================================================================
+__host__ __device__ inline int lds_stride(int cols, int esize) { return cols + 16 / esize; }
+
+struct ChainLayout {
+  int sX1a, sX1b, sX2a, sX2b;          // row strides (elements)
+  int oX1a, oX1b, oX2a, oX2b;          // offsets (elements)
+  int total;                           // elements of T
+  int red_off;                         // byte offset of the reduction area
+  int bytes;                           // total bytes
+};
+
+__host__ __device__ inline ChainLayout chain_layout(const Geom& G, int esize, int accsize) {
+  ChainLayout L;
+  const int P = G.PT * 16, N1 = G.N1T * 16, N2 = G.NJB * 16;
+  L.sX1a = lds_stride(P, esize);
+  L.sX1b = lds_stride(N1, esize);
+  L.sX2a = lds_stride(P, esize);
+  L.sX2b = lds_stride(N2, esize);
+  L.oX1a = 0;
+  L.oX1b = L.oX1a + N1 * L.sX1a;
+  L.oX2a = L.oX1b + P * L.sX1b;
+  L.oX2b = L.oX2a + N2 * L.sX2a;
+  L.total = L.oX2b + P * L.sX2b;
+  L.red_off = ((L.total * esize + 15) / 16) * 16;
+  L.bytes = L.red_off + 2 * P * P * accsize;   // two-level cross-wave tree
+  return L;
+}
+
+constexpr int CH = 4;   // mode-1 tiles held in registers at once
+
+template <typename T, int PT, int MODE>
+__global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
+  typedef Tr<T> R;
+  typedef typename R::acc_t A;
+  typedef typename R::accv_t AV;
+  typedef typename R::frag_t F;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = (T*)smem_raw;
+  __shared__ double sred[4 * 4];
+  const Geom& G = P.G;
+  const ChainLayout L = chain_layout(G, (int)sizeof(T), (int)sizeof(A));
+  A* red = (A*)(smem_raw + L.red_off);
+  const int tid = threadIdx.x, lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
+  const int N1 = G.N1T * 16, N2 = G.NJB * 16, PP = PT * 16;
+  constexpr bool NEED_FWD = MODE != SM_ADJ_STD;
+  constexpr bool NEED_ADJ = MODE == SM_ADJ_STD || MODE == SM_FUSED || MODE == SM_FAMILY || MODE == SM_NLL_BWD;
+
+  // ---- stage the mode-1 and mode-2 factors once (zero padded, k-blocked rows) ----
+  {
+    const T* X1 = (const T*)P.X1;
+    const T* X2 = (const T*)P.X2;
+    for (int idx = tid; idx < N1 * PP; idx += WG) {
+      const int i = idx % N1, k = idx / N1;
+      T v = (i < G.n1 && k < G.p1) ? X1[i + (long long)G.n1 * k] : zero_val<T>();
+      sm[L.oX1a + i * L.sX1a + kpos<T>(k)] = v;   // rows n1, contraction p1
+      sm[L.oX1b + k * L.sX1b + kpos<T>(i)] = v;   // rows p1, contraction n1
+    }
+    for (int idx = tid; idx < N2 * PP; idx += WG) {
+      const int i = idx % N2, k = idx / N2;
+      T v = (i < G.n2 && k < G.p2) ? X2[i + (long long)G.n2 * k] : zero_val<T>();
+      sm[L.oX2a + i * L.sX2a + kpos<T>(k)] = v;   // rows n2, contraction p2
+      sm[L.oX2b + k * L.sX2b + kpos<T>(i)] = v;   // rows p2, contraction n2
+    }
+  }
+  __syncthreads();
+
+  double s_nll = 0.0, s_vmax = 0.0;
+
+  for (int i3 = blockIdx.x; i3 < G.n3; i3 += gridDim.x) {
+    F fT1[PT][PT];
+    if (NEED_FWD) {
+      const T* t1 = (const T*)P.T1 + (long long)i3 * PT * PT * 256 + lane * 4;
+#pragma unroll
+      for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+        for (int kb = 0; kb < PT; ++kb) fT1[mt][kb] = load_frag(t1 + (mt * PT + kb) * 256);
+    }
+    AV S2acc[PT][PT];
+#pragma unroll
+    for (int a = 0; a < PT; ++a)
+#pragma unroll
+      for (int b = 0; b < PT; ++b) S2acc[a][b] = R::zero();
+
+    for (int jb = w; jb < G.NJB; jb += WG / 64) {
+      F fT2[PT];
+      if (NEED_FWD) {
+        // step 1: T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T (p2 x 16)
+        F fx2[PT];
+#pragma unroll
+        for (int kb = 0; kb < PT; ++kb) fx2[kb] = load_frag(&sm[L.oX2a + (jb * 16 + r) * L.sX2a + kb * 16 + 4 * g]);
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt) {
+          AV acc = R::zero();
+#pragma unroll
+          for (int kb = 0; kb < PT; ++kb) mma(acc, fT1[mt][kb], fx2[kb]);
+          fT2[mt] = acc_frag<T>(acc);
+        }
+      }
+      AV S1[PT];
+#pragma unroll
+      for (int nt = 0; nt < PT; ++nt) S1[nt] = R::zero();
+
+      for (int u0 = 0; u0 < G.N1T; u0 += CH) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int ut = u0 + c;
+          if (ut >= G.N1T) break;
+          AV E = R::zero();
+          if (NEED_FWD) {
+            // step 2: eta tile (16 x 16) = X1_tile (16 x p1) T2 (p1 x 16)
+#pragma unroll
+            for (int kb = 0; kb < PT; ++kb)
+              mma(E, load_frag(&sm[L.oX1a + (ut * 16 + r) * L.sX1a + kb * 16 + 4 * g]), fT2[kb]);
+          }
+          // step 3: entrywise stage; lane holds rows i1 = 16 ut + kidx(g, i), column i2 = 16 jb + r
+          const int i2 = jb * 16 + r;
+          const long long tbase = (((long long)i3 * G.NJB + jb) * G.N1T + ut) * 256 + r * 16;
+          F fR = zero_frag<T>();
+          if (MODE == SM_FWD_STD) {
+            typedef typename OutOf<T>::type O;
+            O* eta = (O*)P.eta_out;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int i1 = ut * 16 + R::kidx(g, i);
+              if (i1 < G.n1 && i2 < G.n2) eta[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)] = (O)E[i];
+            }
+          } else if (MODE == SM_FWD_INT) {
+            A* eta = (A*)P.eta_out;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) eta[tbase + R::kidx(g, i)] = E[i];
+          } else if (MODE == SM_ADJ_STD) {
+            const T* U = (const T*)P.u_in;
+            T uv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int i1 = ut * 16 + R::kidx(g, t);
+              uv[t] = (i1 < G.n1 && i2 < G.n2) ? U[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)] : zero_val<T>();
+            }
+            fR = raw_frag<T>(uv[0], uv[1], uv[2], uv[3]);
+          } else if (MODE == SM_FUSED) {
+            if (P.v_int) {
+              const A* V = (const A*)P.v_int;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) E[i] *= V[tbase + R::kidx(g, i)];
+            }
+            fR = acc_frag<T>(E);
+          } else if (MODE == SM_FAMILY) {
+            // (FP64 chain) family update of Alg. 1 step 2: u (eq. four), w (eq. nine)
+            AV U;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int i1 = ut * 16 + R::kidx(g, i);
+              const bool valid = i1 < G.n1 && i2 < G.n2;
+              const long long ti = tbase + R::kidx(g, i);
+              const double eta = (double)E[i];
+              const double y = P.y_int[ti];
+              const double a = P.a_int[ti];
+              double mu, wgt, nll;
+              if (P.family == 1) {
+                mu = exp(eta);
+                wgt = mu;
+                nll = a * (mu - y * eta);
+              } else {
+                mu = eta;
+                wgt = 1.0;
+                const double d = y - eta;
+                nll = 0.5 * a * d * d;
+              }
+              P.eta_int[ti] = eta;
+              if (P.v_out) {
+                if (P.v_out_f32) ((float*)P.v_out)[ti] = valid ? (float)wgt : 0.f;
+                else ((double*)P.v_out)[ti] = valid ? wgt : 0.0;
+              }
+              if (valid) {
+                s_nll += nll;
+                s_vmax = fmax(s_vmax, wgt);
+              }
+              U[i] = valid ? (A)(a * (y - mu)) : (A)0;
+            }
+            fR = acc_frag<T>(U);
+          } else if (MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
+            AV U;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int i1 = ut * 16 + R::kidx(g, i);
+              const bool valid = i1 < G.n1 && i2 < G.n2;
+              double e = 0.0, y = 0.0, eta = (double)E[i];
+              if (valid) {
+                y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
+                e = exp(eta);
+                s_nll += e - y * eta;
+              }
+              U[i] = valid ? (A)(e - y) : (A)0;
+            }
+            if (MODE == SM_NLL_BWD) fR = acc_frag<T>(U);
+          }
+          if (NEED_ADJ) {
+            // step 4: S1^T (16 x p1) += R_tile^T (16 x 16) X1_tile (16 x p1)
+#pragma unroll
+            for (int nt = 0; nt < PT; ++nt)
+              mma(S1[nt], fR, load_frag(&sm[L.oX1b + (nt * 16 + r) * L.sX1b + ut * 16 + 4 * g]));
+          }
+        }
+      }
+      if (NEED_ADJ) {
+        // step 5: S2^T (p2 x p1) += X2_blk^T (p2 x 16) S1^T (16 x p1)
+        F fS1[PT];
+#pragma unroll
+        for (int nt = 0; nt < PT; ++nt) fS1[nt] = acc_frag<T>(S1[nt]);
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt) {
+          const F fa = load_frag(&sm[L.oX2b + (mt * 16 + r) * L.sX2b + jb * 16 + 4 * g]);
+#pragma unroll
+          for (int nt = 0; nt < PT; ++nt) mma(S2acc[mt][nt], fa, fS1[nt]);
+        }
+      }
+    }
+
+    if (NEED_ADJ) {
+      // cross-wave sum of S2^T (waves 2,3 -> 0,1, then 1 -> 0), then wave 0 writes
+      // S2 (k-blocked, K = n3, C = P12) straight from its registers
+      const int PP2 = PP * PP;
+      if (w >= 2) {
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < PT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[(w - 2) * PP2 + ((mt * PT + nt) * 4 + i) * 64 + lane] = S2acc[mt][nt][i];
+      }
+      __syncthreads();
+      if (w < 2) {
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < PT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S2acc[mt][nt][i] += red[w * PP2 + ((mt * PT + nt) * 4 + i) * 64 + lane];
+      }
+      __syncthreads();
+      if (w == 1) {
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < PT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[((mt * PT + nt) * 4 + i) * 64 + lane] = S2acc[mt][nt][i];
+      }
+      __syncthreads();
+      if (w == 0) {
+        T* S2 = (T*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<T>(i3 & 15);
+#pragma unroll
+        for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < PT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int b = mt * 16 + R::kidx(g, i);   // p2 index
+              const int a = nt * 16 + r;               // p1 index
+              const A s = S2acc[mt][nt][i] + red[((mt * PT + nt) * 4 + i) * 64 + lane];
+              if (a < G.p1 && b < G.p2) S2[(long long)(a + G.p1 * b) * 16] = R::from_acc(s);
+            }
+      }
+      __syncthreads();
+    }
+  }
+
+  if (MODE == SM_FAMILY || MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
+    double v[2] = {s_nll, s_vmax};
+    const int ops[2] = {0, 1};
+    block_reduce<2>(v, ops, sred);
+    if (tid == 0) {
+      P.partials[(long long)blockIdx.x * 2 + 0] = v[0];
+      P.partials[(long long)blockIdx.x * 2 + 1] = v[1];
+    }
+  }
+}
+
+// ============================================================================
+// slab_adj: out (P12 x p3) = S2^T (P12 x n3) X3a (n3 x p3), split-K over the 4
+// waves of a workgroup (one 16 x 16 output tile per workgroup) + epilogue.
+// ============================================================================
+__device__ inline double soft_threshold(double z, double t) {
+  const double a = fabs(z) - t;
+  return a > 0.0 ? copysign(a, z) : 0.0;
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
+  typedef Tr<T> R;
+  typedef typename R::acc_t A;
+  typedef typename R::frag_t F;
+  __shared__ double sred[4 * 4];
+  __shared__ A red[WG / 64][256];
+  const Geom& G = P.G;
+  const T* __restrict__ S2 = (const T*)P.S2;
+  const T* __restrict__ X3 = (const T*)P.X3a;
+  const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
+  const int bm = blockIdx.x, bn = blockIdx.y;
+  const int m = bm * 16 + r;    // A column (P12 index)
+  const int k3 = bn * 16 + r;   // B column (p3 index)
+  const bool am = m < G.P12, bk = k3 < G.p3;
+  typename R::accv_t acc = R::zero();
+  const T* pa = S2 + (long long)m * 16 + 4 * g;
+  const T* pb = X3 + (long long)k3 * 16 + 4 * g;
+  const long long sa = (long long)G.P12 * 16, sb = (long long)G.p3 * 16;
+  int kb = w;
+  if (kb < G.KBN3) {
+    F fa = am ? load_frag(pa + kb * sa) : zero_frag<T>();
+    F fb = bk ? load_frag(pb + kb * sb) : zero_frag<T>();
+    for (kb += WG / 64; kb < G.KBN3; kb += WG / 64) {
+      const F na = am ? load_frag(pa + kb * sa) : zero_frag<T>();
+      const F nb = bk ? load_frag(pb + kb * sb) : zero_frag<T>();
+      mma(acc, fa, fb);
+      fa = na;
+      fb = nb;
+    }
+    mma(acc, fa, fb);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[w][R::kidx(g, i) * 16 + r] = acc[i];
+  __syncthreads();
+
+  // one thread per tile element: row (P12 index) = t % 16, column (p3 index) = t / 16
+  const int t = threadIdx.x;
+  const int row = bm * 16 + (t & 15), col = bn * 16 + (t >> 4);
+  const int q = (t & 15) * 16 + (t >> 4);
+  const double a = (double)(red[0][q] + red[1][q] + red[2][q] + red[3][q]);
+  double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0;
+  if (row < G.P12 && col < G.p3) {
+    const long long j = (long long)row + (long long)G.P12 * col;
+    if (EPI == EPI_STORE) {
+      double s = P.scale;
+      if (P.gscale_dev) s *= *P.gscale_dev;
+      ((typename OutOf<T>::type*)P.out)[j] = (typename OutOf<T>::type)(s * a);
+    } else if (EPI == EPI_GRAD) {
+      const double gv = P.scale * a;
+      P.gout[j] = gv;
+      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      red_lmax = fabs(gv) / wm;
+      if (P.theta) {
+        const double th = P.theta[j];
+        const double lw = P.lambda * wm;
+        red_kkt = th != 0.0 ? fabs(gv + copysign(lw, th)) : fmax(fabs(gv) - lw, 0.0);
+        red_pen = wm * fabs(th);
+      }
+    } else {  // EPI_PROX: one inner PG step (Sec. 3.2) with FISTA extrapolation
+      const double l_iter = (double)(*P.iter);
+      const double om = (l_iter - 1.0) / (l_iter + 2.0);
+      const double incg = P.scale * a;               // G(V H(x - theta_ref)) / n
+      const double gx = P.gref[j] + incg;            // grad h(x^l)
+      const double x = P.x[j], xp = P.xp[j], gp = P.gp[j];
+      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      const double lw = P.lambda * wm;
+      red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
+      red_noise = fabs(incg);
+      const double gy = gx + om * (gx - gp);          // grad h(y) by linearity (h quadratic)
+      const double yv = x + om * (x - xp);
+      const double xn = soft_threshold(yv - P.delta * gy, P.delta * lw);
+      P.xp[j] = x;
+      P.x[j] = xn;
+      P.gp[j] = gx;
+      const double dinc = xn - P.theta_ref[j];
+      red_inc = fabs(dinc);
+      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
+          R::from_acc((typename R::acc_t)dinc);
+    }
+  }
+  if (EPI == EPI_GRAD || EPI == EPI_PROX) {
+    double v[4] = {red_kkt, EPI == EPI_GRAD ? red_lmax : red_noise, EPI == EPI_GRAD ? red_pen : 0.0, red_inc};
+    const int ops[4] = {1, 1, 0, 1};
+    block_reduce<4>(v, ops, sred);
+    if (threadIdx.x == 0) {
+      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) P.partials[b * 4 + s] = v[s];
+    }
+  }
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+static int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s) {
+  dim3 grid((P.G.P12 + 31) / 32, (P.G.n3 + 31) / 32);
+  if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd<double>, grid, dim3(WG), 0, s, P);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_slab_fwd<float>, grid, dim3(WG), 0, s, P);
+  else hipLaunchKernelGGL(k_slab_fwd<bf16>, grid, dim3(WG), 0, s, P);
+  return hipGetLastError();
+}
+
+size_t slab_chain_lds_bytes(int dt, const Geom& G) {
+  return (size_t)chain_layout(G, (int)dt_size(dt), dt == DT_F64 ? 8 : 4).bytes;
+}
+
+int slab_chain_blocks(int dt, const Geom& G) {
+  const size_t lds = slab_chain_lds_bytes(dt, G);
+  int per_cu = (int)((160 * 1024) / (lds + 512));
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 4) per_cu = 4;
+  long long b = (long long)num_cus() * per_cu;
+  if (b > G.n3) b = G.n3;
+  return (int)b;
+}
+
+template <typename K>
+static void set_lds(K fn, size_t lds) {
+  if (lds > 65536) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T, int PT>
+static hipError_t chain_dispatch_mode(int mode, const SlabParams& P, int nb, size_t lds, hipStream_t s) {
+  dim3 grid(nb), blk(WG);
+#define GLAM_CASE(M)                                    \
+  case M: {                                             \
+    auto fn = k_slab_chain<T, PT, M>;                   \
+    set_lds(fn, lds);                                   \
+    hipLaunchKernelGGL(fn, grid, blk, lds, s, P);       \
+    break;                                              \
+  }
+  switch (mode) {
+    GLAM_CASE(SM_FWD_STD)
+    GLAM_CASE(SM_FWD_INT)
+    GLAM_CASE(SM_ADJ_STD)
+    GLAM_CASE(SM_FUSED)
+    GLAM_CASE(SM_NLL_FWD)
+    GLAM_CASE(SM_NLL_BWD)
+    default: return hipErrorInvalidValue;
+  }
+#undef GLAM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s) {
+  const size_t lds = slab_chain_lds_bytes(dt, P.G);
+  const int nb = slab_chain_blocks(dt, P.G);
+  if (nblk_out) *nblk_out = nb;
+  dim3 grid(nb), blk(WG);
+  if (mode == SM_FAMILY) {
+    if (dt != DT_F64) return hipErrorInvalidValue;
+    if (P.G.PT == 1) {
+      auto fn = k_slab_chain<double, 1, SM_FAMILY>;
+      set_lds(fn, lds);
+      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);
+    } else {
+      auto fn = k_slab_chain<double, 2, SM_FAMILY>;
+      set_lds(fn, lds);
+      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);
+    }
+    return hipGetLastError();
+  }
+  const int PT = P.G.PT;
+  if (dt == DT_F64) return PT == 1 ? chain_dispatch_mode<double, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<double, 2>(mode, P, nb, lds, s);
+  if (dt == DT_F32) return PT == 1 ? chain_dispatch_mode<float, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<float, 2>(mode, P, nb, lds, s);
+  return PT == 1 ? chain_dispatch_mode<bf16, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<bf16, 2>(mode, P, nb, lds, s);
+}
+
+int slab_adj_blocks(const Geom& G) { return ((G.P12 + 15) / 16) * ((G.p3 + 15) / 16); }
+
+hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, hipStream_t s) {
+  dim3 grid((P.G.P12 + 15) / 16, (P.G.p3 + 15) / 16);
+  if (nblk_out) *nblk_out = (int)(grid.x * grid.y);
+#define GLAM_ADJ(T)                                                                              \
+  do {                                                                                           \
+    if (epi == EPI_STORE) hipLaunchKernelGGL((k_slab_adj<T, EPI_STORE>), grid, dim3(WG), 0, s, P); \
+    else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_slab_adj<T, EPI_GRAD>), grid, dim3(WG), 0, s, P); \
+    else hipLaunchKernelGGL((k_slab_adj<T, EPI_PROX>), grid, dim3(WG), 0, s, P);                 \
+  } while (0)
+  if (dt == DT_F64) GLAM_ADJ(double);
+  else if (dt == DT_F32) GLAM_ADJ(float);
+  else GLAM_ADJ(bf16);
+#undef GLAM_ADJ
+  return hipGetLastError();
+}
+
+}  // namespace glam

@@ -43,7 +43,7 @@ class GlamOptions(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("nlambda", ctypes.c_int),
                 ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
                 ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp)]
+                ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int)]
 
 
 class GlamResult(ctypes.Structure):
@@ -51,7 +51,8 @@ class GlamResult(ctypes.Structure):
                 ("kkt", ctypes.POINTER(ctypes.c_double)), ("objective", ctypes.POINTER(ctypes.c_double)),
                 ("iters_outer", ctypes.POINTER(ctypes.c_int)), ("iters_inner", ctypes.POINTER(ctypes.c_int)),
                 ("status", ctypes.POINTER(ctypes.c_int)), ("n_done", ctypes.c_int), ("lambda_max", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("chain_ms", ctypes.c_double), ("chain_samples", ctypes.c_int),
+                ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong)]
 
 
 def _sig(name, res, args):
@@ -262,11 +263,15 @@ class PathResult:
     lambda_max: float
     seconds: float
     code: int
+    chain_ms: float = 0.0
+    chain_samples: int = 0
+    iter_ms: float = 0.0
+    inner_total: int = 0
 
 
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
-             check_every=10, theta0=None, stream=None, raise_on_error=True) -> PathResult:
+             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0) -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays."""
     torch = _torch()
@@ -297,6 +302,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.check_every = int(check_every)
     opt.theta0 = theta0.data_ptr() if theta0 is not None else None
     opt.stream = _stream_ptr(stream)
+    opt.profile_every = int(profile_every)
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()
@@ -314,7 +320,8 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
         raise GlamError(code, "glam_fit_path")
     out = PathResult(np.array(lam_out[:]), theta, np.array(kkt[:]), np.array(obj[:]), np.array(io[:]),
                      np.array(ii[:]), np.array(stt[:]), int(res.n_done), float(res.lambda_max),
-                     float(res.seconds), int(code))
+                     float(res.seconds), int(code), float(res.chain_ms), int(res.chain_samples),
+                     float(res.iter_ms), int(res.inner_total))
     if raise_on_error and code != GLAM_OK:
         raise GlamError(code, "glam_fit_path")
     return out
