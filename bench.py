@@ -96,7 +96,8 @@ def main():
     ap.add_argument("--nlambda", type=int, default=100)
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed runs of the other forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--profile-every", type=int, default=16)
+    ap.add_argument("--profile-every", type=int, default=160,
+                    help="time one inner iteration in this many with HIP events (those blocks run un-captured)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -144,6 +145,7 @@ def main():
     achieved = chain / avg_chain if samples else None
     roofline = {
         "kernel": "slab_chain (fused modes 1-2 forward + adjoint of one inner PG iteration)",
+        "timing": "HIP events around sampled eager launches on the fit's stream (event-pair overhead included)",
         "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
         "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
         "frac": (achieved / PEAKS[args.dtype]) if achieved else None,

@@ -119,8 +119,10 @@ typedef struct {
   int check_every;        /* inner iterations between host convergence checks (>= 1) */
   const double* theta0;   /* device, FP64 p-array warm start for the first lambda, or NULL */
   void* stream;           /* hipStream_t (NULL = default stream)                    */
-  int profile_every;      /* > 0: time every profile_every-th inner iteration's fused
-                             slab kernel with HIP events on `stream` (0 = off)      */
+  int profile_every;      /* > 0: time the fused slab kernel of one inner iteration in
+                             every profile_every with HIP events (0 = off)          */
+  int graph_mode;         /* 0: replay each block of check_every inner iterations as a
+                             captured HIP graph (default); 1: plain stream launches */
 } glam_options;
 
 typedef struct {

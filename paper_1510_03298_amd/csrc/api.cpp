@@ -38,7 +38,7 @@ Geom make_geom(const int64_t* n, const int64_t* p) {
   G.nint = (long long)G.n3 * G.NJB * G.N1T * 256;
   G.n = (long long)G.n1 * G.n2 * G.n3;
   G.p = (long long)G.p1 * G.p2 * G.p3;
-  G.t1_len = (long long)G.n3 * G.PT * G.PT * 256;
+  G.t1_len = (long long)G.n3 * G.P12;
   G.s2_len = (long long)G.KBN3 * 16 * G.P12;
   G.inc_len = (long long)G.KB3 * 16 * G.P12;
   G.x3f_len = (long long)G.KB3 * 16 * G.n3;
@@ -74,12 +74,13 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace of the rho / NLL entry points: k-blocked Theta, both packed copies of
 // X_3, fragment-ordered T1, k-blocked S2 and per-workgroup partial sums.
 struct WsLayout {
-  size_t inc, x3f, t1, x3a, s2, part, total;
+  size_t img, inc, x3f, t1, x3a, s2, part, total;
 };
 static WsLayout ws_layout(const Geom& G, int dt) {
   const size_t es = dt_size(dt);
   WsLayout W;
   size_t o = 0;
+  W.img = o; o += align256(chain_image_bytes(dt, G));
   W.inc = o; o += align256(G.inc_len * es);
   W.x3f = o; o += align256(G.x3f_len * es);
   W.t1 = o;  o += align256(G.t1_len * es);
@@ -140,12 +141,12 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, Theta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
-  HIPCHK(launch_zero(ws + W.t1, G.t1_len * es, s));
   FwdParams F{};
   F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1; F.iter = nullptr;
   HIPCHK(launch_slab_fwd(dtype, F, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.eta_out = Eta;
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
+  S.G = G; S.img = ws + W.img; S.T1 = ws + W.t1; S.eta_out = Eta;
   HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, nullptr, s));
   return GLAM_OK;
 }
@@ -165,7 +166,8 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
   HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.S2 = ws + W.s2; S.u_in = U;
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
+  S.G = G; S.img = ws + W.img; S.S2 = ws + W.s2; S.u_in = U;
   HIPCHK(launch_slab_chain(dtype, SM_ADJ_STD, S, nullptr, s));
   AdjParams A{};
   A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = Out; A.scale = 1.0;
@@ -185,7 +187,7 @@ static int nll_prepare(const Geom& G, const void* const* X, const void* beta, in
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, beta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
-  HIPCHK(launch_zero(ws + W.t1, G.t1_len * es, s));
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
   FwdParams F{};
   F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1;
   HIPCHK(launch_slab_fwd(dtype, F, s));
@@ -208,7 +210,7 @@ int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* con
   if (st) return st;
   double* part = (double*)(ws + W.part);
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.y_std = Y; S.partials = part;
+  S.G = G; S.img = ws + W.img; S.T1 = ws + W.t1; S.y_std = Y; S.partials = part;
   int nb = 0;
   HIPCHK(launch_slab_chain(dtype, SM_NLL_FWD, S, &nb, s));
   const int ops[1] = {0};
@@ -234,7 +236,7 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
   HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
-  S.G = G; S.X1 = X[0]; S.X2 = X[1]; S.T1 = ws + W.t1; S.S2 = ws + W.s2; S.y_std = Y;
+  S.G = G; S.img = ws + W.img; S.T1 = ws + W.t1; S.S2 = ws + W.s2; S.y_std = Y;
   S.partials = (double*)(ws + W.part);
   HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, nullptr, s));
   AdjParams A{};

@@ -83,7 +83,8 @@ struct Fit {
   const glam_problem* prob;
   // device buffers (owned; freed by the destructor)
   std::vector<void*> bufs;
-  const void* Xc[2];       // chain-dtype mode-1 and mode-2 factors
+  void* imgc;              // LDS image of X1, X2 in the chain dtype
+  void* imgd;              // LDS image of X1, X2 in FP64
   void *X3fc, *X3ac;       // chain-dtype packed mode-3 factor (slab_fwd / slab_adj operands)
   double *X3fd, *X3ad;     // FP64 packed mode-3 factor
   double* thpk;            // FP64 k-blocked copy of theta (or of a direction)
@@ -100,6 +101,14 @@ struct Fit {
   double sprod;            // prod_j rho(X_j^T X_j)
   std::string err;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
+  hipStream_t us = nullptr;        // caller's stream
+  bool own_stream = false;
+  hipEvent_t sync_ev = nullptr;
+  double* dparams = nullptr;       // device {lambda, delta}
+  double* hparams = nullptr;       // pinned host staging of dparams
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_m = 0;                 // inner iterations per graph replay
   bool pending = false;
   double chain_ms = 0.0, iter_ms = 0.0;
   int samples = 0;
@@ -114,10 +123,15 @@ struct Fit {
   Fit(const Fit&) = delete;
   Fit& operator=(const Fit&) = delete;
   ~Fit() {
-    if (!bufs.empty()) (void)hipStreamSynchronize(s);
+    if (s) (void)hipStreamSynchronize(s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
     for (void* p : bufs) (void)hipFree(p);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (sync_ev) (void)hipEventDestroy(sync_ev);
+    if (hparams) (void)hipHostFree(hparams);
+    if (own_stream && s) (void)hipStreamDestroy(s);
   }
 };
 
@@ -146,7 +160,7 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
   fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
   FCHK(launch_slab_fwd(DT_F64, fw, F.s));
   SlabParams sp{};
-  sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.S2 = F.S2d;
+  sp.G = G; sp.img = F.imgd; sp.T1 = F.T1d; sp.S2 = F.S2d;
   sp.y_int = F.y_int; sp.a_int = F.a_int; sp.eta_int = F.eta_int;
   sp.v_out = F.v_int; sp.v_out_f32 = F.dt != DT_F64; sp.family = F.family; sp.partials = F.part;
   int nbc = 0;
@@ -180,14 +194,14 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c; fw.iter = F.iter;
   FCHK(launch_slab_fwd(F.dt, fw, F.s));
   SlabParams sp{};
-  sp.G = G; sp.X1 = F.Xc[0]; sp.X2 = F.Xc[1]; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
+  sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
   if (sample) FCHK(hipEventRecord(F.ev[1], F.s));
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
   if (sample) FCHK(hipEventRecord(F.ev[2], F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
   ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
-  ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta;
+  ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
   if (sample) {
     FCHK(hipEventRecord(F.ev[3], F.s));
@@ -210,6 +224,39 @@ static int collect_sample(Fit& F) {
   return GLAM_OK;
 }
 
+// One block of m inner iterations followed by the reduction of the last
+// iteration's partial KKT / noise maxima into F.red[0..3].  Captured once per fit
+// as a HIP graph (the only per-lambda / per-outer values live in F.dparams).
+static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
+  for (int q = 0; q < m; ++q) {
+    int r = inner_iteration(F, 0.0, 0.0, nblk, sample_first && q == 0);
+    if (r) return r;
+  }
+  const int ops[4] = {1, 1, 0, 1};
+  FCHK(launch_reduce(F.part, *nblk, 4, ops, 1.0, F.red, F.s));
+  return GLAM_OK;
+}
+
+static int inner_block_graph(Fit& F, int m, int* nblk) {
+  if (!F.gexec || F.graph_m != m) {
+    if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
+    if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
+    FCHK(hipStreamBeginCapture(F.s, hipStreamCaptureModeRelaxed));
+    int r = inner_block_eager(F, m, false, nblk);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(F.s, &g);
+    if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+    FCHK(e);
+    F.graph = g;
+    FCHK(hipGraphInstantiate(&F.gexec, F.graph, nullptr, nullptr, 0));
+    F.graph_m = m;
+  } else {
+    *nblk = slab_adj_blocks(F.G);
+  }
+  FCHK(hipGraphLaunch(F.gexec, F.s));
+  return GLAM_OK;
+}
+
 // Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
 static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* delta_out) {
   const Geom& G = F.G;
@@ -219,7 +266,7 @@ static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* de
   fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
   FCHK(launch_slab_fwd(DT_F64, fw, F.s));
   SlabParams sp{};
-  sp.G = G; sp.X1 = F.prob->X[0]; sp.X2 = F.prob->X[1]; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
+  sp.G = G; sp.img = F.imgd; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
   FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, nullptr, F.s));
   constexpr int NV = ARMIJO_TRIALS + 1;
   const int ops[NV] = {0};
@@ -295,7 +342,14 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   Fit F;
   F.G = make_geom(prob->n, prob->p);
   F.dt = opt->dtype;
-  F.s = (hipStream_t)opt->stream;
+  F.us = (hipStream_t)opt->stream;
+  // work on an internal non-blocking stream (capturable), ordered after the caller's stream
+  if (hipStreamCreateWithFlags(&F.s, hipStreamNonBlocking) != hipSuccess)
+    return fit_fail(GLAM_EDEVICE, "hipStreamCreateWithFlags failed");
+  F.own_stream = true;
+  if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
+    return fit_fail(GLAM_EDEVICE, "stream ordering failed");
   F.family = prob->family;
   F.prob = prob;
   const Geom& G = F.G;
@@ -316,15 +370,15 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   F.X3fd = (double*)A(G.x3f_len * 8);
   F.X3ad = (double*)A(G.x3a_len * 8);
   F.thpk = (double*)A(G.inc_len * 8);
+  F.imgd = A(chain_image_bytes(DT_F64, G));
   if (F.dt == DT_F64) {
-    F.T1c = F.T1d; F.S2c = F.S2d; F.X3fc = F.X3fd; F.X3ac = F.X3ad;
-    for (int j = 0; j < 2; ++j) F.Xc[j] = prob->X[j];
+    F.T1c = F.T1d; F.S2c = F.S2d; F.X3fc = F.X3fd; F.X3ac = F.X3ad; F.imgc = F.imgd;
   } else {
     F.T1c = A(G.t1_len * es);
     F.S2c = A(G.s2_len * es);
     F.X3fc = A(G.x3f_len * es);
     F.X3ac = A(G.x3a_len * es);
-    for (int j = 0; j < 2; ++j) F.Xc[j] = A((size_t)prob->n[j] * prob->p[j] * es);
+    F.imgc = A(chain_image_bytes(F.dt, G));
   }
   F.theta = (double*)A(G.p * 8);
   F.gref = (double*)A(G.p * 8);
@@ -336,11 +390,13 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   F.iter = (int*)A(sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
+  F.dparams = (double*)A(2 * 8);
   if (!ok) return fit_fail(GLAM_ENOMEM, "device allocation failed");
   if (opt->profile_every > 0)
     for (auto& e : F.ev)
       if (hipEventCreate(&e) != hipSuccess) return fit_fail(GLAM_EDEVICE, "hipEventCreate failed");
-  if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess)
+  if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&F.hparams, 2 * sizeof(double)) != hipSuccess)
     return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
   struct HostFree { double* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{F.hred};
 
@@ -371,18 +427,15 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   // ---- setup: tiled data, chain copies of the factors, spectral radii ----
   PCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
   PCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
-  if (F.dt != DT_F64)
-    for (int j = 0; j < 2; ++j)
-      PCHK(launch_convert(F.dt, prob->X[j], (void*)F.Xc[j], (long long)prob->n[j] * prob->p[j], F.s));
+  PCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s));
+  if (F.dt != DT_F64) PCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s));
   // packed mode-3 factor (FP64 and chain dtype); zero the padded intermediates once
   PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fd, F.s));
   PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ad, F.s));
-  PCHK(launch_zero(F.T1d, G.t1_len * 8, F.s));
-  PCHK(launch_zero(F.S2d, G.s2_len * 8, F.s));
+  PCHK(launch_zero(F.S2d, G.s2_len * 8, F.s));   // rows beyond n3 stay zero
   if (F.dt != DT_F64) {
     PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fc, F.s));
     PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ac, F.s));
-    PCHK(launch_zero(F.T1c, G.t1_len * es, F.s));
     PCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
   }
   F.sprod = 1.0;
@@ -448,6 +501,9 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
       if (F.dt == DT_BF16) tol_in = std::max(tol_in, 0.1 * kkt);
       // ---- inner PG loop ----
       PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      F.hparams[0] = lam;
+      F.hparams[1] = delta;
+      PCHK(hipMemcpyAsync(F.dparams, F.hparams, 2 * sizeof(double), hipMemcpyHostToDevice, F.s));
       int it = 0;
       double kin = INFINITY, noise = 0.0;
       double best = INFINITY, window_best = INFINITY;
@@ -455,14 +511,11 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
       while (it < opt->max_inner) {
         int nb = 0;
         const int m = std::min(check_every, opt->max_inner - it);
-        for (int q = 0; q < m; ++q) {
-          const long long gi = inner_total + it + q;
-          const bool sample = opt->profile_every > 0 && (gi % opt->profile_every) == 0 && !F.pending;
-          RCHK(inner_iteration(F, lam, delta, &nb, sample));
-        }
+        const long long gi = path_inner + inner_total + it;
+        const bool sample = opt->profile_every > 0 && (gi / check_every) % std::max(1, opt->profile_every / check_every) == 0;
+        if (opt->graph_mode == 0 && m == check_every && !sample) RCHK(inner_block_graph(F, m, &nb));
+        else RCHK(inner_block_eager(F, m, sample, &nb));
         it += m;
-        const int ops[4] = {1, 1, 0, 1};
-        PCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
         PCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
         PCHK(hipStreamSynchronize(F.s));
         RCHK(collect_sample(F));
@@ -510,6 +563,8 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   }
   PCHK(hipStreamSynchronize(F.s));
   RCHK(collect_sample(F));
+  PCHK(hipEventRecord(F.sync_ev, F.s));
+  PCHK(hipStreamWaitEvent(F.us, F.sync_ev, 0));
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   res->chain_ms = F.chain_ms;
   res->iter_ms = F.iter_ms;

@@ -12,8 +12,7 @@
 //    so that one lane's MFMA fragment is 4 contiguous elements;
 //    S2 (K = n3, C = P12), the increment / Theta (K = p3, C = P12), and the two
 //    copies of X_3 (K = p3, C = n3 for slab_fwd; K = n3, C = p3 for slab_adj).
-//  * T1 in fragment order: slab i3, p1-tile mt, p2-block kb, lane, slot t:
-//      ((((i3 * PT + mt) * PT + kb) * 64 + lane) * 4 + t)
+//  * T1 slab-major: [i3][m], m = i1 + p1 * i2 (one contiguous p1 x p2 block per slab)
 //  * tiled n-arrays (eta, V, Y, a): slab i3, mode-2 tile jb, mode-1 tile ut,
 //    a 16 x 16 column-major tile (i1 fastest):
 //      ((i3 * NJB + jb) * N1T + ut) * 256 + (i2 % 16) * 16 + (i1 % 16)
@@ -33,7 +32,7 @@ struct Geom {
   long long nint;   // length of a tiled n-array
   long long n;      // n1 * n2 * n3
   long long p;      // p1 * p2 * p3
-  long long t1_len; // n3 * PT * PT * 256
+  long long t1_len; // n3 * P12
   long long s2_len; // KBN3 * 16 * P12
   long long inc_len;// KB3 * 16 * P12
   long long x3f_len;// KB3 * 16 * n3
@@ -58,9 +57,8 @@ enum SlabMode {
 
 struct SlabParams {
   Geom G;
-  const void* X1;     // chain type, n1 x p1 column-major
-  const void* X2;     // chain type, n2 x p2 column-major
-  const void* T1;     // chain type, fragment-ordered slabs
+  const void* img;    // LDS image of X1 and X2 in the chain type (launch_pack_chain_image)
+  const void* T1;     // chain type, slab-major [n3][P12]
   void* S2;           // chain type, k-blocked (K = n3, C = P12)
   void* eta_out;      // FWD_STD / FWD_INT output
   const void* u_in;   // ADJ_STD input (chain type, standard layout)
@@ -101,13 +99,15 @@ struct AdjParams {
   void* inc;             // chain type, k-blocked (K = p3, C = P12): x^{l+1} - theta_ref
   const int* iter;       // device iteration counter l
   double delta;          // step size
+  const double* dparams; // optional device {lambda, delta} (overrides the two scalars; lets a
+                         // captured graph be replayed across lambdas and outer iterations)
 };
 
 struct FwdParams {
   Geom G;
   const void* theta;  // chain type, k-blocked (K = p3, C = P12)
   const void* X3f;    // chain type, k-blocked (K = p3, C = n3)
-  void* T1;           // chain type, fragment-ordered
+  void* T1;           // chain type, slab-major [n3][P12]
   int* iter;          // optional: incremented once by the first thread
 };
 
@@ -116,6 +116,10 @@ hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
 hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s);
 hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, hipStream_t s);
 size_t slab_chain_lds_bytes(int dt, const Geom& G);
+// LDS image of the mode-1 / mode-2 factors (X1, X2: n_j x p_j column-major, FP64 or chain dtype)
+size_t chain_image_bytes(int dt, const Geom& G);
+hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void* X1, const void* X2, void* img,
+                                   hipStream_t s);
 int slab_adj_blocks(const Geom& G);
 int slab_chain_blocks(int dt, const Geom& G);
 

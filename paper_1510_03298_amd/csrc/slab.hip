@@ -54,6 +54,42 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
   }
 }
 
+// acc += sum over the k-blocks kb = kb0 + j * kstep (j < nkb) of A_kb^T B_kb, with
+// fragments loaded NB blocks ahead of the matrix-core work (k-blocked operands).
+template <typename T, int NB>
+__device__ inline void kblock_loop(typename Tr<T>::accv_t& acc, const T* pa, const T* pb, long long sa, long long sb,
+                                   int kb0, int kstep, int nkb, bool am, bool bn) {
+  typedef typename Tr<T>::frag_t F;
+  F fa[NB], fb[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const bool in = q < nkb;
+    const long long kb = kb0 + (long long)q * kstep;
+    fa[q] = (in && am) ? load_frag(pa + kb * sa) : zero_frag<T>();
+    fb[q] = (in && bn) ? load_frag(pb + kb * sb) : zero_frag<T>();
+  }
+  for (int j = 0; j < nkb; j += NB) {
+    F na[NB], nb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const bool in = j + NB + q < nkb;
+      const long long kb = kb0 + (long long)(j + NB + q) * kstep;
+      na[q] = (in && am) ? load_frag(pa + kb * sa) : zero_frag<T>();
+      nb[q] = (in && bn) ? load_frag(pb + kb * sb) : zero_frag<T>();
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) mma(acc, fa[q], fb[q]);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      fa[q] = na[q];
+      fb[q] = nb[q];
+    }
+  }
+}
+
+template <typename T> struct KNB { static constexpr int v = 4; };
+template <> struct KNB<bf16> { static constexpr int v = 8; };
+
 // ============================================================================
 // slab_fwd: T1 (P12 x n3) = Theta_kb^T (P12 x p3) X3f (p3 x n3), both k-blocked.
 // One wave per 16 x 16 output tile, 2 x 2 tiles per workgroup.
@@ -77,27 +113,13 @@ __global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
   const T* pa = A + (long long)m * 16 + 4 * g;
   const T* pb = B + (long long)i3 * 16 + 4 * g;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.n3 * 16;
-  F fa = am ? load_frag(pa) : zero_frag<T>();
-  F fb = bn ? load_frag(pb) : zero_frag<T>();
-  for (int kb = 1; kb < G.KB3; ++kb) {
-    const F na = am ? load_frag(pa + kb * sa) : zero_frag<T>();
-    const F nb = bn ? load_frag(pb + kb * sb) : zero_frag<T>();
-    mma(acc, fa, fb);
-    fa = na;
-    fb = nb;
-  }
-  mma(acc, fa, fb);
+  kblock_loop<T, KNB<T>::v>(acc, pa, pb, sa, sb, 0, 1, G.KB3, am, bn);
   if (!bn) return;
-  // scatter into the fragment order of slab_chain's first product
+  // T1 slab-major: T1[i3][m] (the chain kernel reads one contiguous slab)
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int row = mt * 16 + R::kidx(g, i);
-    if (row >= G.P12) continue;
-    const int i1 = row % G.p1, i2 = row / G.p1;
-    const int pp = kpos<T>(i2 & 15);
-    const int lane2 = (pp >> 2) * 16 + (i1 & 15);
-    const long long o = ((((long long)i3 * G.PT + (i1 >> 4)) * G.PT + (i2 >> 4)) * 64 + lane2) * 4 + (pp & 3);
-    T1[o] = R::from_acc(acc[i]);
+    if (row < G.P12) T1[(long long)i3 * G.P12 + row] = R::from_acc(acc[i]);
   }
 }
 
@@ -106,17 +128,23 @@ __global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
 // ============================================================================
 __host__ __device__ inline int lds_stride(int cols, int esize) { return cols + 16 / esize; }
 
+constexpr int CH = 4;   // mode-1 tiles held in registers at once (mode 1 is padded to a multiple)
+
 struct ChainLayout {
   int sX1a, sX1b, sX2a, sX2b;          // row strides (elements)
   int oX1a, oX1b, oX2a, oX2b;          // offsets (elements)
   int total;                           // elements of T
+  int image_bytes;                     // bytes of the factor image (multiple of 16)
+  int t1_off;                          // byte offset of the T1 slab copy (P12 elements)
   int red_off;                         // byte offset of the reduction area
   int bytes;                           // total bytes
 };
 
+__host__ __device__ inline int n1_tiles_padded(const Geom& G) { return ((G.N1T + CH - 1) / CH) * CH; }
+
 __host__ __device__ inline ChainLayout chain_layout(const Geom& G, int esize, int accsize) {
   ChainLayout L;
-  const int P = G.PT * 16, N1 = G.N1T * 16, N2 = G.NJB * 16;
+  const int P = G.PT * 16, N1 = n1_tiles_padded(G) * 16, N2 = G.NJB * 16;
   L.sX1a = lds_stride(P, esize);
   L.sX1b = lds_stride(N1, esize);
   L.sX2a = lds_stride(P, esize);
@@ -126,12 +154,12 @@ __host__ __device__ inline ChainLayout chain_layout(const Geom& G, int esize, in
   L.oX2a = L.oX1b + P * L.sX1b;
   L.oX2b = L.oX2a + N2 * L.sX2a;
   L.total = L.oX2b + P * L.sX2b;
-  L.red_off = ((L.total * esize + 15) / 16) * 16;
+  L.image_bytes = ((L.total * esize + 15) / 16) * 16;
+  L.t1_off = L.image_bytes;
+  L.red_off = L.t1_off + ((G.P12 * esize + 15) / 16) * 16;
   L.bytes = L.red_off + 2 * P * P * accsize;   // two-level cross-wave tree
   return L;
 }
-
-constexpr int CH = 4;   // mode-1 tiles held in registers at once
 
 template <typename T, int PT, int MODE>
 __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
@@ -146,39 +174,50 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
   const ChainLayout L = chain_layout(G, (int)sizeof(T), (int)sizeof(A));
   A* red = (A*)(smem_raw + L.red_off);
   const int tid = threadIdx.x, lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int N1 = G.N1T * 16, N2 = G.NJB * 16, PP = PT * 16;
+  const int PP = PT * 16;
+  T* t1s = (T*)(smem_raw + L.t1_off);
   constexpr bool NEED_FWD = MODE != SM_ADJ_STD;
   constexpr bool NEED_ADJ = MODE == SM_ADJ_STD || MODE == SM_FUSED || MODE == SM_FAMILY || MODE == SM_NLL_BWD;
 
-  // ---- stage the mode-1 and mode-2 factors once (zero padded, k-blocked rows) ----
+  // ---- stage the mode-1 and mode-2 factors once: a straight 16-byte copy of the
+  // pre-packed LDS image (see pack_chain_image) ----
   {
-    const T* X1 = (const T*)P.X1;
-    const T* X2 = (const T*)P.X2;
-    for (int idx = tid; idx < N1 * PP; idx += WG) {
-      const int i = idx % N1, k = idx / N1;
-      T v = (i < G.n1 && k < G.p1) ? X1[i + (long long)G.n1 * k] : zero_val<T>();
-      sm[L.oX1a + i * L.sX1a + kpos<T>(k)] = v;   // rows n1, contraction p1
-      sm[L.oX1b + k * L.sX1b + kpos<T>(i)] = v;   // rows p1, contraction n1
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    const u4v* src = (const u4v*)P.img;
+    u4v* dst = (u4v*)smem_raw;
+    const int nvec = L.image_bytes / 16;
+    int idx = tid;
+    for (; idx + 3 * WG < nvec; idx += 4 * WG) {
+      const u4v a0 = src[idx], a1 = src[idx + WG], a2 = src[idx + 2 * WG], a3 = src[idx + 3 * WG];
+      dst[idx] = a0; dst[idx + WG] = a1; dst[idx + 2 * WG] = a2; dst[idx + 3 * WG] = a3;
     }
-    for (int idx = tid; idx < N2 * PP; idx += WG) {
-      const int i = idx % N2, k = idx / N2;
-      T v = (i < G.n2 && k < G.p2) ? X2[i + (long long)G.n2 * k] : zero_val<T>();
-      sm[L.oX2a + i * L.sX2a + kpos<T>(k)] = v;   // rows n2, contraction p2
-      sm[L.oX2b + k * L.sX2b + kpos<T>(i)] = v;   // rows p2, contraction n2
-    }
+    for (; idx < nvec; idx += WG) dst[idx] = src[idx];
   }
   __syncthreads();
 
   double s_nll = 0.0, s_vmax = 0.0;
 
+  const int N1Tp = n1_tiles_padded(G);
   for (int i3 = blockIdx.x; i3 < G.n3; i3 += gridDim.x) {
     F fT1[PT][PT];
     if (NEED_FWD) {
-      const T* t1 = (const T*)P.T1 + (long long)i3 * PT * PT * 256 + lane * 4;
+      // the slab's p1 x p2 block of T1 (contiguous), then fragments: row p1, contraction p2
+      const T* t1 = (const T*)P.T1 + (long long)i3 * G.P12;
+      for (int idx = tid; idx < G.P12; idx += WG) t1s[idx] = t1[idx];
+      __syncthreads();
 #pragma unroll
       for (int mt = 0; mt < PT; ++mt)
 #pragma unroll
-        for (int kb = 0; kb < PT; ++kb) fT1[mt][kb] = load_frag(t1 + (mt * PT + kb) * 256);
+        for (int kb = 0; kb < PT; ++kb) {
+          T v[4];
+          const int i1 = mt * 16 + r;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i2 = kb * 16 + R::kidx(g, t);
+            v[t] = (i1 < G.p1 && i2 < G.p2) ? t1s[i1 + G.p1 * i2] : zero_val<T>();
+          }
+          fT1[mt][kb] = raw_frag<T>(v[0], v[1], v[2], v[3]);
+        }
     }
     AV S2acc[PT][PT];
 #pragma unroll
@@ -205,11 +244,11 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
 #pragma unroll
       for (int nt = 0; nt < PT; ++nt) S1[nt] = R::zero();
 
-      for (int u0 = 0; u0 < G.N1T; u0 += CH) {
+      for (int u0 = 0; u0 < N1Tp; u0 += CH) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           const int ut = u0 + c;
-          if (ut >= G.N1T) break;
+          const bool tile_ok = ut < G.N1T;   // padded tiles: zero factor rows, no n-array access
           AV E = R::zero();
           if (NEED_FWD) {
             // step 2: eta tile (16 x 16) = X1_tile (16 x p1) T2 (p1 x 16)
@@ -231,8 +270,9 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
             }
           } else if (MODE == SM_FWD_INT) {
             A* eta = (A*)P.eta_out;
+            if (tile_ok)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) eta[tbase + R::kidx(g, i)] = E[i];
+              for (int i = 0; i < 4; ++i) eta[tbase + R::kidx(g, i)] = E[i];
           } else if (MODE == SM_ADJ_STD) {
             const T* U = (const T*)P.u_in;
             T uv[4];
@@ -243,7 +283,7 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
             }
             fR = raw_frag<T>(uv[0], uv[1], uv[2], uv[3]);
           } else if (MODE == SM_FUSED) {
-            if (P.v_int) {
+            if (P.v_int && tile_ok) {
               const A* V = (const A*)P.v_int;
 #pragma unroll
               for (int i = 0; i < 4; ++i) E[i] *= V[tbase + R::kidx(g, i)];
@@ -256,6 +296,10 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
             for (int i = 0; i < 4; ++i) {
               const int i1 = ut * 16 + R::kidx(g, i);
               const bool valid = i1 < G.n1 && i2 < G.n2;
+              if (!tile_ok) {
+                U[i] = (A)0;
+                continue;
+              }
               const long long ti = tbase + R::kidx(g, i);
               const double eta = (double)E[i];
               const double y = P.y_int[ti];
@@ -322,8 +366,7 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
     }
 
     if (NEED_ADJ) {
-      // cross-wave sum of S2^T (waves 2,3 -> 0,1, then 1 -> 0), then wave 0 writes
-      // S2 (k-blocked, K = n3, C = P12) straight from its registers
+      // cross-wave sum of S2^T (waves 2,3 -> 0,1, then 1 -> 0)
       const int PP2 = PP * PP;
       if (w >= 2) {
 #pragma unroll
@@ -353,7 +396,8 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
       }
       __syncthreads();
       if (w == 0) {
-        T* S2 = (T*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<T>(i3 & 15);
+        // final sum, laid out [p2][p1] in the second half of the reduction area
+        A* fin = red + PP2;
 #pragma unroll
         for (int mt = 0; mt < PT; ++mt)
 #pragma unroll
@@ -362,12 +406,19 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
             for (int i = 0; i < 4; ++i) {
               const int b = mt * 16 + R::kidx(g, i);   // p2 index
               const int a = nt * 16 + r;               // p1 index
-              const A s = S2acc[mt][nt][i] + red[((mt * PT + nt) * 4 + i) * 64 + lane];
-              if (a < G.p1 && b < G.p2) S2[(long long)(a + G.p1 * b) * 16] = R::from_acc(s);
+              fin[b * PP + a] = S2acc[mt][nt][i] + red[((mt * PT + nt) * 4 + i) * 64 + lane];
             }
       }
       __syncthreads();
+      // S2 k-blocked (K = n3, C = P12): elem (i3, m) at ((i3/16) P12 + m) 16 + kpos(i3 % 16)
+      T* S2 = (T*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<T>(i3 & 15);
+      const A* fin = red + PP2;
+      for (int idx = tid; idx < G.P12; idx += WG) {
+        const int a = idx % G.p1, b = idx / G.p1;
+        S2[(long long)idx * 16] = R::from_acc(fin[b * PP + a]);
+      }
     }
+    __syncthreads();
   }
 
   if (MODE == SM_FAMILY || MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
@@ -409,19 +460,8 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
   const T* pa = S2 + (long long)m * 16 + 4 * g;
   const T* pb = X3 + (long long)k3 * 16 + 4 * g;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.p3 * 16;
-  int kb = w;
-  if (kb < G.KBN3) {
-    F fa = am ? load_frag(pa + kb * sa) : zero_frag<T>();
-    F fb = bk ? load_frag(pb + kb * sb) : zero_frag<T>();
-    for (kb += WG / 64; kb < G.KBN3; kb += WG / 64) {
-      const F na = am ? load_frag(pa + kb * sa) : zero_frag<T>();
-      const F nb = bk ? load_frag(pb + kb * sb) : zero_frag<T>();
-      mma(acc, fa, fb);
-      fa = na;
-      fb = nb;
-    }
-    mma(acc, fa, fb);
-  }
+  const int nkb = w < G.KBN3 ? (G.KBN3 - w + (WG / 64) - 1) / (WG / 64) : 0;
+  kblock_loop<T, KNB<T>::v>(acc, pa, pb, sa, sb, w, WG / 64, nkb, am, bk);
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[w][R::kidx(g, i) * 16 + r] = acc[i];
   __syncthreads();
@@ -429,8 +469,8 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
   // one thread per tile element: row (P12 index) = t % 16, column (p3 index) = t / 16
   const int t = threadIdx.x;
   const int row = bm * 16 + (t & 15), col = bn * 16 + (t >> 4);
-  const int q = (t & 15) * 16 + (t >> 4);
-  const double a = (double)(red[0][q] + red[1][q] + red[2][q] + red[3][q]);
+  const int qe = (t & 15) * 16 + (t >> 4);
+  const double a = (double)(red[0][qe] + red[1][qe] + red[2][qe] + red[3][qe]);
   double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0;
   if (row < G.P12 && col < G.p3) {
     const long long j = (long long)row + (long long)G.P12 * col;
@@ -450,18 +490,20 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
         red_pen = wm * fabs(th);
       }
     } else {  // EPI_PROX: one inner PG step (Sec. 3.2) with FISTA extrapolation
+      const double lam = P.dparams ? P.dparams[0] : P.lambda;
+      const double delta = P.dparams ? P.dparams[1] : P.delta;
       const double l_iter = (double)(*P.iter);
       const double om = (l_iter - 1.0) / (l_iter + 2.0);
       const double incg = P.scale * a;               // G(V H(x - theta_ref)) / n
       const double gx = P.gref[j] + incg;            // grad h(x^l)
       const double x = P.x[j], xp = P.xp[j], gp = P.gp[j];
       const double wm = P.pen_w ? P.pen_w[j] : 1.0;
-      const double lw = P.lambda * wm;
+      const double lw = lam * wm;
       red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
       red_noise = fabs(incg);
       const double gy = gx + om * (gx - gp);          // grad h(y) by linearity (h quadratic)
       const double yv = x + om * (x - xp);
-      const double xn = soft_threshold(yv - P.delta * gy, P.delta * lw);
+      const double xn = soft_threshold(yv - delta * gy, delta * lw);
       P.xp[j] = x;
       P.x[j] = xn;
       P.gp[j] = gx;
@@ -481,6 +523,61 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
       for (int s = 0; s < 4; ++s) P.partials[b * 4 + s] = v[s];
     }
   }
+}
+
+// LDS image of the mode-1 and mode-2 factors in the chain dtype: X1 with rows n1
+// (contraction p1) and rows p1 (contraction n1), X2 likewise; zero padded,
+// contraction positions permuted by kpos<T>.  src is FP64 or the chain dtype.
+template <typename S, typename T> struct Conv {
+  __device__ static inline T f(S v) { return Tr<T>::from_acc((typename Tr<T>::acc_t)v); }
+};
+template <typename T> struct Conv<T, T> {
+  __device__ static inline T f(T v) { return v; }
+};
+
+template <typename S, typename T>
+__global__ void k_pack_chain_image(Geom G, const S* __restrict__ X1, const S* __restrict__ X2, T* __restrict__ img) {
+  const ChainLayout L = chain_layout(G, (int)sizeof(T), (int)sizeof(typename Tr<T>::acc_t));
+  const int PP = G.PT * 16, N1 = G.N1T * 16, N2 = G.NJB * 16;
+  const int nimg = L.image_bytes / (int)sizeof(T);
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nimg; idx += gridDim.x * blockDim.x) img[idx] = zero_val<T>();
+  __syncthreads();
+  // (single workgroup launch: the zero fill above is visible after the barrier)
+  for (int idx = threadIdx.x; idx < N1 * PP; idx += blockDim.x) {
+    const int i = idx % N1, k = idx / N1;
+    if (i < G.n1 && k < G.p1) {
+      const T v = Conv<S, T>::f(X1[i + (long long)G.n1 * k]);
+      img[L.oX1a + i * L.sX1a + kpos<T>(k)] = v;
+      img[L.oX1b + k * L.sX1b + kpos<T>(i)] = v;
+    }
+  }
+  for (int idx = threadIdx.x; idx < N2 * PP; idx += blockDim.x) {
+    const int i = idx % N2, k = idx / N2;
+    if (i < G.n2 && k < G.p2) {
+      const T v = Conv<S, T>::f(X2[i + (long long)G.n2 * k]);
+      img[L.oX2a + i * L.sX2a + kpos<T>(k)] = v;
+      img[L.oX2b + k * L.sX2b + kpos<T>(i)] = v;
+    }
+  }
+}
+
+size_t chain_image_bytes(int dt, const Geom& G) {
+  return (size_t)chain_layout(G, (int)dt_size(dt), dt == DT_F64 ? 8 : 4).image_bytes;
+}
+
+hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void* X1, const void* X2, void* img,
+                                   hipStream_t s) {
+  dim3 grid(1), blk(WG);
+  if (src_dt == DT_F64) {
+    if (dt == DT_F64) hipLaunchKernelGGL((k_pack_chain_image<double, double>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (double*)img);
+    else if (dt == DT_F32) hipLaunchKernelGGL((k_pack_chain_image<double, float>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (float*)img);
+    else hipLaunchKernelGGL((k_pack_chain_image<double, bf16>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (bf16*)img);
+  } else {
+    if (src_dt != dt) return hipErrorInvalidValue;
+    if (dt == DT_F32) hipLaunchKernelGGL((k_pack_chain_image<float, float>), grid, blk, 0, s, G, (const float*)X1, (const float*)X2, (float*)img);
+    else hipLaunchKernelGGL((k_pack_chain_image<bf16, bf16>), grid, blk, 0, s, G, (const bf16*)X1, (const bf16*)X2, (bf16*)img);
+  }
+  return hipGetLastError();
 }
 
 // ============================================================================
@@ -520,7 +617,7 @@ int slab_chain_blocks(int dt, const Geom& G) {
 
 template <typename K>
 static void set_lds(K fn, size_t lds) {
-  if (lds > 65536) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename T, int PT>

@@ -43,7 +43,8 @@ class GlamOptions(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("nlambda", ctypes.c_int),
                 ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
                 ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int),
+                ("graph_mode", ctypes.c_int)]
 
 
 class GlamResult(ctypes.Structure):
@@ -271,7 +272,8 @@ class PathResult:
 
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
-             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0) -> PathResult:
+             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
+             graph=True) -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays."""
     torch = _torch()
@@ -303,6 +305,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.theta0 = theta0.data_ptr() if theta0 is not None else None
     opt.stream = _stream_ptr(stream)
     opt.profile_every = int(profile_every)
+    opt.graph_mode = 0 if graph else 1
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()
