@@ -113,7 +113,10 @@ typedef struct {
   int dtype;              /* glam_dtype of the inner rho chain (FP64 anchors always) */
   double kkt_tol;         /* target FP64 KKT residual (relative to lambda_max), e.g. 1e-6 */
   double nu;              /* step control (Sec. 6.4): 1 = delta = 1/Lhat, no backtracking;
-                             0 < nu < 1: delta = 1/(nu Lhat) with backtracking      */
+                             0 < nu < 1: delta = 1/(nu Lhat), halved (never below 1/Lhat)
+                             whenever the sufficient-decrease test of a step fails
+                             (host-checked every inner iteration, no graph replay);
+                             nu = 0 is not supported                                */
   int max_outer;          /* outer (Alg. 1) iterations per lambda, e.g. 100         */
   int max_inner;          /* inner PG iterations per outer iteration, e.g. 100000   */
   int check_every;        /* inner iterations between host convergence checks (>= 1) */

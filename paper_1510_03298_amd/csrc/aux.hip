@@ -234,6 +234,21 @@ __global__ void k_zero(uint32_t* p, long long nwords) {
     p[i] = 0u;
 }
 
+template <typename T>
+__global__ void k_bt_redo(Geom G, const double* __restrict__ y, const double* __restrict__ gy,
+                          const double* __restrict__ w, const double* __restrict__ th, double lambda, double delta,
+                          double* __restrict__ x, T* __restrict__ inc) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < G.p; j += (long long)gridDim.x * blockDim.x) {
+    const double lw = lambda * (w ? w[j] : 1.0);
+    const double z = y[j] - delta * gy[j];
+    const double a = fabs(z) - delta * lw;
+    const double xn = a > 0.0 ? copysign(a, z) : 0.0;
+    x[j] = xn;
+    const long long row = j % G.P12, col = j / G.P12;
+    inc[((col >> 4) * G.P12 + row) * 16 + kpos<T>((int)(col & 15))] = Tr<T>::from_acc((typename Tr<T>::acc_t)(xn - th[j]));
+  }
+}
+
 // ============================================================================
 // launchers
 // ============================================================================
@@ -310,6 +325,15 @@ hipError_t launch_axpy(long long p, double alpha, const double* d, double* theta
   hipLaunchKernelGGL(k_axpy, dim3(grid1d(p)), dim3(WG), 0, s, p, alpha, d, theta);
   return hipGetLastError();
 }
+hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
+                          const double* theta_ref, double lambda, double delta, double* x, void* inc, hipStream_t s) {
+  const int gr = grid1d(G.p);
+  if (dt == DT_F64) hipLaunchKernelGGL(k_bt_redo<double>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, x, (double*)inc);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_bt_redo<float>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, x, (float*)inc);
+  else hipLaunchKernelGGL(k_bt_redo<bf16>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, x, (bf16*)inc);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(grid1d(count)), dim3(WG), 0, s, p, count, v);
   return hipGetLastError();

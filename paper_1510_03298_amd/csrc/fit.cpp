@@ -93,11 +93,13 @@ struct Fit {
   void *T1c, *S2c;         // chain dtype intermediates
   double *T1d, *S2d;       // FP64 intermediates
   double *theta, *gref, *x, *xp, *gp, *dvec;
+  double *yb = nullptr, *gyb = nullptr;                     // backtracking: y_{l-1}, grad h(y_{l-1})
+  double *x2 = nullptr, *xp2 = nullptr, *gp2 = nullptr, *yb2 = nullptr, *gyb2 = nullptr;   // next state
   void* inc;
   int* iter;
   double* part;            // partial sums
   double* red;             // reduced values (device)
-  double* hred;            // reduced values (pinned host)
+  double* hred = nullptr;  // reduced values (pinned host)
   double sprod;            // prod_j rho(X_j^T X_j)
   std::string err;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
@@ -131,6 +133,7 @@ struct Fit {
       if (e) (void)hipEventDestroy(e);
     if (sync_ev) (void)hipEventDestroy(sync_ev);
     if (hparams) (void)hipHostFree(hparams);
+    if (hred) (void)hipHostFree(hred);
     if (own_stream && s) (void)hipStreamDestroy(s);
   }
 };
@@ -174,8 +177,8 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
   ap.partials = part2;
   int nb = 0;
   FCHK(launch_slab_adj(DT_F64, EPI_GRAD, ap, &nb, F.s));
-  const int ops4[4] = {1, 1, 0, 1};
-  FCHK(launch_reduce(part2, nb, 4, ops4, 1.0, F.red + 2, F.s));
+  const int ops4[4] = {1, 1, 0, 0};
+  FCHK(launch_reduce_strided(part2, nb, ADJ_NSUM, 4, ops4, 1.0, F.red + 2, F.s));
   FCHK(hipMemcpyAsync(F.hred, F.red, 6 * sizeof(double), hipMemcpyDeviceToHost, F.s));
   FCHK(hipStreamSynchronize(F.s));
   st->nll = F.hred[0];
@@ -232,8 +235,8 @@ static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
     int r = inner_iteration(F, 0.0, 0.0, nblk, sample_first && q == 0);
     if (r) return r;
   }
-  const int ops[4] = {1, 1, 0, 1};
-  FCHK(launch_reduce(F.part, *nblk, 4, ops, 1.0, F.red, F.s));
+  const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
+  FCHK(launch_reduce(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.s));
   return GLAM_OK;
 }
 
@@ -254,6 +257,72 @@ static int inner_block_graph(Fit& F, int m, int* nblk) {
     *nblk = slab_adj_blocks(F.G);
   }
   FCHK(hipGraphLaunch(F.gexec, F.s));
+  return GLAM_OK;
+}
+
+// Inner PG loop with step control nu < 1 (Sec. 6.4; reading R7): delta starts at
+// 1/(nu Lhat); each iteration also tests the Beck-Teboulle sufficient decrease of the
+// step that produced the current iterate and, if it fails, halves delta (never below
+// 1/Lhat) and redoes that step.  The host checks every iteration.
+static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double tol_in, int max_inner,
+                         double lam_scale, double* kin_out, int* it_out) {
+  const Geom& G = F.G;
+  double delta = delta0;
+  const double delta_min = 1.0 / Lhat;
+  // state at l = 1: x = xp = theta^k, gp = grad h(theta^k); y_0 := x^1 (no test at l = 1)
+  FCHK(hipMemcpyAsync(F.yb, F.theta, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+  FCHK(hipMemcpyAsync(F.gyb, F.gref, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+  double* cur[5] = {F.x, F.xp, F.gp, F.yb, F.gyb};
+  double* nxt[5] = {F.x2, F.xp2, F.gp2, F.yb2, F.gyb2};
+  int l = 1, it = 0, window_start = 0;
+  double kin = INFINITY, best = INFINITY, window_best = INFINITY;
+  while (it < max_inner) {
+    F.hparams[0] = lam;
+    F.hparams[1] = delta;
+    F.hparams[2] = (double)l;
+    FCHK(hipMemcpyAsync(F.dparams, F.hparams, 3 * sizeof(double), hipMemcpyHostToDevice, F.s));
+    FwdParams fw{};
+    fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c;
+    FCHK(launch_slab_fwd(F.dt, fw, F.s));
+    SlabParams sp{};
+    sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
+    FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
+    AdjParams ap{};
+    ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+    ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
+    ap.x = cur[0]; ap.xp = cur[1]; ap.gp = cur[2]; ap.yprev = cur[3]; ap.gyprev = cur[4];
+    ap.x_out = nxt[0]; ap.xp_out = nxt[1]; ap.gp_out = nxt[2]; ap.y_out = nxt[3]; ap.gy_out = nxt[4];
+    int nb = 0;
+    FCHK(launch_slab_adj(F.dt, EPI_PROX_BT, ap, &nb, F.s));
+    const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
+    FCHK(launch_reduce(F.part, nb, ADJ_NSUM, ops, 1.0, F.red, F.s));
+    FCHK(hipMemcpyAsync(F.hred, F.red, ADJ_NSUM * sizeof(double), hipMemcpyDeviceToHost, F.s));
+    FCHK(hipStreamSynchronize(F.s));
+    ++it;
+    const double sdg = F.hred[2], sdd = F.hred[3];
+    if (l >= 2 && sdg > (sdd / delta) * (1.0 + 1e-12) && delta > delta_min * (1.0 + 1e-12)) {
+      // divergence of the step into x^l detected: halve delta and redo that step from y_{l-1}
+      delta = std::max(0.5 * delta, delta_min);
+      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.prob->pen_w, F.theta, lam, delta, cur[0], F.inc, F.s));
+      continue;
+    }
+    kin = F.hred[0] / lam_scale;
+    for (int q = 0; q < 5; ++q) std::swap(cur[q], nxt[q]);
+    ++l;
+    if (!std::isfinite(kin)) break;
+    const double noise = 4.0 * kEps[F.dt] * F.hred[1] / lam_scale;
+    if (kin <= std::max(tol_in, noise)) break;
+    best = std::min(best, kin);
+    if (it - window_start >= 200) {
+      if (!(best < 0.5 * window_best) && F.dt != DT_F64) break;   // stalled at the rounding floor
+      window_best = best;
+      window_start = it;
+    }
+  }
+  // make the accepted x^l (now in cur[1]) available where the caller expects it (F.xp)
+  if (cur[1] != F.xp) FCHK(hipMemcpyAsync(F.xp, cur[1], G.p * 8, hipMemcpyDeviceToDevice, F.s));
+  *kin_out = kin;
+  *it_out = it;
   return GLAM_OK;
 }
 
@@ -298,65 +367,17 @@ static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* de
   return GLAM_OK;
 }
 
-}  // namespace glam
-
-using namespace glam;
-
-static int fit_fail(int code, const std::string& msg);
-
-extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res) {
-  auto t_start = std::chrono::steady_clock::now();
-  if (!prob || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
-  if (prob->d != 3) return fit_fail(GLAM_EINVAL, "only d = 3 is supported");
-  for (int j = 0; j < 3; ++j) {
-    if (prob->n[j] < 1 || prob->p[j] < 1) return fit_fail(GLAM_EINVAL, "mode sizes must be >= 1");
-    if (!prob->X[j]) return fit_fail(GLAM_EINVAL, "NULL factor");
-  }
-  if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
-  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) return fit_fail(GLAM_EINVAL, "bad family");
-  if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
-  if (opt->nlambda < 1) return fit_fail(GLAM_EINVAL, "nlambda must be >= 1");
-  if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
-    return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
-  if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
-  if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
-  if (opt->nu != 1.0) return fit_fail(GLAM_EINVAL, "nu < 1 (inner backtracking) is not implemented in this version");
-  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
-    return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
-  if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
-      !res->status)
-    return fit_fail(GLAM_EINVAL, "NULL result array");
-  if (opt->lambda) {
-    for (int l = 0; l < opt->nlambda; ++l) {
-      if (!(opt->lambda[l] >= 0.0) || !std::isfinite(opt->lambda[l]))
-        return fit_fail(GLAM_EINVAL, "lambda values must be finite and >= 0");
-      if (l > 0 && !(opt->lambda[l] < opt->lambda[l - 1]))
-        return fit_fail(GLAM_EINVAL, "lambda sequence must be strictly decreasing");
-    }
-  }
-  size_t ws_probe = glam_rho_workspace_size(3, prob->n, prob->p, opt->dtype);
-  if (ws_probe == 0) return fit_fail(GLAM_EINVAL, glam_last_error());
-  if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024)
-    return fit_fail(GLAM_EINVAL, "modes 1-2 too large for the FP64 slab kernel");
-
-  Fit F;
-  F.G = make_geom(prob->n, prob->p);
-  F.dt = opt->dtype;
-  F.us = (hipStream_t)opt->stream;
-  // work on an internal non-blocking stream (capturable), ordered after the caller's stream
-  if (hipStreamCreateWithFlags(&F.s, hipStreamNonBlocking) != hipSuccess)
-    return fit_fail(GLAM_EDEVICE, "hipStreamCreateWithFlags failed");
-  F.own_stream = true;
-  if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
-    return fit_fail(GLAM_EDEVICE, "stream ordering failed");
+// Allocate the per-problem device state and run the one-time setup kernels: input
+// checks, tiled Y and a, packed factors (FP64 and chain dtype), LDS images, and the
+// spectral radii of Proposition 1.  F.s, F.G and F.dt must be set.
+static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   F.family = prob->family;
   F.prob = prob;
   const Geom& G = F.G;
   const size_t es = dt_size(F.dt);
   const size_t accs = F.dt == DT_F64 ? 8 : 4;
   const size_t nadj = (size_t)slab_adj_blocks(G);
-  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * 4, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1)});
+  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * ADJ_NSUM, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1)});
 
   bool ok = true;
   auto A = [&](size_t b) { void* p = F.alloc(b); if (!p) ok = false; return p; };
@@ -386,19 +407,119 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   F.xp = (double*)A(G.p * 8);
   F.gp = (double*)A(G.p * 8);
   F.dvec = (double*)A(G.p * 8);
+  if (bt) {
+    F.yb = (double*)A(G.p * 8); F.gyb = (double*)A(G.p * 8);
+    F.x2 = (double*)A(G.p * 8); F.xp2 = (double*)A(G.p * 8); F.gp2 = (double*)A(G.p * 8);
+    F.yb2 = (double*)A(G.p * 8); F.gyb2 = (double*)A(G.p * 8);
+  }
   F.inc = A(G.inc_len * es);
   F.iter = (int*)A(sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
-  F.dparams = (double*)A(2 * 8);
-  if (!ok) return fit_fail(GLAM_ENOMEM, "device allocation failed");
-  if (opt->profile_every > 0)
+  F.dparams = (double*)A(4 * 8);
+  if (!ok) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
+  if (events)
     for (auto& e : F.ev)
-      if (hipEventCreate(&e) != hipSuccess) return fit_fail(GLAM_EDEVICE, "hipEventCreate failed");
+      if (hipEventCreate(&e) != hipSuccess) { F.err = "hipEventCreate failed"; return GLAM_EDEVICE; }
   if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&F.hparams, 2 * sizeof(double)) != hipSuccess)
-    return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
-  struct HostFree { double* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{F.hred};
+      hipHostMalloc((void**)&F.hparams, 4 * sizeof(double)) != hipSuccess) {
+    F.err = "pinned host allocation failed";
+    return GLAM_ENOMEM;
+  }
+
+  // ---- input checks (device) ----
+  {
+    int nb = 0;
+    FCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family == GLAM_POISSON, F.part, &nb, F.s));
+    const int ops[4] = {1, 1, 1, 1};
+    FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
+    FCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+    FCHK(hipStreamSynchronize(F.s));
+    if (F.hred[0] != 0.0) { F.err = "Y has non-finite entries"; return GLAM_EINVAL; }
+    if (F.hred[1] != 0.0) { F.err = "Poisson Y must be >= 0"; return GLAM_EINVAL; }
+    if (F.hred[2] != 0.0) { F.err = "obs_w must be finite and >= 0"; return GLAM_EINVAL; }
+    if (F.hred[3] != 0.0) { F.err = "pen_w must be finite and > 0"; return GLAM_EINVAL; }
+  }
+  // ---- setup: tiled data, chain copies of the factors, spectral radii ----
+  FCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
+  FCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
+  FCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s));
+  if (F.dt != DT_F64) FCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s));
+  // packed mode-3 factor (FP64 and chain dtype); zero the padded intermediates once
+  FCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fd, F.s));
+  FCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ad, F.s));
+  FCHK(launch_zero(F.S2d, G.s2_len * 8, F.s));   // rows beyond n3 stay zero
+  if (F.dt != DT_F64) {
+    FCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fc, F.s));
+    FCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ac, F.s));
+    FCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
+  }
+  F.sprod = 1.0;
+  for (int j = 0; j < 3; ++j) {
+    std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
+    FCHK(hipMemcpyAsync(hx.data(), prob->X[j], hx.size() * 8, hipMemcpyDeviceToHost, F.s));
+    FCHK(hipStreamSynchronize(F.s));
+    F.sprod *= gram_spectral_radius(hx, (int)prob->n[j], (int)prob->p[j]);
+  }
+  return GLAM_OK;
+}
+
+}  // namespace glam
+
+using namespace glam;
+
+static int fit_fail(int code, const std::string& msg);
+
+extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!prob || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
+  if (prob->d != 3) return fit_fail(GLAM_EINVAL, "only d = 3 is supported");
+  for (int j = 0; j < 3; ++j) {
+    if (prob->n[j] < 1 || prob->p[j] < 1) return fit_fail(GLAM_EINVAL, "mode sizes must be >= 1");
+    if (!prob->X[j]) return fit_fail(GLAM_EINVAL, "NULL factor");
+  }
+  if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
+  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) return fit_fail(GLAM_EINVAL, "bad family");
+  if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
+  if (opt->nlambda < 1) return fit_fail(GLAM_EINVAL, "nlambda must be >= 1");
+  if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
+    return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
+  if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
+  if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
+  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
+    return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
+  if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
+      !res->status)
+    return fit_fail(GLAM_EINVAL, "NULL result array");
+  if (opt->lambda) {
+    for (int l = 0; l < opt->nlambda; ++l) {
+      if (!(opt->lambda[l] >= 0.0) || !std::isfinite(opt->lambda[l]))
+        return fit_fail(GLAM_EINVAL, "lambda values must be finite and >= 0");
+      if (l > 0 && !(opt->lambda[l] < opt->lambda[l - 1]))
+        return fit_fail(GLAM_EINVAL, "lambda sequence must be strictly decreasing");
+    }
+  }
+  size_t ws_probe = glam_rho_workspace_size(3, prob->n, prob->p, opt->dtype);
+  if (ws_probe == 0) return fit_fail(GLAM_EINVAL, glam_last_error());
+  if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024)
+    return fit_fail(GLAM_EINVAL, "modes 1-2 too large for the FP64 slab kernel");
+
+  Fit F;
+  F.G = make_geom(prob->n, prob->p);
+  F.dt = opt->dtype;
+  F.us = (hipStream_t)opt->stream;
+  // work on an internal non-blocking stream (capturable), ordered after the caller's stream
+  if (hipStreamCreateWithFlags(&F.s, hipStreamNonBlocking) != hipSuccess)
+    return fit_fail(GLAM_EDEVICE, "hipStreamCreateWithFlags failed");
+  F.own_stream = true;
+  if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
+    return fit_fail(GLAM_EDEVICE, "stream ordering failed");
+  {
+    const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
+    if (r) return fit_fail(r, F.err);
+  }
+  const Geom& G = F.G;
 
 #define PCHK(expr)                                                                               \
   do {                                                                                           \
@@ -411,40 +532,6 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
     if (r_ != GLAM_OK) return fit_fail(r_, F.err); \
   } while (0)
 
-  // ---- input checks (device) ----
-  {
-    int nb = 0;
-    PCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family == GLAM_POISSON, F.part, &nb, F.s));
-    const int ops[4] = {1, 1, 1, 1};
-    PCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
-    PCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
-    PCHK(hipStreamSynchronize(F.s));
-    if (F.hred[0] != 0.0) return fit_fail(GLAM_EINVAL, "Y has non-finite entries");
-    if (F.hred[1] != 0.0) return fit_fail(GLAM_EINVAL, "Poisson Y must be >= 0");
-    if (F.hred[2] != 0.0) return fit_fail(GLAM_EINVAL, "obs_w must be finite and >= 0");
-    if (F.hred[3] != 0.0) return fit_fail(GLAM_EINVAL, "pen_w must be finite and > 0");
-  }
-  // ---- setup: tiled data, chain copies of the factors, spectral radii ----
-  PCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
-  PCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
-  PCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s));
-  if (F.dt != DT_F64) PCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s));
-  // packed mode-3 factor (FP64 and chain dtype); zero the padded intermediates once
-  PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fd, F.s));
-  PCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ad, F.s));
-  PCHK(launch_zero(F.S2d, G.s2_len * 8, F.s));   // rows beyond n3 stay zero
-  if (F.dt != DT_F64) {
-    PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fc, F.s));
-    PCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ac, F.s));
-    PCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
-  }
-  F.sprod = 1.0;
-  for (int j = 0; j < 3; ++j) {
-    std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
-    PCHK(hipMemcpyAsync(hx.data(), prob->X[j], hx.size() * 8, hipMemcpyDeviceToHost, F.s));
-    PCHK(hipStreamSynchronize(F.s));
-    F.sprod *= gram_spectral_radius(hx, (int)prob->n[j], (int)prob->p[j]);
-  }
   // ---- lambda_max: the zero solution's gradient (Sec. 6.4) ----
   PCHK(launch_fill(F.theta, G.p, 0.0, F.s));
   StepStats st0;
@@ -501,11 +588,14 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
       if (F.dt == DT_BF16) tol_in = std::max(tol_in, 0.1 * kkt);
       // ---- inner PG loop ----
       PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      int it = 0;
+      double kin = INFINITY, noise = 0.0;
+      if (opt->nu < 1.0) {
+        RCHK(inner_loop_bt(F, lam, delta, Lhat, tol_in, opt->max_inner, lam_scale, &kin, &it));
+      } else {
       F.hparams[0] = lam;
       F.hparams[1] = delta;
       PCHK(hipMemcpyAsync(F.dparams, F.hparams, 2 * sizeof(double), hipMemcpyHostToDevice, F.s));
-      int it = 0;
-      double kin = INFINITY, noise = 0.0;
       double best = INFINITY, window_best = INFINITY;
       int window_start = 0;
       while (it < opt->max_inner) {
@@ -533,6 +623,7 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
           fprintf(stderr, "[glam]   lambda %d k %d it %d kin %.3e noise %.3e\n", l, k, it, kin, noise);
         if (!std::isfinite(kin)) break;
         if (kin <= std::max(tol_in, noise)) break;
+      }
       }
       inner_total += it;
       if (!std::isfinite(kin)) { status = GLAM_ENONFINITE; break; }

@@ -75,7 +75,8 @@ struct SlabParams {
   double* partials;   // per-workgroup partial sums [grid][2]
 };
 
-enum AdjEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_PROX = 2 };
+enum AdjEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_PROX = 2, EPI_PROX_BT = 3 };
+constexpr int ADJ_NSUM = 6;   // partial values per slab_adj workgroup
 
 struct AdjParams {
   Geom G;
@@ -89,7 +90,7 @@ struct AdjParams {
   const double* theta;   // FP64 p-array (KKT at theta) or NULL
   const double* pen_w;   // FP64 p-array or NULL
   double lambda;
-  double* partials;      // per-workgroup [nblk][4]
+  double* partials;      // per-workgroup [nblk][ADJ_NSUM]
   // EPI_PROX (inner PG iteration, FP64 state)
   const double* gref;    // gradient at the anchor
   const double* theta_ref;
@@ -99,8 +100,13 @@ struct AdjParams {
   void* inc;             // chain type, k-blocked (K = p3, C = P12): x^{l+1} - theta_ref
   const int* iter;       // device iteration counter l
   double delta;          // step size
-  const double* dparams; // optional device {lambda, delta} (overrides the two scalars; lets a
+  const double* dparams; // optional device {lambda, delta[, l]} (overrides the scalars; lets a
                          // captured graph be replayed across lambdas and outer iterations)
+  // EPI_PROX_BT (backtracking): previous extrapolation point and its gradient, and the
+  // double-buffered next state (x^{l+1}, x^l, grad h(x^l), y_l, grad h(y_l))
+  const double* yprev;
+  const double* gyprev;
+  double *x_out, *xp_out, *gp_out, *y_out, *gy_out;
 };
 
 struct FwdParams {
@@ -110,6 +116,30 @@ struct FwdParams {
   void* T1;           // chain type, slab-major [n3][P12]
   int* iter;          // optional: incremented once by the first thread
 };
+
+// batched proximal step (many independent problems per launch)
+struct BatchDesc {
+  FwdParams fw;       // theta = increment (k-blocked), X3f, T1
+  SlabParams sp;      // img, T1, S2, v_int
+  AdjParams ap;       // EPI_PROX fields; iter -> the batch step counter
+  int fwd_gx;         // slab_fwd workgroup grid x
+  int adj_gx;         // slab_adj workgroup grid x
+};
+struct BatchParams {
+  const BatchDesc* desc;
+  int nprob;
+  const int* off_fwd;   // prefix sums of slab_fwd tiles per problem (nprob + 1)
+  const int* off_slab;  // prefix sums of n3
+  const int* off_adj;   // prefix sums of slab_adj tiles (also the partials index)
+  const int* active;    // problem mask
+  int* step;            // inner step counter (read by the prox epilogue)
+  unsigned* bar;        // grid barrier state {count, generation}
+  int* err;             // barrier timeout flag
+};
+size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
+int batched_grid(int dt, size_t lds);
+hipError_t launch_batched_step(int dt, const BatchParams& B, int grid, size_t lds, hipStream_t s);
+hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s);
 
 // rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
@@ -148,6 +178,9 @@ hipError_t launch_armijo(const Geom& G, int family, const double* eta_int, const
                          const double* y_int, const double* a_int, int j0, double* partials, int* nblk_out,
                          hipStream_t s);
 hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);
+// backtracking redo of a rejected step: x = S(y - delta gy, delta lambda w), inc = x - theta_ref (k-blocked)
+hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
+                          const double* theta_ref, double lambda, double delta, double* x, void* inc, hipStream_t s);
 // sum_m w_m (|theta_m + t_j d_m| - |theta_m|) for t = 1 (slot 0) and the Armijo trial steps (slots 1..)
 hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, int j0,
                              double* partials, int* nblk_out, hipStream_t s);

@@ -11,6 +11,8 @@
 // Kronecker identity of App. A), so H and G are taken mode 3 first / mode 3
 // last: the same linear maps as the cyclic rho order, with the least work when
 // mode 3 is the largest mode.
+#include <algorithm>
+
 #include "launch.h"
 #include "mfma.h"
 
@@ -94,18 +96,17 @@ template <> struct KNB<bf16> { static constexpr int v = 8; };
 // slab_fwd: T1 (P12 x n3) = Theta_kb^T (P12 x p3) X3f (p3 x n3), both k-blocked.
 // One wave per 16 x 16 output tile, 2 x 2 tiles per workgroup.
 // ============================================================================
+// one workgroup tile (bx, by) of slab_fwd
 template <typename T>
-__global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
+__device__ inline void fwd_tile(const FwdParams& P, int bx, int by) {
   typedef Tr<T> R;
-  typedef typename R::frag_t F;
   const Geom& G = P.G;
   const T* __restrict__ A = (const T*)P.theta;
   const T* __restrict__ B = (const T*)P.X3f;
   T* __restrict__ T1 = (T*)P.T1;
-  if (P.iter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *P.iter += 1;
   const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int mt = blockIdx.x * 2 + (w & 1);
-  const int nt = blockIdx.y * 2 + (w >> 1);
+  const int mt = bx * 2 + (w & 1);
+  const int nt = by * 2 + (w >> 1);
   const int m = mt * 16 + r;     // A column (P12 index)
   const int i3 = nt * 16 + r;    // B column (n3 index)
   const bool am = m < G.P12, bn = i3 < G.n3;
@@ -121,6 +122,12 @@ __global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
     const int row = mt * 16 + R::kidx(g, i);
     if (row < G.P12) T1[(long long)i3 * G.P12 + row] = R::from_acc(acc[i]);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
+  if (P.iter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *P.iter += 1;
+  fwd_tile<T>(P, blockIdx.x, blockIdx.y);
 }
 
 // ============================================================================
@@ -161,44 +168,38 @@ __host__ __device__ inline ChainLayout chain_layout(const Geom& G, int esize, in
   return L;
 }
 
+// staging of the pre-packed factor image into LDS (a straight 16-byte copy)
+__device__ inline void chain_stage(const void* img, int image_bytes, unsigned char* smem_raw) {
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  const u4v* src = (const u4v*)img;
+  u4v* dst = (u4v*)smem_raw;
+  const int nvec = image_bytes / 16;
+  int idx = threadIdx.x;
+  for (; idx + 3 * WG < nvec; idx += 4 * WG) {
+    const u4v a0 = src[idx], a1 = src[idx + WG], a2 = src[idx + 2 * WG], a3 = src[idx + 3 * WG];
+    dst[idx] = a0; dst[idx + WG] = a1; dst[idx + 2 * WG] = a2; dst[idx + 3 * WG] = a3;
+  }
+  for (; idx < nvec; idx += WG) dst[idx] = src[idx];
+  __syncthreads();
+}
+
+// modes 1 and 2 of one slab i3 (the factor image is already in LDS)
 template <typename T, int PT, int MODE>
-__global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
+__device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, unsigned char* smem_raw, int i3,
+                                  double& s_nll, double& s_vmax) {
   typedef Tr<T> R;
   typedef typename R::acc_t A;
   typedef typename R::accv_t AV;
   typedef typename R::frag_t F;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = (T*)smem_raw;
-  __shared__ double sred[4 * 4];
+  const T* sm = (const T*)smem_raw;
   const Geom& G = P.G;
-  const ChainLayout L = chain_layout(G, (int)sizeof(T), (int)sizeof(A));
   A* red = (A*)(smem_raw + L.red_off);
   const int tid = threadIdx.x, lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
   const int PP = PT * 16;
   T* t1s = (T*)(smem_raw + L.t1_off);
   constexpr bool NEED_FWD = MODE != SM_ADJ_STD;
   constexpr bool NEED_ADJ = MODE == SM_ADJ_STD || MODE == SM_FUSED || MODE == SM_FAMILY || MODE == SM_NLL_BWD;
-
-  // ---- stage the mode-1 and mode-2 factors once: a straight 16-byte copy of the
-  // pre-packed LDS image (see pack_chain_image) ----
-  {
-    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-    const u4v* src = (const u4v*)P.img;
-    u4v* dst = (u4v*)smem_raw;
-    const int nvec = L.image_bytes / 16;
-    int idx = tid;
-    for (; idx + 3 * WG < nvec; idx += 4 * WG) {
-      const u4v a0 = src[idx], a1 = src[idx + WG], a2 = src[idx + 2 * WG], a3 = src[idx + 3 * WG];
-      dst[idx] = a0; dst[idx + WG] = a1; dst[idx + 2 * WG] = a2; dst[idx + 3 * WG] = a3;
-    }
-    for (; idx < nvec; idx += WG) dst[idx] = src[idx];
-  }
-  __syncthreads();
-
-  double s_nll = 0.0, s_vmax = 0.0;
-
   const int N1Tp = n1_tiles_padded(G);
-  for (int i3 = blockIdx.x; i3 < G.n3; i3 += gridDim.x) {
     F fT1[PT][PT];
     if (NEED_FWD) {
       // the slab's p1 x p2 block of T1 (contiguous), then fragments: row p1, contraction p2
@@ -419,13 +420,22 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
       }
     }
     __syncthreads();
-  }
+}
 
+template <typename T, int PT, int MODE>
+__global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
+  typedef typename Tr<T>::acc_t A;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sred[4 * 4];
+  const ChainLayout L = chain_layout(P.G, (int)sizeof(T), (int)sizeof(A));
+  chain_stage(P.img, L.image_bytes, smem_raw);
+  double s_nll = 0.0, s_vmax = 0.0;
+  for (int i3 = blockIdx.x; i3 < P.G.n3; i3 += gridDim.x) chain_slab<T, PT, MODE>(P, L, smem_raw, i3, s_nll, s_vmax);
   if (MODE == SM_FAMILY || MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
     double v[2] = {s_nll, s_vmax};
     const int ops[2] = {0, 1};
     block_reduce<2>(v, ops, sred);
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
       P.partials[(long long)blockIdx.x * 2 + 0] = v[0];
       P.partials[(long long)blockIdx.x * 2 + 1] = v[1];
     }
@@ -441,18 +451,17 @@ __device__ inline double soft_threshold(double z, double t) {
   return a > 0.0 ? copysign(a, z) : 0.0;
 }
 
+// one output tile (bm, bn) of slab_adj; its partial maxima / sums go to partials[pidx]
 template <typename T, int EPI>
-__global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
+__device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pidx) {
   typedef Tr<T> R;
   typedef typename R::acc_t A;
-  typedef typename R::frag_t F;
-  __shared__ double sred[4 * 4];
+  __shared__ double sred[4 * ADJ_NSUM];
   __shared__ A red[WG / 64][256];
   const Geom& G = P.G;
   const T* __restrict__ S2 = (const T*)P.S2;
   const T* __restrict__ X3 = (const T*)P.X3a;
   const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int bm = blockIdx.x, bn = blockIdx.y;
   const int m = bm * 16 + r;    // A column (P12 index)
   const int k3 = bn * 16 + r;   // B column (p3 index)
   const bool am = m < G.P12, bk = k3 < G.p3;
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
   const int row = bm * 16 + (t & 15), col = bn * 16 + (t >> 4);
   const int qe = (t & 15) * 16 + (t >> 4);
   const double a = (double)(red[0][qe] + red[1][qe] + red[2][qe] + red[3][qe]);
-  double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0;
+  double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0, red_dg = 0.0, red_dd = 0.0;
   if (row < G.P12 && col < G.p3) {
     const long long j = (long long)row + (long long)G.P12 * col;
     if (EPI == EPI_STORE) {
@@ -489,10 +498,38 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
         red_kkt = th != 0.0 ? fabs(gv + copysign(lw, th)) : fmax(fabs(gv) - lw, 0.0);
         red_pen = wm * fabs(th);
       }
+    } else if (EPI == EPI_PROX_BT) {
+      // inner PG step with Beck-Teboulle backtracking state (step size control nu < 1):
+      // also the sums of the sufficient-decrease test of the step that produced x^l,
+      // which for the quadratic h reads <d, grad h(x^l) - grad h(y)> <= |d|^2 / delta
+      const double lam = P.dparams[0], delta = P.dparams[1], l_iter = P.dparams[2];
+      const double om = (l_iter - 1.0) / (l_iter + 2.0);
+      const double incg = P.scale * a;
+      const double gx = P.gref[j] + incg;
+      const double x = P.x[j], xp = P.xp[j], gp = P.gp[j];
+      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      const double lw = lam * wm;
+      red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
+      red_noise = fabs(incg);
+      const double dv = x - P.yprev[j];
+      red_dg = dv * (gx - P.gyprev[j]);
+      red_dd = dv * dv;
+      const double gy = gx + om * (gx - gp);
+      const double yv = x + om * (x - xp);
+      const double xn = soft_threshold(yv - delta * gy, delta * lw);
+      P.x_out[j] = xn;
+      P.xp_out[j] = x;
+      P.gp_out[j] = gx;
+      P.y_out[j] = yv;
+      P.gy_out[j] = gy;
+      const double dinc = xn - P.theta_ref[j];
+      red_inc = fabs(dinc);
+      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
+          R::from_acc((typename R::acc_t)dinc);
     } else {  // EPI_PROX: one inner PG step (Sec. 3.2) with FISTA extrapolation
       const double lam = P.dparams ? P.dparams[0] : P.lambda;
       const double delta = P.dparams ? P.dparams[1] : P.delta;
-      const double l_iter = (double)(*P.iter);
+      const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const double om = (l_iter - 1.0) / (l_iter + 2.0);
       const double incg = P.scale * a;               // G(V H(x - theta_ref)) / n
       const double gx = P.gref[j] + incg;            // grad h(x^l)
@@ -513,15 +550,137 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
           R::from_acc((typename R::acc_t)dinc);
     }
   }
-  if (EPI == EPI_GRAD || EPI == EPI_PROX) {
-    double v[4] = {red_kkt, EPI == EPI_GRAD ? red_lmax : red_noise, EPI == EPI_GRAD ? red_pen : 0.0, red_inc};
-    const int ops[4] = {1, 1, 0, 1};
-    block_reduce<4>(v, ops, sred);
+  if (EPI != EPI_STORE) {
+    // per-workgroup partials [nblk][ADJ_NSUM]: max KKT residual, max |g|/w (GRAD) or max
+    // |increment gradient| (PROX), sum w|theta| (GRAD) or sum d.gd (PROX_BT), sum d.d
+    // (PROX_BT), max |x - theta_ref| (PROX), unused
+    double v[ADJ_NSUM] = {red_kkt, EPI == EPI_GRAD ? red_lmax : red_noise, EPI == EPI_GRAD ? red_pen : red_dg,
+                          red_dd, red_inc, 0.0};
+    const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
+    block_reduce<ADJ_NSUM>(v, ops, sred);
     if (threadIdx.x == 0) {
-      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) P.partials[b * 4 + s] = v[s];
+      for (int s = 0; s < ADJ_NSUM; ++s) P.partials[pidx * ADJ_NSUM + s] = v[s];
     }
+  }
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
+  adj_tile<T, EPI>(P, blockIdx.x, blockIdx.y, (long long)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// ============================================================================
+// batched proximal step: many independent GLAMs in one persistent launch
+// ============================================================================
+// Grid-wide barrier of a co-resident grid.  The wait is bounded: on timeout the
+// flag *err is raised and the wave proceeds, so every wave of the launch exits.
+__device__ inline void grid_barrier(unsigned* bar, int* err, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1 << 22)) {
+          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+__device__ inline int find_segment(const int* off, int nseg, int item) {
+  int lo = 0, hi = nseg;   // off[lo] <= item < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_batched_step(BatchParams B) {
+  typedef typename Tr<T>::acc_t A;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const unsigned nblocks = gridDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_fetch_add(B.step, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // phase A: mode-3 forward GEMM tiles of every active problem
+  const int totA = B.off_fwd[B.nprob];
+  for (int item = blockIdx.x; item < totA; item += gridDim.x) {
+    const int pb = find_segment(B.off_fwd, B.nprob, item);
+    if (!B.active[pb]) continue;
+    const BatchDesc& D = B.desc[pb];
+    const int loc = item - B.off_fwd[pb];
+    fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
+  }
+  grid_barrier(B.bar, B.err, nblocks);
+  // phase B: the slabs (modes 1-2 forward, adjoint) of every active problem
+  const int totB = B.off_slab[B.nprob];
+  int cur = -1;
+  ChainLayout L;
+  double s_nll = 0.0, s_vmax = 0.0;
+  for (int item = blockIdx.x; item < totB; item += gridDim.x) {
+    const int pb = find_segment(B.off_slab, B.nprob, item);
+    if (!B.active[pb]) continue;
+    const BatchDesc& D = B.desc[pb];
+    if (pb != cur) {
+      __syncthreads();
+      L = chain_layout(D.sp.G, (int)sizeof(T), (int)sizeof(A));
+      chain_stage(D.sp.img, L.image_bytes, smem_raw);
+      cur = pb;
+    }
+    const int i3 = item - B.off_slab[pb];
+    if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+    else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+  }
+  grid_barrier(B.bar, B.err, nblocks);
+  // phase C: mode-3 adjoint tiles + proximal step of every active problem
+  const int totC = B.off_adj[B.nprob];
+  for (int item = blockIdx.x; item < totC; item += gridDim.x) {
+    const int pb = find_segment(B.off_adj, B.nprob, item);
+    if (!B.active[pb]) continue;
+    const BatchDesc& D = B.desc[pb];
+    const int loc = item - B.off_adj[pb];
+    adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, item);
+  }
+}
+
+// per-problem maxima of the adjoint partials (slot 0: KKT, slot 1: noise): out[pb][2]
+__global__ void k_segment_max(const double* __restrict__ part, const int* __restrict__ off, int nprob,
+                              double* __restrict__ out) {
+  __shared__ double sm[2][WG];
+  for (int pb = blockIdx.x; pb < nprob; pb += gridDim.x) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = off[pb] + threadIdx.x; b < off[pb + 1]; b += WG) {
+      a0 = fmax(a0, part[(long long)b * ADJ_NSUM + 0]);
+      a1 = fmax(a1, part[(long long)b * ADJ_NSUM + 1]);
+    }
+    sm[0][threadIdx.x] = a0;
+    sm[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int st = WG / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) {
+        sm[0][threadIdx.x] = fmax(sm[0][threadIdx.x], sm[0][threadIdx.x + st]);
+        sm[1][threadIdx.x] = fmax(sm[1][threadIdx.x], sm[1][threadIdx.x + st]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[2 * pb] = sm[0][0];
+      out[2 * pb + 1] = sm[1][0];
+    }
+    __syncthreads();
   }
 }
 
@@ -676,12 +835,52 @@ hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, h
   do {                                                                                           \
     if (epi == EPI_STORE) hipLaunchKernelGGL((k_slab_adj<T, EPI_STORE>), grid, dim3(WG), 0, s, P); \
     else if (epi == EPI_GRAD) hipLaunchKernelGGL((k_slab_adj<T, EPI_GRAD>), grid, dim3(WG), 0, s, P); \
-    else hipLaunchKernelGGL((k_slab_adj<T, EPI_PROX>), grid, dim3(WG), 0, s, P);                 \
+    else if (epi == EPI_PROX) hipLaunchKernelGGL((k_slab_adj<T, EPI_PROX>), grid, dim3(WG), 0, s, P); \
+    else hipLaunchKernelGGL((k_slab_adj<T, EPI_PROX_BT>), grid, dim3(WG), 0, s, P);              \
   } while (0)
   if (dt == DT_F64) GLAM_ADJ(double);
   else if (dt == DT_F32) GLAM_ADJ(float);
   else GLAM_ADJ(bf16);
 #undef GLAM_ADJ
+  return hipGetLastError();
+}
+
+
+size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob) {
+  size_t m = 0;
+  for (int i = 0; i < nprob; ++i) m = std::max(m, slab_chain_lds_bytes(dt, Gs[i]));
+  return m;
+}
+
+int batched_grid(int dt, size_t lds) {
+  int per_cu = 0;
+  hipError_t e;
+  if (dt == DT_F64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<double>, WG, lds);
+  else if (dt == DT_F32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<float>, WG, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<bf16>, WG, lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  if (per_cu > 2) per_cu = 2;
+  return num_cus() * per_cu;
+}
+
+hipError_t launch_batched_step(int dt, const BatchParams& B, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {(void*)&B};
+  if (dt == DT_F64) {
+    set_lds(k_batched_step<double>, lds);
+    return hipLaunchCooperativeKernel((const void*)k_batched_step<double>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
+  }
+  if (dt == DT_F32) {
+    set_lds(k_batched_step<float>, lds);
+    return hipLaunchCooperativeKernel((const void*)k_batched_step<float>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
+  }
+  set_lds(k_batched_step<bf16>, lds);
+  return hipLaunchCooperativeKernel((const void*)k_batched_step<bf16>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
+}
+
+hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s) {
+  int g = nprob < 1024 ? nprob : 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_segment_max, dim3(g), dim3(WG), 0, s, partials, off, nprob, out);
   return hipGetLastError();
 }
 

@@ -151,3 +151,23 @@ def test_graph_replay_matches_stream_launches(dt):
     assert r1.code == r2.code == 0
     assert np.array_equal(r1.iters_inner, r2.iters_inner)
     assert torch.equal(r1.theta, r2.theta)
+
+
+@pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 1), ("poisson", 0), ("poisson", 1)])
+def test_nu_backtracking(fam, dt):
+    """Step control nu = 0.5 (delta = 2/Lhat with Beck-Teboulle backtracking) reaches the
+    same PMLE as the oracle (unique minimiser)."""
+    torch, glam = need_gpu()
+    if fam == "gaussian":
+        d = inputs.random_problem((21, 17, 29), (8, 7, 9), seed=26)
+    else:
+        d = inputs.config_c3(n=(20, 18, 30), p=(7, 6, 9), nlambda=3)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    lam = 0.05 * lm
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lm, lam], dtype=dt, kkt_tol=1e-7, nu=0.5,
+                        raise_on_error=False)
+    assert res.code == 0, (res.code, res.status)
+    th = _theta(glam, res, 1, d.p)
+    ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200)
+    _check_model(d, fam, th, lam, lm, 1e-7, ref=ref, theta_tol=1e-4)
