@@ -155,6 +155,42 @@ typedef struct {
 int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res);
 
 /* ---------------------------------------------------------------------------
+ * Many independent GLAMs at once (one lambda each): every inner proximal step of
+ * all unconverged problems is one persistent (cooperative) launch; the FP64
+ * outer steps of Algorithm 1 run per problem.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const double* lambda;   /* HOST array of nprob lambdas, or NULL: lambda_ratio * lambda_max_i */
+  double lambda_ratio;    /* used when lambda == NULL (0 < ratio <= 1)                   */
+  int dtype;              /* glam_dtype of the inner rho chain                           */
+  double kkt_tol;         /* FP64 KKT target (relative to each lambda_max_i)             */
+  int max_outer;          /* outer iterations per problem                                */
+  int max_inner;          /* batched proximal steps per outer round                      */
+  int check_every;        /* steps between host convergence checks                       */
+  void* stream;           /* hipStream_t (NULL = default stream)                         */
+} glam_batch_options;
+
+typedef struct {
+  double* const* theta;   /* HOST array of nprob DEVICE pointers; theta[i] -> p_i FP64 (caller-allocated) */
+  double* lambda_out;     /* host, nprob                                                 */
+  double* lambda_max;     /* host, nprob                                                 */
+  double* kkt;            /* host, nprob: FP64 KKT residual / lambda_max_i               */
+  double* objective;      /* host, nprob                                                 */
+  int* iters_outer;       /* host, nprob                                                 */
+  int* status;            /* host, nprob: glam_status per problem                        */
+  long long steps;        /* out: batched proximal-step launches                         */
+  long long problem_steps;/* out: proximal steps summed over problems                    */
+  double seconds;         /* out: wall time of the call                                  */
+} glam_batch_result;
+
+/* Fit nprob independent problems (each as in glam_fit_path with nlambda = 1; nu = 1).
+ * Problems may differ in sizes and family.  Returns GLAM_ENOCONV if any problem did
+ * not converge (its status says which).  Errors: GLAM_EINVAL as glam_fit_path, plus
+ * nprob < 1. */
+int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_options* opt,
+                     glam_batch_result* res);
+
+/* ---------------------------------------------------------------------------
  * Poisson negative log-likelihood in beta (eqs. two, three and four with
  * a = 1, log y! dropped): L(beta) = (1/n) sum_i (exp(eta_i) - y_i eta_i),
  * eta = H(<X_j>, beta); grad L = G(<X_j>, exp(eta) - y) / n.

@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "glam.h"
@@ -662,6 +663,251 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   res->chain_samples = F.samples;
   res->inner_total = path_inner;
   if (path_status != GLAM_OK) return fit_fail(path_status, "path stopped early (see status array)");
+  return GLAM_OK;
+}
+
+
+// ============================================================================
+// glam_fit_batched
+// ============================================================================
+static int validate_problem(const glam_problem* prob, int dtype, std::string* why) {
+  if (prob->d != 3) { *why = "only d = 3 is supported"; return GLAM_EINVAL; }
+  for (int j = 0; j < 3; ++j) {
+    if (prob->n[j] < 1 || prob->p[j] < 1) { *why = "mode sizes must be >= 1"; return GLAM_EINVAL; }
+    if (!prob->X[j]) { *why = "NULL factor"; return GLAM_EINVAL; }
+  }
+  if (!prob->Y) { *why = "NULL Y"; return GLAM_EINVAL; }
+  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) { *why = "bad family"; return GLAM_EINVAL; }
+  if (glam_rho_workspace_size(3, prob->n, prob->p, dtype) == 0) { *why = glam_last_error(); return GLAM_EINVAL; }
+  if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024) {
+    *why = "modes 1-2 too large for the FP64 slab kernel";
+    return GLAM_EINVAL;
+  }
+  return GLAM_OK;
+}
+
+extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_options* opt,
+                                glam_batch_result* res) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!probs || !opt || !res || nprob < 1) return fit_fail(GLAM_EINVAL, "NULL argument or nprob < 1");
+  if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
+  if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
+  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
+    return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
+  if (!opt->lambda && !(opt->lambda_ratio > 0.0 && opt->lambda_ratio <= 1.0))
+    return fit_fail(GLAM_EINVAL, "lambda_ratio must be in (0, 1]");
+  if (!res->theta || !res->lambda_out || !res->lambda_max || !res->kkt || !res->objective || !res->iters_outer ||
+      !res->status)
+    return fit_fail(GLAM_EINVAL, "NULL result array");
+  for (int i = 0; i < nprob; ++i) {
+    std::string why;
+    if (validate_problem(&probs[i], opt->dtype, &why)) return fit_fail(GLAM_EINVAL, "problem " + std::to_string(i) + ": " + why);
+    if (!res->theta[i]) return fit_fail(GLAM_EINVAL, "NULL theta output");
+    if (opt->lambda && !(opt->lambda[i] >= 0.0 && std::isfinite(opt->lambda[i])))
+      return fit_fail(GLAM_EINVAL, "lambda values must be finite and >= 0");
+  }
+  const int dt = opt->dtype;
+  // shared stream, ordered after the caller's stream
+  hipStream_t us = (hipStream_t)opt->stream, s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fit_fail(GLAM_EDEVICE, "stream");
+  struct StreamGuard { hipStream_t s; ~StreamGuard() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } } sg{s};
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fit_fail(GLAM_EDEVICE, "event");
+  struct EvGuard { hipEvent_t e; ~EvGuard() { if (e) (void)hipEventDestroy(e); } } eg{ev};
+  if (hipEventRecord(ev, us) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess)
+    return fit_fail(GLAM_EDEVICE, "stream ordering failed");
+
+  std::vector<std::unique_ptr<Fit>> fits(nprob);
+  std::vector<Geom> Gs(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    fits[i].reset(new Fit());
+    Fit& F = *fits[i];
+    F.G = Gs[i] = make_geom(probs[i].n, probs[i].p);
+    F.dt = dt;
+    F.s = s;
+    F.own_stream = false;
+    const int r = fit_setup(F, &probs[i], false, false);
+    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
+  }
+  // batch bookkeeping
+  std::vector<int> off_fwd(nprob + 1, 0), off_slab(nprob + 1, 0), off_adj(nprob + 1, 0);
+  std::vector<BatchDesc> desc(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const Geom& G = Gs[i];
+    const int fgx = (G.P12 + 31) / 32, fgy = (G.n3 + 31) / 32;
+    const int agx = (G.P12 + 15) / 16, agy = (G.p3 + 15) / 16;
+    off_fwd[i + 1] = off_fwd[i] + fgx * fgy;
+    off_slab[i + 1] = off_slab[i] + G.n3;
+    off_adj[i + 1] = off_adj[i] + agx * agy;
+    desc[i].fwd_gx = fgx;
+    desc[i].adj_gx = agx;
+  }
+  void* dmem = nullptr;
+  const size_t nparts = (size_t)off_adj[nprob] * ADJ_NSUM;
+  auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t piece[8] = {sizeof(BatchDesc) * nprob, sizeof(int) * (nprob + 1), sizeof(int) * (nprob + 1),
+                           sizeof(int) * (nprob + 1), sizeof(int) * nprob, sizeof(double) * nparts,
+                           sizeof(double) * 2 * nprob, 64};
+  size_t bytes = 0;
+  for (size_t b : piece) bytes += r256(b);
+  if (hipMalloc(&dmem, bytes) != hipSuccess) return fit_fail(GLAM_ENOMEM, "device allocation failed");
+  struct MemGuard { void* p; ~MemGuard() { if (p) (void)hipFree(p); } } mg{dmem};
+  char* q = (char*)dmem;
+  auto take = [&](size_t b) { char* r = q; q += r256(b); return (void*)r; };   // same order as piece[]
+  BatchDesc* d_desc = (BatchDesc*)take(sizeof(BatchDesc) * nprob);
+  int* d_off_fwd = (int*)take(sizeof(int) * (nprob + 1));
+  int* d_off_slab = (int*)take(sizeof(int) * (nprob + 1));
+  int* d_off_adj = (int*)take(sizeof(int) * (nprob + 1));
+  int* d_active = (int*)take(sizeof(int) * nprob);
+  double* d_part = (double*)take(sizeof(double) * nparts);
+  double* d_seg = (double*)take(sizeof(double) * 2 * nprob);
+  int* d_misc = (int*)take(64);   // [0] step counter, [1..2] barrier, [3] error flag
+  double* h_seg = nullptr;
+  int* h_misc = nullptr;
+  int* h_active = nullptr;
+  if (hipHostMalloc((void**)&h_seg, sizeof(double) * 2 * nprob) != hipSuccess ||
+      hipHostMalloc((void**)&h_misc, 64) != hipSuccess || hipHostMalloc((void**)&h_active, sizeof(int) * nprob) != hipSuccess)
+    return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
+  struct HGuard { void* a; void* b; void* c; ~HGuard() { if (a) (void)hipHostFree(a); if (b) (void)hipHostFree(b); if (c) (void)hipHostFree(c); } } hg{h_seg, h_misc, h_active};
+  for (int i = 0; i < nprob; ++i) {
+    Fit& F = *fits[i];
+    const Geom& G = Gs[i];
+    BatchDesc& D = desc[i];
+    D.fw = FwdParams{};
+    D.fw.G = G; D.fw.theta = F.inc; D.fw.X3f = F.X3fc; D.fw.T1 = F.T1c; D.fw.iter = nullptr;
+    D.sp = SlabParams{};
+    D.sp.G = G; D.sp.img = F.imgc; D.sp.T1 = F.T1c; D.sp.S2 = F.S2c; D.sp.v_int = F.v_int;
+    D.ap = AdjParams{};
+    D.ap.G = G; D.ap.S2 = F.S2c; D.ap.X3a = F.X3ac; D.ap.scale = 1.0 / (double)G.n; D.ap.pen_w = probs[i].pen_w;
+    D.ap.partials = d_part; D.ap.gref = F.gref; D.ap.theta_ref = F.theta; D.ap.x = F.x; D.ap.xp = F.xp;
+    D.ap.gp = F.gp; D.ap.inc = F.inc; D.ap.iter = d_misc; D.ap.dparams = F.dparams;
+  }
+#define BCHK(expr)                                                                                 \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fit_fail(GLAM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  BCHK(hipMemcpyAsync(d_desc, desc.data(), sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(d_off_fwd, off_fwd.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(d_off_slab, off_slab.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
+  BCHK(hipMemcpyAsync(d_off_adj, off_adj.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
+  BCHK(launch_zero(d_misc, 64, s));
+  BCHK(hipStreamSynchronize(s));   // host vectors above must outlive the copies
+  BatchParams B{};
+  B.desc = d_desc; B.nprob = nprob; B.off_fwd = d_off_fwd; B.off_slab = d_off_slab; B.off_adj = d_off_adj;
+  B.active = d_active; B.step = d_misc; B.bar = (unsigned*)(d_misc + 1); B.err = d_misc + 3;
+  const size_t lds = batched_lds_bytes(dt, Gs.data(), nprob);
+  const int grid = batched_grid(dt, lds);
+
+  // lambda_max_i and lambda_i
+  std::vector<double> lam(nprob), lmax(nprob), scale(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    Fit& F = *fits[i];
+    BCHK(launch_fill(F.theta, Gs[i].p, 0.0, s));
+    StepStats st0;
+    const int r = family_step(F, F.theta, 0.0, &st0);
+    if (r) return fit_fail(r, F.err);
+    lmax[i] = st0.lmax_raw;
+    scale[i] = lmax[i] > 0.0 ? lmax[i] : 1.0;
+    lam[i] = opt->lambda ? opt->lambda[i] : opt->lambda_ratio * lmax[i];
+    res->lambda_out[i] = lam[i];
+    res->lambda_max[i] = lmax[i];
+    res->status[i] = GLAM_ENOCONV;
+    res->iters_outer[i] = 0;
+    res->kkt[i] = INFINITY;
+    res->objective[i] = NAN;
+  }
+  std::vector<char> done(nprob, 0);
+  std::vector<double> tol_in(nprob), best(nprob), wbest(nprob);
+  const double tol = opt->kkt_tol;
+  long long launches = 0, pstep = 0;
+  for (int round = 0; round <= opt->max_outer; ++round) {
+    int nact = 0;
+    for (int i = 0; i < nprob; ++i) {
+      h_active[i] = 0;
+      if (done[i]) continue;
+      Fit& F = *fits[i];
+      StepStats st;
+      const int r = family_step(F, F.theta, lam[i], &st);
+      if (r) return fit_fail(r, F.err);
+      const double kkt = st.kkt_raw / scale[i];
+      res->kkt[i] = kkt;
+      res->objective[i] = st.nll + lam[i] * st.pen;
+      res->iters_outer[i] = round;
+      if (!std::isfinite(kkt)) { res->status[i] = GLAM_ENONFINITE; done[i] = 1; continue; }
+      if (kkt <= tol) { res->status[i] = GLAM_OK; done[i] = 1; continue; }
+      if (round == opt->max_outer) { done[i] = 1; continue; }
+      const double wmax = F.family == GLAM_POISSON ? st.vmax : 1.0;
+      const double Lhat = wmax * F.sprod / (double)Gs[i].n;
+      if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { res->status[i] = GLAM_ENONFINITE; done[i] = 1; continue; }
+      const bool exact_model = F.family == GLAM_GAUSSIAN && probs[i].obs_w == nullptr;
+      tol_in[i] = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
+      if (dt == DT_BF16) tol_in[i] = std::max(tol_in[i], 0.1 * kkt);
+      best[i] = wbest[i] = INFINITY;
+      BCHK(launch_inner_init(Gs[i], F.theta, F.gref, F.x, F.xp, F.gp, dt, F.inc, F.iter, s));
+      F.hparams[0] = lam[i];
+      F.hparams[1] = 1.0 / Lhat;
+      BCHK(hipMemcpyAsync(F.dparams, F.hparams, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+      h_active[i] = 1;
+      ++nact;
+    }
+    if (nact == 0) break;
+    std::vector<char> in_round(nprob);
+    for (int i = 0; i < nprob; ++i) in_round[i] = (char)h_active[i];
+    BCHK(launch_zero(d_misc, 4, s));   // step counter l = 0
+    BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
+    int it = 0, window_start = 0;
+    while (nact > 0 && it < opt->max_inner) {
+      const int m = std::min(opt->check_every, opt->max_inner - it);
+      for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, grid, lds, s));
+      launches += m;
+      pstep += (long long)m * nact;
+      it += m;
+      BCHK(launch_segment_max(d_part, d_off_adj, nprob, d_seg, s));
+      BCHK(hipMemcpyAsync(h_seg, d_seg, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost, s));
+      BCHK(hipMemcpyAsync(h_misc, d_misc, 16, hipMemcpyDeviceToHost, s));
+      BCHK(hipStreamSynchronize(s));
+      if (h_misc[3] != 0) return fit_fail(GLAM_EDEVICE, "grid barrier timeout in the batched step (grid not co-resident)");
+      bool changed = false;
+      const bool window = it - window_start >= 20 * opt->check_every;
+      for (int i = 0; i < nprob; ++i) {
+        if (!h_active[i]) continue;
+        const double kin = h_seg[2 * i] / scale[i];
+        const double noise = 4.0 * kEps[dt] * h_seg[2 * i + 1] / scale[i];
+        best[i] = std::min(best[i], kin);
+        bool stop = !std::isfinite(kin) || kin <= std::max(tol_in[i], noise);
+        if (window && dt != DT_F64) {
+          if (!(best[i] < 0.5 * wbest[i])) stop = true;
+          wbest[i] = best[i];
+        }
+        if (stop) { h_active[i] = 0; --nact; changed = true; }
+      }
+      if (window) window_start = it;
+      if (changed && nact > 0) BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
+    }
+    // step 5 of Algorithm 1 per problem: Armijo along theta~ - theta^k (theta~ = x^l of the last check)
+    for (int i = 0; i < nprob; ++i) {
+      if (!in_round[i]) continue;
+      Fit& F = *fits[i];
+      BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, s));
+      double alpha = 0.0, Delta = 0.0;
+      const int r = armijo(F, lam[i], 0.1, &alpha, &Delta);
+      if (r) return fit_fail(r, F.err);
+      if (alpha > 0.0) BCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, s));
+    }
+  }
+  int worst = GLAM_OK;
+  for (int i = 0; i < nprob; ++i) {
+    BCHK(hipMemcpyAsync(res->theta[i], fits[i]->theta, Gs[i].p * 8, hipMemcpyDeviceToDevice, s));
+    if (res->status[i] != GLAM_OK && worst == GLAM_OK) worst = res->status[i];
+  }
+  BCHK(hipStreamSynchronize(s));
+  BCHK(hipEventRecord(ev, s));
+  BCHK(hipStreamWaitEvent(us, ev, 0));
+  res->steps = launches;
+  res->problem_steps = pstep;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (worst != GLAM_OK) return fit_fail(worst, "some problems did not converge (see status)");
   return GLAM_OK;
 }
 

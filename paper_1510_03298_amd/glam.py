@@ -56,6 +56,20 @@ class GlamResult(ctypes.Structure):
                 ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong)]
 
 
+class GlamBatchOptions(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("lambda_ratio", ctypes.c_double),
+                ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("max_inner", ctypes.c_int), ("check_every", ctypes.c_int), ("stream", _vp)]
+
+
+class GlamBatchResult(ctypes.Structure):
+    _fields_ = [("theta", ctypes.POINTER(_vp)), ("lambda_out", ctypes.POINTER(ctypes.c_double)),
+                ("lambda_max", ctypes.POINTER(ctypes.c_double)), ("kkt", ctypes.POINTER(ctypes.c_double)),
+                ("objective", ctypes.POINTER(ctypes.c_double)), ("iters_outer", ctypes.POINTER(ctypes.c_int)),
+                ("status", ctypes.POINTER(ctypes.c_int)), ("steps", ctypes.c_longlong),
+                ("problem_steps", ctypes.c_longlong), ("seconds", ctypes.c_double)]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -75,6 +89,9 @@ glam_rho_adjoint = _sig("glam_rho_adjoint", ctypes.c_int,
                          ctypes.c_size_t, _vp])
 glam_fit_path = _sig("glam_fit_path", ctypes.c_int,
                      [ctypes.POINTER(GlamProblem), ctypes.POINTER(GlamOptions), ctypes.POINTER(GlamResult)])
+glam_fit_batched = _sig("glam_fit_batched", ctypes.c_int,
+                        [ctypes.POINTER(GlamProblem), ctypes.c_int, ctypes.POINTER(GlamBatchOptions),
+                         ctypes.POINTER(GlamBatchResult)])
 glam_nll_workspace_size = _sig("glam_nll_workspace_size", ctypes.c_size_t, [_i64p, _i64p, ctypes.c_int])
 glam_poisson_nll_forward = _sig("glam_poisson_nll_forward", ctypes.c_int,
                                 [_i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int, _vp,
@@ -84,7 +101,7 @@ glam_poisson_nll_backward = _sig("glam_poisson_nll_backward", ctypes.c_int,
                                   ctypes.c_size_t, _vp])
 
 EXPORTED = ["glam_status_string", "glam_last_error", "glam_version", "glam_rho_workspace_size",
-            "glam_rho_forward", "glam_rho_adjoint", "glam_fit_path", "glam_nll_workspace_size",
+            "glam_rho_forward", "glam_rho_adjoint", "glam_fit_path", "glam_fit_batched", "glam_nll_workspace_size",
             "glam_poisson_nll_forward", "glam_poisson_nll_backward"]
 
 
@@ -327,4 +344,71 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
                      float(res.iter_ms), int(res.inner_total))
     if raise_on_error and code != GLAM_OK:
         raise GlamError(code, "glam_fit_path")
+    return out
+
+
+# ----------------------------------------------------------------------------- batched fits
+@dataclass
+class BatchResult:
+    theta: list              # device FP64 tensors, one p_i-array per problem
+    lambdas: np.ndarray
+    lambda_max: np.ndarray
+    kkt: np.ndarray
+    objective: np.ndarray
+    iters_outer: np.ndarray
+    status: np.ndarray
+    steps: int
+    problem_steps: int
+    seconds: float
+    code: int
+
+
+def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-6, max_outer=100,
+                max_inner=100000, check_every=10, stream=None, raise_on_error=True) -> BatchResult:
+    """Fit many independent problems (one lambda each) with one persistent launch per
+    batched proximal step.  problems: list of dicts with keys X (3 FP64 device
+    factors), Y (FP64 device n-array), n, p, family, and optional obs_w, pen_w."""
+    torch = _torch()
+    nprob = len(problems)
+    arr = (GlamProblem * nprob)()
+    for i, pr in enumerate(problems):
+        P = arr[i]
+        P.d = 3
+        for j in range(3):
+            P.n[j] = int(pr["n"][j])
+            P.p[j] = int(pr["p"][j])
+            P.X[j] = pr["X"][j].data_ptr()
+        P.Y = pr["Y"].data_ptr()
+        P.obs_w = pr["obs_w"].data_ptr() if pr.get("obs_w") is not None else None
+        fam = pr.get("family", "gaussian")
+        P.family = FAMILIES[fam] if isinstance(fam, str) else int(fam)
+        P.pen_w = pr["pen_w"].data_ptr() if pr.get("pen_w") is not None else None
+    opt = GlamBatchOptions()
+    lam_arr = None
+    if lambdas is not None:
+        lam_arr = (ctypes.c_double * nprob)(*[float(v) for v in lambdas])
+        opt.lambda_ = lam_arr
+    opt.lambda_ratio = float(lambda_ratio)
+    opt.dtype = int(dtype)
+    opt.kkt_tol = float(kkt_tol)
+    opt.max_outer, opt.max_inner, opt.check_every = int(max_outer), int(max_inner), int(check_every)
+    opt.stream = _stream_ptr(stream)
+    dev = problems[0]["Y"].device
+    thetas = [torch.zeros(int(np.prod(pr["p"])), dtype=torch.float64, device=dev) for pr in problems]
+    tp = (_vp * nprob)(*[t.data_ptr() for t in thetas])
+    outs = [(ctypes.c_double * nprob)() for _ in range(5)]
+    io = (ctypes.c_int * nprob)()
+    st = (ctypes.c_int * nprob)(*([-1] * nprob))
+    res = GlamBatchResult()
+    res.theta = tp
+    res.lambda_out, res.lambda_max, res.kkt, res.objective = outs[0], outs[1], outs[2], outs[3]
+    res.iters_outer, res.status = io, st
+    code = glam_fit_batched(arr, nprob, ctypes.byref(opt), ctypes.byref(res))
+    if code in (GLAM_EINVAL, GLAM_ENOMEM, GLAM_EDEVICE):
+        raise GlamError(code, "glam_fit_batched")
+    out = BatchResult(thetas, np.array(outs[0][:]), np.array(outs[1][:]), np.array(outs[2][:]),
+                      np.array(outs[3][:]), np.array(io[:]), np.array(st[:]), int(res.steps),
+                      int(res.problem_steps), float(res.seconds), int(code))
+    if raise_on_error and code != GLAM_OK:
+        raise GlamError(code, "glam_fit_batched")
     return out

@@ -1,0 +1,75 @@
+"""Batched fits of many uneven GLAMs (one persistent launch per proximal step)
+against the oracle, problem by problem."""
+import numpy as np
+import pytest
+
+import oracle.glam_oracle as O
+from paper_1510_03298_amd import inputs
+from tests.gpu_util import need_gpu, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _upload(glam, d):
+    return {"X": [glam.to_device_colmajor(X, 0) for X in d.X], "Y": glam.to_device_colmajor(d.Y, 0),
+            "n": d.n, "p": d.p, "family": d.family}
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_batched_mixed_families_match_oracle(dt):
+    torch, glam = need_gpu()
+    print(f"batched dt={dt}", flush=True)
+    probs = inputs.config_c4(nprob=6, lo=16, hi=40, seed_offset=40)
+    res = glam.fit_batched([_upload(glam, d) for d in probs], lambda_ratio=0.1, dtype=dt, kkt_tol=1e-6)
+    assert res.code == 0 and np.all(res.status == 0)
+    for i, d in enumerate(probs):
+        fam = d.family
+        lm = O.lambda_max(fam, d.X, d.Y)
+        assert abs(res.lambda_max[i] - lm) <= 1e-12 * lm
+        lam = 0.1 * lm
+        th = glam.from_colmajor(res.theta[i], d.p)
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, lam, lm) <= 1e-6
+        ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-10, max_outer=200)
+        assert rel_inf(th, ref) <= 1e-3
+
+
+def test_batched_matches_single_problem_fits():
+    """The same PMLE as glam_fit_path on each problem alone."""
+    torch, glam = need_gpu()
+    probs = inputs.config_c4(nprob=4, lo=16, hi=32, seed_offset=41)
+    ups = [_upload(glam, d) for d in probs]
+    res = glam.fit_batched(ups, lambda_ratio=0.2, dtype=1, kkt_tol=1e-7)
+    for i, d in enumerate(probs):
+        r1 = glam.fit_path(ups[i]["X"], ups[i]["Y"], d.n, d.p, d.family, lambdas=[res.lambdas[i]], dtype=1,
+                           kkt_tol=1e-7)
+        a = glam.from_colmajor(res.theta[i], d.p)
+        b = glam.from_colmajor(r1.theta[0], d.p)
+        assert rel_inf(a, b) <= 1e-4
+
+
+def test_batched_rejects_bad_problem():
+    torch, glam = need_gpu()
+    probs = inputs.config_c4(nprob=2, lo=16, hi=20, seed_offset=42)
+    ups = [_upload(glam, d) for d in probs]
+    ups[1]["family"] = 7
+    with pytest.raises(glam.GlamError):
+        glam.fit_batched(ups, lambda_ratio=0.1, dtype=1)
+
+
+def test_batched_full_c4_sampled():
+    """All 256 uneven problems (n_ij in 16..96) in one batch, FP32 inner chain;
+    the KKT residual of a sample of problems recomputed by the oracle."""
+    torch, glam = need_gpu()
+    probs = inputs.config_c4()
+    ups = [_upload(glam, d) for d in probs]
+    res = glam.fit_batched(ups, lambda_ratio=0.1, dtype=1, kkt_tol=1e-6)
+    assert res.code == 0 and np.all(res.status == 0)
+    assert np.all(res.kkt <= 1e-6)
+    rng = np.random.default_rng(7)
+    for i in sorted(rng.choice(len(probs), size=6, replace=False)):
+        d = probs[i]
+        lm = O.lambda_max(d.family, d.X, d.Y)
+        th = glam.from_colmajor(res.theta[i], d.p)
+        g = O.smooth_gradient(d.family, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, 0.1 * lm, lm) <= 1e-6, i
