@@ -87,6 +87,87 @@ def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
     }
 
 
+def copy_calibration(torch, dev, mib):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    counter readings give the scale from counter units to bytes."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": mib << 20, "copy_calibration_bytes_written": mib << 20}))
+
+
+def poisson_path(glam, inputs, torch, stream):
+    """Poisson counts, n = (64, 64, 365), p = (24, 24, 120), 50-lambda log grid to
+    1e-4 lambda_max, KKT <= 1e-6, BF16 inner chain (FP64 Armijo, KKT and anchors)."""
+    d = inputs.config_c3()
+    Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    out = {"workload": "poisson_path_n64x64x365_p24x24x120_50lambda_kkt1e-6", "dtype": "bf16"}
+    for dt, name in ((glam.BF16, "bf16"), (glam.F64, "f64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=d.nlambda, lambda_min_ratio=d.lambda_min_ratio,
+                          dtype=dt, kkt_tol=1e-6, stream=stream, raise_on_error=False)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "converged": r.code == 0 and r.n_done == d.nlambda,
+                     "max_kkt": float(np.max(r.kkt[:r.n_done])) if r.n_done else None,
+                     "inner": int(r.inner_total), "outer": int(r.iters_outer.sum())}
+    out["speedup_bf16_vs_f64"] = out["f64"]["seconds"] / out["bf16"]["seconds"]
+    return out
+
+
+def batched(glam, inputs, torch, stream):
+    """256 independent GLAMs, n_ij ~ U{16..96}, p_ij = round(n_ij / 4), even
+    Gaussian / odd Poisson, lambda_i = 0.1 lambda_max_i, FP32 inner chain, all to
+    KKT <= 1e-6 (one persistent launch per batched proximal step)."""
+    probs = inputs.config_c4()
+    ups = [{"X": [glam.to_device_colmajor(X, glam.F64) for X in q.X], "Y": glam.to_device_colmajor(q.Y, glam.F64),
+            "n": q.n, "p": q.p, "family": q.family} for q in probs]
+    glam.fit_batched(ups[:4], lambda_ratio=0.1, dtype=glam.F32, stream=stream)   # warm-up (module load)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = glam.fit_batched(ups, lambda_ratio=0.1, dtype=glam.F32, kkt_tol=1e-6, stream=stream, raise_on_error=False)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return {"workload": "batched_256_uneven_n16-96_kkt1e-6", "dtype": "f32", "seconds": sec,
+            "converged": bool(r.code == 0 and np.all(r.status == 0)), "max_kkt": float(np.max(r.kkt)),
+            "batched_steps": r.steps, "proximal_steps": r.problem_steps,
+            "proximal_steps_per_s": r.problem_steps / sec,
+            "sum_n": int(sum(np.prod(q.n) for q in probs)), "sum_p": int(sum(np.prod(q.p) for q in probs))}
+
+
+def nll(glam, inputs, torch, stream, reps=50):
+    """Poisson NLL L(beta) = (1/n) sum(exp(eta) - y eta) and its gradient at
+    n = (128, 128, 256), p = (32, 32, 64), BF16 chain: HIP-event time per call."""
+    d = inputs.config_c5()
+    Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    out = {"workload": "poisson_nll_n128x128x256_p32x32x64", "dtype": "bf16"}
+    beta = glam.to_device_colmajor(d.extra["beta"], glam.BF16)
+    ws = torch.empty(glam.nll_workspace_size(d.n, d.p, glam.BF16), dtype=torch.uint8, device=Yd.device)
+    one = torch.ones(1, dtype=torch.float64, device=Yd.device)
+    fwd3, chain, adj3 = flop_model(d.n, d.p)
+    flops_f = fwd3 + chain // 2          # forward chain only
+    flops_b = fwd3 + chain + adj3        # recomputed forward + adjoint
+    calls = (("forward", lambda: glam.poisson_nll_forward(Xd, beta, Yd, d.n, d.p, glam.BF16, ws, stream), flops_f),
+             ("backward", lambda: glam.poisson_nll_backward(Xd, beta, Yd, one, d.n, d.p, glam.BF16, ws, stream),
+              flops_b))
+    for kind, fn, fl in calls:
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        out[kind] = {"us_per_call": us, "tflops": fl / (us * 1e-6) / 1e12, "flops_per_call": fl}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +179,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--profile-every", type=int, default=160,
                     help="time one inner iteration in this many with HIP events (those blocks run un-captured)")
+    ap.add_argument("--lambda-min-ratio", type=float, default=1e-4)
+    ap.add_argument("--eager", action="store_true", help="launch every inner iteration eagerly (no HIP graphs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary workloads (Poisson path, 256-problem batch, Poisson NLL)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -110,6 +197,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(torch, dev, args.copy_calibration)
+        return
     d = inputs.config_c2(nlambda=args.nlambda)
     n, p = d.n, d.p
     Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
@@ -119,9 +209,9 @@ def main():
     dts = {"f64": glam.F64, "f32": glam.F32, "bf16": glam.BF16}
 
     def fit(dt, profile_every=0):
-        return glam.fit_path(Xd, Yd, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=1e-4,
+        return glam.fit_path(Xd, Yd, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=args.lambda_min_ratio,
                              dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
-                             profile_every=profile_every, raise_on_error=False)
+                             profile_every=profile_every, raise_on_error=False, graph=not args.eager)
 
     for _ in range(args.warmup):
         fit(args.dtype)
@@ -171,18 +261,24 @@ def main():
     cpu = None
     if not args.no_cpu and "f64" in forms:
         cpu = cpu_baseline(d, forms["f64"]["inner"], forms["f64"]["outer"])
+    extra = None
+    if not args.no_extra:
+        extra = {"poisson_path_c3": poisson_path(glam, inputs, torch, stream),
+                 "batched_c4": batched(glam, inputs, torch, stream),
+                 "poisson_nll_c5": nll(glam, inputs, torch, stream)}
     out = {
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "gaussian_path_n100x100x1000_p30x30x200_100lambda_kkt1e-6",
-                   "n": list(n), "p": list(p), "nlambda": args.nlambda, "lambda_min_ratio": 1e-4,
-                   "kkt_tol": 1e-6, "family": "gaussian"},
+                   "n": list(n), "p": list(p), "nlambda": args.nlambda, "lambda_min_ratio": args.lambda_min_ratio,
+                   "kkt_tol": 1e-6, "family": "gaussian", "graphs": not args.eager},
         "all_models_converged": ok,
         "forms": forms,
         "flops_per_inner_iteration": fwd3 + chain + adj3,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
 

@@ -443,6 +443,168 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
 }
 
 // ============================================================================
+// slab_chain, one wave per slab (BF16, n1, n2 <= 128, p1, p2 <= 32)
+//
+// The same five products as chain_slab, with 16 x 16 x 32 matrix-core blocks and
+// every factor operand held in registers for the whole slab: each wave owns one
+// slab i3 and needs no LDS and no workgroup barrier.  A 32-deep contraction block
+// is two 16-row accumulator tiles side by side: slot u of lane group g stands for
+// index kw(g, u) = 4 g + u (u < 4) or 16 + 4 g + u - 4 (u >= 4) within the block,
+// so an accumulator pair (rows 0-15, rows 16-31) is directly the next product's
+// operand.  The factor operands are pre-packed in that order ("wave image", one
+// 64-lane x 8-element fragment per operand tile):
+//   FX2T[jb]     (B of T2 = T1_s X2^T)     X2[16 jb + c][kw]        jb < 8
+//   FX1A[ut]     (A of eta = X1 T2)        X1[16 ut + r][kw]        ut < 8
+//   FX1B[q][nt]  (B of S1^T = R^T X1)      X1[32 q + kw][16 nt + c] q < 4, nt < 2
+//   FX2A[mt][q]  (A of S2^T = X2^T S1^T)   X2[32 q + kw][16 mt + r] mt < 2, q < 4
+// The slab order is XCD-aware: workgroups go round-robin to the 8 XCDs, and the 16
+// slabs that share a k-block of S2 are placed on one XCD, so that their 2-byte
+// stores into the same lines merge in that XCD's L2.
+// ============================================================================
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v_t __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE_FRAGS = 32;
+constexpr int WAVE_IMAGE_BYTES = WAVE_FRAGS * 64 * 16;
+__host__ __device__ inline int kw_index(int g, int u) { return u < 4 ? 4 * g + u : 12 + 4 * g + u; }
+__host__ __device__ inline bool wave_chain_ok(const Geom& G) { return G.N1T <= 8 && G.NJB <= 8 && G.PT <= 2; }
+__host__ __device__ inline size_t wave_image_offset(const Geom& G) {
+  return ((size_t)chain_layout(G, 2, 4).image_bytes + 255) & ~(size_t)255;
+}
+
+__device__ inline bf8v pack_acc2(const f4v& lo, const f4v& hi) {
+  bf8v v;
+  v[0] = (__bf16)lo[0]; v[1] = (__bf16)lo[1]; v[2] = (__bf16)lo[2]; v[3] = (__bf16)lo[3];
+  v[4] = (__bf16)hi[0]; v[5] = (__bf16)hi[1]; v[6] = (__bf16)hi[2]; v[7] = (__bf16)hi[3];
+  return v;
+}
+__device__ inline f4v mma32(const bf8v& a, const bf8v& b, const f4v& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline bf8v load_wfrag(const unsigned char* img, int frag, int lane) {
+  return __builtin_bit_cast(bf8v, ((const u4v_t*)img)[frag * 64 + lane]);
+}
+
+__device__ inline bf16 to_bf16(double v) { bf16 b; b.u = f32_to_bf16((float)v); return b; }
+__device__ inline bf16 to_bf16(bf16 v) { return v; }
+
+// wave image: one fragment per workgroup (frag = blockIdx.x, lane = threadIdx.x)
+template <typename S>
+__global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __restrict__ X2, bf16* __restrict__ out) {
+  const int f = blockIdx.x, l = threadIdx.x, rc = l & 15, g = l >> 4;
+  if (f >= WAVE_FRAGS || l >= 64) return;
+  for (int u = 0; u < 8; ++u) {
+    const int kw = kw_index(g, u);
+    int i, k;
+    bool x1;   // element X1[i][k] or X2[i][k]
+    if (f < 8) { x1 = false; i = 16 * f + rc; k = kw; }                                  // FX2T[jb]
+    else if (f < 16) { x1 = true; i = 16 * (f - 8) + rc; k = kw; }                       // FX1A[ut]
+    else if (f < 24) { x1 = true; i = 32 * ((f - 16) >> 1) + kw; k = 16 * ((f - 16) & 1) + rc; }   // FX1B[q][nt]
+    else { x1 = false; i = 32 * ((f - 24) & 3) + kw; k = 16 * ((f - 24) >> 2) + rc; }              // FX2A[mt][q]
+    bf16 b = zero_val<bf16>();
+    if (x1 && i < G.n1 && k < G.p1) b = to_bf16(X1[i + (long long)G.n1 * k]);
+    if (!x1 && i < G.n2 && k < G.p2) b = to_bf16(X2[i + (long long)G.n2 * k]);
+    out[((long long)f * 64 + l) * 8 + u] = b;
+  }
+}
+
+template <bool HAS_V>
+__global__ __launch_bounds__(64) void k_slab_chain_w(SlabParams P) {
+  const Geom& G = P.G;
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  // XCD-aware slab order: workgroup b runs on XCD b % 8; k-block kb on XCD kb % 8
+  const int b = blockIdx.x, x = b & 7, j = b >> 3;
+  const int kb = x + 8 * (j >> 4);
+  const int i3 = 16 * kb + (j & 15);
+  if (i3 >= G.n3) return;   // whole-wave exit (one wave per workgroup, no barriers)
+  const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G);
+  const int N1T = G.N1T, NJB = G.NJB;
+  // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
+  bf8v ft1[2];
+  {
+    const unsigned short* t1 = (const unsigned short*)P.T1 + (long long)i3 * G.P12;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int i1 = 16 * mt + r;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i2 = kw_index(g, u);
+        const unsigned short h = (i1 < G.p1 && i2 < G.p2) ? t1[i1 + G.p1 * i2] : (unsigned short)0;
+        ft1[mt][u] = __builtin_bit_cast(__bf16, h);
+      }
+    }
+  }
+  bf8v fx2t[8], fx1a[8], fx1b[4][2], fx2a[2][4];
+  const bf8v zf = {};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    fx2t[t] = t < NJB ? load_wfrag(img, t, lane) : zf;
+    fx1a[t] = t < N1T ? load_wfrag(img, 8 + t, lane) : zf;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) fx1b[q][nt] = 2 * q < N1T ? load_wfrag(img, 16 + 2 * q + nt, lane) : zf;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) fx2a[mt][q] = 2 * q < NJB ? load_wfrag(img, 24 + 4 * mt + q, lane) : zf;
+  }
+  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+  f4v s2[2][2] = {{z4, z4}, {z4, z4}};
+  const float* V = (const float*)P.v_int;
+#pragma unroll
+  for (int jq = 0; jq < 4; ++jq) {
+    if (2 * jq >= NJB) break;
+    f4v s1[2][2] = {{z4, z4}, {z4, z4}};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int jb = 2 * jq + h;
+      if (jb >= NJB) break;
+      // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
+      const bf8v ft2 = pack_acc2(mma32(ft1[0], fx2t[jb], z4), mma32(ft1[1], fx2t[jb], z4));
+#pragma unroll
+      for (int uq = 0; uq < 4; ++uq) {
+        const int u0 = 2 * uq;
+        if (u0 >= N1T) break;
+        // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
+        f4v e0 = mma32(fx1a[u0], ft2, z4);
+        f4v e1 = u0 + 1 < N1T ? mma32(fx1a[u0 + 1], ft2, z4) : z4;
+        if (HAS_V) {
+          const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
+          const f4v v0 = *(const f4v*)(V + t0);
+          e0 *= v0;
+          if (u0 + 1 < N1T) {
+            const f4v v1 = *(const f4v*)(V + t0 + 256);
+            e1 *= v1;
+          }
+        }
+        // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
+        const bf8v fr = pack_acc2(e0, e1);
+        s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
+        s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
+      }
+    }
+    // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
+    }
+  }
+  // S2 k-blocked (K = n3, C = P12): elem (i3, m) at ((i3 / 16) P12 + m) 16 + (i3 % 16)
+  unsigned short* S2 = (unsigned short*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<bf16>(i3 & 15);
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+        if (i1 < G.p1 && i2 < G.p2) S2[(long long)(i1 + G.p1 * i2) * 16] = f32_to_bf16(s2[mt][nt][i]);
+      }
+}
+
+// ============================================================================
 // slab_adj: out (P12 x p3) = S2^T (P12 x n3) X3a (n3 x p3), split-K over the 4
 // waves of a workgroup (one 16 x 16 output tile per workgroup) + epilogue.
 // ============================================================================
@@ -721,6 +883,7 @@ __global__ void k_pack_chain_image(Geom G, const S* __restrict__ X1, const S* __
 }
 
 size_t chain_image_bytes(int dt, const Geom& G) {
+  if (dt == DT_BF16 && wave_chain_ok(G)) return wave_image_offset(G) + WAVE_IMAGE_BYTES;
   return (size_t)chain_layout(G, (int)dt_size(dt), dt == DT_F64 ? 8 : 4).image_bytes;
 }
 
@@ -735,6 +898,13 @@ hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void
     if (src_dt != dt) return hipErrorInvalidValue;
     if (dt == DT_F32) hipLaunchKernelGGL((k_pack_chain_image<float, float>), grid, blk, 0, s, G, (const float*)X1, (const float*)X2, (float*)img);
     else hipLaunchKernelGGL((k_pack_chain_image<bf16, bf16>), grid, blk, 0, s, G, (const bf16*)X1, (const bf16*)X2, (bf16*)img);
+  }
+  if (dt == DT_BF16 && wave_chain_ok(G)) {
+    bf16* wimg = (bf16*)((unsigned char*)img + wave_image_offset(G));
+    if (src_dt == DT_F64)
+      hipLaunchKernelGGL((k_pack_wave_image<double>), dim3(WAVE_FRAGS), dim3(64), 0, s, G, (const double*)X1, (const double*)X2, wimg);
+    else
+      hipLaunchKernelGGL((k_pack_wave_image<bf16>), dim3(WAVE_FRAGS), dim3(64), 0, s, G, (const bf16*)X1, (const bf16*)X2, wimg);
   }
   return hipGetLastError();
 }
@@ -818,6 +988,14 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
       set_lds(fn, lds);
       hipLaunchKernelGGL(fn, grid, blk, lds, s, P);
     }
+    return hipGetLastError();
+  }
+  if (dt == DT_BF16 && mode == SM_FUSED && wave_chain_ok(P.G)) {
+    // one wave per slab; 16 workgroups per k-block of S2, rounded up to 8 XCDs
+    const int kbg = (P.G.KBN3 + 7) / 8;
+    dim3 wgrid(8 * 16 * kbg), wblk(64);
+    if (P.v_int) hipLaunchKernelGGL(k_slab_chain_w<true>, wgrid, wblk, 0, s, P);
+    else hipLaunchKernelGGL(k_slab_chain_w<false>, wgrid, wblk, 0, s, P);
     return hipGetLastError();
   }
   const int PT = P.G.PT;
