@@ -206,6 +206,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
   ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
   ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
+  ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
   if (sample) {
     FCHK(hipEventRecord(F.ev[3], F.s));
@@ -293,6 +294,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
     ap.x = cur[0]; ap.xp = cur[1]; ap.gp = cur[2]; ap.yprev = cur[3]; ap.gyprev = cur[4];
     ap.x_out = nxt[0]; ap.xp_out = nxt[1]; ap.gp_out = nxt[2]; ap.y_out = nxt[3]; ap.gy_out = nxt[4];
+    ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
     int nb = 0;
     FCHK(launch_slab_adj(F.dt, EPI_PROX_BT, ap, &nb, F.s));
     const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};

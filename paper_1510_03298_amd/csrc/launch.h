@@ -107,6 +107,7 @@ struct AdjParams {
   const double* yprev;
   const double* gyprev;
   double *x_out, *xp_out, *gp_out, *y_out, *gy_out;
+  int s2_kb4;            // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
 };
 
 struct FwdParams {
@@ -144,6 +145,8 @@ hipError_t launch_segment_max(const double* partials, const int* off, int nprob,
 // rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
 hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s);
+// true when launch_slab_chain writes S2 in 4-deep k-blocks (AdjParams::s2_kb4) for this mode
+bool chain_s2_kb4(int dt, int mode, const Geom& G);
 hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, hipStream_t s);
 size_t slab_chain_lds_bytes(int dt, const Geom& G);
 // LDS image of the mode-1 / mode-2 factors (X1, X2: n_j x p_j column-major, FP64 or chain dtype)

@@ -26,6 +26,41 @@ __device__ inline int wave_id() { return threadIdx.x >> 6; }
 template <typename T> struct OutOf { typedef float type; };
 template <> struct OutOf<double> { typedef double type; };
 
+// 16 x 16 x 32 BF16 blocks: a 32-deep contraction block is two 16-deep blocks side
+// by side (slots 0-3 of lane group g: index 4 g + t of the first block, slots 4-7:
+// the same of the second), the same pairing for both operands.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v_t __attribute__((ext_vector_type(4)));
+
+__device__ inline bf8v pack_acc2(const f4v& lo, const f4v& hi) {
+  bf8v v;
+  v[0] = (__bf16)lo[0]; v[1] = (__bf16)lo[1]; v[2] = (__bf16)lo[2]; v[3] = (__bf16)lo[3];
+  v[4] = (__bf16)hi[0]; v[5] = (__bf16)hi[1]; v[6] = (__bf16)hi[2]; v[7] = (__bf16)hi[3];
+  return v;
+}
+__device__ inline f4v mma32(const bf8v& a, const bf8v& b, const f4v& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline bf8v cat_frag(const Tr<bf16>::frag_t& a, const Tr<bf16>::frag_t& b) {
+  return __builtin_bit_cast(bf8v, __builtin_shufflevector(a.s, b.s, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// acc += sum_q A_q^T B_q over NB 16-deep blocks (BF16: in 32-deep pairs)
+template <typename T, int NB> struct MmaBlocks {
+  __device__ static inline void run(typename Tr<T>::accv_t& acc, const typename Tr<T>::frag_t* fa,
+                                    const typename Tr<T>::frag_t* fb) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) mma(acc, fa[q], fb[q]);
+  }
+};
+template <int NB> struct MmaBlocks<bf16, NB> {
+  __device__ static inline void run(f4v& acc, const Tr<bf16>::frag_t* fa, const Tr<bf16>::frag_t* fb) {
+    static_assert(NB % 2 == 0, "pairs of blocks");
+#pragma unroll
+    for (int q = 0; q < NB; q += 2) acc = mma32(cat_frag(fa[q], fa[q + 1]), cat_frag(fb[q], fb[q + 1]), acc);
+  }
+};
+
 __device__ inline double warp_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -56,41 +91,29 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
   }
 }
 
-// acc += sum over the k-blocks kb = kb0 + j * kstep (j < nkb) of A_kb^T B_kb, with
-// fragments loaded NB blocks ahead of the matrix-core work (k-blocked operands).
+// acc += sum over the k-blocks kb = kb0 + j * kstep (j < nkb) of A_kb^T B_kb
+// (k-blocked operands), NB blocks per round of loads: a contraction of at most NB
+// blocks is one round, so its latency is paid once.
 template <typename T, int NB>
 __device__ inline void kblock_loop(typename Tr<T>::accv_t& acc, const T* pa, const T* pb, long long sa, long long sb,
                                    int kb0, int kstep, int nkb, bool am, bool bn) {
   typedef typename Tr<T>::frag_t F;
-  F fa[NB], fb[NB];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    const bool in = q < nkb;
-    const long long kb = kb0 + (long long)q * kstep;
-    fa[q] = (in && am) ? load_frag(pa + kb * sa) : zero_frag<T>();
-    fb[q] = (in && bn) ? load_frag(pb + kb * sb) : zero_frag<T>();
-  }
   for (int j = 0; j < nkb; j += NB) {
-    F na[NB], nb[NB];
+    F fa[NB], fb[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const bool in = j + NB + q < nkb;
-      const long long kb = kb0 + (long long)(j + NB + q) * kstep;
-      na[q] = (in && am) ? load_frag(pa + kb * sa) : zero_frag<T>();
-      nb[q] = (in && bn) ? load_frag(pb + kb * sb) : zero_frag<T>();
+      const bool in = j + q < nkb;
+      const long long kb = kb0 + (long long)(j + q) * kstep;
+      fa[q] = (in && am) ? load_frag(pa + kb * sa) : zero_frag<T>();
+      fb[q] = (in && bn) ? load_frag(pb + kb * sb) : zero_frag<T>();
     }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) mma(acc, fa[q], fb[q]);
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      fa[q] = na[q];
-      fb[q] = nb[q];
-    }
+    MmaBlocks<T, NB>::run(acc, fa, fb);
   }
 }
 
+// k-blocks loaded per round (a short contraction is then a single round of loads)
 template <typename T> struct KNB { static constexpr int v = 4; };
-template <> struct KNB<bf16> { static constexpr int v = 8; };
+template <> struct KNB<bf16> { static constexpr int v = 16; };
 
 // ============================================================================
 // slab_fwd: T1 (P12 x n3) = Theta_kb^T (P12 x p3) X3f (p3 x n3), both k-blocked.
@@ -115,13 +138,21 @@ __device__ inline void fwd_tile(const FwdParams& P, int bx, int by) {
   const T* pb = B + (long long)i3 * 16 + 4 * g;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.n3 * 16;
   kblock_loop<T, KNB<T>::v>(acc, pa, pb, sa, sb, 0, 1, G.KB3, am, bn);
-  if (!bn) return;
-  // T1 slab-major: T1[i3][m] (the chain kernel reads one contiguous slab)
+  // T1 slab-major: T1[i3][m] (the chain kernel reads one contiguous slab).  The
+  // 32 x 32 workgroup tile is transposed through LDS so that each slab's 32 values
+  // of m are written by 32 consecutive lanes.
+  __shared__ T tt[32][33];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = mt * 16 + R::kidx(g, i);
-    if (row < G.P12) T1[(long long)i3 * G.P12 + row] = R::from_acc(acc[i]);
+  for (int i = 0; i < 4; ++i) tt[16 * (w >> 1) + r][16 * (w & 1) + R::kidx(g, i)] = R::from_acc(acc[i]);
+  __syncthreads();
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+    const int sl = 8 * pass + (tid >> 5), ml = tid & 31;
+    const int i3o = by * 32 + sl, mo = bx * 32 + ml;
+    if (i3o < G.n3 && mo < G.P12) T1[(long long)i3o * G.P12 + mo] = tt[sl][ml];
   }
+  __syncthreads();   // tt is reused by the next tile of a persistent caller
 }
 
 template <typename T>
@@ -461,26 +492,15 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
 // slabs that share a k-block of S2 are placed on one XCD, so that their 2-byte
 // stores into the same lines merge in that XCD's L2.
 // ============================================================================
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-typedef unsigned int u4v_t __attribute__((ext_vector_type(4)));
-
 constexpr int WAVE_FRAGS = 32;
 constexpr int WAVE_IMAGE_BYTES = WAVE_FRAGS * 64 * 16;
 __host__ __device__ inline int kw_index(int g, int u) { return u < 4 ? 4 * g + u : 12 + 4 * g + u; }
 __host__ __device__ inline bool wave_chain_ok(const Geom& G) { return G.N1T <= 8 && G.NJB <= 8 && G.PT <= 2; }
+bool chain_s2_kb4(int dt, int mode, const Geom& G) { return dt == DT_BF16 && mode == SM_FUSED && wave_chain_ok(G); }
 __host__ __device__ inline size_t wave_image_offset(const Geom& G) {
   return ((size_t)chain_layout(G, 2, 4).image_bytes + 255) & ~(size_t)255;
 }
 
-__device__ inline bf8v pack_acc2(const f4v& lo, const f4v& hi) {
-  bf8v v;
-  v[0] = (__bf16)lo[0]; v[1] = (__bf16)lo[1]; v[2] = (__bf16)lo[2]; v[3] = (__bf16)lo[3];
-  v[4] = (__bf16)hi[0]; v[5] = (__bf16)hi[1]; v[6] = (__bf16)hi[2]; v[7] = (__bf16)hi[3];
-  return v;
-}
-__device__ inline f4v mma32(const bf8v& a, const bf8v& b, const f4v& c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
 __device__ inline bf8v load_wfrag(const unsigned char* img, int frag, int lane) {
   return __builtin_bit_cast(bf8v, ((const u4v_t*)img)[frag * 64 + lane]);
 }
@@ -508,100 +528,142 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
   }
 }
 
+constexpr int WG_CW = 512;   // 8 waves: 4 slabs x 2 halves of the mode-2 column blocks
+
 template <bool HAS_V>
-__global__ __launch_bounds__(64) void k_slab_chain_w(SlabParams P) {
+__global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
   const Geom& G = P.G;
-  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
-  // XCD-aware slab order: workgroup b runs on XCD b % 8; k-block kb on XCD kb % 8
-  const int b = blockIdx.x, x = b & 7, j = b >> 3;
-  const int kb = x + 8 * (j >> 4);
-  const int i3 = 16 * kb + (j & 15);
-  if (i3 >= G.n3) return;   // whole-wave exit (one wave per workgroup, no barriers)
-  const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G);
+  const int lane = lane_id(), w = wave_id(), r = lane & 15, g = lane >> 4, tid = threadIdx.x;
+  const int sw = w & 3, half = w >> 2;   // slab within the workgroup, half of the column blocks
+  // XCD-aware order: workgroup b runs on XCD b % 8; the 32-slab group s runs on XCD s % 8
+  const int b = blockIdx.x, x = b & 7, jj = b >> 3;
+  const int q = 8 * (x + 8 * (jj >> 3)) + (jj & 7);   // this workgroup: slabs 4 q .. 4 q + 3
+  const int i3b = 4 * q;
+  if (i3b >= G.n3) return;   // whole workgroup
+  const int nsl = min(4, G.n3 - i3b);
+  const int i3 = i3b + sw;
+  const int P12 = G.P12;
   const int N1T = G.N1T, NJB = G.NJB;
-  // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
-  bf8v ft1[2];
+  const int jb0 = 4 * half;                       // this wave: column blocks jb0 .. jb0 + 3
+  const bool active = sw < nsl && jb0 < NJB;
+  __shared__ __align__(16) unsigned short t1s[4 * 1024];   // T1 of the 4 slabs (P12 <= 1024)
+  __shared__ __align__(16) float s2p[4][1024];               // S2 partial of the second half
+  __shared__ __align__(16) unsigned short s2x[1024 * 4];    // S2 of the 4 slabs, [m][slab]
+  // factor fragments: requested first, so that their latency overlaps the T1 staging
+  const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G);
+  bf8v fx2t[4], fx1a[8], fx1b[4][2], fx2a[2][2];
+  const bf8v zf = {};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) fx1a[t] = t < N1T ? load_wfrag(img, 8 + t, lane) : zf;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) fx2t[t] = jb0 + t < NJB ? load_wfrag(img, jb0 + t, lane) : zf;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) fx1b[qq][nt] = 2 * qq < N1T ? load_wfrag(img, 16 + 2 * qq + nt, lane) : zf;
+#pragma unroll
+  for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+      fx2a[mt][qq] = jb0 + 2 * qq < NJB ? load_wfrag(img, 24 + 4 * mt + 2 * half + qq, lane) : zf;
   {
-    const unsigned short* t1 = (const unsigned short*)P.T1 + (long long)i3 * G.P12;
+    // the 4 slabs are contiguous in slab-major T1: coalesced 8-byte loads (offset 8 q P12 bytes)
+    const unsigned short* src = (const unsigned short*)P.T1 + (long long)i3b * P12;
+    const int nel = nsl * P12, n8 = nel >> 2;
+    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+    for (int k = tid; k < n8; k += WG_CW) ((u16x4*)t1s)[k] = ((const u16x4*)src)[k];
+    for (int k = 4 * n8 + tid; k < nel; k += WG_CW) t1s[k] = src[k];
+  }
+  __syncthreads();
+  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+  f4v s2[2][2] = {{z4, z4}, {z4, z4}};
+  if (active) {
+    // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
+    bf8v ft1[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       const int i1 = 16 * mt + r;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i2 = kw_index(g, u);
-        const unsigned short h = (i1 < G.p1 && i2 < G.p2) ? t1[i1 + G.p1 * i2] : (unsigned short)0;
+        const unsigned short h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (unsigned short)0;
         ft1[mt][u] = __builtin_bit_cast(__bf16, h);
       }
     }
+    const float* V = (const float*)P.v_int;
+#pragma unroll
+    for (int jq = 0; jq < 2; ++jq) {
+      if (jb0 + 2 * jq >= NJB) break;
+      f4v s1[2][2] = {{z4, z4}, {z4, z4}};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jl = 2 * jq + h, jb = jb0 + jl;
+        if (jb >= NJB) break;
+        // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
+        const bf8v ft2 = pack_acc2(mma32(ft1[0], fx2t[jl], z4), mma32(ft1[1], fx2t[jl], z4));
+#pragma unroll
+        for (int uq = 0; uq < 4; ++uq) {
+          const int u0 = 2 * uq;
+          if (u0 >= N1T) break;
+          // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
+          f4v e0 = mma32(fx1a[u0], ft2, z4);
+          f4v e1 = u0 + 1 < N1T ? mma32(fx1a[u0 + 1], ft2, z4) : z4;
+          if (HAS_V) {
+            const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
+            const f4v v0 = *(const f4v*)(V + t0);
+            e0 *= v0;
+            if (u0 + 1 < N1T) {
+              const f4v v1 = *(const f4v*)(V + t0 + 256);
+              e1 *= v1;
+            }
+          }
+          // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
+          const bf8v fr = pack_acc2(e0, e1);
+          s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
+          s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
+        }
+      }
+      // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
+      }
+    }
   }
-  bf8v fx2t[8], fx1a[8], fx1b[4][2], fx2a[2][4];
-  const bf8v zf = {};
+  // S2 = first-half + second-half partials, through LDS ([m][slab]; zeros beyond n3)
+  if (half == 1) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    fx2t[t] = t < NJB ? load_wfrag(img, t, lane) : zf;
-    fx1a[t] = t < N1T ? load_wfrag(img, 8 + t, lane) : zf;
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+          if (i1 < G.p1 && i2 < G.p2) s2p[sw][i1 + G.p1 * i2] = s2[mt][nt][i];
+        }
   }
+  __syncthreads();
+  if (half == 0) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) fx1b[q][nt] = 2 * q < N1T ? load_wfrag(img, 16 + 2 * q + nt, lane) : zf;
+      for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) fx2a[mt][q] = 2 * q < NJB ? load_wfrag(img, 24 + 4 * mt + q, lane) : zf;
-  }
-  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-  f4v s2[2][2] = {{z4, z4}, {z4, z4}};
-  const float* V = (const float*)P.v_int;
-#pragma unroll
-  for (int jq = 0; jq < 4; ++jq) {
-    if (2 * jq >= NJB) break;
-    f4v s1[2][2] = {{z4, z4}, {z4, z4}};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int jb = 2 * jq + h;
-      if (jb >= NJB) break;
-      // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
-      const bf8v ft2 = pack_acc2(mma32(ft1[0], fx2t[jb], z4), mma32(ft1[1], fx2t[jb], z4));
-#pragma unroll
-      for (int uq = 0; uq < 4; ++uq) {
-        const int u0 = 2 * uq;
-        if (u0 >= N1T) break;
-        // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
-        f4v e0 = mma32(fx1a[u0], ft2, z4);
-        f4v e1 = u0 + 1 < N1T ? mma32(fx1a[u0 + 1], ft2, z4) : z4;
-        if (HAS_V) {
-          const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
-          const f4v v0 = *(const f4v*)(V + t0);
-          e0 *= v0;
-          if (u0 + 1 < N1T) {
-            const f4v v1 = *(const f4v*)(V + t0 + 256);
-            e1 *= v1;
+        for (int i = 0; i < 4; ++i) {
+          const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+          if (i1 < G.p1 && i2 < G.p2) {
+            const int m = i1 + G.p1 * i2;
+            s2x[m * 4 + sw] = f32_to_bf16(s2[mt][nt][i] + s2p[sw][m]);
           }
         }
-        // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
-        const bf8v fr = pack_acc2(e0, e1);
-        s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
-        s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
-      }
-    }
-    // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
-    }
   }
-  // S2 k-blocked (K = n3, C = P12): elem (i3, m) at ((i3 / 16) P12 + m) 16 + (i3 % 16)
-  unsigned short* S2 = (unsigned short*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<bf16>(i3 & 15);
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
-        if (i1 < G.p1 && i2 < G.p2) S2[(long long)(i1 + G.p1 * i2) * 16] = f32_to_bf16(s2[mt][nt][i]);
-      }
+  __syncthreads();
+  // ... to S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4, one 8-byte store per m
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  u32x2* dst = (u32x2*)P.S2 + (long long)q * P12;
+  for (int m = tid; m < P12; m += WG_CW) dst[m] = ((const u32x2*)s2x)[m];
 }
 
 // ============================================================================
@@ -628,23 +690,35 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
   const int k3 = bn * 16 + r;   // B column (p3 index)
   const bool am = m < G.P12, bk = k3 < G.p3;
   typename R::accv_t acc = R::zero();
-  const T* pa = S2 + (long long)m * 16 + 4 * g;
+  // S2 k-blocked by 16 or by 4 (a 16-block of either spans the same 16 P12 elements)
+  const T* pa = P.s2_kb4 ? S2 + ((long long)g * G.P12 + m) * 4 : S2 + (long long)m * 16 + 4 * g;
   const T* pb = X3 + (long long)k3 * 16 + 4 * g;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.p3 * 16;
   const int nkb = w < G.KBN3 ? (G.KBN3 - w + (WG / 64) - 1) / (WG / 64) : 0;
+  // the epilogue's operands, loaded ahead of the contraction (one tile element per thread)
+  const int t = threadIdx.x;
+  const int row = bm * 16 + (t & 15), col = bn * 16 + (t >> 4);
+  const bool valid = row < G.P12 && col < G.p3;
+  const long long j = (long long)row + (long long)G.P12 * col;
+  double e_gref = 0.0, e_x = 0.0, e_xp = 0.0, e_gp = 0.0, e_w = 1.0, e_th = 0.0, e_y = 0.0, e_gy = 0.0;
+  if (valid) {
+    if (P.pen_w && EPI != EPI_STORE) e_w = P.pen_w[j];
+    if (EPI == EPI_GRAD && P.theta) e_th = P.theta[j];
+    if (EPI == EPI_PROX || EPI == EPI_PROX_BT) {
+      e_gref = P.gref[j]; e_x = P.x[j]; e_xp = P.xp[j]; e_gp = P.gp[j]; e_th = P.theta_ref[j];
+    }
+    if (EPI == EPI_PROX_BT) { e_y = P.yprev[j]; e_gy = P.gyprev[j]; }
+  }
   kblock_loop<T, KNB<T>::v>(acc, pa, pb, sa, sb, w, WG / 64, nkb, am, bk);
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[w][R::kidx(g, i) * 16 + r] = acc[i];
   __syncthreads();
 
   // one thread per tile element: row (P12 index) = t % 16, column (p3 index) = t / 16
-  const int t = threadIdx.x;
-  const int row = bm * 16 + (t & 15), col = bn * 16 + (t >> 4);
   const int qe = (t & 15) * 16 + (t >> 4);
   const double a = (double)(red[0][qe] + red[1][qe] + red[2][qe] + red[3][qe]);
   double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0, red_dg = 0.0, red_dd = 0.0;
-  if (row < G.P12 && col < G.p3) {
-    const long long j = (long long)row + (long long)G.P12 * col;
+  if (valid) {
     if (EPI == EPI_STORE) {
       double s = P.scale;
       if (P.gscale_dev) s *= *P.gscale_dev;
@@ -652,10 +726,10 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
     } else if (EPI == EPI_GRAD) {
       const double gv = P.scale * a;
       P.gout[j] = gv;
-      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      const double wm = e_w;
       red_lmax = fabs(gv) / wm;
       if (P.theta) {
-        const double th = P.theta[j];
+        const double th = e_th;
         const double lw = P.lambda * wm;
         red_kkt = th != 0.0 ? fabs(gv + copysign(lw, th)) : fmax(fabs(gv) - lw, 0.0);
         red_pen = wm * fabs(th);
@@ -667,14 +741,14 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double lam = P.dparams[0], delta = P.dparams[1], l_iter = P.dparams[2];
       const double om = (l_iter - 1.0) / (l_iter + 2.0);
       const double incg = P.scale * a;
-      const double gx = P.gref[j] + incg;
-      const double x = P.x[j], xp = P.xp[j], gp = P.gp[j];
-      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      const double gx = e_gref + incg;
+      const double x = e_x, xp = e_xp, gp = e_gp;
+      const double wm = e_w;
       const double lw = lam * wm;
       red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
       red_noise = fabs(incg);
-      const double dv = x - P.yprev[j];
-      red_dg = dv * (gx - P.gyprev[j]);
+      const double dv = x - e_y;
+      red_dg = dv * (gx - e_gy);
       red_dd = dv * dv;
       const double gy = gx + om * (gx - gp);
       const double yv = x + om * (x - xp);
@@ -684,7 +758,7 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       P.gp_out[j] = gx;
       P.y_out[j] = yv;
       P.gy_out[j] = gy;
-      const double dinc = xn - P.theta_ref[j];
+      const double dinc = xn - e_th;
       red_inc = fabs(dinc);
       ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
           R::from_acc((typename R::acc_t)dinc);
@@ -694,9 +768,9 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const double om = (l_iter - 1.0) / (l_iter + 2.0);
       const double incg = P.scale * a;               // G(V H(x - theta_ref)) / n
-      const double gx = P.gref[j] + incg;            // grad h(x^l)
-      const double x = P.x[j], xp = P.xp[j], gp = P.gp[j];
-      const double wm = P.pen_w ? P.pen_w[j] : 1.0;
+      const double gx = e_gref + incg;               // grad h(x^l)
+      const double x = e_x, xp = e_xp, gp = e_gp;
+      const double wm = e_w;
       const double lw = lam * wm;
       red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
       red_noise = fabs(incg);
@@ -706,7 +780,7 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       P.xp[j] = x;
       P.x[j] = xn;
       P.gp[j] = gx;
-      const double dinc = xn - P.theta_ref[j];
+      const double dinc = xn - e_th;
       red_inc = fabs(dinc);
       ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
           R::from_acc((typename R::acc_t)dinc);
@@ -990,10 +1064,9 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
     }
     return hipGetLastError();
   }
-  if (dt == DT_BF16 && mode == SM_FUSED && wave_chain_ok(P.G)) {
-    // one wave per slab; 16 workgroups per k-block of S2, rounded up to 8 XCDs
-    const int kbg = (P.G.KBN3 + 7) / 8;
-    dim3 wgrid(8 * 16 * kbg), wblk(64);
+  if (chain_s2_kb4(dt, mode, P.G)) {
+    // one wave per slab, 4 slabs per workgroup, 32-slab groups spread over 8 XCDs
+    dim3 wgrid(64 * ((P.G.n3 + 255) / 256)), wblk(WG_CW);
     if (P.v_int) hipLaunchKernelGGL(k_slab_chain_w<true>, wgrid, wblk, 0, s, P);
     else hipLaunchKernelGGL(k_slab_chain_w<false>, wgrid, wblk, 0, s, P);
     return hipGetLastError();
