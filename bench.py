@@ -87,6 +87,31 @@ def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slab_chain_gaussian_100x100x1000_bf16_hbm_traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1510_03298_amd", "csrc", "slab.hip")
+    with open(src, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_per_launch(kernel, dtype):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or None when
+    that summary was taken on a different kernel source or dtype."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != kernel_source_hash() or rec.get("dtype") != dtype:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
 def copy_calibration(torch, dev, mib):
     """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
     counter readings give the scale from counter units to bytes."""
@@ -235,11 +260,12 @@ def main():
     achieved = chain / avg_chain if samples else None
     roofline = {
         "kernel": "slab_chain (fused modes 1-2 forward + adjoint of one inner PG iteration)",
-        "timing": "HIP events around sampled eager launches on the fit's stream (event-pair overhead included)",
+        "timing": ("HIP events on the fit's stream around 8 back-to-back re-launches of the kernel on the "
+                   "sampled iteration's own input, one sample per profile_every inner iterations"),
         "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
         "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
         "frac": (achieved / PEAKS[args.dtype]) if achieved else None,
-        "traffic": None,
+        "traffic": traffic_per_launch("slab_chain", args.dtype),
         "flops_per_launch": chain, "launches_sampled": samples,
         "avg_launch_us": avg_chain * 1e6,
         "algorithmic_bytes_per_launch": chain_bytes(n, p, dtb),

@@ -122,8 +122,10 @@ typedef struct {
   int check_every;        /* inner iterations between host convergence checks (>= 1) */
   const double* theta0;   /* device, FP64 p-array warm start for the first lambda, or NULL */
   void* stream;           /* hipStream_t (NULL = default stream)                    */
-  int profile_every;      /* > 0: time the fused slab kernel of one inner iteration in
-                             every profile_every with HIP events (0 = off)          */
+  int profile_every;      /* > 0: in one inner iteration in every profile_every, time the
+                             iteration, then the fused slab kernel re-run 8 times back to
+                             back on that iteration's own input, with HIP events on the
+                             fit's stream (0 = off; the re-runs rewrite identical values) */
   int graph_mode;         /* 0: replay each block of check_every inner iterations as a
                              captured HIP graph (default); 1: plain stream launches */
 } glam_options;
@@ -139,7 +141,7 @@ typedef struct {
   int n_done;             /* out: number of models fitted (< nlambda on early exit) */
   double lambda_max;      /* out: lambda_max (Sec. 6.4)                              */
   double seconds;         /* out: wall time of the call                              */
-  double chain_ms;        /* out: summed duration of the sampled fused slab kernels  */
+  double chain_ms;        /* out: summed per-launch duration of the sampled fused slab kernels */
   int chain_samples;      /* out: number of sampled launches (profile_every > 0)     */
   double iter_ms;         /* out: summed duration of the sampled whole inner iterations */
   long long inner_total;  /* out: inner iterations over the whole path               */

@@ -43,24 +43,52 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
 // ============================================================================
 // small kernels
 // ============================================================================
-__global__ void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval, int ops_bits, double scale,
-                         double* __restrict__ out) {
-  __shared__ double sm[WG];
-  for (int v = 0; v < nval; ++v) {
-    const int op = (ops_bits >> v) & 1;
-    double a = op ? -INFINITY : 0.0;
+// out[v] = scale * sum_b part[b][v] (ops bit v = 0) or max_b part[b][v] (bit v = 1), v < nval <= 32,
+// 8 values per pass with a fixed summation order.  With hout != NULL the values are
+// also published to host memory (fine-grained, mapped), followed by an incremented
+// sequence number *hseq (kept in *seq_dev), so that the host can wait on it without a
+// copy.
+constexpr int RED_MAXV = 8;
+__global__ void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval, unsigned ops_bits,
+                         double scale, double* __restrict__ out, double* hout, unsigned* seq_dev, unsigned* hseq) {
+  __shared__ double sm[WG / 64][RED_MAXV];
+  for (int v0 = 0; v0 < nval; v0 += RED_MAXV) {
+    double a[RED_MAXV];
+#pragma unroll
+    for (int v = 0; v < RED_MAXV; ++v) a[v] = ((ops_bits >> (v0 + v)) & 1u) ? -INFINITY : 0.0;
     for (int b = threadIdx.x; b < nblk; b += WG) {
-      const double x = part[(long long)b * stride + v];
-      a = op ? fmax(a, x) : a + x;
+#pragma unroll
+      for (int v = 0; v < RED_MAXV; ++v) {
+        if (v0 + v < nval) {
+          const double x = part[(long long)b * stride + v0 + v];
+          a[v] = ((ops_bits >> (v0 + v)) & 1u) ? fmax(a[v], x) : a[v] + x;
+        }
+      }
     }
-    sm[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) sm[threadIdx.x] = op ? fmax(sm[threadIdx.x], sm[threadIdx.x + s]) : sm[threadIdx.x] + sm[threadIdx.x + s];
-      __syncthreads();
+#pragma unroll
+    for (int v = 0; v < RED_MAXV; ++v) a[v] = ((ops_bits >> (v0 + v)) & 1u) ? warp_max(a[v]) : warp_sum(a[v]);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int v = 0; v < RED_MAXV; ++v) sm[wave_id()][v] = a[v];
     }
-    if (threadIdx.x == 0) out[v] = op ? sm[0] : scale * sm[0];
     __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 0; v < RED_MAXV && v0 + v < nval; ++v) {
+        const unsigned op = (ops_bits >> (v0 + v)) & 1u;
+        double r = sm[0][v];
+        for (int w = 1; w < WG / 64; ++w) r = op ? fmax(r, sm[w][v]) : r + sm[w][v];
+        r = op ? r : scale * r;
+        out[v0 + v] = r;
+        if (hout) __hip_atomic_store(&hout[v0 + v], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    __syncthreads();
+  }
+  if (hout && threadIdx.x == 0) {
+    const unsigned s = *seq_dev + 1u;
+    *seq_dev = s;
+    __threadfence_system();
+    __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -283,9 +311,21 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
                                  double* out, hipStream_t s) {
-  int bits = 0;
-  for (int v = 0; v < nval; ++v) bits |= (ops[v] & 1) << v;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, stride, nval, bits, scale, out);
+  unsigned bits = 0;
+  for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
+  if (nval > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, stride, nval, bits, scale, out,
+                     (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
+                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s) {
+  unsigned bits = 0;
+  for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
+  if (nval > 32 || !hout || !seq_dev || !hseq) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, nval, nval, bits, scale, out, hout, seq_dev,
+                     hseq);
   return hipGetLastError();
 }
 

@@ -101,6 +101,12 @@ struct Fit {
   double* part;            // partial sums
   double* red;             // reduced values (device)
   double* hred = nullptr;  // reduced values (pinned host)
+  double* hpub = nullptr;  // published check values (fine-grained pinned host, mapped)
+  double* hpub_dev = nullptr;
+  unsigned* hseq = nullptr;       // published sequence number (host view) ...
+  unsigned* hseq_dev = nullptr;   // ... and its device address
+  unsigned* seq_dev = nullptr;    // device-side counter of published checks
+  unsigned seq_expect = 0;
   double sprod;            // prod_j rho(X_j^T X_j)
   std::string err;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
@@ -135,6 +141,7 @@ struct Fit {
     if (sync_ev) (void)hipEventDestroy(sync_ev);
     if (hparams) (void)hipHostFree(hparams);
     if (hred) (void)hipHostFree(hred);
+    if (hpub) (void)hipHostFree(hpub);
     if (own_stream && s) (void)hipStreamDestroy(s);
   }
 };
@@ -190,6 +197,8 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
   return GLAM_OK;
 }
 
+constexpr int kSampleReps = 8;   // back-to-back launches of the fused slab kernel per timing sample
+
 // One inner PG iteration (Sec. 3.2) in the chain dtype.
 static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool sample) {
   const Geom& G = F.G;
@@ -199,9 +208,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   FCHK(launch_slab_fwd(F.dt, fw, F.s));
   SlabParams sp{};
   sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
-  if (sample) FCHK(hipEventRecord(F.ev[1], F.s));
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
-  if (sample) FCHK(hipEventRecord(F.ev[2], F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
   ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
@@ -209,6 +216,12 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
   if (sample) {
+    // the whole iteration between ev[0] and ev[1]; then the fused slab kernel alone,
+    // re-run kSampleReps times back to back on this iteration's own T1 (it rewrites
+    // the same S2, which only the next iteration's own slab kernel overwrites)
+    FCHK(hipEventRecord(F.ev[1], F.s));
+    FCHK(hipEventRecord(F.ev[2], F.s));
+    for (int r = 0; r < kSampleReps; ++r) FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
     FCHK(hipEventRecord(F.ev[3], F.s));
     F.pending = true;
   }
@@ -219,10 +232,11 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
 // after the stream synchronisation of the convergence check).
 static int collect_sample(Fit& F) {
   if (!F.pending) return GLAM_OK;
+  FCHK(hipEventSynchronize(F.ev[3]));
   float a = 0.f, b = 0.f;
-  FCHK(hipEventElapsedTime(&a, F.ev[1], F.ev[2]));
-  FCHK(hipEventElapsedTime(&b, F.ev[0], F.ev[3]));
-  F.chain_ms += a;
+  FCHK(hipEventElapsedTime(&a, F.ev[2], F.ev[3]));
+  FCHK(hipEventElapsedTime(&b, F.ev[0], F.ev[1]));
+  F.chain_ms += a / kSampleReps;
   F.iter_ms += b;
   F.samples += 1;
   F.pending = false;
@@ -238,7 +252,31 @@ static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
     if (r) return r;
   }
   const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-  FCHK(launch_reduce(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.s));
+  FCHK(launch_reduce_publish(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.hpub_dev, F.seq_dev, F.hseq_dev, F.s));
+  return GLAM_OK;
+}
+
+// Wait for the check values of the block just launched: the last kernel of the block
+// writes them to mapped host memory, then the next sequence number.  The host spins on
+// that number (no copy, no stream synchronisation) and queries the stream for errors.
+static int wait_published(Fit& F, double* vals, int nval) {
+  const unsigned want = ++F.seq_expect;
+  for (long long spin = 0;; ++spin) {
+    if (__atomic_load_n(F.hseq, __ATOMIC_ACQUIRE) == want) break;
+    if ((spin & 255) == 255) {
+      const hipError_t e = hipStreamQuery(F.s);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(F.hseq, __ATOMIC_ACQUIRE) == want) break;
+        F.err = "check values were not published";
+        return GLAM_EDEVICE;
+      }
+      if (e != hipErrorNotReady) {
+        F.err = std::string("inner block: ") + hipGetErrorString(e);
+        return GLAM_EDEVICE;
+      }
+    }
+  }
+  for (int v = 0; v < nval; ++v) vals[v] = ((const volatile double*)F.hpub)[v];
   return GLAM_OK;
 }
 
@@ -425,10 +463,24 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     for (auto& e : F.ev)
       if (hipEventCreate(&e) != hipSuccess) { F.err = "hipEventCreate failed"; return GLAM_EDEVICE; }
   if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&F.hparams, 4 * sizeof(double)) != hipSuccess) {
+      hipHostMalloc((void**)&F.hparams, 4 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&F.hpub, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     F.err = "pinned host allocation failed";
     return GLAM_ENOMEM;
   }
+  F.hseq = (unsigned*)(F.hpub + 8);
+  *F.hseq = 0u;
+  if (hipHostGetDevicePointer((void**)&F.hpub_dev, F.hpub, 0) != hipSuccess) {
+    F.err = "hipHostGetDevicePointer failed";
+    return GLAM_EDEVICE;
+  }
+  F.hseq_dev = (unsigned*)(F.hpub_dev + 8);
+  F.seq_dev = (unsigned*)A(256);
+  if (!F.seq_dev || hipMemsetAsync(F.seq_dev, 0, 256, F.s) != hipSuccess) {
+    F.err = "device allocation failed";
+    return GLAM_ENOMEM;
+  }
+  F.seq_expect = 0;
 
   // ---- input checks (device) ----
   {
@@ -609,12 +661,12 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
         if (opt->graph_mode == 0 && m == check_every && !sample) RCHK(inner_block_graph(F, m, &nb));
         else RCHK(inner_block_eager(F, m, sample, &nb));
         it += m;
-        PCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
-        PCHK(hipStreamSynchronize(F.s));
+        double chk[2];
+        RCHK(wait_published(F, chk, 2));
         RCHK(collect_sample(F));
-        kin = F.hred[0] / lam_scale;
+        kin = chk[0] / lam_scale;
         // rounding floor of the low-precision chain output (a lower bound of its error)
-        noise = 4.0 * kEps[F.dt] * F.hred[1] / lam_scale;
+        noise = 4.0 * kEps[F.dt] * chk[1] / lam_scale;
         best = std::min(best, kin);
         if (it - window_start >= 20 * check_every) {
           // stalled: no 2x progress over the window -> leave for an FP64 re-anchor

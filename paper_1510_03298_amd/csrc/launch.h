@@ -167,6 +167,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // summation order is fixed, so results are reproducible run to run.
 hipError_t launch_reduce(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
                          hipStream_t s);
+// the same, also published to mapped host memory hout[0..nval) followed by the sequence
+// number *hseq = ++*seq_dev (device counter), for a host wait without a copy (nval <= 8)
+hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
+                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s);
 // same with partials[b * stride + v], v < nval <= stride
 hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
                                  double* out, hipStream_t s);
