@@ -145,7 +145,7 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
   F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1; F.iter = nullptr;
   HIPCHK(launch_slab_fwd(dtype, F, s));
   SlabParams S{};
-  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s, chain_image_need(dtype, SM_FWD_STD, G)));
   S.G = G; S.img = ws + W.img; S.T1 = ws + W.t1; S.eta_out = Eta;
   HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, nullptr, s));
   return GLAM_OK;
@@ -166,7 +166,7 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
   HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
-  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s, chain_image_need(dtype, SM_ADJ_STD, G)));
   S.G = G; S.img = ws + W.img; S.S2 = ws + W.s2; S.u_in = U;
   HIPCHK(launch_slab_chain(dtype, SM_ADJ_STD, S, nullptr, s));
   AdjParams A{};
@@ -187,7 +187,8 @@ static int nll_prepare(const Geom& G, const void* const* X, const void* beta, in
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, beta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
-  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s));
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s,
+                                 chain_image_need(dtype, SM_NLL_FWD, G) | chain_image_need(dtype, SM_NLL_BWD, G)));
   FwdParams F{};
   F.G = G; F.theta = ws + W.inc; F.X3f = ws + W.x3f; F.T1 = ws + W.t1;
   HIPCHK(launch_slab_fwd(dtype, F, s));
@@ -241,6 +242,7 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
   HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, nullptr, s));
   AdjParams A{};
   A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
+  A.s2_kb4 = chain_s2_kb4(dtype, SM_NLL_BWD, G);
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
   return GLAM_OK;
 }

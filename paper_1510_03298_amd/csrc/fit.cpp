@@ -112,6 +112,7 @@ struct Fit {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
   hipStream_t us = nullptr;        // caller's stream
   bool own_stream = false;
+  bool batched = false;            // set up for glam_fit_batched (its persistent step uses the LDS image)
   hipEvent_t sync_ev = nullptr;
   double* dparams = nullptr;       // device {lambda, delta}
   double* hparams = nullptr;       // pinned host staging of dparams
@@ -498,8 +499,11 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   // ---- setup: tiled data, chain copies of the factors, spectral radii ----
   FCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
   FCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
-  FCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s));
-  if (F.dt != DT_F64) FCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s));
+  FCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s, PACK_LDS));
+  // the inner-loop chain (and, in a batched fit, the persistent step's per-slab chain)
+  if (F.dt != DT_F64)
+    FCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s,
+                                 chain_image_need(F.dt, SM_FUSED, G) | (F.batched ? PACK_LDS : 0)));
   // packed mode-3 factor (FP64 and chain dtype); zero the padded intermediates once
   FCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.p3, G.n3, G.n3, 1, F.X3fd, F.s));
   FCHK(launch_pack(DT_F64, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ad, F.s));
@@ -780,6 +784,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
     F.dt = dt;
     F.s = s;
     F.own_stream = false;
+    F.batched = true;
     const int r = fit_setup(F, &probs[i], false, false);
     if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
   }

@@ -151,8 +151,13 @@ hipError_t launch_slab_adj(int dt, int epi, const AdjParams& P, int* nblk_out, h
 size_t slab_chain_lds_bytes(int dt, const Geom& G);
 // LDS image of the mode-1 / mode-2 factors (X1, X2: n_j x p_j column-major, FP64 or chain dtype)
 size_t chain_image_bytes(int dt, const Geom& G);
+// need: PACK_LDS (the workgroup-per-slab kernel's LDS image) and / or PACK_WAVE (the
+// register fragments of the one-wave-per-slab BF16 kernel); chain_image_need(dt, mode, G)
+// gives the part that launch_slab_chain reads for a mode
+enum { PACK_LDS = 1, PACK_WAVE = 2 };
+int chain_image_need(int dt, int mode, const Geom& G);
 hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void* X1, const void* X2, void* img,
-                                   hipStream_t s);
+                                   hipStream_t s, int need);
 int slab_adj_blocks(const Geom& G);
 int slab_chain_blocks(int dt, const Geom& G);
 

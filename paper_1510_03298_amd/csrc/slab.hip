@@ -496,7 +496,10 @@ constexpr int WAVE_FRAGS = 32;
 constexpr int WAVE_IMAGE_BYTES = WAVE_FRAGS * 64 * 16;
 __host__ __device__ inline int kw_index(int g, int u) { return u < 4 ? 4 * g + u : 12 + 4 * g + u; }
 __host__ __device__ inline bool wave_chain_ok(const Geom& G) { return G.N1T <= 8 && G.NJB <= 8 && G.PT <= 2; }
-bool chain_s2_kb4(int dt, int mode, const Geom& G) { return dt == DT_BF16 && mode == SM_FUSED && wave_chain_ok(G); }
+static bool wave_chain_used(int dt, int mode, const Geom& G) {
+  return dt == DT_BF16 && (mode == SM_FUSED || mode == SM_NLL_FWD || mode == SM_NLL_BWD) && wave_chain_ok(G);
+}
+bool chain_s2_kb4(int dt, int mode, const Geom& G) { return wave_chain_used(dt, mode, G) && mode != SM_NLL_FWD; }
 __host__ __device__ inline size_t wave_image_offset(const Geom& G) {
   return ((size_t)chain_layout(G, 2, 4).image_bytes + 255) & ~(size_t)255;
 }
@@ -528,55 +531,66 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
   }
 }
 
-constexpr int WG_CW = 512;   // 8 waves: 4 slabs x 2 halves of the mode-2 column blocks
-
-template <bool HAS_V>
-__global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
+// MODE: SM_FUSED (R = eta .* V, V optional), SM_NLL_FWD (partial sums of exp(eta) - y eta
+// only), SM_NLL_BWD (the same sums and R = exp(eta) - y).  A workgroup holds SPW
+// consecutive slabs (4 or 1) and NPART waves per slab (2 or 4), each wave taking 8 / NPART
+// of the (at most 8) mode-2 column blocks; the waves' S2 partials are summed in LDS.
+// Partial NLL sums per workgroup in partials[slab group][2].
+template <int MODE, bool HAS_V, int SPW, int NPART>
+__global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
+  constexpr bool ADJ = MODE != SM_NLL_FWD;
+  constexpr bool NLL = MODE == SM_NLL_FWD || MODE == SM_NLL_BWD;
+  constexpr int NT = 64 * SPW * NPART;   // threads per workgroup
+  constexpr int JPW = 8 / NPART;         // column blocks per wave (4 or 2)
+  constexpr int QPW = JPW / 2;           // column-block pairs per wave
   const Geom& G = P.G;
   const int lane = lane_id(), w = wave_id(), r = lane & 15, g = lane >> 4, tid = threadIdx.x;
-  const int sw = w & 3, half = w >> 2;   // slab within the workgroup, half of the column blocks
-  // XCD-aware order: workgroup b runs on XCD b % 8; the 32-slab group s runs on XCD s % 8
+  const int sw = w % SPW, part = w / SPW;   // slab within the workgroup, part of the column blocks
+  // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
+  // the 8-byte chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
   const int b = blockIdx.x, x = b & 7, jj = b >> 3;
-  const int q = 8 * (x + 8 * (jj >> 3)) + (jj & 7);   // this workgroup: slabs 4 q .. 4 q + 3
-  const int i3b = 4 * q;
+  const int grp = SPW == 4 ? 8 * (x + 8 * (jj >> 3)) + (jj & 7) : 4 * (x + 8 * (jj >> 2)) + (jj & 3);
+  const int i3b = SPW * grp;
   if (i3b >= G.n3) return;   // whole workgroup
-  const int nsl = min(4, G.n3 - i3b);
+  const int nsl = min(SPW, G.n3 - i3b);
   const int i3 = i3b + sw;
   const int P12 = G.P12;
   const int N1T = G.N1T, NJB = G.NJB;
-  const int jb0 = 4 * half;                       // this wave: column blocks jb0 .. jb0 + 3
+  const int jb0 = JPW * part;                     // this wave: column blocks jb0 .. jb0 + JPW - 1
   const bool active = sw < nsl && jb0 < NJB;
-  __shared__ __align__(16) unsigned short t1s[4 * 1024];   // T1 of the 4 slabs (P12 <= 1024)
-  __shared__ __align__(16) float s2p[4][1024];               // S2 partial of the second half
-  __shared__ __align__(16) unsigned short s2x[1024 * 4];    // S2 of the 4 slabs, [m][slab]
+  __shared__ __align__(16) unsigned short t1s[SPW * 1024];            // T1 of the slabs (P12 <= 1024)
+  __shared__ __align__(16) float s2p[NPART - 1][SPW][1024];           // S2 partials of parts 1..
+  __shared__ __align__(16) unsigned short s2x[SPW == 4 ? 4096 : 1];   // S2 of 4 slabs, [m][slab]
   // factor fragments: requested first, so that their latency overlaps the T1 staging
   const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G);
-  bf8v fx2t[4], fx1a[8], fx1b[4][2], fx2a[2][2];
+  bf8v fx2t[JPW], fx1a[8], fx1b[4][2], fx2a[2][QPW];
   const bf8v zf = {};
 #pragma unroll
   for (int t = 0; t < 8; ++t) fx1a[t] = t < N1T ? load_wfrag(img, 8 + t, lane) : zf;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) fx2t[t] = jb0 + t < NJB ? load_wfrag(img, jb0 + t, lane) : zf;
+  for (int t = 0; t < JPW; ++t) fx2t[t] = jb0 + t < NJB ? load_wfrag(img, jb0 + t, lane) : zf;
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) fx1b[qq][nt] = 2 * qq < N1T ? load_wfrag(img, 16 + 2 * qq + nt, lane) : zf;
 #pragma unroll
-  for (int qq = 0; qq < 2; ++qq)
+  for (int qq = 0; qq < QPW; ++qq)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
-      fx2a[mt][qq] = jb0 + 2 * qq < NJB ? load_wfrag(img, 24 + 4 * mt + 2 * half + qq, lane) : zf;
+      fx2a[mt][qq] = jb0 + 2 * qq < NJB ? load_wfrag(img, 24 + 4 * mt + QPW * part + qq, lane) : zf;
   {
-    // the 4 slabs are contiguous in slab-major T1: coalesced 8-byte loads (offset 8 q P12 bytes)
+    // the slabs are contiguous in slab-major T1: coalesced 8-byte loads when aligned
     const unsigned short* src = (const unsigned short*)P.T1 + (long long)i3b * P12;
-    const int nel = nsl * P12, n8 = nel >> 2;
+    const int nel = nsl * P12;
     typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-    for (int k = tid; k < n8; k += WG_CW) ((u16x4*)t1s)[k] = ((const u16x4*)src)[k];
-    for (int k = 4 * n8 + tid; k < nel; k += WG_CW) t1s[k] = src[k];
+    const int n8 = (((unsigned long long)src & 7) == 0) ? (nel >> 2) : 0;
+    for (int k = tid; k < n8; k += NT) ((u16x4*)t1s)[k] = ((const u16x4*)src)[k];
+    for (int k = 4 * n8 + tid; k < nel; k += NT) t1s[k] = src[k];
   }
   __syncthreads();
   const f4v z4 = {0.f, 0.f, 0.f, 0.f};
   f4v s2[2][2] = {{z4, z4}, {z4, z4}};
+  double s_nll = 0.0;
   if (active) {
     // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
     bf8v ft1[2];
@@ -592,7 +606,7 @@ __global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
     }
     const float* V = (const float*)P.v_int;
 #pragma unroll
-    for (int jq = 0; jq < 2; ++jq) {
+    for (int jq = 0; jq < QPW; ++jq) {
       if (jb0 + 2 * jq >= NJB) break;
       f4v s1[2][2] = {{z4, z4}, {z4, z4}};
 #pragma unroll
@@ -617,23 +631,62 @@ __global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
               e1 *= v1;
             }
           }
-          // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
-          const bf8v fr = pack_acc2(e0, e1);
-          s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
-          s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
+          if (NLL) {
+            // Poisson NLL terms exp(eta) - y eta (FP64), R = exp(eta) - y
+            const int i2 = 16 * jb + r;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+              f4v& e = hh ? e1 : e0;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int i1 = 16 * (u0 + hh) + 4 * g + i;
+                float rv = 0.f;
+                if (i1 < G.n1 && i2 < G.n2) {
+                  const double eta = (double)e[i];
+                  const double y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
+                  // (exp in FP32: eta carries the BF16 chain's error, far above FP32 rounding)
+                  const double ex = (double)expf(e[i]);
+                  s_nll += ex - y * eta;
+                  rv = (float)(ex - y);
+                }
+                e[i] = rv;
+              }
+            }
+          }
+          if (ADJ) {
+            // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
+            const bf8v fr = pack_acc2(e0, e1);
+            s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
+            s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
+          }
         }
       }
       // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
+      if (ADJ) {
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
+        for (int nt = 0; nt < 2; ++nt) {
+          const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
+          for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
+        }
       }
     }
   }
-  // S2 = first-half + second-half partials, through LDS ([m][slab]; zeros beyond n3)
-  if (half == 1) {
+  if (NLL) {
+    __shared__ double sred[NT / 64];
+    const double v = warp_sum(s_nll);
+    if (lane == 0) sred[w] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0;
+      for (int k = 0; k < NT / 64; ++k) a += sred[k];
+      P.partials[2 * grp] = a;
+      P.partials[2 * grp + 1] = 0.0;
+    }
+  }
+  if (!ADJ) return;
+  // S2 = sum of the parts' partials, through LDS (zeros for slabs beyond n3)
+  if (part > 0) {
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -641,11 +694,13 @@ __global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
-          if (i1 < G.p1 && i2 < G.p2) s2p[sw][i1 + G.p1 * i2] = s2[mt][nt][i];
+          if (i1 < G.p1 && i2 < G.p2) s2p[part - 1][sw][i1 + G.p1 * i2] = s2[mt][nt][i];
         }
   }
   __syncthreads();
-  if (half == 0) {
+  // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
+  if (part == 0) {
+    unsigned short* S2 = (unsigned short*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -655,15 +710,21 @@ __global__ __launch_bounds__(WG_CW) void k_slab_chain_w(SlabParams P) {
           const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
           if (i1 < G.p1 && i2 < G.p2) {
             const int m = i1 + G.p1 * i2;
-            s2x[m * 4 + sw] = f32_to_bf16(s2[mt][nt][i] + s2p[sw][m]);
+            float v = s2[mt][nt][i];
+#pragma unroll
+            for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
+            if (SPW == 4) s2x[m * 4 + sw] = f32_to_bf16(v);
+            else if (sw < nsl) S2[(long long)m * 4] = f32_to_bf16(v);
           }
         }
   }
-  __syncthreads();
-  // ... to S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4, one 8-byte store per m
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  u32x2* dst = (u32x2*)P.S2 + (long long)q * P12;
-  for (int m = tid; m < P12; m += WG_CW) dst[m] = ((const u32x2*)s2x)[m];
+  if (SPW == 4) {
+    // the 4 slabs' values of each m form one 8-byte chunk
+    __syncthreads();
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    u32x2* dst = (u32x2*)P.S2 + (long long)grp * P12;
+    for (int m = tid; m < P12; m += NT) dst[m] = ((const u32x2*)s2x)[m];
+  }
 }
 
 // ============================================================================
@@ -961,10 +1022,15 @@ size_t chain_image_bytes(int dt, const Geom& G) {
   return (size_t)chain_layout(G, (int)dt_size(dt), dt == DT_F64 ? 8 : 4).image_bytes;
 }
 
+int chain_image_need(int dt, int mode, const Geom& G) { return wave_chain_used(dt, mode, G) ? PACK_WAVE : PACK_LDS; }
+
 hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void* X1, const void* X2, void* img,
-                                   hipStream_t s) {
+                                   hipStream_t s, int need) {
   dim3 grid(1), blk(WG);
-  if (src_dt == DT_F64) {
+  if (src_dt != DT_F64 && src_dt != dt) return hipErrorInvalidValue;
+  if ((need & PACK_WAVE) && !(dt == DT_BF16 && wave_chain_ok(G))) return hipErrorInvalidValue;
+  if (!(need & PACK_LDS)) {
+  } else if (src_dt == DT_F64) {
     if (dt == DT_F64) hipLaunchKernelGGL((k_pack_chain_image<double, double>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (double*)img);
     else if (dt == DT_F32) hipLaunchKernelGGL((k_pack_chain_image<double, float>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (float*)img);
     else hipLaunchKernelGGL((k_pack_chain_image<double, bf16>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (bf16*)img);
@@ -973,7 +1039,7 @@ hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void
     if (dt == DT_F32) hipLaunchKernelGGL((k_pack_chain_image<float, float>), grid, blk, 0, s, G, (const float*)X1, (const float*)X2, (float*)img);
     else hipLaunchKernelGGL((k_pack_chain_image<bf16, bf16>), grid, blk, 0, s, G, (const bf16*)X1, (const bf16*)X2, (bf16*)img);
   }
-  if (dt == DT_BF16 && wave_chain_ok(G)) {
+  if (need & PACK_WAVE) {
     bf16* wimg = (bf16*)((unsigned char*)img + wave_image_offset(G));
     if (src_dt == DT_F64)
       hipLaunchKernelGGL((k_pack_wave_image<double>), dim3(WAVE_FRAGS), dim3(64), 0, s, G, (const double*)X1, (const double*)X2, wimg);
@@ -1064,11 +1130,21 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
     }
     return hipGetLastError();
   }
-  if (chain_s2_kb4(dt, mode, P.G)) {
-    // one wave per slab, 4 slabs per workgroup, 32-slab groups spread over 8 XCDs
-    dim3 wgrid(64 * ((P.G.n3 + 255) / 256)), wblk(WG_CW);
-    if (P.v_int) hipLaunchKernelGGL(k_slab_chain_w<true>, wgrid, wblk, 0, s, P);
-    else hipLaunchKernelGGL(k_slab_chain_w<false>, wgrid, wblk, 0, s, P);
+  if (wave_chain_used(dt, mode, P.G)) {
+    // one wave per part of a slab's column blocks; 4 slabs per workgroup when that
+    // still gives workgroups to 3/4 of the CUs, else 1 slab and 4 parts per workgroup
+    const bool four = 4 * ((P.G.n3 + 3) / 4) >= 3 * num_cus();
+    if (nblk_out) *nblk_out = four ? (P.G.n3 + 3) / 4 : P.G.n3;
+#define GLAM_WAVE(M, V)                                                                          \
+    do {                                                                                         \
+      if (four) hipLaunchKernelGGL((k_slab_chain_w<M, V, 4, 2>), dim3(64 * ((P.G.n3 + 255) / 256)), dim3(512), 0, s, P); \
+      else hipLaunchKernelGGL((k_slab_chain_w<M, V, 1, 4>), dim3(32 * ((P.G.n3 + 31) / 32)), dim3(256), 0, s, P); \
+    } while (0)
+    if (mode == SM_NLL_FWD) GLAM_WAVE(SM_NLL_FWD, false);
+    else if (mode == SM_NLL_BWD) GLAM_WAVE(SM_NLL_BWD, false);
+    else if (P.v_int) GLAM_WAVE(SM_FUSED, true);
+    else GLAM_WAVE(SM_FUSED, false);
+#undef GLAM_WAVE
     return hipGetLastError();
   }
   const int PT = P.G.PT;

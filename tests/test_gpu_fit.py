@@ -171,3 +171,22 @@ def test_nu_backtracking(fam, dt):
     th = _theta(glam, res, 1, d.p)
     ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200)
     _check_model(d, fam, th, lam, lm, 1e-7, ref=ref, theta_tol=1e-4)
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+def test_bf16_chain_all_register_tiles(fam):
+    """BF16 inner chain at mode-1/2 sizes that use every operand tile of the
+    one-wave-per-slab kernel: p1, p2 in (16, 32], n1, n2 in (64, 128] with ragged
+    16-tiles, more than 4 column blocks (both halves of a slab active), and
+    n3 % 4 != 0 (a partly filled last group of slabs).  The oracle's FP64 KKT
+    evaluator certifies the BF16 solution, whose objective matches the FP64 form's."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((100, 83, 45), (30, 21, 10), family=fam, seed=27)
+    print(f"bf16 wave-chain shapes {fam}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    lam = 0.05 * lm
+    r2 = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lam], dtype=2, kkt_tol=1e-6)
+    r0 = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lam], dtype=0, kkt_tol=1e-9)
+    assert abs(r2.lambda_max - lm) <= 1e-12 * lm
+    _check_model(d, fam, _theta(glam, r2, 0, d.p), lam, lm, 1e-6, ref=_theta(glam, r0, 0, d.p))
