@@ -146,7 +146,7 @@ def poisson_path(glam, inputs, torch, stream):
 def batched(glam, inputs, torch, stream):
     """256 independent GLAMs, n_ij ~ U{16..96}, p_ij = round(n_ij / 4), even
     Gaussian / odd Poisson, lambda_i = 0.1 lambda_max_i, FP32 inner chain, all to
-    KKT <= 1e-6 (one persistent launch per batched proximal step)."""
+    KKT <= 1e-6 (three batched launches per proximal step of all unconverged problems)."""
     probs = inputs.config_c4()
     ups = [{"X": [glam.to_device_colmajor(X, glam.F64) for X in q.X], "Y": glam.to_device_colmajor(q.Y, glam.F64),
             "n": q.n, "p": q.p, "family": q.family} for q in probs]

@@ -158,8 +158,9 @@ int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result
 
 /* ---------------------------------------------------------------------------
  * Many independent GLAMs at once (one lambda each): every inner proximal step of
- * all unconverged problems is one persistent (cooperative) launch; the FP64
- * outer steps of Algorithm 1 run per problem.
+ * all unconverged problems is three batched launches (mode-3 forward tiles, the
+ * slabs, mode-3 adjoint tiles with the proximal step); the FP64 outer steps of
+ * Algorithm 1 run per problem.
  * ------------------------------------------------------------------------- */
 typedef struct {
   const double* lambda;   /* HOST array of nprob lambdas, or NULL: lambda_ratio * lambda_max_i */

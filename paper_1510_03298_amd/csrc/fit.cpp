@@ -112,7 +112,7 @@ struct Fit {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
   hipStream_t us = nullptr;        // caller's stream
   bool own_stream = false;
-  bool batched = false;            // set up for glam_fit_batched (its persistent step uses the LDS image)
+  bool batched = false;            // set up for glam_fit_batched (its batched step uses the LDS image)
   hipEvent_t sync_ev = nullptr;
   double* dparams = nullptr;       // device {lambda, delta}
   double* hparams = nullptr;       // pinned host staging of dparams
@@ -165,7 +165,9 @@ struct StepStats {
   } while (0)
 
 // Step 2 of Algorithm 1 at theta (FP64): eta, V, -l/n, g = -G(U)/n, KKT.
-static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats* st) {
+// Enqueue step 2 of Algorithm 1 at theta (values land in F.hred after the stream
+// completes); family_collect reads them.
+static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   const Geom& G = F.G;
   FCHK(launch_pack(DT_F64, DT_F64, theta_dev, G.p3, G.P12, G.P12, 1, F.thpk, F.s));
   FwdParams fw{};
@@ -189,12 +191,22 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
   const int ops4[4] = {1, 1, 0, 0};
   FCHK(launch_reduce_strided(part2, nb, ADJ_NSUM, 4, ops4, 1.0, F.red + 2, F.s));
   FCHK(hipMemcpyAsync(F.hred, F.red, 6 * sizeof(double), hipMemcpyDeviceToHost, F.s));
-  FCHK(hipStreamSynchronize(F.s));
+  return GLAM_OK;
+}
+
+static void family_collect(const Fit& F, StepStats* st) {
   st->nll = F.hred[0];
   st->vmax = F.hred[1];
   st->kkt_raw = F.hred[2];
   st->lmax_raw = F.hred[3];
   st->pen = F.hred[4];
+}
+
+static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats* st) {
+  const int r = family_enqueue(F, theta_dev, lambda);
+  if (r) return r;
+  FCHK(hipStreamSynchronize(F.s));
+  family_collect(F, st);
   return GLAM_OK;
 }
 
@@ -369,44 +381,68 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
 }
 
 // Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
-static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* delta_out) {
+// Enqueue one pass of the Armijo rule (step sizes 2^-j0 .. 2^-(j0+15)) along d =
+// F.dvec; j0 == 0 also computes H(d) in FP64 (the trials use eta + t H(d)).  The sums
+// land in F.hred after the stream completes; armijo_decide reads them.
+static int armijo_enqueue(Fit& F, int j0) {
   const Geom& G = F.G;
-  // xd = H(d) in FP64 (tiled)
-  FCHK(launch_pack(DT_F64, DT_F64, F.dvec, G.p3, G.P12, G.P12, 1, F.thpk, F.s));
-  FwdParams fw{};
-  fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
-  FCHK(launch_slab_fwd(DT_F64, fw, F.s));
-  SlabParams sp{};
-  sp.G = G; sp.img = F.imgd; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
-  FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, nullptr, F.s));
+  if (j0 == 0) {
+    FCHK(launch_pack(DT_F64, DT_F64, F.dvec, G.p3, G.P12, G.P12, 1, F.thpk, F.s));
+    FwdParams fw{};
+    fw.G = G; fw.theta = F.thpk; fw.X3f = F.X3fd; fw.T1 = F.T1d;
+    FCHK(launch_slab_fwd(DT_F64, fw, F.s));
+    SlabParams sp{};
+    sp.G = G; sp.img = F.imgd; sp.T1 = F.T1d; sp.eta_out = F.xd_int;
+    FCHK(launch_slab_chain(DT_F64, SM_FWD_INT, sp, nullptr, F.s));
+  }
   constexpr int NV = ARMIJO_TRIALS + 1;
   const int ops[NV] = {0};
-  double Delta = 0.0;
-  for (int j0 = 0; j0 < 64; j0 += ARMIJO_TRIALS) {
-    int nb1 = 0, nb2 = 0;
-    FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
-    FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
-    double* part2 = F.part + (size_t)nb1 * NV;
-    FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, j0, part2, &nb2, F.s));
-    FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
-    FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
-    FCHK(hipStreamSynchronize(F.s));
-    const double* sm = F.hred;         // [0] = sum u xd / n ; [1+j] = smooth change / n
-    const double* pj = F.hred + NV;    // [0] = J(theta~) - J(theta) ; [1+j] = J change at t_j
-    if (j0 == 0) Delta = -sm[0] + lambda * pj[0];
-    for (int j = 0; j < ARMIJO_TRIALS; ++j) {
-      const double t = std::ldexp(1.0, -(j0 + j));
-      const double dF = sm[1 + j] + lambda * pj[1 + j];
-      if (std::isfinite(dF) && dF <= t * v * Delta) {
-        *alpha_out = t;
-        *delta_out = Delta;
-        return GLAM_OK;
-      }
+  int nb1 = 0, nb2 = 0;
+  FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
+  FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
+  double* part2 = F.part + (size_t)nb1 * NV;
+  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, j0, part2, &nb2, F.s));
+  FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
+  FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
+  return GLAM_OK;
+}
+
+// The first accepted trial of a pass: true with *alpha_out set, or false (try the next
+// pass).  *delta_out = Delta of the rule (set on the first pass).
+static bool armijo_decide(const Fit& F, int j0, double lambda, double v, double* alpha_out, double* delta_out) {
+  constexpr int NV = ARMIJO_TRIALS + 1;
+  const double* sm = F.hred;         // [0] = sum u xd / n ; [1+j] = smooth change / n
+  const double* pj = F.hred + NV;    // [0] = J(theta~) - J(theta) ; [1+j] = J change at t_j
+  if (j0 == 0) *delta_out = -sm[0] + lambda * pj[0];
+  for (int j = 0; j < ARMIJO_TRIALS; ++j) {
+    const double t = std::ldexp(1.0, -(j0 + j));
+    const double dF = sm[1 + j] + lambda * pj[1 + j];
+    if (std::isfinite(dF) && dF <= t * v * *delta_out) {
+      *alpha_out = t;
+      return true;
     }
   }
+  return false;
+}
+
+// Armijo rule from pass first_j0 on (the pass at first_j0 already enqueued when queued);
+// alpha = 0 when no step size down to 2^-63 is accepted.
+static int armijo_finish(Fit& F, double lambda, double v, bool queued, double* alpha_out, double* delta_out) {
+  for (int j0 = 0; j0 < 64; j0 += ARMIJO_TRIALS) {
+    if (!(queued && j0 == 0)) {
+      const int r = armijo_enqueue(F, j0);
+      if (r) return r;
+    }
+    FCHK(hipStreamSynchronize(F.s));
+    if (armijo_decide(F, j0, lambda, v, alpha_out, delta_out)) return GLAM_OK;
+  }
   *alpha_out = 0.0;
-  *delta_out = Delta;
   return GLAM_OK;
+}
+
+static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* delta_out) {
+  *delta_out = 0.0;
+  return armijo_finish(F, lambda, v, false, alpha_out, delta_out);
 }
 
 // Allocate the per-problem device state and run the one-time setup kernels: input
@@ -500,7 +536,7 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   FCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
   FCHK(launch_to_tiled(G, prob->obs_w, 1.0, F.a_int, F.s));
   FCHK(launch_pack_chain_image(DT_F64, DT_F64, G, prob->X[0], prob->X[1], F.imgd, F.s, PACK_LDS));
-  // the inner-loop chain (and, in a batched fit, the persistent step's per-slab chain)
+  // the inner-loop chain (and, in a batched fit, the batched step's per-slab chain)
   if (F.dt != DT_F64)
     FCHK(launch_pack_chain_image(F.dt, DT_F64, G, prob->X[0], prob->X[1], F.imgc, F.s,
                                  chain_image_need(F.dt, SM_FUSED, G) | (F.batched ? PACK_LDS : 0)));
@@ -820,14 +856,17 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
   int* d_active = (int*)take(sizeof(int) * nprob);
   double* d_part = (double*)take(sizeof(double) * nparts);
   double* d_seg = (double*)take(sizeof(double) * 2 * nprob);
-  int* d_misc = (int*)take(64);   // [0] step counter, [1..2] barrier, [3] error flag
-  double* h_seg = nullptr;
-  int* h_misc = nullptr;
-  int* h_active = nullptr;
-  if (hipHostMalloc((void**)&h_seg, sizeof(double) * 2 * nprob) != hipSuccess ||
-      hipHostMalloc((void**)&h_misc, 64) != hipSuccess || hipHostMalloc((void**)&h_active, sizeof(int) * nprob) != hipSuccess)
+  int* d_misc = (int*)take(64);   // [0] step counter of the batched inner loop
+  struct HGuard {
+    double* seg = nullptr;
+    int* active = nullptr;
+    ~HGuard() { if (seg) (void)hipHostFree(seg); if (active) (void)hipHostFree(active); }
+  } hg;
+  if (hipHostMalloc((void**)&hg.seg, sizeof(double) * 2 * nprob) != hipSuccess ||
+      hipHostMalloc((void**)&hg.active, sizeof(int) * nprob) != hipSuccess)
     return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
-  struct HGuard { void* a; void* b; void* c; ~HGuard() { if (a) (void)hipHostFree(a); if (b) (void)hipHostFree(b); if (c) (void)hipHostFree(c); } } hg{h_seg, h_misc, h_active};
+  double* h_seg = hg.seg;
+  int* h_active = hg.active;
   for (int i = 0; i < nprob; ++i) {
     Fit& F = *fits[i];
     const Geom& G = Gs[i];
@@ -854,9 +893,9 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
   BCHK(hipStreamSynchronize(s));   // host vectors above must outlive the copies
   BatchParams B{};
   B.desc = d_desc; B.nprob = nprob; B.off_fwd = d_off_fwd; B.off_slab = d_off_slab; B.off_adj = d_off_adj;
-  B.active = d_active; B.step = d_misc; B.bar = (unsigned*)(d_misc + 1); B.err = d_misc + 3;
+  B.active = d_active; B.step = d_misc;
   const size_t lds = batched_lds_bytes(dt, Gs.data(), nprob);
-  const int grid = batched_grid(dt, lds);
+  const int tot[3] = {off_fwd[nprob], off_slab[nprob], off_adj[nprob]};
 
   // lambda_max_i and lambda_i
   std::vector<double> lam(nprob), lmax(nprob), scale(nprob);
@@ -882,13 +921,19 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
   long long launches = 0, pstep = 0;
   for (int round = 0; round <= opt->max_outer; ++round) {
     int nact = 0;
+    // step 2 of Algorithm 1 for every unfinished problem, one stream synchronisation
+    for (int i = 0; i < nprob; ++i) {
+      if (done[i]) continue;
+      const int r = family_enqueue(*fits[i], fits[i]->theta, lam[i]);
+      if (r) return fit_fail(r, fits[i]->err);
+    }
+    BCHK(hipStreamSynchronize(s));
     for (int i = 0; i < nprob; ++i) {
       h_active[i] = 0;
       if (done[i]) continue;
       Fit& F = *fits[i];
       StepStats st;
-      const int r = family_step(F, F.theta, lam[i], &st);
-      if (r) return fit_fail(r, F.err);
+      family_collect(F, &st);
       const double kkt = st.kkt_raw / scale[i];
       res->kkt[i] = kkt;
       res->objective[i] = st.nll + lam[i] * st.pen;
@@ -918,15 +963,13 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
     int it = 0, window_start = 0;
     while (nact > 0 && it < opt->max_inner) {
       const int m = std::min(opt->check_every, opt->max_inner - it);
-      for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, grid, lds, s));
+      for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, tot, lds, s));
       launches += m;
       pstep += (long long)m * nact;
       it += m;
       BCHK(launch_segment_max(d_part, d_off_adj, nprob, d_seg, s));
       BCHK(hipMemcpyAsync(h_seg, d_seg, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost, s));
-      BCHK(hipMemcpyAsync(h_misc, d_misc, 16, hipMemcpyDeviceToHost, s));
       BCHK(hipStreamSynchronize(s));
-      if (h_misc[3] != 0) return fit_fail(GLAM_EDEVICE, "grid barrier timeout in the batched step (grid not co-resident)");
       bool changed = false;
       const bool window = it - window_start >= 20 * opt->check_every;
       for (int i = 0; i < nprob; ++i) {
@@ -944,14 +987,24 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
       if (window) window_start = it;
       if (changed && nact > 0) BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
     }
-    // step 5 of Algorithm 1 per problem: Armijo along theta~ - theta^k (theta~ = x^l of the last check)
+    // step 5 of Algorithm 1 per problem: Armijo along theta~ - theta^k (theta~ = x^l of the
+    // last check); the first pass of every problem is enqueued before one synchronisation
     for (int i = 0; i < nprob; ++i) {
       if (!in_round[i]) continue;
       Fit& F = *fits[i];
       BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, s));
-      double alpha = 0.0, Delta = 0.0;
-      const int r = armijo(F, lam[i], 0.1, &alpha, &Delta);
+      const int r = armijo_enqueue(F, 0);
       if (r) return fit_fail(r, F.err);
+    }
+    BCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < nprob; ++i) {
+      if (!in_round[i]) continue;
+      Fit& F = *fits[i];
+      double alpha = 0.0, Delta = 0.0;
+      if (!armijo_decide(F, 0, lam[i], 0.1, &alpha, &Delta)) {
+        const int r = armijo_finish(F, lam[i], 0.1, true, &alpha, &Delta);
+        if (r) return fit_fail(r, F.err);
+      }
       if (alpha > 0.0) BCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, s));
     }
   }

@@ -118,7 +118,7 @@ struct FwdParams {
   int* iter;          // optional: incremented once by the first thread
 };
 
-// batched proximal step (many independent problems per launch)
+// batched proximal step (many independent problems per launch, three launches per step)
 struct BatchDesc {
   FwdParams fw;       // theta = increment (k-blocked), X3f, T1
   SlabParams sp;      // img, T1, S2, v_int
@@ -134,12 +134,10 @@ struct BatchParams {
   const int* off_adj;   // prefix sums of slab_adj tiles (also the partials index)
   const int* active;    // problem mask
   int* step;            // inner step counter (read by the prox epilogue)
-  unsigned* bar;        // grid barrier state {count, generation}
-  int* err;             // barrier timeout flag
 };
 size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
-int batched_grid(int dt, size_t lds);
-hipError_t launch_batched_step(int dt, const BatchParams& B, int grid, size_t lds, hipStream_t s);
+// tot: {forward tiles, slabs, adjoint tiles} over all problems (the offsets' last entries)
+hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s);
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s);
 
 // rho kernels

@@ -152,7 +152,7 @@ __device__ inline void fwd_tile(const FwdParams& P, int bx, int by) {
     const int i3o = by * 32 + sl, mo = bx * 32 + ml;
     if (i3o < G.n3 && mo < G.P12) T1[(long long)i3o * G.P12 + mo] = tt[sl][ml];
   }
-  __syncthreads();   // tt is reused by the next tile of a persistent caller
+  __syncthreads();   // tt is reused by the next tile of a grid-stride caller
 }
 
 template <typename T>
@@ -868,34 +868,10 @@ __global__ __launch_bounds__(WG) void k_slab_adj(AdjParams P) {
 }
 
 // ============================================================================
-// batched proximal step: many independent GLAMs in one persistent launch
+// batched proximal step: many independent GLAMs, three launches per step (the launch
+// boundaries order the phases: a grid-wide barrier inside one launch measured far
+// slower on this chip than a kernel boundary)
 // ============================================================================
-// Grid-wide barrier of a co-resident grid.  The wait is bounded: on timeout the
-// flag *err is raised and the wave proceeds, so every wave of the launch exits.
-__device__ inline void grid_barrier(unsigned* bar, int* err, unsigned nblocks) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      int spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1 << 22)) {
-          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
-    }
-    __threadfence();
-  }
-  __syncthreads();
-}
-
 __device__ inline int find_segment(const int* off, int nseg, int item) {
   int lo = 0, hi = nseg;   // off[lo] <= item < off[hi]
   while (hi - lo > 1) {
@@ -905,51 +881,54 @@ __device__ inline int find_segment(const int* off, int nseg, int item) {
   return lo;
 }
 
-template <typename T>
-__global__ __launch_bounds__(WG) void k_batched_step(BatchParams B) {
+// PH 0: mode-3 forward GEMM tiles of every active problem (and the step counter l)
+// PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem, in
+//       contiguous runs per workgroup so that the factor image is restaged rarely
+// PH 2: mode-3 adjoint tiles + proximal step of every active problem
+template <typename T, int PH>
+__global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
   typedef typename Tr<T>::acc_t A;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const unsigned nblocks = gridDim.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    __hip_atomic_fetch_add(B.step, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // phase A: mode-3 forward GEMM tiles of every active problem
-  const int totA = B.off_fwd[B.nprob];
-  for (int item = blockIdx.x; item < totA; item += gridDim.x) {
-    const int pb = find_segment(B.off_fwd, B.nprob, item);
-    if (!B.active[pb]) continue;
-    const BatchDesc& D = B.desc[pb];
-    const int loc = item - B.off_fwd[pb];
-    fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
-  }
-  grid_barrier(B.bar, B.err, nblocks);
-  // phase B: the slabs (modes 1-2 forward, adjoint) of every active problem
-  const int totB = B.off_slab[B.nprob];
-  int cur = -1;
-  ChainLayout L;
-  double s_nll = 0.0, s_vmax = 0.0;
-  for (int item = blockIdx.x; item < totB; item += gridDim.x) {
-    const int pb = find_segment(B.off_slab, B.nprob, item);
-    if (!B.active[pb]) continue;
-    const BatchDesc& D = B.desc[pb];
-    if (pb != cur) {
-      __syncthreads();
-      L = chain_layout(D.sp.G, (int)sizeof(T), (int)sizeof(A));
-      chain_stage(D.sp.img, L.image_bytes, smem_raw);
-      cur = pb;
+  if (PH == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *B.step += 1;
+    const int totA = B.off_fwd[B.nprob];
+    for (int item = blockIdx.x; item < totA; item += gridDim.x) {
+      const int pb = find_segment(B.off_fwd, B.nprob, item);
+      if (!B.active[pb]) continue;
+      const BatchDesc& D = B.desc[pb];
+      const int loc = item - B.off_fwd[pb];
+      fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
     }
-    const int i3 = item - B.off_slab[pb];
-    if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
-    else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
-  }
-  grid_barrier(B.bar, B.err, nblocks);
-  // phase C: mode-3 adjoint tiles + proximal step of every active problem
-  const int totC = B.off_adj[B.nprob];
-  for (int item = blockIdx.x; item < totC; item += gridDim.x) {
-    const int pb = find_segment(B.off_adj, B.nprob, item);
-    if (!B.active[pb]) continue;
-    const BatchDesc& D = B.desc[pb];
-    const int loc = item - B.off_adj[pb];
-    adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, item);
+  } else if (PH == 1) {
+    const int totB = B.off_slab[B.nprob];
+    const int chunk = (totB + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * chunk, i1 = min(totB, i0 + chunk);
+    int cur = -1;
+    ChainLayout L;
+    double s_nll = 0.0, s_vmax = 0.0;
+    for (int item = i0; item < i1; ++item) {
+      const int pb = find_segment(B.off_slab, B.nprob, item);
+      if (!B.active[pb]) continue;
+      const BatchDesc& D = B.desc[pb];
+      if (pb != cur) {
+        __syncthreads();
+        L = chain_layout(D.sp.G, (int)sizeof(T), (int)sizeof(A));
+        chain_stage(D.sp.img, L.image_bytes, smem_raw);
+        cur = pb;
+      }
+      const int i3 = item - B.off_slab[pb];
+      if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+      else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+    }
+  } else {
+    const int totC = B.off_adj[B.nprob];
+    for (int item = blockIdx.x; item < totC; item += gridDim.x) {
+      const int pb = find_segment(B.off_adj, B.nprob, item);
+      if (!B.active[pb]) continue;
+      const BatchDesc& D = B.desc[pb];
+      const int loc = item - B.off_adj[pb];
+      adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, item);
+    }
   }
 }
 
@@ -1179,29 +1158,22 @@ size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob) {
   return m;
 }
 
-int batched_grid(int dt, size_t lds) {
-  int per_cu = 0;
-  hipError_t e;
-  if (dt == DT_F64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<double>, WG, lds);
-  else if (dt == DT_F32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<float>, WG, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_step<bf16>, WG, lds);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  if (per_cu > 2) per_cu = 2;
-  return num_cus() * per_cu;
+template <typename T>
+static hipError_t batched_phases(const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
+  const int cap = 8 * num_cus();
+  const int gA = std::max(1, std::min(tot[0], cap)), gB = std::max(1, std::min(tot[1], 4 * num_cus()));
+  const int gC = std::max(1, std::min(tot[2], cap));
+  hipLaunchKernelGGL((k_batched_phase<T, 0>), dim3(gA), dim3(WG), 0, s, B);
+  set_lds(k_batched_phase<T, 1>, lds);
+  hipLaunchKernelGGL((k_batched_phase<T, 1>), dim3(gB), dim3(WG), lds, s, B);
+  hipLaunchKernelGGL((k_batched_phase<T, 2>), dim3(gC), dim3(WG), 0, s, B);
+  return hipGetLastError();
 }
 
-hipError_t launch_batched_step(int dt, const BatchParams& B, int grid, size_t lds, hipStream_t s) {
-  void* args[] = {(void*)&B};
-  if (dt == DT_F64) {
-    set_lds(k_batched_step<double>, lds);
-    return hipLaunchCooperativeKernel((const void*)k_batched_step<double>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
-  }
-  if (dt == DT_F32) {
-    set_lds(k_batched_step<float>, lds);
-    return hipLaunchCooperativeKernel((const void*)k_batched_step<float>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
-  }
-  set_lds(k_batched_step<bf16>, lds);
-  return hipLaunchCooperativeKernel((const void*)k_batched_step<bf16>, dim3(grid), dim3(WG), args, (unsigned)lds, s);
+hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
+  if (dt == DT_F64) return batched_phases<double>(B, tot, lds, s);
+  if (dt == DT_F32) return batched_phases<float>(B, tot, lds, s);
+  return batched_phases<bf16>(B, tot, lds, s);
 }
 
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s) {

@@ -365,7 +365,7 @@ class BatchResult:
 
 def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-6, max_outer=100,
                 max_inner=100000, check_every=10, stream=None, raise_on_error=True) -> BatchResult:
-    """Fit many independent problems (one lambda each) with one persistent launch per
+    """Fit many independent problems (one lambda each) with three batched launches per
     batched proximal step.  problems: list of dicts with keys X (3 FP64 device
     factors), Y (FP64 device n-array), n, p, family, and optional obs_w, pen_w."""
     torch = _torch()

@@ -1,4 +1,4 @@
-"""Batched fits of many uneven GLAMs (one persistent launch per proximal step)
+"""Batched fits of many uneven GLAMs (three batched launches per proximal step)
 against the oracle, problem by problem."""
 import numpy as np
 import pytest
