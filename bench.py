@@ -123,6 +123,24 @@ def copy_calibration(torch, dev, mib):
     print(json.dumps({"copy_calibration_bytes_read": mib << 20, "copy_calibration_bytes_written": mib << 20}))
 
 
+def gram_path(glam, torch, d, Xd, Yd, stream, nlambda, chain_seconds):
+    """The same Gaussian path with the inner gradient from the Kronecker Gram factors
+    X_j^T X_j (Sec. 6.2, exact for identity weights): p-sized inner products only, the
+    FP64 outer steps still through the rho chain."""
+    out = {"workload": "gaussian_path_n100x100x1000_p30x30x200_100lambda_kkt1e-6_gram_inner"}
+    for dt, name in ((glam.BF16, "bf16"), (glam.F64, "f64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=nlambda, lambda_min_ratio=1e-4, dtype=dt,
+                          kkt_tol=1e-6, stream=stream, raise_on_error=False, inner="gram")
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "converged": r.code == 0 and r.n_done == nlambda,
+                     "max_kkt": float(np.max(r.kkt[:r.n_done])) if r.n_done else None,
+                     "inner": int(r.inner_total), "outer": int(r.iters_outer.sum())}
+    out["speedup_vs_chain_bf16"] = chain_seconds / out["bf16"]["seconds"]
+    return out
+
+
 def poisson_path(glam, inputs, torch, stream):
     """Poisson counts, n = (64, 64, 365), p = (24, 24, 120), 50-lambda log grid to
     1e-4 lambda_max, KKT <= 1e-6, BF16 inner chain (FP64 Armijo, KKT and anchors)."""
@@ -289,7 +307,8 @@ def main():
         cpu = cpu_baseline(d, forms["f64"]["inner"], forms["f64"]["outer"])
     extra = None
     if not args.no_extra:
-        extra = {"poisson_path_c3": poisson_path(glam, inputs, torch, stream),
+        extra = {"gaussian_path_c2_gram": gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec),
+                 "poisson_path_c3": poisson_path(glam, inputs, torch, stream),
                  "batched_c4": batched(glam, inputs, torch, stream),
                  "poisson_nll_c5": nll(glam, inputs, torch, stream)}
     out = {

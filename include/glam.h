@@ -128,7 +128,18 @@ typedef struct {
                              fit's stream (0 = off; the re-runs rewrite identical values) */
   int graph_mode;         /* 0: replay each block of check_every inner iterations as a
                              captured HIP graph (default); 1: plain stream launches */
+  int inner_mode;         /* glam_inner: how the inner loop evaluates grad h (the FP64
+                             outer steps always use the rho chain)                  */
 } glam_options;
+
+/* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the
+ * n-sized rho chain (Sec. 6.1).  GLAM_INNER_GRAM: (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n
+ * with the Gram factors S_j = X_j^T X_j (Sec. 6.2, tensor-product weights with W = I), i.e.
+ * p-sized products only; exact for the Gaussian family without prior weights, and only
+ * there (GLAM_EINVAL for Poisson, obs_w != NULL or nu < 1).  The Gram products run in the
+ * accumulation type of the dtype (FP32 for BF16/F32, FP64 for F64), the mode-3 product on
+ * the matrix cores in the chain dtype. */
+typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1 } glam_inner;
 
 typedef struct {
   double* theta;          /* device, FP64, nlambda x p (model l at offset l*p), caller-allocated */

@@ -131,6 +131,18 @@ def kron_design(Xs: Sequence[np.ndarray]) -> np.ndarray:
     return D
 
 
+def gram_apply(Xs: Sequence[np.ndarray], D: np.ndarray) -> np.ndarray:
+    """X^T X vec(D) for a tensor-product design, taken as the three p-sized mode
+    products with the Gram factors X_j^T X_j (Sec. 6.2: with identity weights the
+    weighted Gram matrix of the array design is the Kronecker product of the
+    factors' Gram matrices, by the mixed-product property of App. A)."""
+    out = np.asarray(D, dtype=np.float64)
+    for X in Xs:
+        S = np.asarray(X, dtype=np.float64).T @ np.asarray(X, dtype=np.float64)
+        out = rho(S, out)
+    return out
+
+
 def rho_chain_flops(n: Sequence[int], p: Sequence[int], order: Sequence[int]) -> int:
     """Multiply-add count (x2) of applying the factors one mode at a time in
     ``order`` (0-based modes) to a p-array, i.e. the cost of the H map when the

@@ -30,9 +30,8 @@
 
 namespace glam {
 
-// Largest eigenvalue of X^T X (X host, n x p column-major) by cyclic Jacobi
-// rotations on the p x p Gram matrix (Proposition 1 needs rho(X_j^T X_j)).
-static double gram_spectral_radius(const std::vector<double>& X, int n, int p) {
+// Gram matrix X^T X (X host, n x p column-major), p x p.
+static std::vector<double> gram_matrix(const std::vector<double>& X, int n, int p) {
   std::vector<double> A((size_t)p * p, 0.0);
   for (int a = 0; a < p; ++a)
     for (int b = a; b < p; ++b) {
@@ -41,6 +40,12 @@ static double gram_spectral_radius(const std::vector<double>& X, int n, int p) {
       A[(size_t)a * p + b] = s;
       A[(size_t)b * p + a] = s;
     }
+  return A;
+}
+
+// Largest eigenvalue of a symmetric p x p matrix by cyclic Jacobi rotations
+// (Proposition 1 needs rho(X_j^T X_j)).
+static double gram_spectral_radius(std::vector<double> A, int p) {
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0, diag = 0.0;
     for (int a = 0; a < p; ++a) {
@@ -92,6 +97,11 @@ struct Fit {
   double *y_int, *a_int, *eta_int, *xd_int;
   void* v_int;             // tiled weights (acc type of the chain) or NULL (Gaussian)
   void *T1c, *S2c;         // chain dtype intermediates
+  bool gram = false;       // inner gradient by the Kronecker Gram factors (Sec. 6.2)
+  double *S1g = nullptr, *S2g = nullptr;   // X_1^T X_1, X_2^T X_2 (FP64)
+  void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
+  void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
+  Geom Gg{};               // geometry of the mode-3 Gram product (contraction length p3)
   double *T1d, *S2d;       // FP64 intermediates
   double *theta, *gref, *x, *xp, *gp, *dvec;
   double *yb = nullptr, *gyb = nullptr;                     // backtracking: y_{l-1}, grad h(y_{l-1})
@@ -216,6 +226,22 @@ constexpr int kSampleReps = 8;   // back-to-back launches of the fused slab kern
 static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool sample) {
   const Geom& G = F.G;
   if (sample) FCHK(hipEventRecord(F.ev[0], F.s));
+  if (F.gram) {
+    // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I)
+    FCHK(launch_gram12(F.dt, G, F.inc, F.S1g, F.S2g, F.Zc, F.iter, F.s));
+    AdjParams ap{};
+    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+    ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
+    ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
+    FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
+    if (sample) {   // iteration time only (there is no rho chain in this iteration)
+      FCHK(hipEventRecord(F.ev[1], F.s));
+      FCHK(hipEventRecord(F.ev[2], F.s));
+      FCHK(hipEventRecord(F.ev[3], F.s));
+      F.pending = true;
+    }
+    return GLAM_OK;
+  }
   FwdParams fw{};
   fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c; fw.iter = F.iter;
   FCHK(launch_slab_fwd(F.dt, fw, F.s));
@@ -550,11 +576,32 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     FCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
   }
   F.sprod = 1.0;
+  std::vector<double> gm[3];
   for (int j = 0; j < 3; ++j) {
     std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
     FCHK(hipMemcpyAsync(hx.data(), prob->X[j], hx.size() * 8, hipMemcpyDeviceToHost, F.s));
     FCHK(hipStreamSynchronize(F.s));
-    F.sprod *= gram_spectral_radius(hx, (int)prob->n[j], (int)prob->p[j]);
+    gm[j] = gram_matrix(hx, (int)prob->n[j], (int)prob->p[j]);
+    F.sprod *= gram_spectral_radius(gm[j], (int)prob->p[j]);
+  }
+  if (F.gram) {
+    F.S1g = (double*)F.alloc(gm[0].size() * 8);
+    F.S2g = (double*)F.alloc(gm[1].size() * 8);
+    double* s3 = (double*)F.alloc(gm[2].size() * 8);
+    F.S3c = F.alloc((size_t)G.KB3 * 16 * G.p3 * es);
+    F.Zc = F.alloc((size_t)G.inc_len * es);
+    if (!F.S1g || !F.S2g || !s3 || !F.S3c || !F.Zc) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
+    FCHK(hipMemcpyAsync(F.S1g, gm[0].data(), gm[0].size() * 8, hipMemcpyHostToDevice, F.s));
+    FCHK(hipMemcpyAsync(F.S2g, gm[1].data(), gm[1].size() * 8, hipMemcpyHostToDevice, F.s));
+    FCHK(hipMemcpyAsync(s3, gm[2].data(), gm[2].size() * 8, hipMemcpyHostToDevice, F.s));
+    FCHK(launch_pack(F.dt, DT_F64, s3, G.p3, G.p3, 1, G.p3, F.S3c, F.s));
+    FCHK(launch_zero(F.Zc, (size_t)G.inc_len * es, F.s));   // contraction padding stays zero
+    FCHK(hipStreamSynchronize(F.s));                        // host Gram matrices go out of scope
+    F.Gg = G;   // out = Z^T S_3: the adjoint GEMM with contraction length p3
+    F.Gg.n3 = G.p3;
+    F.Gg.KBN3 = G.KB3;
+    F.Gg.s2_len = G.inc_len;
+    F.Gg.x3a_len = (long long)G.KB3 * 16 * G.p3;
   }
   return GLAM_OK;
 }
@@ -581,6 +628,11 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
     return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
   if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
+  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM)
+    return fit_fail(GLAM_EINVAL, "bad inner_mode");
+  if (opt->inner_mode == GLAM_INNER_GRAM && (prob->family != GLAM_GAUSSIAN || prob->obs_w || opt->nu < 1.0))
+    return fit_fail(GLAM_EINVAL, "the Gram inner loop is exact only for the Gaussian family without prior "
+                                 "weights (Sec. 6.2) and runs without backtracking (nu = 1)");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
   if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
@@ -610,6 +662,7 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
   if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
+  F.gram = opt->inner_mode == GLAM_INNER_GRAM;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
     if (r) return fit_fail(r, F.err);

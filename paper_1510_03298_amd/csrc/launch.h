@@ -140,6 +140,12 @@ size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
 hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s);
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s);
 
+// Gram inner gradient (Gaussian, identity weights): Z_k3 = S_1 D_k3 S_2 for every slice k3
+// of the k-blocked increment D (K = p3, C = P12) into Z (same layout); S_j FP64 p_j x p_j;
+// increments *iter once when iter != NULL
+hipError_t launch_gram12(int dt, const Geom& G, const void* inc, const double* S1, const double* S2, void* Z, int* iter,
+                         hipStream_t s);
+
 // rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
 hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s);

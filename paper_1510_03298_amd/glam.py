@@ -44,7 +44,7 @@ class GlamOptions(ctypes.Structure):
                 ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
                 ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int),
-                ("graph_mode", ctypes.c_int)]
+                ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int)]
 
 
 class GlamResult(ctypes.Structure):
@@ -290,7 +290,7 @@ class PathResult:
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
              check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
-             graph=True) -> PathResult:
+             graph=True, inner="chain") -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays."""
     torch = _torch()
@@ -323,6 +323,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.stream = _stream_ptr(stream)
     opt.profile_every = int(profile_every)
     opt.graph_mode = 0 if graph else 1
+    opt.inner_mode = {"chain": 0, "gram": 1}[inner]
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()

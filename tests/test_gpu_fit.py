@@ -190,3 +190,43 @@ def test_bf16_chain_all_register_tiles(fam):
     r0 = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lam], dtype=0, kkt_tol=1e-9)
     assert abs(r2.lambda_max - lm) <= 1e-12 * lm
     _check_model(d, fam, _theta(glam, r2, 0, d.p), lam, lm, 1e-6, ref=_theta(glam, r0, 0, d.p))
+
+
+@pytest.mark.parametrize("dt", [0, 1, 2])
+def test_gram_inner_loop_path(dt):
+    """Sec. 6.2 (identity weights): the Gaussian path with the inner gradient from the
+    Kronecker Gram factors reaches the same PMLE, certified by the oracle's KKT."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((23, 19, 37), (9, 7, 12), seed=21)
+    print(f"gram path dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=8, lambda_min_ratio=1e-3, dtype=dt, kkt_tol=1e-6,
+                        inner="gram")
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    ref = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=8, lambda_min_ratio=1e-3, dtype=0, kkt_tol=1e-9)
+    for l in range(8):
+        _check_model(d, "gaussian", _theta(glam, res, l, d.p), res.lambdas[l], lm, 1e-6, ref=_theta(glam, ref, l, d.p))
+
+
+def test_gram_inner_loop_full_tiles_bf16():
+    torch, glam = need_gpu()
+    d = inputs.random_problem((100, 83, 45), (30, 21, 10), seed=27)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    lam = 0.05 * lm
+    r = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", lambdas=[lam], dtype=2, kkt_tol=1e-6, inner="gram")
+    _check_model(d, "gaussian", _theta(glam, r, 0, d.p), lam, lm, 1e-6)
+
+
+def test_gram_inner_loop_rejects_inexact_cases():
+    """The Gram form is exact only for the Gaussian family with identity weights."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((12, 11, 10), (5, 4, 6), seed=28, family="poisson")
+    Xd, Yd, _ = _dev(glam, d)
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=2, inner="gram")
+    a = torch.ones_like(Yd)
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", obs_w=a, nlambda=2, inner="gram")
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=2, nu=0.5, inner="gram")

@@ -62,6 +62,17 @@ def test_kronecker_rho_identity(n, p):
     np.testing.assert_allclose(O.vec(O.G(Xs, U)), O.kron_design(Xs).T @ O.vec(U), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("n,p", [((5, 4, 3), (2, 3, 4)), ((6, 5, 7), (6, 5, 4)), ((3, 8, 5), (3, 2, 5))])
+def test_gram_apply_is_the_explicit_normal_matrix(n, p):
+    """Sec. 6.2 with identity weights: X^T X vec(D) by three p-sized Gram mode products equals the
+    explicit (X_3 x X_2 x X_1)^T (X_3 x X_2 x X_1) vec(D), and G(H(D))."""
+    Xs = [rnd((nj, pj), 60 + j) for j, (nj, pj) in enumerate(zip(n, p))]
+    D = rnd(p, 70)
+    Xd = O.kron_design(Xs)
+    np.testing.assert_allclose(O.vec(O.gram_apply(Xs, D)), Xd.T @ (Xd @ O.vec(D)), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(O.gram_apply(Xs, D), O.G(Xs, O.H(Xs, D)), rtol=1e-11, atol=1e-11)
+
+
 def test_adjoint_dot_product():
     """<H(Theta), U> = <Theta, G(U)> (G uses the transposed factors, eq. nineteen)."""
     n, p = (7, 6, 9), (3, 5, 4)
