@@ -493,27 +493,65 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
 // stores into the same lines merge in that XCD's L2.
 // ============================================================================
 constexpr int WAVE_FRAGS = 32;
-constexpr int WAVE_IMAGE_BYTES = WAVE_FRAGS * 64 * 16;
 __host__ __device__ inline int kw_index(int g, int u) { return u < 4 ? 4 * g + u : 12 + 4 * g + u; }
 __host__ __device__ inline bool wave_chain_ok(const Geom& G) { return G.N1T <= 8 && G.NJB <= 8 && G.PT <= 2; }
 static bool wave_chain_used(int dt, int mode, const Geom& G) {
-  return dt == DT_BF16 && (mode == SM_FUSED || mode == SM_NLL_FWD || mode == SM_NLL_BWD) && wave_chain_ok(G);
+  return (dt == DT_BF16 || dt == DT_F32) && (mode == SM_FUSED || mode == SM_NLL_FWD || mode == SM_NLL_BWD) &&
+         wave_chain_ok(G);
 }
 bool chain_s2_kb4(int dt, int mode, const Geom& G) { return wave_chain_used(dt, mode, G) && mode != SM_NLL_FWD; }
-__host__ __device__ inline size_t wave_image_offset(const Geom& G) {
-  return ((size_t)chain_layout(G, 2, 4).image_bytes + 255) & ~(size_t)255;
+// the wave image follows the LDS image of the same dtype (element size es)
+__host__ __device__ inline size_t wave_image_offset(const Geom& G, int es) {
+  return ((size_t)chain_layout(G, es, 4).image_bytes + 255) & ~(size_t)255;
 }
+__host__ __device__ inline size_t wave_image_bytes(int es) { return (size_t)WAVE_FRAGS * 64 * 8 * es; }
 
-__device__ inline bf8v load_wfrag(const unsigned char* img, int frag, int lane) {
-  return __builtin_bit_cast(bf8v, ((const u4v_t*)img)[frag * 64 + lane]);
-}
+// Per-dtype pieces of the one-wave-per-slab kernel.  A 32-deep operand fragment is 8
+// elements per lane (slot u of lane group g: index kw(g, u) within the block).
+//   BF16: one 16x16x32 matrix-core op per 32-deep block.
+//   FP32: eight 16x16x4 ops, op u taking slot u of every lane (lane group g supplies
+//         contraction index kw(g, u)); the same pairing for both operands, and the
+//         accumulator rows of a 16 x 16 tile are those of every other FP32 op here.
+typedef float f8v __attribute__((ext_vector_type(8)));
+template <typename T> struct WT;
+template <> struct WT<bf16> {
+  typedef bf8v v8;
+  typedef unsigned short st;   // stored element of T1 / S2
+  __device__ static inline v8 load(const unsigned char* img, int frag, int lane) {
+    return __builtin_bit_cast(bf8v, ((const u4v_t*)img)[frag * 64 + lane]);
+  }
+  __device__ static inline v8 pack(const f4v& lo, const f4v& hi) { return pack_acc2(lo, hi); }
+  __device__ static inline f4v mma(const v8& a, const v8& b, const f4v& c) { return mma32(a, b, c); }
+  __device__ static inline st from_f32(float x) { return f32_to_bf16(x); }
+  __device__ static inline void set(v8& v, int u, st h) { v[u] = __builtin_bit_cast(__bf16, h); }
+};
+template <> struct WT<float> {
+  typedef f8v v8;
+  typedef float st;
+  __device__ static inline v8 load(const unsigned char* img, int frag, int lane) {
+    return ((const f8v*)img)[frag * 64 + lane];
+  }
+  __device__ static inline v8 pack(const f4v& lo, const f4v& hi) {
+    const v8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return v;
+  }
+  __device__ static inline f4v mma(const v8& a, const v8& b, f4v c) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], c, 0, 0, 0);
+    return c;
+  }
+  __device__ static inline st from_f32(float x) { return x; }
+  __device__ static inline void set(v8& v, int u, st h) { v[u] = h; }
+};
 
-__device__ inline bf16 to_bf16(double v) { bf16 b; b.u = f32_to_bf16((float)v); return b; }
-__device__ inline bf16 to_bf16(bf16 v) { return v; }
+__device__ inline bf16 to_wave(double v, bf16*) { bf16 b; b.u = f32_to_bf16((float)v); return b; }
+__device__ inline bf16 to_wave(bf16 v, bf16*) { return v; }
+__device__ inline float to_wave(double v, float*) { return (float)v; }
+__device__ inline float to_wave(float v, float*) { return v; }
 
 // wave image: one fragment per workgroup (frag = blockIdx.x, lane = threadIdx.x)
-template <typename S>
-__global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __restrict__ X2, bf16* __restrict__ out) {
+template <typename S, typename T>
+__global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __restrict__ X2, T* __restrict__ out) {
   const int f = blockIdx.x, l = threadIdx.x, rc = l & 15, g = l >> 4;
   if (f >= WAVE_FRAGS || l >= 64) return;
   for (int u = 0; u < 8; ++u) {
@@ -524,9 +562,9 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
     else if (f < 16) { x1 = true; i = 16 * (f - 8) + rc; k = kw; }                       // FX1A[ut]
     else if (f < 24) { x1 = true; i = 32 * ((f - 16) >> 1) + kw; k = 16 * ((f - 16) & 1) + rc; }   // FX1B[q][nt]
     else { x1 = false; i = 32 * ((f - 24) & 3) + kw; k = 16 * ((f - 24) >> 2) + rc; }              // FX2A[mt][q]
-    bf16 b = zero_val<bf16>();
-    if (x1 && i < G.n1 && k < G.p1) b = to_bf16(X1[i + (long long)G.n1 * k]);
-    if (!x1 && i < G.n2 && k < G.p2) b = to_bf16(X2[i + (long long)G.n2 * k]);
+    T b = zero_val<T>();
+    if (x1 && i < G.n1 && k < G.p1) b = to_wave(X1[i + (long long)G.n1 * k], (T*)nullptr);
+    if (!x1 && i < G.n2 && k < G.p2) b = to_wave(X2[i + (long long)G.n2 * k], (T*)nullptr);
     out[((long long)f * 64 + l) * 8 + u] = b;
   }
 }
@@ -536,8 +574,12 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
 // consecutive slabs (4 or 1) and NPART waves per slab (2 or 4), each wave taking 8 / NPART
 // of the (at most 8) mode-2 column blocks; the waves' S2 partials are summed in LDS.
 // Partial NLL sums per workgroup in partials[slab group][2].
-template <int MODE, bool HAS_V, int SPW, int NPART>
+template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
 __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
+  typedef WT<T> W;
+  typedef typename W::v8 V8;
+  typedef typename W::st ST;
+  typedef ST st4 __attribute__((ext_vector_type(4)));
   constexpr bool ADJ = MODE != SM_NLL_FWD;
   constexpr bool NLL = MODE == SM_NLL_FWD || MODE == SM_NLL_BWD;
   constexpr int NT = 64 * SPW * NPART;   // threads per workgroup
@@ -558,34 +600,33 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
   const int N1T = G.N1T, NJB = G.NJB;
   const int jb0 = JPW * part;                     // this wave: column blocks jb0 .. jb0 + JPW - 1
   const bool active = sw < nsl && jb0 < NJB;
-  __shared__ __align__(16) unsigned short t1s[SPW * 1024];            // T1 of the slabs (P12 <= 1024)
+  __shared__ __align__(16) ST t1s[SPW * 1024];                        // T1 of the slabs (P12 <= 1024)
   __shared__ __align__(16) float s2p[NPART - 1][SPW][1024];           // S2 partials of parts 1..
-  __shared__ __align__(16) unsigned short s2x[SPW == 4 ? 4096 : 1];   // S2 of 4 slabs, [m][slab]
+  __shared__ __align__(16) ST s2x[SPW == 4 ? 4096 : 4];               // S2 of 4 slabs, [m][slab]
   // factor fragments: requested first, so that their latency overlaps the T1 staging
-  const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G);
-  bf8v fx2t[JPW], fx1a[8], fx1b[4][2], fx2a[2][QPW];
-  const bf8v zf = {};
+  const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G, (int)sizeof(ST));
+  V8 fx2t[JPW], fx1a[8], fx1b[4][2], fx2a[2][QPW];
+  const V8 zf = {};
 #pragma unroll
-  for (int t = 0; t < 8; ++t) fx1a[t] = t < N1T ? load_wfrag(img, 8 + t, lane) : zf;
+  for (int t = 0; t < 8; ++t) fx1a[t] = t < N1T ? W::load(img, 8 + t, lane) : zf;
 #pragma unroll
-  for (int t = 0; t < JPW; ++t) fx2t[t] = jb0 + t < NJB ? load_wfrag(img, jb0 + t, lane) : zf;
+  for (int t = 0; t < JPW; ++t) fx2t[t] = jb0 + t < NJB ? W::load(img, jb0 + t, lane) : zf;
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) fx1b[qq][nt] = 2 * qq < N1T ? load_wfrag(img, 16 + 2 * qq + nt, lane) : zf;
+    for (int nt = 0; nt < 2; ++nt) fx1b[qq][nt] = 2 * qq < N1T ? W::load(img, 16 + 2 * qq + nt, lane) : zf;
 #pragma unroll
   for (int qq = 0; qq < QPW; ++qq)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
-      fx2a[mt][qq] = jb0 + 2 * qq < NJB ? load_wfrag(img, 24 + 4 * mt + QPW * part + qq, lane) : zf;
+      fx2a[mt][qq] = jb0 + 2 * qq < NJB ? W::load(img, 24 + 4 * mt + QPW * part + qq, lane) : zf;
   {
-    // the slabs are contiguous in slab-major T1: coalesced 8-byte loads when aligned
-    const unsigned short* src = (const unsigned short*)P.T1 + (long long)i3b * P12;
+    // the slabs are contiguous in slab-major T1: coalesced 4-element loads when aligned
+    const ST* src = (const ST*)P.T1 + (long long)i3b * P12;
     const int nel = nsl * P12;
-    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-    const int n8 = (((unsigned long long)src & 7) == 0) ? (nel >> 2) : 0;
-    for (int k = tid; k < n8; k += NT) ((u16x4*)t1s)[k] = ((const u16x4*)src)[k];
-    for (int k = 4 * n8 + tid; k < nel; k += NT) t1s[k] = src[k];
+    const int n4 = (((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) ? (nel >> 2) : 0;
+    for (int k = tid; k < n4; k += NT) ((st4*)t1s)[k] = ((const st4*)src)[k];
+    for (int k = 4 * n4 + tid; k < nel; k += NT) t1s[k] = src[k];
   }
   __syncthreads();
   const f4v z4 = {0.f, 0.f, 0.f, 0.f};
@@ -593,15 +634,15 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
   double s_nll = 0.0;
   if (active) {
     // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
-    bf8v ft1[2];
+    V8 ft1[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       const int i1 = 16 * mt + r;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i2 = kw_index(g, u);
-        const unsigned short h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (unsigned short)0;
-        ft1[mt][u] = __builtin_bit_cast(__bf16, h);
+        const ST h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (ST)0;
+        W::set(ft1[mt], u, h);
       }
     }
     const float* V = (const float*)P.v_int;
@@ -614,14 +655,14 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
         const int jl = 2 * jq + h, jb = jb0 + jl;
         if (jb >= NJB) break;
         // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
-        const bf8v ft2 = pack_acc2(mma32(ft1[0], fx2t[jl], z4), mma32(ft1[1], fx2t[jl], z4));
+        const V8 ft2 = W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
 #pragma unroll
         for (int uq = 0; uq < 4; ++uq) {
           const int u0 = 2 * uq;
           if (u0 >= N1T) break;
           // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
-          f4v e0 = mma32(fx1a[u0], ft2, z4);
-          f4v e1 = u0 + 1 < N1T ? mma32(fx1a[u0 + 1], ft2, z4) : z4;
+          f4v e0 = W::mma(fx1a[u0], ft2, z4);
+          f4v e1 = u0 + 1 < N1T ? W::mma(fx1a[u0 + 1], ft2, z4) : z4;
           if (HAS_V) {
             const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
             const f4v v0 = *(const f4v*)(V + t0);
@@ -644,7 +685,7 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
                 if (i1 < G.n1 && i2 < G.n2) {
                   const double eta = (double)e[i];
                   const double y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
-                  // (exp in FP32: eta carries the BF16 chain's error, far above FP32 rounding)
+                  // (exp in FP32: eta carries the chain's own error, at or above FP32 rounding)
                   const double ex = (double)expf(e[i]);
                   s_nll += ex - y * eta;
                   rv = (float)(ex - y);
@@ -655,9 +696,9 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
           }
           if (ADJ) {
             // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
-            const bf8v fr = pack_acc2(e0, e1);
-            s1[h][0] = mma32(fr, fx1b[uq][0], s1[h][0]);
-            s1[h][1] = mma32(fr, fx1b[uq][1], s1[h][1]);
+            const V8 fr = W::pack(e0, e1);
+            s1[h][0] = W::mma(fr, fx1b[uq][0], s1[h][0]);
+            s1[h][1] = W::mma(fr, fx1b[uq][1], s1[h][1]);
           }
         }
       }
@@ -665,9 +706,9 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
       if (ADJ) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-          const bf8v fs = pack_acc2(s1[0][nt], s1[1][nt]);
+          const V8 fs = W::pack(s1[0][nt], s1[1][nt]);
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = mma32(fx2a[mt][jq], fs, s2[mt][nt]);
+          for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
         }
       }
     }
@@ -700,7 +741,7 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
   __syncthreads();
   // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
   if (part == 0) {
-    unsigned short* S2 = (unsigned short*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
+    ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -713,17 +754,16 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
             float v = s2[mt][nt][i];
 #pragma unroll
             for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
-            if (SPW == 4) s2x[m * 4 + sw] = f32_to_bf16(v);
-            else if (sw < nsl) S2[(long long)m * 4] = f32_to_bf16(v);
+            if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
+            else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
           }
         }
   }
   if (SPW == 4) {
-    // the 4 slabs' values of each m form one 8-byte chunk
+    // the 4 slabs' values of each m form one 4-element chunk
     __syncthreads();
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    u32x2* dst = (u32x2*)P.S2 + (long long)grp * P12;
-    for (int m = tid; m < P12; m += NT) dst[m] = ((const u32x2*)s2x)[m];
+    st4* dst = (st4*)P.S2 + (long long)grp * P12;
+    for (int m = tid; m < P12; m += NT) dst[m] = ((const st4*)s2x)[m];
   }
 }
 
@@ -997,7 +1037,7 @@ __global__ void k_pack_chain_image(Geom G, const S* __restrict__ X1, const S* __
 }
 
 size_t chain_image_bytes(int dt, const Geom& G) {
-  if (dt == DT_BF16 && wave_chain_ok(G)) return wave_image_offset(G) + WAVE_IMAGE_BYTES;
+  if ((dt == DT_BF16 || dt == DT_F32) && wave_chain_ok(G)) return wave_image_offset(G, (int)dt_size(dt)) + wave_image_bytes((int)dt_size(dt));
   return (size_t)chain_layout(G, (int)dt_size(dt), dt == DT_F64 ? 8 : 4).image_bytes;
 }
 
@@ -1007,7 +1047,7 @@ hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void
                                    hipStream_t s, int need) {
   dim3 grid(1), blk(WG);
   if (src_dt != DT_F64 && src_dt != dt) return hipErrorInvalidValue;
-  if ((need & PACK_WAVE) && !(dt == DT_BF16 && wave_chain_ok(G))) return hipErrorInvalidValue;
+  if ((need & PACK_WAVE) && !((dt == DT_BF16 || dt == DT_F32) && wave_chain_ok(G))) return hipErrorInvalidValue;
   if (!(need & PACK_LDS)) {
   } else if (src_dt == DT_F64) {
     if (dt == DT_F64) hipLaunchKernelGGL((k_pack_chain_image<double, double>), grid, blk, 0, s, G, (const double*)X1, (const double*)X2, (double*)img);
@@ -1019,11 +1059,16 @@ hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void
     else hipLaunchKernelGGL((k_pack_chain_image<bf16, bf16>), grid, blk, 0, s, G, (const bf16*)X1, (const bf16*)X2, (bf16*)img);
   }
   if (need & PACK_WAVE) {
-    bf16* wimg = (bf16*)((unsigned char*)img + wave_image_offset(G));
-    if (src_dt == DT_F64)
-      hipLaunchKernelGGL((k_pack_wave_image<double>), dim3(WAVE_FRAGS), dim3(64), 0, s, G, (const double*)X1, (const double*)X2, wimg);
+    void* wimg = (unsigned char*)img + wave_image_offset(G, (int)dt_size(dt));
+    dim3 wg(WAVE_FRAGS), wb(64);
+    if (dt == DT_BF16 && src_dt == DT_F64)
+      hipLaunchKernelGGL((k_pack_wave_image<double, bf16>), wg, wb, 0, s, G, (const double*)X1, (const double*)X2, (bf16*)wimg);
+    else if (dt == DT_BF16)
+      hipLaunchKernelGGL((k_pack_wave_image<bf16, bf16>), wg, wb, 0, s, G, (const bf16*)X1, (const bf16*)X2, (bf16*)wimg);
+    else if (src_dt == DT_F64)
+      hipLaunchKernelGGL((k_pack_wave_image<double, float>), wg, wb, 0, s, G, (const double*)X1, (const double*)X2, (float*)wimg);
     else
-      hipLaunchKernelGGL((k_pack_wave_image<bf16>), dim3(WAVE_FRAGS), dim3(64), 0, s, G, (const bf16*)X1, (const bf16*)X2, wimg);
+      hipLaunchKernelGGL((k_pack_wave_image<float, float>), wg, wb, 0, s, G, (const float*)X1, (const float*)X2, (float*)wimg);
   }
   return hipGetLastError();
 }
@@ -1110,14 +1155,17 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
     return hipGetLastError();
   }
   if (wave_chain_used(dt, mode, P.G)) {
-    // one wave per part of a slab's column blocks; 4 slabs per workgroup when that
-    // still gives workgroups to 3/4 of the CUs, else 1 slab and 4 parts per workgroup
-    const bool four = 4 * ((P.G.n3 + 3) / 4) >= 3 * num_cus();
+    // one wave per part of a slab's column blocks; BF16: 4 slabs per workgroup when that
+    // still gives workgroups to 3/4 of the CUs, else 1 slab and 4 parts per workgroup;
+    // FP32 (twice the fragment registers): always 1 slab and 4 parts
+    const bool four = dt == DT_BF16 && 4 * ((P.G.n3 + 3) / 4) >= 3 * num_cus();
     if (nblk_out) *nblk_out = four ? (P.G.n3 + 3) / 4 : P.G.n3;
-#define GLAM_WAVE(M, V)                                                                          \
-    do {                                                                                         \
-      if (four) hipLaunchKernelGGL((k_slab_chain_w<M, V, 4, 2>), dim3(64 * ((P.G.n3 + 255) / 256)), dim3(512), 0, s, P); \
-      else hipLaunchKernelGGL((k_slab_chain_w<M, V, 1, 4>), dim3(32 * ((P.G.n3 + 31) / 32)), dim3(256), 0, s, P); \
+    const dim3 g4(64 * ((P.G.n3 + 255) / 256)), g1(32 * ((P.G.n3 + 31) / 32));
+#define GLAM_WAVE(M, V)                                                                                    \
+    do {                                                                                                   \
+      if (dt == DT_F32) hipLaunchKernelGGL((k_slab_chain_w<float, M, V, 1, 4>), g1, dim3(256), 0, s, P);    \
+      else if (four) hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 4, 2>), g4, dim3(512), 0, s, P);       \
+      else hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 1, 4>), g1, dim3(256), 0, s, P);                 \
     } while (0)
     if (mode == SM_NLL_FWD) GLAM_WAVE(SM_NLL_FWD, false);
     else if (mode == SM_NLL_BWD) GLAM_WAVE(SM_NLL_BWD, false);
