@@ -947,6 +947,12 @@ extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam
   BatchParams B{};
   B.desc = d_desc; B.nprob = nprob; B.off_fwd = d_off_fwd; B.off_slab = d_off_slab; B.off_adj = d_off_adj;
   B.active = d_active; B.step = d_misc;
+  B.wave = batched_wave(dt, Gs.data(), nprob);
+  if (B.wave) {
+    for (int i = 0; i < nprob; ++i) desc[i].ap.s2_kb4 = 1;
+    BCHK(hipMemcpyAsync(d_desc, desc.data(), sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, s));
+    BCHK(hipStreamSynchronize(s));
+  }
   const size_t lds = batched_lds_bytes(dt, Gs.data(), nprob);
   const int tot[3] = {off_fwd[nprob], off_slab[nprob], off_adj[nprob]};
 

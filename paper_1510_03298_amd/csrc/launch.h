@@ -134,7 +134,10 @@ struct BatchParams {
   const int* off_adj;   // prefix sums of slab_adj tiles (also the partials index)
   const int* active;    // problem mask
   int* step;            // inner step counter (read by the prox epilogue)
+  int wave;             // slabs with the register kernel (S2 in 4-deep k-blocks; batched_wave)
 };
+// true when every problem of the batch fits the one-wave-per-slab kernel of this dtype
+bool batched_wave(int dt, const Geom* Gs, int nprob);
 size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
 // tot: {forward tiles, slabs, adjoint tiles} over all problems (the offsets' last entries)
 hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s);

@@ -574,8 +574,9 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
 // consecutive slabs (4 or 1) and NPART waves per slab (2 or 4), each wave taking 8 / NPART
 // of the (at most 8) mode-2 column blocks; the waves' S2 partials are summed in LDS.
 // Partial NLL sums per workgroup in partials[slab group][2].
+// the slabs SPW grp .. SPW grp + SPW - 1 (a whole workgroup of 64 SPW NPART threads)
 template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
-__global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
+__device__ inline void wave_chain_group(const SlabParams& P, int grp) {
   typedef WT<T> W;
   typedef typename W::v8 V8;
   typedef typename W::st ST;
@@ -588,10 +589,6 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
   const Geom& G = P.G;
   const int lane = lane_id(), w = wave_id(), r = lane & 15, g = lane >> 4, tid = threadIdx.x;
   const int sw = w % SPW, part = w / SPW;   // slab within the workgroup, part of the column blocks
-  // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
-  // the 8-byte chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
-  const int b = blockIdx.x, x = b & 7, jj = b >> 3;
-  const int grp = SPW == 4 ? 8 * (x + 8 * (jj >> 3)) + (jj & 7) : 4 * (x + 8 * (jj >> 2)) + (jj & 3);
   const int i3b = SPW * grp;
   if (i3b >= G.n3) return;   // whole workgroup
   const int nsl = min(SPW, G.n3 - i3b);
@@ -767,6 +764,15 @@ __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P)
   }
 }
 
+template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
+__global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
+  // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
+  // the chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
+  const int b = blockIdx.x, x = b & 7, jj = b >> 3;
+  const int grp = SPW == 4 ? 8 * (x + 8 * (jj >> 3)) + (jj & 7) : 4 * (x + 8 * (jj >> 2)) + (jj & 3);
+  wave_chain_group<T, MODE, HAS_V, SPW, NPART>(P, grp);
+}
+
 // ============================================================================
 // slab_adj: out (P12 x p3) = S2^T (P12 x n3) X3a (n3 x p3), split-K over the 4
 // waves of a workgroup (one 16 x 16 output tile per workgroup) + epilogue.
@@ -925,11 +931,11 @@ __device__ inline int find_segment(const int* off, int nseg, int item) {
 // PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem, in
 //       contiguous runs per workgroup so that the factor image is restaged rarely
 // PH 2: mode-3 adjoint tiles + proximal step of every active problem
-template <typename T, int PH>
+template <typename T, int PH, bool WAVE>
 __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
   typedef typename Tr<T>::acc_t A;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (PH == 0) {
+  if constexpr (PH == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *B.step += 1;
     const int totA = B.off_fwd[B.nprob];
     for (int item = blockIdx.x; item < totA; item += gridDim.x) {
@@ -939,7 +945,19 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
       const int loc = item - B.off_fwd[pb];
       fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
     }
-  } else if (PH == 1) {
+  } else if constexpr (PH == 1 && WAVE) {
+    // one slab per item with the one-wave-per-part register kernel (4 waves per slab)
+    const int totB = B.off_slab[B.nprob];
+    for (int item = blockIdx.x; item < totB; item += gridDim.x) {
+      const int pb = find_segment(B.off_slab, B.nprob, item);
+      if (!B.active[pb]) continue;
+      const BatchDesc& D = B.desc[pb];
+      const int i3 = item - B.off_slab[pb];
+      if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4>(D.sp, i3);
+      else wave_chain_group<T, SM_FUSED, false, 1, 4>(D.sp, i3);
+      __syncthreads();   // LDS of the next item
+    }
+  } else if constexpr (PH == 1) {
     const int totB = B.off_slab[B.nprob];
     const int chunk = (totB + gridDim.x - 1) / gridDim.x;
     const int i0 = blockIdx.x * chunk, i1 = min(totB, i0 + chunk);
@@ -1206,22 +1224,34 @@ size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob) {
   return m;
 }
 
-template <typename T>
+template <typename T, bool WAVE>
 static hipError_t batched_phases(const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
   const int cap = 8 * num_cus();
-  const int gA = std::max(1, std::min(tot[0], cap)), gB = std::max(1, std::min(tot[1], 4 * num_cus()));
+  const int gA = std::max(1, std::min(tot[0], cap));
+  const int gB = std::max(1, std::min(tot[1], WAVE ? cap : 4 * num_cus()));
   const int gC = std::max(1, std::min(tot[2], cap));
-  hipLaunchKernelGGL((k_batched_phase<T, 0>), dim3(gA), dim3(WG), 0, s, B);
-  set_lds(k_batched_phase<T, 1>, lds);
-  hipLaunchKernelGGL((k_batched_phase<T, 1>), dim3(gB), dim3(WG), lds, s, B);
-  hipLaunchKernelGGL((k_batched_phase<T, 2>), dim3(gC), dim3(WG), 0, s, B);
+  hipLaunchKernelGGL((k_batched_phase<T, 0, WAVE>), dim3(gA), dim3(WG), 0, s, B);
+  if (WAVE) {
+    hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(gB), dim3(WG), 0, s, B);
+  } else {
+    set_lds(k_batched_phase<T, 1, WAVE>, lds);
+    hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(gB), dim3(WG), lds, s, B);
+  }
+  hipLaunchKernelGGL((k_batched_phase<T, 2, WAVE>), dim3(gC), dim3(WG), 0, s, B);
   return hipGetLastError();
 }
 
+bool batched_wave(int dt, const Geom* Gs, int nprob) {
+  if (dt != DT_BF16 && dt != DT_F32) return false;
+  for (int i = 0; i < nprob; ++i)
+    if (!wave_chain_ok(Gs[i])) return false;
+  return true;
+}
+
 hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
-  if (dt == DT_F64) return batched_phases<double>(B, tot, lds, s);
-  if (dt == DT_F32) return batched_phases<float>(B, tot, lds, s);
-  return batched_phases<bf16>(B, tot, lds, s);
+  if (dt == DT_F64) return batched_phases<double, false>(B, tot, lds, s);
+  if (dt == DT_F32) return B.wave ? batched_phases<float, true>(B, tot, lds, s) : batched_phases<float, false>(B, tot, lds, s);
+  return B.wave ? batched_phases<bf16, true>(B, tot, lds, s) : batched_phases<bf16, false>(B, tot, lds, s);
 }
 
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s) {
