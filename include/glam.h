@@ -60,7 +60,10 @@ const char* glam_last_error(void);
 const char* glam_version(void);
 
 /* Limits of the fused slab kernels: modes 1 and 2 must satisfy
- * p_j <= GLAM_MAX_INNER_P and n_j <= GLAM_MAX_INNER_N (mode 3 is unrestricted). */
+ * p_j <= GLAM_MAX_INNER_P and n_j <= GLAM_MAX_INNER_N (mode 3 is unrestricted).
+ * d = 2 (Sec. 6.4: the package fits d = 2 and d = 3): X_2 (x) X_1 is taken as the d = 3 model
+ * X_2 (x) [1] (x) X_1 with a 1 x 1 middle factor, which keeps every array's vec layout; then
+ * mode 1 has the limits above and mode 2 is unrestricted. */
 #define GLAM_MAX_INNER_P 32
 #define GLAM_MAX_INNER_N 256
 
@@ -72,12 +75,12 @@ const char* glam_version(void);
 size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype);
 
 /* Eta = H(<X_j>, Theta) = rho(X_3, rho(X_2, rho(X_1, Theta)))  (eq. eighteen).
- *   n, p     : host arrays of length d (d == 3).
+ *   n, p     : host arrays of length d (d == 2 or 3).
  *   X        : host array of d device pointers; X[j] -> n_j x p_j of `dtype`.
- *   Theta    : device, p_1 x p_2 x p_3 of `dtype`.
- *   Eta      : device, n_1 x n_2 x n_3; FP64 for GLAM_F64, FP32 otherwise.
+ *   Theta    : device, p_1 x ... x p_d of `dtype`.
+ *   Eta      : device, n_1 x ... x n_d; FP64 for GLAM_F64, FP32 otherwise.
  *   workspace: device, >= glam_rho_workspace_size(...) bytes, 256-byte aligned.
- * Errors: GLAM_EINVAL for d != 3, sizes < 1 or beyond the inner-mode limits,
+ * Errors: GLAM_EINVAL for d not 2 or 3, sizes < 1 or beyond the inner-mode limits,
  * NULL pointers, a bad dtype or a too-small workspace. */
 int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X,
                      const void* Theta, void* Eta, int dtype, void* workspace,
@@ -96,7 +99,7 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
  * lambda path of the GD-PG algorithm (Sec. 3, Algorithm 1; Sec. 6.4)
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int d;                  /* must be 3                                              */
+  int d;                  /* 2 or 3 (entries d.. of n, p, X are ignored)            */
   int64_t n[3], p[3];     /* mode sizes                                             */
   const double* X[3];     /* device, FP64, X[j] is n_j x p_j column-major           */
   const double* Y;        /* device, FP64 response array n_1 x n_2 x n_3            */

@@ -49,9 +49,13 @@ Geom make_geom(const int64_t* n, const int64_t* p) {
 static const size_t kMaxLds = 159 * 1024;   // 160 KB per CU minus static LDS
 
 // Common size validation of the rho-based entry points.
-static int check_sizes(int d, const int64_t* n, const int64_t* p, int dtype, Geom* Gout) {
-  if (d != 3) return fail(GLAM_EINVAL, "only d = 3 is supported");
-  if (!n || !p) return fail(GLAM_EINVAL, "NULL size array");
+static int check_sizes(int d, const int64_t* n_in, const int64_t* p_in, int dtype, Geom* Gout) {
+  if (d != 2 && d != 3) return fail(GLAM_EINVAL, "d must be 2 or 3");
+  if (!n_in || !p_in) return fail(GLAM_EINVAL, "NULL size array");
+  for (int j = 0; j < d; ++j)
+    if (n_in[j] < 1 || p_in[j] < 1) return fail(GLAM_EINVAL, "mode sizes must be >= 1");
+  int64_t n[3], p[3];
+  lift_sizes(d, n_in, p_in, n, p);
   for (int j = 0; j < 3; ++j) {
     if (n[j] < 1 || p[j] < 1) return fail(GLAM_EINVAL, "mode sizes must be >= 1");
     if (n[j] > (1 << 30) || p[j] > (1 << 30)) return fail(GLAM_EINVAL, "mode size too large");
@@ -74,7 +78,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace of the rho / NLL entry points: k-blocked Theta, both packed copies of
 // X_3, fragment-ordered T1, k-blocked S2 and per-workgroup partial sums.
 struct WsLayout {
-  size_t img, inc, x3f, t1, x3a, s2, part, total;
+  size_t img, inc, x3f, t1, x3a, s2, part, unit, total;
 };
 static WsLayout ws_layout(const Geom& G, int dt) {
   const size_t es = dt_size(dt);
@@ -87,6 +91,7 @@ static WsLayout ws_layout(const Geom& G, int dt) {
   W.x3a = o; o += align256(G.x3a_len * es);
   W.s2 = o;  o += align256(G.s2_len * es);
   W.part = o; o += align256((size_t)G.n3 * 2 * sizeof(double));
+  W.unit = o; o += 256;   // the 1 x 1 middle factor of a d = 2 model
   W.total = o;
   return W;
 }
@@ -127,17 +132,33 @@ size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dt
   return ws_layout(G, dtype).total;
 }
 
-int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* Theta, void* Eta,
+// the factor list of the lifted d = 3 model (d = 2: the middle factor is a 1 in the workspace)
+static int lift_factors(int d, const void* const* X, char* ws, const WsLayout& W, int dtype, hipStream_t s,
+                        const void** X3) {
+  if (!X || !X[0] || !X[1] || (d == 3 && !X[2])) return fail(GLAM_EINVAL, "NULL pointer");
+  if (d == 3) {
+    X3[0] = X[0]; X3[1] = X[1]; X3[2] = X[2];
+    return GLAM_OK;
+  }
+  HIPCHK(launch_set_one(dtype, ws + W.unit, s));
+  X3[0] = X[0]; X3[1] = ws + W.unit; X3[2] = X[1];
+  return GLAM_OK;
+}
+
+int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* Theta, void* Eta,
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   Geom G;
   int st = check_sizes(d, n, p, dtype, &G);
   if (st) return st;
-  if (!X || !X[0] || !X[1] || !X[2] || !Theta || !Eta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (!Theta || !Eta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const WsLayout W = ws_layout(G, dtype);
   char* ws = (char*)workspace;
+  const void* X[3];
+  st = lift_factors(d, X_in, ws, W, dtype, s, X);
+  if (st) return st;
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, Theta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
@@ -151,17 +172,20 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
   return GLAM_OK;
 }
 
-int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* U, void* Out,
+int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* U, void* Out,
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   Geom G;
   int st = check_sizes(d, n, p, dtype, &G);
   if (st) return st;
-  if (!X || !X[0] || !X[1] || !X[2] || !U || !Out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (!U || !Out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const WsLayout W = ws_layout(G, dtype);
   char* ws = (char*)workspace;
+  const void* X[3];
+  st = lift_factors(d, X_in, ws, W, dtype, s, X);
+  if (st) return st;
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
   HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));

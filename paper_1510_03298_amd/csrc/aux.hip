@@ -374,6 +374,17 @@ hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* 
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ void k_set_one(T* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = Tr<T>::from_acc((typename Tr<T>::acc_t)1);
+}
+hipError_t launch_set_one(int dt, void* p, hipStream_t s) {
+  if (dt == DT_F64) hipLaunchKernelGGL(k_set_one<double>, dim3(1), dim3(64), 0, s, (double*)p);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_set_one<float>, dim3(1), dim3(64), 0, s, (float*)p);
+  else hipLaunchKernelGGL(k_set_one<bf16>, dim3(1), dim3(64), 0, s, (bf16*)p);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(grid1d(count)), dim3(WG), 0, s, p, count, v);
   return hipGetLastError();

@@ -612,14 +612,48 @@ using namespace glam;
 
 static int fit_fail(int code, const std::string& msg);
 
-extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res) {
-  auto t_start = std::chrono::steady_clock::now();
-  if (!prob || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
-  if (prob->d != 3) return fit_fail(GLAM_EINVAL, "only d = 3 is supported");
-  for (int j = 0; j < 3; ++j) {
-    if (prob->n[j] < 1 || prob->p[j] < 1) return fit_fail(GLAM_EINVAL, "mode sizes must be >= 1");
-    if (!prob->X[j]) return fit_fail(GLAM_EINVAL, "NULL factor");
+// A d = 2 problem X_2 (x) X_1 as the d = 3 problem X_2 (x) [1] (x) X_1 (every array keeps its
+// vec layout; mode 2 becomes the slab mode); unit holds the device FP64 1 of the middle factor.
+struct UnitFactor {
+  double* p = nullptr;
+  ~UnitFactor() { if (p) (void)hipFree(p); }
+};
+static int lift_problem(const glam_problem* in, glam_problem* out, UnitFactor* unit, std::string* why) {
+  if (in->d != 2 && in->d != 3) { *why = "d must be 2 or 3"; return GLAM_EINVAL; }
+  for (int j = 0; j < in->d; ++j) {
+    if (in->n[j] < 1 || in->p[j] < 1) { *why = "mode sizes must be >= 1"; return GLAM_EINVAL; }
+    if (!in->X[j]) { *why = "NULL factor"; return GLAM_EINVAL; }
   }
+  *out = *in;
+  if (in->d == 2) {
+    if (!unit->p) {
+      const double one = 1.0;
+      if (hipMalloc((void**)&unit->p, 256) != hipSuccess) { *why = "device allocation failed"; return GLAM_ENOMEM; }
+      if (hipMemcpy(unit->p, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        *why = "hipMemcpy failed";
+        return GLAM_EDEVICE;
+      }
+    }
+    lift_sizes(2, in->n, in->p, out->n, out->p);
+    out->d = 3;
+    out->X[0] = in->X[0];
+    out->X[1] = unit->p;
+    out->X[2] = in->X[1];
+  }
+  return GLAM_OK;
+}
+
+extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* opt, glam_result* res) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!prob_in || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
+  glam_problem lifted;
+  UnitFactor unit;
+  {
+    std::string why;
+    const int r = lift_problem(prob_in, &lifted, &unit, &why);
+    if (r) return fit_fail(r, why);
+  }
+  const glam_problem* prob = &lifted;
   if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
   if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) return fit_fail(GLAM_EINVAL, "bad family");
   if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
@@ -818,7 +852,7 @@ extern "C" int glam_fit_path(const glam_problem* prob, const glam_options* opt, 
 // glam_fit_batched
 // ============================================================================
 static int validate_problem(const glam_problem* prob, int dtype, std::string* why) {
-  if (prob->d != 3) { *why = "only d = 3 is supported"; return GLAM_EINVAL; }
+  if (prob->d != 3) { *why = "d must be 2 or 3"; return GLAM_EINVAL; }
   for (int j = 0; j < 3; ++j) {
     if (prob->n[j] < 1 || prob->p[j] < 1) { *why = "mode sizes must be >= 1"; return GLAM_EINVAL; }
     if (!prob->X[j]) { *why = "NULL factor"; return GLAM_EINVAL; }
@@ -833,10 +867,18 @@ static int validate_problem(const glam_problem* prob, int dtype, std::string* wh
   return GLAM_OK;
 }
 
-extern "C" int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_options* opt,
+extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const glam_batch_options* opt,
                                 glam_batch_result* res) {
   auto t_start = std::chrono::steady_clock::now();
-  if (!probs || !opt || !res || nprob < 1) return fit_fail(GLAM_EINVAL, "NULL argument or nprob < 1");
+  if (!probs_in || !opt || !res || nprob < 1) return fit_fail(GLAM_EINVAL, "NULL argument or nprob < 1");
+  std::vector<glam_problem> lifted(nprob);
+  UnitFactor unit;
+  for (int i = 0; i < nprob; ++i) {
+    std::string why;
+    const int r = lift_problem(&probs_in[i], &lifted[i], &unit, &why);
+    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + why);
+  }
+  const glam_problem* probs = lifted.data();
   if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)

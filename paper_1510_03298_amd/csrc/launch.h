@@ -197,6 +197,19 @@ hipError_t launch_armijo(const Geom& G, int family, const double* eta_int, const
                          const double* y_int, const double* a_int, int j0, double* partials, int* nblk_out,
                          hipStream_t s);
 hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);
+// p[0] = 1 in dtype dt (the 1 x 1 middle factor of a lifted d = 2 model)
+hipError_t launch_set_one(int dt, void* p, hipStream_t s);
+
+// A d = 2 model X_2 (x) X_1 is the d = 3 model X_2 (x) [1] (x) X_1 (a 1 x 1 middle factor):
+// the same vec layout of every array; mode 2 becomes the slab mode.  Sizes of the lift:
+inline void lift_sizes(int d, const int64_t* n, const int64_t* p, int64_t* n3, int64_t* p3) {
+  if (d == 2) {
+    n3[0] = n[0]; n3[1] = 1; n3[2] = n[1];
+    p3[0] = p[0]; p3[1] = 1; p3[2] = p[1];
+  } else {
+    for (int j = 0; j < 3; ++j) { n3[j] = n[j]; p3[j] = p[j]; }
+  }
+}
 // backtracking redo of a rejected step: x = S(y - delta gy, delta lambda w), inc = x - theta_ref (k-blocked)
 hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
                           const double* theta_ref, double lambda, double delta, double* x, void* inc, hipStream_t s);

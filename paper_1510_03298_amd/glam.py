@@ -141,7 +141,13 @@ def _stream_ptr(stream=None):
 
 
 def _sizes(n, p):
-    return (ctypes.c_int64 * 3)(*[int(v) for v in n]), (ctypes.c_int64 * 3)(*[int(v) for v in p])
+    """Host size arrays (d = len(n) entries, padded to 3)."""
+    pad = [0] * (3 - len(n))
+    return (ctypes.c_int64 * 3)(*([int(v) for v in n] + pad)), (ctypes.c_int64 * 3)(*([int(v) for v in p] + pad))
+
+
+def _ptrs(Xs):
+    return (_vp * 3)(*([x.data_ptr() for x in Xs] + [None] * (3 - len(Xs))))
 
 
 def _fortran_flat(t):
@@ -164,7 +170,7 @@ def from_colmajor(t, dims):
 # ----------------------------------------------------------------------------- rho transforms
 def rho_workspace_size(n, p, dtype):
     nn, pp = _sizes(n, p)
-    return int(glam_rho_workspace_size(3, nn, pp, int(dtype)))
+    return int(glam_rho_workspace_size(len(n), nn, pp, int(dtype)))
 
 
 def rho_forward(Xs, theta, n, p, dtype, eta=None, workspace=None, stream=None):
@@ -178,8 +184,8 @@ def rho_forward(Xs, theta, n, p, dtype, eta=None, workspace=None, stream=None):
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=theta.device)
     if eta is None:
         eta = torch.empty(int(np.prod(n)), dtype=out_dtype(dtype), device=theta.device)
-    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
-    _check(glam_rho_forward(3, nn, pp, xp, theta.data_ptr(), eta.data_ptr(), int(dtype), workspace.data_ptr(),
+    xp = _ptrs(Xs)
+    _check(glam_rho_forward(len(n), nn, pp, xp, theta.data_ptr(), eta.data_ptr(), int(dtype), workspace.data_ptr(),
                             ws_bytes, _stream_ptr(stream)), "glam_rho_forward")
     return eta
 
@@ -195,8 +201,8 @@ def rho_adjoint(Xs, U, n, p, dtype, out=None, workspace=None, stream=None):
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=U.device)
     if out is None:
         out = torch.empty(int(np.prod(p)), dtype=out_dtype(dtype), device=U.device)
-    xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
-    _check(glam_rho_adjoint(3, nn, pp, xp, U.data_ptr(), out.data_ptr(), int(dtype), workspace.data_ptr(),
+    xp = _ptrs(Xs)
+    _check(glam_rho_adjoint(len(n), nn, pp, xp, U.data_ptr(), out.data_ptr(), int(dtype), workspace.data_ptr(),
                             ws_bytes, _stream_ptr(stream)), "glam_rho_adjoint")
     return out
 
@@ -296,8 +302,8 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     torch = _torch()
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
     prob = GlamProblem()
-    prob.d = 3
-    for j in range(3):
+    prob.d = len(n)
+    for j in range(len(n)):
         prob.n[j] = int(n[j])
         prob.p[j] = int(p[j])
         prob.X[j] = Xs[j].data_ptr()
@@ -374,8 +380,8 @@ def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-
     arr = (GlamProblem * nprob)()
     for i, pr in enumerate(problems):
         P = arr[i]
-        P.d = 3
-        for j in range(3):
+        P.d = len(pr["n"])
+        for j in range(len(pr["n"])):
             P.n[j] = int(pr["n"][j])
             P.p[j] = int(pr["p"][j])
             P.X[j] = pr["X"][j].data_ptr()

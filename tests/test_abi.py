@@ -61,7 +61,14 @@ def test_workspace_size_and_limits():
     w32 = glam.glam_rho_workspace_size(3, n, p, glam.F32)
     w64 = glam.glam_rho_workspace_size(3, n, p, glam.F64)
     assert w32 >= 1000 * 900 * 4 * 2 and w64 > w32
-    assert glam.glam_rho_workspace_size(2, n, p, glam.F64) == 0          # d must be 3
+    assert glam.glam_rho_workspace_size(4, n, p, glam.F64) == 0          # d must be 2 or 3
+    assert glam.glam_rho_workspace_size(1, n, p, glam.F64) == 0
+    # d = 2: (n1, n2) = (100, 1000) runs as (100, 1, 1000); mode 2 is the unrestricted slab mode
+    assert glam.glam_rho_workspace_size(2, n, p, glam.F64) > 0
+    n2, p2 = _sizes((100, 5000, 0), (30, 400, 0))
+    assert glam.glam_rho_workspace_size(2, n2, p2, glam.F32) > 0
+    n2, p2 = _sizes((300, 50, 0), (30, 20, 0))
+    assert glam.glam_rho_workspace_size(2, n2, p2, glam.F32) == 0        # n_1 beyond the inner-mode limit
     n, p = _sizes((100, 100, 1000), (33, 30, 200))
     assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # p_1 beyond the inner-mode limit
     n, p = _sizes((0, 100, 1000), (3, 3, 3))

@@ -230,3 +230,33 @@ def test_gram_inner_loop_rejects_inexact_cases():
         glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", obs_w=a, nlambda=2, inner="gram")
     with pytest.raises(glam.GlamError):
         glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=2, nu=0.5, inner="gram")
+
+
+def _problem_2d(n, p, fam, seed):
+    """A d = 2 model (Sec. 6.4: the package fits d = 2 and 3): Gaussian factors, sparse coefficients."""
+    rng = np.random.default_rng(seed)
+    Xs = [rng.standard_normal((nj, pj)) / np.sqrt(pj) for nj, pj in zip(n, p)]
+    th = np.zeros(p)
+    idx = rng.choice(p[0] * p[1], size=max(1, (p[0] * p[1]) // 5), replace=False)
+    th.reshape(-1, order="F")[idx] = rng.standard_normal(idx.size) * (1.0 if fam == "gaussian" else 0.3)
+    eta = O.H(Xs, th)
+    Y = eta + 0.5 * rng.standard_normal(n) if fam == "gaussian" else rng.poisson(np.exp(eta)).astype(np.float64)
+    return Xs, np.asfortranarray(Y)
+
+
+@pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 2), ("poisson", 0), ("poisson", 1)])
+def test_d2_models(fam, dt):
+    """d = 2 fits against the oracle's FP64 KKT evaluator (the oracle's maps are d-generic)."""
+    torch, glam = need_gpu()
+    n, p = (61, 203), (17, 23)
+    Xs, Y = _problem_2d(n, p, fam, 29)
+    print(f"d=2 {fam} dt={dt}", flush=True)
+    Xd = [glam.to_device_colmajor(X, 0) for X in Xs]
+    Yd = glam.to_device_colmajor(Y, 0)
+    res = glam.fit_path(Xd, Yd, n, p, fam, nlambda=4, lambda_min_ratio=0.05, dtype=dt, kkt_tol=1e-6)
+    lm = O.lambda_max(fam, Xs, Y)
+    assert abs(res.lambda_max - lm) <= 1e-12 * lm
+    for l in range(4):
+        th = glam.from_colmajor(res.theta[l], p)
+        g = O.smooth_gradient(fam, Xs, th, Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6

@@ -27,13 +27,22 @@ SHAPES = [
 ]
 
 
+# d = 2 models (run as X_2 (x) [1] (x) X_1)
+SHAPES_2D = [
+    ((37, 53), (9, 13)),
+    ((100, 700), (30, 150)),            # long second mode (the slab mode)
+    ((256, 40), (32, 7)),               # largest first mode
+    ((1, 1), (1, 1)),
+]
+
+
 def _factors(n, p, seed):
     rng = np.random.default_rng(seed)
     return [rng.standard_normal((nj, pj)) for nj, pj in zip(n, p)]
 
 
 @pytest.mark.parametrize("dt", [0, 1, 2])
-@pytest.mark.parametrize("n,p", SHAPES)
+@pytest.mark.parametrize("n,p", SHAPES + SHAPES_2D)
 def test_forward_parity(n, p, dt):
     torch, glam = need_gpu()
     print(f"forward n={n} p={p} dt={dt}", flush=True)
@@ -52,7 +61,7 @@ def test_forward_parity(n, p, dt):
 
 
 @pytest.mark.parametrize("dt", [0, 1, 2])
-@pytest.mark.parametrize("n,p", SHAPES)
+@pytest.mark.parametrize("n,p", SHAPES + SHAPES_2D)
 def test_adjoint_parity(n, p, dt):
     torch, glam = need_gpu()
     print(f"adjoint n={n} p={p} dt={dt}", flush=True)
