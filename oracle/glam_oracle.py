@@ -46,6 +46,10 @@ R9  soft threshold gives exactly 0 at |z| = t; sign(0) = 0.
 R12 no intercept (the paper's model has none).
 R13 the Gaussian objective keeps the y^2/2 term of the log-density, i.e.
     -l/n = (1/2n) sum a (y - eta)^2 (does not move the minimiser).
+R15 elastic net (Sec. 6.3): J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2), the
+    penalty weights scaling both terms; its prox is the soft threshold divided by
+    1 + 2 alpha gamma w_m, lambda_max is the lasso's (the quadratic term has zero
+    slope at 0), and the KKT residual adds 2 alpha lambda w_m theta_m to the gradient.
 """
 from __future__ import annotations
 
@@ -286,15 +290,18 @@ def working_response_eq10(u, w, eta):
 # =============================================================================
 # Penalty, prox, objective, KKT
 # =============================================================================
-def penalty(theta, pen_w=None):
-    """Weighted l1 penalty J(theta) = sum_m w_m |theta_m| (the convex J of eq. (five))."""
-    t = np.abs(vec(theta))
+def penalty(theta, pen_w=None, alpha=0.0):
+    """Weighted penalty J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2): the l1 penalty
+    (alpha = 0) or the elastic net of Sec. 6.3 (R15: the weights scale both terms)."""
+    th = vec(theta)
+    t = np.abs(th) + alpha * th * th
     return float(np.sum(t if pen_w is None else vec(pen_w) * t))
 
 
-def penalty_change(theta_old, theta_new, pen_w=None):
+def penalty_change(theta_old, theta_new, pen_w=None, alpha=0.0):
     """J(theta_new) - J(theta_old) summed entrywise (no subtraction of totals)."""
-    dj = np.abs(vec(theta_new)) - np.abs(vec(theta_old))
+    a, b = vec(theta_old), vec(theta_new)
+    dj = (np.abs(b) - np.abs(a)) + alpha * (b - a) * (b + a)
     return float(np.sum(dj if pen_w is None else vec(pen_w) * dj))
 
 
@@ -313,10 +320,10 @@ def prox_elastic_net(z, gamma, alpha):
     return soft_threshold(z, gamma) / (1.0 + 2.0 * alpha * gamma)
 
 
-def objective(fam, Xs, Theta, Y, lam, a=None, pen_w=None):
+def objective(fam, Xs, Theta, Y, lam, a=None, pen_w=None, alpha=0.0):
     """F = -l/n + lambda J (eq. five under R1)."""
     eta = H(Xs, Theta)
-    return neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(Theta, pen_w)
+    return neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(Theta, pen_w, alpha)
 
 
 def objective_change(fam, eta, xd, t, Y, a=None):
@@ -343,13 +350,15 @@ def smooth_gradient(fam, Xs, Theta, Y, a=None):
     return -G(Xs, score(fam, eta, Y, a)) / Y.size
 
 
-def kkt_residual(Theta, grad, lam, lam_max, pen_w=None):
-    """R6: max_m r_m / lambda_max with the lasso subgradient residual r_m."""
+def kkt_residual(Theta, grad, lam, lam_max, pen_w=None, alpha=0.0):
+    """R6: max_m r_m / lambda_max with the subgradient residual r_m of the penalty
+    (elastic net: the smooth term's derivative 2 alpha w theta joins the gradient)."""
     th = vec(Theta)
     g = vec(grad)
     w = np.ones_like(th) if pen_w is None else vec(pen_w)
     nz = th != 0
-    r = np.where(nz, np.abs(g + lam * w * np.sign(th)), np.maximum(np.abs(g) - lam * w, 0.0))
+    gs = g + 2.0 * alpha * lam * w * th
+    r = np.where(nz, np.abs(gs + lam * w * np.sign(th)), np.maximum(np.abs(gs) - lam * w, 0.0))
     return float(np.max(r)) / lam_max if r.size else 0.0
 
 
@@ -399,7 +408,7 @@ class FitInfo:
 
 
 def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
-             nu=1.0, Lhat=None, Z=None, record=False):
+             nu=1.0, Lhat=None, Z=None, record=False, alpha=0.0):
     """Inner PG loop of Sec. 3.2 on h(x) = (1/2n)||sqrt(W)(Xx - z)||^2.
 
     grad h(x) = G(V * H(x))/n - c_z  with c_z = G(V * Z)/n  (eqs. twentyfive,
@@ -427,7 +436,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
         y = x + om * (x - x_prev)
         gy = grad_h(y)
         while True:
-            x_new = soft_threshold(y - delta * gy, delta * lam * thr_w)
+            x_new = prox_elastic_net(y - delta * gy, delta * lam * thr_w, alpha)
             if nu >= 1.0 or Z is None:
                 break
             dlt = x_new - y
@@ -438,7 +447,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
             delta = max(delta / 2.0, 1.0 / Lhat)
         x_prev, x = x, x_new
         gx = grad_h(x)
-        r = kkt_residual(x, gx, lam, lam_max, pen_w)
+        r = kkt_residual(x, gx, lam, lam_max, pen_w, alpha)
         if record:
             trace.append(x.copy())
         if r <= tol_inner:
@@ -448,7 +457,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
 
 def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
          max_outer=100, max_inner=100000, nu=1.0, alpha0=1.0, b=0.5, v=0.1,
-         max_ls=60, record_inner=False) -> tuple:
+         max_ls=60, record_inner=False, alpha=0.0) -> tuple:
     """GD-PG, Algorithm 1, for one lambda.
 
     Step 2: eta = H(theta^k); U, V (eq. nine), Z (eq. tennew).
@@ -467,8 +476,8 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         eta = H(Xs, theta)
         u = score(fam, eta, Y, a)
         g = -G(Xs, u) / n
-        kkt_k = kkt_residual(theta, g, lam, lam_max, pen_w)
-        F_k = neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(theta, pen_w)
+        kkt_k = kkt_residual(theta, g, lam, lam_max, pen_w, alpha)
+        F_k = neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(theta, pen_w, alpha)
         info.objective_history.append(F_k)
         info.kkt, info.objective, info.outer = kkt_k, F_k, k
         if kkt_k <= tol:
@@ -487,28 +496,28 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         exact_model = fam.name == "gaussian" and (a is None or bool(np.all(a == 1.0)))
         tol_in = 0.5 * tol if exact_model else max(0.1 * tol, 0.1 * kkt_k)
         x, nin, trace = inner_pg(Xs, V, cz, theta, lam, delta, pen_w, tol_in, lam_max,
-                                 max_inner, nu=nu, Lhat=Lhat, Z=Z, record=record_inner)
+                                 max_inner, nu=nu, Lhat=Lhat, Z=Z, record=record_inner, alpha=alpha)
         info.inner.append(nin)
         if record_inner:
             info.inner_traces.append(trace)
         d = x - theta
         xd = H(Xs, d)
-        Delta = -float(np.sum(u * xd)) / n + lam * penalty_change(theta, x, pen_w)
-        alpha = alpha0
+        Delta = -float(np.sum(u * xd)) / n + lam * penalty_change(theta, x, pen_w, alpha)
+        step = alpha0
         for _ in range(max_ls):
-            dF = objective_change(fam, eta, xd, alpha, Y, a) + lam * penalty_change(
-                theta, theta + alpha * d, pen_w)
-            if np.isfinite(dF) and dF <= alpha * v * Delta:
+            dF = objective_change(fam, eta, xd, step, Y, a) + lam * penalty_change(
+                theta, theta + step * d, pen_w, alpha)
+            if np.isfinite(dF) and dF <= step * v * Delta:
                 break
-            alpha *= b
-        info.alphas.append(alpha)
-        theta = theta + alpha * d
+            step *= b
+        info.alphas.append(step)
+        theta = theta + step * d
     return theta, info
 
 
 def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e-4,
              tol=1e-10, max_outer=100, max_inner=100000, nu=1.0, theta0=None,
-             max_lambdas=None):
+             max_lambdas=None, alpha=0.0):
     """lambda path with warm starts (Sec. 6.4).  Returns (lambdas, thetas, infos,
     lam_max).  Stops early, returning the preceding models, when a fit does not
     converge (the packages' early-exit convention, Sec. 6.5)."""
@@ -522,7 +531,7 @@ def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e
     theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
     thetas, infos = [], []
     for lam in lambdas:
-        theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, pen_w, theta, tol, max_outer, max_inner, nu)
+        theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, pen_w, theta, tol, max_outer, max_inner, nu, alpha=alpha)
         thetas.append(theta.copy())
         infos.append(info)
         if not info.converged:

@@ -45,8 +45,18 @@ MUTANTS = {
                   lambda: [P.test_soft_threshold_is_the_l1_prox] + _gauss_pins()),
     # KKT residual with the wrong subgradient sign
     "kkt_sign": ("kkt_residual",
-                 lambda orig: (lambda th, g, lam, lm, pen_w=None: orig(th, -np.asarray(g), lam, lm, pen_w)),
+                 lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0: orig(th, -np.asarray(g), lam, lm, pen_w,
+                                                                               alpha)),
                  lambda: [P.test_kkt_residual_definition] + _gauss_pins()),
+    # elastic-net prox with 1 + alpha gamma instead of 1 + 2 alpha gamma (Sec. 6.3)
+    "enet_prox_factor": ("prox_elastic_net",
+                         lambda orig: (lambda z, gamma, alpha: orig(z, gamma, 0.5 * alpha)),
+                         lambda: [P.test_elastic_net_closed_form_orthogonal_design]),
+    # KKT residual without the elastic net's smooth term
+    "kkt_drops_enet": ("kkt_residual",
+                       lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0: orig(th, g, lam, lm, pen_w, 0.0)),
+                       lambda: [P.test_elastic_net_kkt_residual_definition,
+                                P.test_elastic_net_closed_form_orthogonal_design]),
     # H applies the factors in reverse order (wrong mode index)
     "H_reversed": ("H", lambda orig: (lambda Xs, Th: orig(list(Xs)[::-1], Th)),
                    lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),

@@ -223,6 +223,50 @@ def test_gaussian_closed_form_orthogonal_design():
     assert info.outer == 1  # Gaussian: a single outer pass
 
 
+def test_elastic_net_kkt_residual_definition():
+    """R15: the smooth term's derivative 2 alpha lambda w theta joins the gradient."""
+    th = np.array([0.0, 1.0, -2.0])
+    g = np.array([0.5, -0.3, 0.1])
+    lam, lm, al = 1.0, 2.0, 0.25
+    # gs = g + 2 al lam th = [.5, .2, -.9]; r = [max(.5-1, 0), |.2+1|, |-.9-1|] = [0, 1.2, 1.9]
+    assert abs(O.kkt_residual(th, g, lam, lm, alpha=al) - 0.95) < 1e-15
+    assert abs(O.penalty(th, alpha=al) - (3.0 + 0.25 * 5.0)) < 1e-15
+
+
+def test_elastic_net_closed_form_orthogonal_design():
+    """Sec. 6.3 elastic net with X^T X = n I: the minimiser of
+    (1/2n)||y - X theta||^2 + lambda sum w (|theta| + alpha theta^2) is
+    S_{lambda w}(X^T y / n) / (1 + 2 alpha lambda w), coordinate by coordinate."""
+    d = inputs.random_problem((8, 7, 6), (4, 3, 5), seed=3, basis="orth")
+    Xd = O.kron_design(d.X)
+    N = Xd.shape[0]
+    pen = np.random.default_rng(10).uniform(0.5, 2.0, d.p)
+    lmw = O.lambda_max("gaussian", d.X, d.Y, pen_w=pen)
+    lam, al = 0.3 * lmw, 0.7
+    th, info = O.gdpg("gaussian", d.X, d.Y, lam, lmw, pen_w=pen, tol=1e-13, alpha=al, max_outer=3, max_inner=3000)
+    assert info.converged
+    w = O.vec(pen)
+    expect = O.soft_threshold(Xd.T @ O.vec(d.Y) / N, lam * w) / (1.0 + 2.0 * al * lam * w)
+    np.testing.assert_allclose(O.vec(th), expect, rtol=1e-11, atol=1e-12 * lmw)
+
+
+def test_elastic_net_poisson_is_stationary_on_explicit_design():
+    """Poisson elastic net: the GD-PG solution is a stationary point of the objective
+    on the explicit design (scalar brute force along every coordinate direction)."""
+    d = inputs.random_problem((6, 5, 4), (3, 3, 2), family="poisson", seed=5, basis="gauss", scale=0.3)
+    lm = O.lambda_max("poisson", d.X, d.Y)
+    lam, al = 0.2 * lm, 0.5
+    th, info = O.gdpg("poisson", d.X, d.Y, lam, lm, tol=1e-12, alpha=al, max_outer=60, max_inner=5000)
+    assert info.converged
+    F0 = O.objective("poisson", d.X, th, d.Y, lam, alpha=al)
+    v = O.vec(th)
+    for m in range(v.size):
+        for h in (1e-4, -1e-4):
+            t = v.copy()
+            t[m] += h
+            assert O.objective("poisson", d.X, O.unvec(t, d.p), d.Y, lam, alpha=al) >= F0 - 1e-13
+
+
 @pytest.mark.parametrize("basis", ["bspline", "gauss"])
 def test_gaussian_matches_coordinate_descent(basis):
     """GD-PG (design-free) vs textbook CD on the explicit design (independent algorithm)."""
