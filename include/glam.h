@@ -133,6 +133,11 @@ typedef struct {
                              captured HIP graph (default); 1: plain stream launches */
   int inner_mode;         /* glam_inner: how the inner loop evaluates grad h (the FP64
                              outer steps always use the rho chain)                  */
+  double alpha;           /* elastic-net weight (Sec. 6.3), >= 0: the penalty becomes
+                             J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2); 0 = lasso.
+                             The prox is the soft threshold divided by 1 + 2 alpha delta
+                             lambda w_m; lambda_max is unchanged (the quadratic term has
+                             zero slope at theta = 0)                               */
 } glam_options;
 
 /* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the
@@ -185,6 +190,7 @@ typedef struct {
   int max_inner;          /* batched proximal steps per outer round                      */
   int check_every;        /* steps between host convergence checks                       */
   void* stream;           /* hipStream_t (NULL = default stream)                         */
+  double alpha;           /* elastic-net weight of every problem, as in glam_options     */
 } glam_batch_options;
 
 typedef struct {

@@ -98,6 +98,7 @@ struct Fit {
   void* v_int;             // tiled weights (acc type of the chain) or NULL (Gaussian)
   void *T1c, *S2c;         // chain dtype intermediates
   bool gram = false;       // inner gradient by the Kronecker Gram factors (Sec. 6.2)
+  double enet = 0.0;       // elastic-net weight alpha (Sec. 6.3): J = sum w (|theta| + alpha theta^2)
   double *S1g = nullptr, *S2g = nullptr;   // X_1^T X_1, X_2^T X_2 (FP64)
   void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
   void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
@@ -193,7 +194,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2d; ap.X3a = F.X3ad; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
-  ap.theta = theta_dev; ap.pen_w = F.prob->pen_w; ap.lambda = lambda;
+  ap.theta = theta_dev; ap.pen_w = F.prob->pen_w; ap.lambda = lambda; ap.alpha = F.enet;
   double* part2 = F.part + (size_t)2 * nbc;
   ap.partials = part2;
   int nb = 0;
@@ -230,7 +231,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I)
     FCHK(launch_gram12(F.dt, G, F.inc, F.S1g, F.S2g, F.Zc, F.iter, F.s));
     AdjParams ap{};
-    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w; ap.alpha = F.enet;
     ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
     ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
     FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
@@ -250,7 +251,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
-  ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
+  ap.alpha = F.enet; ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
   ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
   ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
@@ -368,7 +369,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
     AdjParams ap{};
     ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
-    ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
+    ap.alpha = F.enet; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
     ap.x = cur[0]; ap.xp = cur[1]; ap.gp = cur[2]; ap.yprev = cur[3]; ap.gyprev = cur[4];
     ap.x_out = nxt[0]; ap.xp_out = nxt[1]; ap.gp_out = nxt[2]; ap.y_out = nxt[3]; ap.gy_out = nxt[4];
     ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
@@ -383,7 +384,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     if (l >= 2 && sdg > (sdd / delta) * (1.0 + 1e-12) && delta > delta_min * (1.0 + 1e-12)) {
       // divergence of the step into x^l detected: halve delta and redo that step from y_{l-1}
       delta = std::max(0.5 * delta, delta_min);
-      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.prob->pen_w, F.theta, lam, delta, cur[0], F.inc, F.s));
+      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.prob->pen_w, F.theta, lam, delta, F.enet, cur[0], F.inc, F.s));
       continue;
     }
     kin = F.hred[0] / lam_scale;
@@ -427,7 +428,7 @@ static int armijo_enqueue(Fit& F, int j0) {
   FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
   FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
   double* part2 = F.part + (size_t)nb1 * NV;
-  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, j0, part2, &nb2, F.s));
+  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, F.enet, j0, part2, &nb2, F.s));
   FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
   FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
   return GLAM_OK;
@@ -662,6 +663,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
   if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
+  if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
   if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM)
     return fit_fail(GLAM_EINVAL, "bad inner_mode");
   if (opt->inner_mode == GLAM_INNER_GRAM && (prob->family != GLAM_GAUSSIAN || prob->obs_w || opt->nu < 1.0))
@@ -697,6 +699,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
   F.gram = opt->inner_mode == GLAM_INNER_GRAM;
+  F.enet = opt->alpha;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
     if (r) return fit_fail(r, F.err);
@@ -881,6 +884,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   const glam_problem* probs = lifted.data();
   if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
+  if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
   if (!opt->lambda && !(opt->lambda_ratio > 0.0 && opt->lambda_ratio <= 1.0))
@@ -916,6 +920,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     F.s = s;
     F.own_stream = false;
     F.batched = true;
+    F.enet = opt->alpha;
     const int r = fit_setup(F, &probs[i], false, false);
     if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
   }
@@ -972,6 +977,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     D.sp.G = G; D.sp.img = F.imgc; D.sp.T1 = F.T1c; D.sp.S2 = F.S2c; D.sp.v_int = F.v_int;
     D.ap = AdjParams{};
     D.ap.G = G; D.ap.S2 = F.S2c; D.ap.X3a = F.X3ac; D.ap.scale = 1.0 / (double)G.n; D.ap.pen_w = probs[i].pen_w;
+    D.ap.alpha = opt->alpha;
     D.ap.partials = d_part; D.ap.gref = F.gref; D.ap.theta_ref = F.theta; D.ap.x = F.x; D.ap.xp = F.xp;
     D.ap.gp = F.gp; D.ap.inc = F.inc; D.ap.iter = d_misc; D.ap.dparams = F.dparams;
   }

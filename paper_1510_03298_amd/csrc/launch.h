@@ -108,6 +108,7 @@ struct AdjParams {
   const double* gyprev;
   double *x_out, *xp_out, *gp_out, *y_out, *gy_out;
   int s2_kb4;            // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
+  double alpha;          // elastic-net weight (Sec. 6.3): J = sum w (|theta| + alpha theta^2); 0 = lasso
 };
 
 struct FwdParams {
@@ -212,10 +213,11 @@ inline void lift_sizes(int d, const int64_t* n, const int64_t* p, int64_t* n3, i
 }
 // backtracking redo of a rejected step: x = S(y - delta gy, delta lambda w), inc = x - theta_ref (k-blocked)
 hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
-                          const double* theta_ref, double lambda, double delta, double* x, void* inc, hipStream_t s);
+                          const double* theta_ref, double lambda, double delta, double alpha, double* x, void* inc,
+                          hipStream_t s);
 // sum_m w_m (|theta_m + t_j d_m| - |theta_m|) for t = 1 (slot 0) and the Armijo trial steps (slots 1..)
-hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, int j0,
-                             double* partials, int* nblk_out, hipStream_t s);
+hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, double alpha,
+                             int j0, double* partials, int* nblk_out, hipStream_t s);
 // data checks, per-block maxima of 4 indicators: non-finite y, negative y (Poisson),
 // negative or non-finite a, non-positive or non-finite pen_w
 hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int poisson,

@@ -838,8 +838,9 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       if (P.theta) {
         const double th = e_th;
         const double lw = P.lambda * wm;
-        red_kkt = th != 0.0 ? fabs(gv + copysign(lw, th)) : fmax(fabs(gv) - lw, 0.0);
-        red_pen = wm * fabs(th);
+        const double gs = gv + 2.0 * P.alpha * lw * th;   // elastic net: the smooth term's slope
+        red_kkt = th != 0.0 ? fabs(gs + copysign(lw, th)) : fmax(fabs(gs) - lw, 0.0);
+        red_pen = wm * (fabs(th) + P.alpha * th * th);
       }
     } else if (EPI == EPI_PROX_BT) {
       // inner PG step with Beck-Teboulle backtracking state (step size control nu < 1):
@@ -852,14 +853,16 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double x = e_x, xp = e_xp, gp = e_gp;
       const double wm = e_w;
       const double lw = lam * wm;
-      red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
+      const double gs = gx + 2.0 * P.alpha * lw * x;   // elastic net: the smooth term's slope
+      red_kkt = x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0);
       red_noise = fabs(incg);
       const double dv = x - e_y;
       red_dg = dv * (gx - e_gy);
       red_dd = dv * dv;
       const double gy = gx + om * (gx - gp);
       const double yv = x + om * (x - xp);
-      const double xn = soft_threshold(yv - delta * gy, delta * lw);
+      // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
+      const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
       P.x_out[j] = xn;
       P.xp_out[j] = x;
       P.gp_out[j] = gx;
@@ -879,11 +882,13 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double x = e_x, xp = e_xp, gp = e_gp;
       const double wm = e_w;
       const double lw = lam * wm;
-      red_kkt = x != 0.0 ? fabs(gx + copysign(lw, x)) : fmax(fabs(gx) - lw, 0.0);
+      const double gs = gx + 2.0 * P.alpha * lw * x;   // elastic net: the smooth term's slope
+      red_kkt = x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0);
       red_noise = fabs(incg);
       const double gy = gx + om * (gx - gp);          // grad h(y) by linearity (h quadratic)
       const double yv = x + om * (x - xp);
-      const double xn = soft_threshold(yv - delta * gy, delta * lw);
+      // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
+      const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
       P.xp[j] = x;
       P.x[j] = xn;
       P.gp[j] = gx;

@@ -44,7 +44,7 @@ class GlamOptions(ctypes.Structure):
                 ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
                 ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int),
-                ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int)]
+                ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int), ("alpha", ctypes.c_double)]
 
 
 class GlamResult(ctypes.Structure):
@@ -59,7 +59,8 @@ class GlamResult(ctypes.Structure):
 class GlamBatchOptions(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("lambda_ratio", ctypes.c_double),
                 ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("max_inner", ctypes.c_int), ("check_every", ctypes.c_int), ("stream", _vp)]
+                ("max_inner", ctypes.c_int), ("check_every", ctypes.c_int), ("stream", _vp),
+                ("alpha", ctypes.c_double)]
 
 
 class GlamBatchResult(ctypes.Structure):
@@ -296,9 +297,10 @@ class PathResult:
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
              check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
-             graph=True, inner="chain") -> PathResult:
+             graph=True, inner="chain", alpha=0.0) -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
-    1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays."""
+    1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
+    alpha: elastic-net weight (0 = lasso)."""
     torch = _torch()
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
     prob = GlamProblem()
@@ -330,6 +332,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.profile_every = int(profile_every)
     opt.graph_mode = 0 if graph else 1
     opt.inner_mode = {"chain": 0, "gram": 1}[inner]
+    opt.alpha = float(alpha)
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()
@@ -371,7 +374,7 @@ class BatchResult:
 
 
 def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-6, max_outer=100,
-                max_inner=100000, check_every=10, stream=None, raise_on_error=True) -> BatchResult:
+                max_inner=100000, check_every=10, stream=None, raise_on_error=True, alpha=0.0) -> BatchResult:
     """Fit many independent problems (one lambda each) with three batched launches per
     batched proximal step.  problems: list of dicts with keys X (3 FP64 device
     factors), Y (FP64 device n-array), n, p, family, and optional obs_w, pen_w."""
@@ -400,6 +403,7 @@ def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-
     opt.kkt_tol = float(kkt_tol)
     opt.max_outer, opt.max_inner, opt.check_every = int(max_outer), int(max_inner), int(check_every)
     opt.stream = _stream_ptr(stream)
+    opt.alpha = float(alpha)
     dev = problems[0]["Y"].device
     thetas = [torch.zeros(int(np.prod(pr["p"])), dtype=torch.float64, device=dev) for pr in problems]
     tp = (_vp * nprob)(*[t.data_ptr() for t in thetas])

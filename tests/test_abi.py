@@ -118,3 +118,8 @@ def test_invalid_arguments_rejected_without_device_work():
     lam2 = (ctypes.c_double * 3)(3.0, 2.0, 1.0)
     opt.lambda_ = lam2
     assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+    opt.nu = 1.0
+    for bad in (-0.5, float("nan"), float("inf")):   # elastic-net weight must be finite and >= 0
+        opt.alpha = bad
+        rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+        assert rc == glam.GLAM_EINVAL and b"alpha" in glam.glam_last_error()

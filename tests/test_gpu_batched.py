@@ -73,3 +73,19 @@ def test_batched_full_c4_sampled():
         th = glam.from_colmajor(res.theta[i], d.p)
         g = O.smooth_gradient(d.family, d.X, th, d.Y)
         assert O.kkt_residual(th, g, 0.1 * lm, lm) <= 1e-6, i
+
+
+def test_batched_elastic_net():
+    """Sec. 6.3 elastic net in the batched solver: the oracle's elastic-net KKT
+    evaluator on every problem."""
+    torch, glam = need_gpu()
+    probs = inputs.config_c4(nprob=5, lo=16, hi=40, seed_offset=43)
+    res = glam.fit_batched([_upload(glam, d) for d in probs], lambda_ratio=0.1, dtype=2, kkt_tol=1e-6, alpha=1.0)
+    assert res.code == 0 and np.all(res.status == 0)
+    for i, d in enumerate(probs):
+        lm = O.lambda_max(d.family, d.X, d.Y)
+        th = glam.from_colmajor(res.theta[i], d.p)
+        g = O.smooth_gradient(d.family, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, 0.1 * lm, lm, alpha=1.0) <= 1e-6
+        F = O.objective(d.family, d.X, th, d.Y, 0.1 * lm, alpha=1.0)
+        assert abs(res.objective[i] - F) <= 1e-9 * abs(F)

@@ -260,3 +260,47 @@ def test_d2_models(fam, dt):
         th = glam.from_colmajor(res.theta[l], p)
         g = O.smooth_gradient(fam, Xs, th, Y)
         assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
+
+
+@pytest.mark.parametrize("fam,dt,nu", [("gaussian", 0, 1.0), ("gaussian", 2, 1.0), ("poisson", 0, 1.0),
+                                       ("poisson", 1, 1.0), ("gaussian", 1, 0.5), ("poisson", 2, 0.5)])
+def test_elastic_net_path(fam, dt, nu):
+    """Sec. 6.3 elastic net (alpha = 0.5): every model on the path meets the oracle's
+    elastic-net KKT condition, and its objective is the oracle's minimum (the
+    elastic-net PMLE is unique: the quadratic term makes it strictly convex)."""
+    torch, glam = need_gpu()
+    alpha = 0.5
+    d = inputs.random_problem((21, 17, 29), (8, 7, 9), family=fam, seed=31)
+    print(f"elastic net {fam} dt={dt} nu={nu}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=5, lambda_min_ratio=0.02, dtype=dt, kkt_tol=1e-7,
+                        nu=nu, alpha=alpha)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    assert abs(res.lambda_max - lm) <= 1e-12 * lm
+    for l in range(5):
+        th = _theta(glam, res, l, d.p)
+        lam = res.lambdas[l]
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, lam, lm, alpha=alpha) <= 1e-7
+        F1 = O.objective(fam, d.X, th, d.Y, lam, alpha=alpha)
+        assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
+        ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200, alpha=alpha)
+        F2 = O.objective(fam, d.X, ref, d.Y, lam, alpha=alpha)
+        assert (F1 - F2) / abs(F2) <= 1e-8
+        assert rel_inf(th, ref) <= 1e-4
+    # the quadratic term shrinks the model against the lasso fit at the same lambda
+    las = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[res.lambdas[-1]], dtype=dt, kkt_tol=1e-7, nu=nu)
+    assert np.sum(np.abs(_theta(glam, res, 4, d.p))) < np.sum(np.abs(_theta(glam, las, 0, d.p)))
+
+
+def test_elastic_net_gram_inner_loop():
+    torch, glam = need_gpu()
+    d = inputs.random_problem((23, 19, 37), (9, 7, 12), seed=32)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=4, lambda_min_ratio=0.01, dtype=2, kkt_tol=1e-6,
+                        inner="gram", alpha=2.0)
+    for l in range(4):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient("gaussian", d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm, alpha=2.0) <= 1e-6
