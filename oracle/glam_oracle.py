@@ -46,6 +46,12 @@ R9  soft threshold gives exactly 0 at |z| = t; sign(0) = 0.
 R12 no intercept (the paper's model has none).
 R13 the Gaussian objective keeps the y^2/2 term of the log-density, i.e.
     -l/n = (1/2n) sum a (y - eta)^2 (does not move the minimiser).
+R16 families beyond Gaussian and Poisson (Sec. 6.4 lists Binomial-logit and Gamma-log):
+    Binomial responses are proportions in [0, 1]; Gamma has dispersion 1 and
+    y > 0.  The IRLS weight is eq. (nine) as printed, vartheta'(eta) (g^{-1})'(eta):
+    mu (1 - mu) for the logit, and exactly 1 for the Gamma-log model (Fisher
+    scoring, a non-canonical link), so Gamma shares the Gaussian's unit weights
+    but not its exact quadratic model.
 R15 elastic net (Sec. 6.3): J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2), the
     penalty weights scaling both terms; its prox is the soft threshold divided by
     1 + 2 alpha gamma w_m, lambda_max is the lasso's (the quadratic term has zero
@@ -161,7 +167,9 @@ def rho_chain_flops(n: Sequence[int], p: Sequence[int], order: Sequence[int]) ->
 
 
 # =============================================================================
-# App. B: exponential families (canonical links for Gaussian and Poisson)
+# App. B: exponential families.  Gaussian-identity, Poisson-log and Binomial-logit
+# are canonical (vartheta = eta); Gamma-log is not (vartheta = -1/mu).  These four
+# are the models the paper's package supports (Sec. 6.4).
 # =============================================================================
 class Family:
     name = ""
@@ -237,7 +245,63 @@ class Poisson(Family):
         return np.exp(th)
 
 
-FAMILIES = {"gaussian": Gaussian(), "poisson": Poisson()}
+def _softplus(t):
+    """log(1 + e^t) without overflow."""
+    return np.logaddexp(0.0, t)
+
+
+class Binomial(Family):
+    """Logit link (canonical): vartheta(eta) = eta, b(t) = log(1 + e^t),
+    g^{-1}(eta) = 1 / (1 + e^-eta); responses are proportions y in [0, 1]
+    (a binomial count out of m trials enters as y = count / m with a = m)."""
+    name = "binomial"
+
+    def ginv(self, eta):
+        return 0.5 * (1.0 + np.tanh(0.5 * eta))
+
+    def dginv(self, eta):
+        mu = self.ginv(eta)
+        return mu * (1.0 - mu)
+
+    def dtheta(self, eta):
+        return np.ones_like(eta)
+
+    def gprime(self, mu):
+        return 1.0 / (mu * (1.0 - mu))
+
+    def theta(self, eta):
+        return eta
+
+    def b(self, th):
+        return _softplus(th)
+
+
+class Gamma(Family):
+    """Log link (not canonical): mu = e^eta, vartheta(eta) = -1/mu = -e^-eta,
+    b(t) = -log(-t) (dispersion 1; its scale does not move the PMLE's support
+    pattern along a lambda path, it rescales lambda).  Responses y > 0."""
+    name = "gamma"
+
+    def ginv(self, eta):
+        return np.exp(eta)
+
+    def dginv(self, eta):
+        return np.exp(eta)
+
+    def dtheta(self, eta):
+        return np.exp(-eta)
+
+    def gprime(self, mu):
+        return 1.0 / mu
+
+    def theta(self, eta):
+        return -np.exp(-eta)
+
+    def b(self, th):
+        return -np.log(-th)
+
+
+FAMILIES = {"gaussian": Gaussian(), "poisson": Poisson(), "binomial": Binomial(), "gamma": Gamma()}
 
 
 def family(name) -> Family:
@@ -334,14 +398,24 @@ def objective_change(fam, eta, xd, t, Y, a=None):
     fam = family(fam)
     a = np.ones_like(Y) if a is None else a
     s = t * xd
-    if fam.name == "gaussian":
-        db = s * (eta + 0.5 * s)
-    elif fam.name == "poisson":
-        db = np.exp(eta) * np.expm1(s)
-    else:
-        db = fam.b(fam.theta(eta + s)) - fam.b(fam.theta(eta))
     with np.errstate(over="ignore", invalid="ignore"):
-        return float(np.sum(a * (db - Y * s))) / Y.size
+        if fam.name == "gaussian":
+            dl = s * (eta + 0.5 * s) - Y * s
+        elif fam.name == "poisson":
+            dl = np.exp(eta) * np.expm1(s) - Y * s
+        elif fam.name == "binomial":
+            # b(eta + s) - b(eta) = log(1 + mu (e^s - 1)), mu = g^{-1}(eta); for s < 0 the same
+            # identity taken from eta + s back to eta (both arguments of log1p stay >= 0)
+            up = np.log1p(fam.ginv(eta) * np.expm1(np.abs(s)))
+            dn = -np.log1p(fam.ginv(eta + s) * np.expm1(np.abs(s)))
+            dl = np.where(s >= 0, up, dn) - Y * s
+        elif fam.name == "gamma":
+            # b(vartheta) = eta and -y vartheta = y e^-eta:  s + y e^-eta (e^-s - 1)
+            dl = s + Y * np.exp(-eta) * np.expm1(-s)
+        else:
+            th0, th1 = fam.theta(eta), fam.theta(eta + s)
+            dl = (fam.b(th1) - fam.b(th0)) - Y * (th1 - th0)
+        return float(np.sum(a * dl)) / Y.size
 
 
 def smooth_gradient(fam, Xs, Theta, Y, a=None):

@@ -99,7 +99,7 @@ def basis_count(n_j: int, k: int) -> int:
 @dataclass
 class GlamData:
     name: str
-    family: str                    # "gaussian" | "poisson"
+    family: str                    # "gaussian" | "poisson" | "binomial" | "gamma"
     X: List[np.ndarray]            # X[j] is n_j x p_j, float64, C-contiguous
     Y: np.ndarray                  # n1 x n2 x n3 float64 (Fortran order)
     a: Optional[np.ndarray] = None  # observation weights (None: all ones)
@@ -267,8 +267,14 @@ def random_problem(n, p, family="gaussian", seed=0, sparsity=0.2, noise=0.5, bas
     eta = _signal_from_coefficients(X, theta)
     if family == "gaussian":
         Y = eta + noise * rng.standard_normal(n)
-    else:
+    elif family == "poisson":
         Y = rng.poisson(np.exp(np.clip(eta, -20, 5))).astype(np.float64)
+    elif family == "binomial":   # Bernoulli responses with success probability 1 / (1 + e^-eta)
+        Y = (rng.uniform(size=n) < 1.0 / (1.0 + np.exp(-np.clip(eta, -30, 30)))).astype(np.float64)
+    elif family == "gamma":      # Gamma responses of shape 2 and mean e^eta
+        Y = rng.gamma(2.0, 0.5 * np.exp(np.clip(eta, -5, 5)))
+    else:
+        raise ValueError(family)
     a = None
     if obs_weights:
         a = rng.uniform(0.5, 1.5, size=n)

@@ -57,6 +57,25 @@ MUTANTS = {
                        lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0: orig(th, g, lam, lm, pen_w, 0.0)),
                        lambda: [P.test_elastic_net_kkt_residual_definition,
                                 P.test_elastic_net_closed_form_orthogonal_design]),
+    # Gamma-log score taken as if the link were canonical (vartheta' = 1 dropped)
+    "gamma_score_canonical": ("score",
+                              lambda orig: (lambda fam, eta, y, a=None: (
+                                  (np.ones_like(y) if a is None else a) * (y - np.exp(eta))
+                                  if O.family(fam).name == "gamma" else orig(fam, eta, y, a))),
+                              lambda: [lambda: P.test_identity_factors_closed_form("gamma"),
+                                       lambda: P.test_score_is_derivative_of_loglik("gamma")]),
+    # Binomial IRLS weight mu instead of mu (1 - mu) (eq. nine)
+    "binomial_weight_mu": ("irls_weights",
+                           lambda orig: (lambda fam, eta: O.family(fam).ginv(eta)
+                                         if O.family(fam).name == "binomial" else orig(fam, eta)),
+                           lambda: [lambda: P.test_score_is_derivative_of_loglik("binomial"),
+                                    lambda: P.test_working_response_forms_agree("binomial")]),
+    # Binomial Armijo change without the -y s term
+    "binomial_change_drops_ys": ("objective_change",
+                                 lambda orig: (lambda fam, eta, xd, t, Y, a=None: orig(fam, eta, xd, t, Y, a) + (
+                                     float(np.sum((np.ones_like(Y) if a is None else a) * Y * t * xd)) / Y.size
+                                     if O.family(fam).name == "binomial" else 0.0)),
+                                 lambda: [lambda: P.test_objective_change_is_the_difference_of_objectives("binomial")]),
     # H applies the factors in reverse order (wrong mode index)
     "H_reversed": ("H", lambda orig: (lambda Xs, Th: orig(list(Xs)[::-1], Th)),
                    lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),

@@ -91,12 +91,26 @@ def test_flop_model_square_factors():
 
 
 # ---------------------------------------------------------------- App. B ----
-@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+def _responses(fam, rng, size):
+    """Valid responses of each family: reals, counts, proportions, positive reals."""
+    if fam == "poisson":
+        return rng.poisson(3.0, size=size).astype(float)
+    if fam == "binomial":
+        return rng.uniform(0.0, 1.0, size=size)
+    if fam == "gamma":
+        return rng.gamma(2.0, 1.0, size=size)
+    return rng.standard_normal(size)
+
+
+FAMS = ["gaussian", "poisson", "binomial", "gamma"]
+
+
+@pytest.mark.parametrize("fam", FAMS)
 def test_working_response_forms_agree(fam):
     """eq. (ten) z = W^{-1}u + eta equals eq. (tennew) with the weights of eq. (nine)."""
     rng = np.random.default_rng(5)
     eta = rng.uniform(-2, 2, size=50)
-    y = rng.poisson(3.0, size=50).astype(float) if fam == "poisson" else rng.standard_normal(50)
+    y = _responses(fam, rng, 50)
     a = rng.uniform(0, 2, size=50)
     u = O.score(fam, eta, y, a)
     w = O.irls_weights(fam, eta)
@@ -104,12 +118,12 @@ def test_working_response_forms_agree(fam):
                                rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+@pytest.mark.parametrize("fam", FAMS)
 def test_score_is_derivative_of_loglik(fam):
     """u = grad_eta l (eq. four) checked by central differences of eq. (two)."""
     rng = np.random.default_rng(6)
     eta = rng.uniform(-1, 1, size=8)
-    y = rng.poisson(2.0, size=8).astype(float)
+    y = _responses(fam, rng, 8)
     a = rng.uniform(0.5, 1.5, size=8)
     u = O.score(fam, eta, y, a)
     h = 1e-6
@@ -119,10 +133,32 @@ def test_score_is_derivative_of_loglik(fam):
         e2[i] -= h
         fd = (O.loglik(fam, e1, y, a) - O.loglik(fam, e2, y, a)) / (2 * h)
         assert abs(fd - u[i]) < 1e-7 * max(1, abs(u[i]))
-    # eq. (nine): for canonical links the weight is the derivative of the mean
+    # eq. (nine): the weight is the expected information, -d^2 l / d eta^2 at y = mu
+    # (for canonical links this is the derivative of the mean whatever y is)
     w = O.irls_weights(fam, eta)
-    mu_d = (O.family(fam).ginv(eta + h) - O.family(fam).ginv(eta - h)) / (2 * h)
-    np.testing.assert_allclose(w, mu_d, rtol=1e-8)
+    mu = O.family(fam).ginv(eta)
+    h2 = 1e-4
+    for i in range(8):
+        f = [O.loglik(fam, np.array([eta[i] + k * h2]), np.array([mu[i]])) for k in (-1, 0, 1)]
+        info = -(f[0] - 2 * f[1] + f[2]) / (h2 * h2)
+        assert abs(info - w[i]) < 1e-5 * max(1.0, w[i]), (i, info, w[i])
+    if fam != "gamma":
+        mu_d = (O.family(fam).ginv(eta + h) - O.family(fam).ginv(eta - h)) / (2 * h)
+        np.testing.assert_allclose(w, mu_d, rtol=1e-8)
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_objective_change_is_the_difference_of_objectives(fam):
+    """R5: the entrywise change along t xd equals the difference of the two totals
+    (at sizes where subtracting the totals loses nothing), for steps of both signs."""
+    rng = np.random.default_rng(8)
+    eta = rng.uniform(-3, 3, size=40)
+    xd = rng.uniform(-2, 2, size=40)
+    y = _responses(fam, rng, 40)
+    a = rng.uniform(0.5, 1.5, size=40)
+    for t in (1.0, 0.25, -0.5, 1e-3):
+        direct = O.neg_loglik_scaled(fam, eta + t * xd, y, a) - O.neg_loglik_scaled(fam, eta, y, a)
+        assert abs(O.objective_change(fam, eta, xd, t, y, a) - direct) <= 1e-12 * max(1.0, abs(direct))
 
 
 def test_gaussian_objective_is_half_rss():
@@ -181,7 +217,7 @@ def test_exact_lipschitz_for_tensor_product_weights():
 
 
 # ------------------------------------------------------- lambda_max, KKT ----
-@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+@pytest.mark.parametrize("fam", FAMS)
 def test_lambda_max_gives_zero_solution(fam):
     """Sec. 6.4: lambda_max is the infimum of lambdas with the zero solution."""
     d = inputs.random_problem((5, 4, 4), (3, 3, 2), family=fam, seed=1, scale=0.5, basis="gauss")
@@ -194,6 +230,72 @@ def test_lambda_max_gives_zero_solution(fam):
     Xd = O.kron_design(d.X)
     u0 = O.score(fam, np.zeros(Xd.shape[0]), O.vec(d.Y))
     assert abs(np.max(np.abs(Xd.T @ u0)) / Xd.shape[0] - lm) <= 1e-13 * lm
+
+
+@pytest.mark.parametrize("fam", ["binomial", "gamma"])
+def test_identity_factors_closed_form(fam):
+    """X_j = I makes every cell its own one-parameter problem,
+    (1/n)(b(theta(t)) - y theta(t)) + lambda w |t|, whose minimiser is closed form:
+    Binomial-logit  t = logit(y - n lambda w s),     zero iff |y - 1/2| <= n lambda w;
+    Gamma-log       t = log(y / (1 + n lambda w s)), zero iff |y - 1| <= n lambda w;
+    with s = sign(t).  GD-PG (outer Armijo steps included) must land on it."""
+    n = (3, 2, 2)
+    N = 12
+    rng = np.random.default_rng(11)
+    Xs = [np.eye(k) for k in n]
+    if fam == "binomial":
+        Y = rng.uniform(0.08, 0.92, size=n)
+        gap = np.abs(O.vec(Y) - 0.5)
+    else:
+        Y = rng.uniform(0.25, 4.0, size=n)
+        gap = np.abs(O.vec(Y) - 1.0)
+    pen = rng.uniform(0.5, 1.5, size=n)
+    w = O.vec(pen)
+    lam = float(np.median(gap / w)) / N     # about half of the cells stay at zero
+    lm = O.lambda_max(fam, Xs, Y, pen_w=pen)
+    assert abs(lm - np.max(gap / w) / N) <= 1e-14 * lm
+    th, info = O.gdpg(fam, Xs, Y, lam, lm, pen_w=pen, tol=1e-12, max_outer=200)
+    assert info.converged
+    y = O.vec(Y)
+    with np.errstate(invalid="ignore", divide="ignore"):   # the log branch is discarded where zero
+        if fam == "binomial":
+            s = np.sign(y - 0.5)
+            q = y - N * lam * w * s
+            expect = np.where(gap <= N * lam * w, 0.0, np.log(q / (1 - q)))
+        else:
+            s = np.sign(y - 1.0)
+            expect = np.where(gap <= N * lam * w, 0.0, np.log(y / (1 + N * lam * w * s)))
+    assert np.count_nonzero(expect) not in (0, N)
+    np.testing.assert_allclose(O.vec(th), expect, rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("fam", ["binomial", "gamma"])
+def test_new_families_stationary_on_explicit_design(fam):
+    """Binomial and Gamma lasso fits on a dense Gaussian design: no coordinate move,
+    of either sign, lowers the objective evaluated on the explicit Kronecker design."""
+    d = inputs.random_problem((6, 5, 4), (3, 3, 2), family=fam, seed=12, basis="gauss", scale=0.3)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    lam = 0.1 * lm
+    th, info = O.gdpg(fam, d.X, d.Y, lam, lm, tol=1e-12, max_outer=200, max_inner=20000)
+    assert info.converged and np.count_nonzero(th) >= 2
+    Xd = O.kron_design(d.X)
+    y = O.vec(d.Y)
+
+    def F(v):
+        eta = Xd @ v
+        if fam == "binomial":
+            nll = np.logaddexp(0.0, eta) - y * eta
+        else:
+            nll = y * np.exp(-eta) + eta
+        return float(np.mean(nll)) + lam * float(np.sum(np.abs(v)))
+    v = O.vec(th)
+    F0 = F(v)
+    assert abs(F0 - O.objective(fam, d.X, th, d.Y, lam)) <= 1e-12 * abs(F0)
+    for m in range(v.size):
+        for h in (1e-4, -1e-4):
+            t = v.copy()
+            t[m] += h
+            assert F(t) >= F0 - 1e-13
 
 
 def test_kkt_residual_definition():
