@@ -45,7 +45,12 @@ typedef enum {
   GLAM_ENONFINITE = 5   /* a non-finite gradient or objective was produced         */
 } glam_status;
 
-typedef enum { GLAM_GAUSSIAN = 0, GLAM_POISSON = 1 } glam_family;
+/* Exponential families of App. B with the links the paper's package supports (Sec. 6.4).
+ * Response ranges (checked on the device, GLAM_EINVAL otherwise): Gaussian any finite y;
+ * Poisson y >= 0; Binomial proportions 0 <= y <= 1 (counts out of m trials: y = count/m with
+ * prior weight a = m); Gamma y > 0 (dispersion 1).  IRLS weights (eq. nine): 1, mu,
+ * mu (1 - mu) and 1 respectively (Gamma-log is a non-canonical link: Fisher scoring). */
+typedef enum { GLAM_GAUSSIAN = 0, GLAM_POISSON = 1, GLAM_BINOMIAL = 2, GLAM_GAMMA = 3 } glam_family;
 
 /* Element type of the rho products.  F64: all FP64.  F32: FP32 inputs and
  * outputs, FP32 accumulation.  BF16: bfloat16 inputs (stored as uint16_t),

@@ -140,6 +140,12 @@ __global__ void k_fill(double* p, long long count, double v) {
     p[i] = v;
 }
 
+// 1 / (1 + e^-x) with full relative precision on both tails
+__device__ inline double logistic(double x) {
+  const double ex = exp(-fabs(x));
+  return x >= 0.0 ? 1.0 / (1.0 + ex) : ex / (1.0 + ex);
+}
+
 // Armijo trials (Sec. 5): change of the smooth part of F along t * xd for the
 // step sizes t_j = 2^-(j0 + j), j < ARMIJO_TRIALS, plus sum u . xd (for Delta_k).
 // Padding cells carry a = 0 and contribute nothing.
@@ -154,13 +160,26 @@ __global__ __launch_bounds__(WG) void k_armijo(Geom G, int family, const double*
     const double av = a[t];
     if (av == 0.0) continue;
     const double e = eta[t], s0 = xd[t], yv = y[t];
-    const double mu = family == 1 ? exp(e) : e;
-    acc[0] += av * (yv - mu) * s0;
+    // u (the score, App. B) and the change of -l along s = t xd for each family, written
+    // as differences that never subtract two large values
+    double mu, u;
+    if (family == 1) { mu = exp(e); u = yv - mu; }
+    else if (family == 2) { mu = logistic(e); u = yv - mu; }
+    else if (family == 3) { mu = exp(-e); u = yv * mu - 1.0; }   // here mu holds e^-eta
+    else { mu = e; u = yv - e; }
+    acc[0] += av * u * s0;
 #pragma unroll
     for (int j = 0; j < ARMIJO_TRIALS; ++j) {
       const double s = ldexp(s0, -(j0 + j));
-      const double db = family == 1 ? mu * expm1(s) : s * (e + 0.5 * s);
-      acc[1 + j] += av * (db - yv * s);
+      double dl;
+      if (family == 1) dl = mu * expm1(s) - yv * s;
+      else if (family == 2) {
+        // b(eta + s) - b(eta) = log(1 + mu (e^s - 1)); for s < 0 taken from eta + s back to eta
+        const double em = expm1(fabs(s));
+        dl = (s >= 0.0 ? log1p(mu * em) : -log1p(logistic(e + s) * em)) - yv * s;
+      } else if (family == 3) dl = s + yv * mu * expm1(-s);
+      else dl = s * (e + 0.5 * s) - yv * s;
+      acc[1 + j] += av * dl;
     }
   }
   __shared__ double sm[WG / 64][NV];
@@ -212,13 +231,17 @@ __global__ __launch_bounds__(WG) void k_pen_trials(long long p, const double* __
 // Input checks: per-block maxima of 4 indicator values (non-finite y, negative y
 // for Poisson, bad prior weight, bad penalty weight); reduced with launch_reduce.
 __global__ __launch_bounds__(WG) void k_check(long long n, const double* __restrict__ y, const double* __restrict__ a,
-                                               long long p, const double* __restrict__ w, int poisson,
+                                               long long p, const double* __restrict__ w, int family,
                                                double* __restrict__ part) {
   double f[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n; i += (long long)gridDim.x * WG) {
     const double yv = y[i];
     if (!isfinite(yv)) f[0] = 1.0;
-    if (poisson && yv < 0.0) f[1] = 1.0;
+    // the response range of the family: counts >= 0, proportions in [0, 1], Gamma y > 0.
+    // Evaluated without short-circuit branches (a select, not a conditional store).
+    const int out_of_range = ((family == 1) & (yv < 0.0)) | ((family == 2) & ((yv < 0.0) | (yv > 1.0))) |
+                             ((family == 3) & !(yv > 0.0));
+    f[1] = fmax(f[1], (double)out_of_range);
     if (a) {
       const double av = a[i];
       if (!isfinite(av) || av < 0.0) f[2] = 1.0;
@@ -404,12 +427,12 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
   return hipGetLastError();
 }
 
-hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int poisson,
+hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,
                         double* partials, int* nblk_out, hipStream_t s) {
   int nb = grid1d(n > p ? n : p);
   if (nb > 1024) nb = 1024;
   *nblk_out = nb;
-  hipLaunchKernelGGL(k_check, dim3(nb), dim3(WG), 0, s, n, y, a, p, pen_w, poisson, partials);
+  hipLaunchKernelGGL(k_check, dim3(nb), dim3(WG), 0, s, n, y, a, p, pen_w, family, partials);
   return hipGetLastError();
 }
 

@@ -79,6 +79,9 @@ static double gram_spectral_radius(std::vector<double> A, int p) {
 }
 
 
+// Families whose IRLS weight (eq. nine) varies with eta: the inner chain then reads V.
+static bool family_has_weights(int family) { return family == GLAM_POISSON || family == GLAM_BINOMIAL; }
+
 static const double kEps[3] = {1.1102230246251565e-16, 5.960464477539063e-08, 3.90625e-03};
 
 struct Fit {
@@ -490,7 +493,7 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   F.a_int = (double*)A(G.nint * 8);
   F.eta_int = (double*)A(G.nint * 8);
   F.xd_int = (double*)A(G.nint * 8);
-  F.v_int = F.family == GLAM_POISSON ? A(G.nint * accs) : nullptr;
+  F.v_int = family_has_weights(F.family) ? A(G.nint * accs) : nullptr;
   F.T1d = (double*)A(G.t1_len * 8);
   F.S2d = (double*)A(G.s2_len * 8);
   F.X3fd = (double*)A(G.x3f_len * 8);
@@ -549,13 +552,18 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   // ---- input checks (device) ----
   {
     int nb = 0;
-    FCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family == GLAM_POISSON, F.part, &nb, F.s));
+    FCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family, F.part, &nb, F.s));
     const int ops[4] = {1, 1, 1, 1};
     FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
     FCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
     FCHK(hipStreamSynchronize(F.s));
     if (F.hred[0] != 0.0) { F.err = "Y has non-finite entries"; return GLAM_EINVAL; }
-    if (F.hred[1] != 0.0) { F.err = "Poisson Y must be >= 0"; return GLAM_EINVAL; }
+    if (F.hred[1] != 0.0) {
+      F.err = prob->family == GLAM_POISSON    ? "Poisson Y must be >= 0"
+              : prob->family == GLAM_BINOMIAL ? "Binomial Y must be a proportion in [0, 1]"
+                                              : "Gamma Y must be > 0";
+      return GLAM_EINVAL;
+    }
     if (F.hred[2] != 0.0) { F.err = "obs_w must be finite and >= 0"; return GLAM_EINVAL; }
     if (F.hred[3] != 0.0) { F.err = "pen_w must be finite and > 0"; return GLAM_EINVAL; }
   }
@@ -656,7 +664,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   }
   const glam_problem* prob = &lifted;
   if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
-  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) return fit_fail(GLAM_EINVAL, "bad family");
+  if (prob->family < GLAM_GAUSSIAN || prob->family > GLAM_GAMMA) return fit_fail(GLAM_EINVAL, "bad family");
   if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
   if (opt->nlambda < 1) return fit_fail(GLAM_EINVAL, "nlambda must be >= 1");
   if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
@@ -666,9 +674,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
   if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM)
     return fit_fail(GLAM_EINVAL, "bad inner_mode");
-  if (opt->inner_mode == GLAM_INNER_GRAM && (prob->family != GLAM_GAUSSIAN || prob->obs_w || opt->nu < 1.0))
-    return fit_fail(GLAM_EINVAL, "the Gram inner loop is exact only for the Gaussian family without prior "
-                                 "weights (Sec. 6.2) and runs without backtracking (nu = 1)");
+  if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(prob->family) || prob->obs_w || opt->nu < 1.0))
+    return fit_fail(GLAM_EINVAL, "the Gram inner loop is exact only for unit IRLS weights (Gaussian, Gamma-log) "
+                                 "without prior weights (Sec. 6.2) and runs without backtracking (nu = 1)");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
   if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
@@ -735,7 +743,11 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
 
   const bool exact_model = F.family == GLAM_GAUSSIAN && prob->obs_w == nullptr;
   const double tol = opt->kkt_tol;
-  const int check_every = opt->check_every;
+  // The inner stopping rule is checked every check_every iterations, except for the Gamma-log
+  // model: its Fisher-scoring quadratic (unit weights, a non-canonical link) can be far from
+  // the objective's curvature, and iterating past the first point that meets the rule makes
+  // the outer steps short (the Armijo rule cuts them), so there it is checked every iteration.
+  const int check_every = F.family == GLAM_GAMMA ? 1 : opt->check_every;
   const int log_level = getenv("GLAM_LOG") ? atoi(getenv("GLAM_LOG")) : 0;
   const bool verbose = log_level > 0;
   int path_status = GLAM_OK;
@@ -762,7 +774,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (!std::isfinite(kkt) || !std::isfinite(Fobj)) { status = GLAM_ENONFINITE; break; }
       if (kkt <= tol) { status = GLAM_OK; break; }
       if (k == opt->max_outer) break;
-      const double wmax = F.family == GLAM_POISSON ? st.vmax : 1.0;
+      const double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
       const double delta = 1.0 / (opt->nu * Lhat);
@@ -798,7 +810,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         // rounding floor of the low-precision chain output (a lower bound of its error)
         noise = 4.0 * kEps[F.dt] * chk[1] / lam_scale;
         best = std::min(best, kin);
-        if (it - window_start >= 20 * check_every) {
+        if (it - window_start >= 20 * opt->check_every) {
           // stalled: no 2x progress over the window -> leave for an FP64 re-anchor
           if (!(best < 0.5 * window_best) && F.dt != DT_F64) break;
           window_best = best;
@@ -861,7 +873,7 @@ static int validate_problem(const glam_problem* prob, int dtype, std::string* wh
     if (!prob->X[j]) { *why = "NULL factor"; return GLAM_EINVAL; }
   }
   if (!prob->Y) { *why = "NULL Y"; return GLAM_EINVAL; }
-  if (prob->family != GLAM_GAUSSIAN && prob->family != GLAM_POISSON) { *why = "bad family"; return GLAM_EINVAL; }
+  if (prob->family < GLAM_GAUSSIAN || prob->family > GLAM_GAMMA) { *why = "bad family"; return GLAM_EINVAL; }
   if (glam_rho_workspace_size(3, prob->n, prob->p, dtype) == 0) { *why = glam_last_error(); return GLAM_EINVAL; }
   if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024) {
     *why = "modes 1-2 too large for the FP64 slab kernel";
@@ -1026,6 +1038,10 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   std::vector<double> tol_in(nprob), best(nprob), wbest(nprob);
   const double tol = opt->kkt_tol;
   long long launches = 0, pstep = 0;
+  // checked every step when a Gamma-log problem is in the batch (as in glam_fit_path)
+  int check_every = opt->check_every;
+  for (int i = 0; i < nprob; ++i)
+    if (probs[i].family == GLAM_GAMMA) check_every = 1;
   for (int round = 0; round <= opt->max_outer; ++round) {
     int nact = 0;
     // step 2 of Algorithm 1 for every unfinished problem, one stream synchronisation
@@ -1048,7 +1064,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
       if (!std::isfinite(kkt)) { res->status[i] = GLAM_ENONFINITE; done[i] = 1; continue; }
       if (kkt <= tol) { res->status[i] = GLAM_OK; done[i] = 1; continue; }
       if (round == opt->max_outer) { done[i] = 1; continue; }
-      const double wmax = F.family == GLAM_POISSON ? st.vmax : 1.0;
+      const double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
       const double Lhat = wmax * F.sprod / (double)Gs[i].n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { res->status[i] = GLAM_ENONFINITE; done[i] = 1; continue; }
       const bool exact_model = F.family == GLAM_GAUSSIAN && probs[i].obs_w == nullptr;
@@ -1069,7 +1085,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
     int it = 0, window_start = 0;
     while (nact > 0 && it < opt->max_inner) {
-      const int m = std::min(opt->check_every, opt->max_inner - it);
+      const int m = std::min(check_every, opt->max_inner - it);
       for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, tot, lds, s));
       launches += m;
       pstep += (long long)m * nact;

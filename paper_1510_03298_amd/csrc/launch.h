@@ -69,7 +69,7 @@ struct SlabParams {
   double* eta_int;
   void* v_out;        // tiled weights written for the inner loop (FP32 or FP64), may be NULL
   int v_out_f32;      // 1: v_out is float, 0: double
-  int family;         // 0 Gaussian, 1 Poisson
+  int family;         // glam_family: 0 Gaussian, 1 Poisson, 2 Binomial, 3 Gamma
   // NLL (standard-layout FP64 counts)
   const double* y_std;
   double* partials;   // per-workgroup partial sums [grid][2]
@@ -220,7 +220,7 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
                              int j0, double* partials, int* nblk_out, hipStream_t s);
 // data checks, per-block maxima of 4 indicators: non-finite y, negative y (Poisson),
 // negative or non-finite a, non-positive or non-finite pen_w
-hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int poisson,
+hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,
                         double* partials, int* nblk_out, hipStream_t s);
 
 constexpr int ARMIJO_TRIALS = 16;   // step sizes 2^-j0 .. 2^-(j0+15) evaluated in one pass

@@ -336,16 +336,29 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
               const double eta = (double)E[i];
               const double y = P.y_int[ti];
               const double a = P.a_int[ti];
-              double mu, wgt, nll;
-              if (P.family == 1) {
-                mu = exp(eta);
+              // score u = a vartheta'(eta) (y - mu), weight w = vartheta'(eta) (g^-1)'(eta) (App. B)
+              double wgt, nll, u;
+              if (P.family == 1) {          // Poisson, log link
+                const double mu = exp(eta);
                 wgt = mu;
                 nll = a * (mu - y * eta);
-              } else {
-                mu = eta;
+                u = a * (y - mu);
+              } else if (P.family == 2) {   // Binomial, logit link: mu = 1 / (1 + e^-eta)
+                const double ex = exp(-fabs(eta));
+                const double mu = eta >= 0.0 ? 1.0 / (1.0 + ex) : ex / (1.0 + ex);
+                wgt = ex / ((1.0 + ex) * (1.0 + ex));   // mu (1 - mu) without cancellation
+                nll = a * (fmax(eta, 0.0) + log1p(ex) - y * eta);
+                u = a * (y - mu);
+              } else if (P.family == 3) {   // Gamma, log link (vartheta = -e^-eta): unit weight
+                const double emi = exp(-eta);
+                wgt = 1.0;
+                nll = a * (y * emi + eta);
+                u = a * (y * emi - 1.0);
+              } else {                      // Gaussian, identity link
                 wgt = 1.0;
                 const double d = y - eta;
                 nll = 0.5 * a * d * d;
+                u = a * d;
               }
               P.eta_int[ti] = eta;
               if (P.v_out) {
@@ -356,7 +369,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
                 s_nll += nll;
                 s_vmax = fmax(s_vmax, wgt);
               }
-              U[i] = valid ? (A)(a * (y - mu)) : (A)0;
+              U[i] = valid ? (A)u : (A)0;
             }
             fR = acc_frag<T>(U);
           } else if (MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {

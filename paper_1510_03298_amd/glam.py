@@ -23,12 +23,12 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 GLAM_OK, GLAM_EINVAL, GLAM_ENOMEM, GLAM_EDEVICE, GLAM_ENOCONV, GLAM_ENONFINITE = range(6)
-GAUSSIAN, POISSON = 0, 1
+GAUSSIAN, POISSON, BINOMIAL, GAMMA = 0, 1, 2, 3
 F64, F32, BF16 = 0, 1, 2
 MAX_INNER_P = 32
 MAX_INNER_N = 256
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
-FAMILIES = {"gaussian": GAUSSIAN, "poisson": POISSON}
+FAMILIES = {"gaussian": GAUSSIAN, "poisson": POISSON, "binomial": BINOMIAL, "gamma": GAMMA}
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p

@@ -119,6 +119,10 @@ def test_invalid_arguments_rejected_without_device_work():
     opt.lambda_ = lam2
     assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
     opt.nu = 1.0
+    prob.family = 4   # families are 0..3
+    rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    assert rc == glam.GLAM_EINVAL and b"family" in glam.glam_last_error()
+    prob.family = glam.GAMMA
     for bad in (-0.5, float("nan"), float("inf")):   # elastic-net weight must be finite and >= 0
         opt.alpha = bad
         rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))

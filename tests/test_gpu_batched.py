@@ -89,3 +89,18 @@ def test_batched_elastic_net():
         assert O.kkt_residual(th, g, 0.1 * lm, lm, alpha=1.0) <= 1e-6
         F = O.objective(d.family, d.X, th, d.Y, 0.1 * lm, alpha=1.0)
         assert abs(res.objective[i] - F) <= 1e-9 * abs(F)
+
+
+def test_batched_four_families():
+    """One batch mixing all four families (Gaussian, Poisson, Binomial, Gamma)."""
+    torch, glam = need_gpu()
+    fams = ["gaussian", "poisson", "binomial", "gamma"] * 2
+    probs = [inputs.random_problem((17 + 3 * i, 20 + i, 19 + 2 * i), (5, 6, 5), family=f, seed=50 + i,
+                                   basis="gauss", scale=0.3) for i, f in enumerate(fams)]
+    res = glam.fit_batched([_upload(glam, d) for d in probs], lambda_ratio=0.1, dtype=1, kkt_tol=1e-6)
+    assert res.code == 0 and np.all(res.status == 0)
+    for i, d in enumerate(probs):
+        lm = O.lambda_max(d.family, d.X, d.Y)
+        th = glam.from_colmajor(res.theta[i], d.p)
+        g = O.smooth_gradient(d.family, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, 0.1 * lm, lm) <= 1e-6, (i, d.family)

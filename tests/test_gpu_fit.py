@@ -304,3 +304,62 @@ def test_elastic_net_gram_inner_loop():
         th = _theta(glam, res, l, d.p)
         g = O.smooth_gradient("gaussian", d.X, th, d.Y)
         assert O.kkt_residual(th, g, res.lambdas[l], lm, alpha=2.0) <= 1e-6
+
+
+@pytest.mark.parametrize("fam,dt,nu", [("binomial", 0, 1.0), ("binomial", 2, 1.0), ("binomial", 1, 0.5),
+                                       ("gamma", 0, 1.0), ("gamma", 2, 1.0), ("gamma", 1, 0.5)])
+def test_binomial_gamma_paths(fam, dt, nu):
+    """Binomial-logit and Gamma-log models (Sec. 6.4's family list): every model on a
+    short path meets the oracle's FP64 KKT condition; the objective equals the
+    oracle's minimum (both models are strictly convex in eta, the designs full rank)."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((21, 17, 29), (8, 7, 9), family=fam, seed=33, basis="gauss", scale=0.3)
+    print(f"family {fam} dt={dt} nu={nu}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=5, lambda_min_ratio=0.02, dtype=dt, kkt_tol=1e-7, nu=nu)
+    assert res.code == 0, (res.code, res.status)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    assert abs(res.lambda_max - lm) <= 1e-12 * lm
+    for l in range(5):
+        th = _theta(glam, res, l, d.p)
+        lam = res.lambdas[l]
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, lam, lm) <= 1e-7
+        F1 = O.objective(fam, d.X, th, d.Y, lam)
+        assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
+        ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200)
+        F2 = O.objective(fam, d.X, ref, d.Y, lam)
+        assert (F1 - F2) / abs(F2) <= 1e-8
+        assert rel_inf(th, ref) <= 1e-4
+
+
+def test_gamma_gram_inner_loop():
+    """Gamma-log has unit IRLS weights, so the Sec. 6.2 Gram inner loop is exact for it."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((23, 19, 37), (9, 7, 12), family="gamma", seed=34, basis="gauss", scale=0.3)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max("gamma", d.X, d.Y)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "gamma", nlambda=4, lambda_min_ratio=0.02, dtype=2, kkt_tol=1e-6,
+                        inner="gram")
+    assert res.code == 0
+    for l in range(4):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient("gamma", d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
+    with pytest.raises(glam.GlamError):   # Binomial weights vary with eta: not exact
+        db = inputs.random_problem((12, 11, 10), (5, 4, 6), family="binomial", seed=35, basis="gauss")
+        Xb, Yb, _ = _dev(glam, db)
+        glam.fit_path(Xb, Yb, db.n, db.p, "binomial", nlambda=2, inner="gram")
+
+
+@pytest.mark.parametrize("fam,bad", [("binomial", 1.5), ("binomial", -0.1), ("gamma", 0.0), ("gamma", -2.0),
+                                     ("poisson", -1.0)])
+def test_response_range_rejected(fam, bad):
+    torch, glam = need_gpu()
+    d = inputs.random_problem((12, 11, 10), (5, 4, 6), family=fam, seed=36, basis="gauss")
+    Y = d.Y.copy()
+    Y[3, 4, 5] = bad
+    Xd = [glam.to_device_colmajor(X, 0) for X in d.X]
+    Yd = glam.to_device_colmajor(Y, 0)
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2)
