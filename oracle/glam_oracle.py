@@ -21,6 +21,7 @@ definitions in the paper's notation:
 * Armijo rule ............................... Sec. 5 (Tseng-Yun step size, before Thm. 2)
 * proximal operators ........................ Sec. 6.3
 * lambda path with warm starts .............. Sec. 6.4 (glamlasso package description)
+* SCAD via the multi-step adaptive lasso .... Sec. 6.4 (penalty, steps); SCAD is Fan and Li's
 
 Readings of places where the paper is silent or ambiguous (listed again in the
 design notes):
@@ -52,6 +53,11 @@ R16 families beyond Gaussian and Poisson (Sec. 6.4 lists Binomial-logit and Gamm
     mu (1 - mu) for the logit, and exactly 1 for the Gamma-log model (Fisher
     scoring, a non-canonical link), so Gamma shares the Gaussian's unit weights
     but not its exact quadratic model.
+R17 SCAD (Sec. 6.4): Fan and Li's penalty with a = 3.7; MSA-lasso step 1 is the lasso
+    (with the caller's penalty weights), each further step the weighted lasso with
+    w_m = pen_w_m p'_lambda(|theta_m|) / lambda at the previous step's estimate.  The
+    lambda grid and the KKT scale are the lasso's (lambda_max of step 1); the reported
+    KKT residual and objective are those of the last step's weighted lasso.
 R15 elastic net (Sec. 6.3): J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2), the
     penalty weights scaling both terms; its prox is the soft threshold divided by
     1 + 2 alpha gamma w_m, lambda_max is the lasso's (the quadratic term has zero
@@ -611,6 +617,76 @@ def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e
         if not info.converged:
             break
     return lambdas, thetas, infos, lam_max
+
+
+# =============================================================================
+# Sec. 6.4: the SCAD penalty through the multi-step adaptive lasso (MSA-lasso).
+# The SCAD penalty itself is Fan and Li's (the paper cites it, not defines it);
+# each step replaces it by its local linear approximation at the previous
+# estimate, a weighted l1 problem that Algorithm 1 solves.
+# =============================================================================
+SCAD_A = 3.7
+
+
+def scad_penalty(t, lam, a=SCAD_A):
+    """Fan-Li SCAD penalty p_lambda(t) for t >= 0: lambda t up to lambda, a quadratic
+    joining piece up to a lambda, the constant (a + 1) lambda^2 / 2 beyond."""
+    t = np.abs(np.asarray(t, dtype=np.float64))
+    mid = (2.0 * a * lam * t - t * t - lam * lam) / (2.0 * (a - 1.0))
+    return np.where(t <= lam, lam * t, np.where(t <= a * lam, mid, 0.5 * (a + 1.0) * lam * lam))
+
+
+def scad_derivative(t, lam, a=SCAD_A):
+    """p'_lambda(t) for t >= 0: lambda for t <= lambda, then (a lambda - t)_+ / (a - 1)."""
+    t = np.abs(np.asarray(t, dtype=np.float64))
+    return np.where(t <= lam, lam, np.maximum(a * lam - t, 0.0) / (a - 1.0))
+
+
+def msa_weights(theta, lam, pen_w=None, a=SCAD_A):
+    """Weights of the next MSA step: w_m = pen_w_m p'_lambda(|theta_m|) / lambda, in [0, 1]
+    times pen_w (zero where |theta_m| >= a lambda: those coordinates go unpenalised)."""
+    w = scad_derivative(vec(theta), lam, a) / lam
+    return w if pen_w is None else vec(pen_w) * w
+
+
+def msa_scad(fam, Xs, Y, lam, lam_max, steps, a=None, pen_w=None, theta0=None, tol=1e-10, max_outer=100,
+             max_inner=100000, nu=1.0, scad_a=SCAD_A):
+    """MSA-lasso for one lambda: step 1 is the (pen_w-weighted) lasso, warm-started at
+    theta0; each of the steps - 1 further steps solves the weighted lasso with the
+    msa_weights of the previous step's estimate, warm-started there.  Returns
+    (theta, info of the last step, weights of the last step)."""
+    p = tuple(X.shape[1] for X in Xs)
+    theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
+    w = np.ones(int(np.prod(p))) if pen_w is None else vec(pen_w).copy()
+    info = None
+    for s in range(steps):
+        if s > 0:
+            w = msa_weights(theta, lam, pen_w, scad_a)
+        theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, unvec(w, p), theta, tol, max_outer, max_inner, nu)
+        if not info.converged:
+            break
+    return theta, info, w
+
+
+def msa_scad_path(fam, Xs, Y, steps, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e-4, tol=1e-10,
+                  max_outer=100, max_inner=100000, nu=1.0, scad_a=SCAD_A):
+    """SCAD lambda path (Sec. 6.4): the lasso's lambda_max and grid, MSA-lasso at each
+    lambda warm-started at the previous lambda's estimate."""
+    lam_max = lambda_max(fam, Xs, Y, a, pen_w)
+    if lambdas is None:
+        lambdas = lambda_grid(lam_max, nlambda, ratio)
+    p = tuple(X.shape[1] for X in Xs)
+    theta = np.zeros(p)
+    thetas, infos, weights = [], [], []
+    for lam in np.asarray(lambdas, dtype=np.float64):
+        theta, info, w = msa_scad(fam, Xs, Y, lam, lam_max, steps, a, pen_w, theta, tol, max_outer, max_inner, nu,
+                                  scad_a)
+        thetas.append(theta.copy())
+        infos.append(info)
+        weights.append(w)
+        if not info.converged:
+            break
+    return np.asarray(lambdas, dtype=np.float64), thetas, infos, weights, lam_max
 
 
 # =============================================================================

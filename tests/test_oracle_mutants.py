@@ -76,6 +76,11 @@ MUTANTS = {
                                      float(np.sum((np.ones_like(Y) if a is None else a) * Y * t * xd)) / Y.size
                                      if O.family(fam).name == "binomial" else 0.0)),
                                  lambda: [lambda: P.test_objective_change_is_the_difference_of_objectives("binomial")]),
+    # SCAD slope divided by a instead of a - 1 beyond lambda
+    "scad_slope": ("scad_derivative",
+                   lambda orig: (lambda t, lam, a=O.SCAD_A: np.where(np.abs(t) <= lam, lam,
+                                                                     np.maximum(a * lam - np.abs(t), 0.0) / a)),
+                   lambda: [P.test_scad_penalty_and_slope, P.test_msa_orthogonal_design_reaches_scad_thresholding]),
     # H applies the factors in reverse order (wrong mode index)
     "H_reversed": ("H", lambda orig: (lambda Xs, Th: orig(list(Xs)[::-1], Th)),
                    lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),

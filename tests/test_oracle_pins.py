@@ -298,6 +298,50 @@ def test_new_families_stationary_on_explicit_design(fam):
             assert F(t) >= F0 - 1e-13
 
 
+def test_scad_penalty_and_slope():
+    """Fan-Li SCAD: p'(t) = lambda up to lambda, (a lambda - t)_+ / (a - 1) beyond; the
+    penalty is continuous with p(lambda) = lambda^2 and the constant (a + 1) lambda^2 / 2
+    from a lambda on; the slope is the penalty's central difference everywhere."""
+    lam, a = 0.7, O.SCAD_A
+    t = np.concatenate([np.linspace(0.0, 4.0 * lam * a, 401), [lam, a * lam, 2 * lam]])
+    h = 1e-6
+    fd = (O.scad_penalty(t + h, lam) - O.scad_penalty(np.maximum(t - h, 0.0), lam)) / (t + h - np.maximum(t - h, 0.0))
+    d = O.scad_derivative(t, lam)
+    ok = (np.abs(t - lam) > 2 * h) & (np.abs(t - a * lam) > 2 * h)   # the slope itself has kinks there
+    np.testing.assert_allclose(fd[ok], d[ok], rtol=1e-6, atol=1e-8)
+    assert abs(float(O.scad_penalty(lam, lam)) - lam * lam) < 1e-15
+    for e in (1e-12, -1e-12):
+        assert abs(float(O.scad_penalty(a * lam + e, lam)) - 0.5 * (a + 1) * lam * lam) < 1e-11
+    assert float(O.scad_derivative(lam, lam)) == lam and float(O.scad_derivative(a * lam, lam)) == 0.0
+    assert float(O.scad_derivative(0.5 * (lam + a * lam), lam)) == pytest.approx(0.5 * lam * (a - 1) / (a - 1))
+
+
+def test_msa_orthogonal_design_reaches_scad_thresholding():
+    """With X^T X = n I the SCAD problem separates, and the MSA-lasso iteration converges
+    to Fan and Li's thresholding rule for z = X^T y / n:
+    sign(z)(|z| - lambda)_+ for |z| <= 2 lambda, ((a-1) z - sign(z) a lambda)/(a-2) up to
+    a lambda, and z itself beyond."""
+    d = inputs.random_problem((8, 7, 6), (4, 3, 5), seed=13, basis="orth")
+    Xd = O.kron_design(d.X)
+    N = Xd.shape[0]
+    z = Xd.T @ O.vec(d.Y) / N
+    a = O.SCAD_A
+    lam = float(np.median(np.abs(z))) / 1.5
+    az = np.abs(z)
+    regimes = [np.sum(az <= lam), np.sum((az > lam) & (az <= 2 * lam)), np.sum((az > 2 * lam) & (az <= a * lam)),
+               np.sum(az > a * lam)]
+    assert min(regimes) >= 2, regimes
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    th, info, w = O.msa_scad("gaussian", d.X, d.Y, lam, lm, steps=60, tol=1e-13, max_outer=3, max_inner=5000)
+    assert info.converged
+    expect = np.where(az <= 2 * lam, np.sign(z) * np.maximum(az - lam, 0.0),
+                      np.where(az <= a * lam, ((a - 1) * z - np.sign(z) * a * lam) / (a - 2), z))
+    np.testing.assert_allclose(O.vec(th), expect, rtol=1e-10, atol=1e-11)
+    # one step is the lasso
+    th1, _, _ = O.msa_scad("gaussian", d.X, d.Y, lam, lm, steps=1, tol=1e-13, max_outer=3, max_inner=5000)
+    np.testing.assert_allclose(O.vec(th1), O.soft_threshold(z, lam), rtol=1e-10, atol=1e-11)
+
+
 def test_kkt_residual_definition():
     """R6 on a hand-made case: zero and nonzero coordinates."""
     th = np.array([0.0, 1.0, -2.0, 0.0])
