@@ -52,6 +52,9 @@ typedef enum {
  * mu (1 - mu) and 1 respectively (Gamma-log is a non-canonical link: Fisher scoring). */
 typedef enum { GLAM_GAUSSIAN = 0, GLAM_POISSON = 1, GLAM_BINOMIAL = 2, GLAM_GAMMA = 3 } glam_family;
 
+/* Penalty J of the PMLE (Sec. 2 eq. five; Sec. 6.4). */
+typedef enum { GLAM_PENALTY_LASSO = 0, GLAM_PENALTY_SCAD = 1 } glam_penalty;
+
 /* Element type of the rho products.  F64: all FP64.  F32: FP32 inputs and
  * outputs, FP32 accumulation.  BF16: bfloat16 inputs (stored as uint16_t),
  * FP32 accumulation and FP32 outputs. */
@@ -143,6 +146,16 @@ typedef struct {
                              The prox is the soft threshold divided by 1 + 2 alpha delta
                              lambda w_m; lambda_max is unchanged (the quadratic term has
                              zero slope at theta = 0)                               */
+  int penalty;            /* glam_penalty: GLAM_PENALTY_LASSO, or GLAM_PENALTY_SCAD solved by
+                             the multi-step adaptive lasso (Sec. 6.4): at each lambda, step 1
+                             is the (pen_w-weighted) lasso, and each of msa_steps - 1 further
+                             steps the weighted lasso with w_m = pen_w_m p'(|theta_m|)/lambda
+                             at the previous step's estimate (Fan and Li's SCAD slope, zero
+                             for |theta_m| >= scad_a lambda).  lambda_max and the KKT scale
+                             are the lasso's; kkt and objective report the last step's
+                             weighted lasso.  Not combinable with alpha != 0.        */
+  double scad_a;          /* SCAD shape a > 2 (0 = 3.7)                               */
+  int msa_steps;          /* MSA steps per lambda (>= 1; 1 = the lasso)               */
 } glam_options;
 
 /* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the

@@ -259,6 +259,19 @@ __global__ __launch_bounds__(WG) void k_check(long long n, const double* __restr
     for (int s = 0; s < 4; ++s) part[(long long)blockIdx.x * 4 + s] = f[s];
 }
 
+// Weights of the next multi-step adaptive lasso step for the SCAD penalty (Sec. 6.4):
+// w_m = base_m p'_lambda(|theta_m|) / lambda with Fan and Li's slope, 1 up to lambda, then
+// (a lambda - |theta|)_+ / ((a - 1) lambda).  base == NULL means unit base weights.
+__global__ __launch_bounds__(WG) void k_scad_weights(long long p, const double* __restrict__ theta,
+                                                     const double* __restrict__ base, double lambda, double a,
+                                                     double* __restrict__ w) {
+  for (long long m = blockIdx.x * (long long)WG + threadIdx.x; m < p; m += (long long)gridDim.x * WG) {
+    const double t = fabs(theta[m]);
+    const double d = t <= lambda ? 1.0 : fmax(a * lambda - t, 0.0) / ((a - 1.0) * lambda);
+    w[m] = base ? base[m] * d : d;
+  }
+}
+
 // k-blocked packing: dst elem(k, c) = src[k * sk + c * sc] (converted), zero for k >= K.
 template <typename S, typename T>
 __global__ void k_pack(const S* __restrict__ src, long long K, long long C, long long sk, long long sc,
@@ -424,6 +437,12 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
   if (nb > 256) nb = 256;
   *nblk_out = nb;
   hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, alpha, j0, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_scad_weights(long long p, const double* theta, const double* base, double lambda, double a, double* w,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_scad_weights, dim3(grid1d(p)), dim3(WG), 0, s, p, theta, base, lambda, a, w);
   return hipGetLastError();
 }
 

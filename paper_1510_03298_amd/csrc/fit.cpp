@@ -102,6 +102,7 @@ struct Fit {
   void *T1c, *S2c;         // chain dtype intermediates
   bool gram = false;       // inner gradient by the Kronecker Gram factors (Sec. 6.2)
   double enet = 0.0;       // elastic-net weight alpha (Sec. 6.3): J = sum w (|theta| + alpha theta^2)
+  const double* pen = nullptr;   // penalty weights the kernels read (the caller's, or the SCAD steps' own)
   double *S1g = nullptr, *S2g = nullptr;   // X_1^T X_1, X_2^T X_2 (FP64)
   void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
   void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
@@ -197,7 +198,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2d; ap.X3a = F.X3ad; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
-  ap.theta = theta_dev; ap.pen_w = F.prob->pen_w; ap.lambda = lambda; ap.alpha = F.enet;
+  ap.theta = theta_dev; ap.pen_w = F.pen; ap.lambda = lambda; ap.alpha = F.enet;
   double* part2 = F.part + (size_t)2 * nbc;
   ap.partials = part2;
   int nb = 0;
@@ -234,7 +235,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I)
     FCHK(launch_gram12(F.dt, G, F.inc, F.S1g, F.S2g, F.Zc, F.iter, F.s));
     AdjParams ap{};
-    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w; ap.alpha = F.enet;
+    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen; ap.alpha = F.enet;
     ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
     ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
     FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
@@ -253,7 +254,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
   AdjParams ap{};
-  ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+  ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen;
   ap.alpha = F.enet; ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
   ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
   ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
@@ -371,7 +372,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
     FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
     AdjParams ap{};
-    ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.prob->pen_w;
+    ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen;
     ap.alpha = F.enet; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
     ap.x = cur[0]; ap.xp = cur[1]; ap.gp = cur[2]; ap.yprev = cur[3]; ap.gyprev = cur[4];
     ap.x_out = nxt[0]; ap.xp_out = nxt[1]; ap.gp_out = nxt[2]; ap.y_out = nxt[3]; ap.gy_out = nxt[4];
@@ -387,7 +388,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     if (l >= 2 && sdg > (sdd / delta) * (1.0 + 1e-12) && delta > delta_min * (1.0 + 1e-12)) {
       // divergence of the step into x^l detected: halve delta and redo that step from y_{l-1}
       delta = std::max(0.5 * delta, delta_min);
-      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.prob->pen_w, F.theta, lam, delta, F.enet, cur[0], F.inc, F.s));
+      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.pen, F.theta, lam, delta, F.enet, cur[0], F.inc, F.s));
       continue;
     }
     kin = F.hred[0] / lam_scale;
@@ -431,7 +432,7 @@ static int armijo_enqueue(Fit& F, int j0) {
   FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
   FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
   double* part2 = F.part + (size_t)nb1 * NV;
-  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.prob->pen_w, F.enet, j0, part2, &nb2, F.s));
+  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.pen, F.enet, j0, part2, &nb2, F.s));
   FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
   FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
   return GLAM_OK;
@@ -481,6 +482,7 @@ static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* de
 static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   F.family = prob->family;
   F.prob = prob;
+  F.pen = prob->pen_w;
   const Geom& G = F.G;
   const size_t es = dt_size(F.dt);
   const size_t accs = F.dt == DT_F64 ? 8 : 4;
@@ -672,6 +674,14 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
   if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
   if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
+  if (opt->penalty != GLAM_PENALTY_LASSO && opt->penalty != GLAM_PENALTY_SCAD)
+    return fit_fail(GLAM_EINVAL, "bad penalty");
+  if (opt->penalty == GLAM_PENALTY_SCAD) {
+    if (opt->msa_steps < 1) return fit_fail(GLAM_EINVAL, "msa_steps must be >= 1");
+    if (!(opt->scad_a == 0.0 || (opt->scad_a > 2.0 && std::isfinite(opt->scad_a))))
+      return fit_fail(GLAM_EINVAL, "scad_a must be > 2 (or 0 for 3.7)");
+    if (opt->alpha != 0.0) return fit_fail(GLAM_EINVAL, "SCAD and the elastic net do not combine");
+  }
   if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM)
     return fit_fail(GLAM_EINVAL, "bad inner_mode");
   if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(prob->family) || prob->obs_w || opt->nu < 1.0))
@@ -725,6 +735,23 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     if (r_ != GLAM_OK) return fit_fail(r_, F.err); \
   } while (0)
 
+  // SCAD (Sec. 6.4): the MSA steps reweight a buffer of penalty weights of their own; it
+  // holds the caller's weights (or ones) for step 1, which also defines lambda_max
+  const bool scad = opt->penalty == GLAM_PENALTY_SCAD;
+  const int msa_steps = scad ? opt->msa_steps : 1;
+  const double scad_a = opt->scad_a == 0.0 ? 3.7 : opt->scad_a;
+  double* pen_buf = nullptr;
+  if (scad) {
+    pen_buf = (double*)F.alloc(G.p * 8);
+    if (!pen_buf) return fit_fail(GLAM_ENOMEM, "device allocation failed");
+    F.pen = pen_buf;
+  }
+  auto base_weights = [&]() -> hipError_t {
+    return prob->pen_w ? hipMemcpyAsync(pen_buf, prob->pen_w, G.p * 8, hipMemcpyDeviceToDevice, F.s)
+                       : launch_fill(pen_buf, G.p, 1.0, F.s);
+  };
+  if (scad) PCHK(base_weights());
+
   // ---- lambda_max: the zero solution's gradient (Sec. 6.4) ----
   PCHK(launch_fill(F.theta, G.p, 0.0, F.s));
   StepStats st0;
@@ -766,11 +793,18 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     long long inner_total = 0;
     StepStats st{};
     double kkt = INFINITY, Fobj = NAN;
+    int outer_base = 0;
+    for (int step = 0; step < msa_steps; ++step) {
+    if (scad) {   // MSA-lasso: the lasso first, then weights from the previous step's estimate
+      if (step == 0) PCHK(base_weights());
+      else PCHK(launch_scad_weights(G.p, F.theta, prob->pen_w, lam, scad_a, pen_buf, F.s));
+    }
+    status = GLAM_ENOCONV;
     for (int k = 0; k <= opt->max_outer; ++k) {
       RCHK(family_step(F, F.theta, lam, &st));
       kkt = st.kkt_raw / lam_scale;
       Fobj = st.nll + lam * st.pen;
-      outer = k;
+      outer = outer_base + k;
       if (!std::isfinite(kkt) || !std::isfinite(Fobj)) { status = GLAM_ENONFINITE; break; }
       if (kkt <= tol) { status = GLAM_OK; break; }
       if (k == opt->max_outer) break;
@@ -833,6 +867,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
                 k, kkt, Fobj, it, kin, noise, alpha, Delta);
       if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
     }
+    outer_base = outer;
+    if (status != GLAM_OK) break;
+    }   // MSA steps
     PCHK(hipMemcpyAsync(res->theta + (size_t)l * G.p, F.theta, G.p * 8, hipMemcpyDeviceToDevice, F.s));
     res->kkt[l] = kkt;
     res->objective[l] = Fobj;

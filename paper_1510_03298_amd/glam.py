@@ -29,6 +29,7 @@ MAX_INNER_P = 32
 MAX_INNER_N = 256
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 FAMILIES = {"gaussian": GAUSSIAN, "poisson": POISSON, "binomial": BINOMIAL, "gamma": GAMMA}
+PENALTIES = {"lasso": 0, "scad": 1}
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
@@ -44,7 +45,8 @@ class GlamOptions(ctypes.Structure):
                 ("lambda_min_ratio", ctypes.c_double), ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double),
                 ("nu", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int),
-                ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int), ("alpha", ctypes.c_double)]
+                ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("penalty", ctypes.c_int), ("scad_a", ctypes.c_double), ("msa_steps", ctypes.c_int)]
 
 
 class GlamResult(ctypes.Structure):
@@ -297,10 +299,11 @@ class PathResult:
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
              check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
-             graph=True, inner="chain", alpha=0.0) -> PathResult:
+             graph=True, inner="chain", alpha=0.0, penalty="lasso", scad_a=3.7, msa_steps=3) -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
-    alpha: elastic-net weight (0 = lasso)."""
+    alpha: elastic-net weight (0 = lasso); penalty="scad": SCAD by msa_steps steps of
+    the multi-step adaptive lasso per lambda."""
     torch = _torch()
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
     prob = GlamProblem()
@@ -333,6 +336,9 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.graph_mode = 0 if graph else 1
     opt.inner_mode = {"chain": 0, "gram": 1}[inner]
     opt.alpha = float(alpha)
+    opt.penalty = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
+    opt.scad_a = float(scad_a)
+    opt.msa_steps = int(msa_steps)
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()

@@ -123,6 +123,14 @@ def test_invalid_arguments_rejected_without_device_work():
     rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     assert rc == glam.GLAM_EINVAL and b"family" in glam.glam_last_error()
     prob.family = glam.GAMMA
+    for field, value in (("penalty", 2), ("msa_steps", 0), ("scad_a", 1.5)):   # SCAD options checked on the host
+        opt.penalty, opt.msa_steps, opt.scad_a = 1, 3, 0.0
+        setattr(opt, field, value)
+        assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+    opt.penalty, opt.scad_a, opt.alpha = 1, 0.0, 0.5
+    assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+    assert b"SCAD" in glam.glam_last_error()
+    opt.penalty = 0
     for bad in (-0.5, float("nan"), float("inf")):   # elastic-net weight must be finite and >= 0
         opt.alpha = bad
         rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))

@@ -363,3 +363,47 @@ def test_response_range_rejected(fam, bad):
     Yd = glam.to_device_colmajor(Y, 0)
     with pytest.raises(glam.GlamError):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2)
+
+
+def test_scad_orthogonal_design_thresholding():
+    """SCAD by the multi-step adaptive lasso (Sec. 6.4) on X^T X = n I converges to Fan and
+    Li's thresholding rule of z = X^T y / n (every regime present)."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((8, 7, 6), (4, 3, 5), seed=13, basis="orth")
+    Xd, Yd, _ = _dev(glam, d)
+    Xk = O.kron_design(d.X)
+    z = Xk.T @ O.vec(d.Y) / Xk.shape[0]
+    a, az = 3.7, np.abs(z)
+    lam = float(np.median(az)) / 1.5
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", lambdas=[lam], dtype=0, kkt_tol=1e-11, penalty="scad",
+                        msa_steps=40)
+    assert res.code == 0
+    expect = np.where(az <= 2 * lam, np.sign(z) * np.maximum(az - lam, 0.0),
+                      np.where(az <= a * lam, ((a - 1) * z - np.sign(z) * a * lam) / (a - 2), z))
+    np.testing.assert_allclose(O.vec(_theta(glam, res, 0, d.p)), expect, rtol=1e-8, atol=1e-9)
+
+
+@pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 2), ("poisson", 0), ("binomial", 1)])
+def test_scad_path_matches_oracle(fam, dt):
+    """A 4-lambda SCAD path (3 MSA steps per lambda) against the oracle's MSA path: the
+    same estimates, and the device estimate meets the oracle's last-step weighted KKT."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((21, 17, 29), (8, 7, 9), family=fam, seed=37, basis="gauss", scale=0.5)
+    print(f"scad {fam} dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=4, lambda_min_ratio=0.05, dtype=dt, kkt_tol=1e-8,
+                        penalty="scad", msa_steps=3)
+    assert res.code == 0, (res.code, res.status)
+    lams, ths, infos, ws, lm = O.msa_scad_path(fam, d.X, d.Y, steps=3, nlambda=4, ratio=0.05, tol=1e-10,
+                                               max_outer=200)
+    assert abs(res.lambda_max - lm) <= 1e-12 * lm
+    np.testing.assert_allclose(res.lambdas, lams, rtol=1e-13)
+    for l in range(4):
+        th = _theta(glam, res, l, d.p)
+        assert rel_inf(th, ths[l]) <= 1e-4, (l, rel_inf(th, ths[l]))
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, lams[l], lm, pen_w=ws[l]) <= 1e-5
+    # SCAD leaves large coefficients unpenalised: its last model is closer to the data than the lasso's
+    las = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[res.lambdas[-1]], dtype=dt, kkt_tol=1e-8)
+    nll = lambda t: O.neg_loglik_scaled(fam, O.H(d.X, t), d.Y)
+    assert nll(_theta(glam, res, 3, d.p)) < nll(_theta(glam, las, 0, d.p))
