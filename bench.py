@@ -141,6 +141,29 @@ def gram_path(glam, torch, d, Xd, Yd, stream, nlambda, chain_seconds):
     return out
 
 
+def sim65_path(glam, inputs, torch, stream, family):
+    """Section 6.5's simulated design at the largest size the slab kernel takes (r = 3,
+    q = 0.5, kappa = 0.25; modes (60, 30, 180), p = (30, 15, 90)): the default
+    100-lambda path to 1e-4 lambda_max, KKT <= 1e-6, BF16 and FP64 inner chains."""
+    d = inputs.config_sim(r=3, q=0.5, family=family, kappa=0.25)
+    Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    out = {"workload": f"sec6.5_simulated_{family}_r3_q0.5_kappa0.25_n{d.n[0]}x{d.n[1]}x{d.n[2]}"
+                       f"_p{d.p[0]}x{d.p[1]}x{d.p[2]}_100lambda_kkt1e-6"}
+    for dt, name in ((glam.BF16, "bf16"), (glam.F64, "f64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = glam.fit_path(Xd, Yd, d.n, d.p, family, nlambda=100, lambda_min_ratio=1e-4, dtype=dt, kkt_tol=1e-6,
+                          stream=stream, raise_on_error=False)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "models": int(r.n_done),
+                     "converged": r.code == 0 and r.n_done == 100,
+                     "max_kkt": float(np.max(r.kkt[:r.n_done])) if r.n_done else None,
+                     "inner": int(r.inner_total), "outer": int(r.iters_outer.sum()),
+                     "fp64_from_model": int(r.escalated_at)}
+    return out
+
+
 def poisson_path(glam, inputs, torch, stream):
     """Poisson counts, n = (64, 64, 365), p = (24, 24, 120), 50-lambda log grid to
     1e-4 lambda_max, KKT <= 1e-6, BF16 inner chain (FP64 Armijo, KKT and anchors)."""
@@ -310,7 +333,9 @@ def main():
         extra = {"gaussian_path_c2_gram": gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec),
                  "poisson_path_c3": poisson_path(glam, inputs, torch, stream),
                  "batched_c4": batched(glam, inputs, torch, stream),
-                 "poisson_nll_c5": nll(glam, inputs, torch, stream)}
+                 "poisson_nll_c5": nll(glam, inputs, torch, stream),
+                 "sim65_gaussian": sim65_path(glam, inputs, torch, stream, "gaussian"),
+                 "sim65_poisson": sim65_path(glam, inputs, torch, stream, "poisson")}
     out = {
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,

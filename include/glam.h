@@ -161,8 +161,9 @@ typedef struct {
 /* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the
  * n-sized rho chain (Sec. 6.1).  GLAM_INNER_GRAM: (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n
  * with the Gram factors S_j = X_j^T X_j (Sec. 6.2, tensor-product weights with W = I), i.e.
- * p-sized products only; exact for the Gaussian family without prior weights, and only
- * there (GLAM_EINVAL for Poisson, obs_w != NULL or nu < 1).  The Gram products run in the
+ * p-sized products only; exact for the families with unit IRLS weights (Gaussian, Gamma-log)
+ * without prior weights, and only there (GLAM_EINVAL for Poisson, Binomial, obs_w != NULL or
+ * nu < 1).  The Gram products run in the
  * accumulation type of the dtype (FP32 for BF16/F32, FP64 for F64), the mode-3 product on
  * the matrix cores in the chain dtype. */
 typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1 } glam_inner;
@@ -182,6 +183,10 @@ typedef struct {
   int chain_samples;      /* out: number of sampled launches (profile_every > 0)     */
   double iter_ms;         /* out: summed duration of the sampled whole inner iterations */
   long long inner_total;  /* out: inner iterations over the whole path               */
+  int escalated_at;       /* out: first model whose fit continued with the FP64 inner chain
+                             because the BF16/FP32 chain stopped refining it (three outer
+                             steps in a row ending on the chain's rounding floor with less
+                             than 10% KKT progress; the rest of the path stays FP64), or -1 */
 } glam_result;
 
 /* Fit the whole lambda path with warm starts.  Models are fitted in order;

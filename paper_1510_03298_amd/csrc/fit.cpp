@@ -411,6 +411,17 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
   return GLAM_OK;
 }
 
+// Continue a fit with the FP64 inner chain: the FP64 intermediates, factor copies and LDS
+// image of the outer steps serve the inner loop from now on; the captured graph (built for
+// the old dtype) is dropped.  V and the increment already have 8-byte elements.
+static void escalate_f64(Fit& F) {
+  F.dt = DT_F64;
+  F.T1c = F.T1d; F.S2c = F.S2d; F.X3fc = F.X3fd; F.X3ac = F.X3ad; F.imgc = F.imgd;
+  if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
+  if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
+  F.graph_m = 0;
+}
+
 // Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
 // Enqueue one pass of the Armijo rule (step sizes 2^-j0 .. 2^-(j0+15)) along d =
 // F.dvec; j0 == 0 also computes H(d) in FP64 (the trials use eta + t H(d)).  The sums
@@ -495,7 +506,9 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   F.a_int = (double*)A(G.nint * 8);
   F.eta_int = (double*)A(G.nint * 8);
   F.xd_int = (double*)A(G.nint * 8);
-  F.v_int = family_has_weights(F.family) ? A(G.nint * accs) : nullptr;
+  // V and the increment get 8-byte elements whatever the chain dtype, so that a fit can
+  // continue in FP64 (escalate_f64) without reallocating
+  F.v_int = family_has_weights(F.family) ? A(G.nint * 8) : nullptr;
   F.T1d = (double*)A(G.t1_len * 8);
   F.S2d = (double*)A(G.s2_len * 8);
   F.X3fd = (double*)A(G.x3f_len * 8);
@@ -522,7 +535,7 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     F.x2 = (double*)A(G.p * 8); F.xp2 = (double*)A(G.p * 8); F.gp2 = (double*)A(G.p * 8);
     F.yb2 = (double*)A(G.p * 8); F.gyb2 = (double*)A(G.p * 8);
   }
-  F.inc = A(G.inc_len * es);
+  F.inc = A(G.inc_len * 8);
   F.iter = (int*)A(sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
@@ -780,6 +793,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   int path_status = GLAM_OK;
   long long path_inner = 0;
   res->n_done = 0;
+  res->escalated_at = -1;
   res->chain_ms = 0.0;
   res->iter_ms = 0.0;
   res->chain_samples = 0;
@@ -794,6 +808,13 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     StepStats st{};
     double kkt = INFINITY, Fobj = NAN;
     int outer_base = 0;
+    // precision escalation: a BF16/FP32 inner loop that ends on its rounding floor (stall or
+    // noise rule, not tol_in) three outer steps in a row while the FP64 KKT improves by less
+    // than 10% cannot refine this problem further (its conditioning times the chain's epsilon
+    // is too large); the fit then continues with the FP64 chain for the rest of the path
+    int lowprec_stalls = 0;
+    bool last_limited = false;
+    double kkt_prev = INFINITY;
     for (int step = 0; step < msa_steps; ++step) {
     if (scad) {   // MSA-lasso: the lasso first, then weights from the previous step's estimate
       if (step == 0) PCHK(base_weights());
@@ -808,6 +829,15 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (!std::isfinite(kkt) || !std::isfinite(Fobj)) { status = GLAM_ENONFINITE; break; }
       if (kkt <= tol) { status = GLAM_OK; break; }
       if (k == opt->max_outer) break;
+      if (F.dt != DT_F64 && !F.gram) {
+        lowprec_stalls = (k > 0 && last_limited && kkt > 0.9 * kkt_prev) ? lowprec_stalls + 1 : 0;
+        if (lowprec_stalls >= 3) {
+          escalate_f64(F);
+          if (res->escalated_at < 0) res->escalated_at = l;
+          if (verbose) fprintf(stderr, "[glam] lambda %d k %d: inner chain continues in FP64\n", l, k);
+        }
+      }
+      kkt_prev = kkt;
       const double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
@@ -858,6 +888,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       }
       inner_total += it;
       if (!std::isfinite(kin)) { status = GLAM_ENONFINITE; break; }
+      last_limited = kin > tol_in && it < opt->max_inner;   // ended on the rounding floor
       // theta~ = x^l of the last checked iteration (held in xp)
       PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
       double alpha = 0.0, Delta = 0.0;

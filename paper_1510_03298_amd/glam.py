@@ -55,7 +55,7 @@ class GlamResult(ctypes.Structure):
                 ("iters_outer", ctypes.POINTER(ctypes.c_int)), ("iters_inner", ctypes.POINTER(ctypes.c_int)),
                 ("status", ctypes.POINTER(ctypes.c_int)), ("n_done", ctypes.c_int), ("lambda_max", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("chain_ms", ctypes.c_double), ("chain_samples", ctypes.c_int),
-                ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong)]
+                ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong), ("escalated_at", ctypes.c_int)]
 
 
 class GlamBatchOptions(ctypes.Structure):
@@ -294,6 +294,7 @@ class PathResult:
     chain_samples: int = 0
     iter_ms: float = 0.0
     inner_total: int = 0
+    escalated_at: int = -1   # first model fitted on with the FP64 inner chain, or -1
 
 
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
@@ -357,7 +358,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     out = PathResult(np.array(lam_out[:]), theta, np.array(kkt[:]), np.array(obj[:]), np.array(io[:]),
                      np.array(ii[:]), np.array(stt[:]), int(res.n_done), float(res.lambda_max),
                      float(res.seconds), int(code), float(res.chain_ms), int(res.chain_samples),
-                     float(res.iter_ms), int(res.inner_total))
+                     float(res.iter_ms), int(res.inner_total), int(res.escalated_at))
     if raise_on_error and code != GLAM_OK:
         raise GlamError(code, "glam_fit_path")
     return out

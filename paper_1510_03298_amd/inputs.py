@@ -238,6 +238,41 @@ def config_c5(n=(128, 128, 256), p=(32, 32, 64)) -> GlamData:
                     theta_true=beta_true, extra={"beta": np.asfortranarray(beta)})
 
 
+def config_sim(r=3, q=0.5, family="gaussian", kappa=0.25, seed=6, nlambda=100, ratio=1e-4) -> GlamData:
+    """The simulated design of Section 6.5: n = (60r, 20r, 10r), p_j = max(3, n_j q), rows
+    of X_j i.i.d. N(0, Sigma) with Sigma = (sigma - kappa) I + kappa 1 1^T,
+    theta_m = (-1)^m exp(-(m - 1)/10) B_m with B_m ~ Bernoulli(s).  Gaussian: sigma = 1,
+    s = 1, unit noise; Poisson: sigma = 0.71, s = 0.01.
+
+    The modes are listed with the largest last: (20r, 10r, 60r).  A GLAM is unchanged by a
+    joint permutation of its modes, Y's axes and Theta's axes, and the solver's slab
+    kernel takes the two smaller modes (p_j <= 32 there, hence r <= 3 at q = 0.5; the
+    p > n designs, q = 3, do not fit it).  The coefficient index m runs over the
+    permuted array in vec order."""
+    rng = np.random.default_rng(SEED_BASE + seed)
+    n_paper = (60 * r, 20 * r, 10 * r)
+    order = (1, 2, 0)
+    n = tuple(n_paper[j] for j in order)
+    p = tuple(max(3, int(round(nj * q))) for nj in n)
+    gaussian = family == "gaussian"
+    sigma, s = (1.0, 1.0) if gaussian else (0.71, 0.01)
+    X = []
+    for nj, pj in zip(n, p):
+        cov = (sigma - kappa) * np.eye(pj) + kappa * np.ones((pj, pj))
+        X.append(np.ascontiguousarray(rng.multivariate_normal(np.zeros(pj), cov, size=nj)))
+    P = int(np.prod(p))
+    m = np.arange(1, P + 1)
+    B = rng.uniform(size=P) < s
+    theta = np.asfortranarray(((-1.0) ** m * np.exp(-(m - 1) / 10.0) * B).reshape(p, order="F"))
+    eta = _signal_from_coefficients(X, theta)
+    if gaussian:
+        Y = eta + rng.standard_normal(n)
+    else:
+        Y = rng.poisson(np.exp(np.clip(eta, -30, 30))).astype(np.float64)
+    return GlamData(f"sim65_{family}_r{r}_q{q}_k{kappa}", family, X, np.asfortranarray(Y), nlambda=nlambda,
+                    lambda_min_ratio=ratio, theta_true=theta)
+
+
 def random_problem(n, p, family="gaussian", seed=0, sparsity=0.2, noise=0.5, basis="bspline",
                    obs_weights=False, scale=1.0) -> GlamData:
     """Small seeded problem for parity tests.

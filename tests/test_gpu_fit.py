@@ -189,6 +189,7 @@ def test_bf16_chain_all_register_tiles(fam):
     r2 = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lam], dtype=2, kkt_tol=1e-6)
     r0 = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lam], dtype=0, kkt_tol=1e-9)
     assert abs(r2.lambda_max - lm) <= 1e-12 * lm
+    assert r2.escalated_at == -1   # a well-conditioned problem stays in BF16
     _check_model(d, fam, _theta(glam, r2, 0, d.p), lam, lm, 1e-6, ref=_theta(glam, r0, 0, d.p))
 
 
@@ -407,3 +408,39 @@ def test_scad_path_matches_oracle(fam, dt):
     las = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[res.lambdas[-1]], dtype=dt, kkt_tol=1e-8)
     nll = lambda t: O.neg_loglik_scaled(fam, O.H(d.X, t), d.Y)
     assert nll(_theta(glam, res, 3, d.p)) < nll(_theta(glam, las, 0, d.p))
+
+
+@pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 2), ("poisson", 0), ("poisson", 2)])
+def test_sec65_simulated_design(fam, dt):
+    """Section 6.5's simulated benchmark design (correlated Gaussian factors, kappa = 0.25,
+    r = 1, q = 0.5): a 10-lambda path, every model certified by the oracle's KKT."""
+    torch, glam = need_gpu()
+    d = inputs.config_sim(r=1, family=fam)
+    print(f"sec65 {fam} dt={dt} n={d.n} p={d.p}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=10, lambda_min_ratio=1e-2, dtype=dt, kkt_tol=1e-6)
+    assert res.code == 0, (res.code, res.status)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    assert abs(res.lambda_max - lm) <= 1e-12 * lm
+    for l in (1, 5, 9):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
+
+
+def test_precision_escalation_on_ill_conditioned_design():
+    """Section 6.5's Poisson design at r = 3 (correlated Gaussian factors, condition number
+    of X^T X in the tens of millions): the BF16 chain cannot refine it, so the fit goes on
+    with the FP64 chain and the whole path still converges, certified by the oracle."""
+    torch, glam = need_gpu()
+    d = inputs.config_sim(r=3, family="poisson")
+    print(f"escalation n={d.n} p={d.p}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=40, lambda_min_ratio=0.02, dtype=2, kkt_tol=1e-6)
+    assert res.code == 0 and res.n_done == 40
+    assert 0 <= res.escalated_at < 40
+    lm = O.lambda_max("poisson", d.X, d.Y)
+    for l in (res.escalated_at, 39):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient("poisson", d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
