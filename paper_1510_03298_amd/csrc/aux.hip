@@ -434,7 +434,7 @@ hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
 hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, double alpha,
                              int j0, double* partials, int* nblk_out, hipStream_t s) {
   int nb = grid1d(p);
-  if (nb > 256) nb = 256;
+  if (nb > kPenTrialsMaxBlocks) nb = kPenTrialsMaxBlocks;
   *nblk_out = nb;
   hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, alpha, j0, partials);
   return hipGetLastError();
@@ -457,8 +457,10 @@ hipError_t launch_check(long long n, const double* y, const double* a, long long
 
 hipError_t launch_armijo(const Geom& G, int family, const double* eta_int, const double* xd_int, const double* y_int,
                          const double* a_int, int j0, double* partials, int* nblk_out, hipStream_t s) {
+  // up to 2048 workgroups (8 waves per SIMD) to hide the latency of the four FP64 streams;
+  // the partials buffer holds 2048 rows of trial sums plus the penalty trials' 256
   int nb = grid1d(G.nint);
-  if (nb > 1024) nb = 1024;
+  if (nb > kArmijoMaxBlocks) nb = kArmijoMaxBlocks;
   *nblk_out = nb;
   hipLaunchKernelGGL(k_armijo, dim3(nb), dim3(WG), 0, s, G, family, eta_int, xd_int, y_int, a_int, j0, partials);
   return hipGetLastError();

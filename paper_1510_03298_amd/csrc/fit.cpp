@@ -106,6 +106,10 @@ struct Fit {
   double *S1g = nullptr, *S2g = nullptr;   // X_1^T X_1, X_2^T X_2 (FP64)
   void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
   void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
+  double* S3g = nullptr;   // X_3^T X_3 (FP64)
+  bool gram_fused = false; // Gram iteration as one launch (k_gram_iter): increment and counter double-buffered
+  void* inc2 = nullptr;    // the second increment buffer
+  int gpar = 0;            // which of (inc, inc2) / (iter[0], iter[1]) holds the current increment / counter
   Geom Gg{};               // geometry of the mode-3 Gram product (contraction length p3)
   double *T1d, *S2d;       // FP64 intermediates
   double *theta, *gref, *x, *xp, *gp, *dvec;
@@ -231,6 +235,25 @@ constexpr int kSampleReps = 8;   // back-to-back launches of the fused slab kern
 static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool sample) {
   const Geom& G = F.G;
   if (sample) FCHK(hipEventRecord(F.ev[0], F.s));
+  if (F.gram && F.gram_fused) {
+    // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I) and the
+    // proximal step, one launch; reads the current increment / counter, writes the other pair
+    GramIterParams gp{};
+    gp.G = G; gp.S1 = F.S1g; gp.S2 = F.S2g; gp.S3 = F.S3g;
+    gp.inc_in = F.gpar ? F.inc2 : F.inc; gp.inc_out = F.gpar ? F.inc : F.inc2;
+    gp.iter_in = F.iter + F.gpar; gp.iter_out = F.iter + (1 - F.gpar);
+    gp.gref = F.gref; gp.theta_ref = F.theta; gp.pen_w = F.pen; gp.x = F.x; gp.xp = F.xp; gp.gp = F.gp;
+    gp.dparams = F.dparams; gp.alpha = F.enet; gp.scale = 1.0 / (double)G.n; gp.partials = F.part;
+    FCHK(launch_gram_iter(F.dt, gp, nblk, F.s));
+    F.gpar ^= 1;
+    if (sample) {   // iteration time only
+      FCHK(hipEventRecord(F.ev[1], F.s));
+      FCHK(hipEventRecord(F.ev[2], F.s));
+      FCHK(hipEventRecord(F.ev[3], F.s));
+      F.pending = true;
+    }
+    return GLAM_OK;
+  }
   if (F.gram) {
     // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I)
     FCHK(launch_gram12(F.dt, G, F.inc, F.S1g, F.S2g, F.Zc, F.iter, F.s));
@@ -325,6 +348,8 @@ static int wait_published(Fit& F, double* vals, int nval) {
 }
 
 static int inner_block_graph(Fit& F, int m, int* nblk) {
+  // a fused Gram block alternates its buffers: replayable only from buffer 0 with even m
+  if (F.gram_fused && (F.gpar != 0 || (m & 1))) return inner_block_eager(F, m, false, nblk);
   if (!F.gexec || F.graph_m != m) {
     if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
     if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
@@ -338,7 +363,7 @@ static int inner_block_graph(Fit& F, int m, int* nblk) {
     FCHK(hipGraphInstantiate(&F.gexec, F.graph, nullptr, nullptr, 0));
     F.graph_m = m;
   } else {
-    *nblk = slab_adj_blocks(F.G);
+    *nblk = F.gram_fused ? gram_iter_blocks(F.dt, F.G) : slab_adj_blocks(F.G);
   }
   FCHK(hipGraphLaunch(F.gexec, F.s));
   return GLAM_OK;
@@ -498,7 +523,8 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   const size_t es = dt_size(F.dt);
   const size_t accs = F.dt == DT_F64 ? 8 : 4;
   const size_t nadj = (size_t)slab_adj_blocks(G);
-  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * ADJ_NSUM, 1024 * (ARMIJO_TRIALS + 1) * 2 + 256 * (ARMIJO_TRIALS + 1)});
+  const size_t npart = std::max<size_t>({(size_t)G.n3 * 2 + nadj * ADJ_NSUM, (size_t)(kArmijoMaxBlocks + kPenTrialsMaxBlocks) * (ARMIJO_TRIALS + 1),
+                                         (size_t)gram_iter_blocks(F.dt, G) * ADJ_NSUM});
 
   bool ok = true;
   auto A = [&](size_t b) { void* p = F.alloc(b); if (!p) ok = false; return p; };
@@ -536,7 +562,7 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     F.yb2 = (double*)A(G.p * 8); F.gyb2 = (double*)A(G.p * 8);
   }
   F.inc = A(G.inc_len * 8);
-  F.iter = (int*)A(sizeof(int));
+  F.iter = (int*)A(2 * sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
   F.dparams = (double*)A(4 * 8);
@@ -626,6 +652,13 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     F.Gg.KBN3 = G.KB3;
     F.Gg.s2_len = G.inc_len;
     F.Gg.x3a_len = (long long)G.KB3 * 16 * G.p3;
+    F.S3g = s3;
+    F.gram_fused = gram_iter_pays(F.dt, G);
+    if (F.gram_fused) {
+      F.inc2 = F.alloc(G.inc_len * 8);
+      if (!F.inc2) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
+      FCHK(launch_zero(F.inc2, G.inc_len * 8, F.s));   // padding of the k-blocks stays zero
+    }
   }
   return GLAM_OK;
 }
@@ -849,6 +882,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (F.dt == DT_BF16) tol_in = std::max(tol_in, 0.1 * kkt);
       // ---- inner PG loop ----
       PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      F.gpar = 0;   // the increment and the counter start in buffer 0
       int it = 0;
       double kin = INFINITY, noise = 0.0;
       if (opt->nu < 1.0) {

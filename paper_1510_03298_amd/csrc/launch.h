@@ -149,6 +149,29 @@ hipError_t launch_segment_max(const double* partials, const int* off, int nprob,
 // increments *iter once when iter != NULL
 hipError_t launch_gram12(int dt, const Geom& G, const void* inc, const double* S1, const double* S2, void* Z, int* iter,
                          hipStream_t s);
+// One inner PG iteration of the Gram form (Sec. 6.2) in one launch; see gram.hip.
+constexpr int GRAM_MAX_P3 = 2048;   // contraction length p3 (padded to 16) the fused kernel takes
+struct GramIterParams {
+  Geom G;
+  const void* inc_in;       // increment x - theta_ref (chain dtype, k-blocked), read
+  void* inc_out;            // next increment, written (must not alias inc_in)
+  const double *S1, *S2, *S3;   // FP64 Gram factors X_j^T X_j (p_j x p_j, symmetric)
+  const double *gref, *theta_ref, *pen_w;
+  double *x, *xp, *gp;      // FISTA state, updated on each workgroup's own slice
+  const double* dparams;    // device {lambda, delta}
+  const int* iter_in;       // iteration counter l - 1, read
+  int* iter_out;            // l, written (must not alias iter_in)
+  double alpha;             // elastic-net weight
+  double scale;             // 1 / n
+  double* partials;         // [nblk][ADJ_NSUM], slab_adj's layout
+  int per_xcd;              // set by the launcher
+};
+int gram_iter_blocks(int dt, const Geom& G);
+bool gram_iter_fits(const Geom& G);
+// the fused iteration is used for BF16 and FP32 increments: in FP64 each workgroup's read of
+// the whole increment (8 bytes an element) costs more than the two-kernel form
+bool gram_iter_pays(int dt, const Geom& G);
+hipError_t launch_gram_iter(int dt, const GramIterParams& P, int* nblk_out, hipStream_t s);
 
 // rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);
@@ -225,6 +248,8 @@ hipError_t launch_scad_weights(long long p, const double* theta, const double* b
 hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,
                         double* partials, int* nblk_out, hipStream_t s);
 
+constexpr int kArmijoMaxBlocks = 2048;     // workgroups of k_armijo (rows of trial partials)
+constexpr int kPenTrialsMaxBlocks = 256;   // workgroups of k_pen_trials
 constexpr int ARMIJO_TRIALS = 16;   // step sizes 2^-j0 .. 2^-(j0+15) evaluated in one pass
 
 }  // namespace glam
