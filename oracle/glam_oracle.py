@@ -53,6 +53,11 @@ R16 families beyond Gaussian and Poisson (Sec. 6.4 lists Binomial-logit and Gamm
     mu (1 - mu) for the logit, and exactly 1 for the Gamma-log model (Fisher
     scoring, a non-canonical link), so Gamma shares the Gaussian's unit weights
     but not its exact quadratic model.
+R18 tensor-product weights (Sec. 6.2): V-hat = Vbar * prod_j v_j with the paper's
+    geometric-mean factors v_j; the displayed product omits Vbar, without which V-hat
+    would not reproduce a V that is already a tensor product.  W = V-hat enters the outer
+    loop through eq. (ten) (z = W^{-1} u + eta), so the model's gradient at theta^k is
+    exact and only its curvature is approximated; Lhat is Proposition 1 with max V-hat.
 R17 SCAD (Sec. 6.4): Fan and Li's penalty with a = 3.7; MSA-lasso step 1 is the lasso
     (with the caller's penalty weights), each further step the weighted lasso with
     w_m = pen_w_m p'_lambda(|theta_m|) / lambda at the previous step's estimate.  The
@@ -357,6 +362,26 @@ def working_response_eq10(u, w, eta):
     return u / w + eta
 
 
+def kron_weights(V):
+    """Sec. 6.2: the tensor-product approximation of a positive weight array V.
+    v_j[i] = exp(mean of log V over the other indices at i_j = i, minus log Vbar), with
+    Vbar the geometric mean of V; V-hat = Vbar * prod_j v_j[i_j] (R18: the factor Vbar
+    makes V-hat = V whenever V is itself a tensor product).  Returns (V-hat, [v_j], Vbar)."""
+    L = np.log(V)
+    d = V.ndim
+    logbar = float(L.mean())
+    Vh = np.full(V.shape, math.exp(logbar))
+    factors = []
+    for j in range(d):
+        axes = tuple(k for k in range(d) if k != j)
+        vj = np.exp(L.mean(axis=axes) - logbar)
+        factors.append(vj)
+        shape = [1] * d
+        shape[j] = V.shape[j]
+        Vh = Vh * vj.reshape(shape)
+    return Vh, factors, math.exp(logbar)
+
+
 # =============================================================================
 # Penalty, prox, objective, KKT
 # =============================================================================
@@ -537,10 +562,13 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
 
 def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
          max_outer=100, max_inner=100000, nu=1.0, alpha0=1.0, b=0.5, v=0.1,
-         max_ls=60, record_inner=False, alpha=0.0) -> tuple:
+         max_ls=60, record_inner=False, alpha=0.0, weights="exact") -> tuple:
     """GD-PG, Algorithm 1, for one lambda.
 
-    Step 2: eta = H(theta^k); U, V (eq. nine), Z (eq. tennew).
+    Step 2: eta = H(theta^k); U, V (eq. nine), Z (eq. tennew).  weights="kron": W^(k)
+    is the tensor-product approximation V-hat of Sec. 6.2 and Z follows eq. (ten) with
+    that W (the outer loop of Sec. 3.1 admits any positive diagonal W^(k); the model's
+    gradient at theta^k stays -X^T u / n).
     Step 3: delta = 1/(nu Lhat) with Lhat from Proposition 1.
     Step 4: inner PG loop from x^(0) = x^(1) = theta^k.
     Step 5: Armijo rule (alpha_0 b^j, v), Delta_k = -u^T X d / n + lambda (J(theta~) - J(theta)).
@@ -567,6 +595,9 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
             break
         V = irls_weights(fam, eta)
         Z = working_response(fam, eta, Y, a)
+        if weights == "kron":
+            V = kron_weights(V)[0]
+            Z = working_response_eq10(u, V, eta)
         Lhat = float(np.max(V)) * s_prod / n
         delta = 1.0 / (nu * Lhat) if nu > 0 else 1.0
         cz = G(Xs, V * Z) / n
@@ -597,7 +628,7 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
 
 def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e-4,
              tol=1e-10, max_outer=100, max_inner=100000, nu=1.0, theta0=None,
-             max_lambdas=None, alpha=0.0):
+             max_lambdas=None, alpha=0.0, weights="exact"):
     """lambda path with warm starts (Sec. 6.4).  Returns (lambdas, thetas, infos,
     lam_max).  Stops early, returning the preceding models, when a fit does not
     converge (the packages' early-exit convention, Sec. 6.5)."""
@@ -611,7 +642,8 @@ def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e
     theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
     thetas, infos = [], []
     for lam in lambdas:
-        theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, pen_w, theta, tol, max_outer, max_inner, nu, alpha=alpha)
+        theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, pen_w, theta, tol, max_outer, max_inner, nu, alpha=alpha,
+                           weights=weights)
         thetas.append(theta.copy())
         infos.append(info)
         if not info.converged:

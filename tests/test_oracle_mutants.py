@@ -81,6 +81,10 @@ MUTANTS = {
                    lambda orig: (lambda t, lam, a=O.SCAD_A: np.where(np.abs(t) <= lam, lam,
                                                                      np.maximum(a * lam - np.abs(t), 0.0) / a)),
                    lambda: [P.test_scad_penalty_and_slope, P.test_msa_orthogonal_design_reaches_scad_thresholding]),
+    # tensor-product weights without the geometric-mean factor Vbar (the displayed product alone)
+    "kron_no_vbar": ("kron_weights",
+                     lambda orig: (lambda V: (lambda r: (r[0] / r[2], r[1], r[2]))(orig(V))),
+                     lambda: [P.test_kron_weights_exact_for_tensor_products]),
     # H applies the factors in reverse order (wrong mode index)
     "H_reversed": ("H", lambda orig: (lambda Xs, Th: orig(list(Xs)[::-1], Th)),
                    lambda: [lambda: P.test_kronecker_rho_identity((6, 5, 4), (6, 5, 4)), P.test_adjoint_dot_product]),
