@@ -166,7 +166,13 @@ typedef struct {
  * nu < 1).  The Gram products run in the
  * accumulation type of the dtype (FP32 for BF16/F32, FP64 for F64), the mode-3 product on
  * the matrix cores in the chain dtype. */
-typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1 } glam_inner;
+/* GLAM_INNER_KRON: the same p-sized inner loop for any family, with the IRLS weights replaced
+ * by their tensor-product approximation V-hat (Sec. 6.2): each outer step forms
+ * S_j = X_j^T diag(v_j) X_j from the geometric means of log V over all but one index, and
+ * W = V-hat enters through eq. (ten), so the model's gradient at theta^k is exact and only its
+ * curvature is approximated (the Armijo rule and the FP64 KKT test are unchanged).  For the
+ * unit-weight families it is GLAM_INNER_GRAM.  Needs nu = 1 (GLAM_EINVAL otherwise). */
+typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1, GLAM_INNER_KRON = 2 } glam_inner;
 
 typedef struct {
   double* theta;          /* device, FP64, nlambda x p (model l at offset l*p), caller-allocated */

@@ -107,6 +107,9 @@ struct Fit {
   void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
   void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
   double* S3g = nullptr;   // X_3^T X_3 (FP64)
+  bool kron = false;       // Gram factors reweighted each outer step with tensor-product weights (Sec. 6.2)
+  double* kron_work = nullptr;    // log-weight margins and the factors v_j
+  double* kron_stats = nullptr;   // {max v_1, max v_2, max v_3, Vbar} (device)
   bool gram_fused = false; // Gram iteration as one launch (k_gram_iter): increment and counter double-buffered
   void* inc2 = nullptr;    // the second increment buffer
   int gpar = 0;            // which of (inc, inc2) / (iter[0], iter[1]) holds the current increment / counter
@@ -654,6 +657,11 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     F.Gg.x3a_len = (long long)G.KB3 * 16 * G.p3;
     F.S3g = s3;
     F.gram_fused = gram_iter_pays(F.dt, G);
+    if (F.kron) {
+      F.kron_work = (double*)F.alloc(kron_work_doubles(G) * 8);
+      F.kron_stats = (double*)F.alloc(8 * 8);
+      if (!F.kron_work || !F.kron_stats) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
+    }
     if (F.gram_fused) {
       F.inc2 = F.alloc(G.inc_len * 8);
       if (!F.inc2) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
@@ -728,8 +736,10 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       return fit_fail(GLAM_EINVAL, "scad_a must be > 2 (or 0 for 3.7)");
     if (opt->alpha != 0.0) return fit_fail(GLAM_EINVAL, "SCAD and the elastic net do not combine");
   }
-  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM)
+  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM && opt->inner_mode != GLAM_INNER_KRON)
     return fit_fail(GLAM_EINVAL, "bad inner_mode");
+  if (opt->inner_mode == GLAM_INNER_KRON && opt->nu < 1.0)
+    return fit_fail(GLAM_EINVAL, "the tensor-product-weight inner loop runs without backtracking (nu = 1)");
   if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(prob->family) || prob->obs_w || opt->nu < 1.0))
     return fit_fail(GLAM_EINVAL, "the Gram inner loop is exact only for unit IRLS weights (Gaussian, Gamma-log) "
                                  "without prior weights (Sec. 6.2) and runs without backtracking (nu = 1)");
@@ -762,7 +772,8 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
-  F.gram = opt->inner_mode == GLAM_INNER_GRAM;
+  F.gram = opt->inner_mode == GLAM_INNER_GRAM || opt->inner_mode == GLAM_INNER_KRON;
+  F.kron = opt->inner_mode == GLAM_INNER_KRON && family_has_weights(prob->family);
   F.enet = opt->alpha;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
@@ -816,11 +827,12 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
 
   const bool exact_model = F.family == GLAM_GAUSSIAN && prob->obs_w == nullptr;
   const double tol = opt->kkt_tol;
-  // The inner stopping rule is checked every check_every iterations, except for the Gamma-log
-  // model: its Fisher-scoring quadratic (unit weights, a non-canonical link) can be far from
-  // the objective's curvature, and iterating past the first point that meets the rule makes
-  // the outer steps short (the Armijo rule cuts them), so there it is checked every iteration.
-  const int check_every = F.family == GLAM_GAMMA ? 1 : opt->check_every;
+  // The inner stopping rule is checked every check_every iterations, except where the model's
+  // curvature can be far from the objective's: the Gamma-log model (Fisher scoring with unit
+  // weights, a non-canonical link) and the tensor-product weights of Sec. 6.2.  There,
+  // iterating past the first point that meets the rule makes the outer steps short (the
+  // Armijo rule cuts them), so the rule is checked every iteration.
+  const int check_every = (F.family == GLAM_GAMMA || F.kron) ? 1 : opt->check_every;
   const int log_level = getenv("GLAM_LOG") ? atoi(getenv("GLAM_LOG")) : 0;
   const bool verbose = log_level > 0;
   int path_status = GLAM_OK;
@@ -871,7 +883,17 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         }
       }
       kkt_prev = kkt;
-      const double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
+      double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
+      if (F.kron) {
+        // W^(k) = V-hat (Sec. 6.2): reweighted Gram factors from this step's eta; Proposition 1
+        // with max V-hat = Vbar prod_j max v_j
+        PCHK(launch_kron_weights(G, F.family, F.eta_int, prob->X[0], prob->X[1], prob->X[2], F.kron_work,
+                                 F.kron_stats, F.S1g, F.S2g, F.S3g, F.s));
+        if (!F.gram_fused) PCHK(launch_pack(F.dt, DT_F64, F.S3g, G.p3, G.p3, 1, G.p3, F.S3c, F.s));
+        PCHK(hipMemcpyAsync(F.hred, F.kron_stats, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+        PCHK(hipStreamSynchronize(F.s));
+        wmax = F.hred[3] * F.hred[0] * F.hred[1] * F.hred[2];
+      }
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
       const double delta = 1.0 / (opt->nu * Lhat);

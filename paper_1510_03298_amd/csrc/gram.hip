@@ -272,4 +272,141 @@ hipError_t launch_gram_iter(int dt, const GramIterParams& P0, int* nblk_out, hip
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Tensor-product approximation of the IRLS weights (Sec. 6.2) for the Gram inner loop of a
+// family whose weights vary with eta.  log V is averaged over all but one index per mode:
+//   v_j[i] = exp(mean_{others} log V - log Vbar),  Vbar = geometric mean of V,
+// and the model's curvature uses V-hat = Vbar prod_j v_j[i_j], i.e. the Gram factors
+// S_j = X_j^T diag(v_j) X_j with Vbar folded into S_3.
+__device__ inline double log_weight(int family, double eta) {
+  if (family == 1) return eta;                                          // Poisson: w = e^eta
+  if (family == 2) return -fabs(eta) - 2.0 * log1p(exp(-fabs(eta)));   // Binomial: mu (1 - mu)
+  return 0.0;                                                           // unit weights
+}
+
+// one workgroup per slab i3 (grid-stride): per-slab sums of log V over i2 (for each i1), over
+// i1 (for each i2) and over the whole slab, from the tiled eta of the family step
+__global__ __launch_bounds__(256) void k_logv_margins(Geom G, int family, const double* __restrict__ eta_int,
+                                                      double* __restrict__ P1, double* __restrict__ P2,
+                                                      double* __restrict__ P3) {
+  __shared__ double s1[256], s2[256], sw[4];
+  const int t = threadIdx.x;
+  const long long per_slab = (long long)G.NJB * G.N1T * 256;
+  for (int i3 = blockIdx.x; i3 < G.n3; i3 += gridDim.x) {
+    s1[t] = 0.0;
+    s2[t] = 0.0;
+    __syncthreads();
+    double tot = 0.0;
+    const double* e = eta_int + (long long)i3 * per_slab;
+    for (long long q = t; q < per_slab; q += 256) {
+      const int i1l = (int)(q & 15), i2l = (int)((q >> 4) & 15);
+      const long long tile = q >> 8;
+      const int i1 = (int)(tile % G.N1T) * 16 + i1l, i2 = (int)(tile / G.N1T) * 16 + i2l;
+      if (i1 < G.n1 && i2 < G.n2) {
+        const double L = log_weight(family, e[q]);
+        tot += L;
+        atomicAdd(&s1[i1], L);
+        atomicAdd(&s2[i2], L);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if ((t & 63) == 0) sw[t >> 6] = tot;
+    __syncthreads();
+    if (t < G.n1) P1[(long long)i3 * G.n1 + t] = s1[t];
+    if (t < G.n2) P2[(long long)i3 * G.n2 + t] = s2[t];
+    if (t == 0) P3[i3] = sw[0] + sw[1] + sw[2] + sw[3];
+    __syncthreads();
+  }
+}
+
+// v_1, v_2, v_3 (n1 + n2 + n3 values) and stats = {max v_1, max v_2, max v_3, Vbar}: one workgroup
+__global__ __launch_bounds__(256) void k_kron_factors(Geom G, const double* __restrict__ P1,
+                                                      const double* __restrict__ P2, const double* __restrict__ P3,
+                                                      double* __restrict__ v, double* __restrict__ stats) {
+  __shared__ double red[4][4];
+  const int t = threadIdx.x;
+  const int n1 = G.n1, n2 = G.n2, n3 = G.n3;
+  double tot = 0.0;
+  for (int i3 = t; i3 < n3; i3 += 256) tot += P3[i3];
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  if ((t & 63) == 0) red[0][t >> 6] = tot;
+  __syncthreads();
+  const double logbar = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) / (double)G.n;
+  double mx[3] = {0.0, 0.0, 0.0};
+  for (int i = t; i < n1; i += 256) {
+    double s = 0.0;
+    for (int i3 = 0; i3 < n3; ++i3) s += P1[(long long)i3 * n1 + i];
+    const double vi = exp(s / ((double)n2 * n3) - logbar);
+    v[i] = vi;
+    mx[0] = fmax(mx[0], vi);
+  }
+  for (int i = t; i < n2; i += 256) {
+    double s = 0.0;
+    for (int i3 = 0; i3 < n3; ++i3) s += P2[(long long)i3 * n2 + i];
+    const double vi = exp(s / ((double)n1 * n3) - logbar);
+    v[n1 + i] = vi;
+    mx[1] = fmax(mx[1], vi);
+  }
+  for (int i = t; i < n3; i += 256) {
+    const double vi = exp(P3[i] / ((double)n1 * n2) - logbar);
+    v[n1 + n2 + i] = vi;
+    mx[2] = fmax(mx[2], vi);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    for (int o = 32; o > 0; o >>= 1) mx[j] = fmax(mx[j], __shfl_xor(mx[j], o, 64));
+    if ((t & 63) == 0) red[1 + j][t >> 6] = mx[j];
+  }
+  __syncthreads();
+  if (t < 3) stats[t] = fmax(fmax(red[1 + t][0], red[1 + t][1]), fmax(red[1 + t][2], red[1 + t][3]));
+  if (t == 3) stats[3] = exp(logbar);
+}
+
+// S_j = X_j^T diag(v_j) X_j (FP64, p_j x p_j, column-major), S_3 scaled by Vbar: one thread per entry
+__global__ __launch_bounds__(256) void k_kron_gram(Geom G, const double* __restrict__ X1, const double* __restrict__ X2,
+                                                   const double* __restrict__ X3, const double* __restrict__ v,
+                                                   const double* __restrict__ stats, double* __restrict__ S1,
+                                                   double* __restrict__ S2, double* __restrict__ S3) {
+  const long long e1 = (long long)G.p1 * G.p1, e2 = (long long)G.p2 * G.p2, e3 = (long long)G.p3 * G.p3;
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < e1 + e2 + e3; q += (long long)gridDim.x * 256) {
+    const double* X;
+    const double* vj;
+    double* S;
+    long long e;
+    int nj, pj;
+    double scale = 1.0;
+    if (q < e1) { X = X1; vj = v; S = S1; e = q; nj = G.n1; pj = G.p1; }
+    else if (q < e1 + e2) { X = X2; vj = v + G.n1; S = S2; e = q - e1; nj = G.n2; pj = G.p2; }
+    else { X = X3; vj = v + G.n1 + G.n2; S = S3; e = q - e1 - e2; nj = G.n3; pj = G.p3; scale = stats[3]; }
+    const int a = (int)(e % pj), b = (int)(e / pj);
+    const double* xa = X + (long long)a * nj;
+    const double* xb = X + (long long)b * nj;
+    double s = 0.0;
+    for (int i = 0; i < nj; ++i) s += xa[i] * vj[i] * xb[i];
+    S[e] = scale * s;
+  }
+}
+
+hipError_t launch_kron_weights(const Geom& G, int family, const double* eta_int, const double* X1, const double* X2,
+                               const double* X3, double* work, double* stats, double* S1, double* S2, double* S3,
+                               hipStream_t s) {
+  if (G.n1 > 256 || G.n2 > 256) return hipErrorInvalidValue;
+  double* P1 = work;
+  double* P2 = P1 + (long long)G.n3 * G.n1;
+  double* P3 = P2 + (long long)G.n3 * G.n2;
+  double* v = P3 + G.n3;
+  const int nb = G.n3 < 2048 ? G.n3 : 2048;
+  hipLaunchKernelGGL(k_logv_margins, dim3(nb), dim3(256), 0, s, G, family, eta_int, P1, P2, P3);
+  hipLaunchKernelGGL(k_kron_factors, dim3(1), dim3(256), 0, s, G, P1, P2, P3, v, stats);
+  const long long ne = (long long)G.p1 * G.p1 + (long long)G.p2 * G.p2 + (long long)G.p3 * G.p3;
+  const int gb = (int)((ne + 255) / 256 < 4096 ? (ne + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_kron_gram, dim3(gb), dim3(256), 0, s, G, X1, X2, X3, v, stats, S1, S2, S3);
+  return hipGetLastError();
+}
+
+size_t kron_work_doubles(const Geom& G) {
+  return (size_t)G.n3 * G.n1 + (size_t)G.n3 * G.n2 + 2 * (size_t)G.n3 + G.n1 + G.n2;
+}
+
 }  // namespace glam

@@ -171,6 +171,13 @@ bool gram_iter_fits(const Geom& G);
 // the fused iteration is used for BF16 and FP32 increments: in FP64 each workgroup's read of
 // the whole increment (8 bytes an element) costs more than the two-kernel form
 bool gram_iter_pays(int dt, const Geom& G);
+// Tensor-product weights (Sec. 6.2) from the tiled eta of a family step: the weighted Gram
+// factors S_j = X_j^T diag(v_j) X_j (S_3 times Vbar) and stats = {max v_1, max v_2, max v_3,
+// Vbar} (device).  work: kron_work_doubles(G) doubles.  X_j: FP64 column-major factors.
+size_t kron_work_doubles(const Geom& G);
+hipError_t launch_kron_weights(const Geom& G, int family, const double* eta_int, const double* X1, const double* X2,
+                               const double* X3, double* work, double* stats, double* S1, double* S2, double* S3,
+                               hipStream_t s);
 hipError_t launch_gram_iter(int dt, const GramIterParams& P, int* nblk_out, hipStream_t s);
 
 // rho kernels
