@@ -141,7 +141,12 @@ def gram_path(glam, torch, d, Xd, Yd, stream, nlambda, chain_seconds):
     return out
 
 
-def sim65_path(glam, inputs, torch, stream, family):
+def progress(msg):
+    """One progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def sim65_path(glam, inputs, torch, stream, family, forms=("bf16", "f64")):
     """Section 6.5's simulated design at the largest size the slab kernel takes (r = 3,
     q = 0.5, kappa = 0.25; modes (60, 30, 180), p = (30, 15, 90)): the default
     100-lambda path to 1e-4 lambda_max, KKT <= 1e-6, BF16 and FP64 inner chains."""
@@ -151,6 +156,8 @@ def sim65_path(glam, inputs, torch, stream, family):
     out = {"workload": f"sec6.5_simulated_{family}_r3_q0.5_kappa0.25_n{d.n[0]}x{d.n[1]}x{d.n[2]}"
                        f"_p{d.p[0]}x{d.p[1]}x{d.p[2]}_100lambda_kkt1e-6"}
     for dt, name in ((glam.BF16, "bf16"), (glam.F64, "f64")):
+        if name not in forms:
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = glam.fit_path(Xd, Yd, d.n, d.p, family, nlambda=100, lambda_min_ratio=1e-4, dtype=dt, kkt_tol=1e-6,
@@ -299,6 +306,7 @@ def main():
                              dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
                              profile_every=profile_every, raise_on_error=False, graph=not args.eager)
 
+    progress(f"C2 path, {args.warmup} warmup + {args.steps} timed steps ({args.dtype})")
     for _ in range(args.warmup):
         fit(args.dtype)
     torch.cuda.synchronize()
@@ -340,6 +348,7 @@ def main():
         for dt in ["f64", "f32", "bf16"]:
             if dt in forms:
                 continue
+            progress(f"C2 path, {dt} form (untimed comparison)")
             r = fit(dt)
             forms[dt] = {"seconds": r.seconds, "inner": int(r.inner_total), "outer": int(r.iters_outer.sum()),
                          "max_kkt": float(np.max(r.kkt)), "ok": r.code == 0 and r.n_done == args.nlambda}
@@ -347,16 +356,22 @@ def main():
             forms[dt]["speedup_vs_f64"] = forms["f64"]["seconds"] / forms[dt]["seconds"]
     cpu = None
     if not args.no_cpu and "f64" in forms:
+        progress("oracle CPU baseline (bounded sample)")
         cpu = cpu_baseline(d, forms["f64"]["inner"], forms["f64"]["outer"])
     extra = None
     if not args.no_extra:
-        extra = {"gaussian_path_c2_gram": gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec),
-                 "poisson_path_c3": poisson_path(glam, inputs, torch, stream),
-                 "poisson_path_c3_kron": poisson_path_kron(glam, inputs, torch, stream),
-                 "batched_c4": batched(glam, inputs, torch, stream),
-                 "poisson_nll_c5": nll(glam, inputs, torch, stream),
-                 "sim65_gaussian": sim65_path(glam, inputs, torch, stream, "gaussian"),
-                 "sim65_poisson": sim65_path(glam, inputs, torch, stream, "poisson")}
+        jobs = [("gaussian_path_c2_gram", lambda: gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec)),
+                ("poisson_path_c3", lambda: poisson_path(glam, inputs, torch, stream)),
+                ("poisson_path_c3_kron", lambda: poisson_path_kron(glam, inputs, torch, stream)),
+                ("batched_c4", lambda: batched(glam, inputs, torch, stream)),
+                ("poisson_nll_c5", lambda: nll(glam, inputs, torch, stream)),
+                ("sim65_gaussian", lambda: sim65_path(glam, inputs, torch, stream, "gaussian")),
+                # BF16 only: its FP64 form takes ~46 s (1.97M launch-bound inner iterations at n = 324k)
+                ("sim65_poisson", lambda: sim65_path(glam, inputs, torch, stream, "poisson", forms=("bf16",)))]
+        extra = {}
+        for name, job in jobs:
+            progress(f"workload {name}")
+            extra[name] = job()
     out = {
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
