@@ -199,9 +199,11 @@ typedef struct {
  * on a fit that does not converge (GLAM_ENOCONV) or produces non-finite values
  * (GLAM_ENONFINITE) the path stops and only the preceding models are valid
  * (n_done), as the reference package does (Sec. 6.5).
- * Errors: GLAM_EINVAL for bad sizes/pointers/options, non-finite Y, negative Y
- * for the Poisson family, negative obs_w, non-positive pen_w, or a lambda
- * sequence that is not strictly decreasing and positive. */
+ * Errors: GLAM_EINVAL for bad sizes/pointers/options, non-finite Y, Y outside the
+ * family's range, negative obs_w, non-positive pen_w, or a lambda sequence that is not
+ * strictly decreasing and positive.  Sizes: besides the rho limits, the FP64 outer steps
+ * hold both orientations of X_1 and X_2 in LDS, so a fit takes n_1, n_2 <= 256 when
+ * p_1, p_2 <= 16, and about n_1 + n_2 <= 256 when max(p_1, p_2) is 17..32 (GLAM_EINVAL beyond). */
 int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res);
 
 /* ---------------------------------------------------------------------------

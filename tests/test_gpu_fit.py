@@ -469,3 +469,57 @@ def test_kron_weight_inner_loop(fam, dt):
         assert (F1 - F2) / abs(F2) <= 1e-8
     with pytest.raises(glam.GlamError):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="kron", nu=0.5)
+
+
+@pytest.mark.parametrize("fam,dt,n,p", [("gaussian", 2, (256, 256, 9), (16, 16, 4)),
+                                        ("poisson", 1, (128, 128, 9), (32, 32, 4))])
+def test_largest_inner_modes(fam, dt, n, p):
+    """The largest inner modes a fit takes: its FP64 outer steps hold both orientations of X_1
+    and X_2 in LDS, so n_1, n_2 <= 256 with p_1, p_2 <= 16, and n_1 + n_2 <= 256 with p up to
+    32; beyond, the fit is refused."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem(n, p, family=fam, seed=39, basis="gauss", scale=0.2)
+    print(f"largest inner modes {fam} dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=3, lambda_min_ratio=0.1, dtype=dt, kkt_tol=1e-6)
+    assert res.code == 0
+    lm = O.lambda_max(fam, d.X, d.Y)
+    th = _theta(glam, res, 2, d.p)
+    g = O.smooth_gradient(fam, d.X, th, d.Y)
+    assert O.kkt_residual(th, g, res.lambdas[2], lm) <= 1e-6
+    big = inputs.random_problem((256, 256, 3), (32, 32, 2), family=fam, seed=39, basis="gauss", scale=0.2)
+    Xb, Yb, _ = _dev(glam, big)
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xb, Yb, big.n, big.p, fam, nlambda=2, dtype=dt)
+
+
+def test_degenerate_fits():
+    torch, glam = need_gpu()
+    d = inputs.random_problem((12, 11, 10), (5, 4, 6), seed=40, basis="gauss")
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    # lambda = lambda_max: the zero solution, with no outer step
+    r = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", lambdas=[lm], dtype=2)
+    assert r.code == 0 and r.iters_outer[0] == 0 and float(r.theta.abs().max()) == 0.0
+    # Y = 0: lambda_max = 0 and every model is zero
+    Z = torch.zeros_like(Yd)
+    r = glam.fit_path(Xd, Z, d.n, d.p, "gaussian", nlambda=3, dtype=1)
+    assert r.code == 0 and r.lambda_max == 0.0 and float(r.theta.abs().max()) == 0.0
+    # one coefficient: X_j = 1 (n_j x 1) makes eta = theta everywhere and X^T X / n = 1, so the
+    # Gaussian lasso solution is the soft threshold of the mean response
+    n = (7, 9, 13)
+    rng = np.random.default_rng(41)
+    Y = rng.standard_normal(n) + 0.8
+    ones = [glam.to_device_colmajor(np.ones((k, 1)), 0) for k in n]
+    Yd1 = glam.to_device_colmajor(Y, 0)
+    lam = 0.3 * abs(float(Y.mean()))
+    r = glam.fit_path(ones, Yd1, n, (1, 1, 1), "gaussian", lambdas=[lam], dtype=0, kkt_tol=1e-10)
+    expect = np.sign(Y.mean()) * max(abs(Y.mean()) - lam, 0.0)
+    assert abs(float(r.theta[0, 0]) - expect) <= 1e-12 * abs(expect)
+    # a single slab (n_3 = 1)
+    d1 = inputs.random_problem((30, 20, 1), (8, 6, 1), seed=42, basis="gauss")
+    Xd1, Yd2, _ = _dev(glam, d1)
+    r = glam.fit_path(Xd1, Yd2, d1.n, d1.p, "gaussian", nlambda=3, lambda_min_ratio=0.1, dtype=2)
+    lm1 = O.lambda_max("gaussian", d1.X, d1.Y)
+    th = _theta(glam, r, 2, d1.p)
+    assert O.kkt_residual(th, O.smooth_gradient("gaussian", d1.X, th, d1.Y), r.lambdas[2], lm1) <= 1e-6

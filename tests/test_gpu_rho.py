@@ -76,6 +76,28 @@ def test_adjoint_parity(n, p, dt):
     assert rel_inf(got, ref) <= TOL[dt], rel_inf(got, ref)
 
 
+@pytest.mark.parametrize("dt", [1, 2, 0])
+def test_largest_inner_n_and_p(dt):
+    """n_1 = n_2 = 256 with p_1, p_2 near 32: BF16 and FP32 chains take it; the FP64 slab
+    kernel's LDS image (both orientations of X_1, X_2 in FP64) does not, and is refused."""
+    torch, glam = need_gpu()
+    n, p = (256, 256, 3), (32, 31, 2)
+    print(f"largest inner modes dt={dt}", flush=True)
+    Xs = _factors(n, p, 5)
+    Th = np.random.default_rng(6).standard_normal(p)
+    Xd = [glam.to_device_colmajor(X, dt) for X in Xs]
+    th = glam.to_device_colmajor(Th, dt)
+    if dt == 0:
+        with pytest.raises(glam.GlamError):
+            glam.rho_forward(Xd, th, n, p, dt)
+        return
+    got = glam.from_colmajor(glam.rho_forward(Xd, th, n, p, dt), n)
+    assert rel_inf(got, O.H(Xs, Th)) <= TOL[dt]
+    U = np.random.default_rng(7).standard_normal(n)
+    got = glam.from_colmajor(glam.rho_adjoint(Xd, glam.to_device_colmajor(U, dt), n, p, dt), p)
+    assert rel_inf(got, O.G(Xs, U)) <= TOL[dt]
+
+
 @pytest.mark.parametrize("dt", [0, 1])
 def test_kronecker_explicit_small(dt):
     """Device H against the explicit Kronecker design (App. A identity)."""
