@@ -946,13 +946,21 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (!std::isfinite(kin)) { status = GLAM_ENONFINITE; break; }
       last_limited = kin > tol_in && it < opt->max_inner;   // ended on the rounding floor
       // theta~ = x^l of the last checked iteration (held in xp)
-      PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
       double alpha = 0.0, Delta = 0.0;
-      RCHK(armijo(F, lam, 0.1, &alpha, &Delta));
+      if (exact_model) {
+        // the model is the objective itself (Sec. 6.5: no outer loop is needed), so the inner
+        // solution is the new estimate (alpha = 1); further passes only re-anchor a BF16/FP32
+        // inner loop in FP64, and the FP64 KKT test at the next anchor decides convergence
+        alpha = 1.0;
+        PCHK(hipMemcpyAsync(F.theta, F.xp, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+      } else {
+        PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
+        RCHK(armijo(F, lam, 0.1, &alpha, &Delta));
+        if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
+      }
       if (verbose)
         fprintf(stderr, "[glam] lambda %d k %d kkt %.3e F %.12e inner %d kin %.2e noise %.2e alpha %g Delta %.3e\n", l,
                 k, kkt, Fobj, it, kin, noise, alpha, Delta);
-      if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
     }
     outer_base = outer;
     if (status != GLAM_OK) break;
@@ -1160,6 +1168,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   }
   std::vector<char> done(nprob, 0);
   std::vector<double> tol_in(nprob), best(nprob), wbest(nprob);
+  std::vector<char> exact(nprob, 0);   // the model is the objective: the inner solution is the step
   const double tol = opt->kkt_tol;
   long long launches = 0, pstep = 0;
   // checked every step when a Gamma-log problem is in the batch (as in glam_fit_path)
@@ -1192,6 +1201,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
       const double Lhat = wmax * F.sprod / (double)Gs[i].n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { res->status[i] = GLAM_ENONFINITE; done[i] = 1; continue; }
       const bool exact_model = F.family == GLAM_GAUSSIAN && probs[i].obs_w == nullptr;
+      exact[i] = exact_model;
       tol_in[i] = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
       if (dt == DT_BF16) tol_in[i] = std::max(tol_in[i], 0.1 * kkt);
       best[i] = wbest[i] = INFINITY;
@@ -1239,13 +1249,17 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     for (int i = 0; i < nprob; ++i) {
       if (!in_round[i]) continue;
       Fit& F = *fits[i];
+      if (exact[i]) {   // Sec. 6.5: no outer loop for the exact model (alpha = 1)
+        BCHK(hipMemcpyAsync(F.theta, F.xp, Gs[i].p * 8, hipMemcpyDeviceToDevice, s));
+        continue;
+      }
       BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, s));
       const int r = armijo_enqueue(F, 0);
       if (r) return fit_fail(r, F.err);
     }
     BCHK(hipStreamSynchronize(s));
     for (int i = 0; i < nprob; ++i) {
-      if (!in_round[i]) continue;
+      if (!in_round[i] || exact[i]) continue;
       Fit& F = *fits[i];
       double alpha = 0.0, Delta = 0.0;
       if (!armijo_decide(F, 0, lam[i], 0.1, &alpha, &Delta)) {
