@@ -82,6 +82,15 @@ static double gram_spectral_radius(std::vector<double> A, int p) {
 // Families whose IRLS weight (eq. nine) varies with eta: the inner chain then reads V.
 static bool family_has_weights(int family) { return family == GLAM_POISSON || family == GLAM_BINOMIAL; }
 
+// A low-precision inner loop whose best KKT residual has not halved over this many checks
+// leaves for an FP64 re-anchor.  Where the model is the objective (no line search, R19) a
+// re-anchor costs one FP64 family step and restarts the extrapolation: 10 checks measured
+// 23% faster than 20 on the C2 path (and 50% slower on an ill-conditioned design whose slow
+// but steady passes it cuts short).  Elsewhere each re-anchor also runs the Armijo rule, and
+// 20 checks measured faster (C3: 1.02 s against 1.22 s).  The batched solver uses 10.
+constexpr int kStallChecks = 10;
+constexpr int kStallChecksLineSearch = 20;
+
 static const double kEps[3] = {1.1102230246251565e-16, 5.960464477539063e-08, 3.90625e-03};
 
 struct Fit {
@@ -448,6 +457,29 @@ static void escalate_f64(Fit& F) {
   if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
   if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
   F.graph_m = 0;
+}
+
+// Continue a BF16 fit with the FP32 inner chain (the intermediate rung before FP64): its
+// intermediates, mode-3 factor copies and factor image are allocated and packed here, once.
+static int escalate_f32(Fit& F) {
+  const Geom& G = F.G;
+  void* t1 = F.alloc(G.t1_len * 4);
+  void* s2 = F.alloc(G.s2_len * 4);
+  void* x3f = F.alloc(G.x3f_len * 4);
+  void* x3a = F.alloc(G.x3a_len * 4);
+  void* img = F.alloc(chain_image_bytes(DT_F32, G));
+  if (!t1 || !s2 || !x3f || !x3a || !img) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
+  FCHK(launch_pack(DT_F32, DT_F64, F.prob->X[2], G.p3, G.n3, G.n3, 1, x3f, F.s));
+  FCHK(launch_pack(DT_F32, DT_F64, F.prob->X[2], G.n3, G.p3, 1, G.n3, x3a, F.s));
+  FCHK(launch_zero(s2, G.s2_len * 4, F.s));   // rows beyond n3 stay zero
+  FCHK(launch_pack_chain_image(DT_F32, DT_F64, G, F.prob->X[0], F.prob->X[1], img, F.s,
+                               chain_image_need(DT_F32, SM_FUSED, G)));
+  F.dt = DT_F32;
+  F.T1c = t1; F.S2c = s2; F.X3fc = x3f; F.X3ac = x3a; F.imgc = img;
+  if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
+  if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
+  F.graph_m = 0;
+  return GLAM_OK;
 }
 
 // Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
@@ -856,7 +888,8 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     // precision escalation: a BF16/FP32 inner loop that ends on its rounding floor (stall or
     // noise rule, not tol_in) three outer steps in a row while the FP64 KKT improves by less
     // than 10% cannot refine this problem further (its conditioning times the chain's epsilon
-    // is too large); the fit then continues with the FP64 chain for the rest of the path
+    // is too large); the fit then continues one rung up, BF16 -> FP32 -> FP64, for the rest
+    // of the path
     int lowprec_stalls = 0;
     bool last_limited = false;
     double kkt_prev = INFINITY;
@@ -877,9 +910,12 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (F.dt != DT_F64 && !F.gram) {
         lowprec_stalls = (k > 0 && last_limited && kkt > 0.9 * kkt_prev) ? lowprec_stalls + 1 : 0;
         if (lowprec_stalls >= 3) {
-          escalate_f64(F);
+          if (F.dt == DT_BF16) RCHK(escalate_f32(F));
+          else escalate_f64(F);
+          lowprec_stalls = 0;
           if (res->escalated_at < 0) res->escalated_at = l;
-          if (verbose) fprintf(stderr, "[glam] lambda %d k %d: inner chain continues in FP64\n", l, k);
+          if (verbose)
+            fprintf(stderr, "[glam] lambda %d k %d: inner chain continues in %s\n", l, k, F.dt == DT_F32 ? "FP32" : "FP64");
         }
       }
       kkt_prev = kkt;
@@ -931,8 +967,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         // rounding floor of the low-precision chain output (a lower bound of its error)
         noise = 4.0 * kEps[F.dt] * chk[1] / lam_scale;
         best = std::min(best, kin);
-        if (it - window_start >= 20 * opt->check_every) {
-          // stalled: no 2x progress over the window -> leave for an FP64 re-anchor
+        if (it - window_start >= (exact_model ? kStallChecks : kStallChecksLineSearch) * opt->check_every) {
+          // stalled: no 2x progress over the window -> leave for an FP64 re-anchor (which
+          // also restarts the extrapolation)
           if (!(best < 0.5 * window_best) && F.dt != DT_F64) break;
           window_best = best;
           window_start = it;
@@ -1229,7 +1266,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
       BCHK(hipMemcpyAsync(h_seg, d_seg, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost, s));
       BCHK(hipStreamSynchronize(s));
       bool changed = false;
-      const bool window = it - window_start >= 20 * opt->check_every;
+      const bool window = it - window_start >= kStallChecks * opt->check_every;
       for (int i = 0; i < nprob; ++i) {
         if (!h_active[i]) continue;
         const double kin = h_seg[2 * i] / scale[i];
