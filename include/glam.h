@@ -202,8 +202,11 @@ typedef struct {
  * Errors: GLAM_EINVAL for bad sizes/pointers/options, non-finite Y, Y outside the
  * family's range, negative obs_w, non-positive pen_w, or a lambda sequence that is not
  * strictly decreasing and positive.  Sizes: besides the rho limits, the FP64 outer steps
- * hold both orientations of X_1 and X_2 in LDS, so a fit takes n_1, n_2 <= 256 when
- * p_1, p_2 <= 16, and about n_1 + n_2 <= 256 when max(p_1, p_2) is 17..32 (GLAM_EINVAL beyond). */
+ * hold both orientations of X_1 and X_2 in LDS, so the two slab modes take n_1, n_2 <= 256
+ * when p_1, p_2 <= 16, and about n_1 + n_2 <= 256 when max(p_1, p_2) is 17..32.  When the
+ * caller's order does not fit, the fit reorders the modes itself (the largest remaining mode
+ * last; Y, obs_w, pen_w and theta0 are permuted on the caller's stream into buffers of its own,
+ * and theta is returned in the caller's order); GLAM_EINVAL when no order fits. */
 int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res);
 
 /* ---------------------------------------------------------------------------

@@ -272,6 +272,22 @@ __global__ __launch_bounds__(WG) void k_scad_weights(long long p, const double* 
   }
 }
 
+// Axis permutation of a column-major 3-D FP64 array: out has dims (d[q0], d[q1], d[q2]) and
+// out[i'] = in[i] with i[q_k] = i'_k (a GLAM is unchanged by a joint permutation of its
+// modes, of Y's axes and of Theta's axes).
+__global__ __launch_bounds__(WG) void k_permute3(const double* __restrict__ in, double* __restrict__ out, long long d0,
+                                                 long long d1, long long d2, int q0, int q1, int q2, long long total) {
+  const long long d[3] = {d0, d1, d2};
+  const long long e0 = d[q0], e1 = d[q1];
+  for (long long t = blockIdx.x * (long long)WG + threadIdx.x; t < total; t += (long long)gridDim.x * WG) {
+    long long i[3];
+    i[q0] = t % e0;
+    i[q1] = (t / e0) % e1;
+    i[q2] = t / (e0 * e1);
+    out[t] = in[i[0] + d0 * (i[1] + d1 * i[2])];
+  }
+}
+
 // k-blocked packing: dst elem(k, c) = src[k * sk + c * sc] (converted), zero for k >= K.
 template <typename S, typename T>
 __global__ void k_pack(const S* __restrict__ src, long long K, long long C, long long sk, long long sc,
@@ -437,6 +453,14 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
   if (nb > kPenTrialsMaxBlocks) nb = kPenTrialsMaxBlocks;
   *nblk_out = nb;
   hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, alpha, j0, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute3(const double* in, double* out, const int64_t* dims, const int* q, hipStream_t s) {
+  const long long total = (long long)dims[0] * dims[1] * dims[2];
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute3, dim3(grid1d(total)), dim3(WG), 0, s, in, out, (long long)dims[0], (long long)dims[1],
+                     (long long)dims[2], q[0], q[1], q[2], total);
   return hipGetLastError();
 }
 

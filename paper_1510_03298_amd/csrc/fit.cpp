@@ -740,11 +740,74 @@ static int lift_problem(const glam_problem* in, glam_problem* out, UnitFactor* u
   return GLAM_OK;
 }
 
-extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* opt, glam_result* res) {
+// The slab kernels take modes 1 and 2 within the limits of the rho entry points and of the FP64
+// outer steps' LDS image.
+static bool inner_modes_fit(const int64_t* n, const int64_t* p, int dtype) {
+  if (glam_rho_workspace_size(3, n, p, dtype) == 0) return false;
+  return slab_chain_lds_bytes(DT_F64, make_geom(n, p)) <= 159 * 1024;
+}
+
+// Device copies of a problem with its modes reordered (Y, obs_w: n-arrays; pen_w, theta0:
+// p-arrays), freed when the fit returns.
+struct PermutedProblem {
+  int q[3] = {0, 1, 2};      // position k holds the caller's mode q[k]
+  bool active = false;
+  std::vector<void*> bufs;
+  ~PermutedProblem() { for (void* b : bufs) (void)hipFree(b); }
+  double* alloc(size_t count) {
+    void* b = nullptr;
+    if (hipMalloc(&b, std::max<size_t>(count * 8, 256)) != hipSuccess) return nullptr;
+    bufs.push_back(b);
+    return (double*)b;
+  }
+};
+
+// If the caller's mode order does not fit the slab kernels, pick an order that does (the largest
+// remaining mode last), and permute the problem's arrays on the caller's stream.
+static int permute_problem(glam_problem* prob, glam_options* opt, PermutedProblem* pp, hipStream_t us, std::string* why) {
+  if (inner_modes_fit(prob->n, prob->p, opt->dtype)) return GLAM_OK;
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 2, 0}, {1, 0, 2}, {2, 0, 1}, {2, 1, 0}};
+  int best = -1;
+  for (int c = 1; c < 6; ++c) {
+    int64_t n[3], p[3];
+    for (int k = 0; k < 3; ++k) { n[k] = prob->n[perms[c][k]]; p[k] = prob->p[perms[c][k]]; }
+    if (!inner_modes_fit(n, p, opt->dtype)) continue;
+    if (best < 0 || n[2] > prob->n[perms[best][2]]) best = c;
+  }
+  if (best < 0) {
+    *why = "no order of the modes fits the slab kernels (two modes need p <= 32 and n <= 256, FP64 LDS image)";
+    return GLAM_EINVAL;
+  }
+  pp->active = true;
+  for (int k = 0; k < 3; ++k) pp->q[k] = perms[best][k];
+  glam_problem out = *prob;
+  for (int k = 0; k < 3; ++k) { out.n[k] = prob->n[pp->q[k]]; out.p[k] = prob->p[pp->q[k]]; out.X[k] = prob->X[pp->q[k]]; }
+  const long long n = prob->n[0] * prob->n[1] * prob->n[2], p = prob->p[0] * prob->p[1] * prob->p[2];
+  auto copy = [&](const double* src, long long count, const int64_t* dims, const double** dst) -> int {
+    if (!src) return GLAM_OK;
+    double* b = pp->alloc((size_t)count);
+    if (!b) { *why = "device allocation failed"; return GLAM_ENOMEM; }
+    if (launch_permute3(src, b, dims, pp->q, us) != hipSuccess) { *why = "permutation kernel failed"; return GLAM_EDEVICE; }
+    *dst = b;
+    return GLAM_OK;
+  };
+  int r;
+  if ((r = copy(prob->Y, n, prob->n, &out.Y))) return r;
+  if ((r = copy(prob->obs_w, n, prob->n, &out.obs_w))) return r;
+  if ((r = copy(prob->pen_w, p, prob->p, &out.pen_w))) return r;
+  if ((r = copy(opt->theta0, p, prob->p, &opt->theta0))) return r;
+  *prob = out;
+  return GLAM_OK;
+}
+
+extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* opt_in, glam_result* res) {
   auto t_start = std::chrono::steady_clock::now();
-  if (!prob_in || !opt || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
+  if (!prob_in || !opt_in || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
   glam_problem lifted;
   UnitFactor unit;
+  glam_options opt_local = *opt_in;
+  const glam_options* opt = &opt_local;
+  PermutedProblem perm;   // declared before the Fit: its buffers outlive the fit's stream work
   {
     std::string why;
     const int r = lift_problem(prob_in, &lifted, &unit, &why);
@@ -788,10 +851,12 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         return fit_fail(GLAM_EINVAL, "lambda sequence must be strictly decreasing");
     }
   }
-  size_t ws_probe = glam_rho_workspace_size(3, prob->n, prob->p, opt->dtype);
-  if (ws_probe == 0) return fit_fail(GLAM_EINVAL, glam_last_error());
-  if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024)
-    return fit_fail(GLAM_EINVAL, "modes 1-2 too large for the FP64 slab kernel");
+  {
+    // modes reordered, when needed, so that two of them fit the slab kernels (R20)
+    std::string why;
+    const int r = permute_problem(&lifted, &opt_local, &perm, (hipStream_t)opt_in->stream, &why);
+    if (r) return fit_fail(r, why);
+  }
 
   Fit F;
   F.G = make_geom(prob->n, prob->p);
@@ -1003,7 +1068,13 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     outer_base = outer;
     if (status != GLAM_OK) break;
     }   // MSA steps
-    PCHK(hipMemcpyAsync(res->theta + (size_t)l * G.p, F.theta, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+    if (perm.active) {   // back to the caller's mode order
+      int qi[3];
+      for (int k = 0; k < 3; ++k) qi[perm.q[k]] = k;
+      PCHK(launch_permute3(F.theta, res->theta + (size_t)l * G.p, prob->p, qi, F.s));
+    } else {
+      PCHK(hipMemcpyAsync(res->theta + (size_t)l * G.p, F.theta, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+    }
     res->kkt[l] = kkt;
     res->objective[l] = Fobj;
     res->iters_outer[l] = outer;

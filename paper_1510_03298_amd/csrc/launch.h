@@ -250,6 +250,8 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
                              int j0, double* partials, int* nblk_out, hipStream_t s);
 // data checks, per-block maxima of 4 indicators: non-finite y, negative y (Poisson),
 // negative or non-finite a, non-positive or non-finite pen_w
+// out (dims d[q0], d[q1], d[q2]) = in (dims d) with its axes permuted: out[i'] = in[i], i[q_k] = i'_k
+hipError_t launch_permute3(const double* in, double* out, const int64_t* dims, const int* q, hipStream_t s);
 hipError_t launch_scad_weights(long long p, const double* theta, const double* base, double lambda, double a, double* w,
                                hipStream_t s);
 hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,

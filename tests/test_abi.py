@@ -135,3 +135,27 @@ def test_invalid_arguments_rejected_without_device_work():
         opt.alpha = bad
         rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
         assert rc == glam.GLAM_EINVAL and b"alpha" in glam.glam_last_error()
+
+
+def test_no_mode_order_fits_is_rejected_on_the_host():
+    """When no order of the three modes puts two of them within the slab kernels' limits
+    (p <= 32), the fit is refused before any device work."""
+    from paper_1510_03298_amd import glam
+    prob = glam.GlamProblem()
+    prob.d = 3
+    dummy = ctypes.c_double(0.0)
+    for j in range(3):
+        prob.n[j], prob.p[j] = 50, 40
+        prob.X[j] = ctypes.addressof(dummy)
+    prob.Y = ctypes.addressof(dummy)
+    opt = glam.GlamOptions()
+    opt.nlambda, opt.lambda_min_ratio, opt.dtype = 2, 0.1, glam.F64
+    opt.kkt_tol, opt.nu, opt.max_outer, opt.max_inner, opt.check_every = 1e-6, 1.0, 10, 10, 1
+    res = glam.GlamResult()
+    out = (ctypes.c_double * 2)()
+    io = (ctypes.c_int * 2)()
+    res.theta = ctypes.addressof(dummy)
+    res.lambda_out = res.kkt = res.objective = out
+    res.iters_outer = res.iters_inner = res.status = io
+    rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    assert rc == glam.GLAM_EINVAL and b"order of the modes" in glam.glam_last_error()

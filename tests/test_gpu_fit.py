@@ -476,7 +476,8 @@ def test_kron_weight_inner_loop(fam, dt):
 def test_largest_inner_modes(fam, dt, n, p):
     """The largest inner modes a fit takes: its FP64 outer steps hold both orientations of X_1
     and X_2 in LDS, so n_1, n_2 <= 256 with p_1, p_2 <= 16, and n_1 + n_2 <= 256 with p up to
-    32; beyond, the fit is refused."""
+    32.  Beyond, the fit reorders the modes when another order fits (refusal when none does
+    is checked on the host, in test_abi)."""
     torch, glam = need_gpu()
     d = inputs.random_problem(n, p, family=fam, seed=39, basis="gauss", scale=0.2)
     print(f"largest inner modes {fam} dt={dt}", flush=True)
@@ -489,8 +490,11 @@ def test_largest_inner_modes(fam, dt, n, p):
     assert O.kkt_residual(th, g, res.lambdas[2], lm) <= 1e-6
     big = inputs.random_problem((256, 256, 3), (32, 32, 2), family=fam, seed=39, basis="gauss", scale=0.2)
     Xb, Yb, _ = _dev(glam, big)
-    with pytest.raises(glam.GlamError):
-        glam.fit_path(Xb, Yb, big.n, big.p, fam, nlambda=2, dtype=dt)
+    rb = glam.fit_path(Xb, Yb, big.n, big.p, fam, nlambda=2, lambda_min_ratio=0.3, dtype=dt, kkt_tol=1e-6)
+    assert rb.code == 0
+    lmb = O.lambda_max(fam, big.X, big.Y)
+    thb = _theta(glam, rb, 1, big.p)
+    assert O.kkt_residual(thb, O.smooth_gradient(fam, big.X, thb, big.Y), rb.lambdas[1], lmb) <= 1e-6
 
 
 def test_degenerate_fits():
@@ -523,3 +527,33 @@ def test_degenerate_fits():
     lm1 = O.lambda_max("gaussian", d1.X, d1.Y)
     th = _theta(glam, r, 2, d1.p)
     assert O.kkt_residual(th, O.smooth_gradient("gaussian", d1.X, th, d1.Y), r.lambdas[2], lm1) <= 1e-6
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+def test_mode_order_is_chosen_by_the_library(fam):
+    """Section 6.5's design in the paper's own mode order (60r, 20r, 10r), r = 2: p_1 = 60 does not
+    fit the slab kernels, so the fit reorders the modes itself.  Same estimates, bit for bit, as
+    the same problem given in an order that fits, and the oracle's KKT on the caller's order."""
+    torch, glam = need_gpu()
+    d = inputs.config_sim(r=2, family=fam, seed=8)            # listed as (20r, 10r, 60r)
+    Xs = [d.X[2], d.X[0], d.X[1]]                             # the paper's order
+    Y = np.asfortranarray(d.Y.transpose(2, 0, 1))
+    n = tuple(X.shape[0] for X in Xs)
+    p = tuple(X.shape[1] for X in Xs)
+    print(f"mode order {fam} n={n} p={p}", flush=True)
+    Xd = [glam.to_device_colmajor(X, 0) for X in Xs]
+    Yd = glam.to_device_colmajor(Y, 0)
+    kw = dict(nlambda=4, lambda_min_ratio=0.05, dtype=0, kkt_tol=1e-7)
+    r1 = glam.fit_path(Xd, Yd, n, p, fam, **kw)
+    Xd2 = [glam.to_device_colmajor(X, 0) for X in d.X]
+    Yd2 = glam.to_device_colmajor(d.Y, 0)
+    r2 = glam.fit_path(Xd2, Yd2, d.n, d.p, fam, **kw)
+    assert r1.code == r2.code == 0
+    assert np.array_equal(r1.iters_inner, r2.iters_inner)
+    lm = O.lambda_max(fam, Xs, Y)
+    for l in range(4):
+        a = glam.from_colmajor(r1.theta[l], p)
+        b = glam.from_colmajor(r2.theta[l], d.p)
+        assert np.array_equal(a, np.asfortranarray(b.transpose(2, 0, 1)))
+        g = O.smooth_gradient(fam, Xs, a, Y)
+        assert O.kkt_residual(a, g, r1.lambdas[l], lm) <= 1e-7
