@@ -15,6 +15,7 @@
 //          accumulator puts row 4 i + g in register i of lane group g)
 //   FP32 : v_mfma_f32_16x16x4f32, 4 instructions per block, kidx = 4 g + t
 //   BF16 : v_mfma_f32_16x16x16bf16_1k, 1 instruction per block, kidx = 4 g + t
+//          (the GEMM and slab kernels pair two 16-blocks into one v_mfma_f32_16x16x32_bf16)
 // (lane layouts measured on gfx950 with a one-wave check).
 #pragma once
 #include <hip/hip_runtime.h>
