@@ -9,10 +9,14 @@
 //   step 4 : inner PG loop (Sec. 3.2) in the chosen dtype on the increment:
 //            grad h(x) = g^k + G(V .* H(x - theta^k)) / n  (exact because h is
 //            quadratic and grad h(theta^k) = g^k), with FISTA extrapolation;
-//   step 5 : Armijo rule on FP64 reductions (F differences along t d).
+//   step 5 : Armijo rule on FP64 reductions (F differences along t d); for the exact
+//            Gaussian model (no prior weights) the inner solution is taken as is.
 // The low-precision chain only ever sees the increment x - theta^k, and every
 // outer iteration re-anchors at an FP64 gradient: this is the residual
 // correction that lets FP32/BF16 rho products reach an FP64-certified KKT.
+// Around it: the inner forms of Sec. 6.2 (Gram factors, tensor-product weights),
+// the elastic net and SCAD (MSA steps) penalties, precision escalation
+// (BF16 -> FP32 -> FP64) and the choice of mode order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
