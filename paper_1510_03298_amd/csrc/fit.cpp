@@ -35,7 +35,7 @@
 namespace glam {
 
 // Gram matrix X^T X (X host, n x p column-major), p x p.
-static std::vector<double> gram_matrix(const std::vector<double>& X, int n, int p) {
+static std::vector<double> gram_matrix(const double* X, int n, int p) {
   std::vector<double> A((size_t)p * p, 0.0);
   for (int a = 0; a < p; ++a)
     for (int b = a; b < p; ++b) {
@@ -97,14 +97,72 @@ constexpr int kStallChecksLineSearch = 20;
 
 static const double kEps[3] = {1.1102230246251565e-16, 5.960464477539063e-08, 3.90625e-03};
 
+// Device memory and pinned host memory carved from a few large allocations.  A fit holds
+// some thirty buffers; with one allocation call each, the set-up of a batch of small fits
+// was dominated by the calls.  Shared by the fits of a batch; freed when the last owner
+// goes (after the fits have synchronised their streams).
+struct Arena {
+  static constexpr size_t kDevChunk = (size_t)32 << 20, kHostChunk = (size_t)256 << 10;
+  std::vector<void*> dev, host;
+  char* dcur = nullptr;
+  size_t dleft = 0;
+  char *hcur = nullptr, *hdcur = nullptr;   // host chunk and its device-side address
+  size_t hleft = 0;
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() {
+    for (void* p : dev) (void)hipFree(p);
+    for (void* p : host) (void)hipHostFree(p);
+  }
+  static size_t round_up(size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; }
+  // 256-byte aligned device buffer, or NULL
+  void* dev_alloc(size_t bytes) {
+    bytes = round_up(bytes);
+    if (bytes > dleft) {
+      void* p = nullptr;
+      const bool own = bytes >= kDevChunk / 2;   // a large buffer takes an allocation of its own
+      if (hipMalloc(&p, own ? bytes : kDevChunk) != hipSuccess) return nullptr;
+      dev.push_back(p);
+      if (own) return p;
+      dcur = (char*)p;
+      dleft = kDevChunk;
+    }
+    void* r = dcur;
+    dcur += bytes;
+    dleft -= bytes;
+    return r;
+  }
+  // 256-byte aligned pinned host buffer (mapped, coherent) and its device address, or NULL
+  void* host_alloc(size_t bytes, void** dev_addr) {
+    bytes = round_up(bytes);
+    if (bytes > hleft) {
+      const size_t sz = std::max(bytes, kHostChunk);
+      void *p = nullptr, *d = nullptr;
+      if (hipHostMalloc(&p, sz, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return nullptr;
+      host.push_back(p);
+      if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) return nullptr;
+      hcur = (char*)p;
+      hdcur = (char*)d;
+      hleft = sz;
+    }
+    void* r = hcur;
+    if (dev_addr) *dev_addr = hdcur;
+    hcur += bytes;
+    hdcur += bytes;
+    hleft -= bytes;
+    return r;
+  }
+};
+
 struct Fit {
   Geom G;
   int dt;
   hipStream_t s;
   int family;
   const glam_problem* prob;
-  // device buffers (owned; freed by the destructor)
-  std::vector<void*> bufs;
+  // device and pinned host buffers (from the arena, which may be shared with other fits)
+  std::shared_ptr<Arena> arena;
   void* imgc;              // LDS image of X1, X2 in the chain dtype
   void* imgd;              // LDS image of X1, X2 in FP64
   void *X3fc, *X3ac;       // chain-dtype packed mode-3 factor (slab_fwd / slab_adj operands)
@@ -135,7 +193,8 @@ struct Fit {
   int* iter;
   double* part;            // partial sums
   double* red;             // reduced values (device)
-  double* hred = nullptr;  // reduced values (pinned host)
+  double* hred = nullptr;  // reduced values (pinned host); [32..35] input-check flags
+  double* hx[3] = {nullptr, nullptr, nullptr};   // pinned host copies of the factors (set-up)
   double* hpub = nullptr;  // published check values (fine-grained pinned host, mapped)
   double* hpub_dev = nullptr;
   unsigned* hseq = nullptr;       // published sequence number (host view) ...
@@ -159,10 +218,12 @@ struct Fit {
   int samples = 0;
 
   void* alloc(size_t bytes) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
-    bufs.push_back(p);
-    return p;
+    if (!arena) arena = std::make_shared<Arena>();
+    return arena->dev_alloc(bytes);
+  }
+  double* host_alloc(size_t count, double** dev_addr = nullptr) {
+    if (!arena) arena = std::make_shared<Arena>();
+    return (double*)arena->host_alloc(count * sizeof(double), (void**)dev_addr);
   }
   Fit() = default;
   Fit(const Fit&) = delete;
@@ -171,14 +232,11 @@ struct Fit {
     if (s) (void)hipStreamSynchronize(s);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : bufs) (void)hipFree(p);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (sync_ev) (void)hipEventDestroy(sync_ev);
-    if (hparams) (void)hipHostFree(hparams);
-    if (hred) (void)hipHostFree(hred);
-    if (hpub) (void)hipHostFree(hpub);
     if (own_stream && s) (void)hipStreamDestroy(s);
+    arena.reset();   // the buffers go with the last owner of the arena
   }
 };
 
@@ -551,10 +609,11 @@ static int armijo(Fit& F, double lambda, double v, double* alpha_out, double* de
   return armijo_finish(F, lambda, v, false, alpha_out, delta_out);
 }
 
-// Allocate the per-problem device state and run the one-time setup kernels: input
-// checks, tiled Y and a, packed factors (FP64 and chain dtype), LDS images, and the
-// spectral radii of Proposition 1.  F.s, F.G and F.dt must be set.
-static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
+// Allocate the per-problem device state and enqueue the one-time setup kernels: input
+// checks, tiled Y and a, packed factors (FP64 and chain dtype), LDS images, and host
+// copies of the factors.  No host synchronisation: fit_setup_finish completes the set-up
+// once the stream has run.  F.s, F.G and F.dt must be set.
+static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool events) {
   F.family = prob->family;
   F.prob = prob;
   F.pen = prob->pen_w;
@@ -609,18 +668,16 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   if (events)
     for (auto& e : F.ev)
       if (hipEventCreate(&e) != hipSuccess) { F.err = "hipEventCreate failed"; return GLAM_EDEVICE; }
-  if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&F.hparams, 4 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&F.hpub, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+  F.hred = F.host_alloc(64);
+  F.hparams = F.host_alloc(4);
+  F.hpub = F.host_alloc(16, &F.hpub_dev);
+  for (int j = 0; j < 3; ++j) F.hx[j] = F.host_alloc((size_t)prob->n[j] * prob->p[j]);
+  if (!F.hred || !F.hparams || !F.hpub || !F.hx[0] || !F.hx[1] || !F.hx[2]) {
     F.err = "pinned host allocation failed";
     return GLAM_ENOMEM;
   }
   F.hseq = (unsigned*)(F.hpub + 8);
   *F.hseq = 0u;
-  if (hipHostGetDevicePointer((void**)&F.hpub_dev, F.hpub, 0) != hipSuccess) {
-    F.err = "hipHostGetDevicePointer failed";
-    return GLAM_EDEVICE;
-  }
   F.hseq_dev = (unsigned*)(F.hpub_dev + 8);
   F.seq_dev = (unsigned*)A(256);
   if (!F.seq_dev || hipMemsetAsync(F.seq_dev, 0, 256, F.s) != hipSuccess) {
@@ -629,23 +686,13 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
   }
   F.seq_expect = 0;
 
-  // ---- input checks (device) ----
+  // ---- input checks (device; flags read by fit_setup_finish) ----
   {
     int nb = 0;
     FCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family, F.part, &nb, F.s));
     const int ops[4] = {1, 1, 1, 1};
-    FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red, F.s));
-    FCHK(hipMemcpyAsync(F.hred, F.red, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
-    FCHK(hipStreamSynchronize(F.s));
-    if (F.hred[0] != 0.0) { F.err = "Y has non-finite entries"; return GLAM_EINVAL; }
-    if (F.hred[1] != 0.0) {
-      F.err = prob->family == GLAM_POISSON    ? "Poisson Y must be >= 0"
-              : prob->family == GLAM_BINOMIAL ? "Binomial Y must be a proportion in [0, 1]"
-                                              : "Gamma Y must be > 0";
-      return GLAM_EINVAL;
-    }
-    if (F.hred[2] != 0.0) { F.err = "obs_w must be finite and >= 0"; return GLAM_EINVAL; }
-    if (F.hred[3] != 0.0) { F.err = "pen_w must be finite and > 0"; return GLAM_EINVAL; }
+    FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red + 32, F.s));
+    FCHK(hipMemcpyAsync(F.hred + 32, F.red + 32, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
   }
   // ---- setup: tiled data, chain copies of the factors, spectral radii ----
   FCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
@@ -664,13 +711,31 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     FCHK(launch_pack(F.dt, DT_F64, prob->X[2], G.n3, G.p3, 1, G.n3, F.X3ac, F.s));
     FCHK(launch_zero(F.S2c, G.s2_len * es, F.s));
   }
+  for (int j = 0; j < 3; ++j)
+    FCHK(hipMemcpyAsync(F.hx[j], prob->X[j], (size_t)prob->n[j] * prob->p[j] * 8, hipMemcpyDeviceToHost, F.s));
+  return GLAM_OK;
+}
+
+// The rest of the set-up, after the stream has completed what fit_setup_enqueue queued:
+// the input-check verdicts, the spectral radii of Proposition 1 from the host copies of
+// the factors, and (Gram and Kron forms) the Gram factors.
+static int fit_setup_finish(Fit& F) {
+  const glam_problem* prob = F.prob;
+  const Geom& G = F.G;
+  const size_t es = dt_size(F.dt);
+  if (F.hred[32] != 0.0) { F.err = "Y has non-finite entries"; return GLAM_EINVAL; }
+  if (F.hred[33] != 0.0) {
+    F.err = prob->family == GLAM_POISSON    ? "Poisson Y must be >= 0"
+            : prob->family == GLAM_BINOMIAL ? "Binomial Y must be a proportion in [0, 1]"
+                                            : "Gamma Y must be > 0";
+    return GLAM_EINVAL;
+  }
+  if (F.hred[34] != 0.0) { F.err = "obs_w must be finite and >= 0"; return GLAM_EINVAL; }
+  if (F.hred[35] != 0.0) { F.err = "pen_w must be finite and > 0"; return GLAM_EINVAL; }
   F.sprod = 1.0;
   std::vector<double> gm[3];
   for (int j = 0; j < 3; ++j) {
-    std::vector<double> hx((size_t)prob->n[j] * prob->p[j]);
-    FCHK(hipMemcpyAsync(hx.data(), prob->X[j], hx.size() * 8, hipMemcpyDeviceToHost, F.s));
-    FCHK(hipStreamSynchronize(F.s));
-    gm[j] = gram_matrix(hx, (int)prob->n[j], (int)prob->p[j]);
+    gm[j] = gram_matrix(F.hx[j], (int)prob->n[j], (int)prob->p[j]);
     F.sprod *= gram_spectral_radius(gm[j], (int)prob->p[j]);
   }
   if (F.gram) {
@@ -705,6 +770,13 @@ static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
     }
   }
   return GLAM_OK;
+}
+
+static int fit_setup(Fit& F, const glam_problem* prob, bool bt, bool events) {
+  const int r = fit_setup_enqueue(F, prob, bt, events);
+  if (r) return r;
+  FCHK(hipStreamSynchronize(F.s));
+  return fit_setup_finish(F);
 }
 
 }  // namespace glam
@@ -1167,39 +1239,47 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   if (hipEventRecord(ev, us) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
 
+  // one arena for the whole batch; every set-up is queued before one synchronisation
+  std::shared_ptr<Arena> arena = std::make_shared<Arena>();
   std::vector<std::unique_ptr<Fit>> fits(nprob);
   std::vector<Geom> Gs(nprob);
   for (int i = 0; i < nprob; ++i) {
     fits[i].reset(new Fit());
     Fit& F = *fits[i];
+    F.arena = arena;
     F.G = Gs[i] = make_geom(probs[i].n, probs[i].p);
     F.dt = dt;
     F.s = s;
     F.own_stream = false;
     F.batched = true;
     F.enet = opt->alpha;
-    const int r = fit_setup(F, &probs[i], false, false);
+    const int r = fit_setup_enqueue(F, &probs[i], false, false);
     if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
   }
+  if (hipStreamSynchronize(s) != hipSuccess) return fit_fail(GLAM_EDEVICE, "set-up failed");
+  for (int i = 0; i < nprob; ++i) {
+    const int r = fit_setup_finish(*fits[i]);
+    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + fits[i]->err);
+  }
   // batch bookkeeping
-  std::vector<int> off_fwd(nprob + 1, 0), off_slab(nprob + 1, 0), off_adj(nprob + 1, 0);
+  std::vector<int> nfwd(nprob), nadj(nprob), off_adj(nprob + 1, 0);
   std::vector<BatchDesc> desc(nprob);
   for (int i = 0; i < nprob; ++i) {
     const Geom& G = Gs[i];
     const int fgx = (G.P12 + 31) / 32, fgy = (G.n3 + 31) / 32;
     const int agx = (G.P12 + 15) / 16, agy = (G.p3 + 15) / 16;
-    off_fwd[i + 1] = off_fwd[i] + fgx * fgy;
-    off_slab[i + 1] = off_slab[i] + G.n3;
-    off_adj[i + 1] = off_adj[i] + agx * agy;
+    nfwd[i] = fgx * fgy;
+    nadj[i] = agx * agy;
+    off_adj[i + 1] = off_adj[i] + nadj[i];
     desc[i].fwd_gx = fgx;
     desc[i].adj_gx = agx;
   }
   void* dmem = nullptr;
   const size_t nparts = (size_t)off_adj[nprob] * ADJ_NSUM;
+  const size_t nwork = (size_t)4 * (nprob + 1);   // act, aoff_fwd, aoff_run, aoff_adj
   auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t piece[8] = {sizeof(BatchDesc) * nprob, sizeof(int) * (nprob + 1), sizeof(int) * (nprob + 1),
-                           sizeof(int) * (nprob + 1), sizeof(int) * nprob, sizeof(double) * nparts,
-                           sizeof(double) * 2 * nprob, 64};
+  const size_t piece[6] = {sizeof(BatchDesc) * nprob, sizeof(int) * (nprob + 1), sizeof(int) * nwork,
+                           sizeof(double) * nparts, sizeof(double) * 2 * nprob, 64};
   size_t bytes = 0;
   for (size_t b : piece) bytes += r256(b);
   if (hipMalloc(&dmem, bytes) != hipSuccess) return fit_fail(GLAM_ENOMEM, "device allocation failed");
@@ -1207,23 +1287,15 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   char* q = (char*)dmem;
   auto take = [&](size_t b) { char* r = q; q += r256(b); return (void*)r; };   // same order as piece[]
   BatchDesc* d_desc = (BatchDesc*)take(sizeof(BatchDesc) * nprob);
-  int* d_off_fwd = (int*)take(sizeof(int) * (nprob + 1));
-  int* d_off_slab = (int*)take(sizeof(int) * (nprob + 1));
   int* d_off_adj = (int*)take(sizeof(int) * (nprob + 1));
-  int* d_active = (int*)take(sizeof(int) * nprob);
+  int* d_work = (int*)take(sizeof(int) * nwork);
   double* d_part = (double*)take(sizeof(double) * nparts);
   double* d_seg = (double*)take(sizeof(double) * 2 * nprob);
   int* d_misc = (int*)take(64);   // [0] step counter of the batched inner loop
-  struct HGuard {
-    double* seg = nullptr;
-    int* active = nullptr;
-    ~HGuard() { if (seg) (void)hipHostFree(seg); if (active) (void)hipHostFree(active); }
-  } hg;
-  if (hipHostMalloc((void**)&hg.seg, sizeof(double) * 2 * nprob) != hipSuccess ||
-      hipHostMalloc((void**)&hg.active, sizeof(int) * nprob) != hipSuccess)
-    return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
-  double* h_seg = hg.seg;
-  int* h_active = hg.active;
+  double* h_seg = (double*)arena->host_alloc(sizeof(double) * 2 * nprob, nullptr);
+  int* h_work = (int*)arena->host_alloc(sizeof(int) * nwork, nullptr);
+  if (!h_seg || !h_work) return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
+  std::vector<int> h_active(nprob, 0);
   for (int i = 0; i < nprob; ++i) {
     Fit& F = *fits[i];
     const Geom& G = Gs[i];
@@ -1244,14 +1316,15 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     if (e_ != hipSuccess) return fit_fail(GLAM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
   BCHK(hipMemcpyAsync(d_desc, desc.data(), sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, s));
-  BCHK(hipMemcpyAsync(d_off_fwd, off_fwd.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
-  BCHK(hipMemcpyAsync(d_off_slab, off_slab.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
   BCHK(hipMemcpyAsync(d_off_adj, off_adj.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
   BCHK(launch_zero(d_misc, 64, s));
   BCHK(hipStreamSynchronize(s));   // host vectors above must outlive the copies
   BatchParams B{};
-  B.desc = d_desc; B.nprob = nprob; B.off_fwd = d_off_fwd; B.off_slab = d_off_slab; B.off_adj = d_off_adj;
-  B.active = d_active; B.step = d_misc;
+  B.desc = d_desc; B.nprob = nprob; B.off_adj = d_off_adj; B.step = d_misc;
+  B.act = d_work;
+  B.aoff_fwd = d_work + (nprob + 1);
+  B.aoff_run = d_work + 2 * (nprob + 1);
+  B.aoff_adj = d_work + 3 * (nprob + 1);
   B.wave = batched_wave(dt, Gs.data(), nprob);
   if (B.wave) {
     for (int i = 0; i < nprob; ++i) desc[i].ap.s2_kb4 = 1;
@@ -1259,16 +1332,50 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     BCHK(hipStreamSynchronize(s));
   }
   const size_t lds = batched_lds_bytes(dt, Gs.data(), nprob);
-  const int tot[3] = {off_fwd[nprob], off_slab[nprob], off_adj[nprob]};
+  int tot[3] = {0, 0, 0};
+  // Compact work lists of the active problems, uploaded from pinned memory (the host rewrites
+  // it only after a stream synchronisation, so the previous upload has completed).  Runs of
+  // several slabs share one load of the factor operands; they are as long as still leaves
+  // about 2048 runs (8 at most), so that a nearly finished batch keeps the CUs busy.
+  auto upload_work = [&]() -> hipError_t {
+    int* act = h_work;
+    int* afwd = h_work + (nprob + 1);
+    int* arun = h_work + 2 * (nprob + 1);
+    int* aadj = h_work + 3 * (nprob + 1);
+    long long slabs = 0;
+    for (int i = 0; i < nprob; ++i)
+      if (h_active[i]) slabs += Gs[i].n3;
+    const int run = B.wave ? (int)std::max(1LL, std::min(8LL, slabs / 2048)) : 1;
+    int k = 0;
+    afwd[0] = arun[0] = aadj[0] = 0;
+    for (int i = 0; i < nprob; ++i) {
+      if (!h_active[i]) continue;
+      act[k] = i;
+      afwd[k + 1] = afwd[k] + nfwd[i];
+      arun[k + 1] = arun[k] + (Gs[i].n3 + run - 1) / run;
+      aadj[k + 1] = aadj[k] + nadj[i];
+      ++k;
+    }
+    B.nact = k;
+    B.run = run;
+    tot[0] = afwd[k];
+    tot[1] = arun[k];
+    tot[2] = aadj[k];
+    return hipMemcpyAsync(d_work, h_work, sizeof(int) * nwork, hipMemcpyHostToDevice, s);
+  };
 
-  // lambda_max_i and lambda_i
+  // lambda_max_i and lambda_i (every problem's step 2 at theta = 0 before one synchronisation)
   std::vector<double> lam(nprob), lmax(nprob), scale(nprob);
   for (int i = 0; i < nprob; ++i) {
     Fit& F = *fits[i];
     BCHK(launch_fill(F.theta, Gs[i].p, 0.0, s));
-    StepStats st0;
-    const int r = family_step(F, F.theta, 0.0, &st0);
+    const int r = family_enqueue(F, F.theta, 0.0);
     if (r) return fit_fail(r, F.err);
+  }
+  BCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < nprob; ++i) {
+    StepStats st0;
+    family_collect(*fits[i], &st0);
     lmax[i] = st0.lmax_raw;
     scale[i] = lmax[i] > 0.0 ? lmax[i] : 1.0;
     lam[i] = opt->lambda ? opt->lambda[i] : opt->lambda_ratio * lmax[i];
@@ -1329,7 +1436,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     std::vector<char> in_round(nprob);
     for (int i = 0; i < nprob; ++i) in_round[i] = (char)h_active[i];
     BCHK(launch_zero(d_misc, 4, s));   // step counter l = 0
-    BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
+    BCHK(upload_work());
     int it = 0, window_start = 0;
     while (nact > 0 && it < opt->max_inner) {
       const int m = std::min(check_every, opt->max_inner - it);
@@ -1355,7 +1462,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
         if (stop) { h_active[i] = 0; --nact; changed = true; }
       }
       if (window) window_start = it;
-      if (changed && nact > 0) BCHK(hipMemcpyAsync(d_active, h_active, sizeof(int) * nprob, hipMemcpyHostToDevice, s));
+      if (changed && nact > 0) BCHK(upload_work());
     }
     // step 5 of Algorithm 1 per problem: Armijo along theta~ - theta^k (theta~ = x^l of the
     // last check); the first pass of every problem is enqueued before one synchronisation

@@ -130,17 +130,22 @@ struct BatchDesc {
 struct BatchParams {
   const BatchDesc* desc;
   int nprob;
-  const int* off_fwd;   // prefix sums of slab_fwd tiles per problem (nprob + 1)
-  const int* off_slab;  // prefix sums of n3
-  const int* off_adj;   // prefix sums of slab_adj tiles (also the partials index)
-  const int* active;    // problem mask
+  const int* off_adj;   // prefix sums of slab_adj tiles over all problems (the partials index)
+  // compact work lists over the nact active problems
+  int nact;
+  const int* act;       // active problem indices (nact)
+  const int* aoff_fwd;  // prefix sums of slab_fwd tiles (nact + 1)
+  const int* aoff_run;  // prefix sums of slab runs, ceil(n3 / run) per problem (nact + 1)
+  const int* aoff_adj;  // prefix sums of slab_adj tiles (nact + 1)
+  int run;              // slabs per run
   int* step;            // inner step counter (read by the prox epilogue)
   int wave;             // slabs with the register kernel (S2 in 4-deep k-blocks; batched_wave)
 };
 // true when every problem of the batch fits the one-wave-per-slab kernel of this dtype
 bool batched_wave(int dt, const Geom* Gs, int nprob);
 size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
-// tot: {forward tiles, slabs, adjoint tiles} over all problems (the offsets' last entries)
+// tot: {forward tiles, slab runs, adjoint tiles} over the active problems (the compact
+// offsets' last entries)
 hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s);
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s);
 

@@ -657,9 +657,11 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
 // consecutive slabs (4 or 1) and NPART waves per slab (2 or 4), each wave taking 8 / NPART
 // of the (at most 8) mode-2 column blocks; the waves' S2 partials are summed in LDS.
 // Partial NLL sums per workgroup in partials[slab group][2].
-// the slabs SPW grp .. SPW grp + SPW - 1 (a whole workgroup of 64 SPW NPART threads)
+// The slab groups grp .. grp + nrep - 1, group g holding the slabs SPW g .. SPW g + SPW - 1
+// (a whole workgroup of 64 SPW NPART threads); the factor fragments are loaded once for
+// all of them.
 template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
-__device__ inline void wave_chain_group(const SlabParams& P, int grp) {
+__device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep = 1) {
   typedef WT<T> W;
   typedef typename W::v8 V8;
   typedef typename W::st ST;
@@ -672,14 +674,10 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp) {
   const Geom& G = P.G;
   const int lane = lane_id(), w = wave_id(), r = lane & 15, g = lane >> 4, tid = threadIdx.x;
   const int sw = w % SPW, part = w / SPW;   // slab within the workgroup, part of the column blocks
-  const int i3b = SPW * grp;
-  if (i3b >= G.n3) return;   // whole workgroup
-  const int nsl = min(SPW, G.n3 - i3b);
-  const int i3 = i3b + sw;
+  if (SPW * grp0 >= G.n3) return;   // whole workgroup
   const int P12 = G.P12;
   const int N1T = G.N1T, NJB = G.NJB;
   const int jb0 = JPW * part;                     // this wave: column blocks jb0 .. jb0 + JPW - 1
-  const bool active = sw < nsl && jb0 < NJB;
   __shared__ __align__(16) ST t1s[SPW * 1024];                        // T1 of the slabs (P12 <= 1024)
   __shared__ __align__(16) float s2p[NPART - 1][SPW][1024];           // S2 partials of parts 1..
   __shared__ __align__(16) ST s2x[SPW == 4 ? 4096 : 4];               // S2 of 4 slabs, [m][slab]
@@ -700,150 +698,160 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp) {
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
       fx2a[mt][qq] = jb0 + 2 * qq < NJB ? W::load(img, 24 + 4 * mt + QPW * part + qq, lane) : zf;
-  {
-    // the slabs are contiguous in slab-major T1: coalesced 4-element loads when aligned
-    const ST* src = (const ST*)P.T1 + (long long)i3b * P12;
-    const int nel = nsl * P12;
-    const int n4 = (((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) ? (nel >> 2) : 0;
-    for (int k = tid; k < n4; k += NT) ((st4*)t1s)[k] = ((const st4*)src)[k];
-    for (int k = 4 * n4 + tid; k < nel; k += NT) t1s[k] = src[k];
-  }
-  __syncthreads();
-  const f4v z4 = {0.f, 0.f, 0.f, 0.f};
-  f4v s2[2][2] = {{z4, z4}, {z4, z4}};
-  double s_nll = 0.0;
-  if (active) {
-    // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
-    V8 ft1[2];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      const int i1 = 16 * mt + r;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i2 = kw_index(g, u);
-        const ST h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (ST)0;
-        W::set(ft1[mt], u, h);
-      }
+  // LDS reuse across groups: t1s is read before the S2 barrier of a group and rewritten after
+  // it; s2p and s2x are read before the next group's staging barrier
+  for (int rep = 0; rep < nrep; ++rep) {
+    const int grp = grp0 + rep;
+    const int i3b = SPW * grp;
+    if (i3b >= G.n3) break;   // whole workgroup
+    const int nsl = min(SPW, G.n3 - i3b);
+    const int i3 = i3b + sw;
+    const bool active = sw < nsl && jb0 < NJB;
+    {
+      // the slabs are contiguous in slab-major T1: coalesced 4-element loads when aligned
+      const ST* src = (const ST*)P.T1 + (long long)i3b * P12;
+      const int nel = nsl * P12;
+      const int n4 = (((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) ? (nel >> 2) : 0;
+      for (int k = tid; k < n4; k += NT) ((st4*)t1s)[k] = ((const st4*)src)[k];
+      for (int k = 4 * n4 + tid; k < nel; k += NT) t1s[k] = src[k];
     }
-    const float* V = (const float*)P.v_int;
-#pragma unroll
-    for (int jq = 0; jq < QPW; ++jq) {
-      if (jb0 + 2 * jq >= NJB) break;
-      f4v s1[2][2] = {{z4, z4}, {z4, z4}};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int jl = 2 * jq + h, jb = jb0 + jl;
-        if (jb >= NJB) break;
-        // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
-        const V8 ft2 = W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
-#pragma unroll
-        for (int uq = 0; uq < 4; ++uq) {
-          const int u0 = 2 * uq;
-          if (u0 >= N1T) break;
-          // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
-          f4v e0 = W::mma(fx1a[u0], ft2, z4);
-          f4v e1 = u0 + 1 < N1T ? W::mma(fx1a[u0 + 1], ft2, z4) : z4;
-          if (HAS_V) {
-            const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
-            const f4v v0 = *(const f4v*)(V + t0);
-            e0 *= v0;
-            if (u0 + 1 < N1T) {
-              const f4v v1 = *(const f4v*)(V + t0 + 256);
-              e1 *= v1;
-            }
-          }
-          if (NLL) {
-            // Poisson NLL terms exp(eta) - y eta (FP64), R = exp(eta) - y
-            const int i2 = 16 * jb + r;
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-              f4v& e = hh ? e1 : e0;
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int i1 = 16 * (u0 + hh) + 4 * g + i;
-                float rv = 0.f;
-                if (i1 < G.n1 && i2 < G.n2) {
-                  const double eta = (double)e[i];
-                  const double y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
-                  // (exp in FP32: eta carries the chain's own error, at or above FP32 rounding)
-                  const double ex = (double)expf(e[i]);
-                  s_nll += ex - y * eta;
-                  rv = (float)(ex - y);
-                }
-                e[i] = rv;
+    __syncthreads();
+    const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+    f4v s2[2][2] = {{z4, z4}, {z4, z4}};
+    double s_nll = 0.0;
+    if (active) {
+      // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
+      V8 ft1[2];
+  #pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int i1 = 16 * mt + r;
+  #pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i2 = kw_index(g, u);
+          const ST h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (ST)0;
+          W::set(ft1[mt], u, h);
+        }
+      }
+      const float* V = (const float*)P.v_int;
+  #pragma unroll
+      for (int jq = 0; jq < QPW; ++jq) {
+        if (jb0 + 2 * jq >= NJB) break;
+        f4v s1[2][2] = {{z4, z4}, {z4, z4}};
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int jl = 2 * jq + h, jb = jb0 + jl;
+          if (jb >= NJB) break;
+          // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
+          const V8 ft2 = W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
+  #pragma unroll
+          for (int uq = 0; uq < 4; ++uq) {
+            const int u0 = 2 * uq;
+            if (u0 >= N1T) break;
+            // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
+            f4v e0 = W::mma(fx1a[u0], ft2, z4);
+            f4v e1 = u0 + 1 < N1T ? W::mma(fx1a[u0 + 1], ft2, z4) : z4;
+            if (HAS_V) {
+              const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
+              const f4v v0 = *(const f4v*)(V + t0);
+              e0 *= v0;
+              if (u0 + 1 < N1T) {
+                const f4v v1 = *(const f4v*)(V + t0 + 256);
+                e1 *= v1;
               }
             }
+            if (NLL) {
+              // Poisson NLL terms exp(eta) - y eta (FP64), R = exp(eta) - y
+              const int i2 = 16 * jb + r;
+  #pragma unroll
+              for (int hh = 0; hh < 2; ++hh) {
+                f4v& e = hh ? e1 : e0;
+  #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const int i1 = 16 * (u0 + hh) + 4 * g + i;
+                  float rv = 0.f;
+                  if (i1 < G.n1 && i2 < G.n2) {
+                    const double eta = (double)e[i];
+                    const double y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
+                    // (exp in FP32: eta carries the chain's own error, at or above FP32 rounding)
+                    const double ex = (double)expf(e[i]);
+                    s_nll += ex - y * eta;
+                    rv = (float)(ex - y);
+                  }
+                  e[i] = rv;
+                }
+              }
+            }
+            if (ADJ) {
+              // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
+              const V8 fr = W::pack(e0, e1);
+              s1[h][0] = W::mma(fr, fx1b[uq][0], s1[h][0]);
+              s1[h][1] = W::mma(fr, fx1b[uq][1], s1[h][1]);
+            }
           }
-          if (ADJ) {
-            // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
-            const V8 fr = W::pack(e0, e1);
-            s1[h][0] = W::mma(fr, fx1b[uq][0], s1[h][0]);
-            s1[h][1] = W::mma(fr, fx1b[uq][1], s1[h][1]);
+        }
+        // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
+        if (ADJ) {
+  #pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            const V8 fs = W::pack(s1[0][nt], s1[1][nt]);
+  #pragma unroll
+            for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
           }
         }
       }
-      // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
-      if (ADJ) {
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const V8 fs = W::pack(s1[0][nt], s1[1][nt]);
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
-        }
+    }
+    if (NLL) {
+      __shared__ double sred[NT / 64];
+      const double v = warp_sum(s_nll);
+      if (lane == 0) sred[w] = v;
+      __syncthreads();
+      if (tid == 0) {
+        double a = 0.0;
+        for (int k = 0; k < NT / 64; ++k) a += sred[k];
+        P.partials[2 * grp] = a;
+        P.partials[2 * grp + 1] = 0.0;
       }
     }
-  }
-  if (NLL) {
-    __shared__ double sred[NT / 64];
-    const double v = warp_sum(s_nll);
-    if (lane == 0) sred[w] = v;
-    __syncthreads();
-    if (tid == 0) {
-      double a = 0.0;
-      for (int k = 0; k < NT / 64; ++k) a += sred[k];
-      P.partials[2 * grp] = a;
-      P.partials[2 * grp + 1] = 0.0;
-    }
-  }
-  if (!ADJ) return;
-  // S2 = sum of the parts' partials, through LDS (zeros for slabs beyond n3)
-  if (part > 0) {
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
-          if (i1 < G.p1 && i2 < G.p2) s2p[part - 1][sw][i1 + G.p1 * i2] = s2[mt][nt][i];
-        }
-  }
-  __syncthreads();
-  // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
-  if (part == 0) {
-    ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
-          if (i1 < G.p1 && i2 < G.p2) {
-            const int m = i1 + G.p1 * i2;
-            float v = s2[mt][nt][i];
-#pragma unroll
-            for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
-            if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
-            else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
+    if (!ADJ) continue;
+    // S2 = sum of the parts' partials, through LDS (zeros for slabs beyond n3)
+    if (part > 0) {
+  #pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+  #pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+            if (i1 < G.p1 && i2 < G.p2) s2p[part - 1][sw][i1 + G.p1 * i2] = s2[mt][nt][i];
           }
-        }
-  }
-  if (SPW == 4) {
-    // the 4 slabs' values of each m form one 4-element chunk
+    }
     __syncthreads();
-    st4* dst = (st4*)P.S2 + (long long)grp * P12;
-    for (int m = tid; m < P12; m += NT) dst[m] = ((const st4*)s2x)[m];
+    // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
+    if (part == 0) {
+      ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
+  #pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+  #pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+            if (i1 < G.p1 && i2 < G.p2) {
+              const int m = i1 + G.p1 * i2;
+              float v = s2[mt][nt][i];
+  #pragma unroll
+              for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
+              if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
+              else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
+            }
+          }
+    }
+    if (SPW == 4) {
+      // the 4 slabs' values of each m form one 4-element chunk
+      __syncthreads();
+      st4* dst = (st4*)P.S2 + (long long)grp * P12;
+      for (int m = tid; m < P12; m += NT) dst[m] = ((const st4*)s2x)[m];
+    }
   }
 }
 
@@ -1015,9 +1023,11 @@ __device__ inline int find_segment(const int* off, int nseg, int item) {
   return lo;
 }
 
+// Work items come from compact lists over the active problems (act, with prefix sums of
+// each phase's items), rebuilt by the host when the active set changes.
 // PH 0: mode-3 forward GEMM tiles of every active problem (and the step counter l)
-// PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem, in
-//       contiguous runs per workgroup so that the factor image is restaged rarely
+// PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem in runs of
+//       B.run consecutive slabs, so that the factor operands are loaded once per run
 // PH 2: mode-3 adjoint tiles + proximal step of every active problem
 template <typename T, int PH, bool WAVE>
 __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
@@ -1025,36 +1035,37 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if constexpr (PH == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *B.step += 1;
-    const int totA = B.off_fwd[B.nprob];
+    const int totA = B.aoff_fwd[B.nact];
     for (int item = blockIdx.x; item < totA; item += gridDim.x) {
-      const int pb = find_segment(B.off_fwd, B.nprob, item);
-      if (!B.active[pb]) continue;
-      const BatchDesc& D = B.desc[pb];
-      const int loc = item - B.off_fwd[pb];
+      const int k = find_segment(B.aoff_fwd, B.nact, item);
+      const BatchDesc& D = B.desc[B.act[k]];
+      const int loc = item - B.aoff_fwd[k];
       fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
     }
   } else if constexpr (PH == 1 && WAVE) {
-    // one slab per item with the one-wave-per-part register kernel (4 waves per slab)
-    const int totB = B.off_slab[B.nprob];
+    // one run per item with the one-wave-per-part register kernel (4 waves per slab)
+    const int totB = B.aoff_run[B.nact];
     for (int item = blockIdx.x; item < totB; item += gridDim.x) {
-      const int pb = find_segment(B.off_slab, B.nprob, item);
-      if (!B.active[pb]) continue;
-      const BatchDesc& D = B.desc[pb];
-      const int i3 = item - B.off_slab[pb];
-      if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4>(D.sp, i3);
-      else wave_chain_group<T, SM_FUSED, false, 1, 4>(D.sp, i3);
+      const int k = find_segment(B.aoff_run, B.nact, item);
+      const BatchDesc& D = B.desc[B.act[k]];
+      const int s0 = (item - B.aoff_run[k]) * B.run;
+      const int nrep = min(B.run, D.sp.G.n3 - s0);
+      if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4>(D.sp, s0, nrep);
+      else wave_chain_group<T, SM_FUSED, false, 1, 4>(D.sp, s0, nrep);
       __syncthreads();   // LDS of the next item
     }
   } else if constexpr (PH == 1) {
-    const int totB = B.off_slab[B.nprob];
+    // contiguous stretches of runs per workgroup: the LDS image is restaged only when the
+    // problem changes
+    const int totB = B.aoff_run[B.nact];
     const int chunk = (totB + gridDim.x - 1) / gridDim.x;
     const int i0 = blockIdx.x * chunk, i1 = min(totB, i0 + chunk);
     int cur = -1;
     ChainLayout L;
     double s_nll = 0.0, s_vmax = 0.0;
     for (int item = i0; item < i1; ++item) {
-      const int pb = find_segment(B.off_slab, B.nprob, item);
-      if (!B.active[pb]) continue;
+      const int k = find_segment(B.aoff_run, B.nact, item);
+      const int pb = B.act[k];
       const BatchDesc& D = B.desc[pb];
       if (pb != cur) {
         __syncthreads();
@@ -1062,18 +1073,21 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
         chain_stage(D.sp.img, L.image_bytes, smem_raw);
         cur = pb;
       }
-      const int i3 = item - B.off_slab[pb];
-      if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
-      else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+      const int s0 = (item - B.aoff_run[k]) * B.run, s1 = min(D.sp.G.n3, s0 + B.run);
+      for (int i3 = s0; i3 < s1; ++i3) {
+        if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+        else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
+      }
     }
   } else {
-    const int totC = B.off_adj[B.nprob];
+    const int totC = B.aoff_adj[B.nact];
     for (int item = blockIdx.x; item < totC; item += gridDim.x) {
-      const int pb = find_segment(B.off_adj, B.nprob, item);
-      if (!B.active[pb]) continue;
+      const int k = find_segment(B.aoff_adj, B.nact, item);
+      const int pb = B.act[k];
       const BatchDesc& D = B.desc[pb];
-      const int loc = item - B.off_adj[pb];
-      adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, item);
+      const int loc = item - B.aoff_adj[k];
+      // partials at the problem's own offset (read per problem by k_segment_max)
+      adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, B.off_adj[pb] + loc);
     }
   }
 }
