@@ -1206,9 +1206,16 @@ static int num_cus() {
   return n;
 }
 
+// FP64: 64 x 64 workgroup tiles where they still give half the CUs a workgroup (C2's shape:
+// 240 tiles, 26.7 -> 22.1 us); below that, 32 x 32 tiles (a Sec. 6.5 design at P12 = 450,
+// n3 = 180 has 24 large tiles against 90 small ones, and its FP64 path ran 25% slower on them)
+static bool slab_fwd_f64_wide(const Geom& G) { return (long long)((G.P12 + 63) / 64) * ((G.n3 + 63) / 64) >= 128; }
+
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s) {
   dim3 grid((P.G.P12 + 31) / 32, (P.G.n3 + 31) / 32);
-  if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd64, dim3((P.G.P12 + 63) / 64, (P.G.n3 + 63) / 64), dim3(WG), 0, s, P);
+  if (dt == DT_F64 && slab_fwd_f64_wide(P.G))
+    hipLaunchKernelGGL(k_slab_fwd64, dim3((P.G.P12 + 63) / 64, (P.G.n3 + 63) / 64), dim3(WG), 0, s, P);
+  else if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd<double>, grid, dim3(WG), 0, s, P);
   else if (dt == DT_F32) hipLaunchKernelGGL(k_slab_fwd<float>, grid, dim3(WG), 0, s, P);
   else hipLaunchKernelGGL(k_slab_fwd<bf16>, grid, dim3(WG), 0, s, P);
   return hipGetLastError();

@@ -24,6 +24,7 @@ SHAPES = [
     ((5, 3, 200), (1, 2, 70)),          # tiny inner modes, long slab mode
     ((128, 128, 8), (32, 32, 4)),       # largest inner p
     ((64, 64, 37), (24, 24, 12)),       # Poisson workload's inner modes
+    ((40, 30, 700), (25, 30, 50)),      # FP64 forward with 64 x 64 tiles (132 of them), ragged
 ]
 
 
