@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <memory>
 #include <vector>
@@ -1238,9 +1239,33 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   struct EvGuard { hipEvent_t e; ~EvGuard() { if (e) (void)hipEventDestroy(e); } } eg{ev};
   if (hipEventRecord(ev, us) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
+  // Each problem's own work (set-up, FP64 steps 2 and 5 of Algorithm 1) goes to one of a few
+  // streams, so that the small per-problem kernels of different problems overlap; the batched
+  // inner steps run on s.  The host synchronises every stream between the phases.
+  constexpr int kPoolStreams = 4;
+  struct PoolGuard {
+    hipStream_t p[kPoolStreams] = {};
+    ~PoolGuard() { for (hipStream_t q : p) if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); } }
+  } pool;
+  const int npool = std::min(kPoolStreams, nprob);
+  for (int k = 0; k < npool; ++k)
+    if (hipStreamCreateWithFlags(&pool.p[k], hipStreamNonBlocking) != hipSuccess || hipStreamWaitEvent(pool.p[k], ev, 0) != hipSuccess)
+      return fit_fail(GLAM_EDEVICE, "stream");
+  auto sync_all = [&]() -> hipError_t {
+    hipError_t e = hipStreamSynchronize(s);
+    for (int k = 0; k < npool; ++k) {
+      const hipError_t ek = hipStreamSynchronize(pool.p[k]);
+      if (e == hipSuccess) e = ek;
+    }
+    return e;
+  };
 
   // one arena for the whole batch; every set-up is queued before one synchronisation
   std::shared_ptr<Arena> arena = std::make_shared<Arena>();
+  struct SyncGuard {   // every stream idle before the arena goes (on early returns too)
+    std::function<hipError_t()> f;
+    ~SyncGuard() { (void)f(); }
+  } syncg{sync_all};
   std::vector<std::unique_ptr<Fit>> fits(nprob);
   std::vector<Geom> Gs(nprob);
   for (int i = 0; i < nprob; ++i) {
@@ -1249,14 +1274,14 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     F.arena = arena;
     F.G = Gs[i] = make_geom(probs[i].n, probs[i].p);
     F.dt = dt;
-    F.s = s;
+    F.s = pool.p[i % npool];
     F.own_stream = false;
     F.batched = true;
     F.enet = opt->alpha;
     const int r = fit_setup_enqueue(F, &probs[i], false, false);
     if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
   }
-  if (hipStreamSynchronize(s) != hipSuccess) return fit_fail(GLAM_EDEVICE, "set-up failed");
+  if (sync_all() != hipSuccess) return fit_fail(GLAM_EDEVICE, "set-up failed");
   for (int i = 0; i < nprob; ++i) {
     const int r = fit_setup_finish(*fits[i]);
     if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + fits[i]->err);
@@ -1368,11 +1393,11 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   std::vector<double> lam(nprob), lmax(nprob), scale(nprob);
   for (int i = 0; i < nprob; ++i) {
     Fit& F = *fits[i];
-    BCHK(launch_fill(F.theta, Gs[i].p, 0.0, s));
+    BCHK(launch_fill(F.theta, Gs[i].p, 0.0, F.s));
     const int r = family_enqueue(F, F.theta, 0.0);
     if (r) return fit_fail(r, F.err);
   }
-  BCHK(hipStreamSynchronize(s));
+  BCHK(sync_all());
   for (int i = 0; i < nprob; ++i) {
     StepStats st0;
     family_collect(*fits[i], &st0);
@@ -1403,7 +1428,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
       const int r = family_enqueue(*fits[i], fits[i]->theta, lam[i]);
       if (r) return fit_fail(r, fits[i]->err);
     }
-    BCHK(hipStreamSynchronize(s));
+    BCHK(sync_all());
     for (int i = 0; i < nprob; ++i) {
       h_active[i] = 0;
       if (done[i]) continue;
@@ -1470,14 +1495,14 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
       if (!in_round[i]) continue;
       Fit& F = *fits[i];
       if (exact[i]) {   // Sec. 6.5: no outer loop for the exact model (alpha = 1)
-        BCHK(hipMemcpyAsync(F.theta, F.xp, Gs[i].p * 8, hipMemcpyDeviceToDevice, s));
+        BCHK(hipMemcpyAsync(F.theta, F.xp, Gs[i].p * 8, hipMemcpyDeviceToDevice, F.s));
         continue;
       }
-      BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, s));
+      BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, F.s));
       const int r = armijo_enqueue(F, 0);
       if (r) return fit_fail(r, F.err);
     }
-    BCHK(hipStreamSynchronize(s));
+    BCHK(sync_all());
     for (int i = 0; i < nprob; ++i) {
       if (!in_round[i] || exact[i]) continue;
       Fit& F = *fits[i];
@@ -1486,15 +1511,15 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
         const int r = armijo_finish(F, lam[i], 0.1, true, &alpha, &Delta);
         if (r) return fit_fail(r, F.err);
       }
-      if (alpha > 0.0) BCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, s));
+      if (alpha > 0.0) BCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, F.s));
     }
   }
   int worst = GLAM_OK;
   for (int i = 0; i < nprob; ++i) {
-    BCHK(hipMemcpyAsync(res->theta[i], fits[i]->theta, Gs[i].p * 8, hipMemcpyDeviceToDevice, s));
+    BCHK(hipMemcpyAsync(res->theta[i], fits[i]->theta, Gs[i].p * 8, hipMemcpyDeviceToDevice, fits[i]->s));
     if (res->status[i] != GLAM_OK && worst == GLAM_OK) worst = res->status[i];
   }
-  BCHK(hipStreamSynchronize(s));
+  BCHK(sync_all());
   BCHK(hipEventRecord(ev, s));
   BCHK(hipStreamWaitEvent(us, ev, 0));
   res->steps = launches;
