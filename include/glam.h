@@ -241,9 +241,13 @@ typedef struct {
 } glam_batch_result;
 
 /* Fit nprob independent problems (each as in glam_fit_path with nlambda = 1; nu = 1).
- * Problems may differ in sizes and family.  Returns GLAM_ENOCONV if any problem did
- * not converge (its status says which).  Errors: GLAM_EINVAL as glam_fit_path, plus
- * nprob < 1. */
+ * Problems may differ in sizes and family.  A problem whose modes do not fit the slab
+ * kernels in the caller's order is solved in another order, as in glam_fit_path (its Y,
+ * obs_w and pen_w permuted on opt->stream into buffers of its own, theta[i] returned in
+ * the caller's order).  Per-problem set-up and outer steps run on a few internal streams
+ * ordered after opt->stream; the call returns once all of them are done.  Returns
+ * GLAM_ENOCONV if any problem did not converge (its status says which).  Errors:
+ * GLAM_EINVAL as glam_fit_path, plus nprob < 1. */
 int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_options* opt,
                      glam_batch_result* res);
 

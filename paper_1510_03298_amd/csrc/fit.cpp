@@ -830,6 +830,9 @@ struct PermutedProblem {
   int q[3] = {0, 1, 2};      // position k holds the caller's mode q[k]
   bool active = false;
   std::vector<void*> bufs;
+  PermutedProblem() = default;
+  PermutedProblem(const PermutedProblem&) = delete;
+  PermutedProblem& operator=(const PermutedProblem&) = delete;
   ~PermutedProblem() { for (void* b : bufs) (void)hipFree(b); }
   double* alloc(size_t count) {
     void* b = nullptr;
@@ -841,14 +844,15 @@ struct PermutedProblem {
 
 // If the caller's mode order does not fit the slab kernels, pick an order that does (the largest
 // remaining mode last), and permute the problem's arrays on the caller's stream.
-static int permute_problem(glam_problem* prob, glam_options* opt, PermutedProblem* pp, hipStream_t us, std::string* why) {
-  if (inner_modes_fit(prob->n, prob->p, opt->dtype)) return GLAM_OK;
+static int permute_problem(glam_problem* prob, int dtype, const double** theta0, PermutedProblem* pp, hipStream_t us,
+                           std::string* why) {
+  if (inner_modes_fit(prob->n, prob->p, dtype)) return GLAM_OK;
   static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 2, 0}, {1, 0, 2}, {2, 0, 1}, {2, 1, 0}};
   int best = -1;
   for (int c = 1; c < 6; ++c) {
     int64_t n[3], p[3];
     for (int k = 0; k < 3; ++k) { n[k] = prob->n[perms[c][k]]; p[k] = prob->p[perms[c][k]]; }
-    if (!inner_modes_fit(n, p, opt->dtype)) continue;
+    if (!inner_modes_fit(n, p, dtype)) continue;
     if (best < 0 || n[2] > prob->n[perms[best][2]]) best = c;
   }
   if (best < 0) {
@@ -872,7 +876,7 @@ static int permute_problem(glam_problem* prob, glam_options* opt, PermutedProble
   if ((r = copy(prob->Y, n, prob->n, &out.Y))) return r;
   if ((r = copy(prob->obs_w, n, prob->n, &out.obs_w))) return r;
   if ((r = copy(prob->pen_w, p, prob->p, &out.pen_w))) return r;
-  if ((r = copy(opt->theta0, p, prob->p, &opt->theta0))) return r;
+  if (theta0 && (r = copy(*theta0, p, prob->p, theta0))) return r;
   *prob = out;
   return GLAM_OK;
 }
@@ -931,7 +935,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   {
     // modes reordered, when needed, so that two of them fit the slab kernels (R20)
     std::string why;
-    const int r = permute_problem(&lifted, &opt_local, &perm, (hipStream_t)opt_in->stream, &why);
+    const int r = permute_problem(&lifted, opt_local.dtype, &opt_local.theta0, &perm, (hipStream_t)opt_in->stream, &why);
     if (r) return fit_fail(r, why);
   }
 
@@ -1213,6 +1217,14 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   }
   const glam_problem* probs = lifted.data();
   if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
+  // a problem whose modes 1-2 do not fit the slab kernels is solved in another mode order
+  // (its arrays permuted on the caller's stream, theta returned in the caller's order)
+  std::vector<PermutedProblem> perms(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    std::string why;
+    const int r = permute_problem(&lifted[i], opt->dtype, nullptr, &perms[i], (hipStream_t)opt->stream, &why);
+    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + why);
+  }
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
   if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
@@ -1516,7 +1528,13 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   }
   int worst = GLAM_OK;
   for (int i = 0; i < nprob; ++i) {
-    BCHK(hipMemcpyAsync(res->theta[i], fits[i]->theta, Gs[i].p * 8, hipMemcpyDeviceToDevice, fits[i]->s));
+    if (perms[i].active) {   // back to the caller's mode order
+      int qi[3];
+      for (int k = 0; k < 3; ++k) qi[perms[i].q[k]] = k;
+      BCHK(launch_permute3(fits[i]->theta, res->theta[i], probs[i].p, qi, fits[i]->s));
+    } else {
+      BCHK(hipMemcpyAsync(res->theta[i], fits[i]->theta, Gs[i].p * 8, hipMemcpyDeviceToDevice, fits[i]->s));
+    }
     if (res->status[i] != GLAM_OK && worst == GLAM_OK) worst = res->status[i];
   }
   BCHK(sync_all());

@@ -104,3 +104,36 @@ def test_batched_four_families():
         th = glam.from_colmajor(res.theta[i], d.p)
         g = O.smooth_gradient(d.family, d.X, th, d.Y)
         assert O.kkt_residual(th, g, 0.1 * lm, lm) <= 1e-6, (i, d.family)
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+def test_batched_mode_order_chosen_by_the_library(fam, dt):
+    """A batch holding Section 6.5's design in the paper's own mode order (60r, 20r, 10r), r = 2,
+    whose p_1 = 60 does not fit the slab kernels: the batched solver reorders that problem itself.
+    Bit for bit the estimates of the same batch with the problem given in an order that fits, and
+    the oracle's KKT on the caller's order."""
+    torch, glam = need_gpu()
+    d = inputs.config_sim(r=2, family=fam, seed=9)            # listed as (20r, 10r, 60r)
+    Xs = [d.X[2], d.X[0], d.X[1]]                             # the paper's order
+    Y = np.asfortranarray(d.Y.transpose(2, 0, 1))
+    n = tuple(X.shape[0] for X in Xs)
+    p = tuple(X.shape[1] for X in Xs)
+    other = inputs.config_c4(nprob=1, lo=16, hi=24, seed_offset=43)[0]
+    print(f"batched mode order {fam} dt={dt} n={n} p={p}", flush=True)
+    up = {"X": [glam.to_device_colmajor(X, 0) for X in Xs], "Y": glam.to_device_colmajor(Y, 0),
+          "n": n, "p": p, "family": fam}
+    up_fit = {"X": [glam.to_device_colmajor(X, 0) for X in d.X], "Y": glam.to_device_colmajor(d.Y, 0),
+              "n": d.n, "p": d.p, "family": fam}
+    r1 = glam.fit_batched([up, _upload(glam, other)], lambda_ratio=0.1, dtype=dt, kkt_tol=1e-7)
+    r2 = glam.fit_batched([up_fit, _upload(glam, other)], lambda_ratio=0.1, dtype=dt, kkt_tol=1e-7)
+    assert r1.code == r2.code == 0
+    assert np.array_equal(r1.iters_outer, r2.iters_outer)
+    a = glam.from_colmajor(r1.theta[0], p)
+    b = glam.from_colmajor(r2.theta[0], d.p)
+    assert np.array_equal(a, np.asfortranarray(b.transpose(2, 0, 1)))
+    assert np.array_equal(glam.from_colmajor(r1.theta[1], other.p), glam.from_colmajor(r2.theta[1], other.p))
+    lm = O.lambda_max(fam, Xs, Y)
+    assert abs(r1.lambda_max[0] - lm) <= 1e-12 * lm
+    g = O.smooth_gradient(fam, Xs, a, Y)
+    assert O.kkt_residual(a, g, 0.1 * lm, lm) <= 1e-7
