@@ -270,6 +270,28 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
                               void* grad, int dtype, void* workspace, size_t ws_bytes,
                               void* stream);
 
+/* The same loss and gradient with X and Y packed into the workspace once (a fit or a
+ * training loop evaluates L at many beta for one design and one response).
+ * glam_poisson_nll_pack writes the packed factors and a copy of the counts (FP32,
+ * tiled like the slab kernel's tiles, for BF16/FP32 chains with n_1, n_2 <= 128; FP64
+ * otherwise) into a workspace of glam_nll_packed_workspace_size bytes, on `stream`.
+ * The *_packed calls then take only beta: they read that workspace (which must have
+ * been packed for the same n, p and dtype, and not written since) and give the same
+ * values as glam_poisson_nll_forward / _backward (bit for bit for integer counts below
+ * 2^24).  Y must be integer-valued counts when the FP32 copy is used.  Calls that share
+ * a workspace must not overlap (the T1 and partial-sum regions are reused).  Errors:
+ * GLAM_EINVAL for bad sizes, NULL pointers or a workspace too small. */
+size_t glam_nll_packed_workspace_size(const int64_t* n, const int64_t* p, int dtype);
+int glam_poisson_nll_pack(const int64_t* n, const int64_t* p, const void* const* X,
+                          const double* Y, int dtype, void* workspace, size_t ws_bytes,
+                          void* stream);
+int glam_poisson_nll_forward_packed(const int64_t* n, const int64_t* p, const void* beta,
+                                    double* loss, int dtype, void* workspace, size_t ws_bytes,
+                                    void* stream);
+int glam_poisson_nll_backward_packed(const int64_t* n, const int64_t* p, const void* beta,
+                                     const double* gscale, void* grad, int dtype,
+                                     void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -271,4 +271,113 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
   return GLAM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// NLL with the factors and counts packed once (the workspace keeps them between calls)
+// ---------------------------------------------------------------------------
+// Layout: the rho workspace, then the counts: tiled FP32 for the one-wave-per-slab kernel,
+// else an FP64 copy in the standard layout.
+struct NllPacked {
+  WsLayout W;
+  size_t y, total;
+  bool tiled;
+};
+static NllPacked nll_packed_layout(const Geom& G, int dt) {
+  NllPacked L;
+  L.W = ws_layout(G, dt);
+  L.tiled = chain_image_need(dt, SM_NLL_FWD, G) == PACK_WAVE;
+  L.y = L.W.total;
+  L.total = L.y + align256(L.tiled ? (size_t)G.nint * sizeof(float) : (size_t)G.n * sizeof(double));
+  return L;
+}
+
+size_t glam_nll_packed_workspace_size(const int64_t* n, const int64_t* p, int dtype) {
+  Geom G;
+  if (check_sizes(3, n, p, dtype, &G) != GLAM_OK) return 0;
+  return nll_packed_layout(G, dtype).total;
+}
+
+int glam_poisson_nll_pack(const int64_t* n, const int64_t* p, const void* const* X, const double* Y, int dtype,
+                          void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Geom G;
+  int st = check_sizes(3, n, p, dtype, &G);
+  if (st) return st;
+  if (!X || !X[0] || !X[1] || !X[2] || !Y || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_nll_packed_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const NllPacked L = nll_packed_layout(G, dtype);
+  const WsLayout& W = L.W;
+  const size_t es = dt_size(dtype);
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
+  HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
+  HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s,
+                                 chain_image_need(dtype, SM_NLL_FWD, G) | chain_image_need(dtype, SM_NLL_BWD, G)));
+  HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
+  if (L.tiled) HIPCHK(launch_to_tiled_f32(G, Y, (float*)(ws + L.y), s));
+  else HIPCHK(hipMemcpyAsync(ws + L.y, Y, (size_t)G.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return GLAM_OK;
+}
+
+// checks shared by the packed entry points; eta = H(beta) into T1 of the workspace
+static int nll_packed_begin(const int64_t* n, const int64_t* p, const void* beta, int dtype, void* workspace,
+                            size_t ws_bytes, hipStream_t s, Geom* G, NllPacked* L) {
+  int st = check_sizes(3, n, p, dtype, G);
+  if (st) return st;
+  if (!beta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < glam_nll_packed_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  *L = nll_packed_layout(*G, dtype);
+  char* ws = (char*)workspace;
+  HIPCHK(launch_pack(dtype, dtype, beta, G->p3, G->P12, G->P12, 1, ws + L->W.inc, s));
+  FwdParams F{};
+  F.G = *G; F.theta = ws + L->W.inc; F.X3f = ws + L->W.x3f; F.T1 = ws + L->W.t1;
+  HIPCHK(launch_slab_fwd(dtype, F, s));
+  return GLAM_OK;
+}
+
+int glam_poisson_nll_forward_packed(const int64_t* n, const int64_t* p, const void* beta, double* loss, int dtype,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!loss) return fail(GLAM_EINVAL, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Geom G;
+  NllPacked L;
+  int st = nll_packed_begin(n, p, beta, dtype, workspace, ws_bytes, s, &G, &L);
+  if (st) return st;
+  char* ws = (char*)workspace;
+  double* part = (double*)(ws + L.W.part);
+  SlabParams S{};
+  S.G = G; S.img = ws + L.W.img; S.T1 = ws + L.W.t1; S.partials = part;
+  if (L.tiled) S.y_tiled = (const float*)(ws + L.y);
+  else S.y_std = (const double*)(ws + L.y);
+  int nb = 0;
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_FWD, S, &nb, s));
+  const int ops[1] = {0};
+  HIPCHK(launch_reduce_strided(part, nb, 2, 1, ops, 1.0 / (double)G.n, loss, s));
+  return GLAM_OK;
+}
+
+int glam_poisson_nll_backward_packed(const int64_t* n, const int64_t* p, const void* beta, const double* gscale,
+                                     void* grad, int dtype, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!grad) return fail(GLAM_EINVAL, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Geom G;
+  NllPacked L;
+  int st = nll_packed_begin(n, p, beta, dtype, workspace, ws_bytes, s, &G, &L);
+  if (st) return st;
+  char* ws = (char*)workspace;
+  SlabParams S{};
+  S.G = G; S.img = ws + L.W.img; S.T1 = ws + L.W.t1; S.S2 = ws + L.W.s2;
+  S.partials = (double*)(ws + L.W.part);
+  if (L.tiled) S.y_tiled = (const float*)(ws + L.y);
+  else S.y_std = (const double*)(ws + L.y);
+  HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, nullptr, s));
+  AdjParams A{};
+  A.G = G; A.S2 = ws + L.W.s2; A.X3a = ws + L.W.x3a; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
+  A.s2_kb4 = chain_s2_kb4(dtype, SM_NLL_BWD, G);
+  HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  return GLAM_OK;
+}
+
 }  // extern "C"

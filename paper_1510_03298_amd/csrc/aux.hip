@@ -98,7 +98,8 @@ __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, l
     dst[i] = Tr<T>::from_acc((typename Tr<T>::acc_t)src[i]);
 }
 
-__global__ void k_to_tiled(Geom G, const double* __restrict__ src, double fill, double* __restrict__ dst) {
+template <typename T>
+__global__ void k_to_tiled(Geom G, const double* __restrict__ src, double fill, T* __restrict__ dst) {
   // one thread per tiled element; src == NULL means the constant `fill` on valid cells
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < G.nint; t += (long long)gridDim.x * blockDim.x) {
     const int i1l = (int)(t & 15), i2l = (int)((t >> 4) & 15);
@@ -110,7 +111,7 @@ __global__ void k_to_tiled(Geom G, const double* __restrict__ src, double fill, 
     const int i1 = ut * 16 + i1l, i2 = jb * 16 + i2l;
     double v = 0.0;
     if (i1 < G.n1 && i2 < G.n2) v = src ? src[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)] : fill;
-    dst[t] = v;
+    dst[t] = (T)v;
   }
 }
 
@@ -399,7 +400,12 @@ hipError_t launch_convert(int dt, const double* src, void* dst, long long count,
 }
 
 hipError_t launch_to_tiled(const Geom& G, const double* src_std, double fill_valid, double* dst_tiled, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_tiled, dim3(grid1d(G.nint)), dim3(WG), 0, s, G, src_std, fill_valid, dst_tiled);
+  hipLaunchKernelGGL(k_to_tiled<double>, dim3(grid1d(G.nint)), dim3(WG), 0, s, G, src_std, fill_valid, dst_tiled);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_tiled_f32(const Geom& G, const double* src_std, float* dst_tiled, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_tiled<float>, dim3(grid1d(G.nint)), dim3(WG), 0, s, G, src_std, 0.0, dst_tiled);
   return hipGetLastError();
 }
 

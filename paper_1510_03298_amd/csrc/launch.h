@@ -72,6 +72,7 @@ struct SlabParams {
   int family;         // glam_family: 0 Gaussian, 1 Poisson, 2 Binomial, 3 Gamma
   // NLL (standard-layout FP64 counts)
   const double* y_std;
+  const float* y_tiled;   // NLL, one-wave-per-slab kernel: the counts tiled like v_int (FP32), used instead of y_std
   double* partials;   // per-workgroup partial sums [grid][2]
 };
 
@@ -223,6 +224,8 @@ hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, con
 hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
                                  double* out, hipStream_t s);
 hipError_t launch_convert(int dt, const double* src, void* dst, long long count, hipStream_t s);
+// the same tiling into FP32 (zeros outside the model)
+hipError_t launch_to_tiled_f32(const Geom& G, const double* src_std, float* dst_tiled, hipStream_t s);
 hipError_t launch_to_tiled(const Geom& G, const double* src_std, double fill_valid, double* dst_tiled,
                            hipStream_t s);
 hipError_t launch_inner_init(const Geom& G, const double* theta, const double* gref, double* x, double* xp,

@@ -722,10 +722,10 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
     if (active) {
       // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
       V8 ft1[2];
-  #pragma unroll
+#pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
         const int i1 = 16 * mt + r;
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int i2 = kw_index(g, u);
           const ST h = (i1 < G.p1 && i2 < G.p2) ? t1s[sw * P12 + i1 + G.p1 * i2] : (ST)0;
@@ -733,21 +733,28 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
         }
       }
       const float* V = (const float*)P.v_int;
-  #pragma unroll
+#pragma unroll
       for (int jq = 0; jq < QPW; ++jq) {
         if (jb0 + 2 * jq >= NJB) break;
         f4v s1[2][2] = {{z4, z4}, {z4, z4}};
-  #pragma unroll
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int jl = 2 * jq + h, jb = jb0 + jl;
           if (jb >= NJB) break;
           // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
           const V8 ft2 = W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
-  #pragma unroll
+#pragma unroll
           for (int uq = 0; uq < 4; ++uq) {
             const int u0 = 2 * uq;
             if (u0 >= N1T) break;
             // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
+            // NLL counts of these two tiles from the tiled FP32 copy (requested before the products)
+            f4v yt0 = z4, yt1 = z4;
+            if (NLL && P.y_tiled) {
+              const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
+              yt0 = *(const f4v*)(P.y_tiled + t0);
+              if (u0 + 1 < N1T) yt1 = *(const f4v*)(P.y_tiled + t0 + 256);
+            }
             f4v e0 = W::mma(fx1a[u0], ft2, z4);
             f4v e1 = u0 + 1 < N1T ? W::mma(fx1a[u0 + 1], ft2, z4) : z4;
             if (HAS_V) {
@@ -762,16 +769,17 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
             if (NLL) {
               // Poisson NLL terms exp(eta) - y eta (FP64), R = exp(eta) - y
               const int i2 = 16 * jb + r;
-  #pragma unroll
+#pragma unroll
               for (int hh = 0; hh < 2; ++hh) {
                 f4v& e = hh ? e1 : e0;
-  #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
                   const int i1 = 16 * (u0 + hh) + 4 * g + i;
                   float rv = 0.f;
                   if (i1 < G.n1 && i2 < G.n2) {
                     const double eta = (double)e[i];
-                    const double y = P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
+                    const double y = P.y_tiled ? (double)(hh ? yt1 : yt0)[i]
+                                               : P.y_std[i1 + (long long)G.n1 * (i2 + (long long)G.n2 * i3)];
                     // (exp in FP32: eta carries the chain's own error, at or above FP32 rounding)
                     const double ex = (double)expf(e[i]);
                     s_nll += ex - y * eta;
@@ -791,10 +799,10 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
         }
         // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
         if (ADJ) {
-  #pragma unroll
+#pragma unroll
           for (int nt = 0; nt < 2; ++nt) {
             const V8 fs = W::pack(s1[0][nt], s1[1][nt]);
-  #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
           }
         }
@@ -815,11 +823,11 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
     if (!ADJ) continue;
     // S2 = sum of the parts' partials, through LDS (zeros for slabs beyond n3)
     if (part > 0) {
-  #pragma unroll
+#pragma unroll
       for (int mt = 0; mt < 2; ++mt)
-  #pragma unroll
+#pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
             if (i1 < G.p1 && i2 < G.p2) s2p[part - 1][sw][i1 + G.p1 * i2] = s2[mt][nt][i];
@@ -829,17 +837,17 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
     // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
     if (part == 0) {
       ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
-  #pragma unroll
+#pragma unroll
       for (int mt = 0; mt < 2; ++mt)
-  #pragma unroll
+#pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
             if (i1 < G.p1 && i2 < G.p2) {
               const int m = i1 + G.p1 * i2;
               float v = s2[mt][nt][i];
-  #pragma unroll
+#pragma unroll
               for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
               if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
               else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);

@@ -103,9 +103,18 @@ glam_poisson_nll_backward = _sig("glam_poisson_nll_backward", ctypes.c_int,
                                  [_i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp, ctypes.c_int, _vp,
                                   ctypes.c_size_t, _vp])
 
+glam_nll_packed_workspace_size = _sig("glam_nll_packed_workspace_size", ctypes.c_size_t, [_i64p, _i64p, ctypes.c_int])
+glam_poisson_nll_pack = _sig("glam_poisson_nll_pack", ctypes.c_int,
+                             [_i64p, _i64p, ctypes.POINTER(_vp), _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp])
+glam_poisson_nll_forward_packed = _sig("glam_poisson_nll_forward_packed", ctypes.c_int,
+                                       [_i64p, _i64p, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp])
+glam_poisson_nll_backward_packed = _sig("glam_poisson_nll_backward_packed", ctypes.c_int,
+                                        [_i64p, _i64p, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp])
+
 EXPORTED = ["glam_status_string", "glam_last_error", "glam_version", "glam_rho_workspace_size",
             "glam_rho_forward", "glam_rho_adjoint", "glam_fit_path", "glam_fit_batched", "glam_nll_workspace_size",
-            "glam_poisson_nll_forward", "glam_poisson_nll_backward"]
+            "glam_poisson_nll_forward", "glam_poisson_nll_backward", "glam_nll_packed_workspace_size",
+            "glam_poisson_nll_pack", "glam_poisson_nll_forward_packed", "glam_poisson_nll_backward_packed"]
 
 
 class GlamError(RuntimeError):
@@ -242,6 +251,42 @@ def poisson_nll_backward(Xs, beta, Y, gscale, n, p, dtype, workspace=None, strea
                                      int(dtype), workspace.data_ptr(), wsb, _stream_ptr(stream)),
            "glam_poisson_nll_backward")
     return grad
+
+
+class PackedPoissonNLL:
+    """Poisson NLL with X and Y packed once into a workspace of its own: forward(beta) and
+    backward(beta, gscale) then run only the beta-dependent work."""
+
+    def __init__(self, Xs, Y, n, p, dtype, stream=None):
+        torch = _torch()
+        self.n, self.p, self.dtype, self.stream = tuple(n), tuple(p), int(dtype), stream
+        nn, pp = _sizes(n, p)
+        self.wsb = int(glam_nll_packed_workspace_size(nn, pp, self.dtype))
+        if self.wsb == 0:
+            raise GlamError(GLAM_EINVAL, "glam_nll_packed_workspace_size")
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=Y.device)
+        xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
+        _check(glam_poisson_nll_pack(nn, pp, xp, Y.data_ptr(), self.dtype, self.ws.data_ptr(), self.wsb,
+                                     _stream_ptr(stream)), "glam_poisson_nll_pack")
+
+    def forward(self, beta):
+        torch = _torch()
+        nn, pp = _sizes(self.n, self.p)
+        loss = torch.empty(1, dtype=torch.float64, device=beta.device)
+        _check(glam_poisson_nll_forward_packed(nn, pp, beta.data_ptr(), loss.data_ptr(), self.dtype,
+                                               self.ws.data_ptr(), self.wsb, _stream_ptr(self.stream)),
+               "glam_poisson_nll_forward_packed")
+        return loss
+
+    def backward(self, beta, gscale):
+        torch = _torch()
+        nn, pp = _sizes(self.n, self.p)
+        grad = torch.empty(int(np.prod(self.p)), dtype=out_dtype(self.dtype), device=beta.device)
+        gs = gscale.to(torch.float64).reshape(1).contiguous()
+        _check(glam_poisson_nll_backward_packed(nn, pp, beta.data_ptr(), gs.data_ptr(), grad.data_ptr(), self.dtype,
+                                                self.ws.data_ptr(), self.wsb, _stream_ptr(self.stream)),
+               "glam_poisson_nll_backward_packed")
+        return grad
 
 
 class PoissonNLL:

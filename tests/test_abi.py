@@ -159,3 +159,26 @@ def test_no_mode_order_fits_is_rejected_on_the_host():
     res.iters_outer = res.iters_inner = res.status = io
     rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     assert rc == glam.GLAM_EINVAL and b"order of the modes" in glam.glam_last_error()
+
+
+def test_packed_nll_workspace_and_argument_checks():
+    """The packed NLL entry points: workspace size (the rho workspace plus the counts) and the
+    host-side refusals that come before any device work."""
+    from paper_1510_03298_amd import glam
+    n, p = _sizes((128, 128, 256), (32, 32, 64))
+    w = glam.glam_nll_workspace_size(n, p, glam.BF16)
+    wp = glam.glam_nll_packed_workspace_size(n, p, glam.BF16)
+    assert wp >= w + 128 * 128 * 256 * 4          # tiled FP32 counts
+    wp64 = glam.glam_nll_packed_workspace_size(n, p, glam.F64)
+    assert wp64 >= glam.glam_nll_workspace_size(n, p, glam.F64) + 128 * 128 * 256 * 8   # FP64 copy
+    bad_n, bad_p = _sizes((128, 128, 256), (40, 32, 64))
+    assert glam.glam_nll_packed_workspace_size(bad_n, bad_p, glam.BF16) == 0
+    X = (ctypes.c_void_p * 3)(None, None, None)
+    assert glam.glam_poisson_nll_pack(n, p, X, None, glam.BF16, None, 0, None) == glam.GLAM_EINVAL
+    assert b"NULL" in glam.glam_last_error()
+    dummy = ctypes.c_double(0.0)
+    ptr = ctypes.addressof(dummy)
+    rc = glam.glam_poisson_nll_forward_packed(n, p, ptr, ptr, glam.BF16, ptr, wp - 1, None)
+    assert rc == glam.GLAM_EINVAL and b"workspace" in glam.glam_last_error()
+    rc = glam.glam_poisson_nll_backward_packed(n, p, ptr, ptr, None, glam.BF16, ptr, wp, None)
+    assert rc == glam.GLAM_EINVAL and b"NULL" in glam.glam_last_error()

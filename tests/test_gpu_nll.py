@@ -82,3 +82,47 @@ def test_nll_full_size_workload(dt):
     loss.backward()
     torch.cuda.synchronize()
     _check(glam, d, beta, float(loss.detach()), b.grad, dt)
+
+
+@pytest.mark.parametrize("dt", [0, 1, 2])
+@pytest.mark.parametrize("n,p", [((21, 18, 30), (7, 6, 9)), ((40, 33, 17), (20, 17, 5)),
+                                 ((150, 20, 12), (10, 8, 5))])   # n_1 > 128: the LDS kernel, FP64 counts
+def test_nll_packed_matches_unpacked(n, p, dt):
+    """X and Y packed once: loss and gradient at two successive betas bit for bit those of the
+    one-shot entry points (integer counts), and within the oracle's bound."""
+    torch, glam = need_gpu()
+    print(f"nll packed n={n} p={p} dt={dt}", flush=True)
+    d = inputs.random_problem(n, p, family="poisson", seed=33, scale=0.3)
+    Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    one = torch.ones(1, dtype=torch.float64, device=Yd.device)
+    packed = glam.PackedPoissonNLL(Xd, Yd, n, p, dt)
+    for k in range(2):
+        beta = np.random.default_rng(50 + k).normal(0.0, 0.2, p)
+        b = glam.to_device_colmajor(beta, dt)
+        l1 = packed.forward(b)
+        g1 = packed.backward(b, one)
+        l0 = glam.poisson_nll_forward(Xd, b, Yd, n, p, dt)
+        g0 = glam.poisson_nll_backward(Xd, b, Yd, one, n, p, dt)
+        torch.cuda.synchronize()
+        assert float(l1) == float(l0)
+        assert torch.equal(g1, g0)
+        _check(glam, d, beta, float(l1), g1, dt)
+
+
+def test_nll_packed_full_size_workload():
+    """n=(128,128,256), p=(32,32,64), BF16: the packed calls bit for bit the one-shot calls."""
+    torch, glam = need_gpu()
+    d = inputs.config_c5()
+    dt = 2
+    Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    b = glam.to_device_colmajor(d.extra["beta"], dt)
+    one = torch.ones(1, dtype=torch.float64, device=Yd.device)
+    packed = glam.PackedPoissonNLL(Xd, Yd, d.n, d.p, dt)
+    l1, g1 = packed.forward(b), packed.backward(b, one)
+    l0 = glam.poisson_nll_forward(Xd, b, Yd, d.n, d.p, dt)
+    g0 = glam.poisson_nll_backward(Xd, b, Yd, one, d.n, d.p, dt)
+    torch.cuda.synchronize()
+    assert float(l1) == float(l0)
+    assert torch.equal(g1, g0)
