@@ -43,52 +43,43 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
 // ============================================================================
 // small kernels
 // ============================================================================
-// out[v] = scale * sum_b part[b][v] (ops bit v = 0) or max_b part[b][v] (bit v = 1), v < nval <= 32,
-// 8 values per pass with a fixed summation order.  With hout != NULL the values are
-// also published to host memory (fine-grained, mapped), followed by an incremented
-// sequence number *hseq (kept in *seq_dev), so that the host can wait on it without a
-// copy.
-constexpr int RED_MAXV = 8;
-__global__ void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval, unsigned ops_bits,
-                         double scale, double* __restrict__ out, double* hout, unsigned* seq_dev, unsigned* hseq) {
-  __shared__ double sm[WG / 64][RED_MAXV];
-  for (int v0 = 0; v0 < nval; v0 += RED_MAXV) {
-    double a[RED_MAXV];
-#pragma unroll
-    for (int v = 0; v < RED_MAXV; ++v) a[v] = ((ops_bits >> (v0 + v)) & 1u) ? -INFINITY : 0.0;
-    for (int b = threadIdx.x; b < nblk; b += WG) {
-#pragma unroll
-      for (int v = 0; v < RED_MAXV; ++v) {
-        if (v0 + v < nval) {
-          const double x = part[(long long)b * stride + v0 + v];
-          a[v] = ((ops_bits >> (v0 + v)) & 1u) ? fmax(a[v], x) : a[v] + x;
-        }
+// out[v] = scale * sum_b part[b][v] (ops bit v = 0) or max_b part[b][v] (bit v = 1), v < nval <= 32.
+// One wave per value (values v, v + 16, ... on wave v % 16 of a 1024-thread workgroup): lane l
+// takes the blocks l, l + 64, ... in order, then a fixed butterfly across the wave, so the
+// summation order is fixed and every value is one round of independent loads.  With
+// hout != NULL the values are also published to host memory (fine-grained, mapped),
+// followed by an incremented sequence number *hseq (kept in *seq_dev), so that the host
+// can wait on it without a copy.
+constexpr int RED_WG = 1024;
+__global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval,
+                                                   unsigned ops_bits, double scale, double* __restrict__ out,
+                                                   double* hout, unsigned* seq_dev, unsigned* hseq) {
+  const int lane = lane_id(), w = wave_id();
+  for (int v = w; v < nval; v += RED_WG / 64) {
+    const bool mx = (ops_bits >> v) & 1u;
+    double a = mx ? -INFINITY : 0.0;
+    for (int b = lane; b < nblk; b += 64) {
+      const double x = part[(long long)b * stride + v];
+      a = mx ? fmax(a, x) : a + x;
+    }
+    a = mx ? warp_max(a) : warp_sum(a);
+    if (lane == 0) {
+      const double r = mx ? a : scale * a;
+      out[v] = r;
+      if (hout) {
+        __hip_atomic_store(&hout[v], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __threadfence_system();   // visible to the host before the sequence number below
       }
     }
-#pragma unroll
-    for (int v = 0; v < RED_MAXV; ++v) a[v] = ((ops_bits >> (v0 + v)) & 1u) ? warp_max(a[v]) : warp_sum(a[v]);
-    if (lane_id() == 0) {
-#pragma unroll
-      for (int v = 0; v < RED_MAXV; ++v) sm[wave_id()][v] = a[v];
-    }
+  }
+  if (hout) {
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int v = 0; v < RED_MAXV && v0 + v < nval; ++v) {
-        const unsigned op = (ops_bits >> (v0 + v)) & 1u;
-        double r = sm[0][v];
-        for (int w = 1; w < WG / 64; ++w) r = op ? fmax(r, sm[w][v]) : r + sm[w][v];
-        r = op ? r : scale * r;
-        out[v0 + v] = r;
-        if (hout) __hip_atomic_store(&hout[v0 + v], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+      const unsigned s = *seq_dev + 1u;
+      *seq_dev = s;
+      __threadfence_system();
+      __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    __syncthreads();
-  }
-  if (hout && threadIdx.x == 0) {
-    const unsigned s = *seq_dev + 1u;
-    *seq_dev = s;
-    __threadfence_system();
-    __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -371,7 +362,7 @@ hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, i
   unsigned bits = 0;
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
   if (nval > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, stride, nval, bits, scale, out,
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, stride, nval, bits, scale, out,
                      (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr);
   return hipGetLastError();
 }
@@ -381,7 +372,7 @@ hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, con
   unsigned bits = 0;
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
   if (nval > 32 || !hout || !seq_dev || !hseq) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WG), 0, s, partials, nblk, nval, nval, bits, scale, out, hout, seq_dev,
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, nval, nval, bits, scale, out, hout, seq_dev,
                      hseq);
   return hipGetLastError();
 }
