@@ -1385,14 +1385,22 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     const int run = B.wave ? (int)std::max(1LL, std::min(8LL, slabs / 2048)) : 1;
     int k = 0;
     afwd[0] = arun[0] = aadj[0] = 0;
-    for (int i = 0; i < nprob; ++i) {
-      if (!h_active[i]) continue;
-      act[k] = i;
-      afwd[k + 1] = afwd[k] + nfwd[i];
-      arun[k + 1] = arun[k] + (Gs[i].n3 + run - 1) / run;
-      aadj[k + 1] = aadj[k] + nadj[i];
-      ++k;
+    // grouped by the register kernel's shape class (one slab-phase launch per class)
+    for (int c = 0; c < 4; ++c) {
+      B.cls_k[c] = k;
+      for (int i = 0; i < nprob; ++i) {
+        if (!h_active[i]) continue;
+        const int ci = (Gs[i].PT == 1 ? 1 : 0) + (Gs[i].N1T <= 4 ? 2 : 0);
+        if (ci != c) continue;
+        act[k] = i;
+        afwd[k + 1] = afwd[k] + nfwd[i];
+        arun[k + 1] = arun[k] + (Gs[i].n3 + run - 1) / run;
+        aadj[k + 1] = aadj[k] + nadj[i];
+        ++k;
+      }
+      B.cls_runs[c] = arun[k] - arun[B.cls_k[c]];
     }
+    B.cls_k[4] = k;
     B.nact = k;
     B.run = run;
     tot[0] = afwd[k];

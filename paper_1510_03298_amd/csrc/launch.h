@@ -139,6 +139,11 @@ struct BatchParams {
   const int* aoff_run;  // prefix sums of slab runs, ceil(n3 / run) per problem (nact + 1)
   const int* aoff_adj;  // prefix sums of slab_adj tiles (nact + 1)
   int run;              // slabs per run
+  // register-kernel slab phase: the compact list is ordered by shape class (class c = P16 (p1, p2
+  // <= 16) + 2 N1B4 (n1 <= 64)); class c holds entries cls_k[c] .. cls_k[c+1] - 1 and cls_runs[c] runs
+  int cls_k[5];
+  int cls_runs[4];
+  int k0, k1;           // the class of one slab-phase launch
   int* step;            // inner step counter (read by the prox epilogue)
   int wave;             // slabs with the register kernel (S2 in 4-deep k-blocks; batched_wave)
 };

@@ -605,6 +605,8 @@ template <> struct WT<bf16> {
   }
   __device__ static inline v8 pack(const f4v& lo, const f4v& hi) { return pack_acc2(lo, hi); }
   __device__ static inline f4v mma(const v8& a, const v8& b, const f4v& c) { return mma32(a, b, c); }
+  // a contraction whose indices 16..31 are zero: one instruction either way
+  __device__ static inline f4v mma16(const v8& a, const v8& b, const f4v& c) { return mma32(a, b, c); }
   __device__ static inline st from_f32(float x) { return f32_to_bf16(x); }
   __device__ static inline void set(v8& v, int u, st h) { v[u] = __builtin_bit_cast(__bf16, h); }
 };
@@ -621,6 +623,13 @@ template <> struct WT<float> {
   __device__ static inline f4v mma(const v8& a, const v8& b, f4v c) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], c, 0, 0, 0);
+    return c;
+  }
+  // a contraction whose indices 16..31 are zero (slots u >= 4): half the products, the
+  // same sums (the dropped terms are exact zeros added last)
+  __device__ static inline f4v mma16(const v8& a, const v8& b, f4v c) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], c, 0, 0, 0);
     return c;
   }
   __device__ static inline st from_f32(float x) { return x; }
@@ -659,9 +668,18 @@ __global__ void k_pack_wave_image(Geom G, const S* __restrict__ X1, const S* __r
 // Partial NLL sums per workgroup in partials[slab group][2].
 // The slab groups grp .. grp + nrep - 1, group g holding the slabs SPW g .. SPW g + SPW - 1
 // (a whole workgroup of 64 SPW NPART threads); the factor fragments are loaded once for
-// all of them.
-template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
-__device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep = 1) {
+// all of them.  P16: p1, p2 <= 16, so the contractions over p1 or p2 stop at 16 and only
+// the first 16 x 16 tile of T2's rows, S1's columns and S2 is nonzero (the same values,
+// fewer products).  N1B: the row tiles of X1 held in registers (8, or 4 when n1 <= 64, which
+// halves the X1 fragments).  lds: wave_lds_bytes<T, SPW, NPART>() bytes, 16-byte aligned.
+template <typename T, int SPW, int NPART>
+__host__ __device__ constexpr int wave_lds_bytes() {
+  return SPW * 1024 * (int)sizeof(typename WT<T>::st) + (NPART - 1) * SPW * 1024 * 4 +
+         (SPW == 4 ? 4096 * (int)sizeof(typename WT<T>::st) : 0);
+}
+
+template <typename T, int MODE, bool HAS_V, int SPW, int NPART, bool P16, int N1B = 8>
+__device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds, int grp0, int nrep = 1) {
   typedef WT<T> W;
   typedef typename W::v8 V8;
   typedef typename W::st ST;
@@ -678,19 +696,19 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
   const int P12 = G.P12;
   const int N1T = G.N1T, NJB = G.NJB;
   const int jb0 = JPW * part;                     // this wave: column blocks jb0 .. jb0 + JPW - 1
-  __shared__ __align__(16) ST t1s[SPW * 1024];                        // T1 of the slabs (P12 <= 1024)
-  __shared__ __align__(16) float s2p[NPART - 1][SPW][1024];           // S2 partials of parts 1..
-  __shared__ __align__(16) ST s2x[SPW == 4 ? 4096 : 4];               // S2 of 4 slabs, [m][slab]
+  ST* t1s = (ST*)lds;                                                 // T1 of the slabs (P12 <= 1024)
+  float* s2p = (float*)(lds + SPW * 1024 * sizeof(ST));               // S2 partials of parts 1.., [part-1][slab][m]
+  ST* s2x = (ST*)(lds + SPW * 1024 * sizeof(ST) + (NPART - 1) * SPW * 1024 * 4);   // S2 of 4 slabs, [m][slab]
   // factor fragments: requested first, so that their latency overlaps the T1 staging
   const unsigned char* img = (const unsigned char*)P.img + wave_image_offset(G, (int)sizeof(ST));
-  V8 fx2t[JPW], fx1a[8], fx1b[4][2], fx2a[2][QPW];
+  V8 fx2t[JPW], fx1a[N1B], fx1b[N1B / 2][2], fx2a[2][QPW];
   const V8 zf = {};
 #pragma unroll
-  for (int t = 0; t < 8; ++t) fx1a[t] = t < N1T ? W::load(img, 8 + t, lane) : zf;
+  for (int t = 0; t < N1B; ++t) fx1a[t] = t < N1T ? W::load(img, 8 + t, lane) : zf;
 #pragma unroll
   for (int t = 0; t < JPW; ++t) fx2t[t] = jb0 + t < NJB ? W::load(img, jb0 + t, lane) : zf;
 #pragma unroll
-  for (int qq = 0; qq < 4; ++qq)
+  for (int qq = 0; qq < N1B / 2; ++qq)
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) fx1b[qq][nt] = 2 * qq < N1T ? W::load(img, 16 + 2 * qq + nt, lane) : zf;
 #pragma unroll
@@ -721,9 +739,9 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
     double s_nll = 0.0;
     if (active) {
       // the slab's T1 block as the A operand of T2: T1_s[16 mt + r][kw(g, u)]
-      V8 ft1[2];
+      V8 ft1[2] = {};
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
+      for (int mt = 0; mt < (P16 ? 1 : 2); ++mt) {
         const int i1 = 16 * mt + r;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -742,9 +760,10 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
           const int jl = 2 * jq + h, jb = jb0 + jl;
           if (jb >= NJB) break;
           // T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T
-          const V8 ft2 = W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
+          const V8 ft2 = P16 ? W::pack(W::mma16(ft1[0], fx2t[jl], z4), z4)
+                             : W::pack(W::mma(ft1[0], fx2t[jl], z4), W::mma(ft1[1], fx2t[jl], z4));
 #pragma unroll
-          for (int uq = 0; uq < 4; ++uq) {
+          for (int uq = 0; uq < N1B / 2; ++uq) {
             const int u0 = 2 * uq;
             if (u0 >= N1T) break;
             // eta tiles (u0, jb), (u0 + 1, jb) = X1_tile T2; R = eta (.* V)
@@ -755,8 +774,8 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
               yt0 = *(const f4v*)(P.y_tiled + t0);
               if (u0 + 1 < N1T) yt1 = *(const f4v*)(P.y_tiled + t0 + 256);
             }
-            f4v e0 = W::mma(fx1a[u0], ft2, z4);
-            f4v e1 = u0 + 1 < N1T ? W::mma(fx1a[u0 + 1], ft2, z4) : z4;
+            f4v e0 = P16 ? W::mma16(fx1a[u0], ft2, z4) : W::mma(fx1a[u0], ft2, z4);
+            f4v e1 = u0 + 1 < N1T ? (P16 ? W::mma16(fx1a[u0 + 1], ft2, z4) : W::mma(fx1a[u0 + 1], ft2, z4)) : z4;
             if (HAS_V) {
               const long long t0 = (((long long)i3 * NJB + jb) * N1T + u0) * 256 + r * 16 + 4 * g;
               const f4v v0 = *(const f4v*)(V + t0);
@@ -793,17 +812,17 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
               // S1^T (16 x p1) += R^T (16 x 32) X1 (32 x p1)
               const V8 fr = W::pack(e0, e1);
               s1[h][0] = W::mma(fr, fx1b[uq][0], s1[h][0]);
-              s1[h][1] = W::mma(fr, fx1b[uq][1], s1[h][1]);
+              if (!P16) s1[h][1] = W::mma(fr, fx1b[uq][1], s1[h][1]);
             }
           }
         }
         // S2^T (p2 x p1) += X2^T (p2 x 32) S1^T (32 x p1)
         if (ADJ) {
 #pragma unroll
-          for (int nt = 0; nt < 2; ++nt) {
+          for (int nt = 0; nt < (P16 ? 1 : 2); ++nt) {
             const V8 fs = W::pack(s1[0][nt], s1[1][nt]);
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
+            for (int mt = 0; mt < (P16 ? 1 : 2); ++mt) s2[mt][nt] = W::mma(fx2a[mt][jq], fs, s2[mt][nt]);
           }
         }
       }
@@ -830,7 +849,7 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
-            if (i1 < G.p1 && i2 < G.p2) s2p[part - 1][sw][i1 + G.p1 * i2] = s2[mt][nt][i];
+            if (i1 < G.p1 && i2 < G.p2) s2p[((part - 1) * SPW + sw) * 1024 + i1 + G.p1 * i2] = s2[mt][nt][i];
           }
     }
     __syncthreads();
@@ -848,7 +867,7 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
               const int m = i1 + G.p1 * i2;
               float v = s2[mt][nt][i];
 #pragma unroll
-              for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[pp][sw][m];
+              for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[(pp * SPW + sw) * 1024 + m];
               if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
               else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
             }
@@ -863,13 +882,14 @@ __device__ inline void wave_chain_group(const SlabParams& P, int grp0, int nrep 
   }
 }
 
-template <typename T, int MODE, bool HAS_V, int SPW, int NPART>
+template <typename T, int MODE, bool HAS_V, int SPW, int NPART, bool P16>
 __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
+  __shared__ __align__(16) unsigned char lds[wave_lds_bytes<T, SPW, NPART>()];
   // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
   // the chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
   const int b = blockIdx.x, x = b & 7, jj = b >> 3;
   const int grp = SPW == 4 ? 8 * (x + 8 * (jj >> 3)) + (jj & 7) : 4 * (x + 8 * (jj >> 2)) + (jj & 3);
-  wave_chain_group<T, MODE, HAS_V, SPW, NPART>(P, grp);
+  wave_chain_group<T, MODE, HAS_V, SPW, NPART, P16>(P, lds, grp);
 }
 
 // ============================================================================
@@ -1050,18 +1070,6 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
       const int loc = item - B.aoff_fwd[k];
       fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
     }
-  } else if constexpr (PH == 1 && WAVE) {
-    // one run per item with the one-wave-per-part register kernel (4 waves per slab)
-    const int totB = B.aoff_run[B.nact];
-    for (int item = blockIdx.x; item < totB; item += gridDim.x) {
-      const int k = find_segment(B.aoff_run, B.nact, item);
-      const BatchDesc& D = B.desc[B.act[k]];
-      const int s0 = (item - B.aoff_run[k]) * B.run;
-      const int nrep = min(B.run, D.sp.G.n3 - s0);
-      if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4>(D.sp, s0, nrep);
-      else wave_chain_group<T, SM_FUSED, false, 1, 4>(D.sp, s0, nrep);
-      __syncthreads();   // LDS of the next item
-    }
   } else if constexpr (PH == 1) {
     // contiguous stretches of runs per workgroup: the LDS image is restaged only when the
     // problem changes
@@ -1097,6 +1105,26 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
       // partials at the problem's own offset (read per problem by k_segment_max)
       adj_tile<T, EPI_PROX>(D.ap, loc % D.adj_gx, loc / D.adj_gx, B.off_adj[pb] + loc);
     }
+  }
+}
+
+// PH 1 with the one-wave-per-slab register kernel, for the active problems B.k0 .. B.k1 - 1 of
+// the compact list (one shape class: P16 when p1, p2 <= 16, N1B = 4 when n1 <= 64), one run
+// per item; each class is its own launch, so that it gets the registers its shape needs.
+// At least two waves per SIMD: the FP32 class with p > 16 and n1 > 64 otherwise takes 272
+// registers (one wave per SIMD); held to 256 it spills 4 and C4 ran 8% faster.
+template <typename T, bool P16, int N1B>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_batched_slabs(BatchParams B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];   // wave_lds_bytes<T, 1, 4>()
+  const int r0 = B.aoff_run[B.k0], r1 = B.aoff_run[B.k1];
+  for (int item = r0 + blockIdx.x; item < r1; item += gridDim.x) {
+    const int k = B.k0 + find_segment(B.aoff_run + B.k0, B.k1 - B.k0, item);
+    const BatchDesc& D = B.desc[B.act[k]];
+    const int s0 = (item - B.aoff_run[k]) * B.run;
+    const int nrep = min(B.run, D.sp.G.n3 - s0);
+    if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4, P16, N1B>(D.sp, smem_raw, s0, nrep);
+    else wave_chain_group<T, SM_FUSED, false, 1, 4, P16, N1B>(D.sp, smem_raw, s0, nrep);
+    __syncthreads();   // LDS of the next item
   }
 }
 
@@ -1296,17 +1324,24 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
     const bool four = dt == DT_BF16 && 4 * ((P.G.n3 + 3) / 4) >= 3 * num_cus();
     if (nblk_out) *nblk_out = four ? (P.G.n3 + 3) / 4 : P.G.n3;
     const dim3 g4(64 * ((P.G.n3 + 255) / 256)), g1(32 * ((P.G.n3 + 31) / 32));
-#define GLAM_WAVE(M, V)                                                                                    \
-    do {                                                                                                   \
-      if (dt == DT_F32) hipLaunchKernelGGL((k_slab_chain_w<float, M, V, 1, 4>), g1, dim3(256), 0, s, P);    \
-      else if (four) hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 4, 2>), g4, dim3(512), 0, s, P);       \
-      else hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 1, 4>), g1, dim3(256), 0, s, P);                 \
+    const bool p16 = P.G.PT == 1;   // p1, p2 <= 16: the shorter contractions
+#define GLAM_WAVE2(M, V, Q)                                                                                   \
+    do {                                                                                                      \
+      if (dt == DT_F32) hipLaunchKernelGGL((k_slab_chain_w<float, M, V, 1, 4, Q>), g1, dim3(256), 0, s, P);    \
+      else if (four) hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 4, 2, Q>), g4, dim3(512), 0, s, P);       \
+      else hipLaunchKernelGGL((k_slab_chain_w<bf16, M, V, 1, 4, Q>), g1, dim3(256), 0, s, P);                 \
+    } while (0)
+#define GLAM_WAVE(M, V)                      \
+    do {                                     \
+      if (p16) GLAM_WAVE2(M, V, true);       \
+      else GLAM_WAVE2(M, V, false);          \
     } while (0)
     if (mode == SM_NLL_FWD) GLAM_WAVE(SM_NLL_FWD, false);
     else if (mode == SM_NLL_BWD) GLAM_WAVE(SM_NLL_BWD, false);
     else if (P.v_int) GLAM_WAVE(SM_FUSED, true);
     else GLAM_WAVE(SM_FUSED, false);
 #undef GLAM_WAVE
+#undef GLAM_WAVE2
     return hipGetLastError();
   }
   const int PT = P.G.PT;
@@ -1348,8 +1383,21 @@ static hipError_t batched_phases(const BatchParams& B, const int* tot, size_t ld
   const int gB = std::max(1, std::min(tot[1], WAVE ? cap : 4 * num_cus()));
   const int gC = std::max(1, std::min(tot[2], cap));
   hipLaunchKernelGGL((k_batched_phase<T, 0, WAVE>), dim3(gA), dim3(WG), 0, s, B);
-  if (WAVE) {
-    hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(gB), dim3(WG), 0, s, B);
+  if constexpr (WAVE) {
+    // one launch per shape class present (class c: P16 = c & 1, N1B = c & 2 ? 4 : 8)
+    constexpr size_t wl = (size_t)wave_lds_bytes<T, 1, 4>();
+    for (int c = 0; c < 4; ++c) {
+      if (B.cls_runs[c] == 0) continue;
+      BatchParams Bc = B;
+      Bc.k0 = B.cls_k[c];
+      Bc.k1 = B.cls_k[c + 1];
+      const dim3 gc(std::max(1, std::min(B.cls_runs[c], cap)));
+      if (c == 0) hipLaunchKernelGGL((k_batched_slabs<T, false, 8>), gc, dim3(WG), wl, s, Bc);
+      else if (c == 1) hipLaunchKernelGGL((k_batched_slabs<T, true, 8>), gc, dim3(WG), wl, s, Bc);
+      else if (c == 2) hipLaunchKernelGGL((k_batched_slabs<T, false, 4>), gc, dim3(WG), wl, s, Bc);
+      else hipLaunchKernelGGL((k_batched_slabs<T, true, 4>), gc, dim3(WG), wl, s, Bc);
+    }
+    (void)gB;
   } else {
     set_lds(k_batched_phase<T, 1, WAVE>, lds);
     hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(gB), dim3(WG), lds, s, B);
