@@ -357,6 +357,7 @@ def main():
         "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
         "frac": (achieved / PEAKS[args.dtype]) if achieved else None,
         "traffic": traffic_per_launch("slab_chain", args.dtype),
+        "kernel_source_sha256_16": kernel_source_hash(),
         "flops_per_launch": chain, "launches_sampled": samples,
         "avg_launch_us": avg_chain * 1e6,
         "algorithmic_bytes_per_launch": chain_bytes(n, p, dtb),
