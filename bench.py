@@ -88,6 +88,7 @@ def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slab_chain_gaussian_100x100x1000_bf16_hbm_traffic.txt")
+STATS_FILE = os.path.join(ROOT, "profiles", "gaussian_path_100x100x1000_bf16_kernel_stats.txt")
 
 
 def kernel_source_hash():
@@ -110,6 +111,18 @@ def traffic_per_launch(kernel, dtype):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def rocprof_chain_durations():
+    """The slab_chain durations of the committed rocprofv3 kernel trace (same command): the
+    sampled back-to-back re-launches this roofline times, and the launches inside the path;
+    None when that trace was taken on a different kernel source."""
+    try:
+        with open(STATS_FILE) as fh:
+            rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    except (OSError, IndexError, ValueError):
+        return None
+    return rec if rec.get("source_sha256_16") == kernel_source_hash() else None
 
 
 def copy_calibration(torch, dev, mib):
@@ -352,7 +365,10 @@ def main():
     roofline = {
         "kernel": "slab_chain (fused modes 1-2 forward + adjoint of one inner PG iteration)",
         "timing": ("HIP events on the fit's stream around 8 back-to-back re-launches of the kernel on the "
-                   "sampled iteration's own input, one sample per profile_every inner iterations"),
+                   "sampled iteration's own input, one sample per profile_every inner iterations; the committed "
+                   "rocprofv3 trace of the same command gives these launches' own durations "
+                   "(rocprof_sampled_avg_us) and those of the launches inside the path (rocprof_in_path_avg_us, "
+                   "colder caches after the adjoint's traffic; frac_in_path uses it)"),
         "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
         "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
         "frac": (achieved / PEAKS[args.dtype]) if achieved else None,
@@ -364,6 +380,10 @@ def main():
         "inner_iteration_us": avg_iter * 1e6,
         "inner_iteration_tflops": (fwd3 + chain + adj3) / avg_iter / 1e12 if samples else None,
     }
+    rp = rocprof_chain_durations() if args.dtype == "bf16" else None
+    roofline["rocprof_sampled_avg_us"] = rp["slab_chain_sampled_avg_us"] if rp else None
+    roofline["rocprof_in_path_avg_us"] = rp["slab_chain_in_path_avg_us"] if rp else None
+    roofline["frac_in_path"] = (chain / (rp["slab_chain_in_path_avg_us"] * 1e-6) / PEAKS[args.dtype]) if rp else None
     forms = {args.dtype: {"seconds": sec, "inner": int(np.mean([r.inner_total for r in results])),
                           "outer": int(np.mean([r.iters_outer.sum() for r in results])),
                           "max_kkt": float(max(np.max(r.kkt) for r in results)), "ok": ok}}
