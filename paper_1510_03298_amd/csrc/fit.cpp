@@ -28,6 +28,8 @@
 #include <functional>
 #include <string>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "glam.h"
@@ -105,6 +107,7 @@ static const double kEps[3] = {1.1102230246251565e-16, 5.960464477539063e-08, 3.
 struct Arena {
   static constexpr size_t kDevChunk = (size_t)32 << 20, kHostChunk = (size_t)256 << 10;
   std::vector<void*> dev, host;
+  std::mutex mu;   // the fits of a batch are set up from several host threads
   char* dcur = nullptr;
   size_t dleft = 0;
   char *hcur = nullptr, *hdcur = nullptr;   // host chunk and its device-side address
@@ -119,6 +122,7 @@ struct Arena {
   static size_t round_up(size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; }
   // 256-byte aligned device buffer, or NULL
   void* dev_alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lock(mu);
     bytes = round_up(bytes);
     if (bytes > dleft) {
       void* p = nullptr;
@@ -136,6 +140,7 @@ struct Arena {
   }
   // 256-byte aligned pinned host buffer (mapped, coherent) and its device address, or NULL
   void* host_alloc(size_t bytes, void** dev_addr) {
+    std::lock_guard<std::mutex> lock(mu);
     bytes = round_up(bytes);
     if (bytes > hleft) {
       const size_t sz = std::max(bytes, kHostChunk);
@@ -1274,11 +1279,40 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
 
   // one arena for the whole batch; every set-up is queued before one synchronisation
   std::shared_ptr<Arena> arena = std::make_shared<Arena>();
+  std::vector<std::unique_ptr<Fit>>* fits_ref = nullptr;
+  // fn(i) for every problem i, the problems of pool stream k enqueued by host thread k: the
+  // per-problem outer steps are thousands of small launches, and submitting them from one
+  // thread left the GPU idle most of the time.  fn returns a status (message in the fit's err);
+  // the failure of the lowest problem index is reported.
+  auto for_each_problem = [&](const std::function<int(int)>& fn) -> int {
+    std::vector<int> bad(npool, -1), code(npool, GLAM_OK);
+    auto work = [&](int k) {
+      for (int i = k; i < nprob; i += npool) {
+        const int r = fn(i);
+        if (r) { bad[k] = i; code[k] = r; return; }
+      }
+    };
+    std::vector<std::thread> th;
+    int k = 1;
+    try {
+      for (; k < npool; ++k) th.emplace_back(work, k);
+    } catch (...) {   // no more threads: the rest on this one
+      for (; k < npool; ++k) work(k);
+    }
+    work(0);
+    for (auto& t : th) t.join();
+    int first = -1, c = GLAM_OK;
+    for (int q = 0; q < npool; ++q)
+      if (bad[q] >= 0 && (first < 0 || bad[q] < first)) { first = bad[q]; c = code[q]; }
+    if (first >= 0) return fit_fail(c, "problem " + std::to_string(first) + ": " + (*fits_ref)[first]->err);
+    return GLAM_OK;
+  };
   struct SyncGuard {   // every stream idle before the arena goes (on early returns too)
     std::function<hipError_t()> f;
     ~SyncGuard() { (void)f(); }
   } syncg{sync_all};
   std::vector<std::unique_ptr<Fit>> fits(nprob);
+  fits_ref = &fits;
   std::vector<Geom> Gs(nprob);
   for (int i = 0; i < nprob; ++i) {
     fits[i].reset(new Fit());
@@ -1290,13 +1324,13 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     F.own_stream = false;
     F.batched = true;
     F.enet = opt->alpha;
-    const int r = fit_setup_enqueue(F, &probs[i], false, false);
-    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + F.err);
   }
-  if (sync_all() != hipSuccess) return fit_fail(GLAM_EDEVICE, "set-up failed");
-  for (int i = 0; i < nprob; ++i) {
-    const int r = fit_setup_finish(*fits[i]);
-    if (r) return fit_fail(r, "problem " + std::to_string(i) + ": " + fits[i]->err);
+  {
+    int r = for_each_problem([&](int i) { return fit_setup_enqueue(*fits[i], &probs[i], false, false); });
+    if (r) return r;
+    if (sync_all() != hipSuccess) return fit_fail(GLAM_EDEVICE, "set-up failed");
+    r = for_each_problem([&](int i) { return fit_setup_finish(*fits[i]); });
+    if (r) return r;
   }
   // batch bookkeeping
   std::vector<int> nfwd(nprob), nadj(nprob), off_adj(nprob + 1, 0);
@@ -1411,11 +1445,13 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
 
   // lambda_max_i and lambda_i (every problem's step 2 at theta = 0 before one synchronisation)
   std::vector<double> lam(nprob), lmax(nprob), scale(nprob);
-  for (int i = 0; i < nprob; ++i) {
-    Fit& F = *fits[i];
-    BCHK(launch_fill(F.theta, Gs[i].p, 0.0, F.s));
-    const int r = family_enqueue(F, F.theta, 0.0);
-    if (r) return fit_fail(r, F.err);
+  {
+    const int r = for_each_problem([&](int i) -> int {
+      Fit& F = *fits[i];
+      if (launch_fill(F.theta, Gs[i].p, 0.0, F.s) != hipSuccess) { F.err = "fill kernel failed"; return GLAM_EDEVICE; }
+      return family_enqueue(F, F.theta, 0.0);
+    });
+    if (r) return r;
   }
   BCHK(sync_all());
   for (int i = 0; i < nprob; ++i) {
@@ -1443,10 +1479,9 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   for (int round = 0; round <= opt->max_outer; ++round) {
     int nact = 0;
     // step 2 of Algorithm 1 for every unfinished problem, one stream synchronisation
-    for (int i = 0; i < nprob; ++i) {
-      if (done[i]) continue;
-      const int r = family_enqueue(*fits[i], fits[i]->theta, lam[i]);
-      if (r) return fit_fail(r, fits[i]->err);
+    {
+      const int r = for_each_problem([&](int i) { return done[i] ? GLAM_OK : family_enqueue(*fits[i], fits[i]->theta, lam[i]); });
+      if (r) return r;
     }
     BCHK(sync_all());
     for (int i = 0; i < nprob; ++i) {
@@ -1511,27 +1546,33 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     }
     // step 5 of Algorithm 1 per problem: Armijo along theta~ - theta^k (theta~ = x^l of the
     // last check); the first pass of every problem is enqueued before one synchronisation
-    for (int i = 0; i < nprob; ++i) {
-      if (!in_round[i]) continue;
-      Fit& F = *fits[i];
-      if (exact[i]) {   // Sec. 6.5: no outer loop for the exact model (alpha = 1)
-        BCHK(hipMemcpyAsync(F.theta, F.xp, Gs[i].p * 8, hipMemcpyDeviceToDevice, F.s));
-        continue;
-      }
-      BCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, F.s));
-      const int r = armijo_enqueue(F, 0);
-      if (r) return fit_fail(r, F.err);
+    {
+      const int r = for_each_problem([&](int i) -> int {
+        if (!in_round[i]) return GLAM_OK;
+        Fit& F = *fits[i];
+        if (exact[i]) {   // Sec. 6.5: no outer loop for the exact model (alpha = 1)
+          FCHK(hipMemcpyAsync(F.theta, F.xp, Gs[i].p * 8, hipMemcpyDeviceToDevice, F.s));
+          return GLAM_OK;
+        }
+        FCHK(launch_sub(Gs[i].p, F.xp, F.theta, F.dvec, F.s));
+        return armijo_enqueue(F, 0);
+      });
+      if (r) return r;
     }
     BCHK(sync_all());
-    for (int i = 0; i < nprob; ++i) {
-      if (!in_round[i] || exact[i]) continue;
-      Fit& F = *fits[i];
-      double alpha = 0.0, Delta = 0.0;
-      if (!armijo_decide(F, 0, lam[i], 0.1, &alpha, &Delta)) {
-        const int r = armijo_finish(F, lam[i], 0.1, true, &alpha, &Delta);
-        if (r) return fit_fail(r, F.err);
-      }
-      if (alpha > 0.0) BCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, F.s));
+    {
+      const int r = for_each_problem([&](int i) -> int {
+        if (!in_round[i] || exact[i]) return GLAM_OK;
+        Fit& F = *fits[i];
+        double alpha = 0.0, Delta = 0.0;
+        if (!armijo_decide(F, 0, lam[i], 0.1, &alpha, &Delta)) {
+          const int r2 = armijo_finish(F, lam[i], 0.1, true, &alpha, &Delta);
+          if (r2) return r2;
+        }
+        if (alpha > 0.0) FCHK(launch_axpy(Gs[i].p, alpha, F.dvec, F.theta, F.s));
+        return GLAM_OK;
+      });
+      if (r) return r;
     }
   }
   int worst = GLAM_OK;

@@ -1233,12 +1233,12 @@ hipError_t launch_pack_chain_image(int dt, int src_dt, const Geom& G, const void
 // launchers
 // ============================================================================
 static int num_cus() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      n = 256;
-  }
+  static const int n = [] {   // initialised once, thread-safely (host threads launch concurrently)
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    return c;
+  }();
   return n;
 }
 
