@@ -1054,8 +1054,9 @@ __device__ inline int find_segment(const int* off, int nseg, int item) {
 // Work items come from compact lists over the active problems (act, with prefix sums of
 // each phase's items), rebuilt by the host when the active set changes.
 // PH 0: mode-3 forward GEMM tiles of every active problem (and the step counter l)
-// PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem in runs of
-//       B.run consecutive slabs, so that the factor operands are loaded once per run
+// PH 1: the slabs (modes 1-2 forward and adjoint) of every active problem with the
+//       workgroup-per-slab LDS kernel (FP64, or shapes beyond the register kernel); with the
+//       register kernel this phase is k_batched_slabs, one launch per shape class
 // PH 2: mode-3 adjoint tiles + proximal step of every active problem
 template <typename T, int PH, bool WAVE>
 __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
