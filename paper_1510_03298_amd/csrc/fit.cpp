@@ -1259,7 +1259,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   // Each problem's own work (set-up, FP64 steps 2 and 5 of Algorithm 1) goes to one of a few
   // streams, so that the small per-problem kernels of different problems overlap; the batched
   // inner steps run on s.  The host synchronises every stream between the phases.
-  constexpr int kPoolStreams = 4;
+  constexpr int kPoolStreams = 8;
   struct PoolGuard {
     hipStream_t p[kPoolStreams] = {};
     ~PoolGuard() { for (hipStream_t q : p) if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); } }
