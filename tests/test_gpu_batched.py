@@ -137,3 +137,21 @@ def test_batched_mode_order_chosen_by_the_library(fam, dt):
     assert abs(r1.lambda_max[0] - lm) <= 1e-12 * lm
     g = O.smooth_gradient(fam, Xs, a, Y)
     assert O.kkt_residual(a, g, 0.1 * lm, lm) <= 1e-7
+
+
+def test_batched_f32_lds_slab_path():
+    """A batch with one problem beyond the register kernel (n_1 = 150 > 128) runs every slab phase
+    on the workgroup-per-slab LDS kernel in FP32: each problem's KKT by the oracle."""
+    torch, glam = need_gpu()
+    probs = inputs.config_c4(nprob=2, lo=16, hi=30, seed_offset=44)
+    big = inputs.random_problem((150, 20, 24), (12, 8, 6), family="poisson", seed=45, scale=0.3)
+    ups = [_upload(glam, d) for d in probs] + [{"X": [glam.to_device_colmajor(X, 0) for X in big.X],
+                                                "Y": glam.to_device_colmajor(big.Y, 0), "n": big.n, "p": big.p,
+                                                "family": "poisson"}]
+    print("batched f32 lds path", flush=True)
+    res = glam.fit_batched(ups, lambda_ratio=0.1, dtype=1, kkt_tol=1e-6)
+    assert res.code == 0 and np.all(res.status == 0)
+    for i, (X, Y, p, fam) in enumerate([(d.X, d.Y, d.p, d.family) for d in probs] + [(big.X, big.Y, big.p, "poisson")]):
+        lm = O.lambda_max(fam, X, Y)
+        th = glam.from_colmajor(res.theta[i], p)
+        assert O.kkt_residual(th, O.smooth_gradient(fam, X, th, Y), 0.1 * lm, lm) <= 1e-6, i
