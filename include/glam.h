@@ -67,8 +67,10 @@ const char* glam_last_error(void);
 /* Library version string, e.g. "glam-mi355x 0.1.0 (gfx950)". */
 const char* glam_version(void);
 
-/* Limits of the fused slab kernels: modes 1 and 2 must satisfy
- * p_j <= GLAM_MAX_INNER_P and n_j <= GLAM_MAX_INNER_N (mode 3 is unrestricted).
+/* Limits of the fused slab kernels: the two modes they contract in registers/LDS (modes 1
+ * and 2 of the order that runs) must satisfy p_j <= GLAM_MAX_INNER_P and n_j <=
+ * GLAM_MAX_INNER_N (the third is unrestricted).  The rho entry points and both fits run a
+ * problem whose own order does not fit in an order that does, when one exists.
  * d = 2 (Sec. 6.4: the package fits d = 2 and d = 3): X_2 (x) X_1 is taken as the d = 3 model
  * X_2 (x) [1] (x) X_1 with a 1 x 1 middle factor, which keeps every array's vec layout; then
  * mode 1 has the limits above and mode 2 is unrestricted. */
@@ -79,7 +81,10 @@ const char* glam_version(void);
  * rho transforms (App. A; Sec. 6.1 eqs. eighteen and nineteen, c = 1)
  * ------------------------------------------------------------------------- */
 
-/* Bytes of device workspace the rho entry points need for these sizes/dtype. */
+/* Bytes of device workspace the rho entry points need for these sizes/dtype (0: the sizes are
+ * refused; glam_last_error says why).  When modes 1-2 of the caller's order do not fit the slab
+ * kernels, the transforms run in a mode order that does (the largest remaining n last) and the
+ * workspace also holds the permuted input and output (n + p elements of 8 bytes). */
 size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype);
 
 /* Eta = H(<X_j>, Theta) = rho(X_3, rho(X_2, rho(X_1, Theta)))  (eq. eighteen).
@@ -88,8 +93,10 @@ size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dt
  *   Theta    : device, p_1 x ... x p_d of `dtype`.
  *   Eta      : device, n_1 x ... x n_d; FP64 for GLAM_F64, FP32 otherwise.
  *   workspace: device, >= glam_rho_workspace_size(...) bytes, 256-byte aligned.
- * Errors: GLAM_EINVAL for d not 2 or 3, sizes < 1 or beyond the inner-mode limits,
- * NULL pointers, a bad dtype or a too-small workspace. */
+ * The mode products commute, so a reordered run (see glam_rho_workspace_size) gives the
+ * same transform; Theta is permuted into the workspace and Eta back out of it.
+ * Errors: GLAM_EINVAL for d not 2 or 3, sizes < 1, sizes no mode order fits, NULL
+ * pointers, a bad dtype or a too-small workspace. */
 int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X,
                      const void* Theta, void* Eta, int dtype, void* workspace,
                      size_t ws_bytes, void* stream);
@@ -98,7 +105,7 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
  * i.e. vec(Out) = X^T vec(U).
  *   U   : device, n_1 x n_2 x n_3 of `dtype`.
  *   Out : device, p_1 x p_2 x p_3; FP64 for GLAM_F64, FP32 otherwise.
- * Other arguments and errors as glam_rho_forward. */
+ * Other arguments, reordering (U permuted in, Out back) and errors as glam_rho_forward. */
 int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X,
                      const void* U, void* Out, int dtype, void* workspace,
                      size_t ws_bytes, void* stream);
@@ -256,6 +263,7 @@ int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_opti
  * a = 1, log y! dropped): L(beta) = (1/n) sum_i (exp(eta_i) - y_i eta_i),
  * eta = H(<X_j>, beta); grad L = G(<X_j>, exp(eta) - y) / n.
  * ------------------------------------------------------------------------- */
+/* The NLL entry points take the caller's mode order as given (no reordering). */
 size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype);
 
 /* loss (device, one FP64) = L(beta).  X and beta of `dtype`; Y FP64 counts. */

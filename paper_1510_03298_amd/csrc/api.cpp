@@ -48,28 +48,87 @@ Geom make_geom(const int64_t* n, const int64_t* p) {
 
 static const size_t kMaxLds = 159 * 1024;   // 160 KB per CU minus static LDS
 
-// Common size validation of the rho-based entry points.
-static int check_sizes(int d, const int64_t* n_in, const int64_t* p_in, int dtype, Geom* Gout) {
+// Size checks shared by the rho-based entry points; n, p: the lifted (d = 3) sizes.
+static int check_basic(int d, const int64_t* n_in, const int64_t* p_in, int dtype, int64_t* n, int64_t* p) {
   if (d != 2 && d != 3) return fail(GLAM_EINVAL, "d must be 2 or 3");
   if (!n_in || !p_in) return fail(GLAM_EINVAL, "NULL size array");
   for (int j = 0; j < d; ++j)
     if (n_in[j] < 1 || p_in[j] < 1) return fail(GLAM_EINVAL, "mode sizes must be >= 1");
-  int64_t n[3], p[3];
   lift_sizes(d, n_in, p_in, n, p);
   for (int j = 0; j < 3; ++j) {
     if (n[j] < 1 || p[j] < 1) return fail(GLAM_EINVAL, "mode sizes must be >= 1");
     if (n[j] > (1 << 30) || p[j] > (1 << 30)) return fail(GLAM_EINVAL, "mode size too large");
   }
   if (dtype < 0 || dtype > 2) return fail(GLAM_EINVAL, "bad dtype");
-  if (p[0] > GLAM_MAX_INNER_P || p[1] > GLAM_MAX_INNER_P)
-    return fail(GLAM_EINVAL, "p_1 and p_2 must be <= GLAM_MAX_INNER_P");
-  if (n[0] > GLAM_MAX_INNER_N || n[1] > GLAM_MAX_INNER_N)
-    return fail(GLAM_EINVAL, "n_1 and n_2 must be <= GLAM_MAX_INNER_N");
+  return GLAM_OK;
+}
+
+// Whether modes 1 and 2 of (n, p) in this order fit the slab kernels (why: the reason if not).
+static bool inner_fit(const int64_t* n, const int64_t* p, int dtype, Geom* Gout, std::string* why) {
+  if (p[0] > GLAM_MAX_INNER_P || p[1] > GLAM_MAX_INNER_P) { *why = "p_1 and p_2 must be <= GLAM_MAX_INNER_P"; return false; }
+  if (n[0] > GLAM_MAX_INNER_N || n[1] > GLAM_MAX_INNER_N) { *why = "n_1 and n_2 must be <= GLAM_MAX_INNER_N"; return false; }
   Geom G = make_geom(n, p);
-  if ((long long)G.n3 * G.P12 > (1LL << 40)) return fail(GLAM_EINVAL, "problem too large");
-  if (slab_chain_lds_bytes(dtype, G) > kMaxLds)
-    return fail(GLAM_EINVAL, "modes 1-2 too large for the slab kernel's LDS budget (n_1, n_2 too big for this dtype)");
+  if ((long long)G.n3 * G.P12 > (1LL << 40)) { *why = "problem too large"; return false; }
+  if (slab_chain_lds_bytes(dtype, G) > kMaxLds) {
+    *why = "modes 1-2 too large for the slab kernel's LDS budget (n_1, n_2 too big for this dtype)";
+    return false;
+  }
   *Gout = G;
+  return true;
+}
+
+// Whether a lifted (d = 3) problem fits the slab kernels in the given order (no reordering):
+// the fits decide their own mode order with it.
+bool rho_order_fits(const int64_t* n, const int64_t* p, int dtype, std::string* why) {
+  int64_t nl[3], pl[3];
+  if (check_basic(3, n, p, dtype, nl, pl) != GLAM_OK) {
+    if (why) *why = g_err;
+    return false;
+  }
+  Geom G;
+  std::string w;
+  const bool ok = inner_fit(nl, pl, dtype, &G, &w);
+  if (!ok && why) *why = w;
+  return ok;
+}
+
+// The NLL entry points: the caller's mode order only.
+static int check_sizes(int d, const int64_t* n_in, const int64_t* p_in, int dtype, Geom* Gout) {
+  int64_t n[3], p[3];
+  const int st = check_basic(d, n_in, p_in, dtype, n, p);
+  if (st) return st;
+  std::string why;
+  if (!inner_fit(n, p, dtype, Gout, &why)) return fail(GLAM_EINVAL, why);
+  return GLAM_OK;
+}
+
+// A rho problem and the mode order it runs in: position k holds the caller's (lifted) mode q[k].
+// The caller's order when it fits the slab kernels; otherwise the fitting order with the
+// largest n last (inputs and outputs are then permuted through the workspace).
+struct RhoPlan {
+  Geom G;                 // geometry of the order that runs
+  int q[3] = {0, 1, 2};
+  bool perm = false;
+  int64_t n[3], p[3];     // lifted sizes in the caller's order
+};
+static int plan_rho(int d, const int64_t* n_in, const int64_t* p_in, int dtype, RhoPlan* R) {
+  int st = check_basic(d, n_in, p_in, dtype, R->n, R->p);
+  if (st) return st;
+  std::string why;
+  if (inner_fit(R->n, R->p, dtype, &R->G, &why)) return GLAM_OK;
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 2, 0}, {1, 0, 2}, {2, 0, 1}, {2, 1, 0}};
+  int best = -1;
+  for (int c = 1; c < 6; ++c) {
+    int64_t n[3], p[3];
+    for (int k = 0; k < 3; ++k) { n[k] = R->n[perms[c][k]]; p[k] = R->p[perms[c][k]]; }
+    Geom G;
+    std::string w;
+    if (!inner_fit(n, p, dtype, &G, &w)) continue;
+    if (best < 0 || n[2] > R->n[perms[best][2]]) { best = c; R->G = G; }
+  }
+  if (best < 0) return fail(GLAM_EINVAL, why + " (in every order of the modes)");
+  R->perm = true;
+  for (int k = 0; k < 3; ++k) R->q[k] = perms[best][k];
   return GLAM_OK;
 }
 
@@ -126,10 +185,18 @@ const char* glam_last_error(void) { return g_err.c_str(); }
 
 const char* glam_version(void) { return "glam-mi355x 0.1.0 (gfx950)"; }
 
+// rho workspace: the layout of the order that runs, then (reordered problems) an n-sized and
+// a p-sized region of 8-byte elements for the permuted input and output
+static size_t rho_ws_total(const RhoPlan& R, int dtype) {
+  size_t t = ws_layout(R.G, dtype).total;
+  if (R.perm) t += align256((size_t)R.G.n * 8) + align256((size_t)R.G.p * 8);
+  return t;
+}
+
 size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype) {
-  Geom G;
-  if (check_sizes(d, n, p, dtype, &G) != GLAM_OK) return 0;
-  return ws_layout(G, dtype).total;
+  RhoPlan R;
+  if (plan_rho(d, n, p, dtype, &R) != GLAM_OK) return 0;
+  return rho_ws_total(R, dtype);
 }
 
 // the factor list of the lifted d = 3 model (d = 2: the middle factor is a 1 in the workspace)
@@ -145,21 +212,32 @@ static int lift_factors(int d, const void* const* X, char* ws, const WsLayout& W
   return GLAM_OK;
 }
 
-int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* Theta, void* Eta,
+int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* Theta_in, void* Eta_out,
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
-  Geom G;
-  int st = check_sizes(d, n, p, dtype, &G);
+  RhoPlan R;
+  int st = plan_rho(d, n, p, dtype, &R);
   if (st) return st;
-  if (!Theta || !Eta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
-  if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  const Geom& G = R.G;
+  if (!Theta_in || !Eta_out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const WsLayout W = ws_layout(G, dtype);
   char* ws = (char*)workspace;
-  const void* X[3];
-  st = lift_factors(d, X_in, ws, W, dtype, s, X);
+  const void* Xl[3];
+  st = lift_factors(d, X_in, ws, W, dtype, s, Xl);
   if (st) return st;
-  const size_t es = dt_size(dtype);
+  const void* X[3] = {Xl[R.q[0]], Xl[R.q[1]], Xl[R.q[2]]};
+  const size_t es = dt_size(dtype), oes = dtype == DT_F64 ? 8 : 4;
+  const void* Theta = Theta_in;
+  void* Eta = Eta_out;
+  char* reg_n = ws + W.total;                             // eta in the order that runs
+  char* reg_p = reg_n + align256((size_t)G.n * 8);        // Theta in that order
+  if (R.perm) {
+    HIPCHK(launch_permute3_es((int)es, Theta_in, reg_p, R.p, R.q, s));
+    Theta = reg_p;
+    Eta = reg_n;
+  }
   HIPCHK(launch_pack(dtype, dtype, Theta, G.p3, G.P12, G.P12, 1, ws + W.inc, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
   FwdParams F{};
@@ -169,24 +247,41 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
   HIPCHK(launch_pack_chain_image(dtype, dtype, G, X[0], X[1], ws + W.img, s, chain_image_need(dtype, SM_FWD_STD, G)));
   S.G = G; S.img = ws + W.img; S.T1 = ws + W.t1; S.eta_out = Eta;
   HIPCHK(launch_slab_chain(dtype, SM_FWD_STD, S, nullptr, s));
+  if (R.perm) {   // back to the caller's order
+    int qi[3];
+    for (int k = 0; k < 3; ++k) qi[R.q[k]] = k;
+    const int64_t nr[3] = {G.n1, G.n2, G.n3};
+    HIPCHK(launch_permute3_es((int)oes, reg_n, Eta_out, nr, qi, s));
+  }
   return GLAM_OK;
 }
 
-int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* U, void* Out,
+int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* U_in, void* Out_p,
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
-  Geom G;
-  int st = check_sizes(d, n, p, dtype, &G);
+  RhoPlan R;
+  int st = plan_rho(d, n, p, dtype, &R);
   if (st) return st;
-  if (!U || !Out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
-  if (ws_bytes < glam_rho_workspace_size(d, n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+  const Geom& G = R.G;
+  if (!U_in || !Out_p || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const WsLayout W = ws_layout(G, dtype);
   char* ws = (char*)workspace;
-  const void* X[3];
-  st = lift_factors(d, X_in, ws, W, dtype, s, X);
+  const void* Xl[3];
+  st = lift_factors(d, X_in, ws, W, dtype, s, Xl);
   if (st) return st;
-  const size_t es = dt_size(dtype);
+  const void* X[3] = {Xl[R.q[0]], Xl[R.q[1]], Xl[R.q[2]]};
+  const size_t es = dt_size(dtype), oes = dtype == DT_F64 ? 8 : 4;
+  const void* U = U_in;
+  void* Out = Out_p;
+  char* reg_n = ws + W.total;                             // U in the order that runs
+  char* reg_p = reg_n + align256((size_t)G.n * 8);        // the output in that order
+  if (R.perm) {
+    HIPCHK(launch_permute3_es((int)es, U_in, reg_n, R.n, R.q, s));
+    U = reg_n;
+    Out = reg_p;
+  }
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
   HIPCHK(launch_zero(ws + W.s2 + (size_t)(G.KBN3 - 1) * 16 * G.P12 * es, (size_t)16 * G.P12 * es, s));
   SlabParams S{};
@@ -196,6 +291,12 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
   AdjParams A{};
   A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = Out; A.scale = 1.0;
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  if (R.perm) {   // back to the caller's order
+    int qi[3];
+    for (int k = 0; k < 3; ++k) qi[R.q[k]] = k;
+    const int64_t pr[3] = {G.p1, G.p2, G.p3};
+    HIPCHK(launch_permute3_es((int)oes, reg_p, Out_p, pr, qi, s));
+  }
   return GLAM_OK;
 }
 

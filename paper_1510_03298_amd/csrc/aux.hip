@@ -264,10 +264,11 @@ __global__ __launch_bounds__(WG) void k_scad_weights(long long p, const double* 
   }
 }
 
-// Axis permutation of a column-major 3-D FP64 array: out has dims (d[q0], d[q1], d[q2]) and
-// out[i'] = in[i] with i[q_k] = i'_k (a GLAM is unchanged by a joint permutation of its
-// modes, of Y's axes and of Theta's axes).
-__global__ __launch_bounds__(WG) void k_permute3(const double* __restrict__ in, double* __restrict__ out, long long d0,
+// Axis permutation of a column-major 3-D array (elements moved as raw bits of T: FP64, FP32 or
+// BF16): out has dims (d[q0], d[q1], d[q2]) and out[i'] = in[i] with i[q_k] = i'_k (a GLAM is
+// unchanged by a joint permutation of its modes, of Y's axes and of Theta's axes).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_permute3(const T* __restrict__ in, T* __restrict__ out, long long d0,
                                                  long long d1, long long d2, int q0, int q1, int q2, long long total) {
   const long long d[3] = {d0, d1, d2};
   const long long e0 = d[q0], e1 = d[q1];
@@ -453,12 +454,20 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
   return hipGetLastError();
 }
 
-hipError_t launch_permute3(const double* in, double* out, const int64_t* dims, const int* q, hipStream_t s) {
+hipError_t launch_permute3_es(int es, const void* in, void* out, const int64_t* dims, const int* q, hipStream_t s) {
   const long long total = (long long)dims[0] * dims[1] * dims[2];
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute3, dim3(grid1d(total)), dim3(WG), 0, s, in, out, (long long)dims[0], (long long)dims[1],
-                     (long long)dims[2], q[0], q[1], q[2], total);
+  const dim3 g(grid1d(total)), b(WG);
+  const long long d0 = dims[0], d1 = dims[1], d2 = dims[2];
+  if (es == 8) hipLaunchKernelGGL(k_permute3<unsigned long long>, g, b, 0, s, (const unsigned long long*)in, (unsigned long long*)out, d0, d1, d2, q[0], q[1], q[2], total);
+  else if (es == 4) hipLaunchKernelGGL(k_permute3<unsigned int>, g, b, 0, s, (const unsigned int*)in, (unsigned int*)out, d0, d1, d2, q[0], q[1], q[2], total);
+  else if (es == 2) hipLaunchKernelGGL(k_permute3<unsigned short>, g, b, 0, s, (const unsigned short*)in, (unsigned short*)out, d0, d1, d2, q[0], q[1], q[2], total);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_permute3(const double* in, double* out, const int64_t* dims, const int* q, hipStream_t s) {
+  return launch_permute3_es(8, in, out, dims, q, s);
 }
 
 hipError_t launch_scad_weights(long long p, const double* theta, const double* base, double lambda, double a, double* w,

@@ -825,7 +825,7 @@ static int lift_problem(const glam_problem* in, glam_problem* out, UnitFactor* u
 // The slab kernels take modes 1 and 2 within the limits of the rho entry points and of the FP64
 // outer steps' LDS image.
 static bool inner_modes_fit(const int64_t* n, const int64_t* p, int dtype) {
-  if (glam_rho_workspace_size(3, n, p, dtype) == 0) return false;
+  if (!rho_order_fits(n, p, dtype, nullptr)) return false;
   return slab_chain_lds_bytes(DT_F64, make_geom(n, p)) <= 159 * 1024;
 }
 
@@ -1201,7 +1201,7 @@ static int validate_problem(const glam_problem* prob, int dtype, std::string* wh
   }
   if (!prob->Y) { *why = "NULL Y"; return GLAM_EINVAL; }
   if (prob->family < GLAM_GAUSSIAN || prob->family > GLAM_GAMMA) { *why = "bad family"; return GLAM_EINVAL; }
-  if (glam_rho_workspace_size(3, prob->n, prob->p, dtype) == 0) { *why = glam_last_error(); return GLAM_EINVAL; }
+  if (!rho_order_fits(prob->n, prob->p, dtype, why)) return GLAM_EINVAL;
   if (slab_chain_lds_bytes(DT_F64, make_geom(prob->n, prob->p)) > 159 * 1024) {
     *why = "modes 1-2 too large for the FP64 slab kernel";
     return GLAM_EINVAL;

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <string>
 
 namespace glam {
 
@@ -265,6 +266,10 @@ hipError_t launch_pen_trials(long long p, const double* theta, const double* d, 
 // negative or non-finite a, non-positive or non-finite pen_w
 // out (dims d[q0], d[q1], d[q2]) = in (dims d) with its axes permuted: out[i'] = in[i], i[q_k] = i'_k
 hipError_t launch_permute3(const double* in, double* out, const int64_t* dims, const int* q, hipStream_t s);
+// modes 1 and 2 of a d = 3 problem fit the slab kernels in this order (why: the reason if not)
+bool rho_order_fits(const int64_t* n, const int64_t* p, int dtype, std::string* why);
+// the same for elements of es bytes (8, 4 or 2), moved as raw bits
+hipError_t launch_permute3_es(int es, const void* in, void* out, const int64_t* dims, const int* q, hipStream_t s);
 hipError_t launch_scad_weights(long long p, const double* theta, const double* base, double lambda, double a, double* w,
                                hipStream_t s);
 hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,

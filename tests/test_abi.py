@@ -67,15 +67,22 @@ def test_workspace_size_and_limits():
     assert glam.glam_rho_workspace_size(2, n, p, glam.F64) > 0
     n2, p2 = _sizes((100, 5000, 0), (30, 400, 0))
     assert glam.glam_rho_workspace_size(2, n2, p2, glam.F32) > 0
+    # n_1 beyond the inner-mode limit: the transform runs in another mode order (mode 1 last),
+    # with room for the permuted input and output in the workspace
     n2, p2 = _sizes((300, 50, 0), (30, 20, 0))
-    assert glam.glam_rho_workspace_size(2, n2, p2, glam.F32) == 0        # n_1 beyond the inner-mode limit
+    w_re = glam.glam_rho_workspace_size(2, n2, p2, glam.F32)
+    assert w_re >= 300 * 50 * 8
     n, p = _sizes((100, 100, 1000), (33, 30, 200))
-    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # p_1 beyond the inner-mode limit
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # only one mode with p <= 32
+    assert b"every order" in glam.glam_last_error()
     n, p = _sizes((0, 100, 1000), (3, 3, 3))
     assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # empty mode
     n, p = _sizes((256, 256, 10), (32, 32, 3))
     assert glam.glam_rho_workspace_size(3, n, p, glam.F32) > 0
-    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) == 0          # FP64 copies exceed the LDS budget
+    # FP64 copies of X1, X2 exceed the LDS budget in this order; (256, 10, 256) fits
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) > glam.glam_rho_workspace_size(3, n, p, glam.F32)
+    n, p = _sizes((256, 256, 256), (32, 32, 32))
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) == 0          # no order fits the FP64 LDS budget
     assert b"LDS" in glam.glam_last_error()
 
 
