@@ -263,7 +263,9 @@ int glam_fit_batched(const glam_problem* probs, int nprob, const glam_batch_opti
  * a = 1, log y! dropped): L(beta) = (1/n) sum_i (exp(eta_i) - y_i eta_i),
  * eta = H(<X_j>, beta); grad L = G(<X_j>, exp(eta) - y) / n.
  * ------------------------------------------------------------------------- */
-/* The NLL entry points take the caller's mode order as given (no reordering). */
+/* Like the rho entry points, a problem whose mode order does not fit the slab kernels runs in
+ * one that does: beta, Y (and the gradient) are permuted through the workspace, whose size
+ * query then includes them. */
 size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype);
 
 /* loss (device, one FP64) = L(beta).  X and beta of `dtype`; Y FP64 counts. */

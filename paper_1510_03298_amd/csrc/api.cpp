@@ -300,10 +300,36 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
   return GLAM_OK;
 }
 
+// NLL workspace: the rho layout of the order that runs, then (reordered problems) regions for
+// Y (n FP64), beta and the gradient (p elements of 8 bytes each) in that order.
+struct NllRegions {
+  char *y, *beta, *grad;
+};
+static size_t nll_extra_bytes(const RhoPlan& R) {
+  return R.perm ? align256((size_t)R.G.n * 8) + 2 * align256((size_t)R.G.p * 8) : 0;
+}
+static NllRegions nll_regions(const RhoPlan& R, char* base) {
+  NllRegions g;
+  g.y = base;
+  g.beta = g.y + align256((size_t)R.G.n * 8);
+  g.grad = g.beta + align256((size_t)R.G.p * 8);
+  return g;
+}
+static void nll_factors(const RhoPlan& R, const void* const* X, const void** Xr) {
+  for (int k = 0; k < 3; ++k) Xr[k] = X[R.q[k]];
+}
+// gradient of the order that ran -> the caller's order
+static hipError_t nll_grad_back(const RhoPlan& R, int dtype, const void* gr, void* grad, hipStream_t s) {
+  int qi[3];
+  for (int k = 0; k < 3; ++k) qi[R.q[k]] = k;
+  const int64_t pr[3] = {R.G.p1, R.G.p2, R.G.p3};
+  return launch_permute3_es(dtype == DT_F64 ? 8 : 4, gr, grad, pr, qi, s);
+}
+
 size_t glam_nll_workspace_size(const int64_t* n, const int64_t* p, int dtype) {
-  Geom G;
-  if (check_sizes(3, n, p, dtype, &G) != GLAM_OK) return 0;
-  return ws_layout(G, dtype).total;
+  RhoPlan R;
+  if (plan_rho(3, n, p, dtype, &R) != GLAM_OK) return 0;
+  return ws_layout(R.G, dtype).total + nll_extra_bytes(R);
 }
 
 // Shared forward part of the NLL entry points: eta = H(beta) inside slab_chain.
@@ -320,18 +346,31 @@ static int nll_prepare(const Geom& G, const void* const* X, const void* beta, in
   return GLAM_OK;
 }
 
-int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* const* X, const void* beta,
-                             const double* Y, double* loss, int dtype, void* workspace, size_t ws_bytes,
+int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* const* X_in, const void* beta_in,
+                             const double* Y_in, double* loss, int dtype, void* workspace, size_t ws_bytes,
                              void* stream) {
   g_err.clear();
-  Geom G;
-  int st = check_sizes(3, n, p, dtype, &G);
+  RhoPlan R;
+  int st = plan_rho(3, n, p, dtype, &R);
   if (st) return st;
-  if (!X || !X[0] || !X[1] || !X[2] || !beta || !Y || !loss || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  const Geom& G = R.G;
+  if (!X_in || !X_in[0] || !X_in[1] || !X_in[2] || !beta_in || !Y_in || !loss || !workspace)
+    return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const WsLayout W = ws_layout(G, dtype);
+  const void* X[3];
+  nll_factors(R, X_in, X);
+  const void* beta = beta_in;
+  const double* Y = Y_in;
+  if (R.perm) {   // Y and beta in the order that runs (the loss is the same)
+    const NllRegions g = nll_regions(R, ws + W.total);
+    HIPCHK(launch_permute3_es((int)dt_size(dtype), beta_in, g.beta, R.p, R.q, s));
+    HIPCHK(launch_permute3_es(8, Y_in, g.y, R.n, R.q, s));
+    beta = g.beta;
+    Y = (const double*)g.y;
+  }
   st = nll_prepare(G, X, beta, dtype, ws, W, s);
   if (st) return st;
   double* part = (double*)(ws + W.part);
@@ -344,19 +383,34 @@ int glam_poisson_nll_forward(const int64_t* n, const int64_t* p, const void* con
   return GLAM_OK;
 }
 
-int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* const* X, const void* beta,
-                              const double* Y, const double* gscale, void* grad, int dtype, void* workspace,
+int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* const* X_in, const void* beta_in,
+                              const double* Y_in, const double* gscale, void* grad_out, int dtype, void* workspace,
                               size_t ws_bytes, void* stream) {
   g_err.clear();
-  Geom G;
-  int st = check_sizes(3, n, p, dtype, &G);
+  RhoPlan R;
+  int st = plan_rho(3, n, p, dtype, &R);
   if (st) return st;
-  if (!X || !X[0] || !X[1] || !X[2] || !beta || !Y || !grad || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  const Geom& G = R.G;
+  if (!X_in || !X_in[0] || !X_in[1] || !X_in[2] || !beta_in || !Y_in || !grad_out || !workspace)
+    return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_nll_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
   const WsLayout W = ws_layout(G, dtype);
   const size_t es = dt_size(dtype);
+  const void* X[3];
+  nll_factors(R, X_in, X);
+  const void* beta = beta_in;
+  const double* Y = Y_in;
+  void* grad = grad_out;
+  const NllRegions g = nll_regions(R, ws + W.total);
+  if (R.perm) {
+    HIPCHK(launch_permute3_es((int)es, beta_in, g.beta, R.p, R.q, s));
+    HIPCHK(launch_permute3_es(8, Y_in, g.y, R.n, R.q, s));
+    beta = g.beta;
+    Y = (const double*)g.y;
+    grad = g.grad;
+  }
   st = nll_prepare(G, X, beta, dtype, ws, W, s);
   if (st) return st;
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
@@ -369,6 +423,7 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
   A.G = G; A.S2 = ws + W.s2; A.X3a = ws + W.x3a; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
   A.s2_kb4 = chain_s2_kb4(dtype, SM_NLL_BWD, G);
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  if (R.perm) HIPCHK(nll_grad_back(R, dtype, g.grad, grad_out, s));
   return GLAM_OK;
 }
 
@@ -377,38 +432,51 @@ int glam_poisson_nll_backward(const int64_t* n, const int64_t* p, const void* co
 // ---------------------------------------------------------------------------
 // Layout: the rho workspace, then the counts: tiled FP32 for the one-wave-per-slab kernel,
 // else an FP64 copy in the standard layout.
+// A reordered problem (see plan_rho) also has the n/p regions of the one-shot calls after it.
 struct NllPacked {
+  RhoPlan R;
   WsLayout W;
-  size_t y, total;
+  size_t y, extra, total;
   bool tiled;
 };
-static NllPacked nll_packed_layout(const Geom& G, int dt) {
+static NllPacked nll_packed_layout(const RhoPlan& R, int dt) {
   NllPacked L;
-  L.W = ws_layout(G, dt);
-  L.tiled = chain_image_need(dt, SM_NLL_FWD, G) == PACK_WAVE;
+  L.R = R;
+  L.W = ws_layout(R.G, dt);
+  L.tiled = chain_image_need(dt, SM_NLL_FWD, R.G) == PACK_WAVE;
   L.y = L.W.total;
-  L.total = L.y + align256(L.tiled ? (size_t)G.nint * sizeof(float) : (size_t)G.n * sizeof(double));
+  L.extra = L.y + align256(L.tiled ? (size_t)R.G.nint * sizeof(float) : (size_t)R.G.n * sizeof(double));
+  L.total = L.extra + nll_extra_bytes(R);
   return L;
 }
 
 size_t glam_nll_packed_workspace_size(const int64_t* n, const int64_t* p, int dtype) {
-  Geom G;
-  if (check_sizes(3, n, p, dtype, &G) != GLAM_OK) return 0;
-  return nll_packed_layout(G, dtype).total;
+  RhoPlan R;
+  if (plan_rho(3, n, p, dtype, &R) != GLAM_OK) return 0;
+  return nll_packed_layout(R, dtype).total;
 }
 
-int glam_poisson_nll_pack(const int64_t* n, const int64_t* p, const void* const* X, const double* Y, int dtype,
+int glam_poisson_nll_pack(const int64_t* n, const int64_t* p, const void* const* X_in, const double* Y_in, int dtype,
                           void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
-  Geom G;
-  int st = check_sizes(3, n, p, dtype, &G);
+  RhoPlan R;
+  int st = plan_rho(3, n, p, dtype, &R);
   if (st) return st;
-  if (!X || !X[0] || !X[1] || !X[2] || !Y || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  const Geom& G = R.G;
+  if (!X_in || !X_in[0] || !X_in[1] || !X_in[2] || !Y_in || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_nll_packed_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  const NllPacked L = nll_packed_layout(G, dtype);
+  const NllPacked L = nll_packed_layout(R, dtype);
   const WsLayout& W = L.W;
+  const void* X[3];
+  nll_factors(R, X_in, X);
+  const double* Y = Y_in;
+  if (R.perm) {   // the counts in the order that runs, then packed from there
+    const NllRegions g = nll_regions(R, ws + L.extra);
+    HIPCHK(launch_permute3_es(8, Y_in, g.y, R.n, R.q, s));
+    Y = (const double*)g.y;
+  }
   const size_t es = dt_size(dtype);
   HIPCHK(launch_pack(dtype, dtype, X[2], G.p3, G.n3, G.n3, 1, ws + W.x3f, s));
   HIPCHK(launch_pack(dtype, dtype, X[2], G.n3, G.p3, 1, G.n3, ws + W.x3a, s));
@@ -421,14 +489,22 @@ int glam_poisson_nll_pack(const int64_t* n, const int64_t* p, const void* const*
 }
 
 // checks shared by the packed entry points; eta = H(beta) into T1 of the workspace
-static int nll_packed_begin(const int64_t* n, const int64_t* p, const void* beta, int dtype, void* workspace,
+static int nll_packed_begin(const int64_t* n, const int64_t* p, const void* beta_in, int dtype, void* workspace,
                             size_t ws_bytes, hipStream_t s, Geom* G, NllPacked* L) {
-  int st = check_sizes(3, n, p, dtype, G);
+  RhoPlan R;
+  int st = plan_rho(3, n, p, dtype, &R);
   if (st) return st;
-  if (!beta || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+  *G = R.G;
+  if (!beta_in || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < glam_nll_packed_workspace_size(n, p, dtype)) return fail(GLAM_EINVAL, "workspace too small");
-  *L = nll_packed_layout(*G, dtype);
+  *L = nll_packed_layout(R, dtype);
   char* ws = (char*)workspace;
+  const void* beta = beta_in;
+  if (R.perm) {
+    const NllRegions g = nll_regions(R, ws + L->extra);
+    HIPCHK(launch_permute3_es((int)dt_size(dtype), beta_in, g.beta, R.p, R.q, s));
+    beta = g.beta;
+  }
   HIPCHK(launch_pack(dtype, dtype, beta, G->p3, G->P12, G->P12, 1, ws + L->W.inc, s));
   FwdParams F{};
   F.G = *G; F.theta = ws + L->W.inc; F.X3f = ws + L->W.x3f; F.T1 = ws + L->W.t1;
@@ -459,9 +535,9 @@ int glam_poisson_nll_forward_packed(const int64_t* n, const int64_t* p, const vo
 }
 
 int glam_poisson_nll_backward_packed(const int64_t* n, const int64_t* p, const void* beta, const double* gscale,
-                                     void* grad, int dtype, void* workspace, size_t ws_bytes, void* stream) {
+                                     void* grad_out, int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
-  if (!grad) return fail(GLAM_EINVAL, "NULL pointer");
+  if (!grad_out) return fail(GLAM_EINVAL, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
   Geom G;
   NllPacked L;
@@ -475,9 +551,12 @@ int glam_poisson_nll_backward_packed(const int64_t* n, const int64_t* p, const v
   else S.y_std = (const double*)(ws + L.y);
   HIPCHK(launch_slab_chain(dtype, SM_NLL_BWD, S, nullptr, s));
   AdjParams A{};
+  const NllRegions g = nll_regions(L.R, ws + L.extra);
+  void* grad = L.R.perm ? (void*)g.grad : grad_out;
   A.G = G; A.S2 = ws + L.W.s2; A.X3a = ws + L.W.x3a; A.out = grad; A.scale = 1.0 / (double)G.n; A.gscale_dev = gscale;
   A.s2_kb4 = chain_s2_kb4(dtype, SM_NLL_BWD, G);
   HIPCHK(launch_slab_adj(dtype, EPI_STORE, A, nullptr, s));
+  if (L.R.perm) HIPCHK(nll_grad_back(L.R, dtype, g.grad, grad_out, s));
   return GLAM_OK;
 }
 

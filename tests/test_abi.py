@@ -178,8 +178,11 @@ def test_packed_nll_workspace_and_argument_checks():
     assert wp >= w + 128 * 128 * 256 * 4          # tiled FP32 counts
     wp64 = glam.glam_nll_packed_workspace_size(n, p, glam.F64)
     assert wp64 >= glam.glam_nll_workspace_size(n, p, glam.F64) + 128 * 128 * 256 * 8   # FP64 copy
-    bad_n, bad_p = _sizes((128, 128, 256), (40, 32, 64))
+    re_n, re_p = _sizes((128, 128, 256), (40, 32, 16))   # p_1 > 32: another mode order, plus the permuted arrays
+    assert glam.glam_nll_packed_workspace_size(re_n, re_p, glam.BF16) > glam.glam_nll_workspace_size(re_n, re_p, glam.BF16) > 0
+    bad_n, bad_p = _sizes((128, 128, 256), (40, 40, 64))  # no order fits
     assert glam.glam_nll_packed_workspace_size(bad_n, bad_p, glam.BF16) == 0
+    assert glam.glam_nll_workspace_size(bad_n, bad_p, glam.BF16) == 0
     X = (ctypes.c_void_p * 3)(None, None, None)
     assert glam.glam_poisson_nll_pack(n, p, X, None, glam.BF16, None, 0, None) == glam.GLAM_EINVAL
     assert b"NULL" in glam.glam_last_error()

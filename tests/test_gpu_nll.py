@@ -28,7 +28,9 @@ def _check(glam, d, beta, loss, grad, dt):
 
 
 @pytest.mark.parametrize("dt", [0, 1, 2])
-@pytest.mark.parametrize("n,p", [((21, 18, 30), (7, 6, 9)), ((40, 33, 17), (20, 17, 5))])
+@pytest.mark.parametrize("n,p", [((21, 18, 30), (7, 6, 9)), ((40, 33, 17), (20, 17, 5)),
+                                 ((60, 18, 30), (40, 6, 9)),      # p_1 > 32: runs in another mode order
+                                 ((150, 20, 30), (10, 40, 6))])   # p_2 > 32: reordered, LDS slab kernel
 def test_nll_value_and_gradient(n, p, dt):
     torch, glam = need_gpu()
     print(f"nll n={n} p={p} dt={dt}", flush=True)
@@ -86,7 +88,8 @@ def test_nll_full_size_workload(dt):
 
 @pytest.mark.parametrize("dt", [0, 1, 2])
 @pytest.mark.parametrize("n,p", [((21, 18, 30), (7, 6, 9)), ((40, 33, 17), (20, 17, 5)),
-                                 ((150, 20, 12), (10, 8, 5))])   # n_1 > 128: the LDS kernel, FP64 counts
+                                 ((150, 20, 12), (10, 8, 5)),    # n_1 > 128: the LDS kernel, FP64 counts
+                                 ((60, 18, 30), (40, 6, 9))])    # reordered: beta, Y and the gradient permuted
 def test_nll_packed_matches_unpacked(n, p, dt):
     """X and Y packed once: loss and gradient at two successive betas bit for bit those of the
     one-shot entry points (integer counts), and within the oracle's bound."""
