@@ -185,8 +185,9 @@ def sim65_path(glam, inputs, torch, stream, family, forms=("bf16", "f64")):
 
 
 def poisson_path_kron(glam, inputs, torch, stream):
-    """The C3 Poisson path with Sec. 6.2's tensor-product weights: p-sized inner iterations
-    on reweighted Gram factors (exact gradient, approximate curvature), same FP64 KKT."""
+    """The Poisson path n = (64, 64, 365), p = (24, 24, 120) with Sec. 6.2's tensor-product
+    weights: p-sized inner iterations on reweighted Gram factors (exact gradient, approximate
+    curvature), same FP64 KKT."""
     d = inputs.config_c3()
     Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
     Yd = glam.to_device_colmajor(d.Y, glam.F64)
@@ -324,7 +325,7 @@ def main():
                              dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
                              profile_every=profile_every, raise_on_error=False, graph=not args.eager)
 
-    progress(f"C2 path, {args.warmup} warmup + {args.steps} timed steps ({args.dtype})")
+    progress(f"Gaussian 100x100x1000 path, {args.warmup} warmup + {args.steps} timed steps ({args.dtype})")
     for _ in range(args.warmup):
         fit(args.dtype)
     torch.cuda.synchronize()
@@ -339,7 +340,7 @@ def main():
 
     # the same path with its host-device copies inside the clock (X, Y up from host memory, the
     # theta path back down): reported beside the device-resident time, never as the value
-    progress("C2 path with the host-device copies")
+    progress("Gaussian 100x100x1000 path with the host-device copies")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Xc = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
@@ -391,7 +392,7 @@ def main():
         for dt in ["f64", "f32", "bf16"]:
             if dt in forms:
                 continue
-            progress(f"C2 path, {dt} form (untimed comparison)")
+            progress(f"Gaussian 100x100x1000 path, {dt} form (untimed comparison)")
             r = fit(dt)
             forms[dt] = {"seconds": r.seconds, "inner": int(r.inner_total), "outer": int(r.iters_outer.sum()),
                          "max_kkt": float(np.max(r.kkt)), "ok": r.code == 0 and r.n_done == args.nlambda}

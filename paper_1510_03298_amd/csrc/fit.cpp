@@ -90,11 +90,13 @@ static double gram_spectral_radius(std::vector<double> A, int p) {
 static bool family_has_weights(int family) { return family == GLAM_POISSON || family == GLAM_BINOMIAL; }
 
 // A low-precision inner loop whose best KKT residual has not halved over this many checks
-// leaves for an FP64 re-anchor.  Where the model is the objective (no line search, R19) a
-// re-anchor costs one FP64 family step and restarts the extrapolation: 10 checks measured
-// 23% faster than 20 on the C2 path (and 50% slower on an ill-conditioned design whose slow
+// leaves for an FP64 re-anchor.  Where the model is the objective (the Gaussian model without
+// prior weights: its inner solution is the step, no line search) a re-anchor costs one FP64
+// family step and restarts the extrapolation: 10 checks measured 23% faster than 20 on the
+// Gaussian n = (100, 100, 1000) path (and 50% slower on an ill-conditioned design whose slow
 // but steady passes it cuts short).  Elsewhere each re-anchor also runs the Armijo rule, and
-// 20 checks measured faster (C3: 1.02 s against 1.22 s).  The batched solver uses 10.
+// 20 checks measured faster (Poisson n = (64, 64, 365) path: 1.02 s against 1.22 s).  The
+// batched solver uses 10.
 constexpr int kStallChecks = 10;
 constexpr int kStallChecksLineSearch = 20;
 
@@ -449,7 +451,7 @@ static int inner_block_graph(Fit& F, int m, int* nblk) {
   return GLAM_OK;
 }
 
-// Inner PG loop with step control nu < 1 (Sec. 6.4; reading R7): delta starts at
+// Inner PG loop with step control nu < 1 (Sec. 6.4): delta starts at
 // 1/(nu Lhat); each iteration also tests the Beck-Teboulle sufficient decrease of the
 // step that produced the current iterate and, if it fails, halves delta (never below
 // 1/Lhat) and redoes that step.  The host checks every iteration.
@@ -938,7 +940,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     }
   }
   {
-    // modes reordered, when needed, so that two of them fit the slab kernels (R20)
+    // modes reordered, when needed, so that two of them fit the slab kernels
     std::string why;
     const int r = permute_problem(&lifted, opt_local.dtype, &opt_local.theta0, &perm, (hipStream_t)opt_in->stream, &why);
     if (r) return fit_fail(r, why);

@@ -1113,7 +1113,8 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
 // the compact list (one shape class: P16 when p1, p2 <= 16, N1B = 4 when n1 <= 64), one run
 // per item; each class is its own launch, so that it gets the registers its shape needs.
 // At least two waves per SIMD: the FP32 class with p > 16 and n1 > 64 otherwise takes 272
-// registers (one wave per SIMD); held to 256 it spills 4 and C4 ran 8% faster.
+// registers (one wave per SIMD); held to 256 it spills 4 and a batch of 256 problems with
+// modes n_ij in 16..96 ran 8% faster.
 template <typename T, bool P16, int N1B>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_batched_slabs(BatchParams B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];   // wave_lds_bytes<T, 1, 4>()
@@ -1243,9 +1244,10 @@ static int num_cus() {
   return n;
 }
 
-// FP64: 64 x 64 workgroup tiles where they still give half the CUs a workgroup (C2's shape:
-// 240 tiles, 26.7 -> 22.1 us); below that, 32 x 32 tiles (a Sec. 6.5 design at P12 = 450,
-// n3 = 180 has 24 large tiles against 90 small ones, and its FP64 path ran 25% slower on them)
+// FP64: 64 x 64 workgroup tiles where they still give half the CUs a workgroup (n = (100, 100,
+// 1000), p = (30, 30, 200): 240 tiles, 26.7 -> 22.1 us); below that, 32 x 32 tiles (a Sec. 6.5
+// design at P12 = 450, n3 = 180 has 24 large tiles against 90 small ones, and its FP64 path
+// ran 25% slower on them)
 static bool slab_fwd_f64_wide(const Geom& G) { return (long long)((G.P12 + 63) / 64) * ((G.n3 + 63) / 64) >= 128; }
 
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s) {

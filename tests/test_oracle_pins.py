@@ -577,7 +577,7 @@ def test_path_early_exit_returns_preceding_models():
     assert not infos[-1].converged and len(thetas) < 6
 
 
-# ---------------------------------------------------------------- C5 NLL ---
+# ---------------------------------------------------------- Poisson NLL ---
 def test_poisson_nll_gradient_central_differences():
     d = inputs.random_problem((6, 5, 4), (3, 3, 2), family="poisson", seed=13, scale=0.3, basis="gauss")
     beta = np.random.default_rng(1).normal(0, 0.3, d.p)
