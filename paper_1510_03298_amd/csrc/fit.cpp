@@ -202,6 +202,7 @@ struct Fit {
   double* part;            // partial sums
   double* red;             // reduced values (device)
   double* hred = nullptr;  // reduced values (pinned host); [32..35] input-check flags
+  double* hred_dev = nullptr;   // its device address: the reductions of steps 2 and 5 write there directly
   double* hx[3] = {nullptr, nullptr, nullptr};   // pinned host copies of the factors (set-up)
   double* hpub = nullptr;  // published check values (fine-grained pinned host, mapped)
   double* hpub_dev = nullptr;
@@ -266,7 +267,8 @@ struct StepStats {
   } while (0)
 
 // Step 2 of Algorithm 1 at theta (FP64): eta, V, -l/n, g = -G(U)/n, KKT.
-// Enqueue step 2 of Algorithm 1 at theta (values land in F.hred after the stream
+// Enqueue step 2 of Algorithm 1 at theta (values land in F.hred, written by the reductions
+// themselves through its mapped address, after the stream
 // completes); family_collect reads them.
 static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   const Geom& G = F.G;
@@ -281,7 +283,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   int nbc = 0;
   FCHK(launch_slab_chain(DT_F64, SM_FAMILY, sp, &nbc, F.s));
   const int ops2[2] = {0, 1};
-  FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.red, F.s));
+  FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.hred_dev, F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2d; ap.X3a = F.X3ad; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
   ap.theta = theta_dev; ap.pen_w = F.pen; ap.lambda = lambda; ap.alpha = F.enet;
@@ -290,8 +292,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   int nb = 0;
   FCHK(launch_slab_adj(DT_F64, EPI_GRAD, ap, &nb, F.s));
   const int ops4[4] = {1, 1, 0, 0};
-  FCHK(launch_reduce_strided(part2, nb, ADJ_NSUM, 4, ops4, 1.0, F.red + 2, F.s));
-  FCHK(hipMemcpyAsync(F.hred, F.red, 6 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+  FCHK(launch_reduce_strided(part2, nb, ADJ_NSUM, 4, ops4, 1.0, F.hred_dev + 2, F.s));
   return GLAM_OK;
 }
 
@@ -555,7 +556,8 @@ static int escalate_f32(Fit& F) {
 // Armijo rule (Sec. 5): d = theta~ - theta^k (in F.dvec).  Returns alpha.
 // Enqueue one pass of the Armijo rule (step sizes 2^-j0 .. 2^-(j0+15)) along d =
 // F.dvec; j0 == 0 also computes H(d) in FP64 (the trials use eta + t H(d)).  The sums
-// land in F.hred after the stream completes; armijo_decide reads them.
+// land in F.hred (written through its mapped address) after the stream completes;
+// armijo_decide reads them.
 static int armijo_enqueue(Fit& F, int j0) {
   const Geom& G = F.G;
   if (j0 == 0) {
@@ -571,11 +573,10 @@ static int armijo_enqueue(Fit& F, int j0) {
   const int ops[NV] = {0};
   int nb1 = 0, nb2 = 0;
   FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
-  FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.red, F.s));
+  FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.hred_dev, F.s));
   double* part2 = F.part + (size_t)nb1 * NV;
   FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.pen, F.enet, j0, part2, &nb2, F.s));
-  FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.red + NV, F.s));
-  FCHK(hipMemcpyAsync(F.hred, F.red, 2 * NV * sizeof(double), hipMemcpyDeviceToHost, F.s));
+  FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.hred_dev + NV, F.s));
   return GLAM_OK;
 }
 
@@ -676,7 +677,7 @@ static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool eve
   if (events)
     for (auto& e : F.ev)
       if (hipEventCreate(&e) != hipSuccess) { F.err = "hipEventCreate failed"; return GLAM_EDEVICE; }
-  F.hred = F.host_alloc(64);
+  F.hred = F.host_alloc(64, &F.hred_dev);
   F.hparams = F.host_alloc(4);
   F.hpub = F.host_alloc(16, &F.hpub_dev);
   for (int j = 0; j < 3; ++j) F.hx[j] = F.host_alloc((size_t)prob->n[j] * prob->p[j]);
@@ -699,8 +700,7 @@ static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool eve
     int nb = 0;
     FCHK(launch_check(G.n, prob->Y, prob->obs_w, G.p, prob->pen_w, prob->family, F.part, &nb, F.s));
     const int ops[4] = {1, 1, 1, 1};
-    FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.red + 32, F.s));
-    FCHK(hipMemcpyAsync(F.hred + 32, F.red + 32, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+    FCHK(launch_reduce(F.part, nb, 4, ops, 1.0, F.hred_dev + 32, F.s));
   }
   // ---- setup: tiled data, chain copies of the factors, spectral radii ----
   FCHK(launch_to_tiled(G, prob->Y, 0.0, F.y_int, F.s));
