@@ -155,3 +155,17 @@ def test_batched_f32_lds_slab_path():
         lm = O.lambda_max(fam, X, Y)
         th = glam.from_colmajor(res.theta[i], p)
         assert O.kkt_residual(th, O.smooth_gradient(fam, X, th, Y), 0.1 * lm, lm) <= 1e-6, i
+
+
+def test_batched_reports_the_invalid_problem():
+    """Input checks run per problem on the device and are read by several host threads: a
+    negative count in problem 3 (Poisson) is reported with that problem's index."""
+    torch, glam = need_gpu()
+    probs = inputs.config_c4(nprob=6, lo=16, hi=24, seed_offset=46)
+    ups = [_upload(glam, d) for d in probs]
+    assert probs[3].family == "poisson"
+    ups[3]["Y"] = ups[3]["Y"].clone()
+    ups[3]["Y"][5] = -1.0
+    with pytest.raises(glam.GlamError) as e:
+        glam.fit_batched(ups, lambda_ratio=0.1, dtype=1)
+    assert "problem 3" in str(e.value) and "Poisson Y must be >= 0" in str(e.value)
