@@ -261,11 +261,13 @@ def nll(glam, inputs, torch, stream, reps=50):
     flops_b = fwd3 + chain + adj3        # recomputed forward + adjoint
     Xb = [glam.to_device_colmajor(X, glam.BF16) for X in d.X]
     packed = glam.PackedPoissonNLL(Xb, Yd, d.n, d.p, glam.BF16, stream=stream)   # X and Y packed once
+    loss_buf = torch.empty(1, dtype=torch.float64, device=Yd.device)            # outputs reused across calls
+    grad_buf = torch.empty(int(np.prod(d.p)), dtype=torch.float32, device=Yd.device)
     calls = (("forward", lambda: glam.poisson_nll_forward(Xb, beta, Yd, d.n, d.p, glam.BF16, ws, stream), flops_f),
              ("backward", lambda: glam.poisson_nll_backward(Xb, beta, Yd, one, d.n, d.p, glam.BF16, ws, stream),
               flops_b),
-             ("forward_packed", lambda: packed.forward(beta), flops_f),
-             ("backward_packed", lambda: packed.backward(beta, one), flops_b))
+             ("forward_packed", lambda: packed.forward(beta, out=loss_buf), flops_f),
+             ("backward_packed", lambda: packed.backward(beta, one, out=grad_buf), flops_b))
     for kind, fn, fl in calls:
         for _ in range(3):
             fn()

@@ -269,20 +269,24 @@ class PackedPoissonNLL:
         _check(glam_poisson_nll_pack(nn, pp, xp, Y.data_ptr(), self.dtype, self.ws.data_ptr(), self.wsb,
                                      _stream_ptr(stream)), "glam_poisson_nll_pack")
 
-    def forward(self, beta):
+    def forward(self, beta, out=None):
+        """loss (device FP64 1-tensor, written into out when given)."""
         torch = _torch()
         nn, pp = _sizes(self.n, self.p)
-        loss = torch.empty(1, dtype=torch.float64, device=beta.device)
+        loss = out if out is not None else torch.empty(1, dtype=torch.float64, device=beta.device)
         _check(glam_poisson_nll_forward_packed(nn, pp, beta.data_ptr(), loss.data_ptr(), self.dtype,
                                                self.ws.data_ptr(), self.wsb, _stream_ptr(self.stream)),
                "glam_poisson_nll_forward_packed")
         return loss
 
-    def backward(self, beta, gscale):
+    def backward(self, beta, gscale, out=None):
+        """gscale * grad L(beta) (written into out when given: FP32 for F32/BF16, FP64 for F64)."""
         torch = _torch()
         nn, pp = _sizes(self.n, self.p)
-        grad = torch.empty(int(np.prod(self.p)), dtype=out_dtype(self.dtype), device=beta.device)
-        gs = gscale.to(torch.float64).reshape(1).contiguous()
+        grad = out if out is not None else torch.empty(int(np.prod(self.p)), dtype=out_dtype(self.dtype),
+                                                        device=beta.device)
+        gs = gscale if (gscale.dtype == torch.float64 and gscale.is_contiguous()) else \
+            gscale.to(torch.float64).reshape(1).contiguous()
         _check(glam_poisson_nll_backward_packed(nn, pp, beta.data_ptr(), gs.data_ptr(), grad.data_ptr(), self.dtype,
                                                 self.ws.data_ptr(), self.wsb, _stream_ptr(self.stream)),
                "glam_poisson_nll_backward_packed")
