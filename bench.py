@@ -263,9 +263,10 @@ def nll(glam, inputs, torch, stream, reps=50):
     packed = glam.PackedPoissonNLL(Xb, Yd, d.n, d.p, glam.BF16, stream=stream)   # X and Y packed once
     loss_buf = torch.empty(1, dtype=torch.float64, device=Yd.device)            # outputs reused across calls
     grad_buf = torch.empty(int(np.prod(d.p)), dtype=torch.float32, device=Yd.device)
-    calls = (("forward", lambda: glam.poisson_nll_forward(Xb, beta, Yd, d.n, d.p, glam.BF16, ws, stream), flops_f),
-             ("backward", lambda: glam.poisson_nll_backward(Xb, beta, Yd, one, d.n, d.p, glam.BF16, ws, stream),
-              flops_b),
+    calls = (("forward", lambda: glam.poisson_nll_forward(Xb, beta, Yd, d.n, d.p, glam.BF16, ws, stream, out=loss_buf),
+              flops_f),
+             ("backward", lambda: glam.poisson_nll_backward(Xb, beta, Yd, one, d.n, d.p, glam.BF16, ws, stream,
+                                                            out=grad_buf), flops_b),
              ("forward_packed", lambda: packed.forward(beta, out=loss_buf), flops_f),
              ("backward_packed", lambda: packed.backward(beta, one, out=grad_buf), flops_b))
     for kind, fn, fl in calls:

@@ -225,27 +225,28 @@ def nll_workspace_size(n, p, dtype):
     return int(glam_nll_workspace_size(nn, pp, int(dtype)))
 
 
-def poisson_nll_forward(Xs, beta, Y, n, p, dtype, workspace=None, stream=None):
+def poisson_nll_forward(Xs, beta, Y, n, p, dtype, workspace=None, stream=None, out=None):
     torch = _torch()
     nn, pp = _sizes(n, p)
     wsb = nll_workspace_size(n, p, dtype)
     if workspace is None:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=beta.device)
-    loss = torch.empty(1, dtype=torch.float64, device=beta.device)
+    loss = out if out is not None else torch.empty(1, dtype=torch.float64, device=beta.device)
     xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
     _check(glam_poisson_nll_forward(nn, pp, xp, beta.data_ptr(), Y.data_ptr(), loss.data_ptr(), int(dtype),
                                     workspace.data_ptr(), wsb, _stream_ptr(stream)), "glam_poisson_nll_forward")
     return loss
 
 
-def poisson_nll_backward(Xs, beta, Y, gscale, n, p, dtype, workspace=None, stream=None):
+def poisson_nll_backward(Xs, beta, Y, gscale, n, p, dtype, workspace=None, stream=None, out=None):
     torch = _torch()
     nn, pp = _sizes(n, p)
     wsb = nll_workspace_size(n, p, dtype)
     if workspace is None:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=beta.device)
-    grad = torch.empty(int(np.prod(p)), dtype=out_dtype(dtype), device=beta.device)
-    gs = gscale.to(torch.float64).reshape(1).contiguous()
+    grad = out if out is not None else torch.empty(int(np.prod(p)), dtype=out_dtype(dtype), device=beta.device)
+    gs = gscale if (gscale.dtype == torch.float64 and gscale.is_contiguous()) else \
+        gscale.to(torch.float64).reshape(1).contiguous()
     xp = (_vp * 3)(*[x.data_ptr() for x in Xs])
     _check(glam_poisson_nll_backward(nn, pp, xp, beta.data_ptr(), Y.data_ptr(), gs.data_ptr(), grad.data_ptr(),
                                      int(dtype), workspace.data_ptr(), wsb, _stream_ptr(stream)),
