@@ -298,6 +298,9 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch every inner iteration eagerly (no HIP graphs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (Poisson path, 256-problem batch, Poisson NLL)")
+    ap.add_argument("--only", default=None, metavar="NAME",
+                    help="run only this secondary workload (its JSON on one line), e.g. batched_c4 or poisson_nll_c5; "
+                         "for profiling one workload's kernels")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -314,6 +317,17 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration(torch, dev, args.copy_calibration)
+        return
+    if args.only:
+        stream = torch.cuda.current_stream(dev)
+        only = {"batched_c4": lambda: batched(glam, inputs, torch, stream),
+                "poisson_nll_c5": lambda: nll(glam, inputs, torch, stream),
+                "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream)}
+        if args.only not in only:
+            print(f"bench.py: --only takes one of {sorted(only)}", file=sys.stderr)
+            sys.exit(2)
+        progress(f"workload {args.only} alone")
+        print(json.dumps({args.only: only[args.only]()}), flush=True)
         return
     d = inputs.config_c2(nlambda=args.nlambda)
     n, p = d.n, d.p
