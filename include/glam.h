@@ -14,17 +14,20 @@
  *     first index runs fastest.  X_j is n_j x p_j with leading dimension n_j;
  *     Theta is p_1 x p_2 x p_3; Eta, U, Y and observation weights are
  *     n_1 x n_2 x n_3.
- *   - Only d = 3 is supported (a d = 2 model is a d = 3 model with n_3 = p_3 = 1
- *     and X_3 = [1]).  Sizes are int64_t; every n_j and p_j must be >= 1.
+ *   - d = 2 and d = 3 (where an entry point takes d; the NLL entry points are
+ *     d = 3).  A d = 2 model X_2 (x) X_1 runs as the d = 3 model X_2 (x) [1] (x) X_1,
+ *     which keeps every array's vec layout.  Sizes are int64_t; every n_j and p_j
+ *     must be >= 1.
  *   - Array pointers are DEVICE pointers owned by the caller unless stated
  *     otherwise.  The library never frees or retains them after a call returns.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *   - Return value: a glam_status code.  GLAM_EINVAL is returned before any
- *     work is enqueued; glam_last_error() then gives a message for the calling
- *     thread.
- *   - The rho entry points are asynchronous on `stream`; glam_fit_path is
- *     synchronous (it needs host control flow) and returns when its results are
- *     in place.
+ *   - Return value: a glam_status code.  Size and option errors (GLAM_EINVAL) are
+ *     returned before any work is enqueued; the fits' data checks (Y, obs_w,
+ *     pen_w) run on the device and also return GLAM_EINVAL.  glam_last_error()
+ *     then gives a message for the calling thread.
+ *   - The rho and NLL entry points are asynchronous on `stream`; glam_fit_path
+ *     and glam_fit_batched are synchronous (they need host control flow) and
+ *     return when their results are in place.
  */
 #ifndef GLAM_H
 #define GLAM_H
