@@ -182,7 +182,13 @@ typedef struct {
  * W = V-hat enters through eq. (ten), so the model's gradient at theta^k is exact and only its
  * curvature is approximated (the Armijo rule and the FP64 KKT test are unchanged).  For the
  * unit-weight families it is GLAM_INNER_GRAM.  Needs nu = 1 (GLAM_EINVAL otherwise). */
-typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1, GLAM_INNER_KRON = 2 } glam_inner;
+/* GLAM_INNER_ONE: unit IRLS weights w_i = 1 in the quadratic model of every outer step, for
+ * any family (Sec. 3: the convergence argument holds for any strictly positive continuous
+ * weights, and constant ones are the notable special case; the package's iwls = "one").  The
+ * inner loop is then the p-sized Gram form above; the model's gradient at theta^k is the exact
+ * FP64 one and the Armijo rule and the FP64 KKT test are unchanged, so the fit reaches the same
+ * PMLE.  For the unit-weight families it is GLAM_INNER_GRAM.  Needs obs_w = NULL and nu = 1. */
+typedef enum { GLAM_INNER_CHAIN = 0, GLAM_INNER_GRAM = 1, GLAM_INNER_KRON = 2, GLAM_INNER_ONE = 3 } glam_inner;
 
 typedef struct {
   double* theta;          /* device, FP64, nlambda x p (model l at offset l*p), caller-allocated */

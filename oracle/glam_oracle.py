@@ -568,7 +568,8 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
     Step 2: eta = H(theta^k); U, V (eq. nine), Z (eq. tennew).  weights="kron": W^(k)
     is the tensor-product approximation V-hat of Sec. 6.2 and Z follows eq. (ten) with
     that W (the outer loop of Sec. 3.1 admits any positive diagonal W^(k); the model's
-    gradient at theta^k stays -X^T u / n).
+    gradient at theta^k stays -X^T u / n).  weights="one": W^(k) = I, the special case of
+    constant weights named in Sec. 3 (Z again from eq. (ten)).
     Step 3: delta = 1/(nu Lhat) with Lhat from Proposition 1.
     Step 4: inner PG loop from x^(0) = x^(1) = theta^k.
     Step 5: Armijo rule (alpha_0 b^j, v), Delta_k = -u^T X d / n + lambda (J(theta~) - J(theta)).
@@ -597,6 +598,9 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         Z = working_response(fam, eta, Y, a)
         if weights == "kron":
             V = kron_weights(V)[0]
+            Z = working_response_eq10(u, V, eta)
+        elif weights == "one":
+            V = np.ones_like(V)
             Z = working_response_eq10(u, V, eta)
         Lhat = float(np.max(V)) * s_prod / n
         delta = 1.0 / (nu * Lhat) if nu > 0 else 1.0

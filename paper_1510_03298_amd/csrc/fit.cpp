@@ -187,6 +187,7 @@ struct Fit {
   void* Zc = nullptr;      // S_1 D S_2 per slice, k-blocked like the increment
   double* S3g = nullptr;   // X_3^T X_3 (FP64)
   bool kron = false;       // Gram factors reweighted each outer step with tensor-product weights (Sec. 6.2)
+  bool unit_w = false;     // unit IRLS weights in the model of every family (the Gram form with W = I)
   double* kron_work = nullptr;    // log-weight margins and the factors v_j
   double* kron_stats = nullptr;   // {max v_1, max v_2, max v_3, Vbar} (device)
   bool gram_fused = false; // Gram iteration as one launch (k_gram_iter): increment and counter double-buffered
@@ -919,8 +920,11 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       return fit_fail(GLAM_EINVAL, "scad_a must be > 2 (or 0 for 3.7)");
     if (opt->alpha != 0.0) return fit_fail(GLAM_EINVAL, "SCAD and the elastic net do not combine");
   }
-  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM && opt->inner_mode != GLAM_INNER_KRON)
+  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM && opt->inner_mode != GLAM_INNER_KRON &&
+      opt->inner_mode != GLAM_INNER_ONE)
     return fit_fail(GLAM_EINVAL, "bad inner_mode");
+  if (opt->inner_mode == GLAM_INNER_ONE && (prob->obs_w || opt->nu < 1.0))
+    return fit_fail(GLAM_EINVAL, "the unit-weight inner loop takes no prior weights and runs without backtracking (nu = 1)");
   if (opt->inner_mode == GLAM_INNER_KRON && opt->nu < 1.0)
     return fit_fail(GLAM_EINVAL, "the tensor-product-weight inner loop runs without backtracking (nu = 1)");
   if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(prob->family) || prob->obs_w || opt->nu < 1.0))
@@ -957,8 +961,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (hipEventCreateWithFlags(&F.sync_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(F.sync_ev, F.us) != hipSuccess || hipStreamWaitEvent(F.s, F.sync_ev, 0) != hipSuccess)
     return fit_fail(GLAM_EDEVICE, "stream ordering failed");
-  F.gram = opt->inner_mode == GLAM_INNER_GRAM || opt->inner_mode == GLAM_INNER_KRON;
+  F.gram = opt->inner_mode == GLAM_INNER_GRAM || opt->inner_mode == GLAM_INNER_KRON || opt->inner_mode == GLAM_INNER_ONE;
   F.kron = opt->inner_mode == GLAM_INNER_KRON && family_has_weights(prob->family);
+  F.unit_w = opt->inner_mode == GLAM_INNER_ONE && family_has_weights(prob->family);
   F.enet = opt->alpha;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
@@ -1017,7 +1022,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   // weights, a non-canonical link) and the tensor-product weights of Sec. 6.2.  There,
   // iterating past the first point that meets the rule makes the outer steps short (the
   // Armijo rule cuts them), so the rule is checked every iteration.
-  const int check_every = (F.family == GLAM_GAMMA || F.kron) ? 1 : opt->check_every;
+  // an approximate model (Gamma's unit Fisher weights, tensor-product or unit weights) is
+  // checked every iteration: a coarser check over-solves it past what its outer step can use
+  const int check_every = (F.family == GLAM_GAMMA || F.kron || F.unit_w) ? 1 : opt->check_every;
   const int log_level = getenv("GLAM_LOG") ? atoi(getenv("GLAM_LOG")) : 0;
   const bool verbose = log_level > 0;
   int path_status = GLAM_OK;
@@ -1072,7 +1079,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         }
       }
       kkt_prev = kkt;
-      double wmax = family_has_weights(F.family) ? st.vmax : 1.0;
+      double wmax = family_has_weights(F.family) && !F.unit_w ? st.vmax : 1.0;
       if (F.kron) {
         // W^(k) = V-hat (Sec. 6.2): reweighted Gram factors from this step's eta; Proposition 1
         // with max V-hat = Vbar prod_j max v_j

@@ -385,7 +385,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.stream = _stream_ptr(stream)
     opt.profile_every = int(profile_every)
     opt.graph_mode = 0 if graph else 1
-    opt.inner_mode = {"chain": 0, "gram": 1, "kron": 2}[inner]
+    opt.inner_mode = {"chain": 0, "gram": 1, "kron": 2, "one": 3}[inner]
     opt.alpha = float(alpha)
     opt.penalty = PENALTIES[penalty] if isinstance(penalty, str) else int(penalty)
     opt.scad_a = float(scad_a)

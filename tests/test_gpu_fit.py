@@ -557,3 +557,30 @@ def test_mode_order_is_chosen_by_the_library(fam):
         assert np.array_equal(a, np.asfortranarray(b.transpose(2, 0, 1)))
         g = O.smooth_gradient(fam, Xs, a, Y)
         assert O.kkt_residual(a, g, r1.lambdas[l], lm) <= 1e-7
+
+
+@pytest.mark.parametrize("fam,dt", [("poisson", 1), ("binomial", 1), ("poisson", 0)])
+def test_unit_weight_inner_loop(fam, dt):
+    """inner="one": unit IRLS weights in every outer step's model (Sec. 3's constant weights), the
+    p-sized Gram inner loop for a weighted family; the FP64 gradient, Armijo rule and KKT test are
+    unchanged, so the path reaches the PMLE: the oracle's KKT and objective on every model."""
+    torch, glam = need_gpu()
+    # moderate counts (mean ~1): far from unit curvature (counts in the hundreds) the steps get
+    # short and the outer loop long, as the paper's remark on weight choices implies
+    d = inputs.random_problem((23, 19, 37), (9, 7, 12), family=fam, seed=47, basis="gauss", scale=0.05)
+    print(f"unit weights {fam} dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=4, lambda_min_ratio=0.05, dtype=dt, kkt_tol=1e-6,
+                        inner="one", max_outer=400)
+    assert res.code == 0, (res.code, res.status)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    for l in range(4):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
+        ref, info = O.gdpg(fam, d.X, d.Y, res.lambdas[l], lm, theta0=th, tol=1e-11, max_outer=200)
+        F1 = O.objective(fam, d.X, th, d.Y, res.lambdas[l])
+        F2 = O.objective(fam, d.X, ref, d.Y, res.lambdas[l])
+        assert (F1 - F2) / abs(F2) <= 1e-8
+    with pytest.raises(glam.GlamError):
+        glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="one", nu=0.5)

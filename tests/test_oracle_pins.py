@@ -601,3 +601,27 @@ def test_bf16_rounding_matches_torch():
     x = np.random.default_rng(2).standard_normal(10000) * 10.0 ** np.random.default_rng(3).integers(-5, 5, 10000)
     ref = torch.from_numpy(x).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(O.round_to_bf16(x), ref)
+
+
+def test_unit_weights_gaussian_is_the_exact_form():
+    """Sec. 3 (constant weights): the Gaussian IRLS weights are already 1, so weights="one" takes
+    the very same steps as the exact weights."""
+    d = inputs.random_problem((7, 6, 5), (4, 4, 3), family="gaussian", seed=18, basis="gauss")
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    a, ia = O.gdpg("gaussian", d.X, d.Y, 0.2 * lm, lm, tol=1e-10)
+    b, ib = O.gdpg("gaussian", d.X, d.Y, 0.2 * lm, lm, tol=1e-10, weights="one")
+    assert np.array_equal(a, b) and ia.inner == ib.inner
+
+
+@pytest.mark.parametrize("fam", ["poisson", "binomial"])
+def test_unit_weights_reach_the_same_pmle(fam):
+    """Sec. 3: any strictly positive continuous weights give a convergent GD-PG; with w_i = 1 the
+    quadratic models differ from the IRLS ones but the minimiser reached is the same."""
+    d = inputs.random_problem((7, 6, 5), (4, 4, 3), family=fam, seed=19, scale=0.5, basis="gauss")
+    lm = O.lambda_max(fam, d.X, d.Y)
+    exact, ie = O.gdpg(fam, d.X, d.Y, 0.2 * lm, lm, tol=1e-10, max_outer=400)
+    one, io = O.gdpg(fam, d.X, d.Y, 0.2 * lm, lm, tol=1e-10, max_outer=400, weights="one")
+    assert ie.converged and io.converged
+    assert np.max(np.abs(one - exact)) <= 1e-6 * max(1.0, np.max(np.abs(exact)))
+    g = O.smooth_gradient(fam, d.X, one, d.Y)
+    assert O.kkt_residual(one, g, 0.2 * lm, lm) <= 1e-10
