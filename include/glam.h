@@ -183,7 +183,8 @@ typedef struct {
  * curvature is approximated (the Armijo rule and the FP64 KKT test are unchanged).  For the
  * unit-weight families it is GLAM_INNER_GRAM.  Needs nu = 1 (GLAM_EINVAL otherwise). */
 /* GLAM_INNER_ONE: unit IRLS weights w_i = 1 in the quadratic model of every outer step, for
- * any family (Sec. 3: the convergence argument holds for any strictly positive continuous
+ * any family (Sec. 5, the remark after the corollary to Theorem 2: the convergence argument holds
+ * for any strictly positive continuous
  * weights, and constant ones are the notable special case; the package's iwls = "one").  The
  * inner loop is then the p-sized Gram form above; the model's gradient at theta^k is the exact
  * FP64 one and the Armijo rule and the FP64 KKT test are unchanged, so the fit reaches the same

@@ -569,7 +569,7 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
     is the tensor-product approximation V-hat of Sec. 6.2 and Z follows eq. (ten) with
     that W (the outer loop of Sec. 3.1 admits any positive diagonal W^(k); the model's
     gradient at theta^k stays -X^T u / n).  weights="one": W^(k) = I, the special case of
-    constant weights named in Sec. 3 (Z again from eq. (ten)).
+    constant weights named in Sec. 5 after the corollary to Theorem 2 (Z again from eq. (ten)).
     Step 3: delta = 1/(nu Lhat) with Lhat from Proposition 1.
     Step 4: inner PG loop from x^(0) = x^(1) = theta^k.
     Step 5: Armijo rule (alpha_0 b^j, v), Delta_k = -u^T X d / n + lambda (J(theta~) - J(theta)).
@@ -619,6 +619,10 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         xd = H(Xs, d)
         Delta = -float(np.sum(u * xd)) / n + lam * penalty_change(theta, x, pen_w, alpha)
         step = alpha0
+        # the rule needs a descent direction (Delta < 0, Sec. 5, Theorem 2's search direction);
+        # an inexact inner solve that returns one with Delta >= 0 gives no step
+        if not Delta < 0.0:
+            step, max_ls = 0.0, 0
         for _ in range(max_ls):
             dF = objective_change(fam, eta, xd, step, Y, a) + lam * penalty_change(
                 theta, theta + step * d, pen_w, alpha)

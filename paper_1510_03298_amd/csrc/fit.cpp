@@ -588,6 +588,14 @@ static bool armijo_decide(const Fit& F, int j0, double lambda, double v, double*
   const double* sm = F.hred;         // [0] = sum u xd / n ; [1+j] = smooth change / n
   const double* pj = F.hred + NV;    // [0] = J(theta~) - J(theta) ; [1+j] = J change at t_j
   if (j0 == 0) *delta_out = -sm[0] + lambda * pj[0];
+  // The rule presumes a descent direction (Delta < 0; Sec. 5, the search direction of
+  // Theorem 2).  A low-precision inner loop that ended on its rounding floor or stall rule
+  // can return a point with Delta >= 0: no step is taken (alpha = 0), and the outer loop
+  // counts it as a step that ended on the chain's floor (precision escalation).
+  if (!(*delta_out < 0.0)) {
+    *alpha_out = 0.0;
+    return true;
+  }
   for (int j = 0; j < ARMIJO_TRIALS; ++j) {
     const double t = std::ldexp(1.0, -(j0 + j));
     const double dF = sm[1 + j] + lambda * pj[1 + j];
@@ -1127,6 +1135,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         // rounding floor of the low-precision chain output (a lower bound of its error)
         noise = 4.0 * kEps[F.dt] * chk[1] / lam_scale;
         best = std::min(best, kin);
+        // the window counts inner iterations (the checks of the requested interval): where every
+        // iteration is checked (Gamma-log, tensor-product and unit weights) it spans 10 or 20 times
+        // the requested check_every iterations, not 10 or 20 checks
         if (it - window_start >= (exact_model ? kStallChecks : kStallChecksLineSearch) * opt->check_every) {
           // stalled: no 2x progress over the window -> leave for an FP64 re-anchor (which
           // also restarts the extrapolation)
@@ -1155,6 +1166,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
         RCHK(armijo(F, lam, 0.1, &alpha, &Delta));
         if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
+        else if (F.dt != DT_F64) last_limited = true;   // no descent from this low-precision pass
       }
       if (verbose)
         fprintf(stderr, "[glam] lambda %d k %d kkt %.3e F %.12e inner %d kin %.2e noise %.2e alpha %g Delta %.3e\n", l,

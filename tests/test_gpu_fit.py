@@ -26,6 +26,19 @@ def _theta(glam, res, l, p):
     return glam.from_colmajor(res.theta[l], p)
 
 
+_ORACLE_PATHS = {}
+
+
+def _oracle_path(key, fam, d, **kw):
+    """The oracle's own lambda path on d (its lambda_max and grid, warm starts from its own previous
+    model, never from a GPU iterate), computed once per key and shared by the dtype cases."""
+    if key not in _ORACLE_PATHS:
+        lams, ths, infos, lm = O.fit_path(fam, d.X, d.Y, **kw)
+        assert all(i.converged for i in infos), key
+        _ORACLE_PATHS[key] = (np.asarray(lams), ths, lm)
+    return _ORACLE_PATHS[key]
+
+
 def _check_model(d, fam, th, lam, lm, tol, a=None, ref=None, theta_tol=None):
     g = O.smooth_gradient(fam, d.X, th, d.Y, a)
     kkt = O.kkt_residual(th, g, lam, lm)
@@ -74,11 +87,11 @@ def test_gaussian_path_small(dt):
     np.testing.assert_allclose(res.lambdas, O.lambda_grid(lm, 12, 1e-3), rtol=1e-12)
     assert res.n_done == 12
     assert np.all(res.theta[0].cpu().numpy() == 0.0)
+    olams, oths, _ = _oracle_path("gauss21", "gaussian", d, nlambda=12, ratio=1e-3, tol=1e-9)
     for l in [1, 5, 11]:
         lam = res.lambdas[l]
         th = _theta(glam, res, l, d.p)
-        ref, info = O.gdpg("gaussian", d.X, d.Y, lam, lm, theta0=th, tol=1e-11)
-        _check_model(d, "gaussian", th, lam, lm, 1e-6, ref=ref, theta_tol=1e-3)
+        _check_model(d, "gaussian", th, lam, lm, 1e-6, ref=oths[l], theta_tol=1e-3)
 
 
 @pytest.mark.parametrize("dt", [0, 1, 2])
@@ -91,11 +104,12 @@ def test_poisson_path_small(dt):
     lm = O.lambda_max("poisson", d.X, d.Y)
     assert abs(res.lambda_max - lm) <= 1e-12 * lm
     assert res.n_done == 6
+    olams, oths, _ = _oracle_path("pois_c3small", "poisson", d, nlambda=6, ratio=1e-2, tol=1e-10, max_outer=200)
+    np.testing.assert_allclose(res.lambdas, olams, rtol=1e-12)
     for l in [1, 3, 5]:
         lam = res.lambdas[l]
         th = _theta(glam, res, l, d.p)
-        ref, info = O.gdpg("poisson", d.X, d.Y, lam, lm, theta0=th, tol=1e-10, max_outer=200)
-        _check_model(d, "poisson", th, lam, lm, 1e-6, ref=ref, theta_tol=1e-3)
+        _check_model(d, "poisson", th, lam, lm, 1e-6, ref=oths[l], theta_tol=1e-3)
 
 
 def test_observation_weights_and_penalty_weights():
@@ -169,7 +183,8 @@ def test_nu_backtracking(fam, dt):
                         raise_on_error=False)
     assert res.code == 0, (res.code, res.status)
     th = _theta(glam, res, 1, d.p)
-    ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200)
+    ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, tol=1e-11, max_outer=200)   # the oracle from zero
+    assert info.converged
     _check_model(d, fam, th, lam, lm, 1e-7, ref=ref, theta_tol=1e-4)
 
 
@@ -201,12 +216,14 @@ def test_gram_inner_loop_path(dt):
     d = inputs.random_problem((23, 19, 37), (9, 7, 12), seed=21)
     print(f"gram path dt={dt}", flush=True)
     Xd, Yd, _ = _dev(glam, d)
-    res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=8, lambda_min_ratio=1e-3, dtype=dt, kkt_tol=1e-6,
+    res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=12, lambda_min_ratio=1e-3, dtype=dt, kkt_tol=1e-6,
                         inner="gram")
     lm = O.lambda_max("gaussian", d.X, d.Y)
-    ref = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=8, lambda_min_ratio=1e-3, dtype=0, kkt_tol=1e-9)
-    for l in range(8):
-        _check_model(d, "gaussian", _theta(glam, res, l, d.p), res.lambdas[l], lm, 1e-6, ref=_theta(glam, ref, l, d.p))
+    olams, oths, _ = _oracle_path("gauss21", "gaussian", d, nlambda=12, ratio=1e-3, tol=1e-9)
+    np.testing.assert_allclose(res.lambdas, olams, rtol=1e-12)
+    for l in range(12):
+        _check_model(d, "gaussian", _theta(glam, res, l, d.p), res.lambdas[l], lm, 1e-6, ref=oths[l],
+                     theta_tol=1e-3 if l else None)
 
 
 def test_gram_inner_loop_full_tiles_bf16():
@@ -285,7 +302,9 @@ def test_elastic_net_path(fam, dt, nu):
         assert O.kkt_residual(th, g, lam, lm, alpha=alpha) <= 1e-7
         F1 = O.objective(fam, d.X, th, d.Y, lam, alpha=alpha)
         assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
-        ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200, alpha=alpha)
+        olams, oths, _ = _oracle_path(f"enet_{fam}", fam, d, nlambda=5, ratio=0.02, tol=1e-11, max_outer=200,
+                                      alpha=alpha)
+        ref = oths[l]
         F2 = O.objective(fam, d.X, ref, d.Y, lam, alpha=alpha)
         assert (F1 - F2) / abs(F2) <= 1e-8
         assert rel_inf(th, ref) <= 1e-4
@@ -328,7 +347,8 @@ def test_binomial_gamma_paths(fam, dt, nu):
         assert O.kkt_residual(th, g, lam, lm) <= 1e-7
         F1 = O.objective(fam, d.X, th, d.Y, lam)
         assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
-        ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, theta0=th, tol=1e-11, max_outer=200)
+        olams, oths, _ = _oracle_path(f"fam33_{fam}", fam, d, nlambda=5, ratio=0.02, tol=1e-11, max_outer=200)
+        ref = oths[l]
         F2 = O.objective(fam, d.X, ref, d.Y, lam)
         assert (F1 - F2) / abs(F2) <= 1e-8
         assert rel_inf(th, ref) <= 1e-4
@@ -463,9 +483,9 @@ def test_kron_weight_inner_loop(fam, dt):
         th = _theta(glam, res, l, d.p)
         g = O.smooth_gradient(fam, d.X, th, d.Y)
         assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
-        ref, info = O.gdpg(fam, d.X, d.Y, res.lambdas[l], lm, theta0=th, tol=1e-11, max_outer=200)
+        olams, oths, _ = _oracle_path(f"kron38_{fam}", fam, d, nlambda=4, ratio=0.05, tol=1e-11, max_outer=200)
         F1 = O.objective(fam, d.X, th, d.Y, res.lambdas[l])
-        F2 = O.objective(fam, d.X, ref, d.Y, res.lambdas[l])
+        F2 = O.objective(fam, d.X, oths[l], d.Y, res.lambdas[l])
         assert (F1 - F2) / abs(F2) <= 1e-8
     with pytest.raises(glam.GlamError):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="kron", nu=0.5)
@@ -559,9 +579,9 @@ def test_mode_order_is_chosen_by_the_library(fam):
         assert O.kkt_residual(a, g, r1.lambdas[l], lm) <= 1e-7
 
 
-@pytest.mark.parametrize("fam,dt", [("poisson", 1), ("binomial", 1), ("poisson", 0)])
+@pytest.mark.parametrize("fam,dt", [("poisson", 1), ("binomial", 1), ("poisson", 0), ("poisson", 2)])
 def test_unit_weight_inner_loop(fam, dt):
-    """inner="one": unit IRLS weights in every outer step's model (Sec. 3's constant weights), the
+    """inner="one": unit IRLS weights in every outer step's model (the constant weights of Sec. 5, after the corollary to Theorem 2), the
     p-sized Gram inner loop for a weighted family; the FP64 gradient, Armijo rule and KKT test are
     unchanged, so the path reaches the PMLE: the oracle's KKT and objective on every model."""
     torch, glam = need_gpu()
@@ -578,9 +598,12 @@ def test_unit_weight_inner_loop(fam, dt):
         th = _theta(glam, res, l, d.p)
         g = O.smooth_gradient(fam, d.X, th, d.Y)
         assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
-        ref, info = O.gdpg(fam, d.X, d.Y, res.lambdas[l], lm, theta0=th, tol=1e-11, max_outer=200)
+        # the oracle's own path (exact weights: the same PMLE), from zero and its own warm starts
+        olams, oths, _ = _oracle_path(f"unit47_{fam}", fam, d, nlambda=4, ratio=0.05, tol=1e-11, max_outer=200)
         F1 = O.objective(fam, d.X, th, d.Y, res.lambdas[l])
-        F2 = O.objective(fam, d.X, ref, d.Y, res.lambdas[l])
+        F2 = O.objective(fam, d.X, oths[l], d.Y, res.lambdas[l])
         assert (F1 - F2) / abs(F2) <= 1e-8
     with pytest.raises(glam.GlamError):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="one", nu=0.5)
+    with pytest.raises(glam.GlamError):   # unit weights take no prior weights
+        glam.fit_path(Xd, Yd, d.n, d.p, fam, obs_w=torch.ones_like(Yd), nlambda=2, inner="one")

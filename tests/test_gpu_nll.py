@@ -72,7 +72,9 @@ def test_nll_gradient_central_differences_f64():
 
 @pytest.mark.parametrize("dt", [1, 2])
 def test_nll_full_size_workload(dt):
-    """n=(128,128,256), p=(32,32,64): value and gradient vs the FP64 oracle."""
+    """n=(128,128,256), p=(32,32,64): value and gradient vs the FP64 oracle, the gradient both
+    entrywise on the scale of its terms and as the relative sup norm ||g - g_ref|| / ||g_ref||
+    (BF16 3e-2, FP32 1e-5), with an upstream gradient other than 1 (loss scaled by -1.75)."""
     torch, glam = need_gpu()
     d = inputs.config_c5()
     n, p = d.n, d.p
@@ -80,10 +82,72 @@ def test_nll_full_size_workload(dt):
     Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
     Yd = glam.to_device_colmajor(d.Y, 0)
     b = glam.to_device_colmajor(beta, dt).requires_grad_(True)
+    c = -1.75
     loss = glam.PoissonNLL.apply(b, Xd, Yd, n, p, dt)
-    loss.backward()
+    (c * loss).backward()
     torch.cuda.synchronize()
-    _check(glam, d, beta, float(loss.detach()), b.grad, dt)
+    g = glam.from_colmajor(b.grad.double(), p) / c
+    _check(glam, d, beta, float(loss.detach()), torch.from_numpy(O.vec(g)).to(b.grad.device), dt)
+    gref = O.poisson_nll_grad(d.X, beta, d.Y)
+    err = rel_inf(g, gref)
+    print(f"NLL gradient dt={dt}: relative sup-norm error {err:.3e} (bar {TOL[dt]:.0e})", flush=True)
+    assert err <= TOL[dt], err
+
+
+_FD = {}
+
+
+def _oracle_fd_probes():
+    """Central differences (h = 1e-6) of the oracle's FP64 loss at the n=(128,128,256) evaluation point,
+    along 16 random unit directions and 16 random coordinates; and the same probes of the oracle's
+    analytic gradient (whose difference to the FD values is the FD's own error at this size)."""
+    if not _FD:
+        d = inputs.config_c5()
+        beta = d.extra["beta"]
+        rng = np.random.default_rng(11)
+        P = int(np.prod(d.p))
+        dirs = [v / np.linalg.norm(v) for v in (rng.standard_normal(P) for _ in range(16))]
+        for m in rng.choice(P, size=16, replace=False):
+            e = np.zeros(P)
+            e[m] = 1.0
+            dirs.append(e)
+        h = 1e-6
+        fd = []
+        for v in dirs:
+            V = O.unvec(v, d.p)
+            fd.append((O.poisson_nll(d.X, beta + h * V, d.Y) - O.poisson_nll(d.X, beta - h * V, d.Y)) / (2 * h))
+        ga = O.vec(O.poisson_nll_grad(d.X, beta, d.Y))
+        _FD.update(d=d, dirs=np.array(dirs), fd=np.array(fd), analytic=np.array([ga @ v for v in dirs]))
+    return _FD
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_nll_gradient_vs_central_differences_full_size(dt):
+    """The device gradient (BF16 or FP32 chain) against central differences of the oracle's FP64 loss
+    (h = 1e-6) along 16 random unit directions and 16 random coordinates, at the full size.  The
+    error is taken relative to the largest probe (sup norm over the 32 probes).  At this size the
+    loss (about 3) moves by about 1e-12 over +-h, a few thousand ulps, so the differences themselves
+    resolve the derivative to about 1e-3 of that scale: the bar is the dtype's tolerance (BF16 3e-2)
+    or four times the differences' own measured error (the FP32 1e-5 bar is then the oracle-gradient
+    comparison of test_nll_full_size_workload)."""
+    torch, glam = need_gpu()
+    F = _oracle_fd_probes()
+    d = F["d"]
+    Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    b = glam.to_device_colmajor(d.extra["beta"], dt).requires_grad_(True)
+    glam.PoissonNLL.apply(b, Xd, Yd, d.n, d.p, dt).backward()
+    torch.cuda.synchronize()
+    g = b.grad.double().cpu().numpy()
+    probes = F["dirs"] @ g
+    scale = float(np.max(np.abs(F["fd"])))
+    fd_err = float(np.max(np.abs(F["analytic"] - F["fd"]))) / scale
+    err = float(np.max(np.abs(probes - F["fd"]))) / scale
+    bar = max(TOL[dt], 4.0 * fd_err)
+    print(f"NLL central differences dt={dt}: error {err:.3e}, the differences' own error {fd_err:.3e}, "
+          f"bar {bar:.3e}", flush=True)
+    assert fd_err <= 1e-2   # the probes resolve the derivative (BF16's bar is 3x above this)
+    assert err <= bar, (err, bar)
 
 
 @pytest.mark.parametrize("dt", [0, 1, 2])

@@ -99,6 +99,17 @@ MUTANTS = {
     "lmax_no_n": ("lambda_max",
                   lambda orig: (lambda fam, Xs, Y, a=None, pen_w=None: orig(fam, Xs, Y, a, pen_w) * Y.size),
                   lambda: [lambda: P.test_lambda_max_gives_zero_solution("gaussian")]),
+    # lambda grid with the exponent l / nlambda (one step short of lambda_min)
+    "grid_off_by_one": ("lambda_grid",
+                        lambda orig: (lambda lm, nl, ratio: lm * ratio ** (np.arange(nl) / nl) if nl > 1
+                                      else orig(lm, nl, ratio)),
+                        lambda: [lambda: P.test_lambda_grid_end_point_and_log_spacing(100, 1e-4)]),
+    # Poisson NLL without the 1/n scale, or with +y eta
+    "nll_no_n": ("poisson_nll", lambda orig: (lambda Xs, beta, Y: orig(Xs, beta, Y) * Y.size),
+                 lambda: [P.test_poisson_nll_value_on_the_explicit_design]),
+    "nll_sign_y": ("poisson_nll",
+                   lambda orig: (lambda Xs, beta, Y: float(np.sum(np.exp(O.H(Xs, beta)) + Y * O.H(Xs, beta))) / Y.size),
+                   lambda: [P.test_poisson_nll_constant_predictor_closed_form]),
     # Lipschitz bound with a sum of spectral radii instead of the product
     "lhat_sum": ("lipschitz_bound",
                  lambda orig: (lambda Xs, w, n: float(np.max(w)) * float(np.sum(O.spectral_radii(Xs))) / n),

@@ -555,6 +555,29 @@ def test_nu_backtracking_reaches_same_solution():
     np.testing.assert_allclose(O.vec(th2), O.vec(th1), atol=1e-8 * np.max(np.abs(th1)))
 
 
+def test_armijo_takes_no_step_along_a_non_descent_direction(monkeypatch):
+    """Sec. 5: the Armijo rule presumes a descent direction (Delta_k < 0) and Theorem 2 then gives a
+    nonincreasing F.  An inexact inner solve that returns the reflection 2 theta^k - x of the model's
+    minimiser x gives Delta_k > 0 (J is convex); no step may be taken along it, so F stays put."""
+    d = inputs.random_problem((7, 6, 5), (4, 3, 3), family="poisson", seed=16, scale=0.4, basis="gauss")
+    lm = O.lambda_max("poisson", d.X, d.Y)
+    orig = O.inner_pg
+
+    def reflected(Xs, V, cz, x0, *args, **kw):
+        x, nin, trace = orig(Xs, V, cz, x0, *args, **kw)
+        return 2.0 * x0 - x, nin, trace
+
+    th_ok, info_ok = O.gdpg("poisson", d.X, d.Y, 0.1 * lm, lm, tol=1e-10, max_outer=3)
+    assert info_ok.alphas[0] > 0.0   # the unplanted first step moves
+    monkeypatch.setattr(O, "inner_pg", reflected)
+    th0 = np.full(d.p, 0.05)
+    th, info = O.gdpg("poisson", d.X, d.Y, 0.1 * lm, lm, theta0=th0, tol=1e-10, max_outer=3)
+    assert info.alphas == [0.0, 0.0, 0.0]
+    assert np.array_equal(th, th0)
+    hist = info.objective_history
+    assert all(b <= a for a, b in zip(hist, hist[1:]))
+
+
 # ---------------------------------------------------------------- path -----
 def test_path_warm_start_and_kkt():
     d = inputs.random_problem((6, 6, 6), (4, 4, 4), seed=11)
@@ -567,6 +590,30 @@ def test_path_warm_start_and_kkt():
         assert O.kkt_residual(th, g, lam, lm) <= 1e-10
     nnz = [np.count_nonzero(t) for t in thetas]
     assert nnz[-1] > nnz[1]
+
+
+@pytest.mark.parametrize("nlambda,ratio", [(100, 1e-4), (50, 1e-4), (12, 1e-3), (2, 0.5)])
+def test_lambda_grid_end_point_and_log_spacing(nlambda, ratio):
+    """Sec. 6.4 (R3): the path starts at lambda_max, ends at lambda_min = ratio * lambda_max and its
+    points are equally spaced in log lambda.  The reference is built by repeated multiplication with
+    the common ratio q, q^(nlambda - 1) = ratio, not by the oracle's closed form."""
+    lm = 0.7311
+    grid = O.lambda_grid(lm, nlambda, ratio)
+    assert grid.shape == (nlambda,)
+    assert grid[0] == lm
+    assert abs(grid[-1] - ratio * lm) <= 1e-13 * lm
+    q = math.exp(math.log(ratio) / (nlambda - 1))
+    ref = [lm]
+    for _ in range(nlambda - 1):
+        ref.append(ref[-1] * q)
+    np.testing.assert_allclose(grid, ref, rtol=1e-12)
+    steps = np.diff(np.log(grid))
+    np.testing.assert_allclose(steps, math.log(ratio) / (nlambda - 1), rtol=1e-9)
+
+
+def test_lambda_grid_single_value():
+    """A one-model path is lambda_max alone (the zero solution)."""
+    assert list(O.lambda_grid(2.5, 1, 1e-4)) == [2.5]
 
 
 def test_path_early_exit_returns_preceding_models():
@@ -595,6 +642,28 @@ def test_poisson_nll_gradient_central_differences():
     np.testing.assert_allclose(O.vec(g), Xd.T @ (np.exp(eta) - O.vec(d.Y)) / Xd.shape[0], rtol=1e-12, atol=1e-14)
 
 
+def test_poisson_nll_value_on_the_explicit_design():
+    """Sec. 2, eqs. (two)-(four) with a = 1 and log y! dropped: L(beta) = (1/n) sum_i (e^{eta_i} -
+    y_i eta_i) with eta = X beta on the explicit Kronecker design (App. A)."""
+    d = inputs.random_problem((6, 5, 4), (3, 3, 2), family="poisson", seed=14, scale=0.3, basis="gauss")
+    beta = np.random.default_rng(4).normal(0, 0.3, d.p)
+    Xd = O.kron_design(d.X)
+    eta = Xd @ O.vec(beta)
+    y = O.vec(d.Y)
+    ref = sum(math.exp(e) - yi * e for e, yi in zip(eta, y)) / len(y)
+    assert abs(O.poisson_nll(d.X, beta, d.Y) - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_poisson_nll_constant_predictor_closed_form():
+    """Clamped B-spline factors are a partition of unity, so beta = c 1 gives eta = c everywhere and
+    L = e^c - c mean(y) in closed form."""
+    d = inputs.random_problem((9, 7, 8), (5, 4, 6), family="poisson", seed=15, scale=0.3)
+    for c in (-0.4, 0.0, 1.3):
+        beta = np.full(d.p, c)
+        ref = math.exp(c) - c * float(np.mean(d.Y))
+        assert abs(O.poisson_nll(d.X, beta, d.Y) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
 # ---------------------------------------------------------- rounding -------
 def test_bf16_rounding_matches_torch():
     torch = pytest.importorskip("torch")
@@ -604,7 +673,7 @@ def test_bf16_rounding_matches_torch():
 
 
 def test_unit_weights_gaussian_is_the_exact_form():
-    """Sec. 3 (constant weights): the Gaussian IRLS weights are already 1, so weights="one" takes
+    """Sec. 5, after the corollary to Theorem 2 (constant weights): the Gaussian IRLS weights are already 1, so weights="one" takes
     the very same steps as the exact weights."""
     d = inputs.random_problem((7, 6, 5), (4, 4, 3), family="gaussian", seed=18, basis="gauss")
     lm = O.lambda_max("gaussian", d.X, d.Y)
@@ -615,7 +684,7 @@ def test_unit_weights_gaussian_is_the_exact_form():
 
 @pytest.mark.parametrize("fam", ["poisson", "binomial"])
 def test_unit_weights_reach_the_same_pmle(fam):
-    """Sec. 3: any strictly positive continuous weights give a convergent GD-PG; with w_i = 1 the
+    """Sec. 5, after the corollary to Theorem 2: any strictly positive continuous weights give a convergent GD-PG; with w_i = 1 the
     quadratic models differ from the IRLS ones but the minimiser reached is the same."""
     d = inputs.random_problem((7, 6, 5), (4, 4, 3), family=fam, seed=19, scale=0.5, basis="gauss")
     lm = O.lambda_max(fam, d.X, d.Y)
