@@ -104,6 +104,21 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
                      const void* Theta, void* Eta, int dtype, void* workspace,
                      size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): glam_rho_forward with its workspace taken from a static
+ * device array of the library, GLAM_STATIC_SCRATCH_BYTES on every GPU it runs on (held until the
+ * process ends); the call itself allocates nothing.  Arguments, results and the mode reordering are
+ * those of glam_rho_forward; the caller still provides Theta and Eta.
+ * Sharing: every call on one GPU uses that GPU's one array, so calls on a GPU must not overlap
+ * (two streams, or two host threads, in flight at once race on it); calls queued one after another
+ * on one stream are fine.  Nothing in the array needs to start at any value.
+ * Errors: those of glam_rho_forward, GLAM_EINVAL when glam_rho_workspace_size(d, n, p, dtype)
+ * exceeds GLAM_STATIC_SCRATCH_BYTES (glam_last_error says how much the sizes need), and
+ * GLAM_EDEVICE if the array's device address cannot be looked up. */
+#define GLAM_STATIC_SCRATCH_BYTES (32u << 20)
+int glam_rho_forward_static(int d, const int64_t* n, const int64_t* p, const void* const* X,
+                            const void* Theta, void* Eta, int dtype, void* stream);
+
 /* Out = G(<X_j>, U) = rho(X_3^T, rho(X_2^T, rho(X_1^T, U)))  (eq. nineteen),
  * i.e. vec(Out) = X^T vec(U).
  *   U   : device, n_1 x n_2 x n_3 of `dtype`.

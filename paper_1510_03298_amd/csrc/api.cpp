@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -155,6 +156,36 @@ static WsLayout ws_layout(const Geom& G, int dt) {
   return W;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free forward transform: one array per GPU, in the
+// library's code object, held until the process ends.  Host code never passes the
+// symbol itself to a kernel (on the host it only names a shadow); it looks up each
+// device's address once, with that device current, and uses that pointer.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[GLAM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on that device).
+static int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(GLAM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GLAM_EDEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(GLAM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GLAM_OK;
+}
+
 #define HIPCHK(expr)                                                           \
   do {                                                                         \
     hipError_t e_ = (expr);                                                    \
@@ -254,6 +285,24 @@ int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* cons
     HIPCHK(launch_permute3_es((int)oes, reg_n, Eta_out, nr, qi, s));
   }
   return GLAM_OK;
+}
+
+int glam_rho_forward_static(int d, const int64_t* n, const int64_t* p, const void* const* X, const void* Theta,
+                            void* Eta, int dtype, void* stream) {
+  g_err.clear();
+  RhoPlan R;
+  const int st = plan_rho(d, n, p, dtype, &R);
+  if (st) return st;
+  const size_t need = rho_ws_total(R, dtype);
+  if (need > (size_t)GLAM_STATIC_SCRATCH_BYTES)
+    return fail(GLAM_EINVAL, "these sizes need " + std::to_string(need) + " bytes of workspace, more than the " +
+                                 std::to_string((size_t)GLAM_STATIC_SCRATCH_BYTES) + "-byte static scratch");
+  void* ws = nullptr;
+  const int sa = scratch_address(&ws);
+  if (sa) return sa;
+  // the same kernels as glam_rho_forward: every workspace region it reads is written first on
+  // the stream (packing zero-fills the padding), so the previous call's contents do not matter
+  return glam_rho_forward(d, n, p, X, Theta, Eta, dtype, ws, (size_t)GLAM_STATIC_SCRATCH_BYTES, stream);
 }
 
 int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* U_in, void* Out_p,

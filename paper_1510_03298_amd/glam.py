@@ -87,6 +87,8 @@ glam_rho_workspace_size = _sig("glam_rho_workspace_size", ctypes.c_size_t, [ctyp
 glam_rho_forward = _sig("glam_rho_forward", ctypes.c_int,
                         [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_int, _vp,
                          ctypes.c_size_t, _vp])
+glam_rho_forward_static = _sig("glam_rho_forward_static", ctypes.c_int,
+                               [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_int, _vp])
 glam_rho_adjoint = _sig("glam_rho_adjoint", ctypes.c_int,
                         [ctypes.c_int, _i64p, _i64p, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_int, _vp,
                          ctypes.c_size_t, _vp])
@@ -112,7 +114,7 @@ glam_poisson_nll_backward_packed = _sig("glam_poisson_nll_backward_packed", ctyp
                                         [_i64p, _i64p, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp])
 
 EXPORTED = ["glam_status_string", "glam_last_error", "glam_version", "glam_rho_workspace_size",
-            "glam_rho_forward", "glam_rho_adjoint", "glam_fit_path", "glam_fit_batched", "glam_nll_workspace_size",
+            "glam_rho_forward", "glam_rho_forward_static", "glam_rho_adjoint", "glam_fit_path", "glam_fit_batched", "glam_nll_workspace_size",
             "glam_poisson_nll_forward", "glam_poisson_nll_backward", "glam_nll_packed_workspace_size",
             "glam_poisson_nll_pack", "glam_poisson_nll_forward_packed", "glam_poisson_nll_backward_packed"]
 
@@ -199,6 +201,19 @@ def rho_forward(Xs, theta, n, p, dtype, eta=None, workspace=None, stream=None):
     xp = _ptrs(Xs)
     _check(glam_rho_forward(len(n), nn, pp, xp, theta.data_ptr(), eta.data_ptr(), int(dtype), workspace.data_ptr(),
                             ws_bytes, _stream_ptr(stream)), "glam_rho_forward")
+    return eta
+
+
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def rho_forward_static(Xs, theta, n, p, dtype, eta, stream=None):
+    """eta = H(<X_j>, theta) into the caller's eta, with the library's static device scratch as the
+    workspace (no allocation in the call; calls on one GPU must not overlap)."""
+    nn, pp = _sizes(n, p)
+    xp = _ptrs(Xs)
+    _check(glam_rho_forward_static(len(n), nn, pp, xp, theta.data_ptr(), eta.data_ptr(), int(dtype),
+                                   _stream_ptr(stream)), "glam_rho_forward_static")
     return eta
 
 

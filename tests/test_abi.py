@@ -192,3 +192,18 @@ def test_packed_nll_workspace_and_argument_checks():
     assert rc == glam.GLAM_EINVAL and b"workspace" in glam.glam_last_error()
     rc = glam.glam_poisson_nll_backward_packed(n, p, ptr, ptr, None, glam.BF16, ptr, wp, None)
     assert rc == glam.GLAM_EINVAL and b"NULL" in glam.glam_last_error()
+
+
+def test_static_forward_refuses_oversize_and_bad_arguments_on_the_host():
+    """glam_rho_forward_static checks sizes against its static scratch before any device call."""
+    from paper_1510_03298_amd import glam
+    n, p = _sizes((600, 100, 100), (40, 30, 30))     # reordered (mode 1 last): a 48 MB region for eta
+    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) > glam.STATIC_SCRATCH_BYTES
+    X = (ctypes.c_void_p * 3)(None, None, None)
+    rc = glam.glam_rho_forward_static(3, n, p, X, None, None, glam.F64, None)
+    assert rc == glam.GLAM_EINVAL and b"static scratch" in glam.glam_last_error()
+    ok_n, ok_p = _sizes((100, 100, 1000), (30, 30, 200))
+    for dt in (glam.F64, glam.F32, glam.BF16):   # the headline sizes fit in every dtype
+        assert 0 < glam.glam_rho_workspace_size(3, ok_n, ok_p, dt) <= glam.STATIC_SCRATCH_BYTES
+    assert glam.glam_rho_forward_static(3, ok_n, ok_p, X, None, None, 7, None) == glam.GLAM_EINVAL
+    assert glam.glam_rho_forward_static(4, ok_n, ok_p, X, None, None, glam.F32, None) == glam.GLAM_EINVAL
