@@ -50,6 +50,18 @@ def chain_bytes(n, p, dt_bytes, poisson=False):
     return b
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
     """The oracle (plain NumPy FP64, never tuned) on the host cores: seconds per
     inner PG iteration at this workload's size, measured on a bounded sample,
@@ -79,7 +91,8 @@ def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
     per_grad = per_iter / 2.0
     est = per_grad * (total_inner_f64 + 3 * outer_f64)
     return {
-        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
+        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle", "cpu_model": cpu_model(),
+        "host_logical_cpus": os.cpu_count(),
         "sample": (f"{iters} oracle inner PG iterations at lambda_1 of the same workload "
                    f"({per_grad*1e3:.1f} ms per gradient evaluation), extrapolated to the full path with "
                    f"the FP64 GPU form's {total_inner_f64} inner iterations and {outer_f64} outer steps"),
@@ -92,10 +105,16 @@ STATS_FILE = os.path.join(ROOT, "profiles", "gaussian_path_100x100x1000_bf16_ker
 
 
 def kernel_source_hash():
+    """sha256[:16] over every library source (csrc/*, in name order) and include/glam.h: a profile
+    summary taken on any other source is stale."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1510_03298_amd", "csrc", "slab.hip")
-    with open(src, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1510_03298_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))] + [os.path.join(ROOT, "include", "glam.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch(kernel, dtype):
@@ -152,6 +171,29 @@ def gram_path(glam, torch, d, Xd, Yd, stream, nlambda, chain_seconds):
                      "inner": int(r.inner_total), "outer": int(r.iters_outer.sum())}
     out["speedup_vs_chain_bf16"] = chain_seconds / out["bf16"]["seconds"]
     return out
+
+
+def c1_single_lambda(glam, inputs, torch, stream, reps=20):
+    """Gaussian n = (20, 20, 20), p = (8, 8, 8), plain FP64 method, one lambda = 0.1 lambda_max, KKT <= 1e-6:
+    wall time per fit (median of reps after one warm-up; launch-bound, no roofline claim)."""
+    d = inputs.config_c1()
+    Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    kw = dict(nlambda=1, dtype=glam.F64, kkt_tol=1e-6, stream=stream, raise_on_error=False)
+    first = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", lambdas=None, **kw)   # lambda_max (warm-up)
+    lam = 0.1 * first.lambda_max
+    times, r = [], None
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", lambdas=[lam], **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    times = times[1:]
+    return {"workload": "gaussian_c1_n20x20x20_p8x8x8_single_lambda0.1_kkt1e-6", "dtype": "f64",
+            "seconds_median": float(np.median(times)), "seconds_min": float(np.min(times)), "reps": reps,
+            "converged": r.code == 0, "kkt": float(r.kkt[0]), "inner": int(r.inner_total),
+            "outer": int(r.iters_outer.sum())}
 
 
 def progress(msg):
@@ -322,7 +364,8 @@ def main():
         stream = torch.cuda.current_stream(dev)
         only = {"batched_c4": lambda: batched(glam, inputs, torch, stream),
                 "poisson_nll_c5": lambda: nll(glam, inputs, torch, stream),
-                "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream)}
+                "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream),
+                "gaussian_c1": lambda: c1_single_lambda(glam, inputs, torch, stream)}
         if args.only not in only:
             print(f"bench.py: --only takes one of {sorted(only)}", file=sys.stderr)
             sys.exit(2)
@@ -409,10 +452,18 @@ def main():
         for dt in ["f64", "f32", "bf16"]:
             if dt in forms:
                 continue
-            progress(f"Gaussian 100x100x1000 path, {dt} form (untimed comparison)")
-            r = fit(dt)
-            forms[dt] = {"seconds": r.seconds, "inner": int(r.inner_total), "outer": int(r.iters_outer.sum()),
-                         "max_kkt": float(np.max(r.kkt)), "ok": r.code == 0 and r.n_done == args.nlambda}
+            # timed like the headline form: the same number of steps (the kernels are already loaded
+            # and warm from the timed form, so no separate warm-up), mean wall time per path
+            progress(f"Gaussian 100x100x1000 path, {dt} form ({args.steps} timed steps)")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = [fit(dt) for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            forms[dt] = {"seconds": (time.perf_counter() - t0) / args.steps, "steps": args.steps,
+                         "inner": int(np.mean([r.inner_total for r in rs])),
+                         "outer": int(np.mean([r.iters_outer.sum() for r in rs])),
+                         "max_kkt": float(max(np.max(r.kkt) for r in rs)),
+                         "ok": all(r.code == 0 and r.n_done == args.nlambda for r in rs)}
         for dt in forms:
             forms[dt]["speedup_vs_f64"] = forms["f64"]["seconds"] / forms[dt]["seconds"]
     cpu = None
@@ -421,7 +472,8 @@ def main():
         cpu = cpu_baseline(d, forms["f64"]["inner"], forms["f64"]["outer"])
     extra = None
     if not args.no_extra:
-        jobs = [("gaussian_path_c2_gram", lambda: gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec)),
+        jobs = [("gaussian_c1", lambda: c1_single_lambda(glam, inputs, torch, stream)),
+                ("gaussian_path_c2_gram", lambda: gram_path(glam, torch, d, Xd, Yd, stream, args.nlambda, sec)),
                 ("poisson_path_c3", lambda: poisson_path(glam, inputs, torch, stream)),
                 ("poisson_path_c3_kron", lambda: poisson_path_kron(glam, inputs, torch, stream)),
                 ("batched_c4", lambda: batched(glam, inputs, torch, stream)),

@@ -347,7 +347,10 @@ def test_binomial_gamma_paths(fam, dt, nu):
         assert O.kkt_residual(th, g, lam, lm) <= 1e-7
         F1 = O.objective(fam, d.X, th, d.Y, lam)
         assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
-        olams, oths, _ = _oracle_path(f"fam33_{fam}", fam, d, nlambda=5, ratio=0.02, tol=1e-11, max_outer=200)
+        # Gamma-log's Fisher-scoring outer loop converges linearly and stalls near 1e-9 in FP64
+        # (the oracle's own KKT), so its reference path is solved to 1e-9, still 100x inside the bar
+        otol = 1e-9 if fam == "gamma" else 1e-11
+        olams, oths, _ = _oracle_path(f"fam33_{fam}", fam, d, nlambda=5, ratio=0.02, tol=otol, max_outer=400)
         ref = oths[l]
         F2 = O.objective(fam, d.X, ref, d.Y, lam)
         assert (F1 - F2) / abs(F2) <= 1e-8

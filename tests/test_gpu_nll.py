@@ -90,20 +90,42 @@ def test_nll_full_size_workload(dt):
     _check(glam, d, beta, float(loss.detach()), torch.from_numpy(O.vec(g)).to(b.grad.device), dt)
     gref = O.poisson_nll_grad(d.X, beta, d.Y)
     err = rel_inf(g, gref)
-    print(f"NLL gradient dt={dt}: relative sup-norm error {err:.3e} (bar {TOL[dt]:.0e})", flush=True)
-    assert err <= TOL[dt], err
+    print(f"NLL gradient dt={dt}: relative sup-norm error {err:.3e} against the exact inputs", flush=True)
+    if dt == 1:
+        assert err <= TOL[dt], err
+    else:
+        # BF16 (R10): the inputs themselves carry 8-bit mantissas.  At this evaluation point, 0.05 from
+        # the optimum, the gradient is small next to its terms, and rounding beta and X to BF16 alone
+        # moves the exact FP64 gradient by 6% in this norm.  The bar is therefore taken against the
+        # oracle fed the same RNE-rounded inputs (the tight BF16 form), and the distance to the
+        # unrounded inputs' gradient is only bounded by that input effect plus the bar.
+        Xr = [O.round_to_bf16(X) for X in d.X]
+        br = O.round_to_bf16(beta)
+        g_in = O.poisson_nll_grad(Xr, br, d.Y)
+        err_r = rel_inf(g, g_in)
+        in_eff = rel_inf(g_in, gref)
+        print(f"NLL gradient BF16: {err_r:.3e} against the oracle on the rounded inputs (bar {TOL[dt]:.0e}); "
+              f"input rounding alone moves the gradient by {in_eff:.3e}", flush=True)
+        assert err_r <= TOL[dt], err_r
+        assert err <= in_eff + TOL[dt], (err, in_eff)
 
 
 _FD = {}
 
 
-def _oracle_fd_probes():
+def _oracle_fd_probes(rounded_inputs=False):
     """Central differences (h = 1e-6) of the oracle's FP64 loss at the n=(128,128,256) evaluation point,
     along 16 random unit directions and 16 random coordinates; and the same probes of the oracle's
-    analytic gradient (whose difference to the FD values is the FD's own error at this size)."""
-    if not _FD:
+    analytic gradient (whose difference to the FD values is the FD's own error at this size).
+    rounded_inputs: the loss of the BF16-rounded (RNE) factors and beta, the values a BF16 chain
+    is given (R10)."""
+    key = bool(rounded_inputs)
+    if key not in _FD:
         d = inputs.config_c5()
         beta = d.extra["beta"]
+        if rounded_inputs:
+            d.X = [O.round_to_bf16(X) for X in d.X]
+            beta = O.round_to_bf16(beta)
         rng = np.random.default_rng(11)
         P = int(np.prod(d.p))
         dirs = [v / np.linalg.norm(v) for v in (rng.standard_normal(P) for _ in range(16))]
@@ -117,8 +139,8 @@ def _oracle_fd_probes():
             V = O.unvec(v, d.p)
             fd.append((O.poisson_nll(d.X, beta + h * V, d.Y) - O.poisson_nll(d.X, beta - h * V, d.Y)) / (2 * h))
         ga = O.vec(O.poisson_nll_grad(d.X, beta, d.Y))
-        _FD.update(d=d, dirs=np.array(dirs), fd=np.array(fd), analytic=np.array([ga @ v for v in dirs]))
-    return _FD
+        _FD[key] = dict(d=d, dirs=np.array(dirs), fd=np.array(fd), analytic=np.array([ga @ v for v in dirs]))
+    return _FD[key]
 
 
 @pytest.mark.parametrize("dt", [2, 1])
@@ -129,9 +151,11 @@ def test_nll_gradient_vs_central_differences_full_size(dt):
     loss (about 3) moves by about 1e-12 over +-h, a few thousand ulps, so the differences themselves
     resolve the derivative to about 1e-3 of that scale: the bar is the dtype's tolerance (BF16 3e-2)
     or four times the differences' own measured error (the FP32 1e-5 bar is then the oracle-gradient
-    comparison of test_nll_full_size_workload)."""
+    comparison of test_nll_full_size_workload).  The BF16 chain is compared with the differences of
+    the loss at its own BF16-rounded inputs (R10; rounding the inputs alone moves this gradient by
+    6% in this norm, see test_nll_full_size_workload)."""
     torch, glam = need_gpu()
-    F = _oracle_fd_probes()
+    F = _oracle_fd_probes(rounded_inputs=(dt == 2))
     d = F["d"]
     Xd = [glam.to_device_colmajor(X, dt) for X in d.X]
     Yd = glam.to_device_colmajor(d.Y, 0)
