@@ -161,7 +161,10 @@ typedef struct {
   int profile_every;      /* > 0: in one inner iteration in every profile_every, time the
                              iteration, then the fused slab kernel re-run 8 times back to
                              back on that iteration's own input, with HIP events on the
-                             fit's stream (0 = off; the re-runs rewrite identical values) */
+                             fit's stream (0 = off; the re-runs rewrite identical values);
+                             for BF16/FP32 chains with nu = 1 the mode-3 forward kernel and
+                             the adjoint + proximal-step kernel are re-run the same way (the
+                             latter writes into scratch buffers of the fit)          */
   int graph_mode;         /* 0: replay each block of check_every inner iterations as a
                              captured HIP graph (default); 1: plain stream launches */
   int inner_mode;         /* glam_inner: how the inner loop evaluates grad h (the FP64
@@ -225,6 +228,9 @@ typedef struct {
                              because the BF16/FP32 chain stopped refining it (three outer
                              steps in a row ending on the chain's rounding floor with less
                              than 10% KKT progress; the rest of the path stays FP64), or -1 */
+  double adj_ms;          /* out: summed per-launch duration of the sampled mode-3 adjoint +
+                             proximal-step kernel (BF16/FP32 chains, nu = 1; 0 otherwise) */
+  double fwd_ms;          /* out: the same for the mode-3 forward kernel                  */
 } glam_result;
 
 /* Fit the whole lambda path with warm starts.  Models are fitted in order;

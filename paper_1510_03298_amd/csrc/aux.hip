@@ -1,6 +1,8 @@
 // aux.hip -- small gfx950 kernels around the rho chain: reductions, layout
 // conversion, the elementwise parts of the GD-PG iteration (Sec. 3) and the
 // FP64 Armijo trial sums (Sec. 5).
+#include <algorithm>
+
 #include "launch.h"
 #include "mfma.h"
 
@@ -117,6 +119,47 @@ __global__ void k_inner_init(long long p, long long inc_len, const double* __res
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < inc_len; i += (long long)gridDim.x * blockDim.x)
     inc[i] = zero_val<T>();
   if (blockIdx.x == 0 && threadIdx.x == 0) *iter = 0;
+}
+
+// inner state of the FP32-increment PG step (AdjIncParams), in the adjoint tile layout
+__device__ inline long long adj_tiled_index(const Geom& G, long long j) {
+  const int m = (int)(j % G.P12), k3 = (int)(j / G.P12);
+  const int NBM = (G.P12 + 15) >> 4;
+  return ((long long)(k3 >> 4) * NBM + (m >> 4)) * 256 + (m & 15) * 16 + (k3 & 15);
+}
+
+template <typename T>
+__global__ void k_inner_init_inc(Geom G, long long inc_len, const double* __restrict__ theta,
+                                 const double* __restrict__ gref, const double* __restrict__ pen_w,
+                                 double* __restrict__ tT, double* __restrict__ gT, double* __restrict__ penT,
+                                 float* __restrict__ d0, float* __restrict__ d1, float* __restrict__ q,
+                                 T* __restrict__ inc, int* iter) {
+  const long long tl = (long long)((G.P12 + 15) / 16) * ((G.p3 + 15) / 16) * 256;
+  const long long step = (long long)gridDim.x * blockDim.x;
+  // (the padding elements of the tiles are never read: the step kernel reads valid elements only)
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tl; i += step) {
+    d0[i] = 0.f;   // x^1 = x^0 = theta_ref
+    d1[i] = 0.f;
+    q[i] = 0.f;    // grad h(x^0) = grad h(theta_ref)
+  }
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < G.p; j += step) {
+    const long long e = adj_tiled_index(G, j);
+    tT[e] = theta[j];
+    gT[e] = gref[j];
+    if (penT) penT[e] = pen_w[j];
+  }
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < inc_len; i += step) inc[i] = zero_val<T>();
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iter = 0;
+}
+
+// x = theta_ref + d (0 where d codes an exact zero); out = x, or x - theta_ref (diff)
+__global__ void k_inc_state_out(Geom G, const float* __restrict__ d, const double* theta, int diff, double* out) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < G.p; j += (long long)gridDim.x * blockDim.x) {
+    const float dv = d[adj_tiled_index(G, j)];
+    const double th = theta[j];
+    const double x = __builtin_isnan(dv) ? 0.0 : th + (double)dv;
+    out[j] = diff ? x - th : x;
+  }
 }
 
 __global__ void k_sub(long long p, const double* a, const double* b, double* out) {
@@ -411,6 +454,27 @@ hipError_t launch_inner_init(const Geom& G, const double* theta, const double* g
   return hipGetLastError();
 }
 
+hipError_t launch_inner_init_inc(int dt, const Geom& G, const double* theta, const double* gref, const double* pen_w,
+                                 double* tT, double* gT, double* penT, float* d0, float* d1, float* q, void* inc,
+                                 int* iter, hipStream_t s) {
+  if (!pen_w) penT = nullptr;
+  const long long tl = adj_tiled_len(G);
+  const int gr = grid1d(std::max(tl, G.inc_len));
+  if (dt == DT_F32)
+    hipLaunchKernelGGL(k_inner_init_inc<float>, dim3(gr), dim3(WG), 0, s, G, G.inc_len, theta, gref, pen_w, tT, gT,
+                       penT, d0, d1, q, (float*)inc, iter);
+  else if (dt == DT_BF16)
+    hipLaunchKernelGGL(k_inner_init_inc<bf16>, dim3(gr), dim3(WG), 0, s, G, G.inc_len, theta, gref, pen_w, tT, gT,
+                       penT, d0, d1, q, (bf16*)inc, iter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_inc_state_out(const Geom& G, const float* d, const double* theta, int diff, double* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_inc_state_out, dim3(grid1d(G.p)), dim3(WG), 0, s, G, d, theta, diff, out);
+  return hipGetLastError();
+}
 hipError_t launch_sub(long long p, const double* a, const double* b, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sub, dim3(grid1d(p)), dim3(WG), 0, s, p, a, b, out);
   return hipGetLastError();

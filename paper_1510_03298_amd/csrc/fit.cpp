@@ -213,7 +213,7 @@ struct Fit {
   unsigned seq_expect = 0;
   double sprod;            // prod_j rho(X_j^T X_j)
   std::string err;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sampled kernel timing
+  hipEvent_t ev[8] = {};   // sampled kernel timing
   hipStream_t us = nullptr;        // caller's stream
   bool own_stream = false;
   bool batched = false;            // set up for glam_fit_batched (its batched step uses the LDS image)
@@ -223,6 +223,21 @@ struct Fit {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_m = 0;                 // inner iterations per graph replay
+  // the BF16 / FP32 chain loop (nu = 1) keeps its iterate as FP32 increments (AdjIncParams);
+  // its two increment buffers alternate, so a block replayed from the second buffer has a
+  // graph of its own
+  bool incst = false;
+  double *tT = nullptr, *gT = nullptr, *penT = nullptr;
+  float* dst[2] = {nullptr, nullptr};
+  float* qst = nullptr;
+  hipGraph_t graph1 = nullptr;
+  hipGraphExec_t gexec1 = nullptr;
+  int graph1_m = 0;
+  // sampled re-runs of the step kernel write here (the fit's own state is left untouched)
+  float *dS = nullptr, *qS = nullptr;
+  void* incS = nullptr;
+  double* partS = nullptr;
+  double adj_ms = 0.0, fwd_ms = 0.0;
   bool pending = false;
   double chain_ms = 0.0, iter_ms = 0.0;
   int samples = 0;
@@ -242,6 +257,8 @@ struct Fit {
     if (s) (void)hipStreamSynchronize(s);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (gexec1) (void)hipGraphExecDestroy(gexec1);
+    if (graph1) (void)hipGraphDestroy(graph1);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (sync_ev) (void)hipEventDestroy(sync_ev);
@@ -360,6 +377,36 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   SlabParams sp{};
   sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
+  if (F.incst && F.dt != DT_F64) {
+    // x^{l+1} from x^l = theta_ref + d[gpar] and x^{l-1} = theta_ref + d[1 - gpar], written over
+    // the latter (AdjIncParams)
+    AdjIncParams ai{};
+    ai.G = G; ai.S2 = F.S2c; ai.X3a = F.X3ac; ai.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
+    ai.gT = F.gT; ai.tT = F.tT; ai.penT = F.pen ? F.penT : nullptr;
+    ai.dcur = F.dst[F.gpar]; ai.dprev = F.dst[1 - F.gpar]; ai.dout = F.dst[1 - F.gpar];
+    ai.q_in = F.qst; ai.q_out = F.qst; ai.inc = F.inc; ai.iter = F.iter; ai.dparams = F.dparams;
+    ai.scale = 1.0 / (double)G.n; ai.alpha = F.enet; ai.partials = F.part; ai.xmap = kAdjIncForm;
+    FCHK(launch_slab_adj_inc(F.dt, ai, nblk, F.s));
+    F.gpar ^= 1;
+    if (sample) {
+      // the whole iteration between ev[0] and ev[1]; then each of its three kernels re-run
+      // kSampleReps times back to back on this iteration's own inputs: slab_fwd (no counter
+      // step) and slab_chain rewrite identical T1 and S2, the step kernel writes its outputs
+      // into scratch buffers
+      FCHK(hipEventRecord(F.ev[1], F.s));
+      FCHK(hipEventRecord(F.ev[2], F.s));
+      for (int r = 0; r < kSampleReps; ++r) FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
+      FCHK(hipEventRecord(F.ev[3], F.s));
+      ai.dout = F.dS; ai.q_out = F.qS; ai.inc = F.incS; ai.partials = F.partS;
+      for (int r = 0; r < kSampleReps; ++r) FCHK(launch_slab_adj_inc(F.dt, ai, nullptr, F.s));
+      FCHK(hipEventRecord(F.ev[4], F.s));
+      fw.iter = nullptr;
+      for (int r = 0; r < kSampleReps; ++r) FCHK(launch_slab_fwd(F.dt, fw, F.s));
+      FCHK(hipEventRecord(F.ev[5], F.s));
+      F.pending = true;
+    }
+    return GLAM_OK;
+  }
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen;
   ap.alpha = F.enet; ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
@@ -383,12 +430,20 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
 // after the stream synchronisation of the convergence check).
 static int collect_sample(Fit& F) {
   if (!F.pending) return GLAM_OK;
-  FCHK(hipEventSynchronize(F.ev[3]));
+  const bool three = F.incst && F.dt != DT_F64 && !F.gram;   // the step kernel and slab_fwd sampled too
+  FCHK(hipEventSynchronize(F.ev[three ? 5 : 3]));
   float a = 0.f, b = 0.f;
   FCHK(hipEventElapsedTime(&a, F.ev[2], F.ev[3]));
   FCHK(hipEventElapsedTime(&b, F.ev[0], F.ev[1]));
   F.chain_ms += a / kSampleReps;
   F.iter_ms += b;
+  if (three) {
+    float c = 0.f, d = 0.f;
+    FCHK(hipEventElapsedTime(&c, F.ev[3], F.ev[4]));
+    FCHK(hipEventElapsedTime(&d, F.ev[4], F.ev[5]));
+    F.adj_ms += c / kSampleReps;
+    F.fwd_ms += d / kSampleReps;
+  }
   F.samples += 1;
   F.pending = false;
   return GLAM_OK;
@@ -431,25 +486,40 @@ static int wait_published(Fit& F, double* vals, int nval) {
   return GLAM_OK;
 }
 
+static void drop_graphs(Fit& F) {
+  if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
+  if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
+  if (F.gexec1) { (void)hipGraphExecDestroy(F.gexec1); F.gexec1 = nullptr; }
+  if (F.graph1) { (void)hipGraphDestroy(F.graph1); F.graph1 = nullptr; }
+  F.graph_m = F.graph1_m = 0;
+}
+
 static int inner_block_graph(Fit& F, int m, int* nblk) {
   // a fused Gram block alternates its buffers: replayable only from buffer 0 with even m
   if (F.gram_fused && (F.gpar != 0 || (m & 1))) return inner_block_eager(F, m, false, nblk);
-  if (!F.gexec || F.graph_m != m) {
-    if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
-    if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
+  // the increment-state loop alternates its buffers too: one graph per starting buffer
+  const bool inc = F.incst && F.dt != DT_F64;
+  const bool second = inc && F.gpar == 1;
+  hipGraph_t& graph = second ? F.graph1 : F.graph;
+  hipGraphExec_t& gexec = second ? F.gexec1 : F.gexec;
+  int& graph_m = second ? F.graph1_m : F.graph_m;
+  if (!gexec || graph_m != m) {
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
     FCHK(hipStreamBeginCapture(F.s, hipStreamCaptureModeRelaxed));
-    int r = inner_block_eager(F, m, false, nblk);
+    int r = inner_block_eager(F, m, false, nblk);   // (flips F.gpar as the replay will)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(F.s, &g);
     if (r) { if (g) (void)hipGraphDestroy(g); return r; }
     FCHK(e);
-    F.graph = g;
-    FCHK(hipGraphInstantiate(&F.gexec, F.graph, nullptr, nullptr, 0));
-    F.graph_m = m;
+    graph = g;
+    FCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    graph_m = m;
   } else {
-    *nblk = F.gram_fused ? gram_iter_blocks(F.dt, F.G) : slab_adj_blocks(F.G);
+    *nblk = F.gram_fused ? gram_iter_blocks(F.dt, F.G) : inc ? slab_adj_inc_partials(F.G, kAdjIncForm) : slab_adj_blocks(F.G);
+    if (inc && (m & 1)) F.gpar ^= 1;
   }
-  FCHK(hipGraphLaunch(F.gexec, F.s));
+  FCHK(hipGraphLaunch(gexec, F.s));
   return GLAM_OK;
 }
 
@@ -526,9 +596,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
 static void escalate_f64(Fit& F) {
   F.dt = DT_F64;
   F.T1c = F.T1d; F.S2c = F.S2d; F.X3fc = F.X3fd; F.X3ac = F.X3ad; F.imgc = F.imgd;
-  if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
-  if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
-  F.graph_m = 0;
+  drop_graphs(F);
 }
 
 // Continue a BF16 fit with the FP32 inner chain (the intermediate rung before FP64): its
@@ -548,9 +616,7 @@ static int escalate_f32(Fit& F) {
                                chain_image_need(DT_F32, SM_FUSED, G)));
   F.dt = DT_F32;
   F.T1c = t1; F.S2c = s2; F.X3fc = x3f; F.X3ac = x3a; F.imgc = img;
-  if (F.gexec) { (void)hipGraphExecDestroy(F.gexec); F.gexec = nullptr; }
-  if (F.graph) { (void)hipGraphDestroy(F.graph); F.graph = nullptr; }
-  F.graph_m = 0;
+  drop_graphs(F);
   return GLAM_OK;
 }
 
@@ -678,6 +744,21 @@ static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool eve
     F.yb2 = (double*)A(G.p * 8); F.gyb2 = (double*)A(G.p * 8);
   }
   F.inc = A(G.inc_len * 8);
+  if (F.incst) {
+    const size_t tl = (size_t)adj_tiled_len(G);
+    F.tT = (double*)A(tl * 8);
+    F.gT = (double*)A(tl * 8);
+    F.penT = (double*)A(tl * 8);
+    F.dst[0] = (float*)A(tl * 4);
+    F.dst[1] = (float*)A(tl * 4);
+    F.qst = (float*)A(tl * 4);
+    if (events) {
+      F.dS = (float*)A(tl * 4);
+      F.qS = (float*)A(tl * 4);
+      F.incS = A(G.inc_len * 8);
+      F.partS = (double*)A(nadj * ADJ_NSUM * 8);
+    }
+  }
   F.iter = (int*)A(2 * sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
@@ -973,6 +1054,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   F.kron = opt->inner_mode == GLAM_INNER_KRON && family_has_weights(prob->family);
   F.unit_w = opt->inner_mode == GLAM_INNER_ONE && family_has_weights(prob->family);
   F.enet = opt->alpha;
+  F.incst = F.dt != DT_F64 && !F.gram && opt->nu >= 1.0;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
     if (r) return fit_fail(r, F.err);
@@ -1040,6 +1122,8 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   res->n_done = 0;
   res->escalated_at = -1;
   res->chain_ms = 0.0;
+  res->adj_ms = 0.0;
+  res->fwd_ms = 0.0;
   res->iter_ms = 0.0;
   res->chain_samples = 0;
   res->inner_total = 0;
@@ -1108,7 +1192,12 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       // cannot get there ends on the noise floor or the stall rule below.
       if (F.dt == DT_BF16) tol_in = std::max(tol_in, 0.01 * kkt);
       // ---- inner PG loop ----
-      PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
+      const bool incst = F.incst && F.dt != DT_F64;
+      if (incst)
+        PCHK(launch_inner_init_inc(F.dt, G, F.theta, F.gref, F.pen, F.tT, F.gT, F.penT, F.dst[0], F.dst[1], F.qst,
+                                   F.inc, F.iter, F.s));
+      else
+        PCHK(launch_inner_init(G, F.theta, F.gref, F.x, F.xp, F.gp, F.dt, F.inc, F.iter, F.s));
       F.gpar = 0;   // the increment and the counter start in buffer 0
       int it = 0;
       double kin = INFINITY, noise = 0.0;
@@ -1154,16 +1243,19 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       inner_total += it;
       if (!std::isfinite(kin)) { status = GLAM_ENONFINITE; break; }
       last_limited = kin > tol_in && it < opt->max_inner;   // ended on the rounding floor
-      // theta~ = x^l of the last checked iteration (held in xp)
+      // theta~ = x^l of the last checked iteration (held in xp; in the increment-state loop,
+      // theta_ref + the buffer the last iteration read as d^l)
       double alpha = 0.0, Delta = 0.0;
       if (exact_model) {
         // the model is the objective itself (Sec. 6.5: no outer loop is needed), so the inner
         // solution is the new estimate (alpha = 1); further passes only re-anchor a BF16/FP32
         // inner loop in FP64, and the FP64 KKT test at the next anchor decides convergence
         alpha = 1.0;
-        PCHK(hipMemcpyAsync(F.theta, F.xp, G.p * 8, hipMemcpyDeviceToDevice, F.s));
+        if (incst) PCHK(launch_inc_state_out(G, F.dst[1 - F.gpar], F.theta, 0, F.theta, F.s));
+        else PCHK(hipMemcpyAsync(F.theta, F.xp, G.p * 8, hipMemcpyDeviceToDevice, F.s));
       } else {
-        PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
+        if (incst) PCHK(launch_inc_state_out(G, F.dst[1 - F.gpar], F.theta, 1, F.dvec, F.s));
+        else PCHK(launch_sub(G.p, F.xp, F.theta, F.dvec, F.s));
         RCHK(armijo(F, lam, 0.1, &alpha, &Delta));
         if (alpha > 0.0) PCHK(launch_axpy(G.p, alpha, F.dvec, F.theta, F.s));
         else if (F.dt != DT_F64) last_limited = true;   // no descent from this low-precision pass
@@ -1203,6 +1295,8 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   PCHK(hipStreamWaitEvent(F.us, F.sync_ev, 0));
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   res->chain_ms = F.chain_ms;
+  res->adj_ms = F.adj_ms;
+  res->fwd_ms = F.fwd_ms;
   res->iter_ms = F.iter_ms;
   res->chain_samples = F.samples;
   res->inner_total = path_inner;

@@ -113,6 +113,54 @@ struct AdjParams {
   double alpha;          // elastic-net weight (Sec. 6.3): J = sum w (|theta| + alpha theta^2); 0 = lasso
 };
 
+// The inner PG step of the BF16 / FP32 chains on FP32 increment state (step control nu = 1).
+// The iterate x^l = theta_ref + d^l is held as FP32 increments d in the adjoint's tile layout
+// (16 x 16 output tile (bm, bn) contiguous at (bn * NBM + bm) * 256, element (m % 16) * 16 +
+// k3 % 16, NBM = ceil(P12 / 16)), with theta_ref and grad h(theta_ref) as FP64 copies in the same
+// layout.  A coordinate whose x is exactly zero (the soft threshold's zero) is stored as a NaN
+// increment, so that exact zeros survive the FP32 rounding of theta_ref.  The extrapolation
+// keeps q = grad h(x^{l-1}) - grad h(theta_ref) (FP32) instead of the FP64 gradient.
+struct AdjIncParams {
+  Geom G;
+  const void* S2;        // chain type, k-blocked (K = n3, C = P12) or in 4-deep k-blocks (s2_kb4)
+  const void* X3a;       // chain type, k-blocked (K = n3, C = p3)
+  int s2_kb4;
+  const double* gT;      // grad h(theta_ref), tiled
+  const double* tT;      // theta_ref, tiled
+  const double* penT;    // penalty weights, tiled, or NULL (all 1)
+  const float* dcur;     // d^l
+  const float* dprev;    // d^{l-1}
+  float* dout;           // d^{l+1} (in the fit: the buffer of dprev, each element read before written)
+  const float* q_in;     // q of x^{l-1}
+  float* q_out;          // q of x^l (in the fit: the buffer of q_in)
+  void* inc;             // chain type, k-blocked (K = p3, C = P12): x^{l+1} - theta_ref
+  const int* iter;       // device iteration counter l
+  const double* dparams; // device {lambda, delta}
+  double scale;          // 1 / n
+  double alpha;          // elastic-net weight
+  double* partials;      // per-workgroup [nblk][ADJ_NSUM], slab_adj's layout
+  int xmap;              // tile order: 0 row blocks fastest; 1 XCD-aware (each XCD a range of row blocks)
+};
+inline long long adj_tiled_len(const Geom& G) { return (long long)((G.P12 + 15) / 16) * ((G.p3 + 15) / 16) * 256; }
+hipError_t launch_slab_adj_inc(int dt, const AdjIncParams& P, int* nblk_out, hipStream_t s);
+int slab_adj_inc_blocks(const Geom& G, int xmap);
+// partial-sum rows a launch writes (the reduction's block count)
+int slab_adj_inc_partials(const Geom& G, int xmap);
+// the tile order the fits use: 16 x 16 tiles, split-K over the 4 waves, row blocks fastest
+// (n = (100, 100, 1000), p = (30, 30, 200), BF16, back to back: 6.95 us against 7.0 us for the
+// XCD-aware order, 7.3 us for 32 x 32 tiles, 10.4 us for whole-contraction waves; 9.45 us for
+// the FP64-state step)
+constexpr int kAdjIncForm = 0;
+// per outer step: tT, gT (and penT when pen_w != NULL) from theta, gref, pen_w; d0 = d1 = q = 0,
+// inc = 0 (k-blocked, chain dtype), *iter = 0
+hipError_t launch_inner_init_inc(int dt, const Geom& G, const double* theta, const double* gref, const double* pen_w,
+                                 double* tT, double* gT, double* penT, float* d0, float* d1, float* q, void* inc,
+                                 int* iter, hipStream_t s);
+// out = x (diff == 0) or x - theta_ref (diff == 1) in the standard layout, x from the tiled
+// increments d and theta (theta_ref, standard layout); out may alias theta
+hipError_t launch_inc_state_out(const Geom& G, const float* d, const double* theta, int diff, double* out,
+                                hipStream_t s);
+
 struct FwdParams {
   Geom G;
   const void* theta;  // chain type, k-blocked (K = p3, C = P12)

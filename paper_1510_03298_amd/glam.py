@@ -55,7 +55,8 @@ class GlamResult(ctypes.Structure):
                 ("iters_outer", ctypes.POINTER(ctypes.c_int)), ("iters_inner", ctypes.POINTER(ctypes.c_int)),
                 ("status", ctypes.POINTER(ctypes.c_int)), ("n_done", ctypes.c_int), ("lambda_max", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("chain_ms", ctypes.c_double), ("chain_samples", ctypes.c_int),
-                ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong), ("escalated_at", ctypes.c_int)]
+                ("iter_ms", ctypes.c_double), ("inner_total", ctypes.c_longlong), ("escalated_at", ctypes.c_int),
+                ("adj_ms", ctypes.c_double), ("fwd_ms", ctypes.c_double)]
 
 
 class GlamBatchOptions(ctypes.Structure):
@@ -360,6 +361,8 @@ class PathResult:
     iter_ms: float = 0.0
     inner_total: int = 0
     escalated_at: int = -1   # first model fitted on with the FP64 inner chain, or -1
+    adj_ms: float = 0.0      # summed sampled launch durations of the adjoint + step kernel
+    fwd_ms: float = 0.0      # ... and of the mode-3 forward kernel
 
 
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
@@ -423,7 +426,8 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     out = PathResult(np.array(lam_out[:]), theta, np.array(kkt[:]), np.array(obj[:]), np.array(io[:]),
                      np.array(ii[:]), np.array(stt[:]), int(res.n_done), float(res.lambda_max),
                      float(res.seconds), int(code), float(res.chain_ms), int(res.chain_samples),
-                     float(res.iter_ms), int(res.inner_total), int(res.escalated_at))
+                     float(res.iter_ms), int(res.inner_total), int(res.escalated_at), float(res.adj_ms),
+                     float(res.fwd_ms))
     if raise_on_error and code != GLAM_OK:
         raise GlamError(code, "glam_fit_path")
     return out
