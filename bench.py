@@ -100,8 +100,10 @@ def cpu_baseline(d, total_inner_f64, outer_f64, budget_s=15.0):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slab_chain_gaussian_100x100x1000_bf16_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inner_kernels_gaussian_100x100x1000_bf16_hbm_traffic.txt")
 STATS_FILE = os.path.join(ROOT, "profiles", "gaussian_path_100x100x1000_bf16_kernel_stats.txt")
+MFMA_FILE = os.path.join(ROOT, "profiles", "inner_kernels_gaussian_100x100x1000_bf16_mfma_counters.txt")
+INNER_KERNELS = ("slab_fwd", "slab_chain", "slab_adj")
 
 
 def kernel_source_hash():
@@ -117,31 +119,39 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch(kernel, dtype):
-    """HBM bytes per launch of the kernel from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or None when
-    that summary was taken on a different kernel source or dtype."""
+def committed_record(path, dtype=None):
+    """The machine-readable line of a committed profile summary, or None when it is missing or was
+    taken on a different library source (or dtype)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("source_sha256_16") != kernel_source_hash() or rec.get("dtype") != dtype:
+    if rec.get("source_sha256_16") != kernel_source_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["hbm_bytes_per_launch"]
+    if dtype is not None and rec.get("dtype") != dtype:
+        return None
+    return rec
 
 
-def rocprof_chain_durations():
-    """The slab_chain durations of the committed rocprofv3 kernel trace (same command): the
-    sampled back-to-back re-launches this roofline times, and the launches inside the path;
-    None when that trace was taken on a different kernel source."""
-    try:
-        with open(STATS_FILE) as fh:
-            rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
-    except (OSError, IndexError, ValueError):
-        return None
-    return rec if rec.get("source_sha256_16") == kernel_source_hash() else None
+def inner_kernel_models(n, p, dt_bytes, family="gaussian"):
+    """Algorithmic work of the three kernels of one inner iteration (executed mode order, mode 3
+    first forward and last adjoint): flops and HBM bytes per launch.
+      slab_fwd  : T1 = inc^T X3 (read the increment and X3, write T1)
+      slab_chain: per slab T2, eta, R, S1, S2 (read T1 and the X1, X2 factors, write S2; V for Poisson)
+      slab_adj  : S2^T X3 + the proximal step on the FP32 increment state (read S2, X3; per
+                  coefficient read grad h(theta_ref) and theta_ref (FP64), d^l, d^{l-1}, q (FP32),
+                  write d^{l+1}, q (FP32) and the next increment (chain dtype))."""
+    n1, n2, n3 = n
+    p1, p2, p3 = p
+    P12, P = p1 * p2, p1 * p2 * p3
+    kb3 = -(-p3 // 16) * 16
+    kbn3 = -(-n3 // 16) * 16
+    fwd3, chain, adj3 = flop_model(n, p)
+    b_fwd = (kb3 * P12 + kb3 * n3 + n3 * P12) * dt_bytes
+    b_chain = chain_bytes(n, p, dt_bytes, poisson=family != "gaussian")
+    b_adj = (kbn3 * P12 + kbn3 * p3) * dt_bytes + P * (8 + 8 + 4 + 4 + 4 + 4 + 4 + dt_bytes)
+    return {"slab_fwd": (fwd3, b_fwd), "slab_chain": (chain, b_chain), "slab_adj": (adj3, b_adj)}
 
 
 def copy_calibration(torch, dev, mib):
@@ -338,6 +348,8 @@ def main():
                     help="time one inner iteration in this many with HIP events (those blocks run un-captured)")
     ap.add_argument("--lambda-min-ratio", type=float, default=1e-4)
     ap.add_argument("--eager", action="store_true", help="launch every inner iteration eagerly (no HIP graphs)")
+    ap.add_argument("--extrapolation", default="restarted", choices=["restarted", "plain"],
+                    help="inner-loop extrapolation sequence of the timed form (the other is timed beside it)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (Poisson path, 256-problem batch, Poisson NLL)")
     ap.add_argument("--only", default=None, metavar="NAME",
@@ -380,10 +392,11 @@ def main():
     stream = torch.cuda.current_stream(dev)
     dts = {"f64": glam.F64, "f32": glam.F32, "bf16": glam.BF16}
 
-    def fit(dt, profile_every=0):
+    def fit(dt, profile_every=0, extrapolation=None):
         return glam.fit_path(Xd, Yd, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=args.lambda_min_ratio,
                              dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
-                             profile_every=profile_every, raise_on_error=False, graph=not args.eager)
+                             profile_every=profile_every, raise_on_error=False, graph=not args.eager,
+                             extrapolation=extrapolation or args.extrapolation)
 
     progress(f"Gaussian 100x100x1000 path, {args.warmup} warmup + {args.steps} timed steps ({args.dtype})")
     for _ in range(args.warmup):
@@ -417,34 +430,65 @@ def main():
 
     fwd3, chain, adj3 = flop_model(n, p)
     dtb = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
-    chain_ms = sum(r.chain_ms for r in results)
     samples = sum(r.chain_samples for r in results)
-    iter_ms = sum(r.iter_ms for r in results)
-    avg_chain = chain_ms / max(samples, 1) * 1e-3
-    avg_iter = iter_ms / max(samples, 1) * 1e-3
-    achieved = chain / avg_chain if samples else None
+    avg_iter = sum(r.iter_ms for r in results) / max(samples, 1) * 1e-3
+    live_us = {"slab_chain": sum(r.chain_ms for r in results) / max(samples, 1) * 1e3,
+               "slab_adj": sum(r.adj_ms for r in results) / max(samples, 1) * 1e3,
+               "slab_fwd": sum(r.fwd_ms for r in results) / max(samples, 1) * 1e3}
+    models = inner_kernel_models(n, p, dtb)
+    stats = committed_record(STATS_FILE) if args.dtype == "bf16" else None
+    traffic = committed_record(TRAFFIC_FILE, args.dtype)
+    mfma = committed_record(MFMA_FILE, args.dtype)
+    peak_mfma = PEAKS[args.dtype]
+    kernels = {}
+    for k in INNER_KERNELS:
+        fl, by = models[k]
+        us = live_us[k] if samples and live_us[k] > 0 else None
+        ai = fl / by
+        entry = {"flops_per_launch": fl, "algorithmic_bytes_per_launch": by, "arithmetic_intensity": ai,
+                 "live_avg_launch_us": us,
+                 "tflops": fl / (us * 1e-6) / 1e12 if us else None,
+                 "gbs": by / (us * 1e-6) / 1e9 if us else None,
+                 "frac_of_mfma_peak": fl / (us * 1e-6) / peak_mfma if us else None,
+                 "attainable_tflops": min(peak_mfma, ai * PEAKS["hbm"]) / 1e12,
+                 "bound": "mfma" if ai * PEAKS["hbm"] >= peak_mfma else "hbm",
+                 "hbm_bytes_per_launch": None, "mfma_util_pct": None}
+        if traffic and k in traffic.get("kernels", {}):
+            entry["hbm_bytes_per_launch"] = traffic["kernels"][k]["hbm_bytes_per_launch"]
+        if mfma and k in mfma.get("kernels", {}):
+            entry["mfma_util_pct"] = mfma["kernels"][k].get("mfma_util_pct")
+            entry["mfma_flops_counted_per_launch"] = mfma["kernels"][k].get("mfma_flops_per_launch")
+        if stats and k in stats.get("kernels", {}):
+            entry["rocprof_in_path_avg_us"] = stats["kernels"][k]["in_path_avg_us"]
+            entry["rocprof_sampled_avg_us"] = stats["kernels"][k].get("sampled_avg_us")
+            entry["rocprof_in_path_total_ms"] = stats["kernels"][k]["in_path_total_ms"]
+        kernels[k] = entry
+    # the dominant kernel: the largest in-path total of the committed trace of this source, else
+    # the largest live per-launch time (the three run once per inner iteration)
+    if stats and all(k in stats.get("kernels", {}) for k in INNER_KERNELS):
+        dom = max(INNER_KERNELS, key=lambda k: stats["kernels"][k]["in_path_total_ms"])
+    else:
+        dom = max(INNER_KERNELS, key=lambda k: live_us[k])
+    e = kernels[dom]
+    if e["bound"] == "mfma":
+        ach, pk, unit = (e["tflops"], peak_mfma / 1e12, "TFLOP/s")
+    else:
+        ach, pk, unit = (e["gbs"], PEAKS["hbm"] / 1e9, "GB/s")
     roofline = {
-        "kernel": "slab_chain (fused modes 1-2 forward + adjoint of one inner PG iteration)",
-        "timing": ("HIP events on the fit's stream around 8 back-to-back re-launches of the kernel on the "
-                   "sampled iteration's own input, one sample per profile_every inner iterations; the committed "
-                   "rocprofv3 trace of the same command gives these launches' own durations "
-                   "(rocprof_sampled_avg_us) and those of the launches inside the path (rocprof_in_path_avg_us, "
-                   "colder caches after the adjoint's traffic; frac_in_path uses it)"),
-        "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
-        "peak": PEAKS[args.dtype] / 1e12, "unit": "TFLOP/s",
-        "frac": (achieved / PEAKS[args.dtype]) if achieved else None,
-        "traffic": traffic_per_launch("slab_chain", args.dtype),
-        "kernel_source_sha256_16": kernel_source_hash(),
-        "flops_per_launch": chain, "launches_sampled": samples,
-        "avg_launch_us": avg_chain * 1e6,
-        "algorithmic_bytes_per_launch": chain_bytes(n, p, dtb),
+        "kernel": dom, "bound": e["bound"], "achieved": ach, "peak": pk, "unit": unit,
+        "frac": ach / pk if ach else None, "traffic": e["hbm_bytes_per_launch"],
+        "timing": ("HIP events on the fit's stream around 8 back-to-back re-launches of each inner-loop kernel on "
+                   "a sampled iteration's own inputs (one sample per profile_every inner iterations; the adjoint "
+                   "step kernel writes its re-run outputs to scratch); the committed rocprofv3 trace of the same "
+                   "command gives the launches inside the path (rocprof_in_path_avg_us)"),
+        "kernel_source_sha256_16": kernel_source_hash(), "launches_sampled": samples,
+        "avg_launch_us": e["live_avg_launch_us"], "flops_per_launch": e["flops_per_launch"],
+        "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
+        "frac_of_mfma_peak": e["frac_of_mfma_peak"],
         "inner_iteration_us": avg_iter * 1e6,
         "inner_iteration_tflops": (fwd3 + chain + adj3) / avg_iter / 1e12 if samples else None,
+        "kernels": kernels,
     }
-    rp = rocprof_chain_durations() if args.dtype == "bf16" else None
-    roofline["rocprof_sampled_avg_us"] = rp["slab_chain_sampled_avg_us"] if rp else None
-    roofline["rocprof_in_path_avg_us"] = rp["slab_chain_in_path_avg_us"] if rp else None
-    roofline["frac_in_path"] = (chain / (rp["slab_chain_in_path_avg_us"] * 1e-6) / PEAKS[args.dtype]) if rp else None
     forms = {args.dtype: {"seconds": sec, "inner": int(np.mean([r.inner_total for r in results])),
                           "outer": int(np.mean([r.iters_outer.sum() for r in results])),
                           "max_kkt": float(max(np.max(r.kkt) for r in results)), "ok": ok}}
@@ -466,6 +510,18 @@ def main():
                          "ok": all(r.code == 0 and r.n_done == args.nlambda for r in rs)}
         for dt in forms:
             forms[dt]["speedup_vs_f64"] = forms["f64"]["seconds"] / forms[dt]["seconds"]
+        # the timed dtype with the other extrapolation sequence (same steps)
+        other = "plain" if args.extrapolation == "restarted" else "restarted"
+        progress(f"Gaussian 100x100x1000 path, {args.dtype} form with the {other} extrapolation sequence")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [fit(args.dtype, extrapolation=other) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        forms[args.dtype + "_" + other + "_extrapolation"] = {
+            "seconds": (time.perf_counter() - t0) / args.steps, "steps": args.steps,
+            "inner": int(np.mean([r.inner_total for r in rs])), "outer": int(np.mean([r.iters_outer.sum() for r in rs])),
+            "max_kkt": float(max(np.max(r.kkt) for r in rs)),
+            "ok": all(r.code == 0 and r.n_done == args.nlambda for r in rs)}
     cpu = None
     if not args.no_cpu and "f64" in forms:
         progress("oracle CPU baseline (bounded sample)")
@@ -491,7 +547,8 @@ def main():
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "gaussian_path_n100x100x1000_p30x30x200_100lambda_kkt1e-6",
                    "n": list(n), "p": list(p), "nlambda": args.nlambda, "lambda_min_ratio": args.lambda_min_ratio,
-                   "kkt_tol": 1e-6, "family": "gaussian", "graphs": not args.eager},
+                   "kkt_tol": 1e-6, "family": "gaussian", "graphs": not args.eager,
+                   "extrapolation": args.extrapolation},
         "all_models_converged": ok,
         "path_with_host_copies": with_copies,
         "forms": forms,

@@ -184,6 +184,15 @@ typedef struct {
                              weighted lasso.  Not combinable with alpha != 0.        */
   double scad_a;          /* SCAD shape a > 2 (0 = 3.7)                               */
   int msa_steps;          /* MSA steps per lambda (>= 1; 1 = the lasso)               */
+  int extrapolation;      /* the inner loop's extrapolation sequence (Sec. 3.2 leaves it to the
+                             implementation: any omega_l in [0, 1)):
+                             0 (default): omega_l = (l' - 1)/(l' + 2) with l' counted from the
+                             last restart; at each convergence check a positive
+                             (y - x^{l+1})^T (x^{l+1} - x^l) restarts it (omega = 0 next; the
+                             gradient restart test of O'Donoghue and Candes); applies to the
+                             rho-chain loop with nu = 1, the other forms keep 1;
+                             1: omega_l = (l - 1)/(l + 2), l counted from the start of each
+                             inner loop (the paper's example sequence)                */
 } glam_options;
 
 /* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the

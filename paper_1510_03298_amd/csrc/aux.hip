@@ -55,7 +55,8 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
 constexpr int RED_WG = 1024;
 __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval,
                                                    unsigned ops_bits, double scale, double* __restrict__ out,
-                                                   double* hout, unsigned* seq_dev, unsigned* hseq) {
+                                                   double* hout, unsigned* seq_dev, unsigned* hseq,
+                                                   int restart_slot, int* restart_iter) {
   const int lane = lane_id(), w = wave_id();
   for (int v = w; v < nval; v += RED_WG / 64) {
     const bool mx = (ops_bits >> v) & 1u;
@@ -68,6 +69,9 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ pa
     if (lane == 0) {
       const double r = mx ? a : scale * a;
       out[v] = r;
+      // restarted extrapolation: a positive test value sets the step counter back, so that the
+      // next iteration takes omega = 0 (the counter is incremented before its use)
+      if (restart_iter && v == restart_slot && r > 0.0) *restart_iter = 0;
       if (hout) {
         __hip_atomic_store(&hout[v], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __threadfence_system();   // visible to the host before the sequence number below
@@ -407,17 +411,18 @@ hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, i
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
   if (nval > 32) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, stride, nval, bits, scale, out,
-                     (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr);
+                     (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, -1, (int*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
-                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s) {
+                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s, int restart_slot,
+                                 int* restart_iter) {
   unsigned bits = 0;
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
   if (nval > 32 || !hout || !seq_dev || !hseq) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, nval, nval, bits, scale, out, hout, seq_dev,
-                     hseq);
+                     hseq, restart_slot, restart_iter);
   return hipGetLastError();
 }
 

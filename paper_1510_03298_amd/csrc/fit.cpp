@@ -227,6 +227,9 @@ struct Fit {
   // its two increment buffers alternate, so a block replayed from the second buffer has a
   // graph of its own
   bool incst = false;
+  // restarted extrapolation sequence (the chain loop with nu = 1): at each check, a positive
+  // (y - x^{l+1})^T (x^{l+1} - x^l) sets the step counter back (omega = 0 next)
+  bool restart = false;
   double *tT = nullptr, *gT = nullptr, *penT = nullptr;
   float* dst[2] = {nullptr, nullptr};
   float* qst = nullptr;
@@ -458,7 +461,8 @@ static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
     if (r) return r;
   }
   const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-  FCHK(launch_reduce_publish(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.hpub_dev, F.seq_dev, F.hseq_dev, F.s));
+  FCHK(launch_reduce_publish(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.hpub_dev, F.seq_dev, F.hseq_dev, F.s, 2,
+                             F.restart ? F.iter : nullptr));
   return GLAM_OK;
 }
 
@@ -1021,6 +1025,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
                                  "without prior weights (Sec. 6.2) and runs without backtracking (nu = 1)");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
+  if (opt->extrapolation != 0 && opt->extrapolation != 1) return fit_fail(GLAM_EINVAL, "bad extrapolation");
   if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
       !res->status)
     return fit_fail(GLAM_EINVAL, "NULL result array");
@@ -1055,6 +1060,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   F.unit_w = opt->inner_mode == GLAM_INNER_ONE && family_has_weights(prob->family);
   F.enet = opt->alpha;
   F.incst = F.dt != DT_F64 && !F.gram && opt->nu >= 1.0;
+  F.restart = opt->extrapolation == 0 && !F.gram && opt->nu >= 1.0;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
     if (r) return fit_fail(r, F.err);

@@ -271,9 +271,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
                          hipStream_t s);
 // the same, also published to mapped host memory hout[0..nval) followed by the sequence
-// number *hseq = ++*seq_dev (device counter), for a host wait without a copy (nval <= 8)
+// number *hseq = ++*seq_dev (device counter), for a host wait without a copy (nval <= 8);
+// restart_iter != NULL: *restart_iter = 0 when value restart_slot is > 0 (the restarted
+// extrapolation sequence of the inner loop)
 hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
-                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s);
+                                 double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s, int restart_slot = -1,
+                                 int* restart_iter = nullptr);
 // same with partials[b * stride + v], v < nval <= stride
 hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
                                  double* out, hipStream_t s);

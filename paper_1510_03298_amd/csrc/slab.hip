@@ -1011,6 +1011,7 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       P.xp[j] = x;
       P.x[j] = xn;
       P.gp[j] = gx;
+      red_dg = (yv - xn) * (xn - x);   // restart test of the extrapolation (summed; > 0: restart)
       const double dinc = xn - e_th;
       red_inc = fabs(dinc);
       ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
@@ -1106,7 +1107,7 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
   for (int i = 0; i < 4; ++i) red[w][R::kidx(g, i) * 16 + r] = acc[i];   // [m % 16][k3 % 16]
   __syncthreads();
   const double a = (double)(red[0][t] + red[1][t] + red[2][t] + red[3][t]);
-  double red_kkt = 0.0, red_noise = 0.0, red_inc = 0.0;
+  double red_kkt = 0.0, red_noise = 0.0, red_inc = 0.0, red_rs = 0.0;
   if (valid) {
     const double lam = P.dparams[0], delta = P.dparams[1];
     const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1128,9 +1129,10 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
     P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
     P.q_out[e] = (float)incg;
     red_inc = fabs(dn);
+    red_rs = (yv - xn) * (xn - x);   // restart test of the extrapolation (summed; > 0: restart)
     ((T*)P.inc)[((long long)(ek >> 4) * G.P12 + em) * 16 + kpos<T>(ek & 15)] = R::from_acc((typename R::acc_t)dn);
   }
-  double v[ADJ_NSUM] = {red_kkt, red_noise, 0.0, 0.0, red_inc, 0.0};
+  double v[ADJ_NSUM] = {red_kkt, red_noise, red_rs, 0.0, red_inc, 0.0};
   const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
   block_reduce<ADJ_NSUM>(v, ops, sred);
   if (threadIdx.x == 0) {
