@@ -272,6 +272,15 @@ typedef struct {
   int check_every;        /* steps between host convergence checks                       */
   void* stream;           /* hipStream_t (NULL = default stream)                         */
   double alpha;           /* elastic-net weight of every problem, as in glam_options     */
+  int tuning;             /* 0: the slab phase's launch choices (run length, kernel width) per
+                             shape class picked by timing the variants once on the batch's
+                             first block (kept per class signature for the process, and in the
+                             file named by GLAM_TUNE_FILE when set); 1: fixed heuristics.  The
+                             variants compute the same values (bit for bit)             */
+  int graph_mode;         /* 0: each block of check_every batched steps replayed as a captured
+                             HIP graph (the work list is read from device memory, so one graph
+                             serves until a grid would grow or could shrink to a quarter);
+                             1: stream launches                                           */
 } glam_batch_options;
 
 typedef struct {
@@ -285,6 +294,8 @@ typedef struct {
   long long steps;        /* out: batched proximal-step launches                         */
   long long problem_steps;/* out: proximal steps summed over problems                    */
   double seconds;         /* out: wall time of the call                                  */
+  long long graph_replays;/* out: blocks of batched steps run as graph replays               */
+  double tune_seconds;    /* out: time spent timing slab-phase variants (0 when cached)      */
 } glam_batch_result;
 
 /* Fit nprob independent problems (each as in glam_fit_path with nlambda = 1; nu = 1).

@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <string>
 #include <memory>
 #include <mutex>
@@ -1314,6 +1315,57 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
 // ============================================================================
 // glam_fit_batched
 // ============================================================================
+// Choices of the batched slab-phase tuner per shape-class signature: kept for the process, and
+// in the text file named by GLAM_TUNE_FILE when that is set (one "key run wide" line per entry,
+// read on first use and appended to).
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(int dt, int cls, int nprob_cls, long long slabs) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return "batched_slabs/cu" + std::to_string(cus) + "/dt" + std::to_string(dt) + "/class" + std::to_string(cls) + "/p" +
+         std::to_string(nprob_cls) + "/s" + std::to_string(slabs);
+}
+
+static void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("GLAM_TUNE_FILE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  int run = 0, wide = 0;
+  while (fscanf(f, "%255s %d %d", key, &run, &wide) == 3)
+    if (run >= 1 && run <= 8 && (wide == 0 || wide == 1)) g_tune[key] = {run, wide};
+  fclose(f);
+}
+
+static bool tune_lookup(const std::string& key, int* run, int* wide) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *run = it->second.first;
+  *wide = it->second.second;
+  return true;
+}
+
+static void tune_store(const std::string& key, int run, int wide) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = {run, wide};
+  const char* path = getenv("GLAM_TUNE_FILE");
+  if (!path || !*path) return;
+  if (FILE* f = fopen(path, "a")) {
+    fprintf(f, "%s %d %d\n", key.c_str(), run, wide);
+    fclose(f);
+  }
+}
+
 static int validate_problem(const glam_problem* prob, int dtype, std::string* why) {
   if (prob->d != 3) { *why = "d must be 2 or 3"; return GLAM_EINVAL; }
   for (int j = 0; j < 3; ++j) {
@@ -1355,6 +1407,8 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
+  if (opt->tuning != 0 && opt->tuning != 1) return fit_fail(GLAM_EINVAL, "bad tuning");
+  if (opt->graph_mode != 0 && opt->graph_mode != 1) return fit_fail(GLAM_EINVAL, "bad graph_mode");
   if (!opt->lambda && !(opt->lambda_ratio > 0.0 && opt->lambda_ratio <= 1.0))
     return fit_fail(GLAM_EINVAL, "lambda_ratio must be in (0, 1]");
   if (!res->theta || !res->lambda_out || !res->lambda_max || !res->kkt || !res->objective || !res->iters_outer ||
@@ -1468,7 +1522,9 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   }
   void* dmem = nullptr;
   const size_t nparts = (size_t)off_adj[nprob] * ADJ_NSUM;
-  const size_t nwork = (size_t)4 * (nprob + 1);   // act, aoff_fwd, aoff_run, aoff_adj
+  // act, aoff_fwd, aoff_run, aoff_adj, then the BatchWork header
+  const size_t nwork_lists = (size_t)4 * (nprob + 1);
+  const size_t nwork = nwork_lists + (sizeof(BatchWork) + sizeof(int) - 1) / sizeof(int);
   auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t piece[6] = {sizeof(BatchDesc) * nprob, sizeof(int) * (nprob + 1), sizeof(int) * nwork,
                            sizeof(double) * nparts, sizeof(double) * 2 * nprob, 64};
@@ -1484,9 +1540,10 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   double* d_part = (double*)take(sizeof(double) * nparts);
   double* d_seg = (double*)take(sizeof(double) * 2 * nprob);
   int* d_misc = (int*)take(64);   // [0] step counter of the batched inner loop
-  double* h_seg = (double*)arena->host_alloc(sizeof(double) * 2 * nprob, nullptr);
+  double* h_seg_dev = nullptr;   // per-problem check maxima, written by the device into mapped host memory
+  double* h_seg = (double*)arena->host_alloc(sizeof(double) * 2 * nprob, (void**)&h_seg_dev);
   int* h_work = (int*)arena->host_alloc(sizeof(int) * nwork, nullptr);
-  if (!h_seg || !h_work) return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
+  if (!h_seg || !h_seg_dev || !h_work) return fit_fail(GLAM_ENOMEM, "pinned host allocation failed");
   std::vector<int> h_active(nprob, 0);
   for (int i = 0; i < nprob; ++i) {
     Fit& F = *fits[i];
@@ -1513,6 +1570,7 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   BCHK(hipStreamSynchronize(s));   // host vectors above must outlive the copies
   BatchParams B{};
   B.desc = d_desc; B.nprob = nprob; B.off_adj = d_off_adj; B.step = d_misc;
+  B.work = (const BatchWork*)(d_work + nwork_lists);
   B.act = d_work;
   B.aoff_fwd = d_work + (nprob + 1);
   B.aoff_run = d_work + 2 * (nprob + 1);
@@ -1525,27 +1583,34 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   }
   const size_t lds = batched_lds_bytes(dt, Gs.data(), nprob);
   int tot[3] = {0, 0, 0};
+  int cls_runs[4] = {0, 0, 0, 0};
+  // slab-phase launch choices per shape class: the run length (0: the heuristic below) and
+  // whether the class runs on the wider kernel (set by the tuner, or left at the defaults)
+  int tuned_run[4] = {0, 0, 0, 0}, tuned_wide[4] = {0, 0, 0, 0};
   // Compact work lists of the active problems, uploaded from pinned memory (the host rewrites
   // it only after a stream synchronisation, so the previous upload has completed).  Runs of
-  // several slabs share one load of the factor operands; they are as long as still leaves
-  // about 2048 runs (8 at most), so that a nearly finished batch keeps the CUs busy.
+  // several slabs share one load of the factor operands; by default they are as long as still
+  // leaves about 2048 runs (8 at most), so that a nearly finished batch keeps the CUs busy.
   auto upload_work = [&]() -> hipError_t {
     int* act = h_work;
     int* afwd = h_work + (nprob + 1);
     int* arun = h_work + 2 * (nprob + 1);
     int* aadj = h_work + 3 * (nprob + 1);
+    BatchWork* hw = (BatchWork*)(h_work + nwork_lists);
     long long slabs = 0;
     for (int i = 0; i < nprob; ++i)
       if (h_active[i]) slabs += Gs[i].n3;
-    const int run = B.wave ? (int)std::max(1LL, std::min(8LL, slabs / 2048)) : 1;
+    const int run0 = B.wave ? (int)std::max(1LL, std::min(8LL, slabs / 2048)) : 1;
     int k = 0;
     afwd[0] = arun[0] = aadj[0] = 0;
     // grouped by the register kernel's shape class (one slab-phase launch per class)
     for (int c = 0; c < 4; ++c) {
-      B.cls_k[c] = k;
+      const int run = B.wave && tuned_run[c] > 0 ? tuned_run[c] : run0;
+      hw->run[c] = run;
+      hw->cls_k[c] = k;
       for (int i = 0; i < nprob; ++i) {
         if (!h_active[i]) continue;
-        const int ci = (Gs[i].PT == 1 ? 1 : 0) + (Gs[i].N1T <= 4 ? 2 : 0);
+        const int ci = B.wave ? (Gs[i].PT == 1 ? 1 : 0) + (Gs[i].N1T <= 4 ? 2 : 0) : 0;
         if (ci != c) continue;
         act[k] = i;
         afwd[k + 1] = afwd[k] + nfwd[i];
@@ -1553,15 +1618,75 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
         aadj[k + 1] = aadj[k] + nadj[i];
         ++k;
       }
-      B.cls_runs[c] = arun[k] - arun[B.cls_k[c]];
+      cls_runs[c] = arun[k] - arun[hw->cls_k[c]];
     }
-    B.cls_k[4] = k;
-    B.nact = k;
-    B.run = run;
+    hw->cls_k[4] = k;
+    hw->nact = k;
     tot[0] = afwd[k];
     tot[1] = arun[k];
     tot[2] = aadj[k];
     return hipMemcpyAsync(d_work, h_work, sizeof(int) * nwork, hipMemcpyHostToDevice, s);
+  };
+  // A block of check_every batched steps and the per-problem check maxima (into mapped host
+  // memory) is replayed as one captured HIP graph.  The kernels read the work list from device
+  // memory, so the graph stays valid while problems drop out; it is captured again when a grid
+  // would grow (a class the list holds has no launch in it, or more runs than workgroups) or
+  // could shrink to a quarter or less (the grid-stride kernels' idle workgroups exit at once,
+  // and every capture costs a few hundred microseconds).
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  struct BGraphGuard {
+    hipGraph_t* g; hipGraphExec_t* e;
+    ~BGraphGuard() { if (*e) (void)hipGraphExecDestroy(*e); if (*g) (void)hipGraphDestroy(*g); }
+  } bgg{&bgraph, &bexec};
+  BatchGrid bgrid{};
+  int bgraph_m = 0;
+  long long graph_replays = 0;
+  int graph_captures = 0;
+  auto block_grid = [&]() {
+    BatchGrid g = batched_grid(tot, cls_runs);
+    for (int c = 0; c < 4; ++c) g.wide[c] = tuned_wide[c];
+    return g;
+  };
+  auto graph_fits = [&](const BatchGrid& want, int m) {
+    if (!bexec || bgraph_m != m) return false;
+    for (int c = 0; c < 4; ++c) {
+      if (want.cls[c] > bgrid.cls[c]) return false;   // a class without a launch, or more runs
+      if (want.cls[c] > 0 && 4 * want.cls[c] <= bgrid.cls[c]) return false;
+      if (want.wide[c] != bgrid.wide[c]) return false;
+    }
+    if (want.fwd > bgrid.fwd || want.adj > bgrid.adj || want.slab > bgrid.slab) return false;
+    return !(4 * want.fwd <= bgrid.fwd || 4 * want.adj <= bgrid.adj || 4 * want.slab <= bgrid.slab);
+  };
+  auto run_block = [&](int m, bool use_graph) -> int {
+    const BatchGrid want = block_grid();
+    if (!use_graph) {
+      for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, want, lds, s));
+      BCHK(launch_segment_max(d_part, d_off_adj, nprob, h_seg_dev, s));
+      return GLAM_OK;
+    }
+    if (!graph_fits(want, m)) {
+      if (bexec) { (void)hipGraphExecDestroy(bexec); bexec = nullptr; }
+      if (bgraph) { (void)hipGraphDestroy(bgraph); bgraph = nullptr; }
+      BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      hipError_t e = hipSuccess;
+      for (int qq = 0; qq < m && e == hipSuccess; ++qq) e = launch_batched_step(dt, B, want, lds, s);
+      if (e == hipSuccess) e = launch_segment_max(d_part, d_off_adj, nprob, h_seg_dev, s);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fit_fail(GLAM_EDEVICE, std::string("batched step capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      bgraph = g;
+      BCHK(hipGraphInstantiate(&bexec, bgraph, nullptr, nullptr, 0));
+      ++graph_captures;
+      bgrid = want;
+      bgraph_m = m;
+    }
+    BCHK(hipGraphLaunch(bexec, s));
+    ++graph_replays;
+    return GLAM_OK;
   };
 
   // lambda_max_i and lambda_i (every problem's step 2 at theta = 0 before one synchronisation)
@@ -1588,6 +1713,61 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     res->kkt[i] = INFINITY;
     res->objective[i] = NAN;
   }
+  // ---- the tuner: the slab-phase variants of each shape class timed on the batch itself ----
+  auto now_seconds = []() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  };
+  bool tune_pending = opt->tuning == 0 && B.wave;
+  double tune_seconds = 0.0;
+  auto tune_classes = [&](bool* timed) -> int {
+    *timed = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fit_fail(GLAM_EDEVICE, "hipEventCreate failed");
+    }
+    struct EvPair { hipEvent_t a, b; ~EvPair() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evp{e0, e1};
+    for (int c = 0; c < 4; ++c) {
+      if (cls_runs[c] == 0) continue;
+      int np = 0;
+      long long slabs = 0;
+      for (int i = 0; i < nprob; ++i)
+        if (h_active[i] && (Gs[i].PT == 1 ? 1 : 0) + (Gs[i].N1T <= 4 ? 2 : 0) == c) { ++np; slabs += Gs[i].n3; }
+      const std::string key = tune_key(dt, c, np, slabs);
+      int run = 0, wide = 0;
+      if (tune_lookup(key, &run, &wide)) {
+        tuned_run[c] = run;
+        tuned_wide[c] = wide;
+        continue;
+      }
+      double best_us = INFINITY;
+      int brun = 1, bwide = 0;
+      *timed = true;
+      for (int w = 0; w < (c == 0 ? 1 : 2); ++w) {
+        for (int rl : {1, 2, 4, 8}) {
+          tuned_run[c] = rl;
+          tuned_wide[c] = w;
+          BCHK(upload_work());
+          const int grid = batched_grid(tot, cls_runs).cls[c];
+          BCHK(launch_batched_class(dt, B, c, w, grid, s));   // warm
+          BCHK(hipEventRecord(e0, s));
+          constexpr int kReps = 3;
+          for (int q = 0; q < kReps; ++q) BCHK(launch_batched_class(dt, B, c, w, grid, s));
+          BCHK(hipEventRecord(e1, s));
+          BCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          BCHK(hipEventElapsedTime(&ms, e0, e1));
+          const double us = ms * 1e3 / kReps;
+          if (us < best_us) { best_us = us; brun = rl; bwide = w; }
+        }
+      }
+      tuned_run[c] = brun;
+      tuned_wide[c] = bwide;
+      tune_store(key, brun, bwide);
+    }
+    return GLAM_OK;
+  };
+
   std::vector<char> done(nprob, 0);
   std::vector<double> tol_in(nprob), best(nprob), wbest(nprob);
   std::vector<char> exact(nprob, 0);   // the model is the objective: the inner solution is the step
@@ -1641,13 +1821,25 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
     int it = 0, window_start = 0;
     while (nact > 0 && it < opt->max_inner) {
       const int m = std::min(check_every, opt->max_inner - it);
-      for (int qq = 0; qq < m; ++qq) BCHK(launch_batched_step(dt, B, tot, lds, s));
+      {
+        const int r = run_block(m, opt->graph_mode == 0);
+        if (r) return r;
+      }
       launches += m;
       pstep += (long long)m * nact;
       it += m;
-      BCHK(launch_segment_max(d_part, d_off_adj, nprob, d_seg, s));
-      BCHK(hipMemcpyAsync(h_seg, d_seg, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost, s));
       BCHK(hipStreamSynchronize(s));
+      if (tune_pending) {
+        // the slab-phase variants of every class, timed once on this batch's own first block
+        // (T1 holds that block's last values; S2 is rewritten by the next step)
+        const double t0 = now_seconds();
+        bool timed = false;
+        const int r = tune_classes(&timed);
+        if (r) return r;
+        if (timed) tune_seconds += now_seconds() - t0;
+        tune_pending = false;
+        BCHK(upload_work());
+      }
       bool changed = false;
       const bool window = it - window_start >= kStallChecks * opt->check_every;
       for (int i = 0; i < nprob; ++i) {
@@ -1712,6 +1904,9 @@ extern "C" int glam_fit_batched(const glam_problem* probs_in, int nprob, const g
   BCHK(hipStreamWaitEvent(us, ev, 0));
   res->steps = launches;
   res->problem_steps = pstep;
+  res->graph_replays = graph_replays;
+  if (getenv("GLAM_LOG")) fprintf(stderr, "[glam] batched: %d graph captures, %lld replays\n", graph_captures, graph_replays);
+  res->tune_seconds = tune_seconds;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   if (worst != GLAM_OK) return fit_fail(worst, "some problems did not converge (see status)");
   return GLAM_OK;

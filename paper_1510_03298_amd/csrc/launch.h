@@ -177,31 +177,46 @@ struct BatchDesc {
   int fwd_gx;         // slab_fwd workgroup grid x
   int adj_gx;         // slab_adj workgroup grid x
 };
+// The compact work list of the active problems lives in device memory, so that a captured graph
+// of batched steps stays valid when the host rewrites the list (the kernels grid-stride over
+// whatever the list holds).  The register-kernel slab phase orders the list by shape class
+// (class c = P16 (p1, p2 <= 16) + 2 N1B4 (n1 <= 64)): class c holds entries cls_k[c] ..
+// cls_k[c+1] - 1, in runs of run[c] consecutive slabs of one problem.
+struct BatchWork {
+  int nact;
+  int cls_k[5];
+  int run[4];           // slabs per run, per class (the LDS slab kernel uses run[0])
+};
 struct BatchParams {
   const BatchDesc* desc;
   int nprob;
   const int* off_adj;   // prefix sums of slab_adj tiles over all problems (the partials index)
-  // compact work lists over the nact active problems
-  int nact;
+  const BatchWork* work;
   const int* act;       // active problem indices (nact)
   const int* aoff_fwd;  // prefix sums of slab_fwd tiles (nact + 1)
   const int* aoff_run;  // prefix sums of slab runs, ceil(n3 / run) per problem (nact + 1)
   const int* aoff_adj;  // prefix sums of slab_adj tiles (nact + 1)
-  int run;              // slabs per run
-  // register-kernel slab phase: the compact list is ordered by shape class (class c = P16 (p1, p2
-  // <= 16) + 2 N1B4 (n1 <= 64)); class c holds entries cls_k[c] .. cls_k[c+1] - 1 and cls_runs[c] runs
-  int cls_k[5];
-  int cls_runs[4];
-  int k0, k1;           // the class of one slab-phase launch
+  int cls;              // the class of one slab-phase launch
   int* step;            // inner step counter (read by the prox epilogue)
   int wave;             // slabs with the register kernel (S2 in 4-deep k-blocks; batched_wave)
+};
+// Launch shape of one batched step: workgroups of the forward phase, of each class's slab launch
+// (0: no launch; the list of a later block may hold fewer entries, never more of a class that
+// had none) and of the adjoint phase; wide[c] = 1 runs class c on the kernel of the next wider
+// shape (the full 32-deep p contraction, or eight X1 row tiles), the same values
+struct BatchGrid {
+  int fwd, adj, slab;   // slab: the LDS slab kernel (not wave)
+  int cls[4];
+  int wide[4];
 };
 // true when every problem of the batch fits the one-wave-per-slab kernel of this dtype
 bool batched_wave(int dt, const Geom* Gs, int nprob);
 size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob);
-// tot: {forward tiles, slab runs, adjoint tiles} over the active problems (the compact
-// offsets' last entries)
-hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s);
+// grid sizes for the given totals {forward tiles, slab runs, adjoint tiles} and class runs
+BatchGrid batched_grid(const int* tot, const int* cls_runs);
+hipError_t launch_batched_step(int dt, const BatchParams& B, const BatchGrid& g, size_t lds, hipStream_t s);
+// one class's slab launch alone (the tuner's timing unit)
+hipError_t launch_batched_class(int dt, const BatchParams& B, int c, int wide, int grid, hipStream_t s);
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s);
 
 // Gram inner gradient (Gaussian, identity weights): Z_k3 = S_1 D_k3 S_2 for every slice k3

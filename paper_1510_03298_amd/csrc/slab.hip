@@ -1395,9 +1395,10 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if constexpr (PH == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *B.step += 1;
-    const int totA = B.aoff_fwd[B.nact];
+    const int nact = B.work->nact;
+    const int totA = B.aoff_fwd[nact];
     for (int item = blockIdx.x; item < totA; item += gridDim.x) {
-      const int k = find_segment(B.aoff_fwd, B.nact, item);
+      const int k = find_segment(B.aoff_fwd, nact, item);
       const BatchDesc& D = B.desc[B.act[k]];
       const int loc = item - B.aoff_fwd[k];
       fwd_tile<T>(D.fw, loc % D.fwd_gx, loc / D.fwd_gx);
@@ -1405,14 +1406,15 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
   } else if constexpr (PH == 1) {
     // contiguous stretches of runs per workgroup: the LDS image is restaged only when the
     // problem changes
-    const int totB = B.aoff_run[B.nact];
+    const int nact = B.work->nact, run = B.work->run[0];
+    const int totB = B.aoff_run[nact];
     const int chunk = (totB + gridDim.x - 1) / gridDim.x;
     const int i0 = blockIdx.x * chunk, i1 = min(totB, i0 + chunk);
     int cur = -1;
     ChainLayout L;
     double s_nll = 0.0, s_vmax = 0.0;
     for (int item = i0; item < i1; ++item) {
-      const int k = find_segment(B.aoff_run, B.nact, item);
+      const int k = find_segment(B.aoff_run, nact, item);
       const int pb = B.act[k];
       const BatchDesc& D = B.desc[pb];
       if (pb != cur) {
@@ -1421,16 +1423,17 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
         chain_stage(D.sp.img, L.image_bytes, smem_raw);
         cur = pb;
       }
-      const int s0 = (item - B.aoff_run[k]) * B.run, s1 = min(D.sp.G.n3, s0 + B.run);
+      const int s0 = (item - B.aoff_run[k]) * run, s1 = min(D.sp.G.n3, s0 + run);
       for (int i3 = s0; i3 < s1; ++i3) {
         if (D.sp.G.PT == 1) chain_slab<T, 1, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
         else chain_slab<T, 2, SM_FUSED>(D.sp, L, smem_raw, i3, s_nll, s_vmax);
       }
     }
   } else {
-    const int totC = B.aoff_adj[B.nact];
+    const int nact = B.work->nact;
+    const int totC = B.aoff_adj[nact];
     for (int item = blockIdx.x; item < totC; item += gridDim.x) {
-      const int k = find_segment(B.aoff_adj, B.nact, item);
+      const int k = find_segment(B.aoff_adj, nact, item);
       const int pb = B.act[k];
       const BatchDesc& D = B.desc[pb];
       const int loc = item - B.aoff_adj[k];
@@ -1449,12 +1452,13 @@ __global__ __launch_bounds__(WG) void k_batched_phase(BatchParams B) {
 template <typename T, bool P16, int N1B>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_batched_slabs(BatchParams B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];   // wave_lds_bytes<T, 1, 4>()
-  const int r0 = B.aoff_run[B.k0], r1 = B.aoff_run[B.k1];
+  const int k0 = B.work->cls_k[B.cls], k1 = B.work->cls_k[B.cls + 1], run = B.work->run[B.cls];
+  const int r0 = B.aoff_run[k0], r1 = B.aoff_run[k1];
   for (int item = r0 + blockIdx.x; item < r1; item += gridDim.x) {
-    const int k = B.k0 + find_segment(B.aoff_run + B.k0, B.k1 - B.k0, item);
+    const int k = k0 + find_segment(B.aoff_run + k0, k1 - k0, item);
     const BatchDesc& D = B.desc[B.act[k]];
-    const int s0 = (item - B.aoff_run[k]) * B.run;
-    const int nrep = min(B.run, D.sp.G.n3 - s0);
+    const int s0 = (item - B.aoff_run[k]) * run;
+    const int nrep = min(run, D.sp.G.n3 - s0);
     if (D.sp.v_int) wave_chain_group<T, SM_FUSED, true, 1, 4, P16, N1B>(D.sp, smem_raw, s0, nrep);
     else wave_chain_group<T, SM_FUSED, false, 1, 4, P16, N1B>(D.sp, smem_raw, s0, nrep);
     __syncthreads();   // LDS of the next item
@@ -1710,33 +1714,51 @@ size_t batched_lds_bytes(int dt, const Geom* Gs, int nprob) {
   return m;
 }
 
-template <typename T, bool WAVE>
-static hipError_t batched_phases(const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
+BatchGrid batched_grid(const int* tot, const int* cls_runs) {
   const int cap = 8 * num_cus();
-  const int gA = std::max(1, std::min(tot[0], cap));
-  const int gB = std::max(1, std::min(tot[1], WAVE ? cap : 4 * num_cus()));
-  const int gC = std::max(1, std::min(tot[2], cap));
-  hipLaunchKernelGGL((k_batched_phase<T, 0, WAVE>), dim3(gA), dim3(WG), 0, s, B);
+  BatchGrid g{};
+  g.fwd = std::max(1, std::min(tot[0], cap));
+  g.slab = std::max(1, std::min(tot[1], 4 * num_cus()));
+  g.adj = std::max(1, std::min(tot[2], cap));
+  for (int c = 0; c < 4; ++c) g.cls[c] = cls_runs[c] > 0 ? std::max(1, std::min(cls_runs[c], cap)) : 0;
+  return g;
+}
+
+// class c (P16 = c & 1, N1B = c & 2 ? 4 : 8); wide: P16 off and N1B = 8 (every shape of the
+// class fits the wider kernel, whose extra products are exact zeros)
+template <typename T>
+static void launch_class(const BatchParams& B, int c, int wide, int grid, hipStream_t s) {
+  constexpr size_t wl = (size_t)wave_lds_bytes<T, 1, 4>();
+  BatchParams Bc = B;
+  Bc.cls = c;
+  const dim3 gc(grid);
+  const bool p16 = (c & 1) && !wide, n1b4 = (c & 2) && !wide;
+  if (!p16 && !n1b4) hipLaunchKernelGGL((k_batched_slabs<T, false, 8>), gc, dim3(WG), wl, s, Bc);
+  else if (p16 && !n1b4) hipLaunchKernelGGL((k_batched_slabs<T, true, 8>), gc, dim3(WG), wl, s, Bc);
+  else if (!p16) hipLaunchKernelGGL((k_batched_slabs<T, false, 4>), gc, dim3(WG), wl, s, Bc);
+  else hipLaunchKernelGGL((k_batched_slabs<T, true, 4>), gc, dim3(WG), wl, s, Bc);
+}
+
+template <typename T, bool WAVE>
+static hipError_t batched_phases(const BatchParams& B, const BatchGrid& g, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_batched_phase<T, 0, WAVE>), dim3(g.fwd), dim3(WG), 0, s, B);
   if constexpr (WAVE) {
-    // one launch per shape class present (class c: P16 = c & 1, N1B = c & 2 ? 4 : 8)
-    constexpr size_t wl = (size_t)wave_lds_bytes<T, 1, 4>();
-    for (int c = 0; c < 4; ++c) {
-      if (B.cls_runs[c] == 0) continue;
-      BatchParams Bc = B;
-      Bc.k0 = B.cls_k[c];
-      Bc.k1 = B.cls_k[c + 1];
-      const dim3 gc(std::max(1, std::min(B.cls_runs[c], cap)));
-      if (c == 0) hipLaunchKernelGGL((k_batched_slabs<T, false, 8>), gc, dim3(WG), wl, s, Bc);
-      else if (c == 1) hipLaunchKernelGGL((k_batched_slabs<T, true, 8>), gc, dim3(WG), wl, s, Bc);
-      else if (c == 2) hipLaunchKernelGGL((k_batched_slabs<T, false, 4>), gc, dim3(WG), wl, s, Bc);
-      else hipLaunchKernelGGL((k_batched_slabs<T, true, 4>), gc, dim3(WG), wl, s, Bc);
-    }
-    (void)gB;
+    // one launch per shape class present
+    for (int c = 0; c < 4; ++c)
+      if (g.cls[c] > 0) launch_class<T>(B, c, g.wide[c], g.cls[c], s);
   } else {
     set_lds(k_batched_phase<T, 1, WAVE>, lds);
-    hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(gB), dim3(WG), lds, s, B);
+    hipLaunchKernelGGL((k_batched_phase<T, 1, WAVE>), dim3(g.slab), dim3(WG), lds, s, B);
   }
-  hipLaunchKernelGGL((k_batched_phase<T, 2, WAVE>), dim3(gC), dim3(WG), 0, s, B);
+  hipLaunchKernelGGL((k_batched_phase<T, 2, WAVE>), dim3(g.adj), dim3(WG), 0, s, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_class(int dt, const BatchParams& B, int c, int wide, int grid, hipStream_t s) {
+  if (!B.wave || grid < 1) return hipErrorInvalidValue;
+  if (dt == DT_F32) launch_class<float>(B, c, wide, grid, s);
+  else if (dt == DT_BF16) launch_class<bf16>(B, c, wide, grid, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1747,10 +1769,10 @@ bool batched_wave(int dt, const Geom* Gs, int nprob) {
   return true;
 }
 
-hipError_t launch_batched_step(int dt, const BatchParams& B, const int* tot, size_t lds, hipStream_t s) {
-  if (dt == DT_F64) return batched_phases<double, false>(B, tot, lds, s);
-  if (dt == DT_F32) return B.wave ? batched_phases<float, true>(B, tot, lds, s) : batched_phases<float, false>(B, tot, lds, s);
-  return B.wave ? batched_phases<bf16, true>(B, tot, lds, s) : batched_phases<bf16, false>(B, tot, lds, s);
+hipError_t launch_batched_step(int dt, const BatchParams& B, const BatchGrid& g, size_t lds, hipStream_t s) {
+  if (dt == DT_F64) return batched_phases<double, false>(B, g, lds, s);
+  if (dt == DT_F32) return B.wave ? batched_phases<float, true>(B, g, lds, s) : batched_phases<float, false>(B, g, lds, s);
+  return B.wave ? batched_phases<bf16, true>(B, g, lds, s) : batched_phases<bf16, false>(B, g, lds, s);
 }
 
 hipError_t launch_segment_max(const double* partials, const int* off, int nprob, double* out, hipStream_t s) {

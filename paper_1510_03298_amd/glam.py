@@ -64,7 +64,7 @@ class GlamBatchOptions(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_double)), ("lambda_ratio", ctypes.c_double),
                 ("dtype", ctypes.c_int), ("kkt_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("max_inner", ctypes.c_int), ("check_every", ctypes.c_int), ("stream", _vp),
-                ("alpha", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("tuning", ctypes.c_int), ("graph_mode", ctypes.c_int)]
 
 
 class GlamBatchResult(ctypes.Structure):
@@ -72,7 +72,8 @@ class GlamBatchResult(ctypes.Structure):
                 ("lambda_max", ctypes.POINTER(ctypes.c_double)), ("kkt", ctypes.POINTER(ctypes.c_double)),
                 ("objective", ctypes.POINTER(ctypes.c_double)), ("iters_outer", ctypes.POINTER(ctypes.c_int)),
                 ("status", ctypes.POINTER(ctypes.c_int)), ("steps", ctypes.c_longlong),
-                ("problem_steps", ctypes.c_longlong), ("seconds", ctypes.c_double)]
+                ("problem_steps", ctypes.c_longlong), ("seconds", ctypes.c_double),
+                ("graph_replays", ctypes.c_longlong), ("tune_seconds", ctypes.c_double)]
 
 
 def _sig(name, res, args):
@@ -451,13 +452,18 @@ class BatchResult:
     problem_steps: int
     seconds: float
     code: int
+    graph_replays: int = 0
+    tune_seconds: float = 0.0
 
 
 def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-6, max_outer=100,
-                max_inner=100000, check_every=10, stream=None, raise_on_error=True, alpha=0.0) -> BatchResult:
+                max_inner=100000, check_every=10, stream=None, raise_on_error=True, alpha=0.0, tuning="auto",
+                graph=True) -> BatchResult:
     """Fit many independent problems (one lambda each) with three batched launches per
     batched proximal step.  problems: list of dicts with keys X (3 FP64 device
-    factors), Y (FP64 device n-array), n, p, family, and optional obs_w, pen_w."""
+    factors), Y (FP64 device n-array), n, p, family, and optional obs_w, pen_w.  tuning: "auto"
+    (the slab-phase variants timed once per shape class) or "fixed"; graph: replay each block of
+    check_every steps as a captured HIP graph."""
     torch = _torch()
     nprob = len(problems)
     arr = (GlamProblem * nprob)()
@@ -484,6 +490,8 @@ def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-
     opt.max_outer, opt.max_inner, opt.check_every = int(max_outer), int(max_inner), int(check_every)
     opt.stream = _stream_ptr(stream)
     opt.alpha = float(alpha)
+    opt.tuning = {"auto": 0, "fixed": 1}[tuning]
+    opt.graph_mode = 0 if graph else 1
     dev = problems[0]["Y"].device
     thetas = [torch.zeros(int(np.prod(pr["p"])), dtype=torch.float64, device=dev) for pr in problems]
     tp = (_vp * nprob)(*[t.data_ptr() for t in thetas])
@@ -499,7 +507,8 @@ def fit_batched(problems, lambdas=None, lambda_ratio=0.1, dtype=F32, kkt_tol=1e-
         raise GlamError(code, "glam_fit_batched")
     out = BatchResult(thetas, np.array(outs[0][:]), np.array(outs[1][:]), np.array(outs[2][:]),
                       np.array(outs[3][:]), np.array(io[:]), np.array(st[:]), int(res.steps),
-                      int(res.problem_steps), float(res.seconds), int(code))
+                      int(res.problem_steps), float(res.seconds), int(code), int(res.graph_replays),
+                      float(res.tune_seconds))
     if raise_on_error and code != GLAM_OK:
         raise GlamError(code, "glam_fit_batched")
     return out

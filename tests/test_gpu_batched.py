@@ -170,3 +170,31 @@ def test_batched_reports_the_invalid_problem():
     with pytest.raises(glam.GlamError) as e:
         glam.fit_batched(ups, lambda_ratio=0.1, dtype=1)
     assert "problem 3" in str(e.value) and "Poisson Y must be >= 0" in str(e.value)
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+def test_batched_tuned_graph_matches_fixed_eager(dt, tmp_path, monkeypatch):
+    """The tuner's slab-phase variants (run length, kernel width) and the graph replays compute the
+    same values: tuned + graph and fixed + stream launches give bit-identical estimates.  The tuned
+    choices are written to GLAM_TUNE_FILE and read back by a second tuned call (no new timing)."""
+    torch, glam = need_gpu()
+    tune = tmp_path / "tune.txt"
+    monkeypatch.setenv("GLAM_TUNE_FILE", str(tune))
+    probs = inputs.config_c4(nprob=24, lo=16, hi=96, seed_offset=43)
+    ups = [_upload(glam, d) for d in probs]
+    print(f"batched tuned vs fixed dt={dt}", flush=True)
+    r1 = glam.fit_batched(ups, lambda_ratio=0.1, dtype=dt, kkt_tol=1e-6, tuning="auto", graph=True)
+    r2 = glam.fit_batched(ups, lambda_ratio=0.1, dtype=dt, kkt_tol=1e-6, tuning="fixed", graph=False)
+    assert r1.code == r2.code == 0
+    assert r1.graph_replays > 0 and r2.graph_replays == 0
+    for a, b in zip(r1.theta, r2.theta):
+        assert torch.equal(a, b)
+    assert np.array_equal(r1.iters_outer, r2.iters_outer)
+    for i, d in enumerate(probs):
+        lm = O.lambda_max(d.family, d.X, d.Y)
+        th = glam.from_colmajor(r1.theta[i], d.p)
+        assert O.kkt_residual(th, O.smooth_gradient(d.family, d.X, th, d.Y), 0.1 * lm, lm) <= 1e-6
+    r3 = glam.fit_batched(ups, lambda_ratio=0.1, dtype=dt, kkt_tol=1e-6, tuning="auto", graph=True)
+    assert r3.tune_seconds == 0.0   # every class signature already tuned in this process
+    for a, b in zip(r1.theta, r3.theta):
+        assert torch.equal(a, b)
