@@ -244,11 +244,12 @@ def poisson_path_kron(glam, inputs, torch, stream):
     Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
     Yd = glam.to_device_colmajor(d.Y, glam.F64)
     out = {"workload": "poisson_path_n64x64x365_p24x24x120_50lambda_kkt1e-6_kron_weights"}
-    for dt, name in ((glam.F32, "f32"), (glam.F64, "f64")):
+    for dt, name, step in ((glam.F32, "f32", "prop1"), (glam.F64, "f64", "prop1"), (glam.F32, "f32_exact_L", "exact")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=d.nlambda, lambda_min_ratio=d.lambda_min_ratio,
-                          dtype=dt, kkt_tol=1e-6, stream=stream, raise_on_error=False, inner="kron", max_outer=400)
+                          dtype=dt, kkt_tol=1e-6, stream=stream, raise_on_error=False, inner="kron", max_outer=400,
+                          kron_step=step)
         torch.cuda.synchronize()
         out[name] = {"seconds": time.perf_counter() - t0, "models": int(r.n_done),
                      "converged": r.code == 0 and r.n_done == d.nlambda,
@@ -388,7 +389,8 @@ def main():
         only = {"batched_c4": lambda: batched(glam, inputs, torch, stream),
                 "poisson_nll_c5": lambda: nll(glam, inputs, torch, stream),
                 "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream),
-                "gaussian_c1": lambda: c1_single_lambda(glam, inputs, torch, stream)}
+                "gaussian_c1": lambda: c1_single_lambda(glam, inputs, torch, stream),
+                "poisson_path_c3_kron": lambda: poisson_path_kron(glam, inputs, torch, stream)}
         if args.only not in only:
             print(f"bench.py: --only takes one of {sorted(only)}", file=sys.stderr)
             sys.exit(2)

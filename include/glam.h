@@ -193,6 +193,13 @@ typedef struct {
                              rho-chain loop with nu = 1, the other forms keep 1;
                              1: omega_l = (l - 1)/(l + 2), l counted from the start of each
                              inner loop (the paper's example sequence)                */
+  int kron_step;          /* GLAM_INNER_KRON only: 0 (default): delta from Proposition 1 with
+                             max V-hat; 1: delta from the exact Lipschitz constant of the
+                             tensor-product model, (1/n) prod_j rho(X_j^T W_j X_j) (Sec. 5),
+                             the radii by the power method each outer step (Proposition 1
+                             where it does not converge).  The longer step shortens the inner
+                             loops but, with V-hat's approximate curvature, can lengthen the
+                             outer loop (Poisson n = (64, 64, 365): it stalls; see the notes) */
 } glam_options;
 
 /* Inner-gradient evaluation.  GLAM_INNER_CHAIN: G(X, V .* H(X, x - theta_ref)) / n through the

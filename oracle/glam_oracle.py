@@ -479,6 +479,14 @@ def lipschitz_bound(Xs, w, n):
     return float(np.max(w)) * float(np.prod(spectral_radii(Xs))) / n
 
 
+def lipschitz_tensor_weights(Xs, factors, n):
+    """Sec. 5, after Proposition 1: when the weights form a tensor product W = W_d (x) ... (x) W_1
+    (W_j = diag(factors[j])), X^T W X is the tensor product of the X_j^T W_j X_j, so the Lipschitz
+    constant of grad h is exactly (1/n) prod_j rho(X_j^T W_j X_j)."""
+    return float(np.prod([np.linalg.eigvalsh(np.asarray(X).T @ (np.asarray(v)[:, None] * np.asarray(X)))[-1]
+                          for X, v in zip(Xs, factors)])) / n
+
+
 def lambda_max(fam, Xs, Y, a=None, pen_w=None):
     """Smallest lambda with the zero solution (Sec. 6.4): at theta = 0 the KKT
     conditions read |g_m| <= lambda w_m with g = -G(U(0))/n."""

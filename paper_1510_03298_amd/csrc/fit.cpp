@@ -190,6 +190,7 @@ struct Fit {
   bool kron = false;       // Gram factors reweighted each outer step with tensor-product weights (Sec. 6.2)
   bool unit_w = false;     // unit IRLS weights in the model of every family (the Gram form with W = I)
   double* kron_work = nullptr;    // log-weight margins and the factors v_j
+  bool kron_first = true;         // the power method of the Gram factors starts from ones
   double* kron_stats = nullptr;   // {max v_1, max v_2, max v_3, Vbar} (device)
   bool gram_fused = false; // Gram iteration as one launch (k_gram_iter): increment and counter double-buffered
   void* inc2 = nullptr;    // the second increment buffer
@@ -1027,6 +1028,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
     return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
   if (opt->extrapolation != 0 && opt->extrapolation != 1) return fit_fail(GLAM_EINVAL, "bad extrapolation");
+  if (opt->kron_step != 0 && opt->kron_step != 1) return fit_fail(GLAM_EINVAL, "bad kron_step");
   if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
       !res->status)
     return fit_fail(GLAM_EINVAL, "NULL result array");
@@ -1185,9 +1187,20 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         PCHK(launch_kron_weights(G, F.family, F.eta_int, prob->X[0], prob->X[1], prob->X[2], F.kron_work,
                                  F.kron_stats, F.S1g, F.S2g, F.S3g, F.s));
         if (!F.gram_fused) PCHK(launch_pack(F.dt, DT_F64, F.S3g, G.p3, G.p3, 1, G.p3, F.S3c, F.s));
-        PCHK(hipMemcpyAsync(F.hred, F.kron_stats, 4 * sizeof(double), hipMemcpyDeviceToHost, F.s));
+        // Sec. 5: with tensor-product weights the Lipschitz constant is exact,
+        // L = (1/n) prod_j rho(X_j^T W_j X_j) (Vbar folded into S_3); the power method's bounds
+        // replace Proposition 1 whenever all three factors converged
+        if (opt->kron_step == 1) {
+          PCHK(launch_gram_radii(G, F.S1g, F.S2g, F.S3g, F.kron_work, F.kron_first ? 1 : 0, F.kron_stats, F.s));
+          F.kron_first = false;
+        }
+        PCHK(hipMemcpyAsync(F.hred, F.kron_stats, 8 * sizeof(double), hipMemcpyDeviceToHost, F.s));
         PCHK(hipStreamSynchronize(F.s));
         wmax = F.hred[3] * F.hred[0] * F.hred[1] * F.hred[2];
+        if (opt->kron_step == 1 && F.hred[7] == 1.0) {
+          const double lex = F.hred[4] * F.hred[5] * F.hred[6] / F.sprod;   // so that Lhat = lex sprod / n
+          if (lex > 0.0 && std::isfinite(lex) && lex <= wmax) wmax = lex;
+        }
       }
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }

@@ -388,6 +388,88 @@ __global__ __launch_bounds__(256) void k_kron_gram(Geom G, const double* __restr
   }
 }
 
+// Spectral radii of the weighted Gram factors (Sec. 5: with tensor-product weights the Lipschitz
+// constant of grad h is exactly (1/n) prod_j rho(X_j^T W_j X_j)).  One workgroup per factor runs
+// the power method on the symmetric positive semidefinite S_j from the previous outer step's
+// vector (or the all-ones vector, first), to a residual ||S x - r x|| <= 1e-9 r of the Rayleigh
+// quotient r = x^T S x (||x|| = 1), at most 500 steps.  Some eigenvalue lies within the residual of
+// r, so stats[4 + j] = r + residual bounds the top one once the vector has converged to it;
+// stats[7] = 1 when all three factors converged (the caller falls back to Proposition 1 otherwise).
+size_t kron_work_doubles(const Geom& G);
+__global__ void k_set_one_d(double* p) { *p = 1.0; }
+
+constexpr int KRON_MAX_P = 2048;
+__global__ __launch_bounds__(256) void k_gram_radii(const double* __restrict__ S1, const double* __restrict__ S2,
+                                                    const double* __restrict__ S3, int p1, int p2, int p3,
+                                                    double* __restrict__ xs, int first, double* __restrict__ stats) {
+  __shared__ double x[KRON_MAX_P], y[KRON_MAX_P];
+  __shared__ double red[2][8];
+  __shared__ int conv_flag;
+  const int j = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double* S = j == 0 ? S1 : (j == 1 ? S2 : S3);
+  const int p = j == 0 ? p1 : (j == 1 ? p2 : p3);
+  double* xv = xs + (j == 0 ? 0 : (j == 1 ? p1 : p1 + p2));
+  // start vector, normalised
+  double ss = 0.0;
+  for (int i = t; i < p; i += 256) {
+    const double v = first ? 1.0 : xv[i];
+    x[i] = v;
+    ss += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+  if (lane == 0) red[0][w] = ss;
+  __syncthreads();
+  double nrm = sqrt(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+  if (!(nrm > 0.0)) nrm = 1.0;   // a zero or non-finite saved vector: start again from ones
+  __syncthreads();
+  for (int i = t; i < p; i += 256) x[i] = (first || !(red[0][0] + red[0][1] + red[0][2] + red[0][3] > 0.0)) ? 1.0 / sqrt((double)p) : x[i] / nrm;
+  if (t == 0) conv_flag = 0;
+  __syncthreads();
+  double rq = 0.0, res = INFINITY;
+  for (int it = 0; it < 500; ++it) {
+    double a = 0.0, b = 0.0;
+    for (int i = t; i < p; i += 256) {
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += S[(long long)k * p + i] * x[k];
+      y[i] = s;
+      a += x[i] * s;
+      b += s * s;
+    }
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_xor(a, o, 64); b += __shfl_xor(b, o, 64); }
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; }
+    __syncthreads();
+    rq = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double yy = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    res = sqrt(fmax(yy - rq * rq, 0.0));   // ||S x - rq x|| for ||x|| = 1
+    const double ny = sqrt(yy);
+    const bool done = res <= 1e-9 * rq || !(ny > 0.0);
+    __syncthreads();
+    if (ny > 0.0)
+      for (int i = t; i < p; i += 256) x[i] = y[i] / ny;
+    __syncthreads();
+    if (done) {
+      if (t == 0) conv_flag = ny > 0.0 ? 1 : 0;
+      break;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < p; i += 256) xv[i] = x[i];
+  if (t == 0) {
+    stats[4 + j] = rq + res;
+    // the converged flags of the three factors multiply into stats[7] (set to 1 before the launch)
+    if (!conv_flag) stats[7] = 0.0;
+  }
+}
+
+hipError_t launch_gram_radii(const Geom& G, const double* S1, const double* S2, const double* S3, double* work,
+                             int first, double* stats, hipStream_t s) {
+  if (G.p1 > KRON_MAX_P || G.p2 > KRON_MAX_P || G.p3 > KRON_MAX_P) return hipErrorInvalidValue;
+  double* xs = work + (kron_work_doubles(G) - (size_t)(G.p1 + G.p2 + G.p3));
+  hipLaunchKernelGGL(k_set_one_d, dim3(1), dim3(1), 0, s, stats + 7);
+  hipLaunchKernelGGL(k_gram_radii, dim3(3), dim3(256), 0, s, S1, S2, S3, G.p1, G.p2, G.p3, xs, first, stats);
+  return hipGetLastError();
+}
+
 hipError_t launch_kron_weights(const Geom& G, int family, const double* eta_int, const double* X1, const double* X2,
                                const double* X3, double* work, double* stats, double* S1, double* S2, double* S3,
                                hipStream_t s) {
@@ -406,7 +488,8 @@ hipError_t launch_kron_weights(const Geom& G, int family, const double* eta_int,
 }
 
 size_t kron_work_doubles(const Geom& G) {
-  return (size_t)G.n3 * G.n1 + (size_t)G.n3 * G.n2 + 2 * (size_t)G.n3 + G.n1 + G.n2;
+  // log-weight margins, the factors v_j, then the power-method vectors of the three Gram factors
+  return (size_t)G.n3 * G.n1 + (size_t)G.n3 * G.n2 + 2 * (size_t)G.n3 + G.n1 + G.n2 + G.p1 + G.p2 + G.p3;
 }
 
 }  // namespace glam

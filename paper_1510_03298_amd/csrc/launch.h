@@ -254,6 +254,11 @@ hipError_t launch_kron_weights(const Geom& G, int family, const double* eta_int,
                                const double* X3, double* work, double* stats, double* S1, double* S2, double* S3,
                                hipStream_t s);
 hipError_t launch_gram_iter(int dt, const GramIterParams& P, int* nblk_out, hipStream_t s);
+// spectral radii of S1, S2, S3 (FP64 p_j x p_j, symmetric PSD) by the power method from the vectors
+// kept in work (first: from ones): stats[4 + j] = an upper bound of rho(S_j) once converged,
+// stats[7] = 1 if all three converged (else 0)
+hipError_t launch_gram_radii(const Geom& G, const double* S1, const double* S2, const double* S3, double* work,
+                             int first, double* stats, hipStream_t s);
 
 // rho kernels
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s);

@@ -47,7 +47,7 @@ class GlamOptions(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("theta0", _vp), ("stream", _vp), ("profile_every", ctypes.c_int),
                 ("graph_mode", ctypes.c_int), ("inner_mode", ctypes.c_int), ("alpha", ctypes.c_double),
                 ("penalty", ctypes.c_int), ("scad_a", ctypes.c_double), ("msa_steps", ctypes.c_int),
-                ("extrapolation", ctypes.c_int)]
+                ("extrapolation", ctypes.c_int), ("kron_step", ctypes.c_int)]
 
 
 class GlamResult(ctypes.Structure):
@@ -371,7 +371,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
              check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
              graph=True, inner="chain", alpha=0.0, penalty="lasso", scad_a=3.7, msa_steps=3,
-             extrapolation="restarted") -> PathResult:
+             extrapolation="restarted", kron_step="prop1") -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
     alpha: elastic-net weight (0 = lasso); penalty="scad": SCAD by msa_steps steps of
@@ -413,6 +413,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.scad_a = float(scad_a)
     opt.msa_steps = int(msa_steps)
     opt.extrapolation = {"restarted": 0, "plain": 1}[extrapolation]
+    opt.kron_step = {"prop1": 0, "exact": 1}[kron_step]
     P = int(np.prod(p))
     theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
     lam_out = (ctypes.c_double * L)()

@@ -494,6 +494,25 @@ def test_kron_weight_inner_loop(fam, dt):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="kron", nu=0.5)
 
 
+@pytest.mark.parametrize("fam,dt", [("binomial", 1), ("poisson", 0)])
+def test_kron_weight_exact_lipschitz(fam, dt):
+    """Sec. 5: with tensor-product weights the Lipschitz constant of the model's gradient is exactly
+    (1/n) prod_j rho(X_j^T W_j X_j).  With that step (kron_step="exact", radii by the power method on
+    the device) the path still reaches the PMLE: the oracle's KKT on every model."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((23, 19, 37), (9, 7, 12), family=fam, seed=38, basis="gauss", scale=0.3)
+    print(f"kron exact L {fam} dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=3, lambda_min_ratio=0.3, dtype=dt, kkt_tol=1e-6,
+                        inner="kron", max_outer=800, kron_step="exact")
+    assert res.code == 0, (res.code, res.status)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    for l in range(3):
+        th = _theta(glam, res, l, d.p)
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6
+
+
 @pytest.mark.parametrize("fam,dt,n,p", [("gaussian", 2, (256, 256, 9), (16, 16, 4)),
                                         ("poisson", 1, (128, 128, 9), (32, 32, 4))])
 def test_largest_inner_modes(fam, dt, n, p):

@@ -110,6 +110,10 @@ MUTANTS = {
     "nll_sign_y": ("poisson_nll",
                    lambda orig: (lambda Xs, beta, Y: float(np.sum(np.exp(O.H(Xs, beta)) + Y * O.H(Xs, beta))) / Y.size),
                    lambda: [P.test_poisson_nll_constant_predictor_closed_form]),
+    # exact tensor-weight Lipschitz constant with the weights dropped from the Gram factors
+    "lexact_no_weights": ("lipschitz_tensor_weights",
+                          lambda orig: (lambda Xs, factors, n: orig(Xs, [np.ones_like(v) for v in factors], n)),
+                          lambda: [P.test_exact_lipschitz_for_tensor_product_weights]),
     # Lipschitz bound with a sum of spectral radii instead of the product
     "lhat_sum": ("lipschitz_bound",
                  lambda orig: (lambda Xs, w, n: float(np.max(w)) * float(np.sum(O.spectral_radii(Xs))) / n),

@@ -544,6 +544,21 @@ def test_fista_rate_theorem1():
         assert Gobj(x) - Gs <= 2 * L * R2 / (l + 1) ** 2 * (1 + 1e-9) + 1e-14
 
 
+def test_exact_lipschitz_for_tensor_product_weights():
+    """Sec. 5: for W = W_3 (x) W_2 (x) W_1 the Lipschitz constant of grad h, rho(X^T W X)/n on the
+    explicit design, equals (1/n) prod_j rho(X_j^T W_j X_j); for other positive W Proposition 1's
+    max(w) prod_j rho(X_j^T X_j)/n only bounds it."""
+    rng = np.random.default_rng(17)
+    Xs = [rng.standard_normal((nj, pj)) for nj, pj in ((6, 3), (5, 4), (7, 2))]
+    vs = [rng.uniform(0.2, 3.0, X.shape[0]) for X in Xs]
+    Xd = O.kron_design(Xs)
+    w = np.kron(vs[2], np.kron(vs[1], vs[0]))   # vec order: mode 1 fastest
+    n = Xd.shape[0]
+    L = float(np.linalg.eigvalsh(Xd.T @ (w[:, None] * Xd))[-1]) / n
+    assert abs(O.lipschitz_tensor_weights(Xs, vs, n) - L) <= 1e-12 * L
+    assert O.lipschitz_bound(Xs, w, n) >= L * (1 - 1e-12)
+
+
 def test_nu_backtracking_reaches_same_solution():
     """nu in (0,1): larger initial step with backtracking (R7) gives the same PMLE."""
     d = inputs.random_problem((7, 6, 5), (4, 3, 3), family="poisson", seed=10, scale=0.4, basis="gauss")
