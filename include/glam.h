@@ -55,8 +55,11 @@ typedef enum {
  * mu (1 - mu) and 1 respectively (Gamma-log is a non-canonical link: Fisher scoring). */
 typedef enum { GLAM_GAUSSIAN = 0, GLAM_POISSON = 1, GLAM_BINOMIAL = 2, GLAM_GAMMA = 3 } glam_family;
 
-/* Penalty J of the PMLE (Sec. 2 eq. five; Sec. 6.4). */
-typedef enum { GLAM_PENALTY_LASSO = 0, GLAM_PENALTY_SCAD = 1 } glam_penalty;
+/* Penalty J of the PMLE (Sec. 2 eq. five; Sec. 6.3, 6.4).  GLAM_PENALTY_RIDGE: J = sum_m w_m
+ * theta_m^2, whose prox is the multiplicative shrinkage z / (1 + 2 delta lambda w_m) (Sec. 6.3); it has
+ * no zero solution, so its lambda grid and KKT scale are the lasso's lambda_max, and the KKT
+ * residual is |g_m + 2 lambda w_m theta_m|; alpha must be 0 with it. */
+typedef enum { GLAM_PENALTY_LASSO = 0, GLAM_PENALTY_SCAD = 1, GLAM_PENALTY_RIDGE = 2 } glam_penalty;
 
 /* Element type of the rho products.  F64: all FP64.  F32: FP32 inputs and
  * outputs, FP32 accumulation.  BF16: bfloat16 inputs (stored as uint16_t),
@@ -152,7 +155,8 @@ typedef struct {
                              0 < nu < 1: delta = 1/(nu Lhat), halved (never below 1/Lhat)
                              whenever the sufficient-decrease test of a step fails
                              (host-checked every inner iteration, no graph replay);
-                             nu = 0 is not supported                                */
+                             nu = 0: delta starts at 1 and the same test runs at every
+                             iteration (halving never below 1/Lhat)                  */
   int max_outer;          /* outer (Alg. 1) iterations per lambda, e.g. 100         */
   int max_inner;          /* inner PG iterations per outer iteration, e.g. 100000   */
   int check_every;        /* inner iterations between host convergence checks (>= 1) */

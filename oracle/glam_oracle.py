@@ -63,6 +63,10 @@ R17 SCAD (Sec. 6.4): Fan and Li's penalty with a = 3.7; MSA-lasso step 1 is the 
     w_m = pen_w_m p'_lambda(|theta_m|) / lambda at the previous step's estimate.  The
     lambda grid and the KKT scale are the lasso's (lambda_max of step 1); the reported
     KKT residual and objective are those of the last step's weighted lasso.
+R21 ridge penalty (Sec. 6.3): J(theta) = sum_m w_m theta_m^2, prox z / (1 + 2 gamma w_m); it has
+    no zero solution, so the lambda grid and the KKT scale are the lasso's lambda_max.
+R22 nu = 0 (Sec. 6.4): the inner step starts at delta = 1 (not relative to Lhat) and the
+    Beck-Teboulle test runs every iteration, halving delta on failure (never below 1/Lhat).
 R15 elastic net (Sec. 6.3): J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2), the
     penalty weights scaling both terms; its prox is the soft threshold divided by
     1 + 2 alpha gamma w_m, lambda_max is the lasso's (the quadratic term has zero
@@ -385,18 +389,19 @@ def kron_weights(V):
 # =============================================================================
 # Penalty, prox, objective, KKT
 # =============================================================================
-def penalty(theta, pen_w=None, alpha=0.0):
-    """Weighted penalty J(theta) = sum_m w_m (|theta_m| + alpha theta_m^2): the l1 penalty
-    (alpha = 0) or the elastic net of Sec. 6.3 (R15: the weights scale both terms)."""
+def penalty(theta, pen_w=None, alpha=0.0, l1=1.0):
+    """Weighted penalty J(theta) = sum_m w_m (l1 |theta_m| + alpha theta_m^2): the l1 penalty
+    (alpha = 0), the elastic net of Sec. 6.3 (R15: the weights scale both terms), or the ridge
+    penalty of Sec. 6.3 (l1 = 0, alpha = 1)."""
     th = vec(theta)
-    t = np.abs(th) + alpha * th * th
+    t = l1 * np.abs(th) + alpha * th * th
     return float(np.sum(t if pen_w is None else vec(pen_w) * t))
 
 
-def penalty_change(theta_old, theta_new, pen_w=None, alpha=0.0):
+def penalty_change(theta_old, theta_new, pen_w=None, alpha=0.0, l1=1.0):
     """J(theta_new) - J(theta_old) summed entrywise (no subtraction of totals)."""
     a, b = vec(theta_old), vec(theta_new)
-    dj = (np.abs(b) - np.abs(a)) + alpha * (b - a) * (b + a)
+    dj = l1 * (np.abs(b) - np.abs(a)) + alpha * (b - a) * (b + a)
     return float(np.sum(dj if pen_w is None else vec(pen_w) * dj))
 
 
@@ -410,15 +415,16 @@ def prox_ridge(z, gamma):
     return z / (1.0 + 2.0 * gamma)
 
 
-def prox_elastic_net(z, gamma, alpha):
-    """Sec. 6.3: prox of gamma (||.||_1 + alpha ||.||_2^2)."""
-    return soft_threshold(z, gamma) / (1.0 + 2.0 * alpha * gamma)
+def prox_elastic_net(z, gamma, alpha, l1=1.0):
+    """Sec. 6.3: prox of gamma (l1 ||.||_1 + alpha ||.||_2^2): the soft threshold at l1 gamma, then
+    the multiplicative shrinkage 1 / (1 + 2 alpha gamma) (l1 = 0: the ridge prox alone)."""
+    return soft_threshold(z, l1 * gamma) / (1.0 + 2.0 * alpha * gamma)
 
 
-def objective(fam, Xs, Theta, Y, lam, a=None, pen_w=None, alpha=0.0):
+def objective(fam, Xs, Theta, Y, lam, a=None, pen_w=None, alpha=0.0, l1=1.0):
     """F = -l/n + lambda J (eq. five under R1)."""
     eta = H(Xs, Theta)
-    return neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(Theta, pen_w, alpha)
+    return neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(Theta, pen_w, alpha, l1)
 
 
 def objective_change(fam, eta, xd, t, Y, a=None):
@@ -455,15 +461,16 @@ def smooth_gradient(fam, Xs, Theta, Y, a=None):
     return -G(Xs, score(fam, eta, Y, a)) / Y.size
 
 
-def kkt_residual(Theta, grad, lam, lam_max, pen_w=None, alpha=0.0):
+def kkt_residual(Theta, grad, lam, lam_max, pen_w=None, alpha=0.0, l1=1.0):
     """R6: max_m r_m / lambda_max with the subgradient residual r_m of the penalty
-    (elastic net: the smooth term's derivative 2 alpha w theta joins the gradient)."""
+    (elastic net: the smooth term's derivative 2 alpha w theta joins the gradient; ridge, l1 = 0:
+    r_m = |g_m + 2 lambda w_m theta_m|, the gradient of the smooth objective)."""
     th = vec(Theta)
     g = vec(grad)
     w = np.ones_like(th) if pen_w is None else vec(pen_w)
     nz = th != 0
     gs = g + 2.0 * alpha * lam * w * th
-    r = np.where(nz, np.abs(gs + lam * w * np.sign(th)), np.maximum(np.abs(gs) - lam * w, 0.0))
+    r = np.where(nz, np.abs(gs + l1 * lam * w * np.sign(th)), np.maximum(np.abs(gs) - l1 * lam * w, 0.0))
     return float(np.max(r)) / lam_max if r.size else 0.0
 
 
@@ -521,7 +528,7 @@ class FitInfo:
 
 
 def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
-             nu=1.0, Lhat=None, Z=None, record=False, alpha=0.0):
+             nu=1.0, Lhat=None, Z=None, record=False, alpha=0.0, l1=1.0):
     """Inner PG loop of Sec. 3.2 on h(x) = (1/2n)||sqrt(W)(Xx - z)||^2.
 
     grad h(x) = G(V * H(x))/n - c_z  with c_z = G(V * Z)/n  (eqs. twentyfive,
@@ -549,7 +556,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
         y = x + om * (x - x_prev)
         gy = grad_h(y)
         while True:
-            x_new = prox_elastic_net(y - delta * gy, delta * lam * thr_w, alpha)
+            x_new = prox_elastic_net(y - delta * gy, delta * lam * thr_w, alpha, l1)
             if nu >= 1.0 or Z is None:
                 break
             dlt = x_new - y
@@ -560,7 +567,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
             delta = max(delta / 2.0, 1.0 / Lhat)
         x_prev, x = x, x_new
         gx = grad_h(x)
-        r = kkt_residual(x, gx, lam, lam_max, pen_w, alpha)
+        r = kkt_residual(x, gx, lam, lam_max, pen_w, alpha, l1)
         if record:
             trace.append(x.copy())
         if r <= tol_inner:
@@ -570,7 +577,7 @@ def inner_pg(Xs, V, cz, x0, lam, delta, pen_w, tol_inner, lam_max, max_inner,
 
 def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
          max_outer=100, max_inner=100000, nu=1.0, alpha0=1.0, b=0.5, v=0.1,
-         max_ls=60, record_inner=False, alpha=0.0, weights="exact") -> tuple:
+         max_ls=60, record_inner=False, alpha=0.0, weights="exact", l1=1.0) -> tuple:
     """GD-PG, Algorithm 1, for one lambda.
 
     Step 2: eta = H(theta^k); U, V (eq. nine), Z (eq. tennew).  weights="kron": W^(k)
@@ -593,8 +600,8 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         eta = H(Xs, theta)
         u = score(fam, eta, Y, a)
         g = -G(Xs, u) / n
-        kkt_k = kkt_residual(theta, g, lam, lam_max, pen_w, alpha)
-        F_k = neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(theta, pen_w, alpha)
+        kkt_k = kkt_residual(theta, g, lam, lam_max, pen_w, alpha, l1)
+        F_k = neg_loglik_scaled(fam, eta, Y, a) + lam * penalty(theta, pen_w, alpha, l1)
         info.objective_history.append(F_k)
         info.kkt, info.objective, info.outer = kkt_k, F_k, k
         if kkt_k <= tol:
@@ -619,13 +626,13 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
         exact_model = fam.name == "gaussian" and (a is None or bool(np.all(a == 1.0)))
         tol_in = 0.5 * tol if exact_model else max(0.1 * tol, 0.1 * kkt_k)
         x, nin, trace = inner_pg(Xs, V, cz, theta, lam, delta, pen_w, tol_in, lam_max,
-                                 max_inner, nu=nu, Lhat=Lhat, Z=Z, record=record_inner, alpha=alpha)
+                                 max_inner, nu=nu, Lhat=Lhat, Z=Z, record=record_inner, alpha=alpha, l1=l1)
         info.inner.append(nin)
         if record_inner:
             info.inner_traces.append(trace)
         d = x - theta
         xd = H(Xs, d)
-        Delta = -float(np.sum(u * xd)) / n + lam * penalty_change(theta, x, pen_w, alpha)
+        Delta = -float(np.sum(u * xd)) / n + lam * penalty_change(theta, x, pen_w, alpha, l1)
         step = alpha0
         # the rule needs a descent direction (Delta < 0, Sec. 5, Theorem 2's search direction);
         # an inexact inner solve that returns one with Delta >= 0 gives no step
@@ -633,7 +640,7 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
             step, max_ls = 0.0, 0
         for _ in range(max_ls):
             dF = objective_change(fam, eta, xd, step, Y, a) + lam * penalty_change(
-                theta, theta + step * d, pen_w, alpha)
+                theta, theta + step * d, pen_w, alpha, l1)
             if np.isfinite(dF) and dF <= step * v * Delta:
                 break
             step *= b
@@ -644,10 +651,11 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
 
 def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e-4,
              tol=1e-10, max_outer=100, max_inner=100000, nu=1.0, theta0=None,
-             max_lambdas=None, alpha=0.0, weights="exact"):
+             max_lambdas=None, alpha=0.0, weights="exact", l1=1.0):
     """lambda path with warm starts (Sec. 6.4).  Returns (lambdas, thetas, infos,
     lam_max).  Stops early, returning the preceding models, when a fit does not
-    converge (the packages' early-exit convention, Sec. 6.5)."""
+    converge (the packages' early-exit convention, Sec. 6.5).  The ridge penalty (l1 = 0,
+    alpha = 1) has no zero solution; its grid and KKT scale are the lasso's lambda_max (R21)."""
     lam_max = lambda_max(fam, Xs, Y, a, pen_w)
     if lambdas is None:
         lambdas = lambda_grid(lam_max, nlambda, ratio)
@@ -659,7 +667,7 @@ def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e
     thetas, infos = [], []
     for lam in lambdas:
         theta, info = gdpg(fam, Xs, Y, lam, lam_max, a, pen_w, theta, tol, max_outer, max_inner, nu, alpha=alpha,
-                           weights=weights)
+                           weights=weights, l1=l1)
         thetas.append(theta.copy())
         infos.append(info)
         if not info.converged:

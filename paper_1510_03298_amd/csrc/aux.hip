@@ -238,19 +238,20 @@ __global__ __launch_bounds__(WG) void k_armijo(Geom G, int family, const double*
 // J(theta + t d) - J(theta) entrywise for t = 1 and the Armijo trial steps.
 __global__ __launch_bounds__(WG) void k_pen_trials(long long p, const double* __restrict__ th,
                                                     const double* __restrict__ d, const double* __restrict__ w,
-                                                    double alpha, int j0, double* __restrict__ part) {
+                                                    double alpha, int no_l1, int j0, double* __restrict__ part) {
   constexpr int NV = ARMIJO_TRIALS + 1;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < p; i += (long long)gridDim.x * WG) {
     // elastic net: w (|theta| + alpha theta^2); the change of the quadratic term along t d is t d (2 theta + t d)
-    const double t0 = th[i], dv = d[i], wm = w ? w[i] : 1.0, a0 = fabs(t0);
-    acc[0] += wm * ((fabs(t0 + dv) - a0) + alpha * dv * (2.0 * t0 + dv));
+    // (the ridge penalty: no l1 term)
+    const double t0 = th[i], dv = d[i], wm = w ? w[i] : 1.0, a0 = fabs(t0), c1 = no_l1 ? 0.0 : 1.0;
+    acc[0] += wm * (c1 * (fabs(t0 + dv) - a0) + alpha * dv * (2.0 * t0 + dv));
 #pragma unroll
     for (int j = 0; j < ARMIJO_TRIALS; ++j) {
       const double td = ldexp(dv, -(j0 + j));
-      acc[1 + j] += wm * ((fabs(t0 + td) - a0) + alpha * td * (2.0 * t0 + td));
+      acc[1 + j] += wm * (c1 * (fabs(t0 + td) - a0) + alpha * td * (2.0 * t0 + td));
     }
   }
   __shared__ double sm[WG / 64][NV];
@@ -361,11 +362,11 @@ __global__ void k_zero(uint32_t* p, long long nwords) {
 template <typename T>
 __global__ void k_bt_redo(Geom G, const double* __restrict__ y, const double* __restrict__ gy,
                           const double* __restrict__ w, const double* __restrict__ th, double lambda, double delta,
-                          double alpha, double* __restrict__ x, T* __restrict__ inc) {
+                          double alpha, int no_l1, double* __restrict__ x, T* __restrict__ inc) {
   for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < G.p; j += (long long)gridDim.x * blockDim.x) {
     const double lw = lambda * (w ? w[j] : 1.0);
     const double z = y[j] - delta * gy[j];
-    const double a = fabs(z) - delta * lw;
+    const double a = fabs(z) - (no_l1 ? 0.0 : delta * lw);
     const double xn = (a > 0.0 ? copysign(a, z) : 0.0) / (1.0 + 2.0 * alpha * delta * lw);   // Sec. 6.3
     x[j] = xn;
     const long long row = j % G.P12, col = j / G.P12;
@@ -489,12 +490,12 @@ hipError_t launch_axpy(long long p, double alpha, const double* d, double* theta
   return hipGetLastError();
 }
 hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
-                          const double* theta_ref, double lambda, double delta, double alpha, double* x, void* inc,
-                          hipStream_t s) {
+                          const double* theta_ref, double lambda, double delta, double alpha, int no_l1, double* x,
+                          void* inc, hipStream_t s) {
   const int gr = grid1d(G.p);
-  if (dt == DT_F64) hipLaunchKernelGGL(k_bt_redo<double>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, x, (double*)inc);
-  else if (dt == DT_F32) hipLaunchKernelGGL(k_bt_redo<float>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, x, (float*)inc);
-  else hipLaunchKernelGGL(k_bt_redo<bf16>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, x, (bf16*)inc);
+  if (dt == DT_F64) hipLaunchKernelGGL(k_bt_redo<double>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, no_l1, x, (double*)inc);
+  else if (dt == DT_F32) hipLaunchKernelGGL(k_bt_redo<float>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, no_l1, x, (float*)inc);
+  else hipLaunchKernelGGL(k_bt_redo<bf16>, dim3(gr), dim3(WG), 0, s, G, y, gy, pen_w, theta_ref, lambda, delta, alpha, no_l1, x, (bf16*)inc);
   return hipGetLastError();
 }
 
@@ -515,11 +516,11 @@ hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
 }
 
 hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, double alpha,
-                             int j0, double* partials, int* nblk_out, hipStream_t s) {
+                             int no_l1, int j0, double* partials, int* nblk_out, hipStream_t s) {
   int nb = grid1d(p);
   if (nb > kPenTrialsMaxBlocks) nb = kPenTrialsMaxBlocks;
   *nblk_out = nb;
-  hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, alpha, j0, partials);
+  hipLaunchKernelGGL(k_pen_trials, dim3(nb), dim3(WG), 0, s, p, theta, d, pen_w, alpha, no_l1, j0, partials);
   return hipGetLastError();
 }
 

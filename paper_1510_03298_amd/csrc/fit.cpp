@@ -182,6 +182,7 @@ struct Fit {
   void *T1c, *S2c;         // chain dtype intermediates
   bool gram = false;       // inner gradient by the Kronecker Gram factors (Sec. 6.2)
   double enet = 0.0;       // elastic-net weight alpha (Sec. 6.3): J = sum w (|theta| + alpha theta^2)
+  int no_l1 = 0;           // the ridge penalty (Sec. 6.3): J = sum w theta^2 (enet = 1, no l1 term)
   const double* pen = nullptr;   // penalty weights the kernels read (the caller's, or the SCAD steps' own)
   double *S1g = nullptr, *S2g = nullptr;   // X_1^T X_1, X_2^T X_2 (FP64)
   void* S3c = nullptr;     // X_3^T X_3, k-blocked (K = C = p3), chain dtype
@@ -309,7 +310,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   FCHK(launch_reduce(F.part, nbc, 2, ops2, 1.0 / (double)G.n, F.hred_dev, F.s));
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2d; ap.X3a = F.X3ad; ap.scale = -1.0 / (double)G.n; ap.gout = F.gref;
-  ap.theta = theta_dev; ap.pen_w = F.pen; ap.lambda = lambda; ap.alpha = F.enet;
+  ap.theta = theta_dev; ap.pen_w = F.pen; ap.lambda = lambda; ap.alpha = F.enet; ap.no_l1 = F.no_l1;
   double* part2 = F.part + (size_t)2 * nbc;
   ap.partials = part2;
   int nb = 0;
@@ -349,7 +350,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     gp.inc_in = F.gpar ? F.inc2 : F.inc; gp.inc_out = F.gpar ? F.inc : F.inc2;
     gp.iter_in = F.iter + F.gpar; gp.iter_out = F.iter + (1 - F.gpar);
     gp.gref = F.gref; gp.theta_ref = F.theta; gp.pen_w = F.pen; gp.x = F.x; gp.xp = F.xp; gp.gp = F.gp;
-    gp.dparams = F.dparams; gp.alpha = F.enet; gp.scale = 1.0 / (double)G.n; gp.partials = F.part;
+    gp.dparams = F.dparams; gp.alpha = F.enet; gp.no_l1 = F.no_l1; gp.scale = 1.0 / (double)G.n; gp.partials = F.part;
     FCHK(launch_gram_iter(F.dt, gp, nblk, F.s));
     F.gpar ^= 1;
     if (sample) {   // iteration time only
@@ -364,7 +365,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     // grad h(x) = g_ref + (S_3 (x) S_2 (x) S_1) vec(x - theta_ref) / n (Sec. 6.2, W = I)
     FCHK(launch_gram12(F.dt, G, F.inc, F.S1g, F.S2g, F.Zc, F.iter, F.s));
     AdjParams ap{};
-    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen; ap.alpha = F.enet;
+    ap.G = F.Gg; ap.S2 = F.Zc; ap.X3a = F.S3c; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen; ap.alpha = F.enet; ap.no_l1 = F.no_l1;
     ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
     ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
     FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
@@ -390,7 +391,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     ai.gT = F.gT; ai.tT = F.tT; ai.penT = F.pen ? F.penT : nullptr;
     ai.dcur = F.dst[F.gpar]; ai.dprev = F.dst[1 - F.gpar]; ai.dout = F.dst[1 - F.gpar];
     ai.q_in = F.qst; ai.q_out = F.qst; ai.inc = F.inc; ai.iter = F.iter; ai.dparams = F.dparams;
-    ai.scale = 1.0 / (double)G.n; ai.alpha = F.enet; ai.partials = F.part; ai.xmap = kAdjIncForm;
+    ai.scale = 1.0 / (double)G.n; ai.alpha = F.enet; ai.no_l1 = F.no_l1; ai.partials = F.part; ai.xmap = kAdjIncForm;
     FCHK(launch_slab_adj_inc(F.dt, ai, nblk, F.s));
     F.gpar ^= 1;
     if (sample) {
@@ -414,7 +415,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
   }
   AdjParams ap{};
   ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen;
-  ap.alpha = F.enet; ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
+  ap.alpha = F.enet; ap.no_l1 = F.no_l1; ap.lambda = lambda; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.x = F.x; ap.xp = F.xp;
   ap.gp = F.gp; ap.inc = F.inc; ap.iter = F.iter; ap.delta = delta; ap.dparams = F.dparams;
   ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
   FCHK(launch_slab_adj(F.dt, EPI_PROX, ap, nblk, F.s));
@@ -558,7 +559,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
     AdjParams ap{};
     ap.G = G; ap.S2 = F.S2c; ap.X3a = F.X3ac; ap.scale = 1.0 / (double)G.n; ap.pen_w = F.pen;
-    ap.alpha = F.enet; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
+    ap.alpha = F.enet; ap.no_l1 = F.no_l1; ap.partials = F.part; ap.gref = F.gref; ap.theta_ref = F.theta; ap.inc = F.inc; ap.dparams = F.dparams;
     ap.x = cur[0]; ap.xp = cur[1]; ap.gp = cur[2]; ap.yprev = cur[3]; ap.gyprev = cur[4];
     ap.x_out = nxt[0]; ap.xp_out = nxt[1]; ap.gp_out = nxt[2]; ap.y_out = nxt[3]; ap.gy_out = nxt[4];
     ap.s2_kb4 = chain_s2_kb4(F.dt, SM_FUSED, G);
@@ -573,7 +574,7 @@ static int inner_loop_bt(Fit& F, double lam, double delta0, double Lhat, double 
     if (l >= 2 && sdg > (sdd / delta) * (1.0 + 1e-12) && delta > delta_min * (1.0 + 1e-12)) {
       // divergence of the step into x^l detected: halve delta and redo that step from y_{l-1}
       delta = std::max(0.5 * delta, delta_min);
-      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.pen, F.theta, lam, delta, F.enet, cur[0], F.inc, F.s));
+      FCHK(launch_bt_redo(F.dt, G, cur[3], cur[4], F.pen, F.theta, lam, delta, F.enet, F.no_l1, cur[0], F.inc, F.s));
       continue;
     }
     kin = F.hred[0] / lam_scale;
@@ -648,7 +649,7 @@ static int armijo_enqueue(Fit& F, int j0) {
   FCHK(launch_armijo(G, F.family, F.eta_int, F.xd_int, F.y_int, F.a_int, j0, F.part, &nb1, F.s));
   FCHK(launch_reduce(F.part, nb1, NV, ops, 1.0 / (double)G.n, F.hred_dev, F.s));
   double* part2 = F.part + (size_t)nb1 * NV;
-  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.pen, F.enet, j0, part2, &nb2, F.s));
+  FCHK(launch_pen_trials(G.p, F.theta, F.dvec, F.pen, F.enet, F.no_l1, j0, part2, &nb2, F.s));
   FCHK(launch_reduce(part2, nb2, NV, ops, 1.0, F.hred_dev + NV, F.s));
   return GLAM_OK;
 }
@@ -1005,10 +1006,12 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
     return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
   if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
-  if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in (0, 1]");
+  if (!(opt->nu >= 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in [0, 1]");
   if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
-  if (opt->penalty != GLAM_PENALTY_LASSO && opt->penalty != GLAM_PENALTY_SCAD)
+  if (opt->penalty != GLAM_PENALTY_LASSO && opt->penalty != GLAM_PENALTY_SCAD && opt->penalty != GLAM_PENALTY_RIDGE)
     return fit_fail(GLAM_EINVAL, "bad penalty");
+  if (opt->penalty == GLAM_PENALTY_RIDGE && opt->alpha != 0.0)
+    return fit_fail(GLAM_EINVAL, "the ridge penalty takes no elastic-net weight (alpha = 0)");
   if (opt->penalty == GLAM_PENALTY_SCAD) {
     if (opt->msa_steps < 1) return fit_fail(GLAM_EINVAL, "msa_steps must be >= 1");
     if (!(opt->scad_a == 0.0 || (opt->scad_a > 2.0 && std::isfinite(opt->scad_a))))
@@ -1062,6 +1065,10 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   F.kron = opt->inner_mode == GLAM_INNER_KRON && family_has_weights(prob->family);
   F.unit_w = opt->inner_mode == GLAM_INNER_ONE && family_has_weights(prob->family);
   F.enet = opt->alpha;
+  if (opt->penalty == GLAM_PENALTY_RIDGE) {   // Sec. 6.3: J = sum_m w_m theta_m^2
+    F.enet = 1.0;
+    F.no_l1 = 1;
+  }
   F.incst = F.dt != DT_F64 && !F.gram && opt->nu >= 1.0;
   F.restart = opt->extrapolation == 0 && !F.gram && opt->nu >= 1.0;
   {
@@ -1204,7 +1211,9 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       }
       const double Lhat = wmax * F.sprod / (double)G.n;
       if (!(Lhat > 0.0) || !std::isfinite(Lhat)) { status = GLAM_ENONFINITE; break; }
-      const double delta = 1.0 / (opt->nu * Lhat);
+      // Sec. 6.4: nu in (0, 1] scales 1/Lhat; nu = 0 starts at delta = 1 and backtracks every
+      // iteration (R22)
+      const double delta = opt->nu > 0.0 ? 1.0 / (opt->nu * Lhat) : 1.0;
       double tol_in = exact_model ? 0.5 * tol : std::max(0.1 * tol, 0.1 * kkt);
       // A BF16 chain perturbs grad h by roughly eps_bf16 * kappa relative to the
       // increment, so one outer pass cannot gain more than that factor: each pass asks for

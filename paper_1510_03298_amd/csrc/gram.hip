@@ -211,11 +211,12 @@ __global__ __launch_bounds__(WG_GI) void k_gram_iter(GramIterParams P) {
         const double wm = e_w[s][q];
         const double lw = lam * wm;
         const double gs = gx + 2.0 * P.alpha * lw * x;   // elastic net: the smooth term's slope
-        red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0));
+        const double l1w = P.no_l1 ? 0.0 : lw;   // the l1 term's weight (0: ridge)
+        red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(l1w, x)) : fmax(fabs(gs) - l1w, 0.0));
         red_noise = fmax(red_noise, fabs(incg));
         const double gy = gx + om * (gx - gp);          // grad h(y) by linearity (h quadratic)
         const double yv = x + om * (x - xp);
-        const double xn = gi_soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+        const double xn = gi_soft_threshold(yv - delta * gy, delta * l1w) / (1.0 + 2.0 * P.alpha * delta * lw);
         P.xp[j] = x;
         P.x[j] = xn;
         P.gp[j] = gx;

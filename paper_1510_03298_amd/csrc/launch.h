@@ -111,6 +111,7 @@ struct AdjParams {
   double *x_out, *xp_out, *gp_out, *y_out, *gy_out;
   int s2_kb4;            // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
   double alpha;          // elastic-net weight (Sec. 6.3): J = sum w (|theta| + alpha theta^2); 0 = lasso
+  int no_l1;             // 1: no l1 term (the ridge penalty, J = sum w alpha theta^2)
 };
 
 // The inner PG step of the BF16 / FP32 chains on FP32 increment state (step control nu = 1).
@@ -138,6 +139,7 @@ struct AdjIncParams {
   const double* dparams; // device {lambda, delta}
   double scale;          // 1 / n
   double alpha;          // elastic-net weight
+  int no_l1;             // 1: the ridge penalty (no l1 term)
   double* partials;      // per-workgroup [nblk][ADJ_NSUM], slab_adj's layout
   int xmap;              // tile order: 0 row blocks fastest; 1 XCD-aware (each XCD a range of row blocks)
 };
@@ -237,6 +239,7 @@ struct GramIterParams {
   const int* iter_in;       // iteration counter l - 1, read
   int* iter_out;            // l, written (must not alias iter_in)
   double alpha;             // elastic-net weight
+  int no_l1;                // 1: the ridge penalty (no l1 term)
   double scale;             // 1 / n
   double* partials;         // [nblk][ADJ_NSUM], slab_adj's layout
   int per_xcd;              // set by the launcher
@@ -328,11 +331,11 @@ inline void lift_sizes(int d, const int64_t* n, const int64_t* p, int64_t* n3, i
 }
 // backtracking redo of a rejected step: x = S(y - delta gy, delta lambda w), inc = x - theta_ref (k-blocked)
 hipError_t launch_bt_redo(int dt, const Geom& G, const double* y, const double* gy, const double* pen_w,
-                          const double* theta_ref, double lambda, double delta, double alpha, double* x, void* inc,
-                          hipStream_t s);
+                          const double* theta_ref, double lambda, double delta, double alpha, int no_l1, double* x,
+                          void* inc, hipStream_t s);
 // sum_m w_m (|theta_m + t_j d_m| - |theta_m|) for t = 1 (slot 0) and the Armijo trial steps (slots 1..)
 hipError_t launch_pen_trials(long long p, const double* theta, const double* d, const double* pen_w, double alpha,
-                             int j0, double* partials, int* nblk_out, hipStream_t s);
+                             int no_l1, int j0, double* partials, int* nblk_out, hipStream_t s);
 // data checks, per-block maxima of 4 indicators: non-finite y, negative y (Poisson),
 // negative or non-finite a, non-positive or non-finite pen_w
 // out (dims d[q0], d[q1], d[q2]) = in (dims d) with its axes permuted: out[i'] = in[i], i[q_k] = i'_k

@@ -958,8 +958,9 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
         const double th = e_th;
         const double lw = P.lambda * wm;
         const double gs = gv + 2.0 * P.alpha * lw * th;   // elastic net: the smooth term's slope
-        red_kkt = th != 0.0 ? fabs(gs + copysign(lw, th)) : fmax(fabs(gs) - lw, 0.0);
-        red_pen = wm * (fabs(th) + P.alpha * th * th);
+        const double l1w = P.no_l1 ? 0.0 : lw;   // the l1 term's weight (0: ridge)
+        red_kkt = th != 0.0 ? fabs(gs + copysign(l1w, th)) : fmax(fabs(gs) - l1w, 0.0);
+        red_pen = wm * ((P.no_l1 ? 0.0 : fabs(th)) + P.alpha * th * th);
       }
     } else if (EPI == EPI_PROX_BT) {
       // inner PG step with Beck-Teboulle backtracking state (step size control nu < 1):
@@ -973,7 +974,7 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double wm = e_w;
       const double lw = lam * wm;
       const double gs = gx + 2.0 * P.alpha * lw * x;   // elastic net: the smooth term's slope
-      red_kkt = x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0);
+      red_kkt = x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0);
       red_noise = fabs(incg);
       const double dv = x - e_y;
       red_dg = dv * (gx - e_gy);
@@ -981,7 +982,7 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double gy = gx + om * (gx - gp);
       const double yv = x + om * (x - xp);
       // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
-      const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+      const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
       P.x_out[j] = xn;
       P.xp_out[j] = x;
       P.gp_out[j] = gx;
@@ -1002,12 +1003,12 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double wm = e_w;
       const double lw = lam * wm;
       const double gs = gx + 2.0 * P.alpha * lw * x;   // elastic net: the smooth term's slope
-      red_kkt = x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0);
+      red_kkt = x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0);
       red_noise = fabs(incg);
       const double gy = gx + om * (gx - gp);          // grad h(y) by linearity (h quadratic)
       const double yv = x + om * (x - xp);
       // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
-      const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+      const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
       P.xp[j] = x;
       P.x[j] = xn;
       P.gp[j] = gx;
@@ -1119,12 +1120,12 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
     const double xp = zp ? 0.0 : e_t + (double)e_dp;   // x^{l-1}
     const double lw = lam * e_w;
     const double gs = gx + 2.0 * P.alpha * lw * x;     // elastic net: the smooth term's slope
-    red_kkt = x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0);
+    red_kkt = x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0);
     red_noise = fabs(incg);
     const double gy = gx + om * (incg - (double)e_q);  // grad h(y) by linearity (h quadratic)
     const double yv = x + om * (x - xp);
     // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
-    const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+    const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
     const double dn = xn - e_t;
     P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
     P.q_out[e] = (float)incg;
@@ -1196,11 +1197,11 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc_rows(AdjIncParams P) {
     const double xp = zp ? 0.0 : e_t[i] + (double)e_dp[i];
     const double lw = lam * e_w[i];
     const double gs = gx + 2.0 * P.alpha * lw * x;
-    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0));
+    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0));
     red_noise = fmax(red_noise, fabs(incg));
     const double gy = gx + om * (incg - (double)e_q[i]);
     const double yv = x + om * (x - xp);
-    const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+    const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
     const double dn = xn - e_t[i];
     P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
     P.q_out[e] = (float)incg;
@@ -1311,11 +1312,11 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc32(AdjIncParams P) {
     const double xp = zp ? 0.0 : e_t[sb] + (double)e_dp[sb];
     const double lw = lam * e_w[sb];
     const double gs = gx + 2.0 * P.alpha * lw * x;
-    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(lw, x)) : fmax(fabs(gs) - lw, 0.0));
+    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0));
     red_noise = fmax(red_noise, fabs(incg));
     const double gy = gx + om * (incg - (double)e_q[sb]);
     const double yv = x + om * (x - xp);
-    const double xn = soft_threshold(yv - delta * gy, delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
+    const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
     const double dn = xn - e_t[sb];
     P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
     P.q_out[e] = (float)incg;

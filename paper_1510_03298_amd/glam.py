@@ -29,7 +29,7 @@ MAX_INNER_P = 32
 MAX_INNER_N = 256
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 FAMILIES = {"gaussian": GAUSSIAN, "poisson": POISSON, "binomial": BINOMIAL, "gamma": GAMMA}
-PENALTIES = {"lasso": 0, "scad": 1}
+PENALTIES = {"lasso": 0, "scad": 1, "ridge": 2}
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p

@@ -121,16 +121,26 @@ def test_invalid_arguments_rejected_without_device_work():
     res.iters_outer = res.iters_inner = res.status = io
     rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     assert rc == glam.GLAM_EINVAL and b"decreasing" in glam.glam_last_error()
-    opt.nu = 0.0
     lam2 = (ctypes.c_double * 3)(3.0, 2.0, 1.0)
     opt.lambda_ = lam2
-    assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+    for bad_nu in (-0.5, 1.5, float("nan")):   # nu in [0, 1] (Sec. 6.4; 0: delta = 1 with backtracking)
+        opt.nu = bad_nu
+        assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+        assert b"nu" in glam.glam_last_error()
     opt.nu = 1.0
+    for field, value in (("extrapolation", 2), ("kron_step", 2)):
+        setattr(opt, field, value)
+        assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+        setattr(opt, field, 0)
+    opt.penalty, opt.alpha = 2, 0.5   # ridge takes no elastic-net weight
+    assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL
+    assert b"ridge" in glam.glam_last_error()
+    opt.penalty, opt.alpha = 0, 0.0
     prob.family = 4   # families are 0..3
     rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     assert rc == glam.GLAM_EINVAL and b"family" in glam.glam_last_error()
     prob.family = glam.GAMMA
-    for field, value in (("penalty", 2), ("msa_steps", 0), ("scad_a", 1.5)):   # SCAD options checked on the host
+    for field, value in (("penalty", 3), ("msa_steps", 0), ("scad_a", 1.5)):   # SCAD options checked on the host
         opt.penalty, opt.msa_steps, opt.scad_a = 1, 3, 0.0
         setattr(opt, field, value)
         assert glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res)) == glam.GLAM_EINVAL

@@ -629,3 +629,52 @@ def test_unit_weight_inner_loop(fam, dt):
         glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=2, inner="one", nu=0.5)
     with pytest.raises(glam.GlamError):   # unit weights take no prior weights
         glam.fit_path(Xd, Yd, d.n, d.p, fam, obs_w=torch.ones_like(Yd), nlambda=2, inner="one")
+
+
+@pytest.mark.parametrize("fam,dt,inner,nu", [("gaussian", 0, "chain", 1.0), ("gaussian", 2, "chain", 1.0),
+                                             ("poisson", 1, "chain", 1.0), ("poisson", 0, "chain", 0.5),
+                                             ("gaussian", 2, "gram", 1.0)])
+def test_ridge_path(fam, dt, inner, nu):
+    """Sec. 6.3's ridge penalty (R21): every model on a short path meets the oracle's ridge KKT
+    condition (the smooth objective's gradient) and matches the oracle's own path (the ridge
+    estimate is unique: strictly convex)."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((21, 17, 29), (8, 7, 9), family=fam, seed=48, basis="gauss", scale=0.3)
+    print(f"ridge {fam} dt={dt} inner={inner} nu={nu}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, nlambda=4, lambda_min_ratio=0.02, dtype=dt, kkt_tol=1e-7,
+                        penalty="ridge", inner=inner, nu=nu)
+    assert res.code == 0, (res.code, res.status)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    olams, oths, _ = _oracle_path(f"ridge48_{fam}", fam, d, nlambda=4, ratio=0.02, tol=1e-11, max_outer=200,
+                                  alpha=1.0, l1=0.0)
+    np.testing.assert_allclose(res.lambdas, olams, rtol=1e-12)
+    for l in range(4):
+        th = _theta(glam, res, l, d.p)
+        lam = res.lambdas[l]
+        g = O.smooth_gradient(fam, d.X, th, d.Y)
+        assert O.kkt_residual(th, g, lam, lm, alpha=1.0, l1=0.0) <= 1e-7
+        F1 = O.objective(fam, d.X, th, d.Y, lam, alpha=1.0, l1=0.0)
+        assert abs(res.objective[l] - F1) <= 1e-9 * abs(F1)
+        F2 = O.objective(fam, d.X, oths[l], d.Y, lam, alpha=1.0, l1=0.0)
+        assert (F1 - F2) / abs(F2) <= 1e-8
+        assert rel_inf(th, oths[l]) <= 1e-4
+        assert np.count_nonzero(th) == th.size   # no exact zeros without the l1 term
+
+
+@pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 1), ("poisson", 0), ("poisson", 2)])
+def test_nu_zero(fam, dt):
+    """Sec. 6.4, nu = 0 (R22): the inner step starts at delta = 1 with the Beck-Teboulle test at
+    every iteration; the path reaches the oracle's PMLE (oracle solved from zero)."""
+    torch, glam = need_gpu()
+    d = inputs.random_problem((21, 17, 29), (8, 7, 9), family=fam, seed=49, basis="gauss", scale=0.3)
+    print(f"nu=0 {fam} dt={dt}", flush=True)
+    Xd, Yd, _ = _dev(glam, d)
+    lm = O.lambda_max(fam, d.X, d.Y)
+    lam = 0.05 * lm
+    res = glam.fit_path(Xd, Yd, d.n, d.p, fam, lambdas=[lm, lam], dtype=dt, kkt_tol=1e-7, nu=0.0)
+    assert res.code == 0, (res.code, res.status)
+    th = _theta(glam, res, 1, d.p)
+    ref, info = O.gdpg(fam, d.X, d.Y, lam, lm, tol=1e-11, max_outer=200)
+    assert info.converged
+    _check_model(d, fam, th, lam, lm, 1e-7, ref=ref, theta_tol=1e-4)

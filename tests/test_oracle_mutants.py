@@ -45,16 +45,22 @@ MUTANTS = {
                   lambda: [P.test_soft_threshold_is_the_l1_prox] + _gauss_pins()),
     # KKT residual with the wrong subgradient sign
     "kkt_sign": ("kkt_residual",
-                 lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0: orig(th, -np.asarray(g), lam, lm, pen_w,
-                                                                               alpha)),
+                 lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0, l1=1.0: orig(th, -np.asarray(g), lam, lm,
+                                                                                       pen_w, alpha, l1)),
                  lambda: [P.test_kkt_residual_definition] + _gauss_pins()),
     # elastic-net prox with 1 + alpha gamma instead of 1 + 2 alpha gamma (Sec. 6.3)
     "enet_prox_factor": ("prox_elastic_net",
-                         lambda orig: (lambda z, gamma, alpha: orig(z, gamma, 0.5 * alpha)),
+                         lambda orig: (lambda z, gamma, alpha, l1=1.0: orig(z, gamma, 0.5 * alpha, l1)),
                          lambda: [P.test_elastic_net_closed_form_orthogonal_design]),
+    # ridge prox with 1 + gamma instead of 1 + 2 gamma (Sec. 6.3)
+    "ridge_prox_factor": ("prox_elastic_net",
+                          lambda orig: (lambda z, gamma, alpha, l1=1.0: orig(z, gamma, 0.5 * alpha, l1) if l1 == 0.0
+                                        else orig(z, gamma, alpha, l1)),
+                          lambda: [P.test_ridge_closed_form_orthogonal_design, P.test_ridge_matches_normal_equations]),
     # KKT residual without the elastic net's smooth term
     "kkt_drops_enet": ("kkt_residual",
-                       lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0: orig(th, g, lam, lm, pen_w, 0.0)),
+                       lambda orig: (lambda th, g, lam, lm, pen_w=None, alpha=0.0, l1=1.0: orig(th, g, lam, lm, pen_w, 0.0,
+                                                                                               l1)),
                        lambda: [P.test_elastic_net_kkt_residual_definition,
                                 P.test_elastic_net_closed_form_orthogonal_design]),
     # Gamma-log score taken as if the link were canonical (vartheta' = 1 dropped)

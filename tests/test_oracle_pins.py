@@ -559,6 +559,70 @@ def test_exact_lipschitz_for_tensor_product_weights():
     assert O.lipschitz_bound(Xs, w, n) >= L * (1 - 1e-12)
 
 
+def test_ridge_closed_form_orthogonal_design():
+    """Sec. 6.3 ridge penalty (R21): with X^T X = n I the Gaussian ridge estimate is the
+    multiplicative shrinkage z / (1 + 2 lambda w) of z = X^T y / n, coordinate by coordinate."""
+    d = inputs.random_problem((8, 7, 6), (4, 3, 5), seed=20, basis="orth")
+    pen = np.random.default_rng(21).uniform(0.5, 2.0, d.p)
+    Xd = O.kron_design(d.X)
+    z = Xd.T @ O.vec(d.Y) / Xd.shape[0]
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    lam = 0.3 * lm
+    th, info = O.gdpg("gaussian", d.X, d.Y, lam, lm, pen_w=pen, tol=1e-12, alpha=1.0, l1=0.0, max_outer=3,
+                      max_inner=5000)
+    assert info.converged
+    np.testing.assert_allclose(O.vec(th), z / (1.0 + 2.0 * lam * O.vec(pen)), rtol=1e-9, atol=1e-12)
+
+
+def test_ridge_matches_normal_equations():
+    """Gaussian ridge on a general (correlated) design: (X^T X / n + 2 lambda I) theta = X^T y / n."""
+    d = inputs.random_problem((7, 6, 5), (3, 4, 3), seed=22, basis="gauss")
+    Xd = O.kron_design(d.X)
+    n = Xd.shape[0]
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    lam = 0.05 * lm
+    ref = np.linalg.solve(Xd.T @ Xd / n + 2 * lam * np.eye(Xd.shape[1]), Xd.T @ O.vec(d.Y) / n)
+    th, info = O.gdpg("gaussian", d.X, d.Y, lam, lm, tol=1e-12, alpha=1.0, l1=0.0, max_inner=20000)
+    assert info.converged
+    np.testing.assert_allclose(O.vec(th), ref, rtol=1e-8, atol=1e-10 * np.max(np.abs(ref)))
+    g = O.smooth_gradient("gaussian", d.X, th, d.Y)
+    assert O.kkt_residual(th, g, lam, lm, alpha=1.0, l1=0.0) <= 1e-12
+
+
+def test_poisson_ridge_matches_newton():
+    """Poisson ridge: Newton's method on the explicit design for (1/n) sum (e^eta - y eta) +
+    lambda ||theta||^2 (smooth and strictly convex) gives the same estimate."""
+    d = inputs.random_problem((7, 6, 5), (3, 3, 2), family="poisson", seed=23, scale=0.3, basis="gauss")
+    Xd = O.kron_design(d.X)
+    y = O.vec(d.Y)
+    n, P = Xd.shape
+    lm = O.lambda_max("poisson", d.X, d.Y)
+    lam = 0.2 * lm
+    b = np.zeros(P)
+    for _ in range(100):
+        mu = np.exp(Xd @ b)
+        gr = Xd.T @ (mu - y) / n + 2 * lam * b
+        Hs = Xd.T @ (mu[:, None] * Xd) / n + 2 * lam * np.eye(P)
+        b = b - np.linalg.solve(Hs, gr)
+        if np.max(np.abs(gr)) < 1e-15:
+            break
+    th, info = O.gdpg("poisson", d.X, d.Y, lam, lm, tol=1e-12, alpha=1.0, l1=0.0, max_outer=300)
+    assert info.converged
+    np.testing.assert_allclose(O.vec(th), b, rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "poisson"])
+def test_nu_zero_reaches_same_solution(fam):
+    """Sec. 6.4, nu = 0 (R22): the inner step starts at 1 with Beck-Teboulle backtracking at every
+    iteration; the fit reaches the same PMLE as nu = 1."""
+    d = inputs.random_problem((7, 6, 5), (4, 3, 3), family=fam, seed=24, scale=0.4, basis="gauss")
+    lm = O.lambda_max(fam, d.X, d.Y)
+    th1, i1 = O.gdpg(fam, d.X, d.Y, 0.1 * lm, lm, tol=1e-11, max_outer=200)
+    th0, i0 = O.gdpg(fam, d.X, d.Y, 0.1 * lm, lm, tol=1e-11, max_outer=200, nu=0.0)
+    assert i1.converged and i0.converged
+    np.testing.assert_allclose(O.vec(th0), O.vec(th1), atol=1e-8 * np.max(np.abs(th1)))
+
+
 def test_nu_backtracking_reaches_same_solution():
     """nu in (0,1): larger initial step with backtracking (R7) gives the same PMLE."""
     d = inputs.random_problem((7, 6, 5), (4, 3, 3), family="poisson", seed=10, scale=0.4, basis="gauss")
