@@ -11,6 +11,9 @@ definitions in the paper's notation:
 
 * vec / rho / Kronecker identity ............ App. A (eq. "index", the rho map)
 * H and G maps .............................. Sec. 6.1, eqs. (eighteen), (nineteen)
+* c > 1 tensor components ................... Sec. 2, eq. (fivenew): H sums the components'
+                                              chains, G stacks their adjoints as theta is
+                                              stacked, Proposition 1 sums over components
 * exponential families, score, weights ...... App. B, eqs. (four), (weights), (tennew)
 * log-likelihood and gradient ............... Sec. 2, eqs. (two), (three)
 * PMLE objective ............................ Sec. 2, eq. (five)
@@ -132,8 +135,40 @@ def rho_loops(X: np.ndarray, A: np.ndarray) -> np.ndarray:
     return out
 
 
+class Components(list):
+    """A design of c tensor components, X = [X_1 | ... | X_c] with X_r = X_{r,d} (x) ... (x) X_{r,1}
+    (Sec. 2, eq. fivenew): Components([Xs_1, ..., Xs_c]), Xs_r the list of component r's marginal
+    matrices.  Its parameter is the flat p-vector theta = (vec(Theta_1), ..., vec(Theta_c)),
+    p = sum_r prod_j p_{r,j}.  A plain list of matrices is the single-component design (c = 1)."""
+
+    def dims(self):
+        return [tuple(np.asarray(X).shape[1] for X in Xs) for Xs in self]
+
+    def split(self, theta):
+        """The arrays Theta_r of a flat theta."""
+        th = vec(theta)
+        out, off = [], 0
+        for dims in self.dims():
+            k = int(np.prod(dims))
+            out.append(unvec(th[off:off + k], dims))
+            off += k
+        if off != th.size:
+            raise ValueError("theta has %d entries, the components %d" % (th.size, off))
+        return out
+
+
+def param_shape(Xs) -> tuple:
+    """Shape of the parameter: (p_1, ..., p_d) for one component, (p,) for Components."""
+    if isinstance(Xs, Components):
+        return (sum(int(np.prod(d)) for d in Xs.dims()),)
+    return tuple(np.asarray(X).shape[1] for X in Xs)
+
+
 def H(Xs: Sequence[np.ndarray], Theta: np.ndarray) -> np.ndarray:
-    """H map, eq. (eighteen) with c = 1: rho(X_d, ..., rho(X_1, Theta))."""
+    """H map, eq. (eighteen): rho(X_d, ..., rho(X_1, Theta)), summed over the components of a
+    Components design."""
+    if isinstance(Xs, Components):
+        return sum(H(Xr, Tr) for Xr, Tr in zip(Xs, Xs.split(Theta)))
     out = np.asarray(Theta, dtype=np.float64)
     for X in Xs:
         out = rho(X, out)
@@ -141,7 +176,10 @@ def H(Xs: Sequence[np.ndarray], Theta: np.ndarray) -> np.ndarray:
 
 
 def G(Xs: Sequence[np.ndarray], U: np.ndarray) -> np.ndarray:
-    """G map, eq. (nineteen) with c = 1: rho(X_d^T, ..., rho(X_1^T, U))."""
+    """G map, eq. (nineteen): rho(X_d^T, ..., rho(X_1^T, U)); for a Components design the tuple
+    of the components' arrays, stacked as theta is (vec of each, in component order)."""
+    if isinstance(Xs, Components):
+        return np.concatenate([vec(G(Xr, U)) for Xr in Xs])
     out = np.asarray(U, dtype=np.float64)
     for X in Xs:
         out = rho(np.asarray(X).T, out)
@@ -149,7 +187,10 @@ def G(Xs: Sequence[np.ndarray], U: np.ndarray) -> np.ndarray:
 
 
 def kron_design(Xs: Sequence[np.ndarray]) -> np.ndarray:
-    """Explicit design X = X_d (x) ... (x) X_1, eq. (fivenew) (tiny inputs only)."""
+    """Explicit design X = X_d (x) ... (x) X_1, eq. (fivenew), and [X_1 | ... | X_c] for a
+    Components design (tiny inputs only)."""
+    if isinstance(Xs, Components):
+        return np.hstack([kron_design(Xr) for Xr in Xs])
     D = np.ones((1, 1))
     for X in Xs:
         D = np.kron(np.asarray(X, dtype=np.float64), D)
@@ -481,9 +522,16 @@ def spectral_radii(Xs):
     return [float(np.max(np.linalg.eigvalsh(np.asarray(X).T @ np.asarray(X)))) for X in Xs]
 
 
+def spectral_bound(Xs):
+    """Proposition 1's factor sum_r prod_j rho(X_{r,j}^T X_{r,j}) (one term for c = 1)."""
+    if isinstance(Xs, Components):
+        return float(sum(np.prod(spectral_radii(Xr)) for Xr in Xs))
+    return float(np.prod(spectral_radii(Xs)))
+
+
 def lipschitz_bound(Xs, w, n):
-    """Proposition 1 with c = 1: Lhat = max(w) prod_j rho(X_j^T X_j) / n."""
-    return float(np.max(w)) * float(np.prod(spectral_radii(Xs))) / n
+    """Proposition 1: Lhat = max(w) sum_r prod_j rho(X_{r,j}^T X_{r,j}) / n."""
+    return float(np.max(w)) * spectral_bound(Xs) / n
 
 
 def lipschitz_tensor_weights(Xs, factors, n):
@@ -592,9 +640,9 @@ def gdpg(fam, Xs, Y, lam, lam_max, a=None, pen_w=None, theta0=None, tol=1e-10,
     """
     fam = family(fam)
     n = Y.size
-    p = tuple(X.shape[1] for X in Xs)
+    p = param_shape(Xs)
     theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
-    s_prod = float(np.prod(spectral_radii(Xs)))
+    s_prod = spectral_bound(Xs)
     info = FitInfo(False, float("inf"), float("nan"), 0)
     for k in range(max_outer + 1):
         eta = H(Xs, theta)
@@ -662,7 +710,7 @@ def fit_path(fam, Xs, Y, a=None, pen_w=None, lambdas=None, nlambda=100, ratio=1e
     lambdas = np.asarray(lambdas, dtype=np.float64)
     if max_lambdas is not None:
         lambdas = lambdas[:max_lambdas]
-    p = tuple(X.shape[1] for X in Xs)
+    p = param_shape(Xs)
     theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
     thetas, infos = [], []
     for lam in lambdas:
@@ -711,7 +759,7 @@ def msa_scad(fam, Xs, Y, lam, lam_max, steps, a=None, pen_w=None, theta0=None, t
     theta0; each of the steps - 1 further steps solves the weighted lasso with the
     msa_weights of the previous step's estimate, warm-started there.  Returns
     (theta, info of the last step, weights of the last step)."""
-    p = tuple(X.shape[1] for X in Xs)
+    p = param_shape(Xs)
     theta = np.zeros(p) if theta0 is None else np.array(theta0, dtype=np.float64).reshape(p, order="F")
     w = np.ones(int(np.prod(p))) if pen_w is None else vec(pen_w).copy()
     info = None
@@ -731,7 +779,7 @@ def msa_scad_path(fam, Xs, Y, steps, a=None, pen_w=None, lambdas=None, nlambda=1
     lam_max = lambda_max(fam, Xs, Y, a, pen_w)
     if lambdas is None:
         lambdas = lambda_grid(lam_max, nlambda, ratio)
-    p = tuple(X.shape[1] for X in Xs)
+    p = param_shape(Xs)
     theta = np.zeros(p)
     thetas, infos, weights = [], [], []
     for lam in np.asarray(lambdas, dtype=np.float64):

@@ -317,3 +317,63 @@ def random_problem(n, p, family="gaussian", seed=0, sparsity=0.2, noise=0.5, bas
         a = np.asfortranarray(a)
     return GlamData(f"rand_{family}_{n}_{p}_{seed}", family, X, np.asfortranarray(Y), a=a,
                     theta_true=theta)
+
+
+@dataclass
+class GlamMultiData:
+    """A model of c tensor components (Sec. 2): comps[r] = [X_{r,1}, ..., X_{r,d}]."""
+    name: str
+    family: str
+    comps: List[List[np.ndarray]]
+    Y: np.ndarray
+    a: Optional[np.ndarray] = None
+    theta_true: Optional[np.ndarray] = None   # flat: (vec(Theta_1), ..., vec(Theta_c))
+
+    @property
+    def n(self):
+        return tuple(int(x.shape[0]) for x in self.comps[0])
+
+    @property
+    def ps(self):
+        return [tuple(int(x.shape[1]) for x in Xs) for Xs in self.comps]
+
+
+def random_components_problem(n, ps, family="gaussian", seed=0, sparsity=0.3, noise=0.5, obs_weights=False,
+                              scale=0.5) -> GlamMultiData:
+    """Small seeded c-component problem: component r has i.i.d. N(0, 1) factors of sizes
+    n_j x ps[r][j] (d = len(n)) and a sparse coefficient array; Y is drawn around the sum of the
+    components' signals (evaluated on the grid, data generation only)."""
+    rng = np.random.default_rng(SEED_BASE + 3000 + seed)
+    d = len(n)
+    comps, thetas = [], []
+    signal = np.zeros(tuple(n))
+    letters = "abc"[:d]
+    for p in ps:
+        Xs = [np.ascontiguousarray(rng.standard_normal((nj, pj))) for nj, pj in zip(n, p)]
+        P = int(np.prod(p))
+        th = np.zeros(P)
+        k = max(1, int(round(sparsity * P)))
+        th[rng.choice(P, size=k, replace=False)] = scale * rng.standard_normal(k)
+        T = th.reshape(p, order="F")
+        spec = ",".join(f"{'ijk'[j]}{letters[j]}" for j in range(d)) + "," + letters + "->" + "ijk"[:d]
+        signal = signal + np.einsum(spec, *Xs, T, optimize=True)
+        comps.append(Xs)
+        thetas.append(th)
+    eta = signal
+    if family == "gaussian":
+        Y = eta + noise * rng.standard_normal(tuple(n))
+    elif family == "poisson":
+        Y = rng.poisson(np.exp(np.clip(eta, -20, 4))).astype(np.float64)
+    elif family == "binomial":
+        Y = (rng.uniform(size=tuple(n)) < 1.0 / (1.0 + np.exp(-np.clip(eta, -30, 30)))).astype(np.float64)
+    elif family == "gamma":
+        Y = rng.gamma(2.0, 0.5 * np.exp(np.clip(eta, -5, 5)))
+    else:
+        raise ValueError(family)
+    a = None
+    if obs_weights:
+        a = rng.uniform(0.5, 1.5, size=tuple(n))
+        a[rng.uniform(size=tuple(n)) < 0.1] = 0.0
+        a = np.asfortranarray(a)
+    return GlamMultiData(f"comp_{family}_{tuple(n)}_{len(ps)}_{seed}", family, comps, np.asfortranarray(Y), a=a,
+                         theta_true=np.concatenate(thetas))

@@ -120,6 +120,25 @@ MUTANTS = {
     "lexact_no_weights": ("lipschitz_tensor_weights",
                           lambda orig: (lambda Xs, factors, n: orig(Xs, [np.ones_like(v) for v in factors], n)),
                           lambda: [P.test_exact_lipschitz_for_tensor_product_weights]),
+    # c > 1: H without the last component's chain (the sum of eq. eighteen cut short)
+    "components_H_drops_last": ("H",
+                                lambda orig: (lambda Xs, Theta: sum(orig(Xr, Tr) for Xr, Tr in
+                                                                    list(zip(Xs, Xs.split(Theta)))[:-1])
+                                              if isinstance(Xs, O.Components) and len(Xs) > 1 else orig(Xs, Theta)),
+                                lambda: [lambda: P.test_components_H_and_G_are_the_concatenated_design(
+                                    (6, 5, 4), [(3, 2, 2), (2, 3, 3)]),
+                                         P.test_components_gaussian_matches_coordinate_descent]),
+    # c > 1: the tuple of eq. nineteen stacked in reverse component order
+    "components_G_reversed": ("G",
+                              lambda orig: (lambda Xs, U: np.concatenate([O.vec(orig(Xr, U)) for Xr in reversed(Xs)])
+                                            if isinstance(Xs, O.Components) else orig(Xs, U)),
+                              lambda: [lambda: P.test_components_H_and_G_are_the_concatenated_design(
+                                  (6, 5, 4), [(3, 2, 2), (2, 3, 3)])]),
+    # Proposition 1 with the largest component's product instead of the sum over components
+    "prop1_max_over_components": ("spectral_bound",
+                                  lambda orig: (lambda Xs: max(float(np.prod(O.spectral_radii(Xr))) for Xr in Xs)
+                                                if isinstance(Xs, O.Components) else orig(Xs)),
+                                  lambda: [P.test_prop1_bound_sums_over_components]),
     # Lipschitz bound with a sum of spectral radii instead of the product
     "lhat_sum": ("lipschitz_bound",
                  lambda orig: (lambda Xs, w, n: float(np.max(w)) * float(np.sum(O.spectral_radii(Xs))) / n),

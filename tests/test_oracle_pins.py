@@ -773,3 +773,98 @@ def test_unit_weights_reach_the_same_pmle(fam):
     assert np.max(np.abs(one - exact)) <= 1e-6 * max(1.0, np.max(np.abs(exact)))
     g = O.smooth_gradient(fam, d.X, one, d.Y)
     assert O.kkt_residual(one, g, 0.2 * lm, lm) <= 1e-10
+
+
+# =============================================================================
+# c > 1 tensor components (Sec. 2 eq. fivenew; Sec. 6.1 eqs. eighteen, nineteen; Proposition 1)
+# =============================================================================
+def _concatenated_design(comps):
+    """[X_1 | ... | X_c] with X_r = X_{r,d} (x) ... (x) X_{r,1}, built here with numpy's kron."""
+    blocks = []
+    for Xs in comps:
+        D = np.ones((1, 1))
+        for X in Xs:
+            D = np.kron(X, D)
+        blocks.append(D)
+    return np.hstack(blocks)
+
+
+@pytest.mark.parametrize("n,ps", [((6, 5, 4), [(3, 2, 2), (2, 3, 3)]),
+                                  ((7, 6), [(3, 2), (2, 4), (4, 3)]),
+                                  ((5, 4, 3), [(2, 2, 2)])])
+def test_components_H_and_G_are_the_concatenated_design(n, ps):
+    """vec(H(<X_rj>, <Theta_r>)) = X theta and G(<X_rj>, U) = X^T vec(U), stacked as theta is."""
+    d = inputs.random_components_problem(n, ps, seed=11)
+    C = O.Components(d.comps)
+    D = _concatenated_design(d.comps)
+    np.testing.assert_array_equal(O.kron_design(C), D)
+    rng = np.random.default_rng(5)
+    th = rng.standard_normal(D.shape[1])
+    np.testing.assert_allclose(O.vec(O.H(C, th)), D @ th, rtol=1e-12, atol=1e-12)
+    U = rng.standard_normal(tuple(n))
+    np.testing.assert_allclose(O.G(C, U), D.T @ O.vec(U), rtol=1e-12, atol=1e-12)
+    assert O.param_shape(C) == (D.shape[1],)
+
+
+def test_prop1_bound_sums_over_components():
+    """Proposition 1: L = rho(X^T W X)/n <= max(w) sum_r prod_j rho(X_rj^T X_rj) / n; with two
+    copies of one component and W = I, X^T X has the spectrum of 2 X_1^T X_1, so the bound is
+    attained."""
+    d = inputs.random_components_problem((6, 5, 4), [(3, 2, 2), (2, 3, 3)], seed=12)
+    C = O.Components(d.comps)
+    D = _concatenated_design(d.comps)
+    n = D.shape[0]
+    w = np.random.default_rng(6).uniform(0.2, 2.0, n)
+    L = float(np.linalg.eigvalsh(D.T @ (w[:, None] * D))[-1]) / n
+    assert L <= O.lipschitz_bound(C, w, n) * (1 + 1e-12)
+    dup = O.Components([d.comps[0], d.comps[0]])
+    Dd = _concatenated_design(dup.__iter__())
+    Ld = float(np.linalg.eigvalsh(Dd.T @ Dd)[-1]) / n
+    np.testing.assert_allclose(O.lipschitz_bound(dup, np.ones(n), n), Ld, rtol=1e-10)
+
+
+def test_components_gaussian_matches_coordinate_descent():
+    """GD-PG on a c = 2 model vs textbook CD on the concatenated explicit design."""
+    d = inputs.random_components_problem((8, 7, 6), [(3, 3, 2), (2, 2, 3)], seed=13)
+    C = O.Components(d.comps)
+    D = _concatenated_design(d.comps)
+    y = O.vec(d.Y)
+    lm = O.lambda_max("gaussian", C, d.Y)
+    np.testing.assert_allclose(lm, np.max(np.abs(D.T @ y)) / y.size, rtol=1e-12)
+    for frac in [0.3, 0.02]:
+        lam = frac * lm
+        th, info = O.gdpg("gaussian", C, d.Y, lam, lm, tol=1e-12)
+        assert info.converged
+        cd = O.cd_weighted_lasso(D, y, np.ones_like(y), lam, tol=1e-15)
+        np.testing.assert_allclose(th, cd, atol=1e-8 * np.max(np.abs(cd)))
+
+
+def test_components_poisson_matches_prox_newton():
+    """Poisson c = 2 with prior weights: GD-PG vs proximal Newton on the explicit design."""
+    d = inputs.random_components_problem((7, 6, 5), [(2, 3, 2), (3, 2, 2)], family="poisson", seed=14,
+                                         obs_weights=True)
+    C = O.Components(d.comps)
+    lm = O.lambda_max("poisson", C, d.Y, a=d.a)
+    lam = 0.1 * lm
+    th, info = O.gdpg("poisson", C, d.Y, lam, lm, a=d.a, tol=1e-10)
+    assert info.converged
+    ref = O.poisson_lasso_explicit(C, d.Y, lam, a=d.a)
+    np.testing.assert_allclose(th, ref, atol=1e-7 * max(1.0, np.max(np.abs(ref))))
+
+
+def test_duplicated_component_ridge_splits_evenly():
+    """Two copies of one component under the ridge penalty: for a fixed sum s = theta_1 + theta_2
+    the penalty lambda (|theta_1|^2 + |theta_2|^2) is least at theta_1 = theta_2 = s/2, where it is
+    (lambda/2) |s|^2, so each half is half the single-component ridge fit at lambda/2."""
+    d = inputs.random_components_problem((7, 6, 5), [(3, 2, 2)], family="poisson", seed=15)
+    one = d.comps
+    dup = O.Components([one[0], one[0]])
+    lm = O.lambda_max("poisson", one[0], d.Y)
+    lam = 0.05 * lm
+    th2, info2 = O.gdpg("poisson", dup, d.Y, lam, lm, tol=1e-11, alpha=1.0, l1=0.0)
+    th1, info1 = O.gdpg("poisson", one[0], d.Y, lam / 2, lm, tol=1e-11, alpha=1.0, l1=0.0)
+    assert info1.converged and info2.converged
+    half = O.vec(th1) / 2
+    k = half.size
+    np.testing.assert_allclose(th2[:k], half, atol=1e-8 * np.max(np.abs(half)))
+    np.testing.assert_allclose(th2[k:], half, atol=1e-8 * np.max(np.abs(half)))
