@@ -100,9 +100,13 @@ size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dt
  *   Eta      : device, n_1 x ... x n_d; FP64 for GLAM_F64, FP32 otherwise.
  *   workspace: device, >= glam_rho_workspace_size(...) bytes, 256-byte aligned.
  * The mode products commute, so a reordered run (see glam_rho_workspace_size) gives the
- * same transform; Theta is permuted into the workspace and Eta back out of it.
- * Errors: GLAM_EINVAL for d not 2 or 3, sizes < 1, sizes no mode order fits, NULL
- * pointers, a bad dtype or a too-small workspace. */
+ * same transform; Theta is permuted into the workspace and Eta back out of it.  When no order
+ * of the modes fits the slab kernels (p_j > n_j designs, large p_j), the transform runs as three
+ * tiled matrix-core GEMMs in the caller's cyclic mode order, with the intermediates in dtype
+ * (the workspace holds X_j^T and two intermediates).
+ * Errors: GLAM_EINVAL for d not 2 or 3, sizes < 1, NULL pointers, a bad dtype or a
+ * too-small workspace; GLAM_EDEVICE for a mode with more than about 2 million entries on the
+ * generic chain (its launch grid). */
 int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X,
                      const void* Theta, void* Eta, int dtype, void* workspace,
                      size_t ws_bytes, void* stream);
@@ -264,8 +268,42 @@ typedef struct {
  * when p_1, p_2 <= 16, and about n_1 + n_2 <= 256 when max(p_1, p_2) is 17..32.  When the
  * caller's order does not fit, the fit reorders the modes itself (the largest remaining mode
  * last; Y, obs_w, pen_w and theta0 are permuted on the caller's stream into buffers of its own,
- * and theta is returned in the caller's order); GLAM_EINVAL when no order fits. */
+ * and theta is returned in the caller's order).  When no order fits (p_j > n_j designs, large
+ * p_j), the path runs on the generic-GEMM solver of glam_fit_path_multi (c = 1), which takes
+ * the rho-chain and unit-weight inner loops (GLAM_EINVAL for the Gram forms). */
 int glam_fit_path(const glam_problem* prob, const glam_options* opt, glam_result* res);
+
+/* ---------------------------------------------------------------------------
+ * models of c >= 1 tensor components (Sec. 2, eq. fivenew: X = [X_1 | ... | X_c] with
+ * X_r = X_{r,d} (x) ... (x) X_{r,1}; theta = (vec(Theta_1), ..., vec(Theta_c)))
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int d;                  /* 2 or 3, shared by every component                      */
+  int64_t n[3];           /* mode sizes of the response array                       */
+  int c;                  /* number of tensor components (>= 1)                     */
+  const int64_t* p;       /* HOST, 3 c entries: p[3 r + j] = p_{r,j} (j >= d ignored) */
+  const double* const* X; /* HOST, 3 c device pointers: X[3 r + j] -> n_j x p_{r,j},
+                             FP64 column-major (j >= d ignored)                      */
+  const double* Y;        /* device, FP64 response array n_1 x ... x n_d            */
+  const double* obs_w;    /* device, FP64 prior weights a_i >= 0, or NULL           */
+  int family;             /* glam_family                                            */
+  const double* pen_w;    /* device, FP64 penalty weights w_m > 0, length
+                             p = sum_r prod_j p_{r,j}, or NULL = 1                  */
+} glam_multi_problem;
+
+/* The lambda path of glam_fit_path for a c-component model: eta = H(<X_rj>, <Theta_r>), the sum
+ * over components of the rho chains (eq. eighteen), the gradient the tuple of the components'
+ * adjoint chains (eq. nineteen), and delta from Proposition 1 with its sum over components,
+ * Lhat = max(w)/n sum_r prod_j rho(X_{r,j}^T X_{r,j}).  Every rho product runs as a tiled
+ * matrix-core GEMM in the paper's cyclic mode order, with no limit on the mode sizes beyond
+ * device memory; glam_fit_path itself uses this solver (c = 1) when no order of the modes fits
+ * its slab kernels (p_j > n_j designs).
+ * Options as glam_fit_path, except: inner_mode GLAM_INNER_CHAIN or GLAM_INNER_ONE only
+ * (GLAM_EINVAL for the Gram forms); graph_mode, profile_every and kron_step are ignored, and
+ * chain_ms, iter_ms, adj_ms, fwd_ms and chain_samples are returned as 0.  res->theta holds
+ * nlambda x p values, model l at offset l p in the order of theta above.
+ * Errors: those of glam_fit_path, and GLAM_EINVAL for c < 1 or NULL p / X. */
+int glam_fit_path_multi(const glam_multi_problem* prob, const glam_options* opt, glam_result* res);
 
 /* ---------------------------------------------------------------------------
  * Many independent GLAMs at once (one lambda each): every inner proximal step of

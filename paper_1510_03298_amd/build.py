@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libglam.so")
-SOURCES = ["slab.hip", "aux.hip", "gram.hip", "api.cpp", "fit.cpp"]
+SOURCES = ["slab.hip", "aux.hip", "gram.hip", "general.hip", "api.cpp", "fit.cpp", "general.cpp"]
 ARCH = "gfx950"
 
 

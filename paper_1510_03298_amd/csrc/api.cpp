@@ -110,9 +110,10 @@ struct RhoPlan {
   Geom G;                 // geometry of the order that runs
   int q[3] = {0, 1, 2};
   bool perm = false;
+  bool generic = false;   // no order fits: the generic GEMM chain (rho entry points only)
   int64_t n[3], p[3];     // lifted sizes in the caller's order
 };
-static int plan_rho(int d, const int64_t* n_in, const int64_t* p_in, int dtype, RhoPlan* R) {
+static int plan_rho(int d, const int64_t* n_in, const int64_t* p_in, int dtype, RhoPlan* R, bool allow_generic = false) {
   int st = check_basic(d, n_in, p_in, dtype, R->n, R->p);
   if (st) return st;
   std::string why;
@@ -127,7 +128,13 @@ static int plan_rho(int d, const int64_t* n_in, const int64_t* p_in, int dtype, 
     if (!inner_fit(n, p, dtype, &G, &w)) continue;
     if (best < 0 || n[2] > R->n[perms[best][2]]) { best = c; R->G = G; }
   }
-  if (best < 0) return fail(GLAM_EINVAL, why + " (in every order of the modes)");
+  if (best < 0) {
+    if (allow_generic) {
+      R->generic = true;
+      return GLAM_OK;
+    }
+    return fail(GLAM_EINVAL, why + " (in every order of the modes)");
+  }
   R->perm = true;
   for (int k = 0; k < 3; ++k) R->q[k] = perms[best][k];
   return GLAM_OK;
@@ -218,7 +225,26 @@ const char* glam_version(void) { return "glam-mi355x 0.1.0 (gfx950)"; }
 
 // rho workspace: the layout of the order that runs, then (reordered problems) an n-sized and
 // a p-sized region of 8-byte elements for the permuted input and output
+// Workspace of the generic chain: X_j^T for the forward products (dtype), two intermediates of
+// general_tmp_elems elements, the unit middle factor of a d = 2 model.
+struct GenWs {
+  size_t xt[3], t1, t2, unit, total;
+};
+static GenWs gen_ws_layout(const RhoPlan& R, int dtype) {
+  const size_t es = dt_size(dtype);
+  GenWs W;
+  size_t o = 0;
+  for (int j = 0; j < 3; ++j) { W.xt[j] = o; o += align256((size_t)R.n[j] * R.p[j] * es); }
+  const size_t tmp = (size_t)general_tmp_elems(R.n, R.p);
+  W.t1 = o; o += align256(tmp * es);
+  W.t2 = o; o += align256(tmp * es);
+  W.unit = o; o += 256;
+  W.total = o;
+  return W;
+}
+
 static size_t rho_ws_total(const RhoPlan& R, int dtype) {
+  if (R.generic) return gen_ws_layout(R, dtype).total;
   size_t t = ws_layout(R.G, dtype).total;
   if (R.perm) t += align256((size_t)R.G.n * 8) + align256((size_t)R.G.p * 8);
   return t;
@@ -226,7 +252,7 @@ static size_t rho_ws_total(const RhoPlan& R, int dtype) {
 
 size_t glam_rho_workspace_size(int d, const int64_t* n, const int64_t* p, int dtype) {
   RhoPlan R;
-  if (plan_rho(d, n, p, dtype, &R) != GLAM_OK) return 0;
+  if (plan_rho(d, n, p, dtype, &R, true) != GLAM_OK) return 0;
   return rho_ws_total(R, dtype);
 }
 
@@ -243,12 +269,53 @@ static int lift_factors(int d, const void* const* X, char* ws, const WsLayout& W
   return GLAM_OK;
 }
 
+// the generic chain: three GEMMs per direction in the caller's (cyclic) mode order
+static int gen_factors(int d, const void* const* X, char* ws, const GenWs& W, int dtype, hipStream_t s,
+                       const void** X3) {
+  if (!X || !X[0] || !X[1] || (d == 3 && !X[2])) return fail(GLAM_EINVAL, "NULL pointer");
+  if (d == 3) {
+    X3[0] = X[0]; X3[1] = X[1]; X3[2] = X[2];
+    return GLAM_OK;
+  }
+  HIPCHK(launch_set_one(dtype, ws + W.unit, s));
+  X3[0] = X[0]; X3[1] = ws + W.unit; X3[2] = X[1];
+  return GLAM_OK;
+}
+static int gen_forward(const RhoPlan& R, int d, const void* const* X_in, const void* Theta, void* Eta, int dtype,
+                       char* ws, hipStream_t s) {
+  const GenWs W = gen_ws_layout(R, dtype);
+  const void* X[3];
+  int st = gen_factors(d, X_in, ws, W, dtype, s, X);
+  if (st) return st;
+  const void* XT[3];
+  for (int j = 0; j < 3; ++j) {
+    HIPCHK(launch_gen_transpose_same(dtype, R.n[j], R.p[j], X[j], ws + W.xt[j], s));
+    XT[j] = ws + W.xt[j];
+  }
+  HIPCHK(general_forward(dtype, R.n, R.p, XT, Theta, ws + W.t1, ws + W.t2, Eta, false, s));
+  return GLAM_OK;
+}
+static int gen_adjoint(const RhoPlan& R, int d, const void* const* X_in, const void* U, void* Out, int dtype, char* ws,
+                       hipStream_t s) {
+  const GenWs W = gen_ws_layout(R, dtype);
+  const void* X[3];
+  int st = gen_factors(d, X_in, ws, W, dtype, s, X);
+  if (st) return st;
+  HIPCHK(general_adjoint(dtype, R.n, R.p, X, U, ws + W.t1, ws + W.t2, Out, s));
+  return GLAM_OK;
+}
+
 int glam_rho_forward(int d, const int64_t* n, const int64_t* p, const void* const* X_in, const void* Theta_in, void* Eta_out,
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   RhoPlan R;
-  int st = plan_rho(d, n, p, dtype, &R);
+  int st = plan_rho(d, n, p, dtype, &R, true);
   if (st) return st;
+  if (R.generic) {
+    if (!Theta_in || !Eta_out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+    if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+    return gen_forward(R, d, X_in, Theta_in, Eta_out, dtype, (char*)workspace, (hipStream_t)stream);
+  }
   const Geom& G = R.G;
   if (!Theta_in || !Eta_out || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");
@@ -291,7 +358,7 @@ int glam_rho_forward_static(int d, const int64_t* n, const int64_t* p, const voi
                             void* Eta, int dtype, void* stream) {
   g_err.clear();
   RhoPlan R;
-  const int st = plan_rho(d, n, p, dtype, &R);
+  const int st = plan_rho(d, n, p, dtype, &R, true);
   if (st) return st;
   const size_t need = rho_ws_total(R, dtype);
   if (need > (size_t)GLAM_STATIC_SCRATCH_BYTES)
@@ -309,8 +376,13 @@ int glam_rho_adjoint(int d, const int64_t* n, const int64_t* p, const void* cons
                      int dtype, void* workspace, size_t ws_bytes, void* stream) {
   g_err.clear();
   RhoPlan R;
-  int st = plan_rho(d, n, p, dtype, &R);
+  int st = plan_rho(d, n, p, dtype, &R, true);
   if (st) return st;
+  if (R.generic) {
+    if (!U_in || !Out_p || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
+    if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");
+    return gen_adjoint(R, d, X_in, U_in, Out_p, dtype, (char*)workspace, (hipStream_t)stream);
+  }
   const Geom& G = R.G;
   if (!U_in || !Out_p || !workspace) return fail(GLAM_EINVAL, "NULL pointer");
   if (ws_bytes < rho_ws_total(R, dtype)) return fail(GLAM_EINVAL, "workspace too small");

@@ -33,13 +33,14 @@
 #include <thread>
 #include <vector>
 
+#include "general.h"
 #include "glam.h"
 #include "launch.h"
 
 namespace glam {
 
 // Gram matrix X^T X (X host, n x p column-major), p x p.
-static std::vector<double> gram_matrix(const double* X, int n, int p) {
+std::vector<double> gram_matrix(const double* X, int n, int p) {
   std::vector<double> A((size_t)p * p, 0.0);
   for (int a = 0; a < p; ++a)
     for (int b = a; b < p; ++b) {
@@ -53,7 +54,7 @@ static std::vector<double> gram_matrix(const double* X, int n, int p) {
 
 // Largest eigenvalue of a symmetric p x p matrix by cyclic Jacobi rotations
 // (Proposition 1 needs rho(X_j^T X_j)).
-static double gram_spectral_radius(std::vector<double> A, int p) {
+double gram_spectral_radius(std::vector<double> A, int p) {
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0, diag = 0.0;
     for (int a = 0; a < p; ++a) {
@@ -985,6 +986,67 @@ static int permute_problem(glam_problem* prob, int dtype, const double** theta0,
   return GLAM_OK;
 }
 
+// The checks of glam_fit_path on its options and result arrays (shared with the generic solver).
+int glam::check_fit_options(const glam_options* opt, const glam_result* res, int family, bool has_obs_w, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return GLAM_EINVAL;
+  };
+  if (opt->dtype < 0 || opt->dtype > 2) return bad("bad dtype");
+  if (opt->nlambda < 1) return bad("nlambda must be >= 1");
+  if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
+    return bad("lambda_min_ratio must be in (0, 1]");
+  if (!(opt->kkt_tol > 0.0)) return bad("kkt_tol must be > 0");
+  if (!(opt->nu >= 0.0 && opt->nu <= 1.0)) return bad("nu must be in [0, 1]");
+  if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return bad("alpha must be finite and >= 0");
+  if (opt->penalty != GLAM_PENALTY_LASSO && opt->penalty != GLAM_PENALTY_SCAD && opt->penalty != GLAM_PENALTY_RIDGE)
+    return bad("bad penalty");
+  if (opt->penalty == GLAM_PENALTY_RIDGE && opt->alpha != 0.0)
+    return bad("the ridge penalty takes no elastic-net weight (alpha = 0)");
+  if (opt->penalty == GLAM_PENALTY_SCAD) {
+    if (opt->msa_steps < 1) return bad("msa_steps must be >= 1");
+    if (!(opt->scad_a == 0.0 || (opt->scad_a > 2.0 && std::isfinite(opt->scad_a))))
+      return bad("scad_a must be > 2 (or 0 for 3.7)");
+    if (opt->alpha != 0.0) return bad("SCAD and the elastic net do not combine");
+  }
+  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM && opt->inner_mode != GLAM_INNER_KRON &&
+      opt->inner_mode != GLAM_INNER_ONE)
+    return bad("bad inner_mode");
+  if (opt->inner_mode == GLAM_INNER_ONE && (has_obs_w || opt->nu < 1.0))
+    return bad("the unit-weight inner loop takes no prior weights and runs without backtracking (nu = 1)");
+  if (opt->inner_mode == GLAM_INNER_KRON && opt->nu < 1.0)
+    return bad("the tensor-product-weight inner loop runs without backtracking (nu = 1)");
+  if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(family) || has_obs_w || opt->nu < 1.0))
+    return bad("the Gram inner loop is exact only for unit IRLS weights (Gaussian, Gamma-log) "
+               "without prior weights (Sec. 6.2) and runs without backtracking (nu = 1)");
+  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
+    return bad("max_outer, max_inner and check_every must be >= 1");
+  if (opt->extrapolation != 0 && opt->extrapolation != 1) return bad("bad extrapolation");
+  if (opt->kron_step != 0 && opt->kron_step != 1) return bad("bad kron_step");
+  if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
+      !res->status)
+    return bad("NULL result array");
+  if (opt->lambda) {
+    for (int l = 0; l < opt->nlambda; ++l) {
+      if (!(opt->lambda[l] >= 0.0) || !std::isfinite(opt->lambda[l]))
+        return bad("lambda values must be finite and >= 0");
+      if (l > 0 && !(opt->lambda[l] < opt->lambda[l - 1]))
+        return bad("lambda sequence must be strictly decreasing");
+    }
+  }
+  return GLAM_OK;
+}
+
+// some order of the modes fits the slab kernels
+static bool any_order_fits(const int64_t* n, const int64_t* p, int dtype) {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 2, 0}, {1, 0, 2}, {2, 0, 1}, {2, 1, 0}};
+  for (const auto& q : perms) {
+    const int64_t nq[3] = {n[q[0]], n[q[1]], n[q[2]]}, pq[3] = {p[q[0]], p[q[1]], p[q[2]]};
+    if (inner_modes_fit(nq, pq, dtype)) return true;
+  }
+  return false;
+}
+
 extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* opt_in, glam_result* res) {
   auto t_start = std::chrono::steady_clock::now();
   if (!prob_in || !opt_in || !res) return fit_fail(GLAM_EINVAL, "NULL argument");
@@ -1001,47 +1063,32 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   const glam_problem* prob = &lifted;
   if (!prob->Y) return fit_fail(GLAM_EINVAL, "NULL Y");
   if (prob->family < GLAM_GAUSSIAN || prob->family > GLAM_GAMMA) return fit_fail(GLAM_EINVAL, "bad family");
-  if (opt->dtype < 0 || opt->dtype > 2) return fit_fail(GLAM_EINVAL, "bad dtype");
-  if (opt->nlambda < 1) return fit_fail(GLAM_EINVAL, "nlambda must be >= 1");
-  if (!opt->lambda && !(opt->lambda_min_ratio > 0.0 && opt->lambda_min_ratio <= 1.0))
-    return fit_fail(GLAM_EINVAL, "lambda_min_ratio must be in (0, 1]");
-  if (!(opt->kkt_tol > 0.0)) return fit_fail(GLAM_EINVAL, "kkt_tol must be > 0");
-  if (!(opt->nu >= 0.0 && opt->nu <= 1.0)) return fit_fail(GLAM_EINVAL, "nu must be in [0, 1]");
-  if (!(opt->alpha >= 0.0) || !std::isfinite(opt->alpha)) return fit_fail(GLAM_EINVAL, "alpha must be finite and >= 0");
-  if (opt->penalty != GLAM_PENALTY_LASSO && opt->penalty != GLAM_PENALTY_SCAD && opt->penalty != GLAM_PENALTY_RIDGE)
-    return fit_fail(GLAM_EINVAL, "bad penalty");
-  if (opt->penalty == GLAM_PENALTY_RIDGE && opt->alpha != 0.0)
-    return fit_fail(GLAM_EINVAL, "the ridge penalty takes no elastic-net weight (alpha = 0)");
-  if (opt->penalty == GLAM_PENALTY_SCAD) {
-    if (opt->msa_steps < 1) return fit_fail(GLAM_EINVAL, "msa_steps must be >= 1");
-    if (!(opt->scad_a == 0.0 || (opt->scad_a > 2.0 && std::isfinite(opt->scad_a))))
-      return fit_fail(GLAM_EINVAL, "scad_a must be > 2 (or 0 for 3.7)");
-    if (opt->alpha != 0.0) return fit_fail(GLAM_EINVAL, "SCAD and the elastic net do not combine");
+  {
+    std::string why;
+    const int r = check_fit_options(opt, res, prob->family, prob->obs_w != nullptr, &why);
+    if (r) return fit_fail(r, why);
   }
-  if (opt->inner_mode != GLAM_INNER_CHAIN && opt->inner_mode != GLAM_INNER_GRAM && opt->inner_mode != GLAM_INNER_KRON &&
-      opt->inner_mode != GLAM_INNER_ONE)
-    return fit_fail(GLAM_EINVAL, "bad inner_mode");
-  if (opt->inner_mode == GLAM_INNER_ONE && (prob->obs_w || opt->nu < 1.0))
-    return fit_fail(GLAM_EINVAL, "the unit-weight inner loop takes no prior weights and runs without backtracking (nu = 1)");
-  if (opt->inner_mode == GLAM_INNER_KRON && opt->nu < 1.0)
-    return fit_fail(GLAM_EINVAL, "the tensor-product-weight inner loop runs without backtracking (nu = 1)");
-  if (opt->inner_mode == GLAM_INNER_GRAM && (family_has_weights(prob->family) || prob->obs_w || opt->nu < 1.0))
-    return fit_fail(GLAM_EINVAL, "the Gram inner loop is exact only for unit IRLS weights (Gaussian, Gamma-log) "
-                                 "without prior weights (Sec. 6.2) and runs without backtracking (nu = 1)");
-  if (opt->max_outer < 1 || opt->max_inner < 1 || opt->check_every < 1)
-    return fit_fail(GLAM_EINVAL, "max_outer, max_inner and check_every must be >= 1");
-  if (opt->extrapolation != 0 && opt->extrapolation != 1) return fit_fail(GLAM_EINVAL, "bad extrapolation");
-  if (opt->kron_step != 0 && opt->kron_step != 1) return fit_fail(GLAM_EINVAL, "bad kron_step");
-  if (!res->theta || !res->lambda_out || !res->kkt || !res->objective || !res->iters_outer || !res->iters_inner ||
-      !res->status)
-    return fit_fail(GLAM_EINVAL, "NULL result array");
-  if (opt->lambda) {
-    for (int l = 0; l < opt->nlambda; ++l) {
-      if (!(opt->lambda[l] >= 0.0) || !std::isfinite(opt->lambda[l]))
-        return fit_fail(GLAM_EINVAL, "lambda values must be finite and >= 0");
-      if (l > 0 && !(opt->lambda[l] < opt->lambda[l - 1]))
-        return fit_fail(GLAM_EINVAL, "lambda sequence must be strictly decreasing");
-    }
+  // modes that fit no order of the slab kernels (p_j > n_j designs, large p_j): the generic-GEMM
+  // solver, which takes the rho-chain and unit-weight inner loops
+  if (!any_order_fits(prob->n, prob->p, opt->dtype)) {
+    if (opt->inner_mode == GLAM_INNER_GRAM || opt->inner_mode == GLAM_INNER_KRON)
+      return fit_fail(GLAM_EINVAL, "no order of the modes fits the slab kernels (two modes need p <= 32 and n <= 256, "
+                                   "FP64 LDS image), and the generic solver takes only the rho-chain and unit-weight "
+                                   "inner loops");
+    GenProblem gp;
+    for (int j = 0; j < 3; ++j) gp.n[j] = prob->n[j];
+    GenComponent c;
+    for (int j = 0; j < 3; ++j) { c.p[j] = prob->p[j]; c.X[j] = prob->X[j]; }
+    gp.comps.push_back(c);
+    gp.Y = prob->Y;
+    gp.obs_w = prob->obs_w;
+    gp.family = prob->family;
+    gp.pen_w = prob->pen_w;
+    std::string why;
+    const int r = general_fit_path(gp, opt, res, &why);
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (r) return fit_fail(r, why);
+    return GLAM_OK;
   }
   {
     // modes reordered, when needed, so that two of them fit the slab kernels

@@ -1,0 +1,452 @@
+// general.hip -- the rho products as tiled matrix-core GEMMs in the paper's cyclic mode order
+// (App. A: rho(X, A) contracts mode 1 of A with X and appends the new mode last), and the
+// elementwise parts of Algorithm 1 on standard-layout arrays.  This is the solver path for the
+// problems the fused slab kernels do not take: modes 1-2 beyond their limits in every order
+// (p > n designs of Sec. 6.5 with q = 3), and models of c > 1 tensor components (Sec. 2,
+// eq. fivenew), whose linear predictor is the sum of the components' H maps.
+//
+// rho step as a GEMM: with A viewed as the K x M column-major matrix A[k + K m] (K = the
+// contracted mode, M = the product of the others) and X (N x K), rho(X, A) is the M x N
+// column-major matrix C[m + M i] = sum_k A[k + K m] X[i + N k].  Both operands are read
+// k-contiguously: A as it is, X through its transpose (packed once: XT[k + K i]).
+#include <algorithm>
+
+#include "launch.h"
+#include "mfma.h"
+
+namespace glam {
+
+constexpr int GWG = 256;   // 4 waves, 2 x 2 tiles of 16 x 16
+
+__device__ inline int g_lane() { return threadIdx.x & 63; }
+__device__ inline int g_wave() { return threadIdx.x >> 6; }
+
+template <typename T> struct GenOut;
+template <> struct GenOut<double> { typedef double type; };
+template <> struct GenOut<float> { typedef float type; };
+template <> struct GenOut<bf16> { typedef bf16 type; };
+
+__device__ inline double g_to(double v, double*) { return v; }
+__device__ inline float g_to(float v, float*) { return v; }
+__device__ inline bf16 g_to(float v, bf16*) { bf16 b; b.u = f32_to_bf16(v); return b; }
+__device__ inline double g_val(double v) { return v; }
+__device__ inline float g_val(float v) { return v; }
+__device__ inline float g_val(bf16 v) { return bf16_to_f32(v.u); }
+
+// C[m + ldc n] (+)= sum_k A[k + lda m] B[k + ldb n], m < M, n < N, k < K; one 32 x 32 output tile
+// per workgroup.  T: operand type; TO: output type (T for the intermediate steps, the
+// accumulation type for the last); ACC: add to C (the components of a c > 1 model).
+template <typename T, typename TO, bool ACC>
+__global__ __launch_bounds__(GWG) void k_rho_gemm(long long M, long long N, long long K, const T* __restrict__ A,
+                                                  long long lda, const T* __restrict__ B, long long ldb,
+                                                  TO* __restrict__ C, long long ldc) {
+  typedef Tr<T> R;
+  typedef typename R::frag_t F;
+  const int lane = g_lane(), r = lane & 15, g = lane >> 4, w = g_wave();
+  const long long m = (long long)blockIdx.x * 32 + 16 * (w & 1) + r;   // A column (output row)
+  const long long nn = (long long)blockIdx.y * 32 + 16 * (w >> 1) + r; // B column (output column)
+  const bool am = m < M, bn = nn < N;
+  typename R::accv_t acc = R::zero();
+  const T* pa = A + (am ? m : 0) * lda;
+  const T* pb = B + (bn ? nn : 0) * ldb;
+  const T z = zero_val<T>();
+  for (long long k0 = 0; k0 < K; k0 += 16) {
+    T a4[4], b4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const long long k = k0 + R::kidx(g, t);
+      const bool in = k < K;
+      a4[t] = (in && am) ? pa[k] : z;
+      b4[t] = (in && bn) ? pb[k] : z;
+    }
+    const F fa = raw_frag<T>(a4[0], a4[1], a4[2], a4[3]);
+    const F fb = raw_frag<T>(b4[0], b4[1], b4[2], b4[3]);
+    mma(acc, fa, fb);
+  }
+  // lane (r, g), register i: output row kidx(g, i) of this wave's tile, column r
+  const long long mb = (long long)blockIdx.x * 32 + 16 * (w & 1);
+  if (!bn) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const long long mo = mb + R::kidx(g, i);
+    if (mo >= M) continue;
+    TO* dst = C + mo + ldc * nn;
+    if (ACC) *dst = g_to((typename R::acc_t)(g_val(*dst) + acc[i]), (TO*)nullptr);
+    else *dst = g_to((typename R::acc_t)acc[i], (TO*)nullptr);
+  }
+}
+
+template <typename T, typename TO, bool ACC>
+static hipError_t gemm_t(long long M, long long N, long long K, const void* A, long long lda, const void* B,
+                         long long ldb, void* C, long long ldc, hipStream_t s) {
+  const long long gx = (M + 31) / 32, gy = (N + 31) / 32;
+  if (gx < 1 || gy < 1 || gy > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_rho_gemm<T, TO, ACC>), dim3((unsigned)gx, (unsigned)gy), dim3(GWG), 0, s, M, N, K, (const T*)A,
+                     lda, (const T*)B, ldb, (TO*)C, ldc);
+  return hipGetLastError();
+}
+
+// one rho step in dtype dt: out_kind 0 = dtype (an intermediate), 1 = the accumulation type
+// (FP32 for BF16/F32, FP64 for F64); acc: add into C
+hipError_t launch_rho_gemm(int dt, int out_kind, bool acc, long long M, long long N, long long K, const void* A,
+                           long long lda, const void* B, long long ldb, void* C, long long ldc, hipStream_t s) {
+  if (dt == DT_F64) return acc ? gemm_t<double, double, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
+                               : gemm_t<double, double, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
+  if (dt == DT_F32) return acc ? gemm_t<float, float, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
+                               : gemm_t<float, float, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
+  if (out_kind == 0) return acc ? gemm_t<bf16, bf16, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
+                                : gemm_t<bf16, bf16, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
+  return acc ? gemm_t<bf16, float, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
+             : gemm_t<bf16, float, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// H and G of one component by three rho steps (App. A; Sec. 6.1 eqs. eighteen, nineteen)
+// ---------------------------------------------------------------------------------------------
+// forward: Theta (p1, p2, p3) -> (p2, p3, n1) -> (p3, n1, n2) -> eta (n1, n2, n3);
+// XT[j]: X_j^T packed k-contiguously (p_j x n_j, element (k, i) at k + p_j i), in dtype dt;
+// eta: the accumulation type, added into when acc
+hipError_t general_forward(int dt, const int64_t* n, const int64_t* p, const void* const* XT, const void* theta,
+                           void* t1, void* t2, void* eta, bool acc, hipStream_t s) {
+  hipError_t e;
+  const long long n1 = n[0], n2 = n[1], n3 = n[2], p1 = p[0], p2 = p[1], p3 = p[2];
+  e = launch_rho_gemm(dt, 0, false, p2 * p3, n1, p1, theta, p1, XT[0], p1, t1, p2 * p3, s);
+  if (e != hipSuccess) return e;
+  e = launch_rho_gemm(dt, 0, false, p3 * n1, n2, p2, t1, p2, XT[1], p2, t2, p3 * n1, s);
+  if (e != hipSuccess) return e;
+  return launch_rho_gemm(dt, 1, acc, n1 * n2, n3, p3, t2, p3, XT[2], p3, eta, n1 * n2, s);
+}
+
+// adjoint: U (n1, n2, n3) -> (n2, n3, p1) -> (n3, p1, p2) -> out (p1, p2, p3); X[j] in dtype dt
+// (n_j x p_j column-major, which is the k-contiguous operand of these steps); out: the
+// accumulation type
+hipError_t general_adjoint(int dt, const int64_t* n, const int64_t* p, const void* const* X, const void* u, void* t1,
+                           void* t2, void* out, hipStream_t s) {
+  hipError_t e;
+  const long long n1 = n[0], n2 = n[1], n3 = n[2], p1 = p[0], p2 = p[1], p3 = p[2];
+  e = launch_rho_gemm(dt, 0, false, n2 * n3, p1, n1, u, n1, X[0], n1, t1, n2 * n3, s);
+  if (e != hipSuccess) return e;
+  e = launch_rho_gemm(dt, 0, false, n3 * p1, p2, n2, t1, n2, X[1], n2, t2, n3 * p1, s);
+  if (e != hipSuccess) return e;
+  return launch_rho_gemm(dt, 1, false, p1 * p2, p3, n3, t2, n3, X[2], n3, out, p1 * p2, s);
+}
+
+long long general_tmp_elems(const int64_t* n, const int64_t* p) {
+  const long long n1 = n[0], n2 = n[1], n3 = n[2], p1 = p[0], p2 = p[1], p3 = p[2];
+  return std::max({p2 * p3 * n1, p3 * n1 * n2, n2 * n3 * p1, n3 * p1 * p2, 1LL});
+}
+
+// ---------------------------------------------------------------------------------------------
+// elementwise kernels (standard layout)
+// ---------------------------------------------------------------------------------------------
+template <typename S, typename T>
+__global__ void k_gen_convert(long long count, const S* __restrict__ src, T* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = g_to((typename Tr<T>::acc_t)g_val(src[i]), (T*)nullptr);
+}
+// X^T of an n x p matrix (FP64 or already in T), in dtype T: out[k + p i] = X[i + n k]
+template <typename S, typename T>
+__global__ void k_gen_transpose(long long nr, long long pc, const S* __restrict__ X, T* __restrict__ out) {
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nr * pc; q += (long long)gridDim.x * blockDim.x) {
+    const long long k = q % pc, i = q / pc;
+    out[q] = g_to((typename Tr<T>::acc_t)g_val(X[i + nr * k]), (T*)nullptr);
+  }
+}
+
+static inline int g_grid(long long n) {
+  long long b = (n + GWG - 1) / GWG;
+  return (int)std::max(1LL, std::min(b, (long long)kGenMaxBlocks));
+}
+
+hipError_t launch_gen_pack(int dt, long long count, const double* src, void* dst, hipStream_t s) {
+  if (dt == DT_F64) hipLaunchKernelGGL((k_gen_convert<double, double>), dim3(g_grid(count)), dim3(GWG), 0, s, count, src, (double*)dst);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_gen_convert<double, float>), dim3(g_grid(count)), dim3(GWG), 0, s, count, src, (float*)dst);
+  else hipLaunchKernelGGL((k_gen_convert<double, bf16>), dim3(g_grid(count)), dim3(GWG), 0, s, count, src, (bf16*)dst);
+  return hipGetLastError();
+}
+hipError_t launch_gen_transpose(int dt, long long nr, long long pc, const double* X, void* out, hipStream_t s) {
+  const dim3 g(g_grid(nr * pc)), b(GWG);
+  if (dt == DT_F64) hipLaunchKernelGGL((k_gen_transpose<double, double>), g, b, 0, s, nr, pc, X, (double*)out);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_gen_transpose<double, float>), g, b, 0, s, nr, pc, X, (float*)out);
+  else hipLaunchKernelGGL((k_gen_transpose<double, bf16>), g, b, 0, s, nr, pc, X, (bf16*)out);
+  return hipGetLastError();
+}
+hipError_t launch_gen_transpose_same(int dt, long long nr, long long pc, const void* X, void* out, hipStream_t s) {
+  const dim3 g(g_grid(nr * pc)), b(GWG);
+  if (dt == DT_F64) hipLaunchKernelGGL((k_gen_transpose<double, double>), g, b, 0, s, nr, pc, (const double*)X, (double*)out);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_gen_transpose<float, float>), g, b, 0, s, nr, pc, (const float*)X, (float*)out);
+  else hipLaunchKernelGGL((k_gen_transpose<bf16, bf16>), g, b, 0, s, nr, pc, (const bf16*)X, (bf16*)out);
+  return hipGetLastError();
+}
+
+__device__ inline double g_warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double g_warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// per-workgroup partials [block][nv] of nv values (ops bit v: 1 = max, 0 = sum)
+template <int NV>
+__device__ inline void g_block_partials(double (&v)[NV], unsigned ops, double* __restrict__ part) {
+  __shared__ double sm[GWG / 64][NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = ((ops >> q) & 1u) ? g_warp_max(v[q]) : g_warp_sum(v[q]);
+  if (g_lane() == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sm[g_wave()][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int q = threadIdx.x;
+    double a = sm[0][q];
+    for (int ww = 1; ww < GWG / 64; ++ww) a = ((ops >> q) & 1u) ? fmax(a, sm[ww][q]) : a + sm[ww][q];
+    part[(long long)blockIdx.x * NV + q] = a;
+  }
+}
+
+// Step 2 of Algorithm 1 on the FP64 eta: u (eq. four) in the adjoint's dtype T, the weights (eq.
+// nine) in the accumulation type A (Poisson, Binomial; NULL otherwise), partial sums of -l and
+// the largest weight.  a == NULL: a_i = 1.
+template <typename T, typename A>
+__global__ __launch_bounds__(GWG) void k_gen_family(long long n, int family, const double* __restrict__ eta,
+                                                    const double* __restrict__ y, const double* __restrict__ a,
+                                                    T* __restrict__ u_out, A* __restrict__ v_out,
+                                                    double* __restrict__ part) {
+  double s_nll = 0.0, s_vmax = 0.0;
+  for (long long i = blockIdx.x * (long long)GWG + threadIdx.x; i < n; i += (long long)gridDim.x * GWG) {
+    const double e = eta[i], yv = y[i], av = a ? a[i] : 1.0;
+    double wgt, nll, u;
+    if (family == 1) {          // Poisson, log link
+      const double mu = exp(e);
+      wgt = mu;
+      nll = av * (mu - yv * e);
+      u = av * (yv - mu);
+    } else if (family == 2) {   // Binomial, logit link
+      const double ex = exp(-fabs(e));
+      const double mu = e >= 0.0 ? 1.0 / (1.0 + ex) : ex / (1.0 + ex);
+      wgt = ex / ((1.0 + ex) * (1.0 + ex));
+      nll = av * (fmax(e, 0.0) + log1p(ex) - yv * e);
+      u = av * (yv - mu);
+    } else if (family == 3) {   // Gamma, log link: unit weight
+      const double emi = exp(-e);
+      wgt = 1.0;
+      nll = av * (yv * emi + e);
+      u = av * (yv * emi - 1.0);
+    } else {                    // Gaussian, identity link
+      const double d = yv - e;
+      wgt = 1.0;
+      nll = 0.5 * av * d * d;
+      u = av * d;
+    }
+    u_out[i] = g_to((typename Tr<T>::acc_t)u, (T*)nullptr);
+    if (v_out) v_out[i] = (A)wgt;
+    s_nll += nll;
+    s_vmax = fmax(s_vmax, wgt);
+  }
+  double v[2] = {s_nll, s_vmax};
+  g_block_partials<2>(v, 2u, part);
+}
+
+hipError_t launch_gen_family(int adj_dt, int v_dt, long long n, int family, const double* eta, const double* y,
+                             const double* a, void* u_out, void* v_out, double* part, int* nblk, hipStream_t s) {
+  const int nb = g_grid(n);
+  *nblk = nb;
+  const dim3 g(nb), b(GWG);
+#define GF(T, A) hipLaunchKernelGGL((k_gen_family<T, A>), g, b, 0, s, n, family, eta, y, a, (T*)u_out, (A*)v_out, part)
+  if (adj_dt == DT_F64 && v_dt == DT_F64) GF(double, double);
+  else if (adj_dt == DT_F64) GF(double, float);
+  else if (adj_dt == DT_F32 && v_dt == DT_F64) GF(float, double);
+  else if (adj_dt == DT_F32) GF(float, float);
+  else if (v_dt == DT_F64) GF(bf16, double);
+  else GF(bf16, float);
+#undef GF
+  return hipGetLastError();
+}
+
+// R = V .* eta (V NULL: 1), in the chain dtype T; eta and V in the accumulation type A
+template <typename T, typename A>
+__global__ void k_gen_weight(long long n, const A* __restrict__ eta, const A* __restrict__ V, T* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const A e = V ? eta[i] * V[i] : eta[i];
+    out[i] = g_to((typename Tr<T>::acc_t)e, (T*)nullptr);
+  }
+}
+hipError_t launch_gen_weight(int dt, long long n, const void* eta, const void* V, void* out, hipStream_t s) {
+  const dim3 g(g_grid(n)), b(GWG);
+  if (dt == DT_F64) hipLaunchKernelGGL((k_gen_weight<double, double>), g, b, 0, s, n, (const double*)eta, (const double*)V, (double*)out);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_gen_weight<float, float>), g, b, 0, s, n, (const float*)eta, (const float*)V, (float*)out);
+  else hipLaunchKernelGGL((k_gen_weight<bf16, float>), g, b, 0, s, n, (const float*)eta, (const float*)V, (bf16*)out);
+  return hipGetLastError();
+}
+
+__device__ inline double g_soft(double z, double t) {
+  const double a = fabs(z) - t;
+  return a > 0.0 ? copysign(a, z) : 0.0;
+}
+
+// gradient statistics at theta (FP64): g = scale * gin; partials {max KKT residual, max |g|/w,
+// sum w (l1 |theta| + alpha theta^2)} (R6; elastic net R15; ridge R21)
+__global__ __launch_bounds__(GWG) void k_gen_grad_stats(long long p, const double* __restrict__ gin, double scale,
+                                                        const double* __restrict__ theta, const double* __restrict__ w,
+                                                        double lambda, double alpha, int no_l1, double* __restrict__ gout,
+                                                        double* __restrict__ part) {
+  double kkt = 0.0, lmax = 0.0, pen = 0.0;
+  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG) {
+    const double g = scale * gin[j], wm = w ? w[j] : 1.0, th = theta ? theta[j] : 0.0;
+    if (gout) gout[j] = g;
+    lmax = fmax(lmax, fabs(g) / wm);
+    const double lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
+    const double gs = g + 2.0 * alpha * lw * th;
+    kkt = fmax(kkt, th != 0.0 ? fabs(gs + copysign(l1w, th)) : fmax(fabs(gs) - l1w, 0.0));
+    pen += wm * ((no_l1 ? 0.0 : fabs(th)) + alpha * th * th);
+  }
+  double v[3] = {kkt, lmax, pen};
+  g_block_partials<3>(v, 3u, part);
+}
+hipError_t launch_gen_grad_stats(long long p, const double* gin, double scale, const double* theta, const double* w,
+                                 double lambda, double alpha, int no_l1, double* gout, double* part, int* nblk,
+                                 hipStream_t s) {
+  const int nb = g_grid(p);
+  *nblk = nb;
+  hipLaunchKernelGGL(k_gen_grad_stats, dim3(nb), dim3(GWG), 0, s, p, gin, scale, theta, w, lambda, alpha, no_l1, gout,
+                     part);
+  return hipGetLastError();
+}
+
+// One inner PG step (Sec. 3.2) with FISTA extrapolation on FP64 state, from the increment gradient
+// gi = G(V .* H(x - theta_ref)) (accumulation type A) of the current iterate: grad h(x^l) = gref +
+// scale gi; y = x^l + om (x^l - x^{l-1}); x^{l+1} = prox(y - delta grad h(y)); the next increment
+// x^{l+1} - theta_ref in the chain dtype T.  Partials {max KKT residual at x^l, max |scale gi|,
+// restart test sum (y - x^{l+1})(x^{l+1} - x^l), max |x^{l+1} - theta_ref|}.
+template <typename T, typename A>
+__global__ __launch_bounds__(GWG) void k_gen_prox(long long p, const A* __restrict__ gi, double scale,
+                                                  const double* __restrict__ gref, const double* __restrict__ theta_ref,
+                                                  const double* __restrict__ w, double* __restrict__ x,
+                                                  double* __restrict__ xp, double* __restrict__ gp,
+                                                  T* __restrict__ inc, double lambda, double delta, double om,
+                                                  double alpha, int no_l1, double* __restrict__ part) {
+  double kkt = 0.0, noise = 0.0, rs = 0.0, dmax = 0.0;
+  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG) {
+    const double incg = scale * (double)gi[j];
+    const double gx = gref[j] + incg;
+    const double xv = x[j], xpv = xp[j], gpv = gp[j];
+    const double wm = w ? w[j] : 1.0, lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
+    const double gs = gx + 2.0 * alpha * lw * xv;
+    kkt = fmax(kkt, xv != 0.0 ? fabs(gs + copysign(l1w, xv)) : fmax(fabs(gs) - l1w, 0.0));
+    noise = fmax(noise, fabs(incg));
+    const double gy = gx + om * (gx - gpv);
+    const double yv = xv + om * (xv - xpv);
+    const double xn = g_soft(yv - delta * gy, delta * l1w) / (1.0 + 2.0 * alpha * delta * lw);
+    xp[j] = xv;
+    x[j] = xn;
+    gp[j] = gx;
+    rs += (yv - xn) * (xn - xv);
+    const double dn = xn - theta_ref[j];
+    dmax = fmax(dmax, fabs(dn));
+    inc[j] = g_to((typename Tr<T>::acc_t)dn, (T*)nullptr);
+  }
+  double v[4] = {kkt, noise, rs, dmax};
+  g_block_partials<4>(v, 1u | 2u | 8u, part);
+}
+hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, const double* gref,
+                           const double* theta_ref, const double* w, double* x, double* xp, double* gp, void* inc,
+                           double lambda, double delta, double om, double alpha, int no_l1, double* part, int* nblk,
+                           hipStream_t s) {
+  const int nb = g_grid(p);
+  *nblk = nb;
+  const dim3 g(nb), b(GWG);
+  if (dt == DT_F64)
+    hipLaunchKernelGGL((k_gen_prox<double, double>), g, b, 0, s, p, (const double*)gi, scale, gref, theta_ref, w, x, xp, gp,
+                       (double*)inc, lambda, delta, om, alpha, no_l1, part);
+  else if (dt == DT_F32)
+    hipLaunchKernelGGL((k_gen_prox<float, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, x, xp, gp,
+                       (float*)inc, lambda, delta, om, alpha, no_l1, part);
+  else
+    hipLaunchKernelGGL((k_gen_prox<bf16, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, x, xp, gp,
+                       (bf16*)inc, lambda, delta, om, alpha, no_l1, part);
+  return hipGetLastError();
+}
+
+// The same step with the sufficient-decrease control of nu < 1 (Sec. 6.4): the state of the step
+// (x^l, x^{l-1}, grad h(x^{l-1}), y_{l-1}, grad h(y_{l-1})) is read from one set of buffers and the
+// next state written to another, so that a rejected step can be redone from y_{l-1}.  Partials
+// {max KKT residual at x^l, max |scale gi|, (x^l - y)^T (grad h(x^l) - grad h(y)),
+// |x^l - y|^2}: for the quadratic h the test of the step into x^l is the first <= the second / delta.
+template <typename T, typename A>
+__global__ __launch_bounds__(GWG) void k_gen_prox_bt(long long p, const A* __restrict__ gi, double scale,
+                                                     const double* __restrict__ gref,
+                                                     const double* __restrict__ theta_ref,
+                                                     const double* __restrict__ w, GenBtState cur, GenBtState nxt,
+                                                     T* __restrict__ inc, double lambda, double delta, double om,
+                                                     double alpha, int no_l1, double* __restrict__ part) {
+  double kkt = 0.0, noise = 0.0, sdg = 0.0, sdd = 0.0;
+  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG) {
+    const double incg = scale * (double)gi[j];
+    const double gx = gref[j] + incg;
+    const double xv = cur.x[j], xpv = cur.xp[j], gpv = cur.gp[j];
+    const double dy = xv - cur.y[j];
+    sdg += dy * (gx - cur.gy[j]);
+    sdd += dy * dy;
+    const double wm = w ? w[j] : 1.0, lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
+    const double gs = gx + 2.0 * alpha * lw * xv;
+    kkt = fmax(kkt, xv != 0.0 ? fabs(gs + copysign(l1w, xv)) : fmax(fabs(gs) - l1w, 0.0));
+    noise = fmax(noise, fabs(incg));
+    const double gy = gx + om * (gx - gpv);
+    const double yv = xv + om * (xv - xpv);
+    const double xn = g_soft(yv - delta * gy, delta * l1w) / (1.0 + 2.0 * alpha * delta * lw);
+    nxt.x[j] = xn;
+    nxt.xp[j] = xv;
+    nxt.gp[j] = gx;
+    nxt.y[j] = yv;
+    nxt.gy[j] = gy;
+    inc[j] = g_to((typename Tr<T>::acc_t)(xn - theta_ref[j]), (T*)nullptr);
+  }
+  double v[4] = {kkt, noise, sdg, sdd};
+  g_block_partials<4>(v, 1u | 2u, part);
+}
+hipError_t launch_gen_prox_bt(int dt, long long p, const void* gi, double scale, const double* gref,
+                              const double* theta_ref, const double* w, const GenBtState& cur, const GenBtState& nxt,
+                              void* inc, double lambda, double delta, double om, double alpha, int no_l1, double* part,
+                              int* nblk, hipStream_t s) {
+  const int nb = g_grid(p);
+  *nblk = nb;
+  const dim3 g(nb), b(GWG);
+  if (dt == DT_F64)
+    hipLaunchKernelGGL((k_gen_prox_bt<double, double>), g, b, 0, s, p, (const double*)gi, scale, gref, theta_ref, w, cur,
+                       nxt, (double*)inc, lambda, delta, om, alpha, no_l1, part);
+  else if (dt == DT_F32)
+    hipLaunchKernelGGL((k_gen_prox_bt<float, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, cur,
+                       nxt, (float*)inc, lambda, delta, om, alpha, no_l1, part);
+  else
+    hipLaunchKernelGGL((k_gen_prox_bt<bf16, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, cur,
+                       nxt, (bf16*)inc, lambda, delta, om, alpha, no_l1, part);
+  return hipGetLastError();
+}
+
+// redo of a rejected step with the halved delta: x = prox(y - delta grad h(y)), inc = x - theta_ref
+template <typename T>
+__global__ void k_gen_bt_redo(long long p, const double* __restrict__ y, const double* __restrict__ gy,
+                              const double* __restrict__ w, const double* __restrict__ theta_ref, double lambda,
+                              double delta, double alpha, int no_l1, double* __restrict__ x, T* __restrict__ inc) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < p; j += (long long)gridDim.x * blockDim.x) {
+    const double wm = w ? w[j] : 1.0, lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
+    const double xn = g_soft(y[j] - delta * gy[j], delta * l1w) / (1.0 + 2.0 * alpha * delta * lw);
+    x[j] = xn;
+    inc[j] = g_to((typename Tr<T>::acc_t)(xn - theta_ref[j]), (T*)nullptr);
+  }
+}
+hipError_t launch_gen_bt_redo(int dt, long long p, const double* y, const double* gy, const double* w,
+                              const double* theta_ref, double lambda, double delta, double alpha, int no_l1, double* x,
+                              void* inc, hipStream_t s) {
+  const dim3 g(g_grid(p)), b(GWG);
+  if (dt == DT_F64)
+    hipLaunchKernelGGL(k_gen_bt_redo<double>, g, b, 0, s, p, y, gy, w, theta_ref, lambda, delta, alpha, no_l1, x, (double*)inc);
+  else if (dt == DT_F32)
+    hipLaunchKernelGGL(k_gen_bt_redo<float>, g, b, 0, s, p, y, gy, w, theta_ref, lambda, delta, alpha, no_l1, x, (float*)inc);
+  else
+    hipLaunchKernelGGL(k_gen_bt_redo<bf16>, g, b, 0, s, p, y, gy, w, theta_ref, lambda, delta, alpha, no_l1, x, (bf16*)inc);
+  return hipGetLastError();
+}
+
+}  // namespace glam

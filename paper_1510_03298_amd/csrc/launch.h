@@ -21,6 +21,7 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 namespace glam {
 
@@ -348,6 +349,61 @@ hipError_t launch_scad_weights(long long p, const double* theta, const double* b
                                hipStream_t s);
 hipError_t launch_check(long long n, const double* y, const double* a, long long p, const double* pen_w, int family,
                         double* partials, int* nblk_out, hipStream_t s);
+
+// ---- generic rho GEMMs and the elementwise steps on standard layouts (general.hip) ----
+// C[m + ldc n] (+)= sum_k A[k + lda m] B[k + ldb n] (m < M, n < N, k < K) on the matrix cores,
+// operands in dtype dt; out_kind 0: C in dt, 1: C in the accumulation type (FP32 for BF16/F32,
+// FP64 for F64); acc: add into C.
+hipError_t launch_rho_gemm(int dt, int out_kind, bool acc, long long M, long long N, long long K, const void* A,
+                           long long lda, const void* B, long long ldb, void* C, long long ldc, hipStream_t s);
+// eta (+)= H(X, Theta) by three GEMMs in the cyclic mode order; XT[j] = X_j^T (p_j x n_j, k-contiguous)
+// in dt; t1, t2: >= general_tmp_elems elements of dt; eta in the accumulation type
+hipError_t general_forward(int dt, const int64_t* n, const int64_t* p, const void* const* XT, const void* theta,
+                           void* t1, void* t2, void* eta, bool acc, hipStream_t s);
+// out = G(X, U); X[j] n_j x p_j in dt; out in the accumulation type
+hipError_t general_adjoint(int dt, const int64_t* n, const int64_t* p, const void* const* X, const void* u, void* t1,
+                           void* t2, void* out, hipStream_t s);
+long long general_tmp_elems(const int64_t* n, const int64_t* p);
+// dst = src (FP64) in dt; out = X^T (n x p FP64 -> p x n in dt)
+hipError_t launch_gen_pack(int dt, long long count, const double* src, void* dst, hipStream_t s);
+hipError_t launch_gen_transpose(int dt, long long nr, long long pc, const double* X, void* out, hipStream_t s);
+// the same for X already in dt
+hipError_t launch_gen_transpose_same(int dt, long long nr, long long pc, const void* X, void* out, hipStream_t s);
+// family step on FP64 eta: u (adj_dt), weights (v_dt, optional), partials {sum -l, max w}
+hipError_t launch_gen_family(int adj_dt, int v_dt, long long n, int family, const double* eta, const double* y,
+                             const double* a, void* u_out, void* v_out, double* part, int* nblk, hipStream_t s);
+// out = V .* eta in dt (eta, V in the accumulation type; V NULL: 1)
+hipError_t launch_gen_weight(int dt, long long n, const void* eta, const void* V, void* out, hipStream_t s);
+// g = scale gin (FP64); partials {max KKT residual, max |g|/w, sum w (l1 |theta| + alpha theta^2)}
+hipError_t launch_gen_grad_stats(long long p, const double* gin, double scale, const double* theta, const double* w,
+                                 double lambda, double alpha, int no_l1, double* gout, double* part, int* nblk,
+                                 hipStream_t s);
+// one inner step in place (x^{l-1} <- x^l, x^l <- x^{l+1}, gp <- grad h(x^l)), inc = x^{l+1} - theta_ref in dt;
+// partials {max KKT at x^l, max |scale gi|, restart test sum, max |x^{l+1} - theta_ref|}
+hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, const double* gref,
+                           const double* theta_ref, const double* w, double* x, double* xp, double* gp, void* inc,
+                           double lambda, double delta, double om, double alpha, int no_l1, double* part, int* nblk,
+                           hipStream_t s);
+struct GenBtState {
+  double* x;    // x^l
+  double* xp;   // x^{l-1}
+  double* gp;   // grad h(x^{l-1})
+  double* y;    // y_{l-1}, the point the step into x^l started from
+  double* gy;   // grad h(y_{l-1})
+};
+hipError_t launch_gen_prox_bt(int dt, long long p, const void* gi, double scale, const double* gref,
+                              const double* theta_ref, const double* w, const GenBtState& cur, const GenBtState& nxt,
+                              void* inc, double lambda, double delta, double om, double alpha, int no_l1, double* part,
+                              int* nblk, hipStream_t s);
+hipError_t launch_gen_bt_redo(int dt, long long p, const double* y, const double* gy, const double* w,
+                              const double* theta_ref, double lambda, double delta, double alpha, int no_l1, double* x,
+                              void* inc, hipStream_t s);
+constexpr int kGenMaxBlocks = 4096;   // workgroups of the generic elementwise kernels (rows of partials)
+
+// Gram matrix X^T X of a host n x p column-major matrix, and the largest eigenvalue of a
+// symmetric p x p matrix (Proposition 1's spectral radii), both on the host (fit.cpp)
+std::vector<double> gram_matrix(const double* X, int n, int p);
+double gram_spectral_radius(std::vector<double> A, int p);
 
 constexpr int kArmijoMaxBlocks = 2048;     // workgroups of k_armijo (rows of trial partials)
 constexpr int kPenTrialsMaxBlocks = 256;   // workgroups of k_pen_trials

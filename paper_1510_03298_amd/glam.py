@@ -50,6 +50,11 @@ class GlamOptions(ctypes.Structure):
                 ("extrapolation", ctypes.c_int), ("kron_step", ctypes.c_int)]
 
 
+class GlamMultiProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("c", ctypes.c_int), ("p", _i64p),
+                ("X", ctypes.POINTER(_vp)), ("Y", _vp), ("obs_w", _vp), ("family", ctypes.c_int), ("pen_w", _vp)]
+
+
 class GlamResult(ctypes.Structure):
     _fields_ = [("theta", _vp), ("lambda_out", ctypes.POINTER(ctypes.c_double)),
                 ("kkt", ctypes.POINTER(ctypes.c_double)), ("objective", ctypes.POINTER(ctypes.c_double)),
@@ -97,6 +102,8 @@ glam_rho_adjoint = _sig("glam_rho_adjoint", ctypes.c_int,
                          ctypes.c_size_t, _vp])
 glam_fit_path = _sig("glam_fit_path", ctypes.c_int,
                      [ctypes.POINTER(GlamProblem), ctypes.POINTER(GlamOptions), ctypes.POINTER(GlamResult)])
+glam_fit_path_multi = _sig("glam_fit_path_multi", ctypes.c_int,
+                           [ctypes.POINTER(GlamMultiProblem), ctypes.POINTER(GlamOptions), ctypes.POINTER(GlamResult)])
 glam_fit_batched = _sig("glam_fit_batched", ctypes.c_int,
                         [ctypes.POINTER(GlamProblem), ctypes.c_int, ctypes.POINTER(GlamBatchOptions),
                          ctypes.POINTER(GlamBatchResult)])
@@ -117,7 +124,7 @@ glam_poisson_nll_backward_packed = _sig("glam_poisson_nll_backward_packed", ctyp
                                         [_i64p, _i64p, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp])
 
 EXPORTED = ["glam_status_string", "glam_last_error", "glam_version", "glam_rho_workspace_size",
-            "glam_rho_forward", "glam_rho_forward_static", "glam_rho_adjoint", "glam_fit_path", "glam_fit_batched", "glam_nll_workspace_size",
+            "glam_rho_forward", "glam_rho_forward_static", "glam_rho_adjoint", "glam_fit_path", "glam_fit_path_multi", "glam_fit_batched", "glam_nll_workspace_size",
             "glam_poisson_nll_forward", "glam_poisson_nll_backward", "glam_nll_packed_workspace_size",
             "glam_poisson_nll_pack", "glam_poisson_nll_forward_packed", "glam_poisson_nll_backward_packed"]
 
@@ -367,31 +374,12 @@ class PathResult:
     fwd_ms: float = 0.0      # ... and of the mode-3 forward kernel
 
 
-def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
-             lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
-             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
-             graph=True, inner="chain", alpha=0.0, penalty="lasso", scad_a=3.7, msa_steps=3,
-             extrapolation="restarted", kron_step="prop1") -> PathResult:
-    """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
-    1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
-    alpha: elastic-net weight (0 = lasso); penalty="scad": SCAD by msa_steps steps of
-    the multi-step adaptive lasso per lambda.  extrapolation: "restarted" (omega_l counted from
-    the last gradient restart at a check) or "plain" (omega_l = (l-1)/(l+2) through each inner loop)."""
-    torch = _torch()
-    fam = FAMILIES[family] if isinstance(family, str) else int(family)
-    prob = GlamProblem()
-    prob.d = len(n)
-    for j in range(len(n)):
-        prob.n[j] = int(n[j])
-        prob.p[j] = int(p[j])
-        prob.X[j] = Xs[j].data_ptr()
-    prob.Y = Y.data_ptr()
-    prob.obs_w = obs_w.data_ptr() if obs_w is not None else None
-    prob.family = fam
-    prob.pen_w = pen_w.data_ptr() if pen_w is not None else None
+def _path_options(lambdas, nlambda, lambda_min_ratio, dtype, kkt_tol, nu, max_outer, max_inner, check_every,
+                  theta0, stream, profile_every, graph, inner, alpha, penalty, scad_a, msa_steps, extrapolation,
+                  kron_step):
     L = int(nlambda if lambdas is None else len(lambdas))
-    lam_arr = None
     opt = GlamOptions()
+    lam_arr = None
     if lambdas is not None:
         lam_arr = (ctypes.c_double * L)(*[float(v) for v in lambdas])
         opt.lambda_ = lam_arr
@@ -414,8 +402,12 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     opt.msa_steps = int(msa_steps)
     opt.extrapolation = {"restarted": 0, "plain": 1}[extrapolation]
     opt.kron_step = {"prop1": 0, "exact": 1}[kron_step]
-    P = int(np.prod(p))
-    theta = torch.zeros((L, P), dtype=torch.float64, device=Y.device)
+    return opt, lam_arr, L
+
+
+def _run_path(fn, where, prob, opt, L, P, device, raise_on_error):
+    torch = _torch()
+    theta = torch.zeros((L, P), dtype=torch.float64, device=device)
     lam_out = (ctypes.c_double * L)()
     kkt = (ctypes.c_double * L)()
     obj = (ctypes.c_double * L)()
@@ -426,17 +418,81 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
     res.theta = theta.data_ptr()
     res.lambda_out, res.kkt, res.objective = lam_out, kkt, obj
     res.iters_outer, res.iters_inner, res.status = io, ii, stt
-    code = glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    code = fn(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     if code == GLAM_EINVAL or code == GLAM_ENOMEM or code == GLAM_EDEVICE:
-        raise GlamError(code, "glam_fit_path")
+        raise GlamError(code, where)
     out = PathResult(np.array(lam_out[:]), theta, np.array(kkt[:]), np.array(obj[:]), np.array(io[:]),
                      np.array(ii[:]), np.array(stt[:]), int(res.n_done), float(res.lambda_max),
                      float(res.seconds), int(code), float(res.chain_ms), int(res.chain_samples),
                      float(res.iter_ms), int(res.inner_total), int(res.escalated_at), float(res.adj_ms),
                      float(res.fwd_ms))
     if raise_on_error and code != GLAM_OK:
-        raise GlamError(code, "glam_fit_path")
+        raise GlamError(code, where)
     return out
+
+
+def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
+             lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
+             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
+             graph=True, inner="chain", alpha=0.0, penalty="lasso", scad_a=3.7, msa_steps=3,
+             extrapolation="restarted", kron_step="prop1") -> PathResult:
+    """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
+    1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
+    alpha: elastic-net weight (0 = lasso); penalty="scad": SCAD by msa_steps steps of
+    the multi-step adaptive lasso per lambda.  extrapolation: "restarted" (omega_l counted from
+    the last gradient restart at a check) or "plain" (omega_l = (l-1)/(l+2) through each inner loop)."""
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    prob = GlamProblem()
+    prob.d = len(n)
+    for j in range(len(n)):
+        prob.n[j] = int(n[j])
+        prob.p[j] = int(p[j])
+        prob.X[j] = Xs[j].data_ptr()
+    prob.Y = Y.data_ptr()
+    prob.obs_w = obs_w.data_ptr() if obs_w is not None else None
+    prob.family = fam
+    prob.pen_w = pen_w.data_ptr() if pen_w is not None else None
+    opt, lam_arr, L = _path_options(lambdas, nlambda, lambda_min_ratio, dtype, kkt_tol, nu, max_outer, max_inner,
+                                    check_every, theta0, stream, profile_every, graph, inner, alpha, penalty, scad_a,
+                                    msa_steps, extrapolation, kron_step)
+    return _run_path(glam_fit_path, "glam_fit_path", prob, opt, L, int(np.prod(p)), Y.device, raise_on_error)
+
+
+def fit_path_multi(components, Y, n, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
+                   lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
+                   check_every=10, theta0=None, stream=None, raise_on_error=True, inner="chain", alpha=0.0,
+                   penalty="lasso", scad_a=3.7, msa_steps=3, extrapolation="restarted") -> PathResult:
+    """GD-PG lambda path of a c-component model X = [X_1 | ... | X_c] (Sec. 2): components is a
+    list of (Xs_r, p_r), Xs_r the d FP64 device factors of component r and p_r its d sizes;
+    theta rows hold (vec(Theta_1), ..., vec(Theta_c)).  Other arguments as fit_path."""
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    d = len(n)
+    c = len(components)
+    prob = GlamMultiProblem()
+    prob.d = d
+    for j in range(d):
+        prob.n[j] = int(n[j])
+    prob.c = c
+    p_arr = (ctypes.c_int64 * (3 * c))()
+    x_arr = (_vp * (3 * c))()
+    P = 0
+    for r, (Xs_r, p_r) in enumerate(components):
+        if len(Xs_r) != d or len(p_r) != d:
+            raise ValueError("every component needs d factors and d sizes")
+        for j in range(d):
+            p_arr[3 * r + j] = int(p_r[j])
+            x_arr[3 * r + j] = Xs_r[j].data_ptr()
+        P += int(np.prod(p_r))
+    prob.p = p_arr
+    prob.X = x_arr
+    prob.Y = Y.data_ptr()
+    prob.obs_w = obs_w.data_ptr() if obs_w is not None else None
+    prob.family = fam
+    prob.pen_w = pen_w.data_ptr() if pen_w is not None else None
+    opt, lam_arr, L = _path_options(lambdas, nlambda, lambda_min_ratio, dtype, kkt_tol, nu, max_outer, max_inner,
+                                    check_every, theta0, stream, 0, True, inner, alpha, penalty, scad_a, msa_steps,
+                                    extrapolation, "prop1")
+    return _run_path(glam_fit_path_multi, "glam_fit_path_multi", prob, opt, L, P, Y.device, raise_on_error)
 
 
 # ----------------------------------------------------------------------------- batched fits

@@ -72,9 +72,12 @@ def test_workspace_size_and_limits():
     n2, p2 = _sizes((300, 50, 0), (30, 20, 0))
     w_re = glam.glam_rho_workspace_size(2, n2, p2, glam.F32)
     assert w_re >= 300 * 50 * 8
+    # only one mode with p <= 32: no order fits the slab kernels, the generic GEMM chain runs;
+    # its workspace holds X_j^T and two intermediates of the largest partial product
     n, p = _sizes((100, 100, 1000), (33, 30, 200))
-    assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # only one mode with p <= 32
-    assert b"every order" in glam.glam_last_error()
+    tmp = max(30 * 200 * 100, 200 * 100 * 100, 100 * 1000 * 33, 1000 * 33 * 30)
+    w_gen = glam.glam_rho_workspace_size(3, n, p, glam.F32)
+    assert w_gen >= 2 * tmp * 4 + (100 * 33 + 100 * 30 + 1000 * 200) * 4
     n, p = _sizes((0, 100, 1000), (3, 3, 3))
     assert glam.glam_rho_workspace_size(3, n, p, glam.F32) == 0          # empty mode
     n, p = _sizes((256, 256, 10), (32, 32, 3))
@@ -82,8 +85,9 @@ def test_workspace_size_and_limits():
     # FP64 copies of X1, X2 exceed the LDS budget in this order; (256, 10, 256) fits
     assert glam.glam_rho_workspace_size(3, n, p, glam.F64) > glam.glam_rho_workspace_size(3, n, p, glam.F32)
     n, p = _sizes((256, 256, 256), (32, 32, 32))
-    assert glam.glam_rho_workspace_size(3, n, p, glam.F64) == 0          # no order fits the FP64 LDS budget
-    assert b"LDS" in glam.glam_last_error()
+    # no order fits the FP64 LDS budget: the generic chain (FP32 still takes the slab kernels)
+    w_gen = glam.glam_rho_workspace_size(3, n, p, glam.F64)
+    assert w_gen >= 2 * (256 * 256 * 32) * 8
 
 
 def test_invalid_arguments_rejected_without_device_work():
@@ -154,9 +158,10 @@ def test_invalid_arguments_rejected_without_device_work():
         assert rc == glam.GLAM_EINVAL and b"alpha" in glam.glam_last_error()
 
 
-def test_no_mode_order_fits_is_rejected_on_the_host():
+def test_no_mode_order_fits_refuses_the_gram_forms_on_the_host():
     """When no order of the three modes puts two of them within the slab kernels' limits
-    (p <= 32), the fit is refused before any device work."""
+    (p <= 32), the fit runs on the generic GEMM solver, which has no Gram inner forms: those
+    are refused before any device work."""
     from paper_1510_03298_amd import glam
     prob = glam.GlamProblem()
     prob.d = 3
@@ -174,8 +179,55 @@ def test_no_mode_order_fits_is_rejected_on_the_host():
     res.theta = ctypes.addressof(dummy)
     res.lambda_out = res.kkt = res.objective = out
     res.iters_outer = res.iters_inner = res.status = io
+    opt.inner_mode = 1   # Gram form
     rc = glam.glam_fit_path(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     assert rc == glam.GLAM_EINVAL and b"order of the modes" in glam.glam_last_error()
+
+
+def test_multi_component_entry_point_refuses_bad_arguments_on_the_host():
+    """glam_fit_path_multi: sizes, pointers and options are checked before any device work."""
+    from paper_1510_03298_amd import glam
+    dummy = ctypes.c_double(0.0)
+    ptr = ctypes.addressof(dummy)
+    opt = glam.GlamOptions()
+    opt.nlambda, opt.lambda_min_ratio, opt.dtype = 2, 0.1, glam.F64
+    opt.kkt_tol, opt.nu, opt.max_outer, opt.max_inner, opt.check_every = 1e-6, 1.0, 10, 10, 1
+    res = glam.GlamResult()
+    out = (ctypes.c_double * 2)()
+    io = (ctypes.c_int * 2)()
+    res.theta = ptr
+    res.lambda_out = res.kkt = res.objective = out
+    res.iters_outer = res.iters_inner = res.status = io
+    pa = (ctypes.c_int64 * 6)(3, 4, 2, 2, 2, 5)
+    xa = (ctypes.c_void_p * 6)(*([ptr] * 6))
+
+    def prob(c=2, d=3, p=pa, X=xa, family=0, Y=ptr):
+        pr = glam.GlamMultiProblem()
+        pr.d, pr.c, pr.family, pr.Y = d, c, family, Y
+        for j in range(3):
+            pr.n[j] = 10
+        pr.p, pr.X = p, X
+        return pr
+
+    def call(pr, o=opt):
+        return glam.glam_fit_path_multi(ctypes.byref(pr), ctypes.byref(o), ctypes.byref(res))
+
+    assert glam.glam_fit_path_multi(None, None, None) == glam.GLAM_EINVAL
+    assert call(prob(c=0)) == glam.GLAM_EINVAL and b"c must be" in glam.glam_last_error()
+    assert call(prob(d=4)) == glam.GLAM_EINVAL
+    assert call(prob(p=None)) == glam.GLAM_EINVAL and b"NULL" in glam.glam_last_error()
+    assert call(prob(Y=None)) == glam.GLAM_EINVAL
+    assert call(prob(family=9)) == glam.GLAM_EINVAL and b"family" in glam.glam_last_error()
+    bad_p = (ctypes.c_int64 * 6)(3, 0, 2, 2, 2, 5)
+    assert call(prob(p=bad_p)) == glam.GLAM_EINVAL and b"sizes" in glam.glam_last_error()
+    bad_x = (ctypes.c_void_p * 6)(ptr, ptr, ptr, ptr, None, ptr)
+    assert call(prob(X=bad_x)) == glam.GLAM_EINVAL and b"NULL factor" in glam.glam_last_error()
+    gram = glam.GlamOptions.from_buffer_copy(opt)
+    gram.inner_mode = 1
+    assert call(prob(), gram) == glam.GLAM_EINVAL and b"rho-chain" in glam.glam_last_error()
+    neg = glam.GlamOptions.from_buffer_copy(opt)
+    neg.nu = 1.5
+    assert call(prob(), neg) == glam.GLAM_EINVAL and b"nu" in glam.glam_last_error()
 
 
 def test_packed_nll_workspace_and_argument_checks():

@@ -148,10 +148,12 @@ def test_full_size_gaussian_workload_sampled(dt):
 
 
 def test_invalid_sizes_raise():
-    """No order of the modes fits (every p_j > 32): refused on the host, before any device work
-    (the dummy operands are never read)."""
+    """Sizes refused on the host (an empty mode, a mode beyond 2^30 entries), before any device
+    work: the workspace query returns 0 and the binding raises (the dummy operands are never read).
+    Designs that fit no mode order of the slab kernels are valid: they run on the generic chain."""
     torch, glam = need_gpu()
-    n, p = (300, 300, 300), (40, 40, 40)
-    with pytest.raises(glam.GlamError):
-        glam.rho_forward([torch.zeros(1, device="cuda", dtype=torch.float64)] * 3,
-                         torch.zeros(64, device="cuda", dtype=torch.float64), n, p, 0)
+    for n, p in [((0, 5, 5), (1, 2, 3)), ((5, 5, 5), (2, 0, 3)), ((2 ** 31, 1, 1), (1, 1, 1))]:
+        assert glam.rho_workspace_size(n, p, 0) == 0
+        with pytest.raises(glam.GlamError):
+            glam.rho_forward([torch.zeros(1, device="cuda", dtype=torch.float64)] * 3,
+                             torch.zeros(64, device="cuda", dtype=torch.float64), n, p, 0)
