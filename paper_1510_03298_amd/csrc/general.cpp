@@ -69,6 +69,8 @@ struct GFit {
   const double* pen = nullptr;
   void *t1d = nullptr, *t2d = nullptr, *t1 = nullptr, *t2 = nullptr;   // GEMM intermediates
   void *etai = nullptr, *R = nullptr, *V = nullptr, *gi = nullptr, *inc = nullptr;
+  float* dst[3] = {nullptr, nullptr, nullptr};   // FP32 increment state (BF16/FP32 chains, nu = 1)
+  float* qst = nullptr;
   bool use_v = false;
   double enet = 0.0;
   int no_l1 = 0;
@@ -155,14 +157,18 @@ int family_step(GFit& F, const double* theta, double lambda, Stats* st) {
   return GLAM_OK;
 }
 
-// gi = G(V .* H(inc)) in the chain dtype (accumulation-type output)
+// gi = G(V .* H(inc)) in the chain dtype (accumulation-type output); the last component's forward
+// chain writes R = V .* (its product + the other components' sum) directly in the chain dtype
 int inner_gradient(GFit& F) {
   const size_t es = dt_size(F.dt), as = acc_size(F.dt);
-  for (size_t r = 0; r < F.comp.size(); ++r) {
-    const Comp& c = F.comp[r];
-    GCHK(general_forward(F.dt, F.n, c.p, c.XTc, (const char*)F.inc + c.off * es, F.t1, F.t2, F.etai, r > 0, F.s));
+  const size_t c = F.comp.size();
+  for (size_t r = 0; r + 1 < c; ++r) {
+    const Comp& cr = F.comp[r];
+    GCHK(general_forward(F.dt, F.n, cr.p, cr.XTc, (const char*)F.inc + cr.off * es, F.t1, F.t2, F.etai, r > 0, F.s));
   }
-  GCHK(launch_gen_weight(F.dt, F.N, F.etai, F.use_v ? F.V : nullptr, F.R, F.s));
+  const Comp& cl = F.comp[c - 1];
+  GCHK(general_forward_weighted(F.dt, F.n, cl.p, cl.XTc, (const char*)F.inc + cl.off * es, F.t1, F.t2,
+                                c > 1 ? F.etai : nullptr, F.use_v ? F.V : nullptr, F.R, F.s));
   for (const Comp& c : F.comp)
     GCHK(general_adjoint(F.dt, F.n, c.p, c.Xc, F.R, F.t1, F.t2, (char*)F.gi + c.off * as, F.s));
   return GLAM_OK;
@@ -177,12 +183,21 @@ int read_red(GFit& F, int nb, int nval, const int* ops, double* out) {
 }
 
 // Inner PG loop with nu = 1 (delta = 1/Lhat fixed).  Leaves theta~ = x^l of the last checked
-// iteration in F.xp.
+// iteration in F.xp.  BF16/FP32 chains keep the state as FP32 increments (k_gen_prox_inc), FP64
+// chains in FP64 (k_gen_prox).
 int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scale, int max_inner, int check_every,
                bool restart, bool exact_model, int* it_out, double* kin_out) {
-  GCHK(hipMemcpyAsync(F.x, F.theta, F.P * 8, hipMemcpyDeviceToDevice, F.s));
-  GCHK(hipMemcpyAsync(F.xp, F.theta, F.P * 8, hipMemcpyDeviceToDevice, F.s));
-  GCHK(hipMemcpyAsync(F.gp, F.gref, F.P * 8, hipMemcpyDeviceToDevice, F.s));
+  const bool incst = F.dt != DT_F64;
+  float* d[3] = {F.dst[0], F.dst[1], F.dst[2]};   // d^l, d^{l-1}, the next
+  if (incst) {
+    GCHK(hipMemsetAsync(d[0], 0, F.P * 4, F.s));
+    GCHK(hipMemsetAsync(d[1], 0, F.P * 4, F.s));
+    GCHK(hipMemsetAsync(F.qst, 0, F.P * 4, F.s));
+  } else {
+    GCHK(hipMemcpyAsync(F.x, F.theta, F.P * 8, hipMemcpyDeviceToDevice, F.s));
+    GCHK(hipMemcpyAsync(F.xp, F.theta, F.P * 8, hipMemcpyDeviceToDevice, F.s));
+    GCHK(hipMemcpyAsync(F.gp, F.gref, F.P * 8, hipMemcpyDeviceToDevice, F.s));
+  }
   GCHK(hipMemsetAsync(F.inc, 0, F.P * dt_size(F.dt), F.s));
   int it = 0, l = 0, window_start = 0;
   double kin = INFINITY, best = INFINITY, window_best = INFINITY;
@@ -193,8 +208,17 @@ int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scal
     int r = inner_gradient(F);
     if (r) return r;
     int nb = 0;
-    GCHK(launch_gen_prox(F.dt, F.P, F.gi, 1.0 / (double)F.N, F.gref, F.theta, F.pen, F.x, F.xp, F.gp, F.inc, lam,
-                         delta, om, F.enet, F.no_l1, F.part, &nb, F.s));
+    if (incst) {
+      GCHK(launch_gen_prox_inc(F.dt, F.P, F.gi, 1.0 / (double)F.N, F.gref, F.theta, F.pen, d[0], d[1], F.qst, d[2],
+                               F.inc, lam, delta, om, F.enet, F.no_l1, F.part, &nb, F.s));
+      float* t = d[1];
+      d[1] = d[0];
+      d[0] = d[2];
+      d[2] = t;
+    } else {
+      GCHK(launch_gen_prox(F.dt, F.P, F.gi, 1.0 / (double)F.N, F.gref, F.theta, F.pen, F.x, F.xp, F.gp, F.inc, lam,
+                           delta, om, F.enet, F.no_l1, F.part, &nb, F.s));
+    }
     ++it;
     if (it % check_every != 0 && it < max_inner) continue;
     double v[4];
@@ -213,6 +237,7 @@ int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scal
     if (!std::isfinite(kin)) break;
     if (kin <= std::max(tol_in, noise)) break;
   }
+  if (incst) GCHK(launch_gen_inc_out(F.P, d[1], F.theta, 0, F.xp, F.s));   // theta~ = x^l
   *it_out = it;
   *kin_out = kin;
   return GLAM_OK;
@@ -371,6 +396,8 @@ int setup(GFit& F, const GenProblem& prob, int dtype, bool bt) {
   if (F.use_v) F.V = A(nb8);
   if (bt)
     for (double*& b : F.bt) b = (double*)A(pb8);
+  else
+    for (int q = 0; q < 4; ++q) (q < 3 ? F.dst[q] : F.qst) = (float*)A((size_t)F.P * 4);
   if (!F.a) F.ones = (double*)A(nb8);
   if (!ok) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
   if (hipHostMalloc((void**)&F.hred, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {

@@ -33,71 +33,139 @@ __device__ inline double g_val(double v) { return v; }
 __device__ inline float g_val(float v) { return v; }
 __device__ inline float g_val(bf16 v) { return bf16_to_f32(v.u); }
 
-// C[m + ldc n] (+)= sum_k A[k + lda m] B[k + ldb n], m < M, n < N, k < K; one 32 x 32 output tile
-// per workgroup.  T: operand type; TO: output type (T for the intermediate steps, the
-// accumulation type for the last); ACC: add to C (the components of a c > 1 model).
-template <typename T, typename TO, bool ACC>
+// C[m + ldc n] = (sum_k A[k + lda m] B[k + ldb n] (+ Cadd[m + ldc n])) (* Vmul[m + ldc n]) for
+// m < M, n < N, k < K.  One 64 x 64 output tile per workgroup, each wave a 32 x 32 block of 2 x 2
+// matrix-core tiles.  The operands go through LDS in 32-deep k-slices: consecutive lanes load
+// consecutive k of one column (both operands are k-contiguous), so a wave's load is two
+// contiguous 32-element runs; the next slice is requested into registers while the current one
+// is multiplied.  The output tile is transposed through LDS so that each column's 64 rows are
+// stored by 64 consecutive lanes.  T: operand type; TO: output type (T for the intermediate steps
+// and the weighted output, the accumulation type AT otherwise); ADD: add Cadd (AT, may be C itself:
+// the components of a c > 1 model); VMUL: multiply by Vmul (AT: the IRLS weights).
+constexpr int GBM = 64, GBN = 64, GKT = 32, GLDK = GKT + 2;
+template <typename T>
+__host__ __device__ constexpr int gemm_lds_bytes() {
+  return (GBM + GBN) * GLDK * (int)sizeof(T) > GBN * (GBM + 1) * (int)sizeof(typename Tr<T>::acc_t)
+             ? (GBM + GBN) * GLDK * (int)sizeof(T)
+             : GBN * (GBM + 1) * (int)sizeof(typename Tr<T>::acc_t);
+}
+
+template <typename T, typename TO, bool ADD, bool VMUL>
 __global__ __launch_bounds__(GWG) void k_rho_gemm(long long M, long long N, long long K, const T* __restrict__ A,
                                                   long long lda, const T* __restrict__ B, long long ldb,
-                                                  TO* __restrict__ C, long long ldc) {
+                                                  TO* C, long long ldc, const typename Tr<T>::acc_t* Cadd,
+                                                  const typename Tr<T>::acc_t* __restrict__ Vmul) {
   typedef Tr<T> R;
   typedef typename R::frag_t F;
-  const int lane = g_lane(), r = lane & 15, g = lane >> 4, w = g_wave();
-  const long long m = (long long)blockIdx.x * 32 + 16 * (w & 1) + r;   // A column (output row)
-  const long long nn = (long long)blockIdx.y * 32 + 16 * (w >> 1) + r; // B column (output column)
-  const bool am = m < M, bn = nn < N;
-  typename R::accv_t acc = R::zero();
-  const T* pa = A + (am ? m : 0) * lda;
-  const T* pb = B + (bn ? nn : 0) * ldb;
+  typedef typename R::acc_t AT;
+  constexpr int NLD = GBM * GKT / GWG;   // elements of each operand slice per thread
+  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T>()];
+  T* As = (T*)smem;
+  T* Bs = As + GBM * GLDK;
+  const int tid = threadIdx.x, lane = tid & 63, r = lane & 15, g = lane >> 4, w = tid >> 6;
+  const long long m0 = (long long)blockIdx.x * GBM, n0 = (long long)blockIdx.y * GBN;
   const T z = zero_val<T>();
-  for (long long k0 = 0; k0 < K; k0 += 16) {
-    T a4[4], b4[4];
+  T ra[NLD], rb[NLD];
+  // element e = tid + GWG j of a slice: column e / GKT of the tile, contraction index e % GKT
+  auto load = [&](long long k0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const long long k = k0 + R::kidx(g, t);
-      const bool in = k < K;
-      a4[t] = (in && am) ? pa[k] : z;
-      b4[t] = (in && bn) ? pb[k] : z;
+    for (int j = 0; j < NLD; ++j) {
+      const int e = tid + GWG * j, c = e / GKT, kk = e % GKT;
+      const long long k = k0 + kk;
+      ra[j] = (m0 + c < M && k < K) ? A[(m0 + c) * lda + k] : z;
+      rb[j] = (n0 + c < N && k < K) ? B[(n0 + c) * ldb + k] : z;
     }
-    const F fa = raw_frag<T>(a4[0], a4[1], a4[2], a4[3]);
-    const F fb = raw_frag<T>(b4[0], b4[1], b4[2], b4[3]);
-    mma(acc, fa, fb);
-  }
-  // lane (r, g), register i: output row kidx(g, i) of this wave's tile, column r
-  const long long mb = (long long)blockIdx.x * 32 + 16 * (w & 1);
-  if (!bn) return;
+  };
+  typename R::accv_t acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const long long mo = mb + R::kidx(g, i);
-    if (mo >= M) continue;
-    TO* dst = C + mo + ldc * nn;
-    if (ACC) *dst = g_to((typename R::acc_t)(g_val(*dst) + acc[i]), (TO*)nullptr);
-    else *dst = g_to((typename R::acc_t)acc[i], (TO*)nullptr);
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = R::zero();
+  const int wm = 32 * (w & 1), wn = 32 * (w >> 1);
+  load(0);
+  for (long long k0 = 0; k0 < K; k0 += GKT) {
+    __syncthreads();   // the previous slice's fragments have been read
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int e = tid + GWG * j, c = e / GKT, kk = e % GKT;
+      As[c * GLDK + kk] = ra[j];
+      Bs[c * GLDK + kk] = rb[j];
+    }
+    __syncthreads();
+    if (k0 + GKT < K) load(k0 + GKT);
+#pragma unroll
+    for (int kb = 0; kb < GKT; kb += 16) {
+      F fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const T* pa = As + (wm + 16 * i + r) * GLDK + kb;
+        const T* pb = Bs + (wn + 16 * i + r) * GLDK + kb;
+        fa[i] = raw_frag<T>(pa[R::kidx(g, 0)], pa[R::kidx(g, 1)], pa[R::kidx(g, 2)], pa[R::kidx(g, 3)]);
+        fb[i] = raw_frag<T>(pb[R::kidx(g, 0)], pb[R::kidx(g, 1)], pb[R::kidx(g, 2)], pb[R::kidx(g, 3)]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) mma(acc[i][j], fa[i], fb[j]);
+    }
+  }
+  // acc[i][j] lane (r, g), register e: row wm + 16 i + kidx(g, e), column wn + 16 j + r
+  __syncthreads();
+  AT* Cs = (AT*)smem;   // [column][row], rows padded to GBM + 1
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Cs[(wn + 16 * j + r) * (GBM + 1) + wm + 16 * i + R::kidx(g, e)] = acc[i][j][e];
+  __syncthreads();
+#pragma unroll 4
+  for (int pass = 0; pass < GBM * GBN / GWG; ++pass) {
+    const int col = pass * (GWG / GBM) + tid / GBM, row = tid % GBM;
+    if (m0 + row >= M || n0 + col >= N) continue;
+    const long long idx = (m0 + row) + ldc * (n0 + col);
+    AT v = Cs[col * (GBM + 1) + row];
+    if (ADD) v += Cadd[idx];
+    if (VMUL) v *= Vmul[idx];
+    C[idx] = g_to(v, (TO*)nullptr);
   }
 }
 
-template <typename T, typename TO, bool ACC>
+template <typename T, typename TO, bool ADD, bool VMUL>
 static hipError_t gemm_t(long long M, long long N, long long K, const void* A, long long lda, const void* B,
-                         long long ldb, void* C, long long ldc, hipStream_t s) {
-  const long long gx = (M + 31) / 32, gy = (N + 31) / 32;
+                         long long ldb, void* C, long long ldc, const void* Cadd, const void* Vmul, hipStream_t s) {
+  typedef typename Tr<T>::acc_t AT;
+  const long long gx = (M + GBM - 1) / GBM, gy = (N + GBN - 1) / GBN;
   if (gx < 1 || gy < 1 || gy > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_rho_gemm<T, TO, ACC>), dim3((unsigned)gx, (unsigned)gy), dim3(GWG), 0, s, M, N, K, (const T*)A,
-                     lda, (const T*)B, ldb, (TO*)C, ldc);
+  hipLaunchKernelGGL((k_rho_gemm<T, TO, ADD, VMUL>), dim3((unsigned)gx, (unsigned)gy), dim3(GWG), 0, s, M, N, K,
+                     (const T*)A, lda, (const T*)B, ldb, (TO*)C, ldc, (const AT*)Cadd, (const AT*)Vmul);
   return hipGetLastError();
 }
 
-// one rho step in dtype dt: out_kind 0 = dtype (an intermediate), 1 = the accumulation type
-// (FP32 for BF16/F32, FP64 for F64); acc: add into C
+template <typename T, typename TO>
+static hipError_t gemm_ev(long long M, long long N, long long K, const void* A, long long lda, const void* B,
+                          long long ldb, void* C, long long ldc, const void* Cadd, const void* Vmul, hipStream_t s) {
+  if (Cadd && Vmul) return gemm_t<T, TO, true, true>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  if (Cadd) return gemm_t<T, TO, true, false>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  if (Vmul) return gemm_t<T, TO, false, true>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  return gemm_t<T, TO, false, false>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+}
+
+// one rho step in dtype dt: out_kind 0 = C in dtype (an intermediate, or the weighted output
+// V .* (product + Cadd)), 1 = C in the accumulation type (FP32 for BF16/F32, FP64 for F64);
+// Cadd, Vmul (accumulation type, optional; Cadd may equal C)
+hipError_t launch_rho_gemm_ex(int dt, int out_kind, long long M, long long N, long long K, const void* A,
+                              long long lda, const void* B, long long ldb, void* C, long long ldc, const void* Cadd,
+                              const void* Vmul, hipStream_t s) {
+  if (dt == DT_F64) return gemm_ev<double, double>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  if (dt == DT_F32) return gemm_ev<float, float>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  if (out_kind == 0) return gemm_ev<bf16, bf16>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+  return gemm_ev<bf16, float>(M, N, K, A, lda, B, ldb, C, ldc, Cadd, Vmul, s);
+}
+
 hipError_t launch_rho_gemm(int dt, int out_kind, bool acc, long long M, long long N, long long K, const void* A,
                            long long lda, const void* B, long long ldb, void* C, long long ldc, hipStream_t s) {
-  if (dt == DT_F64) return acc ? gemm_t<double, double, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
-                               : gemm_t<double, double, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
-  if (dt == DT_F32) return acc ? gemm_t<float, float, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
-                               : gemm_t<float, float, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
-  if (out_kind == 0) return acc ? gemm_t<bf16, bf16, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
-                                : gemm_t<bf16, bf16, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
-  return acc ? gemm_t<bf16, float, true>(M, N, K, A, lda, B, ldb, C, ldc, s)
-             : gemm_t<bf16, float, false>(M, N, K, A, lda, B, ldb, C, ldc, s);
+  return launch_rho_gemm_ex(dt, out_kind, M, N, K, A, lda, B, ldb, C, ldc, acc ? C : nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -115,6 +183,21 @@ hipError_t general_forward(int dt, const int64_t* n, const int64_t* p, const voi
   e = launch_rho_gemm(dt, 0, false, p3 * n1, n2, p2, t1, p2, XT[1], p2, t2, p3 * n1, s);
   if (e != hipSuccess) return e;
   return launch_rho_gemm(dt, 1, acc, n1 * n2, n3, p3, t2, p3, XT[2], p3, eta, n1 * n2, s);
+}
+
+// the same chain with its last step writing R = V .* (H(X, Theta) + Cadd) in dtype dt (the weighted
+// input of the adjoint in the inner loop, Sec. 6.1); Cadd: the other components' sum (accumulation
+// type) or NULL; V: the weights (accumulation type) or NULL
+hipError_t general_forward_weighted(int dt, const int64_t* n, const int64_t* p, const void* const* XT,
+                                    const void* theta, void* t1, void* t2, const void* Cadd, const void* V, void* R,
+                                    hipStream_t s) {
+  hipError_t e;
+  const long long n1 = n[0], n2 = n[1], n3 = n[2], p1 = p[0], p2 = p[1], p3 = p[2];
+  e = launch_rho_gemm(dt, 0, false, p2 * p3, n1, p1, theta, p1, XT[0], p1, t1, p2 * p3, s);
+  if (e != hipSuccess) return e;
+  e = launch_rho_gemm(dt, 0, false, p3 * n1, n2, p2, t1, p2, XT[1], p2, t2, p3 * n1, s);
+  if (e != hipSuccess) return e;
+  return launch_rho_gemm_ex(dt, 0, n1 * n2, n3, p3, t2, p3, XT[2], p3, R, n1 * n2, Cadd, V, s);
 }
 
 // adjoint: U (n1, n2, n3) -> (n2, n3, p1) -> (n3, p1, p2) -> out (p1, p2, p3); X[j] in dtype dt
@@ -264,22 +347,6 @@ hipError_t launch_gen_family(int adj_dt, int v_dt, long long n, int family, cons
   return hipGetLastError();
 }
 
-// R = V .* eta (V NULL: 1), in the chain dtype T; eta and V in the accumulation type A
-template <typename T, typename A>
-__global__ void k_gen_weight(long long n, const A* __restrict__ eta, const A* __restrict__ V, T* __restrict__ out) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const A e = V ? eta[i] * V[i] : eta[i];
-    out[i] = g_to((typename Tr<T>::acc_t)e, (T*)nullptr);
-  }
-}
-hipError_t launch_gen_weight(int dt, long long n, const void* eta, const void* V, void* out, hipStream_t s) {
-  const dim3 g(g_grid(n)), b(GWG);
-  if (dt == DT_F64) hipLaunchKernelGGL((k_gen_weight<double, double>), g, b, 0, s, n, (const double*)eta, (const double*)V, (double*)out);
-  else if (dt == DT_F32) hipLaunchKernelGGL((k_gen_weight<float, float>), g, b, 0, s, n, (const float*)eta, (const float*)V, (float*)out);
-  else hipLaunchKernelGGL((k_gen_weight<bf16, float>), g, b, 0, s, n, (const float*)eta, (const float*)V, (bf16*)out);
-  return hipGetLastError();
-}
-
 __device__ inline double g_soft(double z, double t) {
   const double a = fabs(z) - t;
   return a > 0.0 ? copysign(a, z) : 0.0;
@@ -365,6 +432,78 @@ hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, co
   else
     hipLaunchKernelGGL((k_gen_prox<bf16, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, x, xp, gp,
                        (bf16*)inc, lambda, delta, om, alpha, no_l1, part);
+  return hipGetLastError();
+}
+
+// The same step on FP32 increment state (BF16 / FP32 chains, nu = 1): x^l = theta_ref + d^l with
+// d in FP32 (an exact zero x^l kept as a NaN code), and grad h(x^{l-1}) = gref + q with q the
+// previous increment gradient (FP32), so that a coefficient moves 32 bytes in and 10 out instead of
+// 44 and 26.  Reads dcur (d^l), dprev (d^{l-1}), q; writes dout (d^{l+1}), q (in place) and inc.
+template <typename T, typename A>
+__global__ __launch_bounds__(GWG) void k_gen_prox_inc(long long p, const A* __restrict__ gi, double scale,
+                                                      const double* __restrict__ gref,
+                                                      const double* __restrict__ theta_ref,
+                                                      const double* __restrict__ w, const float* __restrict__ dcur,
+                                                      const float* __restrict__ dprev, float* __restrict__ q,
+                                                      float* __restrict__ dout, T* __restrict__ inc, double lambda,
+                                                      double delta, double om, double alpha, int no_l1,
+                                                      double* __restrict__ part) {
+  double kkt = 0.0, noise = 0.0, rs = 0.0, dmax = 0.0;
+  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG) {
+    const double incg = scale * (double)gi[j];
+    const double tr = theta_ref[j];
+    const float dc = dcur[j], dp = dprev[j];
+    const double xv = __builtin_isnan(dc) ? 0.0 : tr + (double)dc;
+    const double xpv = __builtin_isnan(dp) ? 0.0 : tr + (double)dp;
+    const double gx = gref[j] + incg;
+    const double wm = w ? w[j] : 1.0, lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
+    const double gs = gx + 2.0 * alpha * lw * xv;
+    kkt = fmax(kkt, xv != 0.0 ? fabs(gs + copysign(l1w, xv)) : fmax(fabs(gs) - l1w, 0.0));
+    noise = fmax(noise, fabs(incg));
+    const double gy = gx + om * (incg - (double)q[j]);
+    const double yv = xv + om * (xv - xpv);
+    const double xn = g_soft(yv - delta * gy, delta * l1w) / (1.0 + 2.0 * alpha * delta * lw);
+    const double dn = xn - tr;
+    dout[j] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
+    q[j] = (float)incg;
+    rs += (yv - xn) * (xn - xv);
+    dmax = fmax(dmax, fabs(dn));
+    inc[j] = g_to((typename Tr<T>::acc_t)dn, (T*)nullptr);
+  }
+  double v[4] = {kkt, noise, rs, dmax};
+  g_block_partials<4>(v, 1u | 2u | 8u, part);
+}
+hipError_t launch_gen_prox_inc(int dt, long long p, const void* gi, double scale, const double* gref,
+                               const double* theta_ref, const double* w, const float* dcur, const float* dprev,
+                               float* q, float* dout, void* inc, double lambda, double delta, double om, double alpha,
+                               int no_l1, double* part, int* nblk, hipStream_t s) {
+  const int nb = g_grid(p);
+  *nblk = nb;
+  const dim3 g(nb), b(GWG);
+  if (dt == DT_F32)
+    hipLaunchKernelGGL((k_gen_prox_inc<float, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, dcur,
+                       dprev, q, dout, (float*)inc, lambda, delta, om, alpha, no_l1, part);
+  else if (dt == DT_BF16)
+    hipLaunchKernelGGL((k_gen_prox_inc<bf16, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, dcur,
+                       dprev, q, dout, (bf16*)inc, lambda, delta, om, alpha, no_l1, part);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// x = theta_ref + d (FP64, the NaN code as an exact 0); sub: out = x - theta_ref instead
+__global__ void k_gen_inc_out(long long p, const float* __restrict__ d, const double* __restrict__ theta_ref, int sub,
+                              double* __restrict__ out) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < p; j += (long long)gridDim.x * blockDim.x) {
+    const float dj = d[j];
+    const double tr = theta_ref[j];
+    const double x = __builtin_isnan(dj) ? 0.0 : tr + (double)dj;
+    out[j] = sub ? x - tr : x;
+  }
+}
+hipError_t launch_gen_inc_out(long long p, const float* d, const double* theta_ref, int sub, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_inc_out, dim3(g_grid(p)), dim3(GWG), 0, s, p, d, theta_ref, sub, out);
   return hipGetLastError();
 }
 

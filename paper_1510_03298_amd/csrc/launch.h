@@ -356,6 +356,15 @@ hipError_t launch_check(long long n, const double* y, const double* a, long long
 // FP64 for F64); acc: add into C.
 hipError_t launch_rho_gemm(int dt, int out_kind, bool acc, long long M, long long N, long long K, const void* A,
                            long long lda, const void* B, long long ldb, void* C, long long ldc, hipStream_t s);
+// the same with optional epilogue terms: C = (product + Cadd) .* Vmul, Cadd and Vmul in the accumulation
+// type (either may be NULL; Cadd may equal C); out_kind 0 then writes dtype dt
+hipError_t launch_rho_gemm_ex(int dt, int out_kind, long long M, long long N, long long K, const void* A,
+                              long long lda, const void* B, long long ldb, void* C, long long ldc, const void* Cadd,
+                              const void* Vmul, hipStream_t s);
+// R = V .* (H(X, Theta) + Cadd) in dt (Cadd, V in the accumulation type, optional)
+hipError_t general_forward_weighted(int dt, const int64_t* n, const int64_t* p, const void* const* XT,
+                                    const void* theta, void* t1, void* t2, const void* Cadd, const void* V, void* R,
+                                    hipStream_t s);
 // eta (+)= H(X, Theta) by three GEMMs in the cyclic mode order; XT[j] = X_j^T (p_j x n_j, k-contiguous)
 // in dt; t1, t2: >= general_tmp_elems elements of dt; eta in the accumulation type
 hipError_t general_forward(int dt, const int64_t* n, const int64_t* p, const void* const* XT, const void* theta,
@@ -372,8 +381,6 @@ hipError_t launch_gen_transpose_same(int dt, long long nr, long long pc, const v
 // family step on FP64 eta: u (adj_dt), weights (v_dt, optional), partials {sum -l, max w}
 hipError_t launch_gen_family(int adj_dt, int v_dt, long long n, int family, const double* eta, const double* y,
                              const double* a, void* u_out, void* v_out, double* part, int* nblk, hipStream_t s);
-// out = V .* eta in dt (eta, V in the accumulation type; V NULL: 1)
-hipError_t launch_gen_weight(int dt, long long n, const void* eta, const void* V, void* out, hipStream_t s);
 // g = scale gin (FP64); partials {max KKT residual, max |g|/w, sum w (l1 |theta| + alpha theta^2)}
 hipError_t launch_gen_grad_stats(long long p, const double* gin, double scale, const double* theta, const double* w,
                                  double lambda, double alpha, int no_l1, double* gout, double* part, int* nblk,
@@ -384,6 +391,15 @@ hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, co
                            const double* theta_ref, const double* w, double* x, double* xp, double* gp, void* inc,
                            double lambda, double delta, double om, double alpha, int no_l1, double* part, int* nblk,
                            hipStream_t s);
+// the same step on FP32 increment state (BF16/FP32 chains): x^l = theta_ref + d (NaN: exact 0),
+// grad h(x^{l-1}) = gref + q; reads dcur, dprev, q, writes dout, q, inc; the same partials
+hipError_t launch_gen_prox_inc(int dt, long long p, const void* gi, double scale, const double* gref,
+                               const double* theta_ref, const double* w, const float* dcur, const float* dprev,
+                               float* q, float* dout, void* inc, double lambda, double delta, double om, double alpha,
+                               int no_l1, double* part, int* nblk, hipStream_t s);
+// out = theta_ref + d (sub = 0) or that minus theta_ref (sub = 1), FP64
+hipError_t launch_gen_inc_out(long long p, const float* d, const double* theta_ref, int sub, double* out,
+                              hipStream_t s);
 struct GenBtState {
   double* x;    // x^l
   double* xp;   // x^{l-1}
