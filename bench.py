@@ -236,6 +236,50 @@ def sim65_path(glam, inputs, torch, stream, family, forms=("bf16", "f64")):
     return out
 
 
+def sim65_q3_path(glam, inputs, torch, stream):
+    """Section 6.5's p > n designs (q = 3, kappa = 0, Gaussian), which run on the generic-GEMM
+    path: r = 1 (n = 12,000, p = 324,000), the default 100-lambda path to 1e-4 lambda_max, and
+    r = 2 (n = 96,000, p = 2.59 million), 50 lambdas to 1e-2 lambda_max; KKT <= 1e-6, BF16 chain."""
+    out = {}
+    for r, nl, ratio in ((1, 100, 1e-4), (2, 50, 1e-2)):
+        d = inputs.config_sim(r=r, q=3, family="gaussian", kappa=0.0)
+        Xd = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
+        Yd = glam.to_device_colmajor(d.Y, glam.F64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", nlambda=nl, lambda_min_ratio=ratio, dtype=glam.BF16,
+                            kkt_tol=1e-6, stream=stream, raise_on_error=False)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[f"r{r}"] = {"workload": f"sec6.5_simulated_gaussian_r{r}_q3_kappa0_n{d.n[0]}x{d.n[1]}x{d.n[2]}"
+                                    f"_p{d.p[0]}x{d.p[1]}x{d.p[2]}_{nl}lambda_to_{ratio:g}_kkt1e-6",
+                        "seconds": sec, "models": int(res.n_done), "converged": res.code == 0 and res.n_done == nl,
+                        "max_kkt": float(np.max(res.kkt[:res.n_done])) if res.n_done else None,
+                        "inner": int(res.inner_total), "outer": int(res.iters_outer.sum()),
+                        "us_per_inner_iteration": 1e6 * sec / max(1, int(res.inner_total))}
+    return out
+
+
+def components_path(glam, inputs, torch, stream):
+    """A model of c = 2 tensor components (Sec. 2), n = (100, 100, 100), component sizes (20, 20, 20)
+    and (8, 8, 40), Gaussian, 50 lambdas to 1e-3 lambda_max, KKT <= 1e-6, on the generic-GEMM path."""
+    d = inputs.random_components_problem((100, 100, 100), [(20, 20, 20), (8, 8, 40)], family="gaussian", seed=3,
+                                         sparsity=0.05)
+    comps = [([glam.to_device_colmajor(X, glam.F64) for X in Xs], tuple(X.shape[1] for X in Xs)) for Xs in d.comps]
+    Yd = glam.to_device_colmajor(d.Y, glam.F64)
+    out = {"workload": "gaussian_c2_components_n100x100x100_p20x20x20+8x8x40_50lambda_kkt1e-6"}
+    for dt, name in ((glam.BF16, "bf16"), (glam.F64, "f64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = glam.fit_path_multi(comps, Yd, d.n, "gaussian", nlambda=50, lambda_min_ratio=1e-3, dtype=dt, kkt_tol=1e-6,
+                                stream=stream, raise_on_error=False)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "models": int(r.n_done), "converged": r.code == 0,
+                     "max_kkt": float(np.max(r.kkt[:r.n_done])) if r.n_done else None,
+                     "inner": int(r.inner_total), "outer": int(r.iters_outer.sum())}
+    return out
+
+
 def poisson_path_kron(glam, inputs, torch, stream):
     """The Poisson path n = (64, 64, 365), p = (24, 24, 120) with Sec. 6.2's tensor-product
     weights: p-sized inner iterations on reweighted Gram factors (exact gradient, approximate
@@ -390,7 +434,9 @@ def main():
                 "poisson_nll_c5": lambda: nll(glam, inputs, torch, stream),
                 "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream),
                 "gaussian_c1": lambda: c1_single_lambda(glam, inputs, torch, stream),
-                "poisson_path_c3_kron": lambda: poisson_path_kron(glam, inputs, torch, stream)}
+                "poisson_path_c3_kron": lambda: poisson_path_kron(glam, inputs, torch, stream),
+                "sim65_q3_gaussian": lambda: sim65_q3_path(glam, inputs, torch, stream),
+                "components_c2": lambda: components_path(glam, inputs, torch, stream)}
         if args.only not in only:
             print(f"bench.py: --only takes one of {sorted(only)}", file=sys.stderr)
             sys.exit(2)
@@ -549,7 +595,9 @@ def main():
                 ("poisson_nll_c5", lambda: nll(glam, inputs, torch, stream)),
                 ("sim65_gaussian", lambda: sim65_path(glam, inputs, torch, stream, "gaussian")),
                 # BF16 only: its FP64 form takes ~46 s (1.97M launch-bound inner iterations at n = 324k)
-                ("sim65_poisson", lambda: sim65_path(glam, inputs, torch, stream, "poisson", forms=("bf16",)))]
+                ("sim65_poisson", lambda: sim65_path(glam, inputs, torch, stream, "poisson", forms=("bf16",))),
+                ("sim65_q3_gaussian", lambda: sim65_q3_path(glam, inputs, torch, stream)),
+                ("components_c2", lambda: components_path(glam, inputs, torch, stream))]
         extra = {}
         for name, job in jobs:
             progress(f"workload {name}")
