@@ -149,11 +149,12 @@ hipError_t launch_slab_adj_inc(int dt, const AdjIncParams& P, int* nblk_out, hip
 int slab_adj_inc_blocks(const Geom& G, int xmap);
 // partial-sum rows a launch writes (the reduction's block count)
 int slab_adj_inc_partials(const Geom& G, int xmap);
-// the tile order the fits use: 16 x 16 tiles, split-K over the 4 waves, row blocks fastest
-// (n = (100, 100, 1000), p = (30, 30, 200), BF16, back to back: 6.95 us against 7.0 us for the
-// XCD-aware order, 7.3 us for 32 x 32 tiles, 10.4 us for whole-contraction waves; 9.45 us for
-// the FP64-state step)
-constexpr int kAdjIncForm = 0;
+// the tile order the fits use: 16 x 16 tiles, split-K over the 4 waves, in the XCD-aware order
+// (each XCD a run of row blocks, so its L2 fetches only its part of S2).  n = (100, 100, 1000),
+// p = (30, 30, 200), BF16: back to back 7.7 us in either order (7.3 us for 32 x 32 tiles, 10.4 us
+// for whole-contraction waves; 9.45 us for the FP64-state step), but the XCD order fetches 10.3
+// instead of 22.0 MB per launch and the whole path runs 5% faster with it.
+constexpr int kAdjIncForm = 1;
 // per outer step: tT, gT (and penT when pen_w != NULL) from theta, gref, pen_w; d0 = d1 = q = 0,
 // inc = 0 (k-blocked, chain dtype), *iter = 0
 hipError_t launch_inner_init_inc(int dt, const Geom& G, const double* theta, const double* gref, const double* pen_w,

@@ -161,72 +161,75 @@ __global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
   fwd_tile<T>(P, blockIdx.x, blockIdx.y);
 }
 
-// FP64 slab_fwd with 64 x 64 workgroup tiles, each wave a 32 x 32 block of 2 x 2 matrix-core
-// tiles: with 8-byte operands the 16 x 16 wave tiles above stream four times the L2 traffic
-// per output (each wave reloads its own A and B strips); here each fragment feeds two products.
-__global__ __launch_bounds__(WG) void k_slab_fwd64(FwdParams P) {
-  typedef Tr<double> R;
-  typedef R::frag_t Fr;
-  if (P.iter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *P.iter += 1;
+// slab_fwd with 64 x 64 workgroup tiles (each wave a 32 x 32 block of 2 x 2 matrix-core tiles, so
+// each operand fragment feeds two products; with 16 x 16 wave tiles each wave reloads its own A
+// and B strips), in an XCD-aware order: workgroup b runs on XCD b % 8, and XCD x takes a contiguous
+// run of tiles (consecutive slab columns), so that its L2 fetches only its own part of X3f.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
+  typedef Tr<T> R;
+  typedef typename R::frag_t Fr;
+  constexpr int NB = KNB<T>::v;
+  if (P.iter && blockIdx.x == 0 && threadIdx.x == 0) *P.iter += 1;
   const Geom& G = P.G;
-  const double* __restrict__ A = (const double*)P.theta;
-  const double* __restrict__ B = (const double*)P.X3f;
-  double* __restrict__ T1 = (double*)P.T1;
+  const int NBX = (G.P12 + 63) >> 6, NBY = (G.n3 + 63) >> 6, NT = NBX * NBY, per = (NT + 7) >> 3;
+  const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (t >= NT) return;   // the padding workgroups of the XCD order (whole workgroup)
+  const int bx = t % NBX, by = t / NBX;
+  const T* __restrict__ A = (const T*)P.theta;
+  const T* __restrict__ B = (const T*)P.X3f;
+  T* __restrict__ T1 = (T*)P.T1;
   const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int ml0 = (w & 1) * 32, nl0 = (w >> 1) * 32;   // the wave's block within the tile
+  const int ml0 = (w & 1) * 32, nl0 = (w >> 1) * 32;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.n3 * 16;
-  const double* pa[2];
-  const double* pb[2];
+  const T* pa[2];
+  const T* pb[2];
   bool am[2], bn[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const int m = blockIdx.x * 64 + ml0 + 16 * i + r;    // A column (P12 index)
-    const int i3 = blockIdx.y * 64 + nl0 + 16 * i + r;   // B column (n3 index)
+    const int m = bx * 64 + ml0 + 16 * i + r;
+    const int i3 = by * 64 + nl0 + 16 * i + r;
     am[i] = m < G.P12;
     bn[i] = i3 < G.n3;
     pa[i] = A + (long long)m * 16 + 4 * g;
     pb[i] = B + (long long)i3 * 16 + 4 * g;
   }
-  d4v acc[2][2];
+  typename R::accv_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = R::zero();
-  constexpr int NB = 4;
   for (int kb0 = 0; kb0 < G.KB3; kb0 += NB) {
-    Fr fa[NB][2], fb[NB][2];
+    Fr fa[2][NB], fb[2][NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const bool in = kb0 + q < G.KB3;
       const long long kb = kb0 + q;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        fa[q][i] = (in && am[i]) ? load_frag(pa[i] + kb * sa) : zero_frag<double>();
-        fb[q][i] = (in && bn[i]) ? load_frag(pb[i] + kb * sb) : zero_frag<double>();
+        fa[i][q] = (in && am[i]) ? load_frag(pa[i] + kb * sa) : zero_frag<T>();
+        fb[i][q] = (in && bn[i]) ? load_frag(pb[i] + kb * sb) : zero_frag<T>();
       }
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) mma(acc[i][j], fa[q][i], fb[q][j]);
+      for (int j = 0; j < 2; ++j) MmaBlocks<T, NB>::run(acc[i][j], fa[i], fb[j]);
   }
-  // T1 slab-major, T1[i3][m]: the 64 x 64 tile is transposed through LDS so that each slab's
-  // 64 values of m are written by 64 consecutive lanes
-  __shared__ double tt[64][65];
+  // T1 slab-major, T1[i3][m], through an LDS transpose of the 64 x 64 tile
+  __shared__ T tt[64][65];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) tt[nl0 + 16 * j + r][ml0 + 16 * i + R::kidx(g, e)] = acc[i][j][e];
+      for (int e = 0; e < 4; ++e) tt[nl0 + 16 * j + r][ml0 + 16 * i + R::kidx(g, e)] = R::from_acc(acc[i][j][e]);
   __syncthreads();
   const int tid = threadIdx.x;
 #pragma unroll
   for (int pass = 0; pass < 16; ++pass) {
     const int sl = 4 * pass + (tid >> 6), ml = tid & 63;
-    const int i3o = blockIdx.y * 64 + sl, mo = blockIdx.x * 64 + ml;
+    const int i3o = by * 64 + sl, mo = bx * 64 + ml;
     if (i3o < G.n3 && mo < G.P12) T1[(long long)i3o * G.P12 + mo] = tt[sl][ml];
   }
 }
@@ -1584,13 +1587,22 @@ static int num_cus() {
 // 1000), p = (30, 30, 200): 240 tiles, 26.7 -> 22.1 us); below that, 32 x 32 tiles (a Sec. 6.5
 // design at P12 = 450, n3 = 180 has 24 large tiles against 90 small ones, and its FP64 path
 // ran 25% slower on them)
-static bool slab_fwd_f64_wide(const Geom& G) { return (long long)((G.P12 + 63) / 64) * ((G.n3 + 63) / 64) >= 128; }
+static bool slab_fwd_wide(const Geom& G) { return (long long)((G.P12 + 63) / 64) * ((G.n3 + 63) / 64) >= 128; }
 
 hipError_t launch_slab_fwd(int dt, const FwdParams& P, hipStream_t s) {
   dim3 grid((P.G.P12 + 31) / 32, (P.G.n3 + 31) / 32);
-  if (dt == DT_F64 && slab_fwd_f64_wide(P.G))
-    hipLaunchKernelGGL(k_slab_fwd64, dim3((P.G.P12 + 63) / 64, (P.G.n3 + 63) / 64), dim3(WG), 0, s, P);
-  else if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd<double>, grid, dim3(WG), 0, s, P);
+  // 64 x 64 tiles in the XCD order wherever they still give the chip enough workgroups
+  // (n = (100, 100, 1000), p = (30, 30, 200), BF16: 5.8 us and 3.7 MB fetched per launch, against
+  // 6.4 us and 6.4 MB for 32 x 32 tiles in launch order)
+  if (slab_fwd_wide(P.G)) {
+    const int nt = ((P.G.P12 + 63) / 64) * ((P.G.n3 + 63) / 64);
+    const dim3 gw(8 * ((nt + 7) / 8));
+    if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd_wide<double>, gw, dim3(WG), 0, s, P);
+    else if (dt == DT_F32) hipLaunchKernelGGL(k_slab_fwd_wide<float>, gw, dim3(WG), 0, s, P);
+    else hipLaunchKernelGGL(k_slab_fwd_wide<bf16>, gw, dim3(WG), 0, s, P);
+    return hipGetLastError();
+  }
+  if (dt == DT_F64) hipLaunchKernelGGL(k_slab_fwd<double>, grid, dim3(WG), 0, s, P);
   else if (dt == DT_F32) hipLaunchKernelGGL(k_slab_fwd<float>, grid, dim3(WG), 0, s, P);
   else hipLaunchKernelGGL(k_slab_fwd<bf16>, grid, dim3(WG), 0, s, P);
   return hipGetLastError();
