@@ -247,8 +247,8 @@ def config_sim(r=3, q=0.5, family="gaussian", kappa=0.25, seed=6, nlambda=100, r
     The modes are listed with the largest last: (20r, 10r, 60r).  A GLAM is unchanged by a
     joint permutation of its modes, Y's axes and Theta's axes, and the solver's slab
     kernel takes the two smaller modes (p_j <= 32 there, hence r <= 3 at q = 0.5; the
-    p > n designs, q = 3, do not fit it).  The coefficient index m runs over the
-    permuted array in vec order."""
+    p > n designs, q = 3, run on the generic GEMM chain).  The coefficient index m runs over
+    the permuted array in vec order."""
     rng = np.random.default_rng(SEED_BASE + seed)
     n_paper = (60 * r, 20 * r, 10 * r)
     order = (1, 2, 0)
