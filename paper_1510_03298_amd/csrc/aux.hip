@@ -56,8 +56,20 @@ constexpr int RED_WG = 1024;
 __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval,
                                                    unsigned ops_bits, double scale, double* __restrict__ out,
                                                    double* hout, unsigned* seq_dev, unsigned* hseq,
-                                                   int restart_slot, int* restart_iter) {
+                                                   int restart_slot, int* restart_iter, int* stop,
+                                                   const double* __restrict__ crit) {
   const int lane = lane_id(), w = wave_id();
+  if (stop && *stop) {
+    // the inner loop ended at an earlier block: nothing of this block ran; say so to the host
+    if (hout && threadIdx.x == 0) {
+      const unsigned s = *seq_dev + 1u;
+      *seq_dev = s;
+      __hip_atomic_store(&hout[8 * (s & 1u) + nval], 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __threadfence_system();
+      __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return;   // the whole workgroup (*stop was written by an earlier kernel)
+  }
   for (int v = w; v < nval; v += RED_WG / 64) {
     const bool mx = (ops_bits >> v) & 1u;
     double a = mx ? -INFINITY : 0.0;
@@ -72,18 +84,26 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ pa
       // restarted extrapolation: a positive test value sets the step counter back, so that the
       // next iteration takes omega = 0 (the counter is incremented before its use)
       if (restart_iter && v == restart_slot && r > 0.0) *restart_iter = 0;
-      if (hout) {
-        __hip_atomic_store(&hout[v], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __threadfence_system();   // visible to the host before the sequence number below
-      }
+    }
+  }
+  if (stop) {
+    __syncthreads();   // out[0], out[1] of waves 0 and 1
+    if (threadIdx.x == 0) {
+      const double kin = out[0] / crit[0], noise = crit[2] * out[1] / crit[0];
+      if (!__builtin_isfinite(kin) || kin <= fmax(crit[1], noise)) *stop = 1;
     }
   }
   if (hout) {
-    __syncthreads();
+    // published into slot s % 2 of the host buffer (two blocks may be in flight): the values, the
+    // "skipped" flag 0, then the sequence number s
+    __syncthreads();   // out[v] of every wave
     if (threadIdx.x == 0) {
       const unsigned s = *seq_dev + 1u;
       *seq_dev = s;
-      __threadfence_system();
+      double* slot = hout + 8 * (s & 1u);
+      for (int v = 0; v < nval; ++v) __hip_atomic_store(&slot[v], out[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&slot[nval], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __threadfence_system();   // the values before the sequence number
       __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
@@ -412,18 +432,19 @@ hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, i
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
   if (nval > 32) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, stride, nval, bits, scale, out,
-                     (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, -1, (int*)nullptr);
+                     (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, -1, (int*)nullptr, (int*)nullptr,
+                     (const double*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
                                  double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s, int restart_slot,
-                                 int* restart_iter) {
+                                 int* restart_iter, int* stop, const double* crit) {
   unsigned bits = 0;
   for (int v = 0; v < nval; ++v) bits |= (unsigned)(ops[v] & 1) << v;
-  if (nval > 32 || !hout || !seq_dev || !hseq) return hipErrorInvalidValue;
+  if (nval >= 8 || nval < 2 || !hout || !seq_dev || !hseq || (stop && !crit)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_WG), 0, s, partials, nblk, nval, nval, bits, scale, out, hout, seq_dev,
-                     hseq, restart_slot, restart_iter);
+                     hseq, restart_slot, restart_iter, stop, crit);
   return hipGetLastError();
 }
 

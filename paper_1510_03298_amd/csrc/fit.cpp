@@ -222,8 +222,13 @@ struct Fit {
   bool own_stream = false;
   bool batched = false;            // set up for glam_fit_batched (its batched step uses the LDS image)
   hipEvent_t sync_ev = nullptr;
-  double* dparams = nullptr;       // device {lambda, delta}
+  double* dparams = nullptr;       // device {lambda, delta, -, -, lambda scale, tol_in, 4 eps} (8 slots)
   double* hparams = nullptr;       // pinned host staging of dparams
+  // run-ahead inner loop (the increment-state chain loop): the next block of iterations is queued
+  // before the host has read the current block's check; the reduction of each block tests
+  // convergence on the device and sets *stop, after which the queued kernels do nothing
+  bool runahead = false;
+  int* stop = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_m = 0;                 // inner iterations per graph replay
@@ -378,13 +383,15 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     }
     return GLAM_OK;
   }
+  const bool incst = F.incst && F.dt != DT_F64;
+  const int* stop = incst && F.runahead ? F.stop : nullptr;
   FwdParams fw{};
-  fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c; fw.iter = F.iter;
+  fw.G = G; fw.theta = F.inc; fw.X3f = F.X3fc; fw.T1 = F.T1c; fw.iter = F.iter; fw.stop = stop;
   FCHK(launch_slab_fwd(F.dt, fw, F.s));
   SlabParams sp{};
-  sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int;
+  sp.G = G; sp.img = F.imgc; sp.T1 = F.T1c; sp.S2 = F.S2c; sp.v_int = F.v_int; sp.stop = stop;
   FCHK(launch_slab_chain(F.dt, SM_FUSED, sp, nullptr, F.s));
-  if (F.incst && F.dt != DT_F64) {
+  if (incst) {
     // x^{l+1} from x^l = theta_ref + d[gpar] and x^{l-1} = theta_ref + d[1 - gpar], written over
     // the latter (AdjIncParams)
     AdjIncParams ai{};
@@ -393,6 +400,7 @@ static int inner_iteration(Fit& F, double lambda, double delta, int* nblk, bool 
     ai.dcur = F.dst[F.gpar]; ai.dprev = F.dst[1 - F.gpar]; ai.dout = F.dst[1 - F.gpar];
     ai.q_in = F.qst; ai.q_out = F.qst; ai.inc = F.inc; ai.iter = F.iter; ai.dparams = F.dparams;
     ai.scale = 1.0 / (double)G.n; ai.alpha = F.enet; ai.no_l1 = F.no_l1; ai.partials = F.part; ai.xmap = kAdjIncForm;
+    ai.stop = stop;
     FCHK(launch_slab_adj_inc(F.dt, ai, nblk, F.s));
     F.gpar ^= 1;
     if (sample) {
@@ -465,8 +473,9 @@ static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
     if (r) return r;
   }
   const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
+  const bool ra = F.runahead && F.incst && F.dt != DT_F64;
   FCHK(launch_reduce_publish(F.part, *nblk, ADJ_NSUM, ops, 1.0, F.red, F.hpub_dev, F.seq_dev, F.hseq_dev, F.s, 2,
-                             F.restart ? F.iter : nullptr));
+                             F.restart ? F.iter : nullptr, ra ? F.stop : nullptr, ra ? F.dparams + 4 : nullptr));
   return GLAM_OK;
 }
 
@@ -475,12 +484,15 @@ static int inner_block_eager(Fit& F, int m, bool sample_first, int* nblk) {
 // that number (no copy, no stream synchronisation) and queries the stream for errors.
 static int wait_published(Fit& F, double* vals, int nval) {
   const unsigned want = ++F.seq_expect;
+  // reached: the sequence number is at or past this block's (a block queued behind it may have
+  // published too; its values sit in the other slot)
+  auto reached = [&]() { return (int)(__atomic_load_n(F.hseq, __ATOMIC_ACQUIRE) - want) >= 0; };
   for (long long spin = 0;; ++spin) {
-    if (__atomic_load_n(F.hseq, __ATOMIC_ACQUIRE) == want) break;
+    if (reached()) break;
     if ((spin & 255) == 255) {
       const hipError_t e = hipStreamQuery(F.s);
       if (e == hipSuccess) {
-        if (__atomic_load_n(F.hseq, __ATOMIC_ACQUIRE) == want) break;
+        if (reached()) break;
         F.err = "check values were not published";
         return GLAM_EDEVICE;
       }
@@ -490,7 +502,8 @@ static int wait_published(Fit& F, double* vals, int nval) {
       }
     }
   }
-  for (int v = 0; v < nval; ++v) vals[v] = ((const volatile double*)F.hpub)[v];
+  const volatile double* slot = F.hpub + 8 * (want & 1u);
+  for (int v = 0; v < nval; ++v) vals[v] = slot[v];
   return GLAM_OK;
 }
 
@@ -770,22 +783,23 @@ static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool eve
   F.iter = (int*)A(2 * sizeof(int));
   F.part = (double*)A(npart * 8);
   F.red = (double*)A(64 * 8);
-  F.dparams = (double*)A(4 * 8);
+  F.dparams = (double*)A(8 * 8);
+  F.stop = (int*)A(256);
   if (!ok) { F.err = "device allocation failed"; return GLAM_ENOMEM; }
   if (events)
     for (auto& e : F.ev)
       if (hipEventCreate(&e) != hipSuccess) { F.err = "hipEventCreate failed"; return GLAM_EDEVICE; }
   F.hred = F.host_alloc(64, &F.hred_dev);
-  F.hparams = F.host_alloc(4);
-  F.hpub = F.host_alloc(16, &F.hpub_dev);
+  F.hparams = F.host_alloc(8);
+  F.hpub = F.host_alloc(32, &F.hpub_dev);   // two slots of 8 published values, the sequence number at [24]
   for (int j = 0; j < 3; ++j) F.hx[j] = F.host_alloc((size_t)prob->n[j] * prob->p[j]);
   if (!F.hred || !F.hparams || !F.hpub || !F.hx[0] || !F.hx[1] || !F.hx[2]) {
     F.err = "pinned host allocation failed";
     return GLAM_ENOMEM;
   }
-  F.hseq = (unsigned*)(F.hpub + 8);
+  F.hseq = (unsigned*)(F.hpub + 24);
   *F.hseq = 0u;
-  F.hseq_dev = (unsigned*)(F.hpub_dev + 8);
+  F.hseq_dev = (unsigned*)(F.hpub_dev + 24);
   F.seq_dev = (unsigned*)A(256);
   if (!F.seq_dev || hipMemsetAsync(F.seq_dev, 0, 256, F.s) != hipSuccess) {
     F.err = "device allocation failed";
@@ -1117,6 +1131,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     F.no_l1 = 1;
   }
   F.incst = F.dt != DT_F64 && !F.gram && opt->nu >= 1.0;
+  F.runahead = F.incst;
   F.restart = opt->extrapolation == 0 && !F.gram && opt->nu >= 1.0;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);
@@ -1282,23 +1297,59 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       } else {
       F.hparams[0] = lam;
       F.hparams[1] = delta;
-      PCHK(hipMemcpyAsync(F.dparams, F.hparams, 2 * sizeof(double), hipMemcpyHostToDevice, F.s));
+      F.hparams[4] = lam_scale;            // the device's copy of the convergence test below
+      F.hparams[5] = tol_in;
+      F.hparams[6] = 4.0 * kEps[F.dt];
+      PCHK(hipMemcpyAsync(F.dparams, F.hparams, 7 * sizeof(double), hipMemcpyHostToDevice, F.s));
+      // run ahead (the increment-state chain loop): one block of iterations is queued beyond the
+      // one whose check the host reads next; the reduction ending each block applies the
+      // convergence test on the device and, once it holds, the queued kernels do nothing
+      const bool ra = F.runahead && incst;
+      if (ra) PCHK(hipMemsetAsync(F.stop, 0, sizeof(int), F.s));
       double best = INFINITY, window_best = INFINITY;
       int window_start = 0;
-      while (it < opt->max_inner) {
-        int nb = 0;
-        const int m = std::min(check_every, opt->max_inner - it);
-        const long long gi = path_inner + inner_total + it;
-        const bool sample = opt->profile_every > 0 && (gi / check_every) % std::max(1, opt->profile_every / check_every) == 0;
-        if (opt->graph_mode == 0 && m == check_every && !sample) RCHK(inner_block_graph(F, m, &nb));
-        else RCHK(inner_block_eager(F, m, sample, &nb));
+      int it_q = 0;              // inner iterations queued
+      int inflight[2] = {0, 0};  // sizes of the queued blocks whose checks are not read yet
+      int nq = 0;
+      bool stopping = false;     // the loop has ended: nothing more is queued
+      int nb = 0;
+      auto queue_block = [&]() -> int {
+        const int m = std::min(check_every, opt->max_inner - it_q);
+        if (m <= 0) return GLAM_OK;
+        const long long gi = path_inner + inner_total + it_q;
+        // a sampled block (events around its kernels) is queued only with nothing in flight, so
+        // that it is never a block the device skips
+        const bool sample = nq == 0 && opt->profile_every > 0 &&
+                            (gi / check_every) % std::max(1, opt->profile_every / check_every) == 0;
+        const int r = opt->graph_mode == 0 && m == check_every && !sample ? inner_block_graph(F, m, &nb)
+                                                                          : inner_block_eager(F, m, sample, &nb);
+        if (r) return r;
+        inflight[nq++] = m;
+        it_q += m;
+        return GLAM_OK;
+      };
+      RCHK(queue_block());
+      while (nq > 0) {
+        if (ra && !stopping && nq < 2) RCHK(queue_block());
+        const int m = inflight[0];
+        inflight[0] = inflight[1];
+        --nq;
+        double chk[ADJ_NSUM + 1];
+        RCHK(wait_published(F, chk, ADJ_NSUM + 1));
+        if (chk[ADJ_NSUM] != 0.0) {
+          // skipped on the device (the loop ended at an earlier block): undo the parity flips
+          // of its increment buffers that were booked when it was queued
+          if (m & 1) F.gpar ^= 1;
+          continue;
+        }
         it += m;
-        double chk[2];
-        RCHK(wait_published(F, chk, 2));
         RCHK(collect_sample(F));
         kin = chk[0] / lam_scale;
         // rounding floor of the low-precision chain output (a lower bound of its error)
         noise = 4.0 * kEps[F.dt] * chk[1] / lam_scale;
+        // a block that was in flight when the host ended the loop ran in full: its check values
+        // are the loop's last ones (its last iterate is theta~)
+        if (stopping) continue;
         best = std::min(best, kin);
         // the window counts inner iterations (the checks of the requested interval): where every
         // iteration is checked (Gamma-log, tensor-product and unit weights) it spans 10 or 20 times
@@ -1306,14 +1357,21 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         if (it - window_start >= (exact_model ? kStallChecks : kStallChecksLineSearch) * opt->check_every) {
           // stalled: no 2x progress over the window -> leave for an FP64 re-anchor (which
           // also restarts the extrapolation)
-          if (!(best < 0.5 * window_best) && F.dt != DT_F64) break;
+          if (!(best < 0.5 * window_best) && F.dt != DT_F64) {
+            stopping = true;
+            continue;
+          }
           window_best = best;
           window_start = it;
         }
         if (log_level >= 2)
           fprintf(stderr, "[glam]   lambda %d k %d it %d kin %.3e noise %.3e\n", l, k, it, kin, noise);
-        if (!std::isfinite(kin)) break;
-        if (kin <= std::max(tol_in, noise)) break;
+        // (the device applies the same test to the same values when it runs ahead)
+        if (!std::isfinite(kin) || kin <= std::max(tol_in, noise)) {
+          stopping = true;
+          continue;
+        }
+        if (!ra) RCHK(queue_block());
       }
       }
       inner_total += it;

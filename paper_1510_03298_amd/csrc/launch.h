@@ -76,6 +76,7 @@ struct SlabParams {
   const double* y_std;
   const float* y_tiled;   // NLL, one-wave-per-slab kernel: the counts tiled like v_int (FP32), used instead of y_std
   double* partials;   // per-workgroup partial sums [grid][2]
+  const int* stop;    // optional: the kernel does nothing when *stop != 0 (the inner loop has ended)
 };
 
 enum AdjEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_PROX = 2, EPI_PROX_BT = 3 };
@@ -143,6 +144,7 @@ struct AdjIncParams {
   int no_l1;             // 1: the ridge penalty (no l1 term)
   double* partials;      // per-workgroup [nblk][ADJ_NSUM], slab_adj's layout
   int xmap;              // tile order: 0 row blocks fastest; 1 XCD-aware (each XCD a range of row blocks)
+  const int* stop;       // optional: the kernel does nothing when *stop != 0 (the inner loop has ended)
 };
 inline long long adj_tiled_len(const Geom& G) { return (long long)((G.P12 + 15) / 16) * ((G.p3 + 15) / 16) * 256; }
 hipError_t launch_slab_adj_inc(int dt, const AdjIncParams& P, int* nblk_out, hipStream_t s);
@@ -171,6 +173,7 @@ struct FwdParams {
   const void* X3f;    // chain type, k-blocked (K = p3, C = n3)
   void* T1;           // chain type, slab-major [n3][P12]
   int* iter;          // optional: incremented once by the first thread
+  const int* stop;    // optional: the kernel does nothing when *stop != 0 (the inner loop has ended)
 };
 
 // batched proximal step (many independent problems per launch, three launches per step)
@@ -295,13 +298,17 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // summation order is fixed, so results are reproducible run to run.
 hipError_t launch_reduce(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
                          hipStream_t s);
-// the same, also published to mapped host memory hout[0..nval) followed by the sequence
-// number *hseq = ++*seq_dev (device counter), for a host wait without a copy (nval <= 8);
+// the same, also published to mapped host memory, slot s % 2 of hout (8 doubles per slot:
+// the nval values, then the "skipped" flag) followed by the sequence number *hseq = s = ++*seq_dev
+// (device counter), for a host wait without a copy (nval < 8; two blocks may be in flight);
 // restart_iter != NULL: *restart_iter = 0 when value restart_slot is > 0 (the restarted
-// extrapolation sequence of the inner loop)
+// extrapolation sequence of the inner loop).  stop != NULL: the inner loop's convergence test on
+// the device, crit = {lambda scale, tol_in, 4 eps}: *stop = 1 when value 0 / crit[0] is not finite or
+// is <= max(crit[1], crit[2] value 1 / crit[0]) (the host's own test, in the same arithmetic); a
+// launch that finds *stop already set publishes only the "skipped" flag 1 and the sequence number
 hipError_t launch_reduce_publish(const double* partials, int nblk, int nval, const int* ops, double scale, double* out,
                                  double* hout, unsigned* seq_dev, unsigned* hseq, hipStream_t s, int restart_slot = -1,
-                                 int* restart_iter = nullptr);
+                                 int* restart_iter = nullptr, int* stop = nullptr, const double* crit = nullptr);
 // same with partials[b * stride + v], v < nval <= stride
 hipError_t launch_reduce_strided(const double* partials, int nblk, int stride, int nval, const int* ops, double scale,
                                  double* out, hipStream_t s);

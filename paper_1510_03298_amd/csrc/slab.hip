@@ -157,6 +157,7 @@ __device__ inline void fwd_tile(const FwdParams& P, int bx, int by) {
 
 template <typename T>
 __global__ __launch_bounds__(WG) void k_slab_fwd(FwdParams P) {
+  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
   if (P.iter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *P.iter += 1;
   fwd_tile<T>(P, blockIdx.x, blockIdx.y);
 }
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
   typedef Tr<T> R;
   typedef typename R::frag_t Fr;
   constexpr int NB = KNB<T>::v;
+  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
   if (P.iter && blockIdx.x == 0 && threadIdx.x == 0) *P.iter += 1;
   const Geom& G = P.G;
   const int NBX = (G.P12 + 63) >> 6, NBY = (G.n3 + 63) >> 6, NT = NBX * NBY, per = (NT + 7) >> 3;
@@ -908,6 +910,7 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
 template <typename T, int MODE, bool HAS_V, int SPW, int NPART, bool P16, bool LDSF = false>
 __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
   __shared__ __align__(16) unsigned char lds[wave_lds_bytes<T, SPW, NPART>() + (LDSF ? WAVE_FRAGS * 64 * 16 : 0)];
+  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
   // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
   // the chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
   const int b = blockIdx.x, x = b & 7, jj = b >> 3;
@@ -1085,7 +1088,6 @@ __device__ inline void adj_tile_of(int b, int NBM, int NBN, int xmap, int* bm, i
 
 int slab_adj_inc_blocks(const Geom& G, int xmap) {
   const int T = ((G.P12 + 15) / 16) * ((G.p3 + 15) / 16);
-  if (xmap == 2) return ((((G.P12 + 15) / 16) + 3) / 4) * ((G.p3 + 15) / 16);
   return xmap == 0 ? T : 8 * ((T + 7) / 8);
 }
 
@@ -1095,6 +1097,7 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
   typedef typename R::acc_t A;
   __shared__ double sred[4 * ADJ_NSUM];
   __shared__ A red[WG / 64][256];
+  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
   const Geom& G = P.G;
   const int NBM = (G.P12 + 15) >> 4, NBN = (G.p3 + 15) >> 4;
   int bm, bn, tile;
@@ -1165,225 +1168,13 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
   }
 }
 
-// Form 2: a workgroup of 4 waves covers 64 rows (4 row blocks) x 16 columns; each wave owns one
-// 16 x 16 tile over the whole contraction (all its k-blocks requested in one round), and its
-// epilogue runs from the accumulator registers (no LDS exchange).
-template <typename T>
-__global__ __launch_bounds__(WG) void k_slab_adj_inc_rows(AdjIncParams P) {
-  typedef Tr<T> R;
-  __shared__ double sred[4 * ADJ_NSUM];
-  const Geom& G = P.G;
-  const int NBM = (G.P12 + 15) >> 4;
-  const int NB4 = (NBM + 3) >> 2;
-  const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int b4 = blockIdx.x % NB4, bn = blockIdx.x / NB4;
-  const int bm = 4 * b4 + w;
-  const T* __restrict__ S2 = (const T*)P.S2;
-  const T* __restrict__ X3 = (const T*)P.X3a;
-  const int m = bm * 16 + r, k3 = bn * 16 + r;
-  const bool am = bm < NBM && m < G.P12, bk = k3 < G.p3;
-  // epilogue elements of this lane: (16 bm + 4 g + i, 16 bn + r), i = 0..3
-  const long long tb = ((long long)bn * NBM + bm) * 256;
-  double e_g[4], e_t[4], e_w[4];
-  float e_d[4], e_dp[4], e_q[4];
-  bool ok[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int em = bm * 16 + 4 * g + i;
-    ok[i] = bm < NBM && em < G.P12 && k3 < G.p3;
-    const long long e = tb + (4 * g + i) * 16 + r;
-    e_g[i] = ok[i] ? P.gT[e] : 0.0;
-    e_t[i] = ok[i] ? P.tT[e] : 0.0;
-    e_w[i] = ok[i] && P.penT ? P.penT[e] : 1.0;
-    e_d[i] = ok[i] ? P.dcur[e] : 0.f;
-    e_dp[i] = ok[i] ? P.dprev[e] : 0.f;
-    e_q[i] = ok[i] ? P.q_in[e] : 0.f;
-  }
-  typename R::accv_t acc = R::zero();
-  const T* pa = P.s2_kb4 ? S2 + ((long long)g * G.P12 + m) * 4 : S2 + (long long)m * 16 + 4 * g;
-  const T* pb = X3 + (long long)k3 * 16 + 4 * g;
-  const long long sa = (long long)G.P12 * 16, sb = (long long)G.p3 * 16;
-  kblock_loop<T, 64>(acc, pa, pb, sa, sb, 0, 1, G.KBN3, am, bk);
-  double red_kkt = 0.0, red_noise = 0.0, red_inc = 0.0;
-  const double lam = P.dparams[0], delta = P.dparams[1];
-  const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double om = (l_iter - 1.0) / (l_iter + 2.0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (!ok[i]) continue;
-    const int em = bm * 16 + R::kidx(g, i);   // accumulator row kidx(g, i) = 4 g + i
-    const long long e = tb + (4 * g + i) * 16 + r;
-    const double incg = P.scale * (double)acc[i];
-    const double gx = e_g[i] + incg;
-    const bool z = __builtin_isnan(e_d[i]), zp = __builtin_isnan(e_dp[i]);
-    const double x = z ? 0.0 : e_t[i] + (double)e_d[i];
-    const double xp = zp ? 0.0 : e_t[i] + (double)e_dp[i];
-    const double lw = lam * e_w[i];
-    const double gs = gx + 2.0 * P.alpha * lw * x;
-    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0));
-    red_noise = fmax(red_noise, fabs(incg));
-    const double gy = gx + om * (incg - (double)e_q[i]);
-    const double yv = x + om * (x - xp);
-    const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
-    const double dn = xn - e_t[i];
-    P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
-    P.q_out[e] = (float)incg;
-    red_inc = fmax(red_inc, fabs(dn));
-    ((T*)P.inc)[((long long)bn * G.P12 + em) * 16 + kpos<T>(r)] = R::from_acc((typename R::acc_t)dn);
-  }
-  double v[ADJ_NSUM] = {red_kkt, red_noise, 0.0, 0.0, red_inc, 0.0};
-  const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-  block_reduce<ADJ_NSUM>(v, ops, sred);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < ADJ_NSUM; ++q) P.partials[(long long)blockIdx.x * ADJ_NSUM + q] = v[q];
-  }
-}
-
-// Form 3: 32 x 32 workgroup tiles (2 x 2 state tiles), split-K over the 4 waves, each wave all
-// four 16 x 16 products of its k-blocks (every fragment feeds two products).
-template <typename T>
-__global__ __launch_bounds__(WG) void k_slab_adj_inc32(AdjIncParams P) {
-  typedef Tr<T> R;
-  typedef typename R::frag_t F;
-  __shared__ double sred[4 * ADJ_NSUM];
-  __shared__ float red[WG / 64][1024];
-  const Geom& G = P.G;
-  const int NBM = (G.P12 + 15) >> 4;
-  const int NB2 = (NBM + 1) >> 1;
-  const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
-  const int bm2 = blockIdx.x % NB2, bn2 = blockIdx.x / NB2;
-  const T* __restrict__ S2 = (const T*)P.S2;
-  const T* __restrict__ X3 = (const T*)P.X3a;
-  const int t = threadIdx.x;
-  // epilogue: element t of each of the 4 state tiles (sub-tile s: row block 2 bm2 + (s & 1), column block 2 bn2 + (s >> 1))
-  double e_g[4], e_t[4], e_w[4];
-  float e_d[4], e_dp[4], e_q[4];
-  bool ok[4];
-#pragma unroll
-  for (int sb = 0; sb < 4; ++sb) {
-    const int bm = 2 * bm2 + (sb & 1), bn = 2 * bn2 + (sb >> 1);
-    const int em = bm * 16 + (t >> 4), ek = bn * 16 + (t & 15);
-    ok[sb] = em < G.P12 && ek < G.p3;
-    const long long e = ((long long)bn * NBM + bm) * 256 + t;
-    e_g[sb] = ok[sb] ? P.gT[e] : 0.0;
-    e_t[sb] = ok[sb] ? P.tT[e] : 0.0;
-    e_w[sb] = ok[sb] && P.penT ? P.penT[e] : 1.0;
-    e_d[sb] = ok[sb] ? P.dcur[e] : 0.f;
-    e_dp[sb] = ok[sb] ? P.dprev[e] : 0.f;
-    e_q[sb] = ok[sb] ? P.q_in[e] : 0.f;
-  }
-  typename R::accv_t acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = R::zero();
-  const T* pa[2];
-  const T* pb[2];
-  bool am[2], bk[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int m = 32 * bm2 + 16 * h + r, k3 = 32 * bn2 + 16 * h + r;
-    am[h] = m < G.P12;
-    bk[h] = k3 < G.p3;
-    pa[h] = P.s2_kb4 ? S2 + ((long long)g * G.P12 + m) * 4 : S2 + (long long)m * 16 + 4 * g;
-    pb[h] = X3 + (long long)k3 * 16 + 4 * g;
-  }
-  const long long sa = (long long)G.P12 * 16, sb_ = (long long)G.p3 * 16;
-  const int nkb = w < G.KBN3 ? (G.KBN3 - w + 3) / 4 : 0;
-  constexpr int NB = 8;
-  for (int j = 0; j < nkb; j += NB) {
-    F fa[2][NB], fb[2][NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const bool in = j + q < nkb;
-      const long long kb = w + (long long)(j + q) * 4;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        fa[h][q] = (in && am[h]) ? load_frag(pa[h] + kb * sa) : zero_frag<T>();
-        fb[h][q] = (in && bk[h]) ? load_frag(pb[h] + kb * sb_) : zero_frag<T>();
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) MmaBlocks<T, NB>::run(acc[a][c], fa[a], fb[c]);
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) red[w][(c * 2 + a) * 256 + R::kidx(g, i) * 16 + r] = acc[a][c][i];
-  __syncthreads();
-  const double lam = P.dparams[0], delta = P.dparams[1];
-  const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double om = (l_iter - 1.0) / (l_iter + 2.0);
-  double red_kkt = 0.0, red_noise = 0.0, red_inc = 0.0;
-#pragma unroll
-  for (int sb = 0; sb < 4; ++sb) {
-    if (!ok[sb]) continue;
-    const int bm = 2 * bm2 + (sb & 1), bn = 2 * bn2 + (sb >> 1);
-    const int em = bm * 16 + (t >> 4), ek = bn * 16 + (t & 15);
-    const long long e = ((long long)bn * NBM + bm) * 256 + t;
-    const int qi = sb * 256 + t;
-    const double a = (double)(red[0][qi] + red[1][qi] + red[2][qi] + red[3][qi]);
-    const double incg = P.scale * a;
-    const double gx = e_g[sb] + incg;
-    const bool z = __builtin_isnan(e_d[sb]), zp = __builtin_isnan(e_dp[sb]);
-    const double x = z ? 0.0 : e_t[sb] + (double)e_d[sb];
-    const double xp = zp ? 0.0 : e_t[sb] + (double)e_dp[sb];
-    const double lw = lam * e_w[sb];
-    const double gs = gx + 2.0 * P.alpha * lw * x;
-    red_kkt = fmax(red_kkt, x != 0.0 ? fabs(gs + copysign(P.no_l1 ? 0.0 : lw, x)) : fmax(fabs(gs) - (P.no_l1 ? 0.0 : lw), 0.0));
-    red_noise = fmax(red_noise, fabs(incg));
-    const double gy = gx + om * (incg - (double)e_q[sb]);
-    const double yv = x + om * (x - xp);
-    const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
-    const double dn = xn - e_t[sb];
-    P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
-    P.q_out[e] = (float)incg;
-    red_inc = fmax(red_inc, fabs(dn));
-    ((T*)P.inc)[((long long)(ek >> 4) * G.P12 + em) * 16 + kpos<T>(ek & 15)] = R::from_acc((typename R::acc_t)dn);
-  }
-  double v[ADJ_NSUM] = {red_kkt, red_noise, 0.0, 0.0, red_inc, 0.0};
-  const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-  block_reduce<ADJ_NSUM>(v, ops, sred);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < ADJ_NSUM; ++q) P.partials[(long long)blockIdx.x * ADJ_NSUM + q] = v[q];
-  }
-}
-
-static int adj_inc32_blocks(const Geom& G);
-static int adj_inc_rows_blocks(const Geom& G);
 int slab_adj_inc_partials(const Geom& G, int xmap) {
-  if (xmap == 3) return adj_inc32_blocks(G);
-  if (xmap == 2) return adj_inc_rows_blocks(G);
+  (void)xmap;   // both tile orders write one row of partials per tile
   return ((G.P12 + 15) / 16) * ((G.p3 + 15) / 16);
 }
 
-static int adj_inc32_blocks(const Geom& G) { return ((((G.P12 + 15) / 16) + 1) / 2) * ((((G.p3 + 15) / 16) + 1) / 2); }
-
-static int adj_inc_rows_blocks(const Geom& G) { return ((((G.P12 + 15) / 16) + 3) / 4) * ((G.p3 + 15) / 16); }
-
 hipError_t launch_slab_adj_inc(int dt, const AdjIncParams& P, int* nblk_out, hipStream_t s) {
-  if (P.xmap == 3) {
-    const int nb = adj_inc32_blocks(P.G);
-    if (nblk_out) *nblk_out = nb;
-    if (dt == DT_F32) hipLaunchKernelGGL(k_slab_adj_inc32<float>, dim3(nb), dim3(WG), 0, s, P);
-    else if (dt == DT_BF16) hipLaunchKernelGGL(k_slab_adj_inc32<bf16>, dim3(nb), dim3(WG), 0, s, P);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-  }
-  if (P.xmap == 2) {
-    const int nb = adj_inc_rows_blocks(P.G);
-    if (nblk_out) *nblk_out = nb;
-    if (dt == DT_F32) hipLaunchKernelGGL(k_slab_adj_inc_rows<float>, dim3(nb), dim3(WG), 0, s, P);
-    else if (dt == DT_BF16) hipLaunchKernelGGL(k_slab_adj_inc_rows<bf16>, dim3(nb), dim3(WG), 0, s, P);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-  }
+  if (P.xmap != 0 && P.xmap != 1) return hipErrorInvalidValue;
   const int nb = slab_adj_inc_blocks(P.G, P.xmap);
   if (nblk_out) *nblk_out = ((P.G.P12 + 15) / 16) * ((P.G.p3 + 15) / 16);   // partial rows written
   if (dt == DT_F32) hipLaunchKernelGGL(k_slab_adj_inc<float>, dim3(nb), dim3(WG), 0, s, P);
