@@ -229,6 +229,9 @@ struct Fit {
   // convergence on the device and sets *stop, after which the queued kernels do nothing
   bool runahead = false;
   int* stop = nullptr;
+  // eta of the outer steps is written out only where it is read: the Armijo passes (every model
+  // but the exact Gaussian one) and the tensor-product weights
+  bool keep_eta = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_m = 0;                 // inner iterations per graph replay
@@ -308,7 +311,7 @@ static int family_enqueue(Fit& F, const double* theta_dev, double lambda) {
   FCHK(launch_slab_fwd(DT_F64, fw, F.s));
   SlabParams sp{};
   sp.G = G; sp.img = F.imgd; sp.T1 = F.T1d; sp.S2 = F.S2d;
-  sp.y_int = F.y_int; sp.a_int = F.a_int; sp.eta_int = F.eta_int;
+  sp.y_int = F.y_int; sp.a_int = F.prob->obs_w ? F.a_int : nullptr; sp.eta_int = F.keep_eta ? F.eta_int : nullptr;
   sp.v_out = F.v_int; sp.v_out_f32 = F.dt != DT_F64; sp.family = F.family; sp.partials = F.part;
   int nbc = 0;
   FCHK(launch_slab_chain(DT_F64, SM_FAMILY, sp, &nbc, F.s));
@@ -1132,6 +1135,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   }
   F.incst = F.dt != DT_F64 && !F.gram && opt->nu >= 1.0;
   F.runahead = F.incst;
+  F.keep_eta = !(prob->family == GLAM_GAUSSIAN && prob->obs_w == nullptr) || F.kron;
   F.restart = opt->extrapolation == 0 && !F.gram && opt->nu >= 1.0;
   {
     const int r = fit_setup(F, prob, opt->nu < 1.0, opt->profile_every > 0);

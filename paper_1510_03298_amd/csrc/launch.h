@@ -67,8 +67,8 @@ struct SlabParams {
   const void* v_int;  // FUSED weights (tiled, accumulation type) or NULL = 1
   // FAMILY (FP64 chain)
   const double* y_int;
-  const double* a_int;
-  double* eta_int;
+  const double* a_int;    // prior weights (tiled), or NULL: 1
+  double* eta_int;        // eta written out (tiled), or NULL: not kept
   void* v_out;        // tiled weights written for the inner loop (FP32 or FP64), may be NULL
   int v_out_f32;      // 1: v_out is float, 0: double
   int family;         // glam_family: 0 Gaussian, 1 Poisson, 2 Binomial, 3 Gamma

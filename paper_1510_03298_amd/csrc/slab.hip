@@ -410,7 +410,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
               const long long ti = tbase + R::kidx(g, i);
               const double eta = (double)E[i];
               const double y = P.y_int[ti];
-              const double a = P.a_int[ti];
+              const double a = P.a_int ? P.a_int[ti] : 1.0;   // (no prior weights: a = 1 on valid cells)
               // score u = a vartheta'(eta) (y - mu), weight w = vartheta'(eta) (g^-1)'(eta) (App. B)
               double wgt, nll, u;
               if (P.family == 1) {          // Poisson, log link
@@ -435,7 +435,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
                 nll = 0.5 * a * d * d;
                 u = a * d;
               }
-              P.eta_int[ti] = eta;
+              if (P.eta_int) P.eta_int[ti] = eta;   // kept for the Armijo passes and the V-hat factors
               if (P.v_out) {
                 if (P.v_out_f32) ((float*)P.v_out)[ti] = valid ? (float)wgt : 0.f;
                 else ((double*)P.v_out)[ti] = valid ? wgt : 0.0;
