@@ -261,3 +261,23 @@ def test_sec65_p_greater_than_n_path(fam, dt):
             u = s * r
             dual = (0.5 * float(y @ y) - 0.5 * float((y - u) @ (y - u))) / n
             assert 0.0 <= F1 - dual <= 1e-6 * abs(F1), (F1, dual)
+
+
+def test_precision_escalation_on_the_generic_path():
+    """Section 6.5's Poisson design at r = 3 (correlated Gaussian factors, X^T X condition number in
+    the tens of millions) through the generic solver: the BF16 chain cannot refine it, the fit
+    continues one rung up (FP32, then FP64), and every model still meets the oracle's KKT bar."""
+    torch, glam = need_gpu()
+    d = inputs.config_sim(r=3, family="poisson")
+    print(f"generic escalation n={d.n} p={d.p}", flush=True)
+    Xd = [glam.to_device_colmajor(X, 0) for X in d.X]
+    Yd = glam.to_device_colmajor(d.Y, 0)
+    res = glam.fit_path_multi([(Xd, d.p)], Yd, d.n, "poisson", nlambda=40, lambda_min_ratio=0.02, dtype=2,
+                              kkt_tol=1e-6)
+    assert res.code == 0 and res.n_done == 40
+    assert 0 <= res.escalated_at < 40
+    lm = O.lambda_max("poisson", d.X, d.Y)
+    for l in (res.escalated_at, 39):
+        th = glam.from_colmajor(res.theta[l], d.p)
+        g = O.smooth_gradient("poisson", d.X, th, d.Y)
+        assert O.kkt_residual(th, g, res.lambdas[l], lm) <= 1e-6

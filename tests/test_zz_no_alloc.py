@@ -37,7 +37,8 @@ def test_static_forward_matches_workspace_forward(dt):
 
 def test_static_forward_reordered_and_refused_sizes():
     """A problem run in another mode order (its permuted input and output also live in the static
-    scratch), and sizes whose workspace exceeds the static scratch: refused on the host before any
+    scratch), one that no order fits (the generic chain's transposed factors and intermediates live
+    there), and sizes whose workspace exceeds the static scratch: refused on the host before any
     device work."""
     torch, glam = need_gpu()
     n, p = (120, 40, 20), (60, 20, 10)        # p_1 > 32: reordered
@@ -51,6 +52,17 @@ def test_static_forward_reordered_and_refused_sizes():
     eta_w = glam.rho_forward(Xd, th, n, p, 1)
     torch.cuda.synchronize()
     assert torch.equal(eta_s, eta_w)
+    n, p = (20, 10, 60), (60, 30, 180)        # no mode order fits the slab kernels: the generic GEMM chain
+    Xs = [rng.standard_normal((nj, pj)) for nj, pj in zip(n, p)]
+    Th = rng.standard_normal(p)
+    Xg = [glam.to_device_colmajor(X, 1) for X in Xs]
+    thg = glam.to_device_colmajor(Th, 1)
+    eta_g = torch.empty(int(np.prod(n)), dtype=torch.float32, device=th.device)
+    glam.rho_forward_static(Xg, thg, n, p, 1, eta_g)
+    eta_w = glam.rho_forward(Xg, thg, n, p, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(eta_g, eta_w)
+    assert rel_inf(glam.from_colmajor(eta_g, n), O.H(Xs, Th)) <= TOL[1]
     big_n, big_p = (600, 100, 100), (40, 30, 30)   # reordered (mode 1 last): needs n * 8 = 48 MB of workspace
     assert glam.rho_workspace_size(big_n, big_p, 0) > glam.STATIC_SCRATCH_BYTES
     with pytest.raises(glam.GlamError, match="static scratch"):
