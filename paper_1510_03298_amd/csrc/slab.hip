@@ -289,8 +289,9 @@ __device__ inline void chain_stage(const void* img, int image_bytes, unsigned ch
   __syncthreads();
 }
 
-// modes 1 and 2 of one slab i3 (the factor image is already in LDS)
-template <typename T, int PT, int MODE>
+// modes 1 and 2 of one slab i3 (the factor image is already in LDS).  FAM: the family of the
+// SM_FAMILY update when known at compile time (0..3), or -1 (read from P.family)
+template <typename T, int PT, int MODE, int FAM = -1>
 __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, unsigned char* smem_raw, int i3,
                                   double& s_nll, double& s_vmax) {
   typedef Tr<T> R;
@@ -413,18 +414,19 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
               const double a = P.a_int ? P.a_int[ti] : 1.0;   // (no prior weights: a = 1 on valid cells)
               // score u = a vartheta'(eta) (y - mu), weight w = vartheta'(eta) (g^-1)'(eta) (App. B)
               double wgt, nll, u;
-              if (P.family == 1) {          // Poisson, log link
+              const int fam = FAM >= 0 ? FAM : P.family;
+              if (fam == 1) {               // Poisson, log link
                 const double mu = exp(eta);
                 wgt = mu;
                 nll = a * (mu - y * eta);
                 u = a * (y - mu);
-              } else if (P.family == 2) {   // Binomial, logit link: mu = 1 / (1 + e^-eta)
+              } else if (fam == 2) {        // Binomial, logit link: mu = 1 / (1 + e^-eta)
                 const double ex = exp(-fabs(eta));
                 const double mu = eta >= 0.0 ? 1.0 / (1.0 + ex) : ex / (1.0 + ex);
                 wgt = ex / ((1.0 + ex) * (1.0 + ex));   // mu (1 - mu) without cancellation
                 nll = a * (fmax(eta, 0.0) + log1p(ex) - y * eta);
                 u = a * (y - mu);
-              } else if (P.family == 3) {   // Gamma, log link (vartheta = -e^-eta): unit weight
+              } else if (fam == 3) {        // Gamma, log link (vartheta = -e^-eta): unit weight
                 const double emi = exp(-eta);
                 wgt = 1.0;
                 nll = a * (y * emi + eta);
@@ -541,7 +543,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
     __syncthreads();
 }
 
-template <typename T, int PT, int MODE>
+template <typename T, int PT, int MODE, int FAM = -1>
 __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
   typedef typename Tr<T>::acc_t A;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
   const ChainLayout L = chain_layout(P.G, (int)sizeof(T), (int)sizeof(A));
   chain_stage(P.img, L.image_bytes, smem_raw);
   double s_nll = 0.0, s_vmax = 0.0;
-  for (int i3 = blockIdx.x; i3 < P.G.n3; i3 += gridDim.x) chain_slab<T, PT, MODE>(P, L, smem_raw, i3, s_nll, s_vmax);
+  for (int i3 = blockIdx.x; i3 < P.G.n3; i3 += gridDim.x) chain_slab<T, PT, MODE, FAM>(P, L, smem_raw, i3, s_nll, s_vmax);
   if (MODE == SM_FAMILY || MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
     double v[2] = {s_nll, s_vmax};
     const int ops[2] = {0, 1};
@@ -1467,16 +1469,26 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
   if (nblk_out) *nblk_out = nb;
   dim3 grid(nb), blk(WG);
   if (mode == SM_FAMILY) {
-    if (dt != DT_F64) return hipErrorInvalidValue;
-    if (P.G.PT == 1) {
-      auto fn = k_slab_chain<double, 1, SM_FAMILY>;
-      set_lds(fn, lds);
-      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);
-    } else {
-      auto fn = k_slab_chain<double, 2, SM_FAMILY>;
-      set_lds(fn, lds);
-      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);
-    }
+    // one kernel per family and register tile count: with the family fixed, the update's FP64
+    // math of the other families leaves the kernel (the Gaussian form drops from 256 registers)
+    if (dt != DT_F64 || P.family < 0 || P.family > 3) return hipErrorInvalidValue;
+#define GLAM_FAM(PTV, F)                                   \
+    do {                                                   \
+      auto fn = k_slab_chain<double, PTV, SM_FAMILY, F>;   \
+      set_lds(fn, lds);                                    \
+      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);        \
+    } while (0)
+#define GLAM_FAMS(PTV)                                     \
+    do {                                                   \
+      if (P.family == 0) GLAM_FAM(PTV, 0);                 \
+      else if (P.family == 1) GLAM_FAM(PTV, 1);            \
+      else if (P.family == 2) GLAM_FAM(PTV, 2);            \
+      else GLAM_FAM(PTV, 3);                               \
+    } while (0)
+    if (P.G.PT == 1) GLAM_FAMS(1);
+    else GLAM_FAMS(2);
+#undef GLAM_FAMS
+#undef GLAM_FAM
     return hipGetLastError();
   }
   if (wave_chain_used(dt, mode, P.G)) {
