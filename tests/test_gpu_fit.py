@@ -151,20 +151,33 @@ def test_invalid_data_rejected():
         glam.fit_path(Xd, bad, d.n, d.p, "gaussian", nlambda=2, lambda_min_ratio=0.5)
 
 
-@pytest.mark.parametrize("dt", [1, 2])
-def test_graph_replay_matches_stream_launches(dt):
+@pytest.mark.parametrize("dt,check_every", [(1, 10), (2, 10), (2, 3), (1, 7)])
+def test_graph_replay_matches_stream_launches(dt, check_every):
     """Inner blocks replayed as a captured HIP graph (many replays, with eager FP64
     steps and host synchronisations between them) give the same path, bit for bit,
-    as plain stream launches."""
+    as plain stream launches; so do blocks with timing samples (events and re-launches in the
+    block).  Odd block lengths exercise the run-ahead loop's parity bookkeeping of the increment
+    buffers when the device skips the block queued behind the converged one."""
     torch, glam = need_gpu()
     d = inputs.random_problem((23, 19, 37), (9, 7, 12), seed=25)
+    print(f"graph vs stream dt={dt} check_every={check_every}", flush=True)
     Xd, Yd, _ = _dev(glam, d)
-    kw = dict(nlambda=6, lambda_min_ratio=1e-2, dtype=dt, kkt_tol=1e-6, raise_on_error=False)
+    kw = dict(nlambda=6, lambda_min_ratio=1e-2, dtype=dt, kkt_tol=1e-6, raise_on_error=False,
+              check_every=check_every)
     r1 = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", graph=True, **kw)
     r2 = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", graph=False, **kw)
-    assert r1.code == r2.code == 0
+    r3 = glam.fit_path(Xd, Yd, d.n, d.p, "gaussian", graph=True, profile_every=4 * check_every, **kw)
+    assert r1.code == r2.code == r3.code == 0
     assert np.array_equal(r1.iters_inner, r2.iters_inner)
+    assert np.array_equal(r1.iters_inner, r3.iters_inner)
     assert torch.equal(r1.theta, r2.theta)
+    assert torch.equal(r1.theta, r3.theta)
+    assert r3.chain_samples > 0
+    lm = O.lambda_max("gaussian", d.X, d.Y)
+    for l in range(6):
+        th = _theta(glam, r1, l, d.p)
+        g = O.smooth_gradient("gaussian", d.X, th, d.Y)
+        assert O.kkt_residual(th, g, r1.lambdas[l], lm) <= 1e-6
 
 
 @pytest.mark.parametrize("fam,dt", [("gaussian", 0), ("gaussian", 1), ("poisson", 0), ("poisson", 1)])
