@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--nlambda", type=int, default=100)
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed runs of the other forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--profile-every", type=int, default=160,
+    ap.add_argument("--profile-every", type=int, default=800,
                     help="time one inner iteration in this many with HIP events (those blocks run un-captured)")
     ap.add_argument("--lambda-min-ratio", type=float, default=1e-4)
     ap.add_argument("--eager", action="store_true", help="launch every inner iteration eagerly (no HIP graphs)")

@@ -1314,6 +1314,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       int window_start = 0;
       int it_q = 0;              // inner iterations queued
       int inflight[2] = {0, 0};  // sizes of the queued blocks whose checks are not read yet
+      bool inflight_sample[2] = {false, false};   // ... and whether they carry a timing sample
       int nq = 0;
       bool stopping = false;     // the loop has ended: nothing more is queued
       int nb = 0;
@@ -1321,13 +1322,15 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
         const int m = std::min(check_every, opt->max_inner - it_q);
         if (m <= 0) return GLAM_OK;
         const long long gi = path_inner + inner_total + it_q;
-        // a sampled block (events around its kernels) is queued only with nothing in flight, so
-        // that it is never a block the device skips
-        const bool sample = nq == 0 && opt->profile_every > 0 &&
+        // a sampled block (events around its kernels) that the device skips is dropped from the
+        // timing when its check is read; two sampled blocks are never in flight together (one set
+        // of events)
+        const bool sample = opt->profile_every > 0 && !(nq > 0 && inflight_sample[nq - 1]) &&
                             (gi / check_every) % std::max(1, opt->profile_every / check_every) == 0;
         const int r = opt->graph_mode == 0 && m == check_every && !sample ? inner_block_graph(F, m, &nb)
                                                                           : inner_block_eager(F, m, sample, &nb);
         if (r) return r;
+        inflight_sample[nq] = sample;
         inflight[nq++] = m;
         it_q += m;
         return GLAM_OK;
@@ -1336,14 +1339,17 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       while (nq > 0) {
         if (ra && !stopping && nq < 2) RCHK(queue_block());
         const int m = inflight[0];
+        const bool sampled = inflight_sample[0];
         inflight[0] = inflight[1];
+        inflight_sample[0] = inflight_sample[1];
         --nq;
         double chk[ADJ_NSUM + 1];
         RCHK(wait_published(F, chk, ADJ_NSUM + 1));
         if (chk[ADJ_NSUM] != 0.0) {
           // skipped on the device (the loop ended at an earlier block): undo the parity flips
-          // of its increment buffers that were booked when it was queued
+          // of its increment buffers that were booked when it was queued, and drop its timing
           if (m & 1) F.gpar ^= 1;
+          if (sampled) F.pending = false;
           continue;
         }
         it += m;
