@@ -111,6 +111,41 @@ __device__ inline void kblock_loop(typename Tr<T>::accv_t& acc, const T* pa, con
   }
 }
 
+// kblock_loop for kernels that may find the inner loop ended: the flag value `stopped` (loaded
+// by the caller before any operand) is tested only once the first round of operand loads has been
+// issued, so that its latency overlaps theirs.  Returns false when the caller must exit (nothing
+// has been written).
+template <typename T, int NB>
+__device__ inline bool kblock_loop_or_stop(typename Tr<T>::accv_t& acc, const T* pa, const T* pb, long long sa,
+                                           long long sb, int kb0, int kstep, int nkb, bool am, bool bn, int stopped) {
+  typedef typename Tr<T>::frag_t F;
+  for (int j = 0; j < nkb; j += NB) {
+    // every lane loads (blocks beyond the contraction from block kb0, which exists; the caller
+    // points lanes outside the matrices at rows that exist; both zeroed below), so that the round
+    // of loads is straight-line code ahead of the test
+    F fa[NB], fb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const bool in = j + q < nkb;
+      const long long kb = in ? kb0 + (long long)(j + q) * kstep : kb0;
+      fa[q] = load_frag(pa + kb * sa);
+      fb[q] = load_frag(pb + kb * sb);
+    }
+    if (j == 0) {
+      asm volatile("" : "+v"(stopped) : : "memory");   // the loads above are issued before the flag is waited on
+      if (__builtin_amdgcn_readfirstlane(stopped)) return false;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const bool in = j + q < nkb;
+      if (!(in && am)) fa[q] = zero_frag<T>();
+      if (!(in && bn)) fb[q] = zero_frag<T>();
+    }
+    MmaBlocks<T, NB>::run(acc, fa, fb);
+  }
+  return !(nkb <= 0 && stopped);
+}
+
 // k-blocks loaded per round (a short contraction is then a single round of loads)
 template <typename T> struct KNB { static constexpr int v = 4; };
 template <> struct KNB<bf16> { static constexpr int v = 16; };
@@ -171,8 +206,9 @@ __global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
   typedef Tr<T> R;
   typedef typename R::frag_t Fr;
   constexpr int NB = KNB<T>::v;
-  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
-  if (P.iter && blockIdx.x == 0 && threadIdx.x == 0) *P.iter += 1;
+  // the inner loop has ended when *stop != 0 (the whole grid then exits before writing anything);
+  // the flag is requested first and tested once the operand loads are in flight
+  int stopped = P.stop ? __hip_atomic_load(P.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;   // a vector load (in order with the operand loads)
   const Geom& G = P.G;
   const int NBX = (G.P12 + 63) >> 6, NBY = (G.n3 + 63) >> 6, NT = NBX * NBY, per = (NT + 7) >> 3;
   const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -218,6 +254,10 @@ __global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) MmaBlocks<T, NB>::run(acc[i][j], fa[i], fb[j]);
   }
+  // the products are pinned ahead of the test: the flag's latency overlaps the operand loads (a
+  // block the loop ran ahead of a met test then costs one contraction more per launch)
+  asm volatile("" : "+v"(stopped) : "v"(acc[0][0][0]), "v"(acc[0][1][0]), "v"(acc[1][0][0]), "v"(acc[1][1][0]) : "memory");
+  if (__builtin_amdgcn_readfirstlane(stopped)) return;
   // T1 slab-major, T1[i3][m], through an LDS transpose of the 64 x 64 tile
   __shared__ T tt[64][65];
 #pragma unroll
@@ -234,6 +274,8 @@ __global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
     const int i3o = by * 64 + sl, mo = bx * 64 + ml;
     if (i3o < G.n3 && mo < G.P12) T1[(long long)i3o * G.P12 + mo] = tt[sl][ml];
   }
+  // the iteration counter, last (no barrier waits behind this store)
+  if (P.iter && blockIdx.x == 0 && threadIdx.x == 0) *P.iter += 1;
 }
 
 // ============================================================================
@@ -686,7 +728,8 @@ __host__ __device__ constexpr int wave_lds_bytes() {
 }
 
 template <typename T, int MODE, bool HAS_V, int SPW, int NPART, bool P16, int N1B = 8, bool LDSF = false>
-__device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds, int grp0, int nrep = 1) {
+__device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds, int grp0, int nrep = 1,
+                                        int stopped = 0) {
   typedef WT<T> W;
   typedef typename W::v8 V8;
   typedef typename W::st ST;
@@ -729,16 +772,37 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
         fx2a[mt][qq] = jb0 + 2 * qq < NJB ? W::load(src, 24 + 4 * mt + QPW * part + qq, lane) : zf;
   };
   unsigned char* flds = lds + wave_lds_bytes<T, SPW, NPART>();   // LDSF: the wave image
+  // LDSF: the first group's T1 chunks are requested together with the image (SPW slabs of at most
+  // 1024 elements: at most T1PF 4-element chunks per thread), so that the two loads share one
+  // round trip
+  constexpr int T1PF = LDSF ? (SPW * 1024 / 4 + NT - 1) / NT : 1;
+  st4 t1pre[T1PF];
+  int n4pre = -1;   // >= 0: the first group's aligned chunks are in t1pre
   if constexpr (LDSF) {
     static_assert(sizeof(ST) == 2, "the LDS copy of the wave image is sized for BF16");
+    {
+      const ST* src = (const ST*)P.T1 + (long long)SPW * grp0 * P12;
+      const int nel = min(SPW, G.n3 - SPW * grp0) * P12;
+      if ((((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) && P12 <= 1024) {
+        n4pre = nel >> 2;
+#pragma unroll
+        for (int q = 0; q < T1PF; ++q) {
+          const int k = tid + NT * q;
+          if (k < n4pre) t1pre[q] = ((const st4*)src)[k];
+        }
+      }
+    }
     constexpr int NCH = WAVE_FRAGS * 64 * 8 * 2 / 16;   // 16-byte chunks
     u4v_t ch[NCH / NT];
 #pragma unroll
     for (int q = 0; q < NCH / NT; ++q) ch[q] = ((const u4v_t*)img)[tid + NT * q];
+    asm volatile("" : "+v"(stopped) : : "memory");   // the loads above are issued before the flag is waited on
+    if (__builtin_amdgcn_readfirstlane(stopped)) return;   // the inner loop has ended (whole grid; nothing written)
 #pragma unroll
     for (int q = 0; q < NCH / NT; ++q) ((u4v_t*)flds)[tid + NT * q] = ch[q];
   } else {
     load_frags(img);
+    if (stopped) return;   // the inner loop has ended (whole grid; nothing written)
   }
   // LDS reuse across groups: t1s is read before the S2 barrier of a group and rewritten after
   // it; s2p and s2x are read before the next group's staging barrier
@@ -753,9 +817,18 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
       // the slabs are contiguous in slab-major T1: coalesced 4-element loads when aligned
       const ST* src = (const ST*)P.T1 + (long long)i3b * P12;
       const int nel = nsl * P12;
-      const int n4 = (((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) ? (nel >> 2) : 0;
-      for (int k = tid; k < n4; k += NT) ((st4*)t1s)[k] = ((const st4*)src)[k];
-      for (int k = 4 * n4 + tid; k < nel; k += NT) t1s[k] = src[k];
+      if (rep == 0 && n4pre >= 0) {
+#pragma unroll
+        for (int q = 0; q < T1PF; ++q) {
+          const int k = tid + NT * q;
+          if (k < n4pre) ((st4*)t1s)[k] = t1pre[q];
+        }
+        for (int k = 4 * n4pre + tid; k < nel; k += NT) t1s[k] = src[k];
+      } else {
+        const int n4 = (((unsigned long long)src & (4 * sizeof(ST) - 1)) == 0) ? (nel >> 2) : 0;
+        for (int k = tid; k < n4; k += NT) ((st4*)t1s)[k] = ((const st4*)src)[k];
+        for (int k = 4 * n4 + tid; k < nel; k += NT) t1s[k] = src[k];
+      }
     }
     __syncthreads();
     if constexpr (LDSF) {
@@ -912,12 +985,14 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
 template <typename T, int MODE, bool HAS_V, int SPW, int NPART, bool P16, bool LDSF = false>
 __global__ __launch_bounds__(64 * SPW * NPART) void k_slab_chain_w(SlabParams P) {
   __shared__ __align__(16) unsigned char lds[wave_lds_bytes<T, SPW, NPART>() + (LDSF ? WAVE_FRAGS * 64 * 16 : 0)];
-  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
+  // the inner loop has ended when *stop != 0: the flag is requested first and tested once the
+  // first loads are in flight (the whole grid then exits before writing anything)
+  int stopped = P.stop ? __hip_atomic_load(P.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;   // a vector load (in order with the operand loads)
   // XCD-aware order: workgroup b runs on XCD b % 8, and the slabs 4 c .. 4 c + 3 that share
   // the chunks of S2 run on one XCD (c % 8 for SPW = 1; 32-slab groups for SPW = 4)
   const int b = blockIdx.x, x = b & 7, jj = b >> 3;
   const int grp = SPW == 4 ? 8 * (x + 8 * (jj >> 3)) + (jj & 7) : 4 * (x + 8 * (jj >> 2)) + (jj & 3);
-  wave_chain_group<T, MODE, HAS_V, SPW, NPART, P16, 8, LDSF>(P, lds, grp);
+  wave_chain_group<T, MODE, HAS_V, SPW, NPART, P16, 8, LDSF>(P, lds, grp, 1, stopped);
 }
 
 // ============================================================================
@@ -1099,12 +1174,14 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
   typedef typename R::acc_t A;
   __shared__ double sred[4 * ADJ_NSUM];
   __shared__ A red[WG / 64][256];
-  if (P.stop && *P.stop) return;   // the inner loop has ended (whole grid)
   const Geom& G = P.G;
   const int NBM = (G.P12 + 15) >> 4, NBN = (G.p3 + 15) >> 4;
   int bm, bn, tile;
   adj_tile_of(blockIdx.x, NBM, NBN, P.xmap, &bm, &bn, &tile);
   if (tile < 0) return;   // the padding workgroups of the XCD-aware order (whole workgroup)
+  // the inner loop has ended when *stop != 0 (the whole grid then exits before writing anything);
+  // the flag is requested first and tested once the operand loads are in flight
+  int stopped = P.stop ? __hip_atomic_load(P.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;   // a vector load (in order with the operand loads)
   const T* __restrict__ S2 = (const T*)P.S2;
   const T* __restrict__ X3 = (const T*)P.X3a;
   const int lane = lane_id(), r = lane & 15, g = lane >> 4, w = wave_id();
@@ -1127,16 +1204,22 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
     if (P.penT) e_w = P.penT[e];
   }
   typename R::accv_t acc = R::zero();
-  const T* pa = P.s2_kb4 ? S2 + ((long long)g * G.P12 + m) * 4 : S2 + (long long)m * 16 + 4 * g;
-  const T* pb = X3 + (long long)k3 * 16 + 4 * g;
+  // rows beyond the matrices read row P12 - 1 (or column p3 - 1), zeroed in the loop
+  const int mc = am ? m : G.P12 - 1, kc = bk ? k3 : G.p3 - 1;
+  const T* pa = P.s2_kb4 ? S2 + ((long long)g * G.P12 + mc) * 4 : S2 + (long long)mc * 16 + 4 * g;
+  const T* pb = X3 + (long long)kc * 16 + 4 * g;
   const long long sa = (long long)G.P12 * 16, sb = (long long)G.p3 * 16;
   const int nkb = w < G.KBN3 ? (G.KBN3 - w + (WG / 64) - 1) / (WG / 64) : 0;
-  kblock_loop<T, KNB<T>::v>(acc, pa, pb, sa, sb, w, WG / 64, nkb, am, bk);
+  if (!kblock_loop_or_stop<T, KNB<T>::v>(acc, pa, pb, sa, sb, w, WG / 64, nkb, am, bk, stopped)) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[w][R::kidx(g, i) * 16 + r] = acc[i];   // [m % 16][k3 % 16]
   __syncthreads();
   const double a = (double)(red[0][t] + red[1][t] + red[2][t] + red[3][t]);
   double red_kkt = 0.0, red_noise = 0.0, red_inc = 0.0, red_rs = 0.0;
+  // the outputs are stored after the workgroup reduction: a barrier behind outstanding stores
+  // waits for them to complete, while at the end of the kernel their latency overlaps the exit
+  float o_d = 0.f, o_q = 0.f;
+  typename R::acc_t o_inc = 0;
   if (valid) {
     const double lam = P.dparams[0], delta = P.dparams[1];
     const double l_iter = (double)__hip_atomic_load(P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1155,15 +1238,20 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
     // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
     const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
     const double dn = xn - e_t;
-    P.dout[e] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
-    P.q_out[e] = (float)incg;
+    o_d = xn == 0.0 ? __builtin_nanf("") : (float)dn;
+    o_q = (float)incg;
+    o_inc = (typename R::acc_t)dn;
     red_inc = fabs(dn);
     red_rs = (yv - xn) * (xn - x);   // restart test of the extrapolation (summed; > 0: restart)
-    ((T*)P.inc)[((long long)(ek >> 4) * G.P12 + em) * 16 + kpos<T>(ek & 15)] = R::from_acc((typename R::acc_t)dn);
   }
   double v[ADJ_NSUM] = {red_kkt, red_noise, red_rs, 0.0, red_inc, 0.0};
   const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
   block_reduce<ADJ_NSUM>(v, ops, sred);
+  if (valid) {
+    P.dout[e] = o_d;
+    P.q_out[e] = o_q;
+    ((T*)P.inc)[((long long)(ek >> 4) * G.P12 + em) * 16 + kpos<T>(ek & 15)] = R::from_acc(o_inc);
+  }
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < ADJ_NSUM; ++q) P.partials[(long long)tile * ADJ_NSUM + q] = v[q];
