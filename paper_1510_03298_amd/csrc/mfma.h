@@ -34,12 +34,13 @@ struct bf16 {
 __device__ __host__ inline float bf16_to_f32(uint16_t h) {
   return __uint_as_float(((uint32_t)h) << 16);
 }
-// Round-to-nearest-even float -> bfloat16 (NaN kept quiet).
+// Round-to-nearest-even float -> bfloat16 (NaN kept quiet), written as a select so that it
+// compiles to straight-line code.
 __device__ inline uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t qnan = (u >> 16) | 0x40u;
+  return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? qnan : rne);
 }
 
 template <typename T> struct Tr;

@@ -91,6 +91,49 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
   }
 }
 
+// A 64-lane wave's sum or maximum of a double, returned in every lane: xor butterflies within
+// quads and rotations within 16-lane rows as DPP moves (VALU, no LDS round trip), then the four
+// rows' results through readlane.  Needs all 64 lanes active.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <bool MAX>
+__device__ inline double wave_reduce_dpp(double v) {
+  auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+  v = op(v, dpp_f64<0xB1>(v));    // quad_perm (1, 0, 3, 2): lane ^ 1
+  v = op(v, dpp_f64<0x4E>(v));    // quad_perm (2, 3, 0, 1): lane ^ 2
+  v = op(v, dpp_f64<0x124>(v));   // row_ror 4
+  v = op(v, dpp_f64<0x128>(v));   // row_ror 8: every lane of a row holds the row's result
+  return op(op(readlane_f64(v, 0), readlane_f64(v, 16)), op(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+// Workgroup reduction of NV doubles (sum or max per value) with the DPP wave step; result valid
+// in thread 0.  All threads of the workgroup must take part.
+template <int NV>
+__device__ inline void block_reduce_dpp(double (&v)[NV], const int (&ops)[NV], double* sred /* 4*NV */) {
+#pragma unroll
+  for (int s = 0; s < NV; ++s) v[s] = ops[s] ? wave_reduce_dpp<true>(v[s]) : wave_reduce_dpp<false>(v[s]);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) sred[wave_id() * NV + s] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      double a = sred[s];
+      for (int w = 1; w < WG / 64; ++w) a = ops[s] ? fmax(a, sred[w * NV + s]) : a + sred[w * NV + s];
+      v[s] = a;
+    }
+  }
+}
+
 // acc += sum over the k-blocks kb = kb0 + j * kstep (j < nkb) of A_kb^T B_kb
 // (k-blocked operands), NB blocks per round of loads: a contraction of at most NB
 // blocks is one round, so its latency is paid once.
@@ -956,6 +999,22 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
     // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
     if (part == 0) {
       ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
+      // the partials are read first, all at once (one LDS round trip); the indices stay inside
+      // the 1024-element slots, and entries outside the p1 x p2 block are read but not used
+      float sum[2][2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+            const int m = min(i1 + G.p1 * i2, 1023);
+            float v = s2[mt][nt][i];
+#pragma unroll
+            for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[(pp * SPW + sw) * 1024 + m];
+            sum[mt][nt][i] = v;
+          }
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -965,11 +1024,9 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
             const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
             if (i1 < G.p1 && i2 < G.p2) {
               const int m = i1 + G.p1 * i2;
-              float v = s2[mt][nt][i];
-#pragma unroll
-              for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[(pp * SPW + sw) * 1024 + m];
-              if (SPW == 4) s2x[m * 4 + sw] = W::from_f32(v);
-              else if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
+              const ST h = W::from_f32(sum[mt][nt][i]);
+              if (SPW == 4) s2x[m * 4 + sw] = h;
+              else if (sw < nsl) S2[(long long)m * 4] = h;
             }
           }
     }
@@ -1244,17 +1301,23 @@ __global__ __launch_bounds__(WG) void k_slab_adj_inc(AdjIncParams P) {
     red_inc = fabs(dn);
     red_rs = (yv - xn) * (xn - x);   // restart test of the extrapolation (summed; > 0: restart)
   }
-  double v[ADJ_NSUM] = {red_kkt, red_noise, red_rs, 0.0, red_inc, 0.0};
-  const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-  block_reduce<ADJ_NSUM>(v, ops, sred);
+  // partial row {kkt max, noise max, restart sum, 0, step max, 0} (slab_adj's layout)
+  double v[4] = {red_kkt, red_noise, red_rs, red_inc};
+  const int ops[4] = {1, 1, 0, 1};
+  block_reduce_dpp<4>(v, ops, sred);
   if (valid) {
     P.dout[e] = o_d;
     P.q_out[e] = o_q;
     ((T*)P.inc)[((long long)(ek >> 4) * G.P12 + em) * 16 + kpos<T>(ek & 15)] = R::from_acc(o_inc);
   }
   if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < ADJ_NSUM; ++q) P.partials[(long long)tile * ADJ_NSUM + q] = v[q];
+    double* pr = P.partials + (long long)tile * ADJ_NSUM;
+    pr[0] = v[0];
+    pr[1] = v[1];
+    pr[2] = v[2];
+    pr[3] = 0.0;
+    pr[4] = v[3];
+    pr[5] = 0.0;
   }
 }
 
