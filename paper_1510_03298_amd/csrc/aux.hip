@@ -47,63 +47,74 @@ __device__ inline void block_reduce(double (&v)[NV], const int (&ops)[NV], doubl
 // ============================================================================
 // out[v] = scale * sum_b part[b][v] (ops bit v = 0) or max_b part[b][v] (bit v = 1), v < nval <= 32.
 // One wave per value (values v, v + 16, ... on wave v % 16 of a 1024-thread workgroup): lane l
-// takes the blocks l, l + 64, ... in order, then a fixed butterfly across the wave, so the
-// summation order is fixed and every value is one round of independent loads.  With
-// hout != NULL the values are also published to host memory (fine-grained, mapped),
-// followed by an incremented sequence number *hseq (kept in *seq_dev), so that the host
+// takes the blocks l, l + 64, ... in order (requested RED_UNROLL at a time, so that a value costs
+// one or two rounds of independent loads, not one per block), then a fixed butterfly across the
+// wave, so the summation order is fixed.  The results pass through LDS to thread 0, which writes
+// them out.  With hout != NULL the values are also published to host memory (fine-grained,
+// mapped), followed by an incremented sequence number *hseq (kept in *seq_dev), so that the host
 // can wait on it without a copy.
 constexpr int RED_WG = 1024;
+constexpr int RED_UNROLL = 16;
 __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ part, int nblk, int stride, int nval,
                                                    unsigned ops_bits, double scale, double* __restrict__ out,
                                                    double* hout, unsigned* seq_dev, unsigned* hseq,
                                                    int restart_slot, int* restart_iter, int* stop,
                                                    const double* __restrict__ crit) {
+  __shared__ double sres[32];
   const int lane = lane_id(), w = wave_id();
-  if (stop && *stop) {
-    // the inner loop ended at an earlier block: nothing of this block ran; say so to the host
-    if (hout && threadIdx.x == 0) {
-      const unsigned s = *seq_dev + 1u;
-      *seq_dev = s;
-      __hip_atomic_store(&hout[8 * (s & 1u) + nval], 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __threadfence_system();
-      __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    return;   // the whole workgroup (*stop was written by an earlier kernel)
-  }
+  // *stop was written by an earlier kernel: when set, nothing of this block ran, and the partials
+  // reduced below are ignored (the flag is only waited on after they have been requested)
+  int stopped = stop ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;   // a vector load
+  unsigned seq_prev = 0;   // thread 0: the sequence counter, requested with the partials
+  if (hout && threadIdx.x == 0) seq_prev = __hip_atomic_load(seq_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int v = w; v < nval; v += RED_WG / 64) {
     const bool mx = (ops_bits >> v) & 1u;
-    double a = mx ? -INFINITY : 0.0;
-    for (int b = lane; b < nblk; b += 64) {
-      const double x = part[(long long)b * stride + v];
-      a = mx ? fmax(a, x) : a + x;
+    const double id = mx ? -INFINITY : 0.0;
+    double a = id;
+    for (int b0 = lane; b0 < nblk; b0 += 64 * RED_UNROLL) {
+      double x[RED_UNROLL];
+#pragma unroll
+      for (int u = 0; u < RED_UNROLL; ++u) {
+        const int b = b0 + 64 * u;
+        x[u] = b < nblk ? part[(long long)b * stride + v] : id;
+      }
+#pragma unroll
+      for (int u = 0; u < RED_UNROLL; ++u) a = mx ? fmax(a, x[u]) : a + x[u];
     }
     a = mx ? warp_max(a) : warp_sum(a);
-    if (lane == 0) {
-      const double r = mx ? a : scale * a;
-      out[v] = r;
-      // restarted extrapolation: a positive test value sets the step counter back, so that the
-      // next iteration takes omega = 0 (the counter is incremented before its use)
-      if (restart_iter && v == restart_slot && r > 0.0) *restart_iter = 0;
-    }
+    if (lane == 0) sres[v] = mx ? a : scale * a;
   }
-  if (stop) {
-    __syncthreads();   // out[0], out[1] of waves 0 and 1
-    if (threadIdx.x == 0) {
-      const double kin = out[0] / crit[0], noise = crit[2] * out[1] / crit[0];
+  __syncthreads();   // sres of every wave
+  // the flag and the counter pass through an empty asm here, so that the waits for their loads
+  // are placed here, behind the partials' loads
+  asm volatile("" : "+v"(stopped), "+v"(seq_prev));
+  if (__builtin_amdgcn_readfirstlane(stopped)) {
+    // say so to the host: slot s % 2 carries the "skipped" flag 1
+    if (hout && threadIdx.x == 0) {
+      const unsigned s = seq_prev + 1u;
+      *seq_dev = s;
+      __hip_atomic_store(&hout[8 * (s & 1u) + nval], 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);   // the flag before s
+    }
+    return;
+  }
+  if (w == 0 && lane < nval) out[lane] = sres[lane];
+  if (threadIdx.x == 0) {
+    // restarted extrapolation: a positive test value sets the step counter back, so that the next
+    // iteration takes omega = 0 (the counter is incremented before its use)
+    if (restart_iter && restart_slot >= 0 && restart_slot < nval && sres[restart_slot] > 0.0) *restart_iter = 0;
+    if (stop) {
+      const double kin = sres[0] / crit[0], noise = crit[2] * sres[1] / crit[0];
       if (!__builtin_isfinite(kin) || kin <= fmax(crit[1], noise)) *stop = 1;
     }
-  }
-  if (hout) {
-    // published into slot s % 2 of the host buffer (two blocks may be in flight): the values, the
-    // "skipped" flag 0, then the sequence number s
-    __syncthreads();   // out[v] of every wave
-    if (threadIdx.x == 0) {
-      const unsigned s = *seq_dev + 1u;
+    if (hout) {
+      // published into slot s % 2 of the host buffer (two blocks may be in flight): the values,
+      // the "skipped" flag 0, then (a release store) the sequence number s
+      const unsigned s = seq_prev + 1u;
       *seq_dev = s;
       double* slot = hout + 8 * (s & 1u);
-      for (int v = 0; v < nval; ++v) __hip_atomic_store(&slot[v], out[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      for (int v = 0; v < nval; ++v) __hip_atomic_store(&slot[v], sres[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(&slot[nval], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __threadfence_system();   // the values before the sequence number
       __hip_atomic_store(hseq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
