@@ -12,6 +12,7 @@
 // last: the same linear maps as the cyclic rho order, with the least work when
 // mode 3 is the largest mode.
 #include <algorithm>
+#include <type_traits>
 
 #include "launch.h"
 #include "mfma.h"
@@ -301,7 +302,29 @@ __global__ __launch_bounds__(WG) void k_slab_fwd_wide(FwdParams P) {
   // block the loop ran ahead of a met test then costs one contraction more per launch)
   asm volatile("" : "+v"(stopped) : "v"(acc[0][0][0]), "v"(acc[0][1][0]), "v"(acc[1][0][0]), "v"(acc[1][1][0]) : "memory");
   if (__builtin_amdgcn_readfirstlane(stopped)) return;
-  // T1 slab-major, T1[i3][m], through an LDS transpose of the 64 x 64 tile
+  // T1 slab-major, T1[i3][m].  BF16 / FP32 with P12 % 4 == 0: lane (r, g) of tile (i, j) holds the
+  // 4 consecutive rows m = 16 i + 4 g .. + 3 of column i3 = 16 j + r (kidx(g, e) = 4 g + e), stored
+  // as one aligned 4-element chunk; otherwise through an LDS transpose of the 64 x 64 tile
+  if constexpr (!std::is_same<T, double>::value) {
+    if ((G.P12 & 3) == 0) {
+      typedef typename R::acc_t AT;
+      struct alignas(4 * sizeof(T)) Q4 { T v[4]; };
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int m0 = bx * 64 + ml0 + 16 * i + 4 * g, i3o = by * 64 + nl0 + 16 * j + r;
+          if (i3o < G.n3 && m0 < G.P12) {   // P12 % 4 == 0: the whole chunk is inside
+            Q4 q;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q.v[e] = R::from_acc((AT)acc[i][j][e]);
+            *(Q4*)(T1 + (long long)i3o * G.P12 + m0) = q;
+          }
+        }
+      if (P.iter && blockIdx.x == 0 && threadIdx.x == 0) *P.iter += 1;
+      return;
+    }
+  }
   __shared__ T tt[64][65];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -396,7 +419,20 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
     if (NEED_FWD) {
       // the slab's p1 x p2 block of T1 (contiguous), then fragments: row p1, contraction p2
       const T* t1 = (const T*)P.T1 + (long long)i3 * G.P12;
-      for (int idx = tid; idx < G.P12; idx += WG) t1s[idx] = t1[idx];
+      // requested 4 per thread at a time (one round trip per 4 WG elements, not one per WG)
+      for (int base = 0; base < G.P12; base += 4 * WG) {
+        T tv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int idx = base + q * WG + tid;
+          tv[q] = idx < G.P12 ? t1[idx] : zero_val<T>();
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int idx = base + q * WG + tid;
+          if (idx < G.P12) t1s[idx] = tv[q];
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int mt = 0; mt < PT; ++mt)
@@ -438,6 +474,22 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
       for (int nt = 0; nt < PT; ++nt) S1[nt] = R::zero();
 
       for (int u0 = 0; u0 < N1Tp; u0 += CH) {
+        // SM_FAMILY: the group's responses (and prior weights) are requested first, all at once;
+        // the family step's stores may alias them as far as the compiler knows, which would order
+        // every load behind the previous element's stores
+        double yg[CH][4], ag[CH][4];
+        if (MODE == SM_FAMILY) {
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            const bool ok = u0 + c < G.N1T;
+            const long long tb = (((long long)i3 * G.NJB + jb) * G.N1T + u0 + c) * 256 + r * 16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              yg[c][i] = ok ? P.y_int[tb + R::kidx(g, i)] : 0.0;
+              ag[c][i] = (ok && P.a_int) ? P.a_int[tb + R::kidx(g, i)] : 1.0;
+            }
+          }
+        }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           const int ut = u0 + c;
@@ -495,8 +547,8 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
               }
               const long long ti = tbase + R::kidx(g, i);
               const double eta = (double)E[i];
-              const double y = P.y_int[ti];
-              const double a = P.a_int ? P.a_int[ti] : 1.0;   // (no prior weights: a = 1 on valid cells)
+              const double y = yg[c][i];
+              const double a = ag[c][i];   // (no prior weights: a = 1 on valid cells)
               // score u = a vartheta'(eta) (y - mu), weight w = vartheta'(eta) (g^-1)'(eta) (App. B)
               double wgt, nll, u;
               const int fam = FAM >= 0 ? FAM : P.family;
