@@ -206,8 +206,9 @@ struct Fit {
   int* iter;
   double* part;            // partial sums
   double* red;             // reduced values (device)
-  double* hred = nullptr;  // reduced values (pinned host); [32..35] input-check flags
+  double* hred = nullptr;  // reduced values (pinned host); [32..35] input-check flags, [40..42] kkt_at_lambda
   double* hred_dev = nullptr;   // its device address: the reductions of steps 2 and 5 write there directly
+  size_t npart = 0;             // doubles in part
   double* hx[3] = {nullptr, nullptr, nullptr};   // pinned host copies of the factors (set-up)
   double* hpub = nullptr;  // published check values (fine-grained pinned host, mapped)
   double* hpub_dev = nullptr;
@@ -342,6 +343,26 @@ static int family_step(Fit& F, const double* theta_dev, double lambda, StepStats
   if (r) return r;
   FCHK(hipStreamSynchronize(F.s));
   family_collect(F, st);
+  return GLAM_OK;
+}
+
+// Step 2 of Algorithm 1 at the theta of the last family step, for a new lambda with the same
+// penalty weights (the first outer step of the next model on the path): eta, V, -l/n, the
+// gradient and the penalty sum are those of that step, so only the KKT residual is evaluated
+// again, from the stored gradient (the same expression as the gradient epilogue, hence the same
+// value).  Returns false when the partials buffer is too small (the caller takes the full step).
+static int kkt_at_lambda(Fit& F, double lambda, const StepStats& last, StepStats* st, bool* done) {
+  const Geom& G = F.G;
+  *done = false;
+  if ((size_t)3 * gen_grid_blocks(G.p) > F.npart) return GLAM_OK;
+  int nb = 0;
+  FCHK(launch_gen_grad_stats(G.p, F.gref, 1.0, F.theta, F.pen, lambda, F.enet, F.no_l1, nullptr, F.part, &nb, F.s));
+  const int ops[3] = {1, 1, 0};
+  FCHK(launch_reduce(F.part, nb, 3, ops, 1.0, F.hred_dev + 40, F.s));   // hred[40..42]
+  FCHK(hipStreamSynchronize(F.s));
+  *st = last;
+  st->kkt_raw = F.hred[40];
+  *done = true;
   return GLAM_OK;
 }
 
@@ -785,6 +806,7 @@ static int fit_setup_enqueue(Fit& F, const glam_problem* prob, bool bt, bool eve
   }
   F.iter = (int*)A(2 * sizeof(int));
   F.part = (double*)A(npart * 8);
+  F.npart = npart;
   F.red = (double*)A(64 * 8);
   F.dparams = (double*)A(8 * 8);
   F.stop = (int*)A(256);
@@ -1210,6 +1232,7 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
   res->chain_samples = 0;
   res->inner_total = 0;
 
+  StepStats st_last{};   // the last family step's values (theta unchanged since)
   for (int l = 0; l < opt->nlambda; ++l) {
     const double lam = lams[l];
     res->lambda_out[l] = lam;
@@ -1234,7 +1257,10 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
     }
     status = GLAM_ENOCONV;
     for (int k = 0; k <= opt->max_outer; ++k) {
-      RCHK(family_step(F, F.theta, lam, &st));
+      bool reused = false;
+      if (k == 0 && l > 0 && !scad) RCHK(kkt_at_lambda(F, lam, st_last, &st, &reused));
+      if (!reused) RCHK(family_step(F, F.theta, lam, &st));
+      st_last = st;
       kkt = st.kkt_raw / lam_scale;
       Fobj = st.nll + lam * st.pen;
       outer = outer_base + k;

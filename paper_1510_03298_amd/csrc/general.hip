@@ -371,6 +371,7 @@ __global__ __launch_bounds__(GWG) void k_gen_grad_stats(long long p, const doubl
   double v[3] = {kkt, lmax, pen};
   g_block_partials<3>(v, 3u, part);
 }
+int gen_grid_blocks(long long n) { return g_grid(n); }
 hipError_t launch_gen_grad_stats(long long p, const double* gin, double scale, const double* theta, const double* w,
                                  double lambda, double alpha, int no_l1, double* gout, double* part, int* nblk,
                                  hipStream_t s) {

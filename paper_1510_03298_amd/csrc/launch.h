@@ -389,6 +389,8 @@ hipError_t launch_gen_transpose_same(int dt, long long nr, long long pc, const v
 // family step on FP64 eta: u (adj_dt), weights (v_dt, optional), partials {sum -l, max w}
 hipError_t launch_gen_family(int adj_dt, int v_dt, long long n, int family, const double* eta, const double* y,
                              const double* a, void* u_out, void* v_out, double* part, int* nblk, hipStream_t s);
+// workgroups of the generic elementwise kernels for n elements (their partial-row count)
+int gen_grid_blocks(long long n);
 // g = scale gin (FP64); partials {max KKT residual, max |g|/w, sum w (l1 |theta| + alpha theta^2)}
 hipError_t launch_gen_grad_stats(long long p, const double* gin, double scale, const double* theta, const double* w,
                                  double lambda, double alpha, int no_l1, double* gout, double* part, int* nblk,
