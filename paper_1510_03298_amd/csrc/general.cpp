@@ -157,6 +157,21 @@ int family_step(GFit& F, const double* theta, double lambda, Stats* st) {
   return GLAM_OK;
 }
 
+// Step 2 at the theta of the last family step for a new lambda with the same penalty weights (the
+// first outer step of the next model on the path): only the KKT residual changes; it is evaluated
+// from the stored gradient by the same kernel (the same value); the rest is the last step's.
+int kkt_at_lambda(GFit& F, double lambda, const Stats& last, Stats* st) {
+  int nb = 0;
+  GCHK(launch_gen_grad_stats(F.P, F.gref, 1.0, F.theta, F.pen, lambda, F.enet, F.no_l1, nullptr, F.part, &nb, F.s));
+  const int ops3[3] = {1, 1, 0};
+  GCHK(launch_reduce(F.part, nb, 3, ops3, 1.0, F.red + 2, F.s));
+  GCHK(hipMemcpyAsync(F.hred + 2, F.red + 2, sizeof(double), hipMemcpyDeviceToHost, F.s));
+  GCHK(hipStreamSynchronize(F.s));
+  *st = last;
+  st->kkt_raw = F.hred[2];
+  return GLAM_OK;
+}
+
 // gi = G(V .* H(inc)) in the chain dtype (accumulation-type output); the last component's forward
 // chain writes R = V .* (its product + the other components' sum) directly in the chain dtype
 int inner_gradient(GFit& F) {
@@ -539,6 +554,7 @@ int general_fit_path(const GenProblem& prob, const glam_options* opt, glam_resul
   res->chain_samples = 0;
   res->inner_total = 0;
 
+  Stats st_last{};   // the last family step's values (theta unchanged since)
   for (int l = 0; l < opt->nlambda; ++l) {
     const double lam = lams[l];
     res->lambda_out[l] = lam;
@@ -555,7 +571,9 @@ int general_fit_path(const GenProblem& prob, const glam_options* opt, glam_resul
       status = GLAM_ENOCONV;
       for (int k = 0; k <= opt->max_outer; ++k) {
         Stats st{};
-        RG(family_step(F, F.theta, lam, &st));
+        if (k == 0 && l > 0 && !scad) RG(kkt_at_lambda(F, lam, st_last, &st));
+        else RG(family_step(F, F.theta, lam, &st));
+        st_last = st;
         kkt = st.kkt_raw / lam_scale;
         Fobj = st.nll + lam * st.pen;
         outer = outer_base + k;
