@@ -1156,14 +1156,17 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
   const int qe = (t & 15) * 16 + (t >> 4);
   const double a = (double)(red[0][qe] + red[1][qe] + red[2][qe] + red[3][qe]);
   double red_kkt = 0.0, red_lmax = 0.0, red_pen = 0.0, red_noise = 0.0, red_inc = 0.0, red_dg = 0.0, red_dd = 0.0;
+  // the outputs are stored after the workgroup reduction (a barrier behind outstanding stores waits
+  // for them to complete; at the end of the kernel their latency overlaps the exit)
+  double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0, o4 = 0.0, dinc = 0.0;
   if (valid) {
     if (EPI == EPI_STORE) {
       double s = P.scale;
       if (P.gscale_dev) s *= *P.gscale_dev;
-      ((typename OutOf<T>::type*)P.out)[j] = (typename OutOf<T>::type)(s * a);
+      o0 = s * a;
     } else if (EPI == EPI_GRAD) {
       const double gv = P.scale * a;
-      P.gout[j] = gv;
+      o0 = gv;
       const double wm = e_w;
       red_lmax = fabs(gv) / wm;
       if (P.theta) {
@@ -1195,15 +1198,13 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double yv = x + om * (x - xp);
       // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
       const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
-      P.x_out[j] = xn;
-      P.xp_out[j] = x;
-      P.gp_out[j] = gx;
-      P.y_out[j] = yv;
-      P.gy_out[j] = gy;
-      const double dinc = xn - e_th;
+      o0 = xn;   // x_out
+      o1 = x;    // xp_out
+      o2 = gx;   // gp_out
+      o3 = yv;   // y_out
+      o4 = gy;   // gy_out
+      dinc = xn - e_th;
       red_inc = fabs(dinc);
-      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
-          R::from_acc((typename R::acc_t)dinc);
     } else {  // EPI_PROX: one inner PG step (Sec. 3.2) with FISTA extrapolation
       const double lam = P.dparams ? P.dparams[0] : P.lambda;
       const double delta = P.dparams ? P.dparams[1] : P.delta;
@@ -1221,28 +1222,45 @@ __device__ inline void adj_tile(const AdjParams& P, int bm, int bn, long long pi
       const double yv = x + om * (x - xp);
       // prox of delta lambda w (|.| + alpha (.)^2) (Sec. 6.3)
       const double xn = soft_threshold(yv - delta * gy, P.no_l1 ? 0.0 : delta * lw) / (1.0 + 2.0 * P.alpha * delta * lw);
-      P.xp[j] = x;
-      P.x[j] = xn;
-      P.gp[j] = gx;
+      o0 = xn;   // x
+      o1 = x;    // xp
+      o2 = gx;   // gp
       red_dg = (yv - xn) * (xn - x);   // restart test of the extrapolation (summed; > 0: restart)
-      const double dinc = xn - e_th;
+      dinc = xn - e_th;
       red_inc = fabs(dinc);
-      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] =
-          R::from_acc((typename R::acc_t)dinc);
     }
   }
+  double v[5] = {red_kkt, EPI == EPI_GRAD ? red_lmax : red_noise, EPI == EPI_GRAD ? red_pen : red_dg, red_dd, red_inc};
   if (EPI != EPI_STORE) {
     // per-workgroup partials [nblk][ADJ_NSUM]: max KKT residual, max |g|/w (GRAD) or max
     // |increment gradient| (PROX), sum w|theta| (GRAD) or sum d.gd (PROX_BT), sum d.d
     // (PROX_BT), max |x - theta_ref| (PROX), unused
-    double v[ADJ_NSUM] = {red_kkt, EPI == EPI_GRAD ? red_lmax : red_noise, EPI == EPI_GRAD ? red_pen : red_dg,
-                          red_dd, red_inc, 0.0};
-    const int ops[ADJ_NSUM] = {1, 1, 0, 0, 1, 0};
-    block_reduce<ADJ_NSUM>(v, ops, sred);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int s = 0; s < ADJ_NSUM; ++s) P.partials[pidx * ADJ_NSUM + s] = v[s];
+    const int ops[5] = {1, 1, 0, 0, 1};
+    block_reduce_dpp<5>(v, ops, sred);
+  }
+  if (valid) {
+    if (EPI == EPI_STORE) {
+      ((typename OutOf<T>::type*)P.out)[j] = (typename OutOf<T>::type)o0;
+    } else if (EPI == EPI_GRAD) {
+      P.gout[j] = o0;
+    } else if (EPI == EPI_PROX_BT) {
+      P.x_out[j] = o0;
+      P.xp_out[j] = o1;
+      P.gp_out[j] = o2;
+      P.y_out[j] = o3;
+      P.gy_out[j] = o4;
+      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] = R::from_acc((typename R::acc_t)dinc);
+    } else {
+      P.xp[j] = o1;
+      P.x[j] = o0;
+      P.gp[j] = o2;
+      ((T*)P.inc)[((long long)(col >> 4) * G.P12 + row) * 16 + kpos<T>(col & 15)] = R::from_acc((typename R::acc_t)dinc);
     }
+  }
+  if (EPI != EPI_STORE && threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) P.partials[pidx * ADJ_NSUM + q] = v[q];
+    P.partials[pidx * ADJ_NSUM + 5] = 0.0;
   }
 }
 
