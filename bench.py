@@ -435,6 +435,8 @@ def main():
                 "poisson_path_c3": lambda: poisson_path(glam, inputs, torch, stream),
                 "gaussian_c1": lambda: c1_single_lambda(glam, inputs, torch, stream),
                 "poisson_path_c3_kron": lambda: poisson_path_kron(glam, inputs, torch, stream),
+                "sim65_gaussian": lambda: sim65_path(glam, inputs, torch, stream, "gaussian"),
+                "sim65_poisson": lambda: sim65_path(glam, inputs, torch, stream, "poisson", forms=("bf16",)),
                 "sim65_q3_gaussian": lambda: sim65_q3_path(glam, inputs, torch, stream),
                 "components_c2": lambda: components_path(glam, inputs, torch, stream)}
         if args.only not in only:

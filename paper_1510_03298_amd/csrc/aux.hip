@@ -71,6 +71,12 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ pa
     const bool mx = (ops_bits >> v) & 1u;
     const double id = mx ? -INFINITY : 0.0;
     double a = id;
+    if (nblk <= 64) {   // at most one block per lane
+      if (lane < nblk) {
+        const double x = part[(long long)lane * stride + v];
+        a = mx ? fmax(a, x) : a + x;
+      }
+    } else {
     for (int b0 = lane; b0 < nblk; b0 += 64 * RED_UNROLL) {
       double x[RED_UNROLL];
 #pragma unroll
@@ -81,9 +87,15 @@ __global__ __launch_bounds__(RED_WG) void k_reduce(const double* __restrict__ pa
 #pragma unroll
       for (int u = 0; u < RED_UNROLL; ++u) a = mx ? fmax(a, x[u]) : a + x[u];
     }
+    }
     a = mx ? warp_max(a) : warp_sum(a);
-    if (lane == 0) sres[v] = mx ? a : scale * a;
+    if (lane == 0) {
+      const double r = mx ? a : scale * a;
+      sres[v] = r;
+      if (!stop && !hout) out[v] = r;   // a plain reduction ends here
+    }
   }
+  if (!stop && !hout) return;
   __syncthreads();   // sres of every wave
   // the flag and the counter pass through an empty asm here, so that the waits for their loads
   // are placed here, behind the partials' loads

@@ -1049,7 +1049,26 @@ __device__ inline void wave_chain_group(const SlabParams& P, unsigned char* lds,
     }
     __syncthreads();
     // S2 in 4-deep k-blocks: elem (i3, m) at ((i3 / 4) P12 + m) 4 + i3 % 4
-    if (part == 0) {
+    if (part == 0 && SPW == 1) {
+      // one slab per workgroup (NPART - 1 partials per element): element by element, which keeps
+      // the registers of the batched kernels' waves within their budget
+      ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int i2 = 16 * mt + 4 * g + i, i1 = 16 * nt + r;
+            if (i1 < G.p1 && i2 < G.p2) {
+              const int m = i1 + G.p1 * i2;
+              float v = s2[mt][nt][i];
+#pragma unroll
+              for (int pp = 0; pp < NPART - 1; ++pp) v += s2p[(pp * SPW + sw) * 1024 + m];
+              if (sw < nsl) S2[(long long)m * 4] = W::from_f32(v);
+            }
+          }
+    } else if (part == 0) {
       ST* S2 = (ST*)P.S2 + ((long long)(i3 >> 2) * P12) * 4 + (i3 & 3);
       // the partials are read first, all at once (one LDS round trip); the indices stay inside
       // the 1024-element slots, and entries outside the p1 x p2 block are read but not used

@@ -258,8 +258,12 @@ def config_sim(r=3, q=0.5, family="gaussian", kappa=0.25, seed=6, nlambda=100, r
     sigma, s = (1.0, 1.0) if gaussian else (0.71, 0.01)
     X = []
     for nj, pj in zip(n, p):
-        cov = (sigma - kappa) * np.eye(pj) + kappa * np.ones((pj, pj))
-        X.append(np.ascontiguousarray(rng.multivariate_normal(np.zeros(pj), cov, size=nj)))
+        # a row of N(0, Sigma) drawn exactly as sqrt(sigma - kappa) z + sqrt(kappa) w 1 (z ~ N(0, I),
+        # w ~ N(0, 1)): no matrix factorisation, whose eigenbasis for the repeated eigenvalue
+        # sigma - kappa would depend on the BLAS threading
+        z = rng.standard_normal((nj, pj))
+        w = rng.standard_normal((nj, 1))
+        X.append(np.ascontiguousarray(np.sqrt(sigma - kappa) * z + np.sqrt(kappa) * w))
     P = int(np.prod(p))
     m = np.arange(1, P + 1)
     B = rng.uniform(size=P) < s

@@ -44,3 +44,24 @@ def test_configs_shapes_and_seeds():
     c3 = inputs.config_c3(n=(16, 16, 30), p=(6, 6, 10))
     assert c3.family == "poisson" and np.all(c3.Y >= 0) and np.all(c3.Y == np.round(c3.Y))
     assert abs(np.mean(c3.Y) - 5.0) < 0.5
+
+
+def test_sec65_rows_have_the_stated_covariance_and_do_not_depend_on_blas_threads():
+    """Sec. 6.5's factor rows are N(0, Sigma), Sigma = (sigma - kappa) I + kappa 1 1^T: the sample
+    covariance of many rows matches (diagonal sigma, off-diagonal kappa), and the draw is the same
+    bytes whatever the BLAS thread count (no factorisation of Sigma is involved)."""
+    threadpoolctl = pytest.importorskip("threadpoolctl")
+    for fam, sigma in (("gaussian", 1.0), ("poisson", 0.71)):
+        d = inputs.config_sim(r=9, q=0.1, family=fam, kappa=0.25)   # n = (180, 90, 540), p = (18, 9, 54)
+        Xj = d.X[2]
+        C = np.cov(Xj.T, bias=True)
+        off = C[~np.eye(C.shape[0], dtype=bool)]
+        assert abs(np.mean(np.diag(C)) - sigma) < 0.05, np.mean(np.diag(C))
+        assert abs(np.mean(off) - 0.25) < 0.05, np.mean(off)
+    with threadpoolctl.threadpool_limits(1):
+        a = inputs.config_sim(r=3, family="poisson")
+    with threadpoolctl.threadpool_limits(8):
+        b = inputs.config_sim(r=3, family="poisson")
+    for Xa, Xb in zip(a.X, b.X):
+        assert Xa.tobytes() == Xb.tobytes()
+    assert a.Y.tobytes() == b.Y.tobytes()
