@@ -1270,8 +1270,15 @@ extern "C" int glam_fit_path(const glam_problem* prob_in, const glam_options* op
       if (F.dt != DT_F64 && !F.gram) {
         lowprec_stalls = (k > 0 && last_limited && kkt > 0.9 * kkt_prev) ? lowprec_stalls + 1 : 0;
         if (lowprec_stalls >= 3) {
-          if (F.dt == DT_BF16) RCHK(escalate_f32(F));
-          else escalate_f64(F);
+          if (F.dt == DT_BF16) {
+            RCHK(escalate_f32(F));
+          } else {
+            escalate_f64(F);
+            // the weights V of this step were written for the FP32 chain (4-byte entries); the FP64
+            // chain reads 8-byte ones: step 2 again at the same theta writes them in that format
+            // (the other values are the same)
+            if (F.v_int) RCHK(family_step(F, F.theta, lam, &st));
+          }
           lowprec_stalls = 0;
           if (res->escalated_at < 0) res->escalated_at = l;
           if (verbose)

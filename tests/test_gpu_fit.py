@@ -475,6 +475,13 @@ def test_precision_escalation_on_ill_conditioned_design():
     res = glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=40, lambda_min_ratio=0.02, dtype=2, kkt_tol=1e-6)
     assert res.code == 0 and res.n_done == 40
     assert 0 <= res.escalated_at < 40
+    # every kernel input is defined across the escalations (BF16 -> FP32 -> FP64): plain stream
+    # launches give the same path, bit for bit, as the graph replays
+    r2 = glam.fit_path(Xd, Yd, d.n, d.p, "poisson", nlambda=40, lambda_min_ratio=0.02, dtype=2, kkt_tol=1e-6,
+                       graph=False)
+    assert r2.escalated_at == res.escalated_at
+    assert np.array_equal(r2.iters_inner, res.iters_inner)
+    assert torch.equal(r2.theta, res.theta)
     lm = O.lambda_max("poisson", d.X, d.Y)
     for l in (res.escalated_at, 39):
         th = _theta(glam, res, l, d.p)
