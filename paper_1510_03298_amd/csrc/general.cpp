@@ -189,6 +189,61 @@ int inner_gradient(GFit& F) {
   return GLAM_OK;
 }
 
+// the increment-state inner iteration (BF16 / FP32 chains): the forward chains as in inner_gradient,
+// then each component's adjoint chain with the step fused into its last product; *nb: partial rows
+int inner_step(GFit& F, float* const d[3], double lam, double delta, double om, int* nb) {
+  const size_t es = dt_size(F.dt);
+  const size_t c = F.comp.size();
+  for (size_t r = 0; r + 1 < c; ++r) {
+    const Comp& cr = F.comp[r];
+    GCHK(general_forward(F.dt, F.n, cr.p, cr.XTc, (const char*)F.inc + cr.off * es, F.t1, F.t2, F.etai, r > 0, F.s));
+  }
+  const Comp& cl = F.comp[c - 1];
+  GCHK(general_forward_weighted(F.dt, F.n, cl.p, cl.XTc, (const char*)F.inc + cl.off * es, F.t1, F.t2,
+                                c > 1 ? F.etai : nullptr, F.use_v ? F.V : nullptr, F.R, F.s));
+  auto params = [&](const Comp& cm, int rows) {
+    GenStepParams S{};
+    S.scale = 1.0 / (double)F.N;
+    S.gref = F.gref + cm.off;
+    S.theta_ref = F.theta + cm.off;
+    S.w = F.pen ? F.pen + cm.off : nullptr;
+    S.dcur = d[0] + cm.off;
+    S.dprev = d[1] + cm.off;
+    S.q = F.qst + cm.off;
+    S.dout = d[2] + cm.off;
+    S.inc = (char*)F.inc + cm.off * es;
+    S.lambda = lam;
+    S.delta = delta;
+    S.om = om;
+    S.alpha = F.enet;
+    S.no_l1 = F.no_l1;
+    S.part = F.part + (size_t)rows * 4;
+    return S;
+  };
+  bool any_fused = false;
+  for (const Comp& cm : F.comp) any_fused = any_fused || general_step_fused(cm.p);
+  if (!any_fused) {
+    // every component's last product is small: the adjoint chains into gi, then one step over all
+    // coefficients (one launch)
+    for (const Comp& cm : F.comp)
+      GCHK(general_adjoint(F.dt, F.n, cm.p, cm.Xc, F.R, F.t1, F.t2, (char*)F.gi + cm.off * acc_size(F.dt), F.s));
+    Comp all;
+    all.off = 0;
+    GCHK(launch_gen_step(F.dt, F.P, F.gi, params(all, 0), nb, F.s));
+    return GLAM_OK;
+  }
+  int rows = 0;
+  for (const Comp& cm : F.comp) {
+    const GenStepParams S = params(cm, rows);
+    int r = 0;
+    GCHK(general_adjoint_step(F.dt, F.n, cm.p, cm.Xc, F.R, F.t1, F.t2, (char*)F.gi + cm.off * acc_size(F.dt), S, &r,
+                              F.s));
+    rows += r;
+  }
+  *nb = rows;
+  return GLAM_OK;
+}
+
 int read_red(GFit& F, int nb, int nval, const int* ops, double* out) {
   GCHK(launch_reduce(F.part, nb, nval, ops, 1.0, F.red, F.s));
   GCHK(hipMemcpyAsync(F.hred, F.red, nval * sizeof(double), hipMemcpyDeviceToHost, F.s));
@@ -198,7 +253,8 @@ int read_red(GFit& F, int nb, int nval, const int* ops, double* out) {
 }
 
 // Inner PG loop with nu = 1 (delta = 1/Lhat fixed).  Leaves theta~ = x^l of the last checked
-// iteration in F.xp.  BF16/FP32 chains keep the state as FP32 increments (k_gen_prox_inc), FP64
+// iteration in F.xp.  BF16/FP32 chains keep the state as FP32 increments (the step fused into the
+// last adjoint product, general_adjoint_step), FP64
 // chains in FP64 (k_gen_prox).
 int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scale, int max_inner, int check_every,
                bool restart, bool exact_model, int* it_out, double* kin_out) {
@@ -220,17 +276,17 @@ int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scal
   while (it < max_inner) {
     ++l;
     const double om = (l - 1.0) / (l + 2.0);
-    int r = inner_gradient(F);
-    if (r) return r;
     int nb = 0;
     if (incst) {
-      GCHK(launch_gen_prox_inc(F.dt, F.P, F.gi, 1.0 / (double)F.N, F.gref, F.theta, F.pen, d[0], d[1], F.qst, d[2],
-                               F.inc, lam, delta, om, F.enet, F.no_l1, F.part, &nb, F.s));
+      const int r = inner_step(F, d, lam, delta, om, &nb);
+      if (r) return r;
       float* t = d[1];
       d[1] = d[0];
       d[0] = d[2];
       d[2] = t;
     } else {
+      const int r = inner_gradient(F);
+      if (r) return r;
       GCHK(launch_gen_prox(F.dt, F.P, F.gi, 1.0 / (double)F.N, F.gref, F.theta, F.pen, F.x, F.xp, F.gp, F.inc, lam,
                            delta, om, F.enet, F.no_l1, F.part, &nb, F.s));
     }
@@ -238,8 +294,10 @@ int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scal
     if (it % check_every != 0 && it < max_inner) continue;
     double v[4];
     const int ops[4] = {1, 1, 0, 1};
-    r = read_red(F, nb, 4, ops, v);
-    if (r) return r;
+    {
+      const int r = read_red(F, nb, 4, ops, v);
+      if (r) return r;
+    }
     kin = v[0] / lam_scale;
     const double noise = 4.0 * kEpsG[F.dt] * v[1] / lam_scale;
     if (restart && v[2] > 0.0) l = 0;   // gradient restart test: omega = 0 next
@@ -384,8 +442,10 @@ int setup(GFit& F, const GenProblem& prob, int dtype, bool bt) {
   bool ok = true;
   auto A = [&](size_t b) { void* p = F.alloc(b); if (!p) ok = false; return p; };
   const size_t nb8 = (size_t)F.N * 8, pb8 = (size_t)F.P * 8;
-  const size_t npart = std::max<size_t>((size_t)kGenMaxBlocks * 4,
-                                        (size_t)(kArmijoMaxBlocks + kPenTrialsMaxBlocks) * (ARMIJO_TRIALS + 1));
+  size_t step_rows = 0;   // partial rows of the fused increment-state step (all components)
+  for (const GenComponent& gc : prob.comps) step_rows += (size_t)general_step_rows(gc.p);
+  const size_t npart = std::max<size_t>({(size_t)kGenMaxBlocks * 4, step_rows * 4,
+                                         (size_t)(kArmijoMaxBlocks + kPenTrialsMaxBlocks) * (ARMIJO_TRIALS + 1)});
   F.theta = (double*)A(pb8);
   F.eta = (double*)A(nb8);
   F.u = (double*)A(nb8);

@@ -50,20 +50,19 @@ __host__ __device__ constexpr int gemm_lds_bytes() {
              : GBN * (GBM + 1) * (int)sizeof(typename Tr<T>::acc_t);
 }
 
-template <typename T, typename TO, bool ADD, bool VMUL>
-__global__ __launch_bounds__(GWG) void k_rho_gemm(long long M, long long N, long long K, const T* __restrict__ A,
-                                                  long long lda, const T* __restrict__ B, long long ldb,
-                                                  TO* C, long long ldc, const typename Tr<T>::acc_t* Cadd,
-                                                  const typename Tr<T>::acc_t* __restrict__ Vmul) {
+// The tile of C at (m0, n0): the products accumulated in registers and transposed through LDS,
+// so that on return (after a barrier) Cs[col * (GBM + 1) + row] holds C[m0 + row, n0 + col].
+template <typename T>
+__device__ inline void rho_gemm_tile(long long M, long long N, long long K, const T* __restrict__ A, long long lda,
+                                     const T* __restrict__ B, long long ldb, long long m0, long long n0,
+                                     unsigned char* smem) {
   typedef Tr<T> R;
   typedef typename R::frag_t F;
   typedef typename R::acc_t AT;
   constexpr int NLD = GBM * GKT / GWG;   // elements of each operand slice per thread
-  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T>()];
   T* As = (T*)smem;
   T* Bs = As + GBM * GLDK;
   const int tid = threadIdx.x, lane = tid & 63, r = lane & 15, g = lane >> 4, w = tid >> 6;
-  const long long m0 = (long long)blockIdx.x * GBM, n0 = (long long)blockIdx.y * GBN;
   const T z = zero_val<T>();
   T ra[NLD], rb[NLD];
   // element e = tid + GWG j of a slice: column e / GKT of the tile, contraction index e % GKT
@@ -119,6 +118,19 @@ __global__ __launch_bounds__(GWG) void k_rho_gemm(long long M, long long N, long
 #pragma unroll
       for (int e = 0; e < 4; ++e) Cs[(wn + 16 * j + r) * (GBM + 1) + wm + 16 * i + R::kidx(g, e)] = acc[i][j][e];
   __syncthreads();
+}
+
+template <typename T, typename TO, bool ADD, bool VMUL>
+__global__ __launch_bounds__(GWG) void k_rho_gemm(long long M, long long N, long long K, const T* __restrict__ A,
+                                                  long long lda, const T* __restrict__ B, long long ldb,
+                                                  TO* C, long long ldc, const typename Tr<T>::acc_t* Cadd,
+                                                  const typename Tr<T>::acc_t* __restrict__ Vmul) {
+  typedef typename Tr<T>::acc_t AT;
+  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T>()];
+  const int tid = threadIdx.x;
+  const long long m0 = (long long)blockIdx.x * GBM, n0 = (long long)blockIdx.y * GBN;
+  rho_gemm_tile<T>(M, N, K, A, lda, B, ldb, m0, n0, smem);
+  const AT* Cs = (const AT*)smem;
 #pragma unroll 4
   for (int pass = 0; pass < GBM * GBN / GWG; ++pass) {
     const int col = pass * (GWG / GBM) + tid / GBM, row = tid % GBM;
@@ -440,53 +452,120 @@ hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, co
 // d in FP32 (an exact zero x^l kept as a NaN code), and grad h(x^{l-1}) = gref + q with q the
 // previous increment gradient (FP32), so that a coefficient moves 32 bytes in and 10 out instead of
 // 44 and 26.  Reads dcur (d^l), dprev (d^{l-1}), q; writes dout (d^{l+1}), q (in place) and inc.
-template <typename T, typename A>
-__global__ __launch_bounds__(GWG) void k_gen_prox_inc(long long p, const A* __restrict__ gi, double scale,
-                                                      const double* __restrict__ gref,
-                                                      const double* __restrict__ theta_ref,
-                                                      const double* __restrict__ w, const float* __restrict__ dcur,
-                                                      const float* __restrict__ dprev, float* __restrict__ q,
-                                                      float* __restrict__ dout, T* __restrict__ inc, double lambda,
-                                                      double delta, double om, double alpha, int no_l1,
-                                                      double* __restrict__ part) {
+// One coefficient j, given incg = scale gi[j]; accumulates the check partials {max KKT residual at
+// x^l, max |incg|, restart test sum, max |x^{l+1} - theta_ref|}.
+template <typename T>
+__device__ inline void gen_step_elem(long long j, double incg, const GenStepParams& S, double& kkt, double& noise,
+                                     double& rs, double& dmax) {
+  const double tr = S.theta_ref[j];
+  const float dc = S.dcur[j], dp = S.dprev[j];
+  const double xv = __builtin_isnan(dc) ? 0.0 : tr + (double)dc;
+  const double xpv = __builtin_isnan(dp) ? 0.0 : tr + (double)dp;
+  const double gx = S.gref[j] + incg;
+  const double wm = S.w ? S.w[j] : 1.0, lw = S.lambda * wm, l1w = S.no_l1 ? 0.0 : lw;
+  const double gs = gx + 2.0 * S.alpha * lw * xv;
+  kkt = fmax(kkt, xv != 0.0 ? fabs(gs + copysign(l1w, xv)) : fmax(fabs(gs) - l1w, 0.0));
+  noise = fmax(noise, fabs(incg));
+  const double gy = gx + S.om * (incg - (double)S.q[j]);
+  const double yv = xv + S.om * (xv - xpv);
+  const double xn = g_soft(yv - S.delta * gy, S.delta * l1w) / (1.0 + 2.0 * S.alpha * S.delta * lw);
+  const double dn = xn - tr;
+  S.dout[j] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
+  S.q[j] = (float)incg;
+  rs += (yv - xn) * (xn - xv);
+  dmax = fmax(dmax, fabs(dn));
+  ((T*)S.inc)[j] = g_to((typename Tr<T>::acc_t)dn, (T*)nullptr);
+}
+
+// The last step of the adjoint chain, out (p1 p2 x p3, standard layout) = the usual product, with
+// the step above applied to its output tile in place of a store: gi never goes to memory and
+// the step is no launch of its own.  Partial rows: one per workgroup, blockIdx.y gridDim.x +
+// blockIdx.x, from S.part.
+template <typename T>
+__global__ __launch_bounds__(GWG) void k_rho_gemm_step(long long M, long long N, long long K, const T* __restrict__ A,
+                                                       long long lda, const T* __restrict__ B, long long ldb,
+                                                       long long ldc, GenStepParams S) {
+  typedef typename Tr<T>::acc_t AT;
+  __shared__ __align__(16) unsigned char smem[gemm_lds_bytes<T>()];
+  const int tid = threadIdx.x;
+  const long long m0 = (long long)blockIdx.x * GBM, n0 = (long long)blockIdx.y * GBN;
+  rho_gemm_tile<T>(M, N, K, A, lda, B, ldb, m0, n0, smem);
+  const AT* Cs = (const AT*)smem;
   double kkt = 0.0, noise = 0.0, rs = 0.0, dmax = 0.0;
-  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG) {
-    const double incg = scale * (double)gi[j];
-    const double tr = theta_ref[j];
-    const float dc = dcur[j], dp = dprev[j];
-    const double xv = __builtin_isnan(dc) ? 0.0 : tr + (double)dc;
-    const double xpv = __builtin_isnan(dp) ? 0.0 : tr + (double)dp;
-    const double gx = gref[j] + incg;
-    const double wm = w ? w[j] : 1.0, lw = lambda * wm, l1w = no_l1 ? 0.0 : lw;
-    const double gs = gx + 2.0 * alpha * lw * xv;
-    kkt = fmax(kkt, xv != 0.0 ? fabs(gs + copysign(l1w, xv)) : fmax(fabs(gs) - l1w, 0.0));
-    noise = fmax(noise, fabs(incg));
-    const double gy = gx + om * (incg - (double)q[j]);
-    const double yv = xv + om * (xv - xpv);
-    const double xn = g_soft(yv - delta * gy, delta * l1w) / (1.0 + 2.0 * alpha * delta * lw);
-    const double dn = xn - tr;
-    dout[j] = xn == 0.0 ? __builtin_nanf("") : (float)dn;
-    q[j] = (float)incg;
-    rs += (yv - xn) * (xn - xv);
-    dmax = fmax(dmax, fabs(dn));
-    inc[j] = g_to((typename Tr<T>::acc_t)dn, (T*)nullptr);
+#pragma unroll 4
+  for (int pass = 0; pass < GBM * GBN / GWG; ++pass) {
+    const int col = pass * (GWG / GBM) + tid / GBM, row = tid % GBM;
+    if (m0 + row >= M || n0 + col >= N) continue;
+    const long long j = (m0 + row) + ldc * (n0 + col);
+    gen_step_elem<T>(j, S.scale * (double)Cs[col * (GBM + 1) + row], S, kkt, noise, rs, dmax);
   }
   double v[4] = {kkt, noise, rs, dmax};
-  g_block_partials<4>(v, 1u | 2u | 8u, part);
+  g_block_partials<4>(v, 1u | 2u | 8u, S.part + ((long long)blockIdx.y * gridDim.x) * 4);
 }
-hipError_t launch_gen_prox_inc(int dt, long long p, const void* gi, double scale, const double* gref,
-                               const double* theta_ref, const double* w, const float* dcur, const float* dprev,
-                               float* q, float* dout, void* inc, double lambda, double delta, double om, double alpha,
-                               int no_l1, double* part, int* nblk, hipStream_t s) {
-  const int nb = g_grid(p);
+
+// the standalone form of the step (one coefficient per thread, grid-stride), for components whose
+// last adjoint product has too few workgroups to spread the step over the chip
+template <typename T>
+__global__ __launch_bounds__(GWG) void k_gen_step(long long p, const float* __restrict__ gi, GenStepParams S) {
+  double kkt = 0.0, noise = 0.0, rs = 0.0, dmax = 0.0;
+  for (long long j = blockIdx.x * (long long)GWG + threadIdx.x; j < p; j += (long long)gridDim.x * GWG)
+    gen_step_elem<T>(j, S.scale * (double)gi[j], S, kkt, noise, rs, dmax);
+  double v[4] = {kkt, noise, rs, dmax};
+  g_block_partials<4>(v, 1u | 2u | 8u, S.part);
+}
+
+// the step is fused into the last product when that has at least this many workgroups
+constexpr long long kStepFuseMinBlocks = 256;
+static bool step_fused(const int64_t* p) {
+  return ((p[0] * p[1] + GBM - 1) / GBM) * ((p[2] + GBN - 1) / GBN) >= kStepFuseMinBlocks;
+}
+
+bool general_step_fused(const int64_t* p) { return step_fused(p); }
+
+hipError_t launch_gen_step(int dt, long long pc, const void* gi, const GenStepParams& S, int* nblk, hipStream_t s) {
+  const int nb = g_grid(pc);
   *nblk = nb;
-  const dim3 g(nb), b(GWG);
   if (dt == DT_F32)
-    hipLaunchKernelGGL((k_gen_prox_inc<float, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, dcur,
-                       dprev, q, dout, (float*)inc, lambda, delta, om, alpha, no_l1, part);
+    hipLaunchKernelGGL((k_gen_step<float>), dim3(nb), dim3(GWG), 0, s, pc, (const float*)gi, S);
   else if (dt == DT_BF16)
-    hipLaunchKernelGGL((k_gen_prox_inc<bf16, float>), g, b, 0, s, p, (const float*)gi, scale, gref, theta_ref, w, dcur,
-                       dprev, q, dout, (bf16*)inc, lambda, delta, om, alpha, no_l1, part);
+    hipLaunchKernelGGL((k_gen_step<bf16>), dim3(nb), dim3(GWG), 0, s, pc, (const float*)gi, S);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+long long general_step_rows(const int64_t* p) {
+  return step_fused(p) ? ((p[0] * p[1] + GBM - 1) / GBM) * ((p[2] + GBN - 1) / GBN) : g_grid(p[0] * p[1] * p[2]);
+}
+
+// the adjoint chain of one component followed by the step: fused into its last product when that
+// fills the chip (kStepFuseMinBlocks workgroups), else the plain chain into gi (FP32, the
+// component's block of it) and the standalone step (chains in BF16 or FP32); *nblk: the partial
+// rows written
+hipError_t general_adjoint_step(int dt, const int64_t* n, const int64_t* p, const void* const* X, const void* u,
+                                void* t1, void* t2, void* gi, const GenStepParams& S, int* nblk, hipStream_t s) {
+  hipError_t e;
+  const long long n1 = n[0], n2 = n[1], n3 = n[2], p1 = p[0], p2 = p[1], p3 = p[2];
+  if (dt != DT_F32 && dt != DT_BF16) return hipErrorInvalidValue;
+  if (!step_fused(p)) {
+    // the plain chain into gi (FP32), then the standalone step
+    e = general_adjoint(dt, n, p, X, u, t1, t2, gi, s);
+    if (e != hipSuccess) return e;
+    return launch_gen_step(dt, p1 * p2 * p3, gi, S, nblk, s);
+  }
+  e = launch_rho_gemm(dt, 0, false, n2 * n3, p1, n1, u, n1, X[0], n1, t1, n2 * n3, s);
+  if (e != hipSuccess) return e;
+  e = launch_rho_gemm(dt, 0, false, n3 * p1, p2, n2, t1, n2, X[1], n2, t2, n3 * p1, s);
+  if (e != hipSuccess) return e;
+  const long long M = p1 * p2, N = p3, K = n3;
+  const long long gx = (M + GBM - 1) / GBM, gy = (N + GBN - 1) / GBN;
+  if (gx < 1 || gy < 1 || gy > 65535 || gx * gy > 0x7fffffffLL) return hipErrorInvalidValue;
+  *nblk = (int)(gx * gy);
+  const dim3 grid((unsigned)gx, (unsigned)gy), blk(GWG);
+  if (dt == DT_F32)
+    hipLaunchKernelGGL((k_rho_gemm_step<float>), grid, blk, 0, s, M, N, K, (const float*)t2, n3, (const float*)X[2], n3, M, S);
+  else if (dt == DT_BF16)
+    hipLaunchKernelGGL((k_rho_gemm_step<bf16>), grid, blk, 0, s, M, N, K, (const bf16*)t2, n3, (const bf16*)X[2], n3, M, S);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -401,12 +401,37 @@ hipError_t launch_gen_prox(int dt, long long p, const void* gi, double scale, co
                            const double* theta_ref, const double* w, double* x, double* xp, double* gp, void* inc,
                            double lambda, double delta, double om, double alpha, int no_l1, double* part, int* nblk,
                            hipStream_t s);
-// the same step on FP32 increment state (BF16/FP32 chains): x^l = theta_ref + d (NaN: exact 0),
-// grad h(x^{l-1}) = gref + q; reads dcur, dprev, q, writes dout, q, inc; the same partials
-hipError_t launch_gen_prox_inc(int dt, long long p, const void* gi, double scale, const double* gref,
-                               const double* theta_ref, const double* w, const float* dcur, const float* dprev,
-                               float* q, float* dout, void* inc, double lambda, double delta, double om, double alpha,
-                               int no_l1, double* part, int* nblk, hipStream_t s);
+// One FP32 increment-state step of the generic path (BF16 / FP32 chains, nu = 1), applied by the last
+// product of a component's adjoint chain to its output tile (general_adjoint_step).  Arrays in the
+// standard coefficient layout, offset to the component's block: x^l = theta_ref + d^l (d FP32, an
+// exact zero kept as a NaN code), grad h(x^{l-1}) = gref + q; writes d^{l+1}, q (in place) and
+// inc = x^{l+1} - theta_ref in the chain dtype; partial rows {max KKT residual at x^l, max
+// |scale gi|, restart test sum, max |x^{l+1} - theta_ref|}.
+struct GenStepParams {
+  double scale;                // gi -> increment gradient (1 / n)
+  const double* gref;          // grad h(theta_ref)
+  const double* theta_ref;
+  const double* w;             // penalty weights or NULL (all 1)
+  const float* dcur;           // d^l
+  const float* dprev;          // d^{l-1}
+  float* q;
+  float* dout;                 // d^{l+1}
+  void* inc;
+  double lambda, delta, om, alpha;
+  int no_l1;
+  double* part;                // partial rows, 4 doubles each
+};
+// the adjoint chain of one component with the step fused into its last product (or, when that
+// product has too few workgroups, written to gi, FP32, and followed by a standalone step); *nblk:
+// partial rows
+hipError_t general_adjoint_step(int dt, const int64_t* n, const int64_t* p, const void* const* X, const void* u,
+                                void* t1, void* t2, void* gi, const GenStepParams& S, int* nblk, hipStream_t s);
+// partial rows general_adjoint_step writes for a component with these sizes
+long long general_step_rows(const int64_t* p);
+// whether general_adjoint_step fuses the step into the last product for these sizes
+bool general_step_fused(const int64_t* p);
+// the standalone step over pc coefficients from gi (FP32); *nblk: partial rows
+hipError_t launch_gen_step(int dt, long long pc, const void* gi, const GenStepParams& S, int* nblk, hipStream_t s);
 // out = theta_ref + d (sub = 0) or that minus theta_ref (sub = 1), FP64
 hipError_t launch_gen_inc_out(long long p, const float* d, const double* theta_ref, int sub, double* out,
                               hipStream_t s);
