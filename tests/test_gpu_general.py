@@ -224,16 +224,18 @@ def test_components_penalties_and_step_control(pen, alpha, nu, inner, extrap, dt
 
 
 # ----------------------------------------------------------------------------- Sec. 6.5, q = 3
-@pytest.mark.parametrize("fam,dt", [("gaussian", 1), ("gaussian", 2), ("poisson", 0)])
-def test_sec65_p_greater_than_n_path(fam, dt):
+@pytest.mark.parametrize("fam,dt,r", [("gaussian", 1, 1), ("gaussian", 2, 1), ("poisson", 0, 1), ("gaussian", 2, 2)])
+def test_sec65_p_greater_than_n_path(fam, dt, r):
     """Sec. 6.5's simulated design with q = 3 (p = 324,000 > n = 12,000 at r = 1, kappa = 0):
     glam_fit_path runs it on the generic path.  The lasso solution need not be unique, so each
     model is certified by the oracle's FP64 KKT residual on the GPU's theta and its objective;
     for the Gaussian family also by the lasso's duality gap, which bounds the distance of the
-    objective from its minimum without a reference fit."""
+    objective from its minimum without a reference fit.  At r = 2 (p = 2.59 million; the last
+    adjoint product, 7,200 x 360, has 678 workgroups, ragged in both directions) the increment
+    step runs fused into that product; at r = 1 (87 workgroups) as a kernel of its own."""
     torch, glam = need_gpu()
-    print(f"sec 6.5 q=3 {fam} dt={dt}", flush=True)
-    d = inputs.config_sim(r=1, q=3, family=fam, kappa=0.0)
+    print(f"sec 6.5 q=3 {fam} dt={dt} r={r}", flush=True)
+    d = inputs.config_sim(r=r, q=3, family=fam, kappa=0.0)
     assert int(np.prod(d.p)) > int(np.prod(d.n))
     Xd = [glam.to_device_colmajor(X, 0) for X in d.X]
     Yd = glam.to_device_colmajor(d.Y, 0)
