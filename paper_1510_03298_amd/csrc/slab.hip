@@ -414,7 +414,6 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
   T* t1s = (T*)(smem_raw + L.t1_off);
   constexpr bool NEED_FWD = MODE != SM_ADJ_STD;
   constexpr bool NEED_ADJ = MODE == SM_ADJ_STD || MODE == SM_FUSED || MODE == SM_FAMILY || MODE == SM_NLL_BWD;
-  const int N1Tp = n1_tiles_padded(G);
     F fT1[PT][PT];
     if (NEED_FWD) {
       // the slab's p1 x p2 block of T1 (contiguous), then fragments: row p1, contraction p2
@@ -473,27 +472,29 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
 #pragma unroll
       for (int nt = 0; nt < PT; ++nt) S1[nt] = R::zero();
 
-      for (int u0 = 0; u0 < N1Tp; u0 += CH) {
+      // mode-1 tiles in register groups of CH, then one group of the N1T % CH tiles left over:
+      // the zero rows that pad mode 1 to a multiple of CH in the factor image get no work (their
+      // products would add exact zeros)
+      auto group = [&](auto ncv, const int u0) {
+        constexpr int NC = decltype(ncv)::value;
         // SM_FAMILY: the group's responses (and prior weights) are requested first, all at once;
         // the family step's stores may alias them as far as the compiler knows, which would order
         // every load behind the previous element's stores
-        double yg[CH][4], ag[CH][4];
+        double yg[NC][4], ag[NC][4];
         if (MODE == SM_FAMILY) {
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const bool ok = u0 + c < G.N1T;
+          for (int c = 0; c < NC; ++c) {
             const long long tb = (((long long)i3 * G.NJB + jb) * G.N1T + u0 + c) * 256 + r * 16;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              yg[c][i] = ok ? P.y_int[tb + R::kidx(g, i)] : 0.0;
-              ag[c][i] = (ok && P.a_int) ? P.a_int[tb + R::kidx(g, i)] : 1.0;
+              yg[c][i] = P.y_int[tb + R::kidx(g, i)];
+              ag[c][i] = P.a_int ? P.a_int[tb + R::kidx(g, i)] : 1.0;
             }
           }
         }
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
+        for (int c = 0; c < NC; ++c) {
           const int ut = u0 + c;
-          const bool tile_ok = ut < G.N1T;   // padded tiles: zero factor rows, no n-array access
           AV E = R::zero();
           if (NEED_FWD) {
             // step 2: eta tile (16 x 16) = X1_tile (16 x p1) T2 (p1 x 16)
@@ -515,9 +516,8 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
             }
           } else if (MODE == SM_FWD_INT) {
             A* eta = (A*)P.eta_out;
-            if (tile_ok)
 #pragma unroll
-              for (int i = 0; i < 4; ++i) eta[tbase + R::kidx(g, i)] = E[i];
+            for (int i = 0; i < 4; ++i) eta[tbase + R::kidx(g, i)] = E[i];
           } else if (MODE == SM_ADJ_STD) {
             const T* U = (const T*)P.u_in;
             T uv[4];
@@ -528,7 +528,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
             }
             fR = raw_frag<T>(uv[0], uv[1], uv[2], uv[3]);
           } else if (MODE == SM_FUSED) {
-            if (P.v_int && tile_ok) {
+            if (P.v_int) {
               const A* V = (const A*)P.v_int;
 #pragma unroll
               for (int i = 0; i < 4; ++i) E[i] *= V[tbase + R::kidx(g, i)];
@@ -541,10 +541,6 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
             for (int i = 0; i < 4; ++i) {
               const int i1 = ut * 16 + R::kidx(g, i);
               const bool valid = i1 < G.n1 && i2 < G.n2;
-              if (!tile_ok) {
-                U[i] = (A)0;
-                continue;
-              }
               const long long ti = tbase + R::kidx(g, i);
               const double eta = (double)E[i];
               const double y = yg[c][i];
@@ -609,6 +605,15 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
               mma(S1[nt], fR, load_frag(&sm[L.oX1b + (nt * 16 + r) * L.sX1b + ut * 16 + 4 * g]));
           }
         }
+      };
+      static_assert(CH == 4, "tail groups of 1..3 tiles");
+      int u0 = 0;
+      for (; u0 + CH <= G.N1T; u0 += CH) group(std::integral_constant<int, CH>(), u0);
+      switch (G.N1T - u0) {
+        case 1: group(std::integral_constant<int, 1>(), u0); break;
+        case 2: group(std::integral_constant<int, 2>(), u0); break;
+        case 3: group(std::integral_constant<int, 3>(), u0); break;
+        default: break;
       }
       if (NEED_ADJ) {
         // step 5: S2^T (p2 x p1) += X2_blk^T (p2 x 16) S1^T (16 x p1)
