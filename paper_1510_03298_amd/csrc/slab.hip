@@ -398,8 +398,10 @@ __device__ inline void chain_stage(const void* img, int image_bytes, unsigned ch
 }
 
 // modes 1 and 2 of one slab i3 (the factor image is already in LDS).  FAM: the family of the
-// SM_FAMILY update when known at compile time (0..3), or -1 (read from P.family)
-template <typename T, int PT, int MODE, int FAM = -1>
+// SM_FAMILY update when known at compile time (0..3), or -1 (read from P.family).  PW: the calling
+// wave takes the whole slab by itself (all column blocks, S2 stored from its own accumulators; no
+// LDS beyond the image and no workgroup barrier), else the workgroup's waves share the slab
+template <typename T, int PT, int MODE, int FAM = -1, bool PW = false>
 __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, unsigned char* smem_raw, int i3,
                                   double& s_nll, double& s_vmax) {
   typedef Tr<T> R;
@@ -415,7 +417,24 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
   constexpr bool NEED_FWD = MODE != SM_ADJ_STD;
   constexpr bool NEED_ADJ = MODE == SM_ADJ_STD || MODE == SM_FUSED || MODE == SM_FAMILY || MODE == SM_NLL_BWD;
     F fT1[PT][PT];
-    if (NEED_FWD) {
+    if constexpr (NEED_FWD && PW) {
+      // fragments straight from the slab's contiguous p1 x p2 block of T1 (each 16-lane group
+      // reads 16 consecutive p1 rows of one p2 column)
+      const T* t1 = (const T*)P.T1 + (long long)i3 * G.P12;
+#pragma unroll
+      for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+        for (int kb = 0; kb < PT; ++kb) {
+          T v[4];
+          const int i1 = mt * 16 + r;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i2 = kb * 16 + R::kidx(g, t);
+            v[t] = (i1 < G.p1 && i2 < G.p2) ? t1[i1 + G.p1 * i2] : zero_val<T>();
+          }
+          fT1[mt][kb] = raw_frag<T>(v[0], v[1], v[2], v[3]);
+        }
+    } else if constexpr (NEED_FWD) {
       // the slab's p1 x p2 block of T1 (contiguous), then fragments: row p1, contraction p2
       const T* t1 = (const T*)P.T1 + (long long)i3 * G.P12;
       // requested 4 per thread at a time (one round trip per 4 WG elements, not one per WG)
@@ -453,7 +472,7 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
 #pragma unroll
       for (int b = 0; b < PT; ++b) S2acc[a][b] = R::zero();
 
-    for (int jb = w; jb < G.NJB; jb += WG / 64) {
+    for (int jb = PW ? 0 : w; jb < G.NJB; jb += PW ? 1 : WG / 64) {
       F fT2[PT];
       if (NEED_FWD) {
         // step 1: T2 (p1 x 16) = T1_s (p1 x p2) X2_blk^T (p2 x 16)
@@ -629,7 +648,21 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
       }
     }
 
-    if (NEED_ADJ) {
+    if constexpr (NEED_ADJ && PW) {
+      // S2 k-blocked (K = n3, C = P12): elem (i3, m) at ((i3/16) P12 + m) 16 + kpos(i3 % 16),
+      // m = p1 index + p1 * p2 index
+      T* S2 = (T*)P.S2 + ((long long)(i3 >> 4) * G.P12) * 16 + kpos<T>(i3 & 15);
+#pragma unroll
+      for (int mt = 0; mt < PT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < PT; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int b = mt * 16 + R::kidx(g, i);   // p2 index
+            const int a = nt * 16 + r;               // p1 index
+            if (a < G.p1 && b < G.p2) S2[(long long)(a + G.p1 * b) * 16] = R::from_acc(S2acc[mt][nt][i]);
+          }
+    } else if constexpr (NEED_ADJ) {
       // cross-wave sum of S2^T (waves 2,3 -> 0,1, then 1 -> 0)
       const int PP2 = PP * PP;
       if (w >= 2) {
@@ -682,10 +715,11 @@ __device__ inline void chain_slab(const SlabParams& P, const ChainLayout& L, uns
         S2[(long long)idx * 16] = R::from_acc(fin[b * PP + a]);
       }
     }
-    __syncthreads();
+    if constexpr (!PW) __syncthreads();
 }
 
-template <typename T, int PT, int MODE, int FAM = -1>
+// PW: one slab per wave (WG / 64 slabs per workgroup at a time), else one slab per workgroup
+template <typename T, int PT, int MODE, int FAM = -1, bool PW = false>
 __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
   typedef typename Tr<T>::acc_t A;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -693,7 +727,14 @@ __global__ __launch_bounds__(WG) void k_slab_chain(SlabParams P) {
   const ChainLayout L = chain_layout(P.G, (int)sizeof(T), (int)sizeof(A));
   chain_stage(P.img, L.image_bytes, smem_raw);
   double s_nll = 0.0, s_vmax = 0.0;
-  for (int i3 = blockIdx.x; i3 < P.G.n3; i3 += gridDim.x) chain_slab<T, PT, MODE, FAM>(P, L, smem_raw, i3, s_nll, s_vmax);
+  if constexpr (PW) {
+    constexpr int NW = WG / 64;
+    const int w = __builtin_amdgcn_readfirstlane(wave_id());
+    for (int i3 = blockIdx.x * NW + w; i3 < P.G.n3; i3 += gridDim.x * NW)
+      chain_slab<T, PT, MODE, FAM, true>(P, L, smem_raw, i3, s_nll, s_vmax);
+  } else {
+    for (int i3 = blockIdx.x; i3 < P.G.n3; i3 += gridDim.x) chain_slab<T, PT, MODE, FAM>(P, L, smem_raw, i3, s_nll, s_vmax);
+  }
   if (MODE == SM_FAMILY || MODE == SM_NLL_FWD || MODE == SM_NLL_BWD) {
     double v[2] = {s_nll, s_vmax};
     const int ops[2] = {0, 1};
@@ -1686,14 +1727,16 @@ static void set_lds(K fn, size_t lds) {
 }
 
 template <typename T, int PT>
-static hipError_t chain_dispatch_mode(int mode, const SlabParams& P, int nb, size_t lds, hipStream_t s) {
+static hipError_t chain_dispatch_mode(int mode, const SlabParams& P, int nb, bool pw, size_t lds, hipStream_t s) {
   dim3 grid(nb), blk(WG);
-#define GLAM_CASE(M)                                    \
-  case M: {                                             \
-    auto fn = k_slab_chain<T, PT, M>;                   \
-    set_lds(fn, lds);                                   \
-    hipLaunchKernelGGL(fn, grid, blk, lds, s, P);       \
-    break;                                              \
+#define GLAM_CASE(M)                                                     \
+  case M: {                                                              \
+    auto fn = k_slab_chain<T, PT, M>;                                    \
+    if constexpr (std::is_same<T, double>::value)                        \
+      if (pw) fn = k_slab_chain<T, PT, M, -1, true>;                     \
+    set_lds(fn, lds);                                                    \
+    hipLaunchKernelGGL(fn, grid, blk, lds, s, P);                        \
+    break;                                                               \
   }
   switch (mode) {
     GLAM_CASE(SM_FWD_STD)
@@ -1708,20 +1751,33 @@ static hipError_t chain_dispatch_mode(int mode, const SlabParams& P, int nb, siz
   return hipGetLastError();
 }
 
+// FP64 chains: one slab per wave where that takes fewer column-block rounds per wave than a
+// workgroup's waves sharing each slab (n = (100, 100, 1000): 1000 slabs of 7 column blocks on
+// one workgroup per CU, 7 rounds against 4 slabs x 2 rounds, and no cross-wave S2 sum)
+static bool chain_per_wave(int dt, const Geom& G, int nb) {
+  if (dt != DT_F64) return false;
+  constexpr long long NW = WG / 64;
+  const long long shared = ((G.n3 + nb - 1) / nb) * ((G.NJB + NW - 1) / NW);
+  const long long alone = ((G.n3 + NW * nb - 1) / (NW * nb)) * (long long)G.NJB;
+  return alone < shared;
+}
+
 hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_out, hipStream_t s) {
   const size_t lds = slab_chain_lds_bytes(dt, P.G);
-  const int nb = slab_chain_blocks(dt, P.G);
+  const bool pw = chain_per_wave(dt, P.G, slab_chain_blocks(dt, P.G));
+  const int nb = pw ? (int)std::min<long long>(slab_chain_blocks(dt, P.G), (P.G.n3 + WG / 64 - 1) / (WG / 64))
+                    : slab_chain_blocks(dt, P.G);
   if (nblk_out) *nblk_out = nb;
   dim3 grid(nb), blk(WG);
   if (mode == SM_FAMILY) {
     // one kernel per family and register tile count: with the family fixed, the update's FP64
     // math of the other families leaves the kernel (the Gaussian form drops from 256 registers)
     if (dt != DT_F64 || P.family < 0 || P.family > 3) return hipErrorInvalidValue;
-#define GLAM_FAM(PTV, F)                                   \
-    do {                                                   \
-      auto fn = k_slab_chain<double, PTV, SM_FAMILY, F>;   \
-      set_lds(fn, lds);                                    \
-      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);        \
+#define GLAM_FAM(PTV, F)                                                                           \
+    do {                                                                                           \
+      auto fn = pw ? k_slab_chain<double, PTV, SM_FAMILY, F, true> : k_slab_chain<double, PTV, SM_FAMILY, F>; \
+      set_lds(fn, lds);                                                                            \
+      hipLaunchKernelGGL(fn, grid, blk, lds, s, P);                                                \
     } while (0)
 #define GLAM_FAMS(PTV)                                     \
     do {                                                   \
@@ -1766,9 +1822,9 @@ hipError_t launch_slab_chain(int dt, int mode, const SlabParams& P, int* nblk_ou
     return hipGetLastError();
   }
   const int PT = P.G.PT;
-  if (dt == DT_F64) return PT == 1 ? chain_dispatch_mode<double, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<double, 2>(mode, P, nb, lds, s);
-  if (dt == DT_F32) return PT == 1 ? chain_dispatch_mode<float, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<float, 2>(mode, P, nb, lds, s);
-  return PT == 1 ? chain_dispatch_mode<bf16, 1>(mode, P, nb, lds, s) : chain_dispatch_mode<bf16, 2>(mode, P, nb, lds, s);
+  if (dt == DT_F64) return PT == 1 ? chain_dispatch_mode<double, 1>(mode, P, nb, pw, lds, s) : chain_dispatch_mode<double, 2>(mode, P, nb, pw, lds, s);
+  if (dt == DT_F32) return PT == 1 ? chain_dispatch_mode<float, 1>(mode, P, nb, false, lds, s) : chain_dispatch_mode<float, 2>(mode, P, nb, false, lds, s);
+  return PT == 1 ? chain_dispatch_mode<bf16, 1>(mode, P, nb, false, lds, s) : chain_dispatch_mode<bf16, 2>(mode, P, nb, false, lds, s);
 }
 
 int slab_adj_blocks(const Geom& G) { return ((G.P12 + 15) / 16) * ((G.p3 + 15) / 16); }
