@@ -21,6 +21,7 @@ SHAPES = [
     ((100, 77, 33), (30, 29, 5)),       # two p-tiles, N1T > 4 (chunk loop)
     ((70, 20, 30), (20, 10, 9)),        # N1T = 5: a group of 4 tiles, then one left over
     ((90, 33, 25), (17, 30, 6)),        # N1T = 6: a group of 4 tiles, then two left over
+    ((100, 90, 1000), (30, 28, 7)),     # FP64: one slab per wave (1000 slabs of 6 column blocks)
     ((16, 16, 16), (16, 16, 16)),       # exact tiles
     ((1, 1, 1), (1, 1, 1)),             # degenerate
     ((5, 3, 200), (1, 2, 70)),          # tiny inner modes, long slab mode
