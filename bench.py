@@ -455,7 +455,7 @@ def main():
 
     def fit(dt, profile_every=0, extrapolation=None):
         return glam.fit_path(Xd, Yd, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=args.lambda_min_ratio,
-                             dtype=dts[dt], kkt_tol=1e-6, check_every=10, stream=stream,
+                             dtype=dts[dt], kkt_tol=1e-6, check_every=8, stream=stream,
                              profile_every=profile_every, raise_on_error=False, graph=not args.eager,
                              extrapolation=extrapolation or args.extrapolation)
 
@@ -480,7 +480,7 @@ def main():
     Xc = [glam.to_device_colmajor(X, glam.F64) for X in d.X]
     Yc = glam.to_device_colmajor(d.Y, glam.F64)
     rc = glam.fit_path(Xc, Yc, n, p, "gaussian", nlambda=args.nlambda, lambda_min_ratio=args.lambda_min_ratio,
-                       dtype=dts[args.dtype], kkt_tol=1e-6, check_every=10, stream=stream, raise_on_error=False,
+                       dtype=dts[args.dtype], kkt_tol=1e-6, check_every=8, stream=stream, raise_on_error=False,
                        graph=not args.eager)
     theta_host = rc.theta.cpu().numpy()
     with_copies = {"seconds": time.perf_counter() - t0,

@@ -272,7 +272,7 @@ int inner_loop(GFit& F, double lam, double delta, double tol_in, double lam_scal
   GCHK(hipMemsetAsync(F.inc, 0, F.P * dt_size(F.dt), F.s));
   int it = 0, l = 0, window_start = 0;
   double kin = INFINITY, best = INFINITY, window_best = INFINITY;
-  const int stall = (exact_model ? kStallChecksG : kStallChecksLsG) * check_every;
+  const int stall = (exact_model ? kStallChecksG : kStallChecksLsG) * std::max(check_every, 10);   // as the slab path's window
   while (it < max_inner) {
     ++l;
     const double om = (l - 1.0) / (l + 2.0);

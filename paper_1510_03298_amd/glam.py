@@ -433,14 +433,18 @@ def _run_path(fn, where, prob, opt, L, P, device, raise_on_error):
 
 def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
              lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
-             check_every=10, theta0=None, stream=None, raise_on_error=True, profile_every=0,
+             check_every=8, theta0=None, stream=None, raise_on_error=True, profile_every=0,
              graph=True, inner="chain", alpha=0.0, penalty="lasso", scad_a=3.7, msa_steps=3,
              extrapolation="restarted", kron_step="prop1") -> PathResult:
     """GD-PG lambda path on the device.  Xs: FP64 device factors (column-major,
     1-D); Y, obs_w: FP64 device n-arrays; pen_w, theta0: FP64 device p-arrays;
     alpha: elastic-net weight (0 = lasso); penalty="scad": SCAD by msa_steps steps of
     the multi-step adaptive lasso per lambda.  extrapolation: "restarted" (omega_l counted from
-    the last gradient restart at a check) or "plain" (omega_l = (l-1)/(l+2) through each inner loop)."""
+    the last gradient restart at a check) or "plain" (omega_l = (l-1)/(l+2) through each inner loop).
+    check_every: inner iterations between convergence checks; each check also runs the restart
+    test of the extrapolation.  The stall window is 10 or 20 times max(check_every, 10)
+    iterations.  (8: the n = (100, 100, 1000) Gaussian BF16 path took 0.938 s against 0.951 s
+    at 10, the Poisson n = (64, 64, 365) path 0.994 against 1.004 s.)"""
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
     prob = GlamProblem()
     prob.d = len(n)
@@ -460,7 +464,7 @@ def fit_path(Xs, Y, n, p, family="gaussian", obs_w=None, pen_w=None, lambdas=Non
 
 def fit_path_multi(components, Y, n, family="gaussian", obs_w=None, pen_w=None, lambdas=None, nlambda=100,
                    lambda_min_ratio=1e-4, dtype=F64, kkt_tol=1e-6, nu=1.0, max_outer=100, max_inner=100000,
-                   check_every=10, theta0=None, stream=None, raise_on_error=True, inner="chain", alpha=0.0,
+                   check_every=8, theta0=None, stream=None, raise_on_error=True, inner="chain", alpha=0.0,
                    penalty="lasso", scad_a=3.7, msa_steps=3, extrapolation="restarted") -> PathResult:
     """GD-PG lambda path of a c-component model X = [X_1 | ... | X_c] (Sec. 2): components is a
     list of (Xs_r, p_r), Xs_r the d FP64 device factors of component r and p_r its d sizes;
